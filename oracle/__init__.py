@@ -1,0 +1,229 @@
+"""CPU oracle for sparse Cholesky LL^T and triangular solves (FP64).
+
+TEST INFRASTRUCTURE ONLY: only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It is independent of
+the GPU library (no shared code, headers or tables); the two only share the
+seeded input generators in ``workloads``.
+
+The arithmetic lives in ``oracle.c`` (plain serial C, built with
+``-O2 -ffp-contract=off -fno-fast-math``).  This module marshals numpy
+arrays and adds the error measures used to compare results, all in FP64:
+
+  relres = ||b - A x||_2 / ||b||_2
+  eta    = ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf)
+  forward error  ||x - x_o||_inf / ||x_o||_inf
+  factor error   max_j ||L[:, j] - L_o[:, j]||_inf / ||L_o[:, j]||_inf
+
+Parity status: every function here is pinned by tests/test_oracle.py
+(dense LAPACK Cholesky, closed forms of the 1D Laplacian, exact results for
+diagonal matrices, brute-force boolean elimination for the pattern).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.or_symbolic.argtypes = [I64, P, P, P, I64, P, P, P]
+        lib.or_symbolic.restype = ctypes.c_int
+        lib.or_factor.argtypes = [I64, P, P, P, P, I64, P, P, P, P]
+        lib.or_factor.restype = ctypes.c_int
+        lib.or_solve.argtypes = [I64, P, P, P, P, P, I64]
+        lib.or_solve.restype = None
+        lib.or_spmv.argtypes = [I64, P, P, P, P, P, I64]
+        lib.or_spmv.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+@dataclass
+class Symbolic:
+    n: int
+    nrows: int
+    perm: Optional[np.ndarray]
+    parent: np.ndarray   # int32[n]
+    Lcolptr: np.ndarray  # int64[n+1]
+    Lrowind: np.ndarray  # int32[nnzL]
+
+    @property
+    def nnzL(self) -> int:
+        return int(self.Lcolptr[-1])
+
+    @property
+    def counts(self) -> np.ndarray:
+        return np.diff(self.Lcolptr)
+
+    def flops(self) -> float:
+        """Sum of squared column counts (multiply-add counted as 2 flops)."""
+        c = self.counts.astype(np.float64)
+        return float(np.sum(c * c))
+
+
+def symbolic(n, colptr, rowind, perm=None, nrows=None) -> Symbolic:
+    """Elimination tree and pattern of L for P A P^T (rows < nrows only)."""
+    lib = _load()
+    colptr = _c(colptr, np.int64)
+    rowind = _c(rowind, np.int32)
+    perm = _c(perm, np.int32)
+    nr = n if nrows is None else int(nrows)
+    parent = np.empty(n, dtype=np.int32)
+    Lcolptr = np.empty(n + 1, dtype=np.int64)
+    rc = lib.or_symbolic(n, _p(colptr), _p(rowind), _p(perm), nr, _p(parent),
+                         _p(Lcolptr), None)
+    if rc:
+        raise MemoryError("or_symbolic")
+    Lrowind = np.empty(int(Lcolptr[-1]), dtype=np.int32)
+    rc = lib.or_symbolic(n, _p(colptr), _p(rowind), _p(perm), nr, _p(parent),
+                         _p(Lcolptr), _p(Lrowind))
+    if rc:
+        raise MemoryError("or_symbolic")
+    return Symbolic(n=n, nrows=nr, perm=perm, parent=parent, Lcolptr=Lcolptr,
+                    Lrowind=Lrowind)
+
+
+def factor(n, colptr, rowind, values, sym: Symbolic):
+    """Numeric factor.  Returns (Lx, info) with info = 0 or the 1-based row
+    whose pivot failed."""
+    lib = _load()
+    colptr = _c(colptr, np.int64)
+    rowind = _c(rowind, np.int32)
+    values = _c(values, np.float64)
+    Lx = np.zeros(sym.nnzL, dtype=np.float64)
+    info = lib.or_factor(n, _p(colptr), _p(rowind), _p(values), _p(sym.perm),
+                         sym.nrows, _p(sym.parent), _p(sym.Lcolptr),
+                         _p(sym.Lrowind), _p(Lx))
+    if info < 0:
+        raise MemoryError("or_factor")
+    return Lx, int(info)
+
+
+def solve(sym: Symbolic, Lx, b):
+    """x = A^{-1} b for b of shape [n] or [nrhs, n]."""
+    lib = _load()
+    b = np.array(b, dtype=np.float64, copy=True, order="C")
+    shape = b.shape
+    b2 = b.reshape(-1, sym.n)
+    Lx = _c(Lx, np.float64)
+    lib.or_solve(sym.n, _p(sym.Lcolptr), _p(sym.Lrowind), _p(Lx), _p(sym.perm),
+                 _p(b2), b2.shape[0])
+    return b2.reshape(shape)
+
+
+def spmv(n, colptr, rowind, values, x):
+    """A x with A given by its lower CSC triangle; x of shape [n] or [k, n]."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    shape = x.shape
+    x2 = x.reshape(-1, n)
+    y = np.empty_like(x2)
+    lib.or_spmv(n, _p(_c(colptr, np.int64)), _p(_c(rowind, np.int32)),
+                _p(_c(values, np.float64)), _p(x2), _p(y), x2.shape[0])
+    return y.reshape(shape)
+
+
+def norm_inf_sym(n, colptr, rowind, values) -> float:
+    """||A||_inf of the symmetric matrix stored by its lower triangle."""
+    colptr = np.asarray(colptr, np.int64)
+    rowind = np.asarray(rowind, np.int64)
+    values = np.asarray(values, np.float64)
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    s = np.zeros(n)
+    np.add.at(s, rowind, np.abs(values))
+    off = rowind != cols
+    np.add.at(s, cols[off], np.abs(values[off]))
+    return float(s.max()) if n else 0.0
+
+
+def residual_measures(n, colptr, rowind, values, x, b):
+    """Per right-hand side: (relres, eta).  x, b: [nrhs, n] (or [n])."""
+    x2 = np.asarray(x, np.float64).reshape(-1, n)
+    b2 = np.asarray(b, np.float64).reshape(-1, n)
+    r = b2 - spmv(n, colptr, rowind, values, x2)
+    an = norm_inf_sym(n, colptr, rowind, values)
+    relres = np.linalg.norm(r, axis=1) / np.maximum(np.linalg.norm(b2, axis=1), 1e-300)
+    eta = np.abs(r).max(1) / (an * np.abs(x2).max(1) + np.abs(b2).max(1))
+    return relres, eta
+
+
+def forward_error(x, x_ref) -> float:
+    x = np.asarray(x, np.float64).ravel()
+    x_ref = np.asarray(x_ref, np.float64).ravel()
+    return float(np.abs(x - x_ref).max() / max(np.abs(x_ref).max(), 1e-300))
+
+
+def factor_error(Lcolptr, Lx, Lx_ref) -> float:
+    """max over columns of ||dL[:, j]||_inf / ||L_ref[:, j]||_inf."""
+    Lcolptr = np.asarray(Lcolptr, np.int64)
+    d = np.abs(np.asarray(Lx, np.float64) - np.asarray(Lx_ref, np.float64))
+    a = np.abs(np.asarray(Lx_ref, np.float64))
+    n = len(Lcolptr) - 1
+    counts = np.diff(Lcolptr)
+    nz = counts > 0
+    starts = Lcolptr[:-1][nz]
+    dm = np.maximum.reduceat(d, starts) if d.size else np.zeros(0)
+    am = np.maximum.reduceat(a, starts) if a.size else np.zeros(0)
+    if dm.size == 0:
+        return 0.0
+    return float(np.max(dm / np.maximum(am, 1e-300)))
+
+
+def to_dense_permuted(n, colptr, rowind, values, perm=None) -> np.ndarray:
+    """Dense P A P^T (for small test cases only)."""
+    A = np.zeros((n, n))
+    colptr = np.asarray(colptr, np.int64)
+    for c in range(n):
+        for p in range(colptr[c], colptr[c + 1]):
+            r = int(rowind[p])
+            A[r, c] = values[p]
+            A[c, r] = values[p]
+    if perm is not None:
+        perm = np.asarray(perm, np.int64)
+        A = A[np.ix_(perm, perm)]
+    return A
+
+
+def L_dense(sym: Symbolic, Lx) -> np.ndarray:
+    L = np.zeros((sym.n, sym.n))
+    for j in range(sym.n):
+        for q in range(sym.Lcolptr[j], sym.Lcolptr[j + 1]):
+            L[sym.Lrowind[q], j] = Lx[q]
+    return L

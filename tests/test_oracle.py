@@ -1,0 +1,293 @@
+"""Pins for the CPU oracle, against results fixed by mathematics rather than
+by the oracle itself: dense LAPACK Cholesky (numpy), closed forms of the 1D
+Laplacian, exact results on diagonal matrices, brute-force dense boolean
+elimination for the pattern, and the closed-form fill count of the natural
+5-point grid.  None of these tests needs a GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+def brute_symbolic(n, colptr, rowind, perm=None):
+    """Dense boolean elimination: eliminating k joins all its later
+    neighbours into a clique (structural fill, nothing cancels)."""
+    B = np.zeros((n, n), dtype=bool)
+    for c in range(n):
+        for p in range(colptr[c], colptr[c + 1]):
+            r = int(rowind[p])
+            B[r, c] = B[c, r] = True
+    if perm is not None:
+        perm = np.asarray(perm, np.int64)
+        B = B[np.ix_(perm, perm)]
+    for k in range(n):
+        rows = np.nonzero(B[k + 1:, k])[0] + k + 1
+        if rows.size:
+            B[np.ix_(rows, rows)] = True
+    parent = np.full(n, -1, dtype=np.int32)
+    Lcolptr = [0]
+    Lrowind = []
+    for j in range(n):
+        rows = np.nonzero(B[j:, j])[0] + j
+        below = rows[rows > j]
+        if below.size:
+            parent[j] = below.min()
+        Lrowind.extend(rows.tolist())
+        Lcolptr.append(len(Lrowind))
+    return parent, np.array(Lcolptr, np.int64), np.array(Lrowind, np.int32)
+
+
+def path_laplacian(n):
+    """tridiag(-1, 2, -1) in lower CSC."""
+    e = np.stack([np.arange(n - 1), np.arange(1, n)], 1)
+    pat = W.lower_csc_from_edges(n, e)
+    vals = np.where(pat.rows == pat.cols, 2.0, -1.0)
+    return pat, vals
+
+
+def spd_cases():
+    out = []
+    for seed, (n, dens) in enumerate([(1, 0.0), (2, 1.0), (5, 0.5), (17, 0.2),
+                                      (40, 0.08), (64, 0.05), (64, 0.3)]):
+        out.append(W.random_spd(n, dens, seed=100 + seed, perm=True))
+    out.append(W.small_grid((6, 5), order="natural", seed=3))
+    out.append(W.small_grid((4, 4, 3), order="nd", seed=4))
+    out.append(W.small_grid((7, 9), order="nd", seed=5))
+    return out
+
+
+@pytest.mark.parametrize("case", spd_cases(), ids=lambda w: "%s_n%d" % (w.name, w.pattern.n))
+def test_symbolic_matches_brute_force(case):
+    p = case.pattern
+    s = oracle.symbolic(p.n, p.colptr, p.rowind, case.perm)
+    parent, Lcolptr, Lrowind = brute_symbolic(p.n, p.colptr, p.rowind, case.perm)
+    assert np.array_equal(s.parent, parent)
+    assert np.array_equal(s.Lcolptr, Lcolptr)
+    assert np.array_equal(s.Lrowind, Lrowind)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_symbolic_random_patterns_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(20, 120))
+    w = W.random_spd(n, float(rng.uniform(0.01, 0.1)), seed=500 + seed, perm=True)
+    p = w.pattern
+    s = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    parent, Lcolptr, Lrowind = brute_symbolic(p.n, p.colptr, p.rowind, w.perm)
+    assert np.array_equal(s.parent, parent)
+    assert np.array_equal(s.Lcolptr, Lcolptr)
+    assert np.array_equal(s.Lrowind, Lrowind)
+    # column counts never grow by more than one up the tree
+    c = s.counts
+    for j in range(n):
+        if s.parent[j] >= 0:
+            assert c[j] <= c[s.parent[j]] + 1
+
+
+def test_natural_grid_fill_closed_form():
+    """Natural order k x k 5-point grid: the band fills completely, so
+    nnz(L) = 1 + 2(k-1) + (n-k)(k+1) and the etree is a chain."""
+    for k in (3, 8, 32):
+        w = W.small_grid((k, k), order="natural")
+        p = w.pattern
+        s = oracle.symbolic(p.n, p.colptr, p.rowind, None)
+        n = k * k
+        assert s.nnzL == 1 + 2 * (k - 1) + (n - k) * (k + 1)
+        assert np.array_equal(s.parent[:-1], np.arange(1, n))
+        assert s.parent[-1] == -1
+    w = W.config(0)
+    s = oracle.symbolic(w.pattern.n, w.pattern.colptr, w.pattern.rowind, w.perm)
+    assert s.nnzL == 32799
+
+
+@pytest.mark.parametrize("case", spd_cases(), ids=lambda w: "%s_n%d" % (w.name, w.pattern.n))
+def test_factor_matches_lapack(case):
+    p = case.pattern
+    s = oracle.symbolic(p.n, p.colptr, p.rowind, case.perm)
+    Lx, info = oracle.factor(p.n, p.colptr, p.rowind, case.values[0], s)
+    assert info == 0
+    A = oracle.to_dense_permuted(p.n, p.colptr, p.rowind, case.values[0], case.perm)
+    Lref = np.linalg.cholesky(A)
+    L = oracle.L_dense(s, Lx)
+    scale = np.abs(Lref).max()
+    assert np.abs(L - Lref).max() <= 1e-13 * scale
+    # the structural pattern holds every nonzero of the dense factor
+    assert np.all(np.abs(Lref[L == 0]) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 100, 1000])
+def test_path_laplacian_closed_form(n):
+    """tridiag(-1,2,-1): L_kk = sqrt((k+1)/k), L_{k+1,k} = -sqrt(k/(k+1))
+    (1-based), prod L_kk = sqrt(n+1); with b = 1, x_i = i(n+1-i)/2."""
+    pat, vals = path_laplacian(n)
+    s = oracle.symbolic(n, pat.colptr, pat.rowind, None)
+    Lx, info = oracle.factor(n, pat.colptr, pat.rowind, vals, s)
+    assert info == 0
+    k = np.arange(1, n + 1, dtype=np.float64)
+    diag = Lx[s.Lcolptr[:-1]]
+    assert np.allclose(diag, np.sqrt((k + 1) / k), rtol=1e-14, atol=0)
+    if n > 1:
+        sub = Lx[s.Lcolptr[:-2] + 1]
+        assert np.allclose(sub, -np.sqrt(k[:-1] / (k[:-1] + 1)), rtol=1e-14, atol=0)
+    assert math.isclose(float(np.prod(diag)), math.sqrt(n + 1), rel_tol=1e-12)
+    x = oracle.solve(s, Lx, np.ones(n))
+    assert np.allclose(x, k * (n + 1 - k) / 2, rtol=1e-11, atol=0)
+
+
+def test_path_laplacian_inverse_closed_form():
+    """A^{-1}_ij = min(i,j)(n+1-max(i,j))/(n+1) (1-based)."""
+    n = 12
+    pat, vals = path_laplacian(n)
+    s = oracle.symbolic(n, pat.colptr, pat.rowind, None)
+    Lx, _ = oracle.factor(n, pat.colptr, pat.rowind, vals, s)
+    Ainv = oracle.solve(s, Lx, np.eye(n))
+    i = np.arange(1, n + 1)[:, None]
+    j = np.arange(1, n + 1)[None, :]
+    ref = np.minimum(i, j) * (n + 1 - np.maximum(i, j)) / (n + 1)
+    assert np.abs(Ainv - ref).max() <= 1e-13
+
+
+def test_diagonal_matrix_exact():
+    n = 50
+    rng = np.random.default_rng(1)
+    pat = W.lower_csc_from_edges(n, np.zeros((0, 2)))
+    d = rng.uniform(0.1, 10, n)
+    perm = rng.permutation(n).astype(np.int32)
+    s = oracle.symbolic(n, pat.colptr, pat.rowind, perm)
+    assert np.all(s.parent == -1)
+    Lx, info = oracle.factor(n, pat.colptr, pat.rowind, d, s)
+    assert info == 0
+    assert np.array_equal(Lx, np.array([math.sqrt(v) for v in d[perm]]))
+    b = rng.uniform(-1, 1, n)
+    x = oracle.solve(s, Lx, b)
+    assert np.allclose(x, b / d, rtol=4e-16 * 4, atol=0)
+
+
+def test_not_spd_reports_first_failed_step():
+    n = 30
+    pat, vals = path_laplacian(n)
+    for p in (0, 1, 9, 29):
+        v = vals.copy()
+        v[pat.colptr[p]] = 0.4  # pivot p becomes 0.4 - p/(p+1) < 0 for p >= 1
+        if p == 0:
+            v[pat.colptr[p]] = -1.0
+        s = oracle.symbolic(n, pat.colptr, pat.rowind, None)
+        _, info = oracle.factor(n, pat.colptr, pat.rowind, v, s)
+        assert info == p + 1
+    # NaN on the diagonal fails the d > 0 test as well
+    v = vals.copy(); v[pat.colptr[4]] = np.nan
+    _, info = oracle.factor(n, pat.colptr, pat.rowind, v, s)
+    assert info == 5
+    # with a permutation the step is counted in elimination order
+    perm = np.arange(n)[::-1].astype(np.int32)
+    v = vals.copy(); v[pat.colptr[n - 1]] = -3.0  # vertex n-1 is eliminated first
+    s = oracle.symbolic(n, pat.colptr, pat.rowind, perm)
+    _, info = oracle.factor(n, pat.colptr, pat.rowind, v, s)
+    assert info == 1
+
+
+def test_disconnected_pattern_is_blockwise():
+    a = W.small_grid((5, 4), order="nd", seed=11)
+    b = W.small_grid((3, 3, 2), order="nd", seed=12)
+    na, nb = a.pattern.n, b.pattern.n
+    ea = np.stack([a.pattern.rows, a.pattern.cols], 1)[a.pattern.offdiag_mask()]
+    eb = np.stack([b.pattern.rows, b.pattern.cols], 1)[b.pattern.offdiag_mask()] + na
+    pat = W.lower_csc_from_edges(na + nb, np.concatenate([ea, eb]))
+    # values: copy through (row, col) keys
+    va = dict(zip(zip(a.pattern.rows.tolist(), a.pattern.cols.tolist()), a.values[0]))
+    vb = dict(zip(zip((b.pattern.rows + na).tolist(), (b.pattern.cols + na).tolist()), b.values[0]))
+    va.update(vb)
+    vals = np.array([va[(r, c)] for r, c in zip(pat.rows.tolist(), pat.cols.tolist())])
+    perm = np.concatenate([a.perm, b.perm + na]).astype(np.int32)
+    s = oracle.symbolic(pat.n, pat.colptr, pat.rowind, perm)
+    assert int(np.sum(s.parent == -1)) >= 2
+    Lx, info = oracle.factor(pat.n, pat.colptr, pat.rowind, vals, s)
+    assert info == 0
+    sa = oracle.symbolic(na, a.pattern.colptr, a.pattern.rowind, a.perm)
+    La, _ = oracle.factor(na, a.pattern.colptr, a.pattern.rowind, a.values[0], sa)
+    sb = oracle.symbolic(nb, b.pattern.colptr, b.pattern.rowind, b.perm)
+    Lb, _ = oracle.factor(nb, b.pattern.colptr, b.pattern.rowind, b.values[0], sb)
+    assert np.array_equal(Lx, np.concatenate([La, Lb]))
+
+
+def test_residual_and_reconstruction_invariants():
+    w = W.config(0)
+    p = w.pattern
+    s = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[0], s)
+    assert info == 0
+    A = oracle.to_dense_permuted(p.n, p.colptr, p.rowind, w.values[0], w.perm)
+    L = oracle.L_dense(s, Lx)
+    cmax = int(s.counts.max())
+    assert np.linalg.norm(A - L @ L.T) <= 1e-14 * math.sqrt(cmax) * np.linalg.norm(A)
+    # strict diagonal dominance survives every Schur complement
+    assert np.all(Lx[s.Lcolptr[:-1]] ** 2 >= 0.01)
+    x = oracle.solve(s, Lx, w.b[0])
+    relres, eta = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[0], x, w.b[0])
+    assert relres[0] < 1e-13 and eta[0] < 1e-15
+    # spmv against the dense product
+    assert np.allclose(oracle.spmv(p.n, p.colptr, p.rowind, w.values[0], x[0]),
+                       oracle.to_dense_permuted(p.n, p.colptr, p.rowind, w.values[0]) @ x[0],
+                       rtol=0, atol=1e-12)
+
+
+def test_solution_independent_of_permutation():
+    w = W.small_grid((9, 8), order="natural", seed=21, nrhs=2)
+    p = w.pattern
+    xs = []
+    for perm in (None, W.grid_nd_perm((9, 8)),
+                 np.random.default_rng(0).permutation(p.n).astype(np.int32)):
+        s = oracle.symbolic(p.n, p.colptr, p.rowind, perm)
+        Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[0], s)
+        assert info == 0
+        xs.append(oracle.solve(s, Lx, w.b[0]))
+    for x in xs[1:]:
+        assert oracle.forward_error(x, xs[0]) < 1e-13
+
+
+def test_leading_block_is_cholesky_of_leading_submatrix():
+    """Rows < m of L are the factor of the leading m x m block of P A P^T."""
+    w = W.small_grid((6, 6, 2), order="nd", seed=31)
+    p = w.pattern
+    A = oracle.to_dense_permuted(p.n, p.colptr, p.rowind, w.values[0], w.perm)
+    for m in (1, 17, 40, p.n):
+        s = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm, nrows=m)
+        Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[0], s)
+        assert info == 0
+        L = oracle.L_dense(s, Lx)
+        Lref = np.linalg.cholesky(A[:m, :m])
+        assert np.abs(L[:m, :m] - Lref).max() <= 1e-13 * np.abs(Lref).max()
+        assert np.all(L[m:, :] == 0)
+
+
+def test_multiple_rhs_columns_are_independent():
+    w = W.small_grid((5, 5, 3), order="nd", seed=41, nrhs=3)
+    p = w.pattern
+    s = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    Lx, _ = oracle.factor(p.n, p.colptr, p.rowind, w.values[0], s)
+    X = oracle.solve(s, Lx, w.b[0])
+    for r in range(3):
+        assert np.array_equal(X[r], oracle.solve(s, Lx, w.b[0][r]))
+    A = oracle.to_dense_permuted(p.n, p.colptr, p.rowind, w.values[0])
+    assert np.allclose(np.linalg.solve(A, w.b[0].T).T, X, rtol=0, atol=1e-12)
+
+
+def test_golden_fixture_reproduces():
+    """tests/golden/grid2d_4x4_nd.txt was written by make_golden.py, which
+    calls only the oracle; a change of the oracle's arithmetic shows here."""
+    import os
+    from tests.golden.make_golden import case_grid2d_4x4, read_fixture
+    path = os.path.join(os.path.dirname(__file__), "golden", "grid2d_4x4_nd.txt")
+    fx = read_fixture(path)
+    w = case_grid2d_4x4()
+    p = w.pattern
+    s = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    Lx, _ = oracle.factor(p.n, p.colptr, p.rowind, w.values[0], s)
+    x = oracle.solve(s, Lx, w.b[0])
+    assert np.array_equal(s.Lcolptr, fx["Lcolptr"])
+    assert np.array_equal(s.Lrowind, fx["Lrowind"])
+    assert np.array_equal(Lx, fx["Lx"])
+    assert np.array_equal(x.ravel(), fx["x"])

@@ -1,0 +1,381 @@
+"""Seeded synthetic SPD systems on fixed sparsity patterns.
+
+This module builds inputs only: lower-triangular CSC patterns, value sets,
+right-hand sides and a geometric nested-dissection permutation. It contains
+none of the factorization arithmetic, so both the CPU oracle and the GPU
+library can be fed from it without sharing any code of the method.
+
+Conventions (used by every caller):
+  * A symmetric matrix is passed by its lower triangle in CSC form:
+    ``colptr`` int64[n+1], ``rowind`` int32[nnz], rows sorted ascending inside
+    each column, diagonal entry first.  ``values`` is float64[batch, nnz] in
+    the same entry order.
+  * ``perm`` is int32[n] with ``perm[k]`` = original index of the vertex that
+    is eliminated k-th (new k <- old perm[k]).
+
+The workloads stand in for the mesh-derived systems of the paper's
+evaluation (cotangent Laplacian plus mass matrix, Sec. 5.3; the
+factor/solve that follows assembly in Sec. 5.5 and 5.6).  No mesh or dataset
+from the paper is used; every input is generated from a seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "SymPattern",
+    "Workload",
+    "grid_edges",
+    "lower_csc_from_edges",
+    "grid_nd_perm",
+    "laplacian_values",
+    "rhs",
+    "trimesh_edges_weights",
+    "config",
+    "small_grid",
+    "random_spd",
+]
+
+
+@dataclass
+class SymPattern:
+    """Lower-triangular CSC pattern of a symmetric matrix (diagonal first)."""
+
+    n: int
+    colptr: np.ndarray  # int64[n+1]
+    rowind: np.ndarray  # int32[nnz]
+    # For every stored entry: its (row, col) in original numbering.
+    rows: np.ndarray = field(repr=False, default=None)
+    cols: np.ndarray = field(repr=False, default=None)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colptr[-1])
+
+    def offdiag_mask(self) -> np.ndarray:
+        return self.rows != self.cols
+
+
+@dataclass
+class Workload:
+    """One pattern with a batch of value sets and right-hand sides."""
+
+    name: str
+    pattern: SymPattern
+    perm: Optional[np.ndarray]  # int32[n] or None (natural order)
+    values: np.ndarray  # float64[batch, nnz]
+    b: np.ndarray  # float64[batch, nrhs, n]
+    seed: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def batch(self) -> int:
+        return int(self.values.shape[0])
+
+    @property
+    def nrhs(self) -> int:
+        return int(self.b.shape[1])
+
+
+# ---------------------------------------------------------------------------
+# patterns
+# ---------------------------------------------------------------------------
+
+def grid_edges(dims: Sequence[int]) -> Tuple[int, np.ndarray]:
+    """Edges of the 5-point (2D) or 7-point (3D) grid stencil.
+
+    Vertex (x, y, z) has index x + nx*(y + ny*z).  Returns (n, edges[m, 2])
+    with edges[:, 0] < edges[:, 1].
+    """
+    dims = tuple(int(d) for d in dims)
+    while len(dims) < 3:
+        dims = dims + (1,)
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64).reshape(nz, ny, nx)
+    edges = []
+    if nx > 1:
+        edges.append(np.stack([idx[:, :, :-1].ravel(), idx[:, :, 1:].ravel()], 1))
+    if ny > 1:
+        edges.append(np.stack([idx[:, :-1, :].ravel(), idx[:, 1:, :].ravel()], 1))
+    if nz > 1:
+        edges.append(np.stack([idx[:-1, :, :].ravel(), idx[1:, :, :].ravel()], 1))
+    if edges:
+        e = np.concatenate(edges, 0)
+    else:
+        e = np.zeros((0, 2), dtype=np.int64)
+    return n, e
+
+
+def lower_csc_from_edges(n: int, edges: np.ndarray) -> SymPattern:
+    """Lower CSC pattern with a diagonal plus one entry per undirected edge."""
+    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    lo = np.minimum(edges[:, 0], edges[:, 1])
+    hi = np.maximum(edges[:, 0], edges[:, 1])
+    if np.any(lo == hi):
+        raise ValueError("self loops are not edges")
+    diag = np.arange(n, dtype=np.int64)
+    cols = np.concatenate([diag, lo])
+    rows = np.concatenate([diag, hi])
+    order = np.lexsort((rows, cols))
+    cols = cols[order]
+    rows = rows[order]
+    if len(rows) > 1:
+        dup = (cols[1:] == cols[:-1]) & (rows[1:] == rows[:-1])
+        if np.any(dup):
+            raise ValueError("duplicate edges")
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(colptr, cols + 1, 1)
+    colptr = np.cumsum(colptr)
+    return SymPattern(n=n, colptr=colptr, rowind=rows.astype(np.int32),
+                      rows=rows, cols=cols)
+
+
+def grid_nd_perm(dims: Sequence[int], leaf: int = 8) -> np.ndarray:
+    """Geometric nested-dissection order of a box grid.
+
+    The box is split along its longest axis (ties: x, then y, then z) at the
+    plane m = floor((lo + hi) / 2).  Elimination order is: left part, right
+    part, then the separator plane (numbered x fastest).  Boxes with at most
+    ``leaf`` vertices are numbered naturally.  Returns perm with
+    perm[new] = old.
+    """
+    dims = tuple(int(d) for d in dims)
+    while len(dims) < 3:
+        dims = dims + (1,)
+    nx, ny, nz = dims
+    out: List[np.ndarray] = []
+
+    def box_ids(lo, hi):
+        xs = np.arange(lo[0], hi[0] + 1)
+        ys = np.arange(lo[1], hi[1] + 1)
+        zs = np.arange(lo[2], hi[2] + 1)
+        z, y, x = np.meshgrid(zs, ys, xs, indexing="ij")
+        return (x + nx * (y + ny * z)).ravel()
+
+    stack = [(tuple([0, 0, 0]), tuple([nx - 1, ny - 1, nz - 1]), 0)]
+    # explicit stack to avoid recursion limits; state 0 = visit, 1 = emit sep
+    while stack:
+        lo, hi, state = stack.pop()
+        if state == 1:
+            out.append(box_ids(lo, hi))
+            continue
+        ext = [hi[a] - lo[a] + 1 for a in range(3)]
+        if min(ext) <= 0:
+            continue
+        if ext[0] * ext[1] * ext[2] <= leaf:
+            out.append(box_ids(lo, hi))
+            continue
+        a = int(np.argmax(ext))  # first maximum: x before y before z
+        m = (lo[a] + hi[a]) // 2
+        left_hi = list(hi); left_hi[a] = m - 1
+        right_lo = list(lo); right_lo[a] = m + 1
+        sep_lo = list(lo); sep_lo[a] = m
+        sep_hi = list(hi); sep_hi[a] = m
+        # pushed in reverse: left is processed first, then right, then sep
+        stack.append((tuple(sep_lo), tuple(sep_hi), 1))
+        stack.append((tuple(right_lo), tuple(hi), 0))
+        stack.append((tuple(lo), tuple(left_hi), 0))
+    perm = np.concatenate(out) if out else np.zeros(0, dtype=np.int64)
+    assert perm.size == nx * ny * nz
+    return perm.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# values
+# ---------------------------------------------------------------------------
+
+def laplacian_values(pat: SymPattern, rng: np.random.Generator) -> np.ndarray:
+    """Grid-Laplacian value distribution (strictly diagonally dominant).
+
+    Off-diagonals: -U(0.5, 1.5), drawn in storage order.  Diagonal: the sum of
+    |off-diagonals| of the row (both triangles) plus U(0.01, 0.1), drawn in
+    vertex order.
+    """
+    off = pat.offdiag_mask()
+    vals = np.zeros(pat.nnz, dtype=np.float64)
+    noff = int(off.sum())
+    vals[off] = -rng.uniform(0.5, 1.5, size=noff)
+    rowsum = np.zeros(pat.n, dtype=np.float64)
+    np.add.at(rowsum, pat.rows[off], np.abs(vals[off]))
+    np.add.at(rowsum, pat.cols[off], np.abs(vals[off]))
+    shift = rng.uniform(0.01, 0.1, size=pat.n)
+    vals[~off] = (rowsum + shift)[pat.rows[~off]]
+    return vals
+
+
+def rhs(n: int, nrhs: int, rng: np.random.Generator) -> np.ndarray:
+    return rng.uniform(-1.0, 1.0, size=(nrhs, n))
+
+
+def trimesh_edges_weights(k: int, rng: np.random.Generator):
+    """Jittered k x k triangle mesh and its clipped cotangent edge weights.
+
+    Vertex (i, j) sits at (i, j) + U(-0.2, 0.2)^2; every quad is split along
+    (i, j)-(i+1, j+1).  The weight of edge (a, b) is half the sum of the
+    cotangents of the angles opposite to it, clipped to [0.05, 2].
+    Vertex index: i + k*j.
+    """
+    n = k * k
+    jit = rng.uniform(-0.2, 0.2, size=(n, 2))
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
+    pos = np.stack([ii.ravel(), jj.ravel()], 1).astype(np.float64) + jit
+    q = np.arange(k - 1)
+    qi, qj = np.meshgrid(q, q, indexing="xy")
+    v00 = (qi + k * qj).ravel()
+    v10 = v00 + 1
+    v11 = v00 + 1 + k
+    v01 = v00 + k
+    tris = np.concatenate([np.stack([v00, v10, v11], 1),
+                           np.stack([v00, v11, v01], 1)], 0)
+    ea, eb, cot = [], [], []
+    for c in range(3):
+        a = tris[:, (c + 1) % 3]
+        b = tris[:, (c + 2) % 3]
+        u = pos[a] - pos[tris[:, c]]
+        v = pos[b] - pos[tris[:, c]]
+        dot = (u * v).sum(1)
+        cross = np.abs(u[:, 0] * v[:, 1] - u[:, 1] * v[:, 0])
+        ea.append(a); eb.append(b); cot.append(dot / cross)
+    ea = np.concatenate(ea); eb = np.concatenate(eb); cot = np.concatenate(cot)
+    lo = np.minimum(ea, eb); hi = np.maximum(ea, eb)
+    key = lo.astype(np.int64) * n + hi
+    uk, inv = np.unique(key, return_inverse=True)
+    w = np.zeros(uk.size, dtype=np.float64)
+    np.add.at(w, inv, 0.5 * cot)
+    w = np.clip(w, 0.05, 2.0)
+    edges = np.stack([uk // n, uk % n], 1)
+    return n, edges, w
+
+
+def _stiffness_mass_values(pat: SymPattern, edges: np.ndarray, w: np.ndarray,
+                           mass: np.ndarray, mass_scale: float) -> np.ndarray:
+    n = pat.n
+    # position of each edge (lo, hi) in storage: storage is sorted by (col,row)
+    key_store = pat.cols.astype(np.int64) * n + pat.rows
+    key_edge = edges[:, 0].astype(np.int64) * n + edges[:, 1]
+    pos = np.searchsorted(key_store, key_edge)
+    vals = np.zeros(pat.nnz, dtype=np.float64)
+    vals[pos] = -w
+    deg = np.zeros(n, dtype=np.float64)
+    np.add.at(deg, edges[:, 0], w)
+    np.add.at(deg, edges[:, 1], w)
+    diag = ~pat.offdiag_mask()
+    vals[diag] = (deg + mass_scale * mass)[pat.rows[diag]]
+    return vals
+
+
+# ---------------------------------------------------------------------------
+# named configurations
+# ---------------------------------------------------------------------------
+
+def _streams(seed: int, k: int):
+    return np.random.SeedSequence(seed).spawn(k)
+
+
+def _grid_workload(name: str, dims, order: str, batch: int, nrhs: int,
+                   seed: int, rng_vals=None, rng_rhs=None) -> Workload:
+    n, e = grid_edges(dims)
+    pat = lower_csc_from_edges(n, e)
+    perm = grid_nd_perm(dims) if order == "nd" else None
+    if rng_vals is None:
+        ss = _streams(seed, 4)
+        vss = ss[1].spawn(batch)
+        rss = ss[2].spawn(batch)
+        rng_vals = [np.random.Generator(np.random.PCG64(s)) for s in vss]
+        rng_rhs = [np.random.Generator(np.random.PCG64(s)) for s in rss]
+    vals = np.stack([laplacian_values(pat, rng_vals[s]) for s in range(batch)])
+    b = np.stack([rhs(n, nrhs, rng_rhs[s]) for s in range(batch)])
+    return Workload(name=name, pattern=pat, perm=perm, values=vals, b=b,
+                    seed=seed, extra={"dims": tuple(dims), "order": order})
+
+
+def config(idx: int, batch: Optional[int] = None) -> List[Workload] | Workload:
+    """The five benchmark configurations (seed = 1000 + idx).
+
+    0: 2D 5-point 32x32, natural order, 1 system, 1 RHS (FP64)
+    1: 3D 7-point 64^3, nested dissection, 1 system, 1 RHS (FP64)
+    2: jittered 512x512 triangle mesh, cotangent stiffness + 1e-3 * lumped
+       mass, 64 value sets (weights re-jittered by U(0.9, 1.1)), 3 RHS each
+    3: uneven batch: 2D 16^2, 32^2, 64^2, 128^2 and 3D 8^3, 12^3, 16^3, 24^3,
+       32 value sets each (returns a list of 8 workloads)
+    """
+    seed = 1000 + idx
+    if idx == 0:
+        return _grid_workload("grid2d_32x32_natural", (32, 32), "natural",
+                              batch or 1, 1, seed)
+    if idx == 1:
+        return _grid_workload("grid3d_64^3_nd", (64, 64, 64), "nd",
+                              batch or 1, 1, seed)
+    if idx == 2:
+        return trimesh_workload(512, batch or 64, 3, seed)
+    if idx == 3:
+        shapes = [(16, 16), (32, 32), (64, 64), (128, 128),
+                  (8, 8, 8), (12, 12, 12), (16, 16, 16), (24, 24, 24)]
+        ss = _streams(seed, len(shapes))
+        out = []
+        nb = batch or 32
+        for s, dims in enumerate(shapes):
+            sub = ss[s].spawn(2)
+            rv = [np.random.Generator(np.random.PCG64(c)) for c in sub[0].spawn(nb)]
+            rr = [np.random.Generator(np.random.PCG64(c)) for c in sub[1].spawn(nb)]
+            name = "grid%dd_%s_nd" % (len(dims), "x".join(map(str, dims)))
+            out.append(_grid_workload(name, dims, "nd", nb, 1, seed,
+                                      rng_vals=rv, rng_rhs=rr))
+        return out
+    raise ValueError("unknown configuration %r" % (idx,))
+
+
+def trimesh_workload(k: int, batch: int, nrhs: int, seed: int,
+                     mass_coeff: float = 1e-3) -> Workload:
+    ss = _streams(seed, 4)
+    geo = np.random.Generator(np.random.PCG64(ss[0]))
+    n, edges, w = trimesh_edges_weights(k, geo)
+    mass = geo.uniform(0.5, 1.5, size=n) / n
+    pat = lower_csc_from_edges(n, edges)
+    vss = ss[1].spawn(batch)
+    rss = ss[2].spawn(batch)
+    vals = []
+    for s in range(batch):
+        r = np.random.Generator(np.random.PCG64(vss[s]))
+        ws = np.clip(w * r.uniform(0.9, 1.1, size=w.size), 0.05, 2.0)
+        vals.append(_stiffness_mass_values(pat, edges, ws, mass, mass_coeff))
+    b = np.stack([rhs(n, nrhs, np.random.Generator(np.random.PCG64(s)))
+                  for s in rss])
+    return Workload(name="trimesh_%dx%d_nd" % (k, k), pattern=pat,
+                    perm=grid_nd_perm((k, k)), values=np.stack(vals), b=b,
+                    seed=seed, extra={"dims": (k, k), "order": "nd"})
+
+
+def small_grid(dims, order="nd", batch=1, nrhs=1, seed=7) -> Workload:
+    """Any grid with the Laplacian value rule; handy for tests."""
+    return _grid_workload("grid_%s_%s" % ("x".join(map(str, dims)), order),
+                          dims, order, batch, nrhs, seed)
+
+
+def random_spd(n: int, density: float, seed: int, batch: int = 1,
+               nrhs: int = 1, perm: bool = True) -> Workload:
+    """Random symmetric pattern with the Laplacian value rule (SPD by strict
+    diagonal dominance) and an optional random permutation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = int(round(density * n * (n - 1) / 2))
+    if n > 1 and m > 0:
+        a = rng.integers(0, n, size=4 * m + 8)
+        b = rng.integers(0, n, size=4 * m + 8)
+        keep = a != b
+        lo = np.minimum(a[keep], b[keep]); hi = np.maximum(a[keep], b[keep])
+        key = np.unique(lo.astype(np.int64) * n + hi)[:m]
+        rng.shuffle(key)
+        key = np.sort(key[:m])
+        edges = np.stack([key // n, key % n], 1)
+    else:
+        edges = np.zeros((0, 2), dtype=np.int64)
+    pat = lower_csc_from_edges(n, edges)
+    vals = np.stack([laplacian_values(pat, rng) for _ in range(batch)])
+    b = np.stack([rhs(n, nrhs, rng) for _ in range(batch)])
+    p = rng.permutation(n).astype(np.int32) if perm else None
+    return Workload(name="random_%d" % n, pattern=pat, perm=p, values=vals,
+                    b=b, seed=seed)
