@@ -1,0 +1,251 @@
+/*
+ * spchol.h -- C ABI of the MI355X sparse Cholesky library (libspchol.so).
+ *
+ * The library factors symmetric positive definite matrices A whose sparsity
+ * pattern is fixed while the values change, and solves A x = b with the
+ * factor.  This is the setting the paper targets (Sec. 3.3: control flow
+ * fixed by the input structure, cost amortized over many runs, few distinct
+ * expression shapes): a one-time symbolic pass over the pattern plays the
+ * role of the paper's expression-graph unrolling, decomposition and
+ * grouping (Sec. 3.2, 4.2, 4.3), and each numeric call replays the grouped
+ * work on the GPU.
+ *
+ * What is computed (textbook sparse Cholesky; the paper does not define it):
+ *   A^ = P A P^T with A^_ij = A_{perm[i], perm[j]},  A^ = L L^T,
+ *   x  = P^T L^{-T} L^{-1} P b.
+ *
+ * Conventions for every entry point
+ *   - Every function returns an sc_status; no C++ exception crosses the ABI.
+ *   - Pattern input: the lower triangle (diagonal included) in CSC form,
+ *     colptr int64[n+1], rowind int32[nnz], rows strictly ascending inside a
+ *     column and the diagonal first.  Anything else is SC_EPATTERN.
+ *   - Values: float64, one value per stored pattern entry, in pattern order.
+ *     Each off-diagonal value stands for both A_ij and A_ji.
+ *   - perm (nullable = identity): int32[n], new index k <- old perm[k].
+ *   - Pointers named *_host are host memory, *_dev device memory.  The
+ *     caller owns them; the library only borrows them for the call (and,
+ *     for asynchronous calls, until the stream reaches that point).
+ *   - stream is a hipStream_t passed as void* (NULL = default stream).
+ *     Numeric calls are asynchronous on that stream.
+ *   - A plan is immutable after sc_analyze and may be shared by threads and
+ *     streams.  A numeric object holds one batch of factors; calls that use
+ *     the same numeric object must be ordered by the caller (same stream).
+ */
+#ifndef SPCHOL_H
+#define SPCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SC_OK = 0,
+    SC_EINVAL = -1,   /* bad argument (NULL, size, dtype, batch index ...) */
+    SC_EPATTERN = -2, /* malformed pattern or permutation                  */
+    SC_ENOMEM = -3,   /* host or device allocation failed                   */
+    SC_EDEVICE = -4,  /* a HIP runtime call failed                          */
+    SC_ENOTSPD = -5,  /* some matrix of the batch has a non-positive pivot  */
+    SC_ENOCONV = -6   /* iterative refinement did not meet its tolerance    */
+} sc_status;
+
+typedef enum { SC_F64 = 0, SC_F32 = 1 } sc_dtype;
+
+typedef struct sc_plan sc_plan_t;       /* symbolic analysis (host + device) */
+typedef struct sc_numeric sc_numeric_t; /* numeric factors of one batch      */
+
+/* Options of the symbolic pass.  Fill with sc_options_default first. */
+typedef struct {
+    int32_t relax;        /* 1: merge a supernode into its parent when the
+                             columns are contiguous and few explicit zeros
+                             are added (default); 0: fundamental only     */
+    int32_t relax_cols;   /* always merge while the merged width <= this  */
+    double relax_zeros;   /* otherwise merge while the fraction of stored
+                             zeros of the merged block stays below this   */
+    int32_t small_front;  /* fronts with at most this many rows run in one
+                             workgroup; larger ones use the tiled kernels
+                             (0 = library default)                         */
+} sc_options;
+
+/* Sizes of a plan (per matrix of a batch). */
+typedef struct {
+    int64_t n;          /* order                                          */
+    int64_t nnzA;       /* stored entries of the lower triangle of A      */
+    int64_t nnzL;       /* structural nonzeros of L (exact pattern)       */
+    int64_t nfund;      /* fundamental supernodes                         */
+    int64_t nsuper;     /* supernodes after amalgamation                  */
+    int64_t nlevels;    /* levels of the supernodal elimination tree      */
+    int64_t L_store;    /* scalars of supernodal L storage (with padding) */
+    int64_t U_store;    /* scalars of update-matrix workspace             */
+    int64_t max_front;  /* largest front (rows)                           */
+    int64_t max_width;  /* widest supernode (columns)                     */
+    double flops;       /* sum_j c_j^2 over the exact column counts c_j   */
+    int64_t etree_height; /* height of the column elimination tree        */
+} sc_plan_stats;
+
+/* Human-readable name of a status code (static string). */
+const char *sc_status_string(sc_status s);
+
+/* Default options. */
+sc_status sc_options_default(sc_options *opt);
+
+/*
+ * Symbolic analysis of the pattern (host only, no GPU work): validation,
+ * permutation, elimination tree, column counts, fundamental and relaxed
+ * supernodes, supernodal tree levels (longest path from the leaves, so
+ * every dependency sits at a strictly lower level), relative index maps
+ * and the value scatter map.  The plan copies what it needs; the inputs
+ * may be freed after the call.  Device copies are made on first use.
+ * Errors: SC_EINVAL (NULL pointers, n < 1), SC_EPATTERN (unsorted or
+ * duplicate rows, a row below the diagonal missing or out of range,
+ * missing or misplaced diagonal, colptr not monotone, perm not a
+ * permutation), SC_ENOMEM.
+ */
+sc_status sc_analyze(int64_t n, const int64_t *colptr_host,
+                     const int32_t *rowind_host, const int32_t *perm_host,
+                     const sc_options *opt, sc_plan_t **plan_out);
+
+sc_status sc_plan_info(const sc_plan_t *plan, sc_plan_stats *out);
+
+/*
+ * Exact symbolic result in the permuted numbering, for checking: perm[n],
+ * parent[n] (column elimination tree, -1 for roots), Lcolptr[n+1] and
+ * Lrowind[nnzL] (row indices of every column of L ascending, diagonal
+ * first; the pattern is structural and excludes amalgamation padding).
+ * Any output pointer may be NULL.  All host memory.
+ */
+sc_status sc_plan_export_symbolic(const sc_plan_t *plan, int32_t *perm_host,
+                                  int32_t *parent_host, int64_t *Lcolptr_host,
+                                  int32_t *Lrowind_host);
+
+/*
+ * Supernode partition after amalgamation, for checking (host memory, any
+ * pointer may be NULL): first[nsuper+1] column ranges, parent[nsuper]
+ * supernodal elimination tree (-1 for roots), level[nsuper] (longest path
+ * from the leaves), rowptr[nsuper+1] and rows[rowptr[nsuper]]: the row
+ * structure of each front, ascending, starting with its own columns and
+ * including rows added by amalgamation.
+ */
+sc_status sc_plan_export_supernodes(const sc_plan_t *plan, int32_t *first_host,
+                                    int32_t *parent_host, int32_t *level_host,
+                                    int64_t *rowptr_host, int32_t *rows_host);
+
+void sc_plan_destroy(sc_plan_t *plan);
+
+/*
+ * Allocate device storage for `batch` factors of the plan's pattern in the
+ * given precision (SC_F64, or SC_F32: FP32 factor with FP32 accumulation).
+ * Uploads the plan to the current device if not done yet.
+ * Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_numeric_create(const sc_plan_t *plan, int32_t batch,
+                            sc_dtype dtype, sc_numeric_t **num_out);
+
+void sc_numeric_destroy(sc_numeric_t *num);
+
+/*
+ * Numeric factorization of a batch of value sets (same pattern):
+ * values_dev is float64 [batch][ldv] with ldv >= nnzA; set b is factored
+ * into factor b of `num`.  Overwrites any earlier factor in `num`.
+ * Asynchronous; a non-positive pivot does not stop the call -- query it
+ * with sc_factor_info.  Matrices of a batch never affect each other.
+ * Errors: SC_EINVAL, SC_EDEVICE.
+ */
+sc_status sc_factor(const sc_plan_t *plan, sc_numeric_t *num,
+                    const double *values_dev, int64_t ldv, void *stream);
+
+/*
+ * Per-matrix breakdown flags: info_host[b] = 0 if factor b is complete,
+ * else the smallest 1-based elimination step whose pivot failed d > 0
+ * (the factor beyond that step is unspecified).  Synchronizes the stream.
+ * Returns SC_ENOTSPD if any info_host[b] != 0.
+ */
+sc_status sc_factor_info(const sc_numeric_t *num, int32_t *info_host,
+                         void *stream);
+
+/*
+ * Solve A x = b for every matrix of the batch: b_dev is float64
+ * [batch][nrhs][ldb] (ldb >= n, original numbering), overwritten by x.
+ * The triangular solves read the stored factor (FP64 or FP32) and compute
+ * in FP64.  Asynchronous.  Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_solve(const sc_plan_t *plan, sc_numeric_t *num, double *b_dev,
+                   int32_t nrhs, int64_t ldb, void *stream);
+
+/* Outcome of sc_refine_solve for one (matrix, right-hand side). */
+typedef struct {
+    int32_t iters;   /* corrections applied                               */
+    int32_t clause;  /* 1: relres <= tol; 2: ||r||_2 <= 2 u ||A||_inf
+                        ||x||_2 (FP64 evaluation floor, u = 2^-53);
+                        0: neither after maxit corrections                */
+    double relres;   /* ||b - A x||_2 / ||b||_2 at exit                   */
+    double rnorm;    /* ||b - A x||_2                                     */
+    double bnorm;    /* ||b||_2                                           */
+    double xnorm;    /* ||x||_2                                           */
+} sc_refine_stats;
+
+/*
+ * Solve A x = b by iterative refinement with the factor in `num` (FP32 or
+ * FP64): x = solve(b); then while some system fails the stop rule and
+ * fewer than maxit corrections were applied: r = b - A x in FP64 (A from
+ * values_dev, the same values that were factored), d = solve(r) (FP64
+ * arithmetic on the stored factor), x += d.  Stop rule per system:
+ * ||r||_2 <= tol ||b||_2, or ||r||_2 <= 2 u ||A||_inf ||x||_2 (the residual
+ * has reached what FP64 can resolve).  A matrix stops taking corrections
+ * once all its right-hand sides pass.
+ * b_dev: float64 [batch][nrhs][ldb] (unchanged); x_dev: same shape, output.
+ * stats_host (nullable): [batch * nrhs] outcomes.  Synchronizes the stream
+ * once per refinement step.  Returns SC_ENOCONV if some system did not meet
+ * the rule (x then holds the last iterate).  Errors: SC_EINVAL, SC_ENOMEM,
+ * SC_EDEVICE.
+ */
+sc_status sc_refine_solve(const sc_plan_t *plan, sc_numeric_t *num,
+                          const double *values_dev, int64_t ldv,
+                          const double *b_dev, double *x_dev, int32_t nrhs,
+                          int64_t ldb, double tol, int32_t maxit,
+                          sc_refine_stats *stats_host, void *stream);
+
+/*
+ * Copy factor values of the exact pattern to the host, for checking:
+ * for each requested column j (permuted numbering) the values of
+ * L[:, j] on rows Lrowind[Lcolptr[j] .. Lcolptr[j+1]) are appended to
+ * out_host, in that order, as float64.  Synchronizes the device.
+ * Errors: SC_EINVAL (bad batch index or column), SC_EDEVICE.
+ */
+sc_status sc_numeric_get_columns(const sc_plan_t *plan,
+                                 const sc_numeric_t *num, int32_t b,
+                                 int64_t ncols, const int32_t *cols_host,
+                                 double *out_host);
+
+/* Per-kernel totals of timed launches (see sc_numeric_profile). */
+typedef struct {
+    char name[32];    /* kernel name                                      */
+    int64_t launches; /* launches timed                                   */
+    double ms;        /* summed event time of those launches              */
+    double flops;     /* algorithmic flops of those launches              */
+    double bytes;     /* algorithmic HBM bytes of those launches          */
+} sc_kernel_stat;
+
+/*
+ * Measurement support: with enable != 0, every later launch made for this
+ * numeric object (factor and solve) is bracketed by two HIP events on the
+ * stream it runs on, and its algorithmic flops and bytes are recorded;
+ * enable = 0 stops recording.  Timing adds two event records per launch.
+ */
+sc_status sc_numeric_profile(sc_numeric_t *num, int32_t enable);
+
+/*
+ * Wait for the recorded launches, sum them per kernel into out_host (at
+ * most cap entries; *count_out receives the number written) and clear the
+ * record.  Errors: SC_EINVAL, SC_EDEVICE.
+ */
+sc_status sc_numeric_profile_read(sc_numeric_t *num, int32_t cap,
+                                  sc_kernel_stat *out_host,
+                                  int32_t *count_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPCHOL_H */

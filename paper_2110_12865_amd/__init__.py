@@ -1,0 +1,296 @@
+"""Python binding of libspchol (MI355X sparse Cholesky on a fixed pattern).
+
+Argument marshalling only: every numeric step runs in the library's HIP
+kernels; PyTorch provides device memory and the current stream.  The
+names follow the C ABI in include/spchol.h:
+
+    plan = analyze(colptr, rowind, perm)        # host, once per pattern
+    num  = plan.numeric(batch, "f64")           # device storage
+    num.factor(values)                          # values: cuda f64 [batch, nnzA]
+    num.solve(b)                                # b: cuda f64 [batch, nrhs, n], in place
+
+Importing this package fails loudly if the library has not been built
+(``python paper_2110_12865_amd/build.py``); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspchol.so")
+
+SC_OK, SC_EINVAL, SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD, SC_ENOCONV = \
+    0, -1, -2, -3, -4, -5, -6
+SC_F64, SC_F32 = 0, 1
+_DTYPES = {"f64": SC_F64, "f32": SC_F32}
+
+# names exported by the library, in the order of the header
+EXPORTS = [
+    "sc_status_string", "sc_options_default", "sc_analyze", "sc_plan_info",
+    "sc_plan_export_symbolic", "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create",
+    "sc_numeric_destroy", "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
+    "sc_numeric_get_columns", "sc_numeric_profile", "sc_numeric_profile_read",
+]
+
+
+class SpcholError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, status_string(status), status))
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("relax", ctypes.c_int32), ("relax_cols", ctypes.c_int32),
+                ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class RefineStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("clause", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("rnorm", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("xnorm", ctypes.c_double)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnzA", ctypes.c_int64),
+                ("nnzL", ctypes.c_int64), ("nfund", ctypes.c_int64),
+                ("nsuper", ctypes.c_int64), ("nlevels", ctypes.c_int64),
+                ("L_store", ctypes.c_int64), ("U_store", ctypes.c_int64),
+                ("max_front", ctypes.c_int64), ("max_width", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("etree_height", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libspchol.so is not built (%s); run "
+                          "`python paper_2110_12865_amd/build.py`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "sc_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "sc_options_default": ([P], ctypes.c_int),
+        "sc_analyze": ([I64, P, P, P, P, P], ctypes.c_int),
+        "sc_plan_info": ([P, P], ctypes.c_int),
+        "sc_plan_export_symbolic": ([P, P, P, P, P], ctypes.c_int),
+        "sc_plan_export_supernodes": ([P, P, P, P, P, P], ctypes.c_int),
+        "sc_plan_destroy": ([P], None),
+        "sc_numeric_create": ([P, I32, ctypes.c_int, P], ctypes.c_int),
+        "sc_numeric_destroy": ([P], None),
+        "sc_factor": ([P, P, P, I64, P], ctypes.c_int),
+        "sc_factor_info": ([P, P, P], ctypes.c_int),
+        "sc_solve": ([P, P, P, I32, I64, P], ctypes.c_int),
+        "sc_refine_solve": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, P, P],
+                            ctypes.c_int),
+        "sc_numeric_get_columns": ([P, P, I32, I64, P, P], ctypes.c_int),
+        "sc_numeric_profile": ([P, I32], ctypes.c_int),
+        "sc_numeric_profile_read": ([P, I32, P, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def status_string(s: int) -> str:
+    return _lib.sc_status_string(int(s)).decode()
+
+
+def _check(st: int, what: str):
+    if st != SC_OK:
+        raise SpcholError(st, what)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _check(_lib.sc_options_default(ctypes.byref(o)), "sc_options_default")
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != getattr(torch, dtype_name):
+        raise ValueError("expected %s, got %s" % (dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Symbolic analysis of one pattern (see sc_analyze)."""
+
+    def __init__(self, n, colptr, rowind, perm=None, options: Optional[Options] = None):
+        self.n = int(n)
+        colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(_lib.sc_analyze(self.n, _ptr(colptr), _ptr(rowind), _ptr(perm),
+                               None if options is None else ctypes.byref(options),
+                               ctypes.byref(h)), "sc_analyze")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.sc_plan_destroy(h)
+            self._h = None
+
+    def info(self) -> dict:
+        st = PlanStats()
+        _check(_lib.sc_plan_info(self._h, ctypes.byref(st)), "sc_plan_info")
+        return {k: getattr(st, k) for k, _ in PlanStats._fields_}
+
+    def export_symbolic(self):
+        inf = self.info()
+        n, nnzL = inf["n"], inf["nnzL"]
+        perm = np.empty(n, np.int32)
+        parent = np.empty(n, np.int32)
+        Lcolptr = np.empty(n + 1, np.int64)
+        Lrowind = np.empty(nnzL, np.int32)
+        _check(_lib.sc_plan_export_symbolic(self._h, _ptr(perm), _ptr(parent),
+                                            _ptr(Lcolptr), _ptr(Lrowind)),
+               "sc_plan_export_symbolic")
+        return perm, parent, Lcolptr, Lrowind
+
+    def export_supernodes(self):
+        """(first, parent, level, rowptr, rows) of the amalgamated supernodes."""
+        ns = self.info()["nsuper"]
+        first = np.empty(ns + 1, np.int32)
+        parent = np.empty(ns, np.int32)
+        level = np.empty(ns, np.int32)
+        rowptr = np.empty(ns + 1, np.int64)
+        _check(_lib.sc_plan_export_supernodes(self._h, _ptr(first), _ptr(parent), _ptr(level),
+                                              _ptr(rowptr), None), "sc_plan_export_supernodes")
+        rows = np.empty(int(rowptr[-1]), np.int32)
+        _check(_lib.sc_plan_export_supernodes(self._h, None, None, None, None, _ptr(rows)),
+               "sc_plan_export_supernodes")
+        return first, parent, level, rowptr, rows
+
+    def numeric(self, batch: int = 1, dtype: str = "f64") -> "Numeric":
+        return Numeric(self, batch, dtype)
+
+
+def analyze(colptr, rowind, perm=None, n=None, **opts) -> Plan:
+    n = len(colptr) - 1 if n is None else n
+    return Plan(n, colptr, rowind, perm, default_options(**opts) if opts else None)
+
+
+class Numeric:
+    """Device storage for a batch of factors of one plan."""
+
+    def __init__(self, plan: Plan, batch: int, dtype: str):
+        self.plan = plan
+        self.batch = int(batch)
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        _check(_lib.sc_numeric_create(plan._h, self.batch, _DTYPES[dtype], ctypes.byref(h)),
+               "sc_numeric_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.sc_numeric_destroy(h)
+            self._h = None
+
+    def factor(self, values, stream=None):
+        """values: device float64 tensor [batch, ldv] (ldv >= nnzA)."""
+        if values.dim() != 2 or values.shape[0] != self.batch:
+            raise ValueError("values must be [batch, nnzA]")
+        # contiguous [batch, ldv]: the row pitch is the row length (a size-1
+        # batch dimension may report any stride)
+        _check(_lib.sc_factor(self.plan._h, self._h, _dev_ptr(values, "float64"),
+                              int(values.shape[1]), _stream_handle(stream)), "sc_factor")
+
+    def info(self, stream=None) -> np.ndarray:
+        out = np.empty(self.batch, np.int32)
+        st = _lib.sc_factor_info(self._h, _ptr(out), _stream_handle(stream))
+        if st not in (SC_OK, SC_ENOTSPD):
+            raise SpcholError(st, "sc_factor_info")
+        return out
+
+    def solve(self, b, stream=None):
+        """b: device float64 tensor [batch, nrhs, n]; overwritten by x."""
+        if b.dim() != 3 or b.shape[0] != self.batch:
+            raise ValueError("b must be [batch, nrhs, n]")
+        _check(_lib.sc_solve(self.plan._h, self._h, _dev_ptr(b, "float64"), int(b.shape[1]),
+                             int(b.shape[2]), _stream_handle(stream)), "sc_solve")
+        return b
+
+    def refine_solve(self, values, b, x, tol: float = 1e-10, maxit: int = 10, stream=None):
+        """x <- refined solution of A x = b (see sc_refine_solve).  values:
+        the factored float64 values [batch, nnzA]; b, x: float64
+        [batch, nrhs, n] device tensors.  Returns (status, stats) where stats
+        is a list of dicts per (matrix, rhs)."""
+        if b.shape != x.shape or b.dim() != 3 or b.shape[0] != self.batch:
+            raise ValueError("b and x must be [batch, nrhs, n]")
+        nsys = self.batch * int(b.shape[1])
+        st = (RefineStats * nsys)()
+        rc = _lib.sc_refine_solve(self.plan._h, self._h, _dev_ptr(values, "float64"),
+                                  int(values.shape[1]), _dev_ptr(b, "float64"),
+                                  _dev_ptr(x, "float64"), int(b.shape[1]), int(b.shape[2]),
+                                  float(tol), int(maxit), st, _stream_handle(stream))
+        if rc not in (SC_OK, SC_ENOCONV):
+            raise SpcholError(rc, "sc_refine_solve")
+        return rc, [{k: getattr(st[i], k) for k, _ in RefineStats._fields_}
+                    for i in range(nsys)]
+
+    def get_columns(self, b: int, cols) -> np.ndarray:
+        """Values of L on the exact pattern for the given columns (host)."""
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        _, _, Lcolptr, _ = self._lcolptr()
+        total = int(np.sum(Lcolptr[cols + 1] - Lcolptr[cols])) if cols.size else 0
+        out = np.empty(total, np.float64)
+        _check(_lib.sc_numeric_get_columns(self.plan._h, self._h, int(b), int(cols.size),
+                                           _ptr(cols), _ptr(out)), "sc_numeric_get_columns")
+        return out
+
+    def profile(self, enable: bool = True):
+        """Time every later launch with HIP events (see sc_numeric_profile)."""
+        _check(_lib.sc_numeric_profile(self._h, 1 if enable else 0), "sc_numeric_profile")
+
+    def profile_read(self) -> dict:
+        """Per-kernel totals {name: {launches, ms, flops, bytes}}; clears them."""
+        arr = (KernelStat * 16)()
+        cnt = ctypes.c_int32()
+        _check(_lib.sc_numeric_profile_read(self._h, 16, arr, ctypes.byref(cnt)),
+               "sc_numeric_profile_read")
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms,
+                                       "flops": arr[i].flops, "bytes": arr[i].bytes}
+                for i in range(cnt.value)}
+
+    def _lcolptr(self):
+        if not hasattr(self.plan, "_Lcolptr"):
+            inf = self.plan.info()
+            Lcolptr = np.empty(inf["n"] + 1, np.int64)
+            _check(_lib.sc_plan_export_symbolic(self.plan._h, None, None, _ptr(Lcolptr), None),
+                   "sc_plan_export_symbolic")
+            self.plan._Lcolptr = Lcolptr
+        return None, None, self.plan._Lcolptr, None

@@ -1,0 +1,426 @@
+// C ABI of libspchol: argument checks, plan upload and object lifetimes.
+// The numeric work itself lives in factor.hip and solve.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "device.hpp"
+#include "spchol.h"
+
+const char *const kKernelNames[KK_Count] = {
+    "front_small", "assemble", "potrf", "trsm", "syrk_mfma", "solve_fwd", "solve_bwd"};
+
+void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
+void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
+hipError_t spchol_solve_init();
+
+namespace {
+
+std::mutex g_upload_mutex;
+bool g_kernels_ready[64] = {};
+
+template <typename V>
+hipError_t upload(V **dst, const std::vector<V> &src) {
+    size_t bytes = std::max<size_t>(src.size() * sizeof(V), 8);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice);
+    return e;
+}
+
+void free_devplan(DevPlan *D) {
+    if (!D) return;
+    void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
+                    D->avidx, D->perm, D->lvl_small, D->lvl_big, D->lvl_sn,
+                    D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete D;
+}
+
+// Upload the plan to the current device on first use.
+sc_status ensure_device(const sc_plan *P) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_upload_mutex);
+    if (dev >= 0 && dev < 64 && !g_kernels_ready[dev]) {
+        if (spchol_kernels_init() != hipSuccess) return SC_EDEVICE;
+        if (spchol_solve_init() != hipSuccess) return SC_EDEVICE;
+        g_kernels_ready[dev] = true;
+    }
+    if (P->dev) return P->dev_id == dev ? SC_OK : SC_EINVAL;
+    DevPlan *D = new (std::nothrow) DevPlan();
+    if (!D) return SC_ENOMEM;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = upload(&D->sn, P->sn);
+    if (e == hipSuccess) e = upload(&D->rows, P->rows);
+    if (e == hipSuccess) e = upload(&D->relmap, P->relmap);
+    if (e == hipSuccess) e = upload(&D->chlist, P->chlist);
+    if (e == hipSuccess) e = upload(&D->acolptr, P->acolptr);
+    if (e == hipSuccess) e = upload(&D->aoff, P->aoff);
+    if (e == hipSuccess) e = upload(&D->avidx, P->avidx);
+    if (e == hipSuccess) e = upload(&D->perm, P->perm);
+    if (e == hipSuccess) e = upload(&D->lvl_small, P->lvl_small);
+    if (e == hipSuccess) e = upload(&D->lvl_big, P->lvl_big);
+    if (e == hipSuccess) e = upload(&D->lvl_sn, P->lvl_sn);
+    if (e == hipSuccess) e = upload(&D->big_colstart, P->big_colstart);
+    if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
+    if (e == hipSuccess) e = upload(&D->csr_col, P->csr_col);
+    if (e == hipSuccess) e = upload(&D->csr_vidx, P->csr_vidx);
+    if (e != hipSuccess) {
+        free_devplan(D);
+        return e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EDEVICE;
+    }
+    spchol_build_factor_schedule(P, D);
+    spchol_build_solve_schedule(P, D);
+    P->dev = D;
+    P->dev_id = dev;
+    return SC_OK;
+}
+
+sc_status map_err(hipError_t e) {
+    if (e == hipSuccess) return SC_OK;
+    if (e == hipErrorOutOfMemory) return SC_ENOMEM;
+    return SC_EDEVICE;
+}
+
+// Solve workspaces for nrhs right-hand sides per matrix.
+hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
+    if (nrhs <= N->ws_nrhs) return hipSuccess;
+    if (N->ws_y) (void)hipFree(N->ws_y);
+    if (N->ws_u) (void)hipFree(N->ws_u);
+    N->ws_y = nullptr;
+    N->ws_u = nullptr;
+    N->ws_nrhs = 0;
+    const size_t cnt = size_t(N->batch) * nrhs;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&N->ws_y),
+                             std::max<size_t>(cnt * P->n * sizeof(double), 8));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&N->ws_u),
+                      std::max<size_t>(cnt * P->relsize * sizeof(double), 8));
+    if (e == hipSuccess) N->ws_nrhs = nrhs;
+    return e;
+}
+
+void free_refine_ws(RefineWs &W) {
+    void *ptrs[] = {W.r, W.anorm, W.stat, W.conv, W.active, W.count};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    W = RefineWs{};
+}
+
+hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
+    RefineWs &W = N->rws;
+    const int32_t nsys = N->batch * nrhs;
+    if (W.r && W.nsys >= nsys && W.ldb >= ldb) return hipSuccess;
+    free_refine_ws(W);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&W.r), sizeof(double) * nsys * ldb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.anorm), sizeof(double) * N->batch);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.stat), sizeof(double) * 6 * nsys);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.conv), sizeof(int32_t) * nsys);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.active), sizeof(int32_t) * N->batch);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.count), sizeof(int32_t));
+    if (e != hipSuccess) {
+        free_refine_ws(W);
+        return e;
+    }
+    W.nsys = nsys;
+    W.ldb = ldb;
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sc_status_string(sc_status s) {
+    switch (s) {
+    case SC_OK: return "ok";
+    case SC_EINVAL: return "invalid argument";
+    case SC_EPATTERN: return "malformed pattern or permutation";
+    case SC_ENOMEM: return "out of memory";
+    case SC_EDEVICE: return "HIP runtime error";
+    case SC_ENOTSPD: return "matrix not positive definite";
+    case SC_ENOCONV: return "refinement did not converge";
+    }
+    return "unknown status";
+}
+
+sc_status sc_options_default(sc_options *opt) {
+    if (!opt) return SC_EINVAL;
+    opt->relax = 1;
+    opt->relax_cols = 4;
+    opt->relax_zeros = 0.05;
+    opt->small_front = 64;
+    return SC_OK;
+}
+
+sc_status sc_analyze(int64_t n, const int64_t *colptr_host, const int32_t *rowind_host,
+                     const int32_t *perm_host, const sc_options *opt, sc_plan_t **plan_out) {
+    if (!plan_out) return SC_EINVAL;
+    *plan_out = nullptr;
+    sc_options o;
+    sc_options_default(&o);
+    if (opt) o = *opt;
+    if (o.relax_cols < 0 || o.small_front < 0 || !(o.relax_zeros >= 0.0)) return SC_EINVAL;
+    return spchol_build_plan(n, colptr_host, rowind_host, perm_host, o, plan_out);
+}
+
+sc_status sc_plan_info(const sc_plan_t *P, sc_plan_stats *out) {
+    if (!P || !out) return SC_EINVAL;
+    out->n = P->n;
+    out->nnzA = P->nnzA;
+    out->nnzL = P->nnzL;
+    out->nfund = int64_t(P->ffirst.size()) - 1;
+    out->nsuper = P->ns;
+    out->nlevels = P->nlevels;
+    out->L_store = P->Lsize;
+    out->U_store = P->Usize;
+    out->max_front = P->max_front;
+    out->max_width = P->max_width;
+    out->flops = P->flops;
+    out->etree_height = P->etree_height;
+    return SC_OK;
+}
+
+sc_status sc_plan_export_symbolic(const sc_plan_t *P, int32_t *perm_host, int32_t *parent_host,
+                                  int64_t *Lcolptr_host, int32_t *Lrowind_host) {
+    if (!P) return SC_EINVAL;
+    const int64_t n = P->n;
+    if (perm_host) std::memcpy(perm_host, P->perm.data(), sizeof(int32_t) * n);
+    if (parent_host) std::memcpy(parent_host, P->parent.data(), sizeof(int32_t) * n);
+    if (Lcolptr_host) {
+        Lcolptr_host[0] = 0;
+        for (int64_t j = 0; j < n; j++) Lcolptr_host[j + 1] = Lcolptr_host[j] + P->colcount[j];
+    }
+    if (Lrowind_host) {
+        int64_t o = 0;
+        const int64_t nf = int64_t(P->ffirst.size()) - 1;
+        for (int64_t t = 0; t < nf; t++)
+            for (int32_t j = P->ffirst[t]; j < P->ffirst[t + 1]; j++) {
+                const int64_t a = P->frowptr[t] + (j - P->ffirst[t]);
+                const int64_t b = P->frowptr[t + 1];
+                std::memcpy(Lrowind_host + o, P->frows.data() + a, sizeof(int32_t) * (b - a));
+                o += b - a;
+            }
+    }
+    return SC_OK;
+}
+
+sc_status sc_plan_export_supernodes(const sc_plan_t *P, int32_t *first_host,
+                                    int32_t *parent_host, int32_t *level_host,
+                                    int64_t *rowptr_host, int32_t *rows_host) {
+    if (!P) return SC_EINVAL;
+    for (int32_t s = 0; s < P->ns; s++) {
+        const SnDesc &d = P->sn[s];
+        if (first_host) first_host[s] = d.first;
+        if (parent_host) parent_host[s] = d.parent;
+        if (level_host) level_host[s] = d.level;
+        if (rowptr_host) rowptr_host[s] = d.rowptr;
+    }
+    if (first_host) first_host[P->ns] = int32_t(P->n);
+    if (rowptr_host) rowptr_host[P->ns] = int64_t(P->rows.size());
+    if (rows_host && !P->rows.empty())
+        std::memcpy(rows_host, P->rows.data(), sizeof(int32_t) * P->rows.size());
+    return SC_OK;
+}
+
+void sc_plan_destroy(sc_plan_t *P) {
+    if (!P) return;
+    free_devplan(P->dev);
+    delete P;
+}
+
+sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
+                            sc_numeric_t **num_out) {
+    if (!P || !num_out || batch < 1 || (dtype != SC_F64 && dtype != SC_F32)) return SC_EINVAL;
+    *num_out = nullptr;
+    sc_status st = ensure_device(P);
+    if (st != SC_OK) return st;
+    sc_numeric *N = new (std::nothrow) sc_numeric();
+    if (!N) return SC_ENOMEM;
+    N->plan = P;
+    N->batch = batch;
+    N->dtype = dtype;
+    N->device = P->dev_id;
+    const size_t sz = dtype == SC_F64 ? 8 : 4;
+    hipError_t e = hipMalloc(&N->L, std::max<size_t>(size_t(batch) * P->Lsize * sz, 8));
+    if (e == hipSuccess) e = hipMalloc(&N->U, std::max<size_t>(size_t(batch) * P->Usize * sz, 8));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&N->info), sizeof(int32_t) * batch);
+    if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * batch);
+    if (e != hipSuccess) {
+        sc_numeric_destroy(N);
+        return map_err(e);
+    }
+    *num_out = N;
+    return SC_OK;
+}
+
+void sc_numeric_destroy(sc_numeric_t *N) {
+    if (!N) return;
+    if (N->L) (void)hipFree(N->L);
+    if (N->U) (void)hipFree(N->U);
+    if (N->info) (void)hipFree(N->info);
+    if (N->ws_y) (void)hipFree(N->ws_y);
+    if (N->ws_u) (void)hipFree(N->ws_u);
+    free_refine_ws(N->rws);
+    delete N;
+}
+
+sc_status sc_factor(const sc_plan_t *P, sc_numeric_t *N, const double *values_dev, int64_t ldv,
+                    void *stream) {
+    if (!P || !N || N->plan != P || !values_dev || ldv < P->nnzA) return SC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (dev != N->device) return SC_EINVAL;
+    return map_err(spchol_factor_run(P, N, values_dev, ldv, static_cast<hipStream_t>(stream)));
+}
+
+sc_status sc_factor_info(const sc_numeric_t *N, int32_t *info_host, void *stream) {
+    if (!N || !info_host) return SC_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(info_host, N->info, sizeof(int32_t) * N->batch,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return map_err(e);
+    bool bad = false;
+    for (int32_t b = 0; b < N->batch; b++) {
+        if (info_host[b] == INT_MAX) info_host[b] = 0;
+        if (info_host[b] != 0) bad = true;
+    }
+    return bad ? SC_ENOTSPD : SC_OK;
+}
+
+sc_status sc_solve(const sc_plan_t *P, sc_numeric_t *N, double *b_dev, int32_t nrhs, int64_t ldb,
+                   void *stream) {
+    if (!P || !N || N->plan != P || !b_dev || nrhs < 1 || ldb < P->n) return SC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (dev != N->device) return SC_EINVAL;
+    hipError_t e = ensure_solve_ws(P, N, nrhs);
+    if (e != hipSuccess) return map_err(e);
+    return map_err(
+        spchol_solve_run(P, N, b_dev, nrhs, ldb, static_cast<hipStream_t>(stream), nullptr));
+}
+
+sc_status sc_refine_solve(const sc_plan_t *P, sc_numeric_t *N, const double *values_dev,
+                          int64_t ldv, const double *b_dev, double *x_dev, int32_t nrhs,
+                          int64_t ldb, double tol, int32_t maxit, sc_refine_stats *stats_host,
+                          void *stream) {
+    if (!P || !N || N->plan != P || !values_dev || !b_dev || !x_dev || nrhs < 1 ||
+        ldb < P->n || ldv < P->nnzA || maxit < 0 || !(tol >= 0.0))
+        return SC_EINVAL;
+    if (b_dev == x_dev) return SC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (dev != N->device) return SC_EINVAL;
+    hipError_t e = ensure_solve_ws(P, N, nrhs);
+    if (e == hipSuccess) e = ensure_refine_ws(N, nrhs, ldb);
+    if (e != hipSuccess) return map_err(e);
+    const int32_t nsys = N->batch * nrhs;
+    std::vector<double> stat(size_t(6) * nsys);
+    int32_t nact = 0;
+    e = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, maxit,
+                          stat.data(), &nact, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return map_err(e);
+    bool fail = false;
+    for (int32_t k = 0; k < nsys; k++) {
+        const double *q = &stat[size_t(6) * k];
+        if (q[1] == 0.0) fail = true;
+        if (stats_host) {
+            stats_host[k].iters = int32_t(q[0]);
+            stats_host[k].clause = int32_t(q[1]);
+            stats_host[k].relres = q[2];
+            stats_host[k].rnorm = q[3];
+            stats_host[k].bnorm = q[4];
+            stats_host[k].xnorm = q[5];
+        }
+    }
+    return fail ? SC_ENOCONV : SC_OK;
+}
+
+sc_status sc_numeric_get_columns(const sc_plan_t *P, const sc_numeric_t *N, int32_t b,
+                                 int64_t ncols, const int32_t *cols_host, double *out_host) {
+    if (!P || !N || N->plan != P || b < 0 || b >= N->batch || ncols < 0) return SC_EINVAL;
+    if (ncols > 0 && (!cols_host || !out_host)) return SC_EINVAL;
+    for (int64_t q = 0; q < ncols; q++)
+        if (cols_host[q] < 0 || cols_host[q] >= P->n) return SC_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return SC_EDEVICE;
+    const size_t sz = N->dtype == SC_F64 ? 8 : 4;
+    std::vector<unsigned char> blk;
+    int32_t cached = -1;
+    int64_t o = 0;
+    for (int64_t q = 0; q < ncols; q++) {
+        const int32_t j = cols_host[q];
+        const int32_t s = P->col2sn[j];
+        const SnDesc &d = P->sn[s];
+        if (s != cached) {
+            blk.resize(size_t(d.c) * d.w * sz);
+            const unsigned char *src = static_cast<const unsigned char *>(N->L) +
+                                       (size_t(b) * P->Lsize + d.loff) * sz;
+            if (hipMemcpy(blk.data(), src, blk.size(), hipMemcpyDeviceToHost) != hipSuccess)
+                return SC_EDEVICE;
+            cached = s;
+        }
+        const int64_t t = int64_t(std::upper_bound(P->ffirst.begin(), P->ffirst.end(), j) -
+                                  P->ffirst.begin()) - 1;
+        const int64_t a = P->frowptr[t] + (j - P->ffirst[t]);
+        const int32_t *R = P->rows.data() + d.rowptr;
+        const int64_t cbase = int64_t(j - d.first) * d.c;
+        int32_t pos = j - d.first;
+        for (int64_t e = a; e < P->frowptr[t + 1]; e++) {
+            const int32_t r = P->frows[e];
+            while (pos < d.c && R[pos] < r) pos++;
+            if (pos >= d.c) return SC_EINVAL;  // cannot happen for a valid plan
+            const size_t idx = size_t(cbase + pos);
+            out_host[o++] = sz == 8 ? reinterpret_cast<const double *>(blk.data())[idx]
+                                    : double(reinterpret_cast<const float *>(blk.data())[idx]);
+        }
+    }
+    return SC_OK;
+}
+
+sc_status sc_numeric_profile(sc_numeric_t *N, int32_t enable) {
+    if (!N) return SC_EINVAL;
+    N->prof.on = enable != 0;
+    return SC_OK;
+}
+
+sc_status sc_numeric_profile_read(sc_numeric_t *N, int32_t cap, sc_kernel_stat *out_host,
+                                  int32_t *count_out) {
+    if (!N || cap < 0 || (cap > 0 && !out_host) || !count_out) return SC_EINVAL;
+    Profiler &pr = N->prof;
+    std::vector<sc_kernel_stat> acc(KK_Count);
+    for (int k = 0; k < KK_Count; k++) {
+        std::memset(&acc[k], 0, sizeof(sc_kernel_stat));
+        std::strncpy(acc[k].name, kKernelNames[k], sizeof(acc[k].name) - 1);
+    }
+    sc_status st = SC_OK;
+    for (const Profiler::Rec &r : pr.recs) {
+        float ms = 0.f;
+        if (!r.a || !r.b || hipEventSynchronize(r.b) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            st = SC_EDEVICE;
+            continue;
+        }
+        sc_kernel_stat &a = acc[r.kind];
+        a.launches++;
+        a.ms += ms;
+        a.flops += r.flops;
+        a.bytes += r.bytes;
+    }
+    pr.recs.clear();
+    pr.used = 0;
+    int32_t n = 0;
+    for (int k = 0; k < KK_Count && n < cap; k++)
+        if (acc[k].launches > 0) out_host[n++] = acc[k];
+    *count_out = n;
+    return st;
+}
+
+}  // extern "C"

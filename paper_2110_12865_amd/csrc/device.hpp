@@ -1,0 +1,140 @@
+// Device-side state of a plan and of a batch of numeric factors, and the
+// launchers of the factor and solve kernels.  Internal to libspchol.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "plan.hpp"
+
+// Tile of the blocked dense kernels (rows/columns of a trailing-update tile
+// and panel width of the blocked partial factorization).
+constexpr int kTile = 64;
+
+// One kernel launch of the factor schedule.  The schedule depends only on
+// the pattern, so it is built once per plan and replayed by every call.
+struct FLaunch {
+    enum Kind : int { Small, Assemble, Potrf, Trsm, Syrk } kind;
+    int32_t level;
+    int32_t k;        // panel start column (Potrf/Trsm/Syrk)
+    int32_t list0;    // first entry in the level's list
+    int32_t nlist;    // entries
+    int64_t gridx;    // workgroups along x
+    int32_t lds;      // dynamic LDS size in scalars (times sizeof(T) at launch)
+    double flops;     // algorithmic flops per matrix of the batch
+    double words;     // algorithmic scalars of L/U moved per matrix
+    double ibytes;    // algorithmic index/value bytes per matrix
+};
+
+struct SLaunch {  // one level of a triangular solve
+    int32_t level;
+    int32_t list0, nlist;
+    int32_t maxc;
+    double flops;     // per right-hand side
+    double words;     // factor scalars read per right-hand side
+    double vbytes;    // vector bytes per right-hand side
+};
+
+struct DevPlan {
+    SnDesc *sn = nullptr;
+    int32_t *rows = nullptr;
+    int32_t *relmap = nullptr;
+    int32_t *chlist = nullptr;
+    int64_t *acolptr = nullptr;
+    int32_t *aoff = nullptr;
+    int64_t *avidx = nullptr;
+    int32_t *perm = nullptr;
+    int32_t *lvl_small = nullptr;
+    int32_t *lvl_big = nullptr;
+    int32_t *lvl_sn = nullptr;
+    int64_t *big_colstart = nullptr;  // per big entry: first column index in its level
+    int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
+    int32_t *csr_col = nullptr;
+    int64_t *csr_vidx = nullptr;
+    std::vector<FLaunch> fsched;
+    std::vector<SLaunch> ssched;
+};
+
+// Kernel kinds for per-launch timing.
+enum KernelKind : int {
+    KK_SmallFront = 0, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk, KK_Fwd, KK_Bwd,
+    KK_Count
+};
+extern const char *const kKernelNames[KK_Count];
+
+// Optional event timing of every launch (off by default).  Each launch is
+// bracketed by two events on the stream it runs on; the algorithmic flops
+// and HBM bytes of the launch are attached so rates can be formed.
+struct Profiler {
+    bool on = false;
+    struct Rec { int kind; hipEvent_t a, b; double flops, bytes; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(int kind, double flops, double bytes, hipStream_t st) {
+        if (!on) return;
+        Rec r{kind, get(), get(), flops, bytes};
+        if (r.a) (void)hipEventRecord(r.a, st);
+        recs.push_back(r);
+    }
+    void end(hipStream_t st) {
+        if (!on || recs.empty()) return;
+        if (recs.back().b) (void)hipEventRecord(recs.back().b, st);
+    }
+    ~Profiler() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// Workspace of iterative refinement (allocated on first use).
+struct RefineWs {
+    int32_t nsys = 0;
+    int64_t ldb = 0;
+    double *r = nullptr;        // residual / correction, nsys * ldb
+    double *anorm = nullptr;    // batch
+    double *stat = nullptr;     // nsys * 6
+    int32_t *conv = nullptr;    // nsys
+    int32_t *active = nullptr;  // batch
+    int32_t *count = nullptr;   // 1
+};
+
+struct sc_numeric {
+    const sc_plan *plan = nullptr;
+    int32_t batch = 0;
+    sc_dtype dtype = SC_F64;
+    int device = -1;
+    void *L = nullptr;       // batch * Lsize scalars
+    void *U = nullptr;       // batch * Usize scalars
+    int32_t *info = nullptr; // batch
+    double *ws_y = nullptr;  // batch * nrhs * n
+    double *ws_u = nullptr;  // batch * nrhs * relsize
+    int32_t ws_nrhs = 0;
+    Profiler prof;
+    RefineWs rws;
+};
+
+// Launchers (factor.hip / solve.hip).  Return hipSuccess or the first error.
+hipError_t spchol_factor_run(const sc_plan *P, sc_numeric *N,
+                             const double *vals, int64_t ldv, hipStream_t st);
+// active (nullable, device): matrices b with active[b] == 0 are left untouched
+// (used by refinement to stop correcting converged matrices).
+hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b,
+                            int32_t nrhs, int64_t ldb, hipStream_t st,
+                            const int32_t *active);
+hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
+                             int64_t ldv, const double *b, double *x, int32_t nrhs,
+                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
+                             int32_t *nactive_out, hipStream_t st);
+hipError_t spchol_kernels_init();
+
+// Largest dynamic LDS allocation per workgroup on the current device.
+extern int g_max_lds;

@@ -1,0 +1,91 @@
+// Internal plan layout shared by the host symbolic pass and the HIP
+// launchers.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "spchol.h"
+
+// One supernode as the GPU kernels see it.  A workgroup reads a single
+// record, so an array of structs is the natural layout here.
+struct SnDesc {
+    int64_t loff;    // offset of the c x w column-major L block (scalars)
+    int64_t uoff;    // offset of the m x m column-major update block
+    int64_t rowptr;  // offset of the row list R_s in Plan::rows
+    int64_t relptr;  // offset of the m relative positions in the parent
+    int32_t first;   // first column (permuted numbering)
+    int32_t w;       // width (columns)
+    int32_t c;       // rows of the front, |R_s|
+    int32_t m;       // c - w: update rows
+    int32_t chbeg;   // children: chlist[chbeg .. chend)
+    int32_t chend;
+    int32_t parent;  // supernodal parent, -1 for a root
+    int32_t level;   // longest path from the leaves
+};
+static_assert(sizeof(SnDesc) == 64, "SnDesc layout");
+
+struct DevPlan;  // device copies, defined by the HIP side
+
+struct sc_plan {
+    int64_t n = 0, nnzA = 0;
+    sc_options opt{};
+
+    // permutation (perm[new] = old) and its inverse
+    std::vector<int32_t> perm, pinv;
+    // column elimination tree and exact column counts (diagonal included)
+    std::vector<int32_t> parent;
+    std::vector<int64_t> colcount;
+    int64_t nnzL = 0;
+    double flops = 0.0;
+    int64_t etree_height = 0;
+
+    // fundamental supernodes: columns [ffirst[t], ffirst[t+1]) and the exact
+    // structure of their first column
+    std::vector<int32_t> ffirst;
+    std::vector<int64_t> frowptr;
+    std::vector<int32_t> frows;
+
+    // supernodes after amalgamation
+    int32_t ns = 0;
+    std::vector<SnDesc> sn;
+    std::vector<int32_t> col2sn;  // n
+    std::vector<int32_t> rows;    // concatenated R_s (sorted ascending)
+    std::vector<int32_t> relmap;  // concatenated relative maps
+    std::vector<int32_t> chlist;  // children, ascending per parent
+    int64_t Lsize = 0, Usize = 0, relsize = 0;
+    int32_t nlevels = 0;
+    int64_t max_front = 0, max_width = 0;
+
+    // permuted lower triangle of A by columns: offset of the entry inside
+    // the c x w column-major L block of the column's supernode, and index
+    // into the caller's values
+    std::vector<int64_t> acolptr;  // n+1
+    std::vector<int32_t> aoff;
+    std::vector<int64_t> avidx;
+
+    // A in the caller's numbering with both triangles, by rows, for the
+    // residual A x: column index and index into the caller's values
+    std::vector<int64_t> csr_ptr;  // n+1
+    std::vector<int32_t> csr_col;
+    std::vector<int64_t> csr_vidx;
+
+    // level schedule: supernodes of each level split into fronts done by
+    // one workgroup ("small") and fronts done by the tiled kernels ("big")
+    std::vector<int32_t> lvl_small_ptr, lvl_small;
+    std::vector<int32_t> lvl_big_ptr, lvl_big;
+    std::vector<int32_t> lvl_small_maxc, lvl_big_maxc, lvl_big_maxw;
+    std::vector<int32_t> lvl_ptr, lvl_sn;  // all supernodes of each level
+    std::vector<int32_t> lvl_maxc;
+    std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts
+    std::vector<int64_t> big_colstart;    // per big entry: first column in its level
+
+    mutable DevPlan *dev = nullptr;
+    mutable int dev_id = -1;
+};
+
+// Host symbolic pass (analyze.cpp).  Returns SC_OK or an error; on success
+// *out owns a fully built plan.
+sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
+                            const int32_t *rowind, const int32_t *perm,
+                            const sc_options &opt, sc_plan **out);

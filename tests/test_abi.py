@@ -1,0 +1,181 @@
+"""C-ABI checks that need no GPU: the library loads and exports every
+function the header declares, input validation returns the documented
+status codes, and the host symbolic pass (sc_analyze) matches the oracle's
+elimination tree and pattern bit for bit and satisfies the supernode and
+level invariants the GPU schedule relies on."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "spchol.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    import paper_2110_12865_amd as S
+    names = header_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(S.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(S.EXPORTS) == names
+
+
+def test_status_strings():
+    import paper_2110_12865_amd as S
+    for st in range(-6, 1):
+        assert S.status_string(st)
+
+
+def _analyze_raw(n, colptr, rowind, perm=None):
+    import paper_2110_12865_amd as S
+    colptr = np.ascontiguousarray(colptr, np.int64)
+    rowind = np.ascontiguousarray(rowind, np.int32)
+    h = ctypes.c_void_p()
+    p = None if perm is None else np.ascontiguousarray(perm, np.int32)
+    st = S._lib.sc_analyze(n, S._ptr(colptr), S._ptr(rowind), S._ptr(p), None, ctypes.byref(h))
+    if h:
+        S._lib.sc_plan_destroy(h)
+    return st
+
+
+def test_malformed_patterns_are_rejected():
+    import paper_2110_12865_amd as S
+    w = W.small_grid((4, 3), "natural")
+    cp, ri = w.pattern.colptr.copy(), w.pattern.rowind.copy()
+    n = w.pattern.n
+    assert _analyze_raw(n, cp, ri) == S.SC_OK
+    # diagonal missing / not first
+    bad = ri.copy(); bad[cp[2]] = bad[cp[2] + 1]
+    assert _analyze_raw(n, cp, bad) == S.SC_EPATTERN
+    # unsorted rows
+    bad = ri.copy(); c = 1
+    bad[cp[c] + 1], bad[cp[c] + 2] = bad[cp[c] + 2], bad[cp[c] + 1]
+    assert _analyze_raw(n, cp, bad) == S.SC_EPATTERN
+    # duplicate row
+    bad = ri.copy(); bad[cp[1] + 2] = bad[cp[1] + 1]
+    assert _analyze_raw(n, cp, bad) == S.SC_EPATTERN
+    # row out of range
+    bad = ri.copy(); bad[cp[n - 2] + 1] = n
+    assert _analyze_raw(n, cp, bad) == S.SC_EPATTERN
+    # an entry above the diagonal
+    bad = ri.copy(); bad[cp[5] + 1] = 4
+    assert _analyze_raw(n, cp, bad) == S.SC_EPATTERN
+    # colptr not monotone / not starting at 0
+    badc = cp.copy(); badc[3] = badc[2]
+    assert _analyze_raw(n, badc, ri) == S.SC_EPATTERN
+    badc = cp.copy(); badc[0] = 1
+    assert _analyze_raw(n, badc, ri) == S.SC_EPATTERN
+    # perm: duplicate and out-of-range entries
+    perm = np.arange(n, dtype=np.int32); perm[3] = perm[4]
+    assert _analyze_raw(n, cp, ri, perm) == S.SC_EPATTERN
+    perm = np.arange(n, dtype=np.int32); perm[0] = n
+    assert _analyze_raw(n, cp, ri, perm) == S.SC_EPATTERN
+    # sizes and null pointers
+    assert _analyze_raw(0, np.zeros(1, np.int64), np.zeros(0, np.int32)) == S.SC_EINVAL
+    h = ctypes.c_void_p()
+    assert S._lib.sc_analyze(n, None, S._ptr(ri), None, None, ctypes.byref(h)) == S.SC_EINVAL
+    assert S._lib.sc_analyze(n, S._ptr(cp), S._ptr(ri), None, None, None) == S.SC_EINVAL
+
+
+def symbolic_cases():
+    out = [("cfg0", W.config(0)),
+           ("grid3d_16_nd", W.small_grid((16, 16, 16), "nd")),
+           ("grid2d_50x37_nd", W.small_grid((50, 37), "nd")),
+           ("grid3d_7x9x5_natural", W.small_grid((7, 9, 5), "natural")),
+           ("trimesh_40", W.trimesh_workload(40, 1, 1, seed=5))]
+    for seed in range(6):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(1, 400))
+        out.append(("random_%d" % seed,
+                    W.random_spd(n, float(rng.uniform(0.0, 0.05)), seed=900 + seed)))
+    return out
+
+
+@pytest.mark.parametrize("name,w", symbolic_cases(), ids=[c[0] for c in symbolic_cases()])
+@pytest.mark.parametrize("relax", [1, 0])
+def test_symbolic_bit_exact_and_invariants(name, w, relax):
+    import paper_2110_12865_amd as S
+    p = w.pattern
+    plan = S.analyze(p.colptr, p.rowind, w.perm, relax=relax)
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    perm, parent, Lcolptr, Lrowind = plan.export_symbolic()
+    if w.perm is not None:
+        assert np.array_equal(perm, w.perm)
+    else:
+        assert np.array_equal(perm, np.arange(p.n))
+    assert np.array_equal(parent, sym.parent)
+    assert np.array_equal(Lcolptr, sym.Lcolptr)
+    assert np.array_equal(Lrowind, sym.Lrowind)
+    inf = plan.info()
+    assert inf["nnzL"] == sym.nnzL
+    assert inf["flops"] == pytest.approx(sym.flops(), rel=1e-12)
+    check_supernode_invariants(plan, sym)
+
+
+def check_supernode_invariants(plan, sym):
+    first, sparent, level, rowptr, rows = plan.export_supernodes()
+    n = sym.n
+    ns = len(sparent)
+    assert first[0] == 0 and first[-1] == n and np.all(np.diff(first) > 0)
+    col2sn = np.repeat(np.arange(ns), np.diff(first))
+    for s in range(ns):
+        R = rows[rowptr[s]:rowptr[s + 1]]
+        w = first[s + 1] - first[s]
+        assert np.array_equal(R[:w], np.arange(first[s], first[s + 1]))
+        assert np.all(np.diff(R) > 0)
+        # every exact column structure of the supernode lies inside R
+        for j in (first[s], first[s + 1] - 1):
+            ex = sym.Lrowind[sym.Lcolptr[j]:sym.Lcolptr[j + 1]]
+            assert np.all(np.isin(ex, R))
+        p = sparent[s]
+        last = first[s + 1] - 1
+        if sym.parent[last] < 0:
+            assert p == -1 and len(R) == w
+        else:
+            assert p == col2sn[sym.parent[last]]
+            assert level[p] > level[s]          # strictly lower level
+            Rp = rows[rowptr[p]:rowptr[p + 1]]
+            assert np.all(np.isin(R[w:], Rp))    # update rows land in the parent
+        # every column but the last has its etree parent inside the
+        # supernode (a chain for fundamental supernodes; amalgamation may
+        # attach a child's last column anywhere inside its parent)
+        for j in range(first[s], last):
+            assert first[s] < sym.parent[j] <= last
+    # levels: leaves at 0, every level non-empty
+    assert level.min() == 0
+    assert set(np.unique(level)) == set(range(level.max() + 1))
+
+
+def test_config_sizes_match_survey_estimates():
+    """nnz(A), nnz(L) and flops of configs 0-2 (the generator and the
+    analysis agree with the independent oracle)."""
+    import paper_2110_12865_amd as S
+    for idx, nnzA in ((0, 3008), (2, 1046529)):
+        w = W.config(idx, batch=1)
+        p = w.pattern
+        assert p.nnz == nnzA
+        plan = S.analyze(p.colptr, p.rowind, w.perm)
+        sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+        assert plan.info()["nnzL"] == sym.nnzL
+
+
+def test_options_validation():
+    import paper_2110_12865_amd as S
+    w = W.small_grid((5, 5), "nd")
+    p = w.pattern
+    with pytest.raises(S.SpcholError):
+        S.analyze(p.colptr, p.rowind, w.perm, relax_zeros=-1.0)
+    with pytest.raises(S.SpcholError):
+        S.analyze(p.colptr, p.rowind, w.perm, small_front=-3)
