@@ -409,7 +409,36 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             }
             P->lvl_small_ptr[l + 1] = int32_t(P->lvl_small.size());
             P->lvl_big_ptr[l + 1] = int32_t(P->lvl_big.size());
+            P->max_lvl_big = std::max(P->max_lvl_big, P->lvl_big_ptr[l + 1] - P->lvl_big_ptr[l]);
             P->lvl_ptr[l + 1] = int32_t(P->lvl_sn.size());
+        }
+        // solve schedule and per-supernode solve workspaces
+        P->slv_small_ptr.assign(nlev + 1, 0);
+        P->slv_pan_ptr.assign(nlev + 1, 0);
+        P->slv_small_maxc.assign(nlev, 0);
+        P->slv_pan_maxw.assign(nlev, 0);
+        P->slv_pan_maxc.assign(nlev, 0);
+        for (int32_t s = 0; s < ns; s++) { P->sn[s].dinv = -1; P->sn[s].part = 0; }
+        for (int32_t l = 0; l < nlev; l++) {
+            for (int32_t s : bya[l]) {
+                SnDesc &d = P->sn[s];
+                if (solve_by_panels(d)) {
+                    const int64_t np = (d.w + kSolvePanel - 1) / kSolvePanel;
+                    d.dinv = P->dinv_size;
+                    P->dinv_size += np * kSolvePanel * kSolvePanel;
+                    d.part = P->part_size;
+                    P->part_size += ((d.c + kSolveChunk - 1) / kSolveChunk) * kSolvePanel;
+                    P->slv_pan.push_back(s);
+                    P->slv_pan_maxw[l] = std::max(P->slv_pan_maxw[l], d.w);
+                    P->slv_pan_maxc[l] = std::max(P->slv_pan_maxc[l], d.c);
+                    P->npan++;
+                } else {
+                    P->slv_small.push_back(s);
+                    P->slv_small_maxc[l] = std::max(P->slv_small_maxc[l], d.c);
+                }
+            }
+            P->slv_small_ptr[l + 1] = int32_t(P->slv_small.size());
+            P->slv_pan_ptr[l + 1] = int32_t(P->slv_pan.size());
         }
     } catch (const std::bad_alloc &) {
         delete P;

@@ -13,7 +13,8 @@
 #include "spchol.h"
 
 const char *const kKernelNames[KK_Count] = {
-    "front_small", "assemble", "potrf", "trsm", "syrk_mfma", "solve_fwd", "solve_bwd"};
+    "front_small", "assemble", "potrf", "trsm", "syrk_mfma", "diag_inverse",
+    "solve_fwd", "solve_fwd_panel", "solve_bwd", "solve_bwd_panel"};
 
 void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
@@ -37,7 +38,8 @@ void free_devplan(DevPlan *D) {
     if (!D) return;
     void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
                     D->avidx, D->perm, D->lvl_small, D->lvl_big, D->lvl_sn,
-                    D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx};
+                    D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
+                    D->slv_small, D->slv_pan};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete D;
@@ -69,6 +71,8 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->lvl_big, P->lvl_big);
     if (e == hipSuccess) e = upload(&D->lvl_sn, P->lvl_sn);
     if (e == hipSuccess) e = upload(&D->big_colstart, P->big_colstart);
+    if (e == hipSuccess) e = upload(&D->slv_small, P->slv_small);
+    if (e == hipSuccess) e = upload(&D->slv_pan, P->slv_pan);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
     if (e == hipSuccess) e = upload(&D->csr_col, P->csr_col);
     if (e == hipSuccess) e = upload(&D->csr_vidx, P->csr_vidx);
@@ -92,17 +96,26 @@ sc_status map_err(hipError_t e) {
 // Solve workspaces for nrhs right-hand sides per matrix.
 hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
     if (nrhs <= N->ws_nrhs) return hipSuccess;
-    if (N->ws_y) (void)hipFree(N->ws_y);
-    if (N->ws_u) (void)hipFree(N->ws_u);
+    void *old[] = {N->ws_y, N->ws_u, N->ws_part, N->ws_cnt};
+    for (void *q : old)
+        if (q) (void)hipFree(q);
     N->ws_y = nullptr;
     N->ws_u = nullptr;
+    N->ws_part = nullptr;
+    N->ws_cnt = nullptr;
     N->ws_nrhs = 0;
     const size_t cnt = size_t(N->batch) * nrhs;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&N->ws_y),
                              std::max<size_t>(cnt * P->n * sizeof(double), 8));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&N->ws_u),
-                      std::max<size_t>(cnt * P->relsize * sizeof(double), 8));
+                      std::max<size_t>(cnt * P->rows.size() * sizeof(double), 8));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&N->ws_part),
+                      std::max<size_t>(cnt * P->part_size * sizeof(double), 8));
+    const size_t cbytes = std::max<size_t>(cnt * P->npan * sizeof(int32_t), 8);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&N->ws_cnt), cbytes);
+    if (e == hipSuccess) e = hipMemset(N->ws_cnt, 0, cbytes);
     if (e == hipSuccess) N->ws_nrhs = nrhs;
     return e;
 }
@@ -252,6 +265,12 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
     hipError_t e = hipMalloc(&N->L, std::max<size_t>(size_t(batch) * P->Lsize * sz, 8));
     if (e == hipSuccess) e = hipMalloc(&N->U, std::max<size_t>(size_t(batch) * P->Usize * sz, 8));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&N->info), sizeof(int32_t) * batch);
+    if (e == hipSuccess)
+        e = hipMalloc(&N->pinv,
+                      std::max<size_t>(size_t(batch) * P->max_lvl_big * kTile * kTile * sz, 8));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&N->dinv),
+                      std::max<size_t>(size_t(batch) * P->dinv_size * sizeof(double), 8));
     if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * batch);
     if (e != hipSuccess) {
         sc_numeric_destroy(N);
@@ -266,8 +285,9 @@ void sc_numeric_destroy(sc_numeric_t *N) {
     if (N->L) (void)hipFree(N->L);
     if (N->U) (void)hipFree(N->U);
     if (N->info) (void)hipFree(N->info);
-    if (N->ws_y) (void)hipFree(N->ws_y);
-    if (N->ws_u) (void)hipFree(N->ws_u);
+    void *ws[] = {N->pinv, N->dinv, N->ws_y, N->ws_u, N->ws_part, N->ws_cnt};
+    for (void *q : ws)
+        if (q) (void)hipFree(q);
     free_refine_ws(N->rws);
     delete N;
 }

@@ -11,13 +11,19 @@
 // Tile of the blocked dense kernels (rows/columns of a trailing-update tile
 // and panel width of the blocked partial factorization).
 constexpr int kTile = 64;
+// Width of the outer blocks of the blocked partial factorization: panels of
+// kTile columns update only the columns of their block; the trailing matrix
+// beyond the block is updated once per block with a rank-kBlock product.
+constexpr int kBlock = 256;
 
 // One kernel launch of the factor schedule.  The schedule depends only on
 // the pattern, so it is built once per plan and replayed by every call.
 struct FLaunch {
     enum Kind : int { Small, Assemble, Potrf, Trsm, Syrk } kind;
     int32_t level;
-    int32_t k;        // panel start column (Potrf/Trsm/Syrk)
+    int32_t k;        // panel start column (Potrf/Trsm/Syrk inner)
+    int32_t K0;       // block start column (Syrk)
+    int32_t outer;    // Syrk: 1 = update beyond the block, 0 = inside it
     int32_t list0;    // first entry in the level's list
     int32_t nlist;    // entries
     int64_t gridx;    // workgroups along x
@@ -27,13 +33,21 @@ struct FLaunch {
     double ibytes;    // algorithmic index/value bytes per matrix
 };
 
+struct SPanel {  // one 64-column panel step of a level's panel-solved supernodes
+    int64_t fwd_tiles = 0;   // 64-row tiles below the panel (max over supernodes)
+    int64_t bwd_chunks = 0;  // row chunks of the backward step (max, >= 1)
+    double flops = 0.0;      // per right-hand side
+    double words = 0.0;      // factor scalars read per right-hand side
+    double vbytes = 0.0;     // vector and inverse-block bytes per right-hand side
+};
+
 struct SLaunch {  // one level of a triangular solve
-    int32_t level;
-    int32_t list0, nlist;
-    int32_t maxc;
-    double flops;     // per right-hand side
-    double words;     // factor scalars read per right-hand side
-    double vbytes;    // vector bytes per right-hand side
+    int32_t level = 0;
+    int32_t small0 = 0, nsmall = 0;  // supernodes solved in LDS
+    int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
+    int32_t maxc_small = 0, maxc_pan = 0, maxc = 0;
+    double f_small = 0.0, w_small = 0.0, v_small = 0.0, v_pan = 0.0;
+    std::vector<SPanel> panels;
 };
 
 struct DevPlan {
@@ -49,6 +63,8 @@ struct DevPlan {
     int32_t *lvl_big = nullptr;
     int32_t *lvl_sn = nullptr;
     int64_t *big_colstart = nullptr;  // per big entry: first column index in its level
+    int32_t *slv_small = nullptr;     // solve schedule lists
+    int32_t *slv_pan = nullptr;
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int32_t *csr_col = nullptr;
     int64_t *csr_vidx = nullptr;
@@ -58,8 +74,8 @@ struct DevPlan {
 
 // Kernel kinds for per-launch timing.
 enum KernelKind : int {
-    KK_SmallFront = 0, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk, KK_Fwd, KK_Bwd,
-    KK_Count
+    KK_SmallFront = 0, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk, KK_Dinv,
+    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Count
 };
 extern const char *const kKernelNames[KK_Count];
 
@@ -115,8 +131,12 @@ struct sc_numeric {
     void *L = nullptr;       // batch * Lsize scalars
     void *U = nullptr;       // batch * Usize scalars
     int32_t *info = nullptr; // batch
-    double *ws_y = nullptr;  // batch * nrhs * n
-    double *ws_u = nullptr;  // batch * nrhs * relsize
+    void *pinv = nullptr;    // batch * max_lvl_big * 64 * 64: panel inverses (factor)
+    double *dinv = nullptr;  // batch * dinv_size: inverted diagonal blocks
+    double *ws_y = nullptr;  // batch * nrhs * n: y, then z (permuted)
+    double *ws_u = nullptr;  // batch * nrhs * sum(c_s): front vectors
+    double *ws_part = nullptr;  // batch * nrhs * part_size
+    int32_t *ws_cnt = nullptr;  // npan * batch * nrhs arrival counters
     int32_t ws_nrhs = 0;
     Profiler prof;
     RefineWs rws;
@@ -130,6 +150,7 @@ hipError_t spchol_factor_run(const sc_plan *P, sc_numeric *N,
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b,
                             int32_t nrhs, int64_t ldb, hipStream_t st,
                             const int32_t *active);
+hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
                              int64_t ldv, const double *b, double *x, int32_t nrhs,
                              int64_t ldb, double tol, int32_t maxit, double *stat_host,

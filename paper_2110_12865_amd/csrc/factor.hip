@@ -212,41 +212,152 @@ __global__ __launch_bounds__(256) void k_assemble(
     }
 }
 
-// diagonal block of panel k: unblocked Cholesky in LDS
+// Factor and invert the kb x kb diagonal block (kb <= 64) whose top-left
+// corner is (r0, r0) in a column-major L block, with one wave (lanes 0..63
+// of the calling workgroup; other lanes must not call).  Lane i keeps row i
+// in registers; the right-looking updates read the pivot column with
+// readlane, so the loops are fully unrolled.  The factor is written back
+// (zeros above the diagonal) and through LDS (Ls, 64 x 65 scalars) the
+// inverse X = L^{-1} is formed column by column (lane c owns column c) and
+// stored row-major in PIg (PIg[i * 64 + c] = X[i][c]).  A pivot that fails
+// d > 0 is recorded (smallest 1-based step wins) and replaced by 1.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf(
+__device__ inline T lane_bcast(T v, int src);
+template <>
+__device__ inline double lane_bcast<double>(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<unsigned int>(lo)));
+}
+template <>
+__device__ inline float lane_bcast<float>(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+template <typename T>
+__device__ void wave_diag_factor(T *Lb, int c, int r0, int kb, T *Ls, T *PIg, int col0,
+                                 int32_t *info_b) {
+    const int lane = threadIdx.x & 63;
+    T a[kTile];
+#pragma unroll
+    for (int t = 0; t < kTile; t++)
+        a[t] = (t < kb && lane < kb) ? Lb[int64_t(r0 + t) * c + r0 + lane] : T(0);
+#pragma unroll
+    for (int j = 0; j < kTile; j++) {
+        if (j < kb) {
+            T djj = lane_bcast(a[j], j);
+            const bool bad = !(djj > T(0));
+            if (bad) djj = T(1);
+            const T ljj = dsqrt(djj);
+            if (lane == j) {
+                a[j] = ljj;
+                if (bad) atomicMin(info_b, col0 + j + 1);
+            } else if (lane > j) {
+                a[j] = a[j] / ljj;
+            }
+#pragma unroll
+            for (int t = j + 1; t < kTile; t++) {
+                const T ltj = lane_bcast(a[j], t);
+                if (lane >= t) a[t] -= a[j] * ltj;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kTile; t++) {
+        if (t < kb && lane < kb) Lb[int64_t(r0 + t) * c + r0 + lane] = lane >= t ? a[t] : T(0);
+        Ls[lane * (kTile + 1) + t] = lane >= t ? a[t] : T(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T x[kTile];
+#pragma unroll
+    for (int i = 0; i < kTile; i++) {
+        if (i < kb) {
+            T sum = lane == i ? T(1) : T(0);
+#pragma unroll
+            for (int t = 0; t < i; t++) sum -= Ls[i * (kTile + 1) + t] * x[t];
+            x[i] = sum / Ls[i * (kTile + 1) + i];
+        } else {
+            x[i] = T(0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kTile; i++) PIg[i * kTile + lane] = (lane < kb) ? x[i] : T(0);
+}
+
+// C[j][i] += sum_t sA[t][j] * sB[t][i] for the wave's 32 x 32 quadrant of a
+// 64 x 64 tile (rows j: 32 (wave & 1) + ..., columns i: 32 (wave >> 1) + ...),
+// both operands in LDS as [t][64]; accumulates onto acc.
+template <typename T>
+__device__ inline void tile_mma(const T *sA, const T *sB, int kbr,
+                                typename Mma<T>::acc_t (&acc)[2][2]) {
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int jw = (wv & 1) * 32, iw = (wv >> 1) * 32;
+    const int lk = lane >> 4, lm = lane & 15;
+    for (int kk = 0; kk < kbr; kk += 4) {
+        const T *rA = sA + (kk + lk) * kTile;
+        const T *rB = sB + (kk + lk) * kTile;
+        T av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++) av[a] = rA[jw + 16 * a + lm];
+#pragma unroll
+        for (int q = 0; q < 2; q++) bv[q] = rB[iw + 16 * q + lm];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int q = 0; q < 2; q++) acc[a][q] = Mma<T>::mma(av[a], bv[q], acc[a][q]);
+    }
+}
+
+template <typename T>
+__device__ inline void acc_zero(typename Mma<T>::acc_t (&acc)[2][2]) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int q = 0; q < 2; q++) acc[a][q] = Mma<T>::zero();
+}
+
+// Position of accumulator item (a, q, r) of this lane inside the 64 x 64 tile
+// computed by tile_mma: row j (first operand) and column i (second operand).
+template <typename T>
+__device__ inline void tile_pos(int a, int q, int r, int &j, int &i) {
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    j = (wv & 1) * 32 + 16 * a + Mma<T>::row(lane >> 4, r);
+    i = (wv >> 1) * 32 + 16 * q + (lane & 15);
+}
+
+// Diagonal block of panel k of each large front: factor and invert (one
+// wave per front).
+template <typename T>
+__global__ __launch_bounds__(64) void k_potrf(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
-    T *__restrict__ L, int64_t Lsize, int32_t *__restrict__ info) {
-    __shared__ T tile[kTile * kTile];
+    T *__restrict__ L, int64_t Lsize, T *__restrict__ PI, int64_t pistride,
+    int32_t *__restrict__ info) {
+    __shared__ T Ls[kTile * (kTile + 1)];
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
     const SnDesc d = sn[s];
     if (k >= d.w) return;
     const int kb = min(kTile, d.w - k);
-    const int c = d.c;
     T *Lb = L + int64_t(b) * Lsize + d.loff;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < kb * kb; e += nt) {
-        const int j = e / kb, i = e - j * kb;
-        tile[j * kTile + i] = Lb[int64_t(k + j) * c + k + i];
-    }
-    __syncthreads();
-    lds_partial_chol(tile, kTile, kb, kb, d.first + k, info + b);
-    for (int e = tid; e < kb * kb; e += nt) {
-        const int j = e / kb, i = e - j * kb;
-        Lb[int64_t(k + j) * c + k + i] = i >= j ? tile[j * kTile + i] : T(0);
-    }
+    T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.x) * kTile * kTile;
+    wave_diag_factor(Lb, d.c, k, kb, Ls, PIg, d.first + k, info + b);
 }
 
-// panel rows below the diagonal block: X <- X L_kk^{-T}, one row per lane.
-// L_kk is read as a broadcast; the row tile is stored transposed ([t][lane])
-// so that every lane hits its own LDS bank.
+// Panel rows below the diagonal block: X <- X L_kk^{-T} = X (L_kk^{-1})^T,
+// a 64 x 64 x kb product per workgroup on the matrix cores.
 template <typename T>
-__global__ __launch_bounds__(64) void k_trsm(
+__global__ __launch_bounds__(256) void k_trsm(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
-    T *__restrict__ L, int64_t Lsize) {
-    __shared__ T Lkk[kTile * kTile];
-    __shared__ T X[kTile * kTile];
+    T *__restrict__ L, int64_t Lsize, const T *__restrict__ PI, int64_t pistride) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sX = reinterpret_cast<T *>(smem_raw);  // [t][r] panel rows
+    T *sP = sX + kTile * kTile;               // [t][j] = inverse[j][t]
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
     const SnDesc d = sn[s];
@@ -256,88 +367,105 @@ __global__ __launch_bounds__(64) void k_trsm(
     const int r0 = k + kb + blockIdx.x * kTile;
     if (r0 >= c) return;
     T *Lb = L + int64_t(b) * Lsize + d.loff;
-    const int lane = threadIdx.x;
-    for (int e = lane; e < kb * kb; e += 64) {
-        const int t = e / kb, j = e - t * kb;
-        Lkk[j * kTile + t] = Lb[int64_t(k + t) * c + k + j];
+    const T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.y) * kTile * kTile;
+    const int tid = threadIdx.x;
+    const int kbr = (kb + 3) & ~3;
+    for (int e = tid; e < kbr * kTile; e += 256) {
+        const int t = e / kTile, i = e - t * kTile;
+        sX[e] = (t < kb && r0 + i < c) ? Lb[int64_t(k + t) * c + r0 + i] : T(0);
+        sP[e] = (t < kb && i < kb) ? PIg[i * kTile + t] : T(0);
     }
-    const int r = r0 + lane;
-    if (r < c)
-        for (int t = 0; t < kb; t++) X[t * kTile + lane] = Lb[int64_t(k + t) * c + r];
     __syncthreads();
-    if (r < c) {
-        for (int j = 0; j < kb; j++) {
-            T a = X[j * kTile + lane];
-            const T *lj = Lkk + j * kTile;
-            for (int t = 0; t < j; t++) a -= X[t * kTile + lane] * lj[t];
-            X[j * kTile + lane] = a / lj[j];
-        }
-        for (int t = 0; t < kb; t++) Lb[int64_t(k + t) * c + r] = X[t * kTile + lane];
-    }
+    typename Mma<T>::acc_t acc[2][2];
+    acc_zero<T>(acc);
+    tile_mma(sP, sX, kbr, acc);
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int q = 0; q < 2; q++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                int j, i;
+                tile_pos<T>(a, q, r, j, i);
+                if (j < kb && r0 + i < c) Lb[int64_t(k + j) * c + r0 + i] = acc[a][q][r];
+            }
 }
 
-// trailing update F[i, j] -= sum_t P[i, t] P[j, t] over the lower tiles of
-// the trailing block, P = panel k after the TRSM.  One 64 x 64 tile per
-// workgroup, four waves of 32 x 32, MFMA 16x16x4.  The MFMA's row index runs
-// over matrix columns so that each lane group writes 16 consecutive rows of
-// one column (column-major storage).
+// Update region of a trailing-update launch for one front: columns
+// [cbeg, cend), rows [column, c), with the panel columns [k0, k0 + kw).
+// Inner update (outer = 0): panel k of block K0 updates the rest of its
+// block.  Outer update: the whole block updates everything beyond it.
+struct SyrkRegion {
+    int k0, kw, cbeg, cend;
+};
+__host__ __device__ inline bool syrk_region(int w, int c, int K0, int k, int outer,
+                                            SyrkRegion &r) {
+    if (K0 >= w) return false;
+    const int K1 = min(K0 + kBlock, w);
+    if (outer) {
+        r.k0 = K0;
+        r.kw = K1 - K0;
+        r.cbeg = K1;
+        r.cend = c;
+    } else {
+        if (k >= K1) return false;
+        r.k0 = k;
+        r.kw = min(kTile, w - k);
+        r.cbeg = k + r.kw;
+        r.cend = K1;
+    }
+    return r.cbeg < r.cend;
+}
+__host__ __device__ inline int64_t syrk_pairs(int c, const SyrkRegion &r) {
+    const int64_t nct = (r.cend - r.cbeg + kTile - 1) / kTile;
+    const int64_t nrt = (c - r.cbeg + kTile - 1) / kTile;
+    return nct * nrt - nct * (nct - 1) / 2;
+}
+
+// Trailing update F[i, j] -= sum_t P[i, t] P[j, t] over the lower 64 x 64
+// tiles of a region, P = panel columns after the TRSM, K in chunks of 64
+// through LDS; MFMA 16x16x4 with four waves of 32 x 32.  The MFMA's row
+// index runs over matrix columns so that each lane group writes 16
+// consecutive rows of one column (column-major storage).
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
-    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize) {
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int K0, int k,
+    int outer, T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sI = reinterpret_cast<T *>(smem_raw);  // [t][i] panel rows of tile I
     T *sJ = sI + kTile * kTile;               // [t][j] panel rows of tile J
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
     const SnDesc d = sn[s];
-    if (k >= d.w) return;
     const int c = d.c, w = d.w, m = d.m;
-    const int kb = min(kTile, w - k);
-    const int t0 = k + kb;
-    const int nrem = c - t0;
-    if (nrem <= 0) return;
-    const int ntl = (nrem + kTile - 1) / kTile;
-    const int64_t p = blockIdx.x;
-    if (p >= int64_t(ntl) * (ntl + 1) / 2) return;
-    int I = int((sqrt(8.0 * double(p) + 1.0) - 1.0) * 0.5);
-    while (int64_t(I) * (I + 1) / 2 > p) I--;
-    while (int64_t(I + 1) * (I + 2) / 2 <= p) I++;
-    const int J = int(p - int64_t(I) * (I + 1) / 2);
-    const int row0 = t0 + I * kTile, col0 = t0 + J * kTile;
+    SyrkRegion R;
+    if (!syrk_region(w, c, K0, k, outer, R)) return;
+    const int64_t npairs = syrk_pairs(c, R);
+    int64_t p = blockIdx.x;
+    if (p >= npairs) return;
+    const int nrt = (c - R.cbeg + kTile - 1) / kTile;
+    int J = 0;
+    while (p >= nrt - J) { p -= nrt - J; J++; }
+    const int I = J + int(p);
+    const int row0 = R.cbeg + I * kTile, col0 = R.cbeg + J * kTile;
     T *Lb = L + int64_t(b) * Lsize + d.loff;
     T *Ub = U + int64_t(b) * Usize + d.uoff;
     const int tid = threadIdx.x;
-    const int kbr = (kb + 3) & ~3;
-    for (int e = tid; e < kbr * kTile; e += 256) {
-        const int t = e / kTile, i = e - t * kTile;
-        const bool tk = t < kb;
-        const T *pc = Lb + int64_t(k + t) * c;
-        sI[e] = (tk && row0 + i < c) ? pc[row0 + i] : T(0);
-        sJ[e] = (tk && col0 + i < c) ? pc[col0 + i] : T(0);
-    }
-    __syncthreads();
-    const int wv = tid >> 6, lane = tid & 63;
-    const int jw = (wv & 1) * 32, iw = (wv >> 1) * 32;
-    const int lk = lane >> 4, lm = lane & 15;
-    typedef typename Mma<T>::acc_t acc_t;
-    acc_t acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int q = 0; q < 2; q++) acc[a][q] = Mma<T>::zero();
-    for (int kk = 0; kk < kbr; kk += 4) {
-        const T *rJ = sJ + (kk + lk) * kTile;
-        const T *rI = sI + (kk + lk) * kTile;
-        T av[2], bv[2];
-#pragma unroll
-        for (int a = 0; a < 2; a++) av[a] = rJ[jw + 16 * a + lm];
-#pragma unroll
-        for (int q = 0; q < 2; q++) bv[q] = rI[iw + 16 * q + lm];
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int q = 0; q < 2; q++) acc[a][q] = Mma<T>::mma(av[a], bv[q], acc[a][q]);
+    typename Mma<T>::acc_t acc[2][2];
+    acc_zero<T>(acc);
+    for (int kc = 0; kc < R.kw; kc += kTile) {
+        const int kb = min(kTile, R.kw - kc);
+        const int kbr = (kb + 3) & ~3;
+        if (kc > 0) __syncthreads();
+        for (int e = tid; e < kbr * kTile; e += 256) {
+            const int t = e / kTile, i = e - t * kTile;
+            const bool tk = t < kb;
+            const T *pc = Lb + int64_t(R.k0 + kc + t) * c;
+            sI[e] = (tk && row0 + i < c) ? pc[row0 + i] : T(0);
+            sJ[e] = (tk && col0 + i < R.cend) ? pc[col0 + i] : T(0);
+        }
+        __syncthreads();
+        tile_mma(sJ, sI, kbr, acc);
     }
 #pragma unroll
     for (int a = 0; a < 2; a++)
@@ -345,9 +473,10 @@ __global__ __launch_bounds__(256) void k_syrk(
         for (int q = 0; q < 2; q++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int j = col0 + jw + 16 * a + Mma<T>::row(lk, r);
-                const int i = row0 + iw + 16 * q + lm;
-                if (i < c && j < c && i >= j) {
+                int jj, ii;
+                tile_pos<T>(a, q, r, jj, ii);
+                const int j = col0 + jj, i = row0 + ii;
+                if (i < c && j < R.cend && i >= j) {
                     T *pcol = front_col(Lb, Ub, c, w, m, j);
                     pcol[i] -= acc[a][q][r];
                 }
@@ -361,6 +490,8 @@ void set_lds_limits(int big) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_syrk<T>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trsm<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
@@ -390,7 +521,7 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
     for (int32_t l = 0; l < P->nlevels; l++) {
         const int32_t s0 = P->lvl_small_ptr[l], s1 = P->lvl_small_ptr[l + 1];
         if (s1 > s0) {
-            FLaunch f{FLaunch::Small, l, 0, s0, s1 - s0, s1 - s0,
+            FLaunch f{FLaunch::Small, l, 0, 0, 0, s0, s1 - s0, s1 - s0,
                       P->lvl_small_maxc[l] * P->lvl_small_maxc[l], 0.0, 0.0, 0.0};
             for (int32_t e = s0; e < s1; e++) {
                 const SnDesc &d = P->sn[P->lvl_small[e]];
@@ -402,7 +533,7 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
         }
         const int32_t b0 = P->lvl_big_ptr[l], b1 = P->lvl_big_ptr[l + 1];
         if (b1 == b0) continue;
-        FLaunch fa{FLaunch::Assemble, l, 0, b0, b1 - b0, P->lvl_bigcols[l],
+        FLaunch fa{FLaunch::Assemble, l, 0, 0, 0, b0, b1 - b0, P->lvl_bigcols[l],
                    P->lvl_big_maxc[l], 0.0, 0.0, 0.0};
         for (int32_t e = b0; e < b1; e++) {
             const SnDesc &d = P->sn[P->lvl_big[e]];
@@ -412,34 +543,48 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
             fa.ibytes += a_entries(d) * 20.0;
         }
         D->fsched.push_back(fa);
-        for (int32_t k = 0; k < P->lvl_big_maxw[l]; k += kTile) {
-            int64_t trsm_tiles = 0, pairs = 0;
-            FLaunch fp{FLaunch::Potrf, l, k, b0, b1 - b0, b1 - b0, 0, 0.0, 0.0, 0.0};
-            FLaunch ft{FLaunch::Trsm, l, k, b0, b1 - b0, 0, 0, 0.0, 0.0, 0.0};
-            FLaunch fs{FLaunch::Syrk, l, k, b0, b1 - b0, 0, 2 * kTile * kTile, 0.0, 0.0, 0.0};
+        auto add_syrk = [&](int K0, int k, int outer) {
+            FLaunch fs{FLaunch::Syrk, l, k, K0, outer, b0, b1 - b0, 0, 2 * kTile * kTile,
+                       0.0, 0.0, 0.0};
             for (int32_t e = b0; e < b1; e++) {
                 const SnDesc &d = P->sn[P->lvl_big[e]];
-                if (k >= d.w) continue;
-                const int kb = std::min(kTile, d.w - k);
-                const int64_t nrem = d.c - k - kb;
-                const int64_t nt = (nrem + kTile - 1) / kTile;
-                trsm_tiles = std::max(trsm_tiles, nt);
-                pairs = std::max(pairs, nt * (nt + 1) / 2);
-                const double r = double(nrem);
-                fp.flops += front_flops(kb, kb);
-                fp.words += double(kb) * (kb + 1);
-                ft.flops += r * kb * kb;
-                ft.words += 2.0 * r * kb + double(kb) * (kb + 1) / 2;
-                fs.flops += double(kb) * r * (r + 1);
-                fs.words += r * (r + 1) + r * kb;
+                SyrkRegion R;
+                if (!syrk_region(d.w, d.c, K0, k, outer, R)) continue;
+                fs.gridx = std::max(fs.gridx, syrk_pairs(d.c, R));
+                const double ncol = R.cend - R.cbeg;
+                const double entries = ncol * d.c - (double(R.cend - 1) * R.cend / 2.0 -
+                                                     double(R.cbeg - 1) * R.cbeg / 2.0);
+                fs.flops += 2.0 * R.kw * entries;
+                fs.words += 2.0 * entries + double(d.c - R.cbeg) * R.kw;
             }
-            ft.gridx = trsm_tiles;
-            fs.gridx = pairs;
-            D->fsched.push_back(fp);
-            if (trsm_tiles > 0) {
-                D->fsched.push_back(ft);
-                D->fsched.push_back(fs);
+            if (fs.gridx > 0) D->fsched.push_back(fs);
+        };
+        for (int32_t K0 = 0; K0 < P->lvl_big_maxw[l]; K0 += kBlock) {
+            for (int32_t k = K0; k < std::min(K0 + kBlock, P->lvl_big_maxw[l]); k += kTile) {
+                FLaunch fp{FLaunch::Potrf, l, k, 0, 0, b0, b1 - b0, b1 - b0, 0, 0.0, 0.0, 0.0};
+                for (int32_t e = b0; e < b1; e++) {
+                    const SnDesc &d = P->sn[P->lvl_big[e]];
+                    if (k >= d.w) continue;
+                    const int kb = std::min(kTile, d.w - k);
+                    fp.flops += front_flops(kb, kb) + double(kb) * kb * kb / 3.0;
+                    fp.words += double(kb) * (kb + 1) + double(kb) * kb;
+                }
+                D->fsched.push_back(fp);
+                FLaunch ft{FLaunch::Trsm, l, k, 0, 0, b0, b1 - b0, 0, 2 * kTile * kTile,
+                           0.0, 0.0, 0.0};
+                for (int32_t e = b0; e < b1; e++) {
+                    const SnDesc &d = P->sn[P->lvl_big[e]];
+                    if (k >= d.w) continue;
+                    const int kb = std::min(kTile, d.w - k);
+                    const int64_t nrem = d.c - k - kb;
+                    ft.gridx = std::max<int64_t>(ft.gridx, (nrem + kTile - 1) / kTile);
+                    ft.flops += 2.0 * double(nrem) * kb * kb;
+                    ft.words += 2.0 * double(nrem) * kb + double(kb) * kb;
+                }
+                if (ft.gridx > 0) D->fsched.push_back(ft);
+                add_syrk(K0, k, 0);
             }
+            add_syrk(K0, 0, 1);
         }
     }
 }
@@ -450,6 +595,8 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
     DevPlan *D = P->dev;
     T *L = static_cast<T *>(N->L);
     T *U = static_cast<T *>(N->U);
+    T *PI = static_cast<T *>(N->pinv);
+    const int64_t pistride = int64_t(P->max_lvl_big) * kTile * kTile;
     const int B = N->batch;
     {
         const int64_t nb = (B + 255) / 256;
@@ -478,22 +625,26 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
                                P->Usize);
             break;
         case FLaunch::Potrf:
-            hipLaunchKernelGGL(k_potrf<T>, dim3(unsigned(f.gridx), B), dim3(256), 0, st,
-                               D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize, N->info);
+            hipLaunchKernelGGL(k_potrf<T>, dim3(unsigned(f.gridx), B), dim3(64), 0, st,
+                               D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize, PI, pistride,
+                               N->info);
             break;
         case FLaunch::Trsm:
-            hipLaunchKernelGGL(k_trsm<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(64), 0,
-                               st, D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize);
+            hipLaunchKernelGGL(k_trsm<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),
+                               size_t(f.lds) * sizeof(T), st, D->sn, D->lvl_big + f.list0,
+                               f.k, L, P->Lsize, PI, pistride);
             break;
         case FLaunch::Syrk:
             hipLaunchKernelGGL(k_syrk<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),
                                size_t(f.lds) * sizeof(T), st, D->sn, D->lvl_big + f.list0,
-                               f.k, L, P->Lsize, U, P->Usize);
+                               f.K0, f.k, f.outer, L, P->Lsize, U, P->Usize);
             break;
         }
         prof.end(st);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return spchol_dinv_run(P, N, st);  // inverted diagonal blocks for the solves
 }
 
 }  // namespace

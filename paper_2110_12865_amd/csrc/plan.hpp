@@ -22,8 +22,17 @@ struct SnDesc {
     int32_t chend;
     int32_t parent;  // supernodal parent, -1 for a root
     int32_t level;   // longest path from the leaves
+    int64_t dinv;    // offset of the inverted 64x64 diagonal blocks (solve
+                     // by panels), -1 when the supernode is solved in LDS
+    int64_t part;    // offset of the backward-solve partial sums
 };
-static_assert(sizeof(SnDesc) == 64, "SnDesc layout");
+static_assert(sizeof(SnDesc) == 80, "SnDesc layout");
+
+// A supernode is solved by 64-column panels across many workgroups when it
+// is wide or tall; otherwise one workgroup solves it out of LDS.
+constexpr int kSolvePanel = 64;
+constexpr int kSolveChunk = 256;  // rows per workgroup in the backward panel step
+inline bool solve_by_panels(const SnDesc &d) { return d.w > kSolvePanel || d.c > 512; }
 
 struct DevPlan;  // device copies, defined by the HIP side
 
@@ -77,8 +86,15 @@ struct sc_plan {
     std::vector<int32_t> lvl_small_maxc, lvl_big_maxc, lvl_big_maxw;
     std::vector<int32_t> lvl_ptr, lvl_sn;  // all supernodes of each level
     std::vector<int32_t> lvl_maxc;
+    // solve schedule: per level, supernodes solved in LDS and by panels
+    std::vector<int32_t> slv_small_ptr, slv_small, slv_pan_ptr, slv_pan;
+    std::vector<int32_t> slv_small_maxc, slv_pan_maxw, slv_pan_maxc;
+    int64_t dinv_size = 0;   // scalars of inverted diagonal blocks
+    int64_t part_size = 0;   // partial sums per right-hand side
+    int32_t npan = 0;        // supernodes solved by panels
     std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts
     std::vector<int64_t> big_colstart;    // per big entry: first column in its level
+    int32_t max_lvl_big = 0;              // most large fronts in one level
 
     mutable DevPlan *dev = nullptr;
     mutable int dev_id = -1;

@@ -3,26 +3,80 @@
 // descending, x = P^T z.  The factor may be stored in FP64 or FP32; the
 // solves always compute in FP64.
 //
-// Forward solve, multifrontal style: supernode s solves its diagonal block
-// and produces an update vector u_s (its m update rows), which the parent
-// pulls and folds into its own right-hand side and update vector.  Every
-// value is written by exactly one workgroup, children are read in a fixed
-// order, and no floating-point atomics are used.
-// Backward solve: supernode s gathers the already final solution on its
-// update rows (owned by its ancestors) and solves with L_ss^T.
+// Every supernode s owns a front vector FV_s of c_s entries: the first w_s
+// hold its right-hand side, the last m_s its negated update vector
+// u~_s = -sum over its subtree of L[R_s, k] y_k, which the parent pulls.
+// Every value is written by exactly one workgroup, children are folded in a
+// fixed order and reductions use fixed trees, so results are
+// bit-reproducible and free of floating-point atomics.
+//
+// Small supernodes are solved by one workgroup out of LDS.  Wide or tall
+// ones are solved by 64-column panels across many workgroups, using the
+// inverted 64x64 diagonal blocks computed after the factorization:
+//   forward  y_p = D_p^{-1} v_p (every workgroup recomputes it), then each
+//            workgroup updates its own 64 rows below the panel;
+//   backward each workgroup forms partial dot products for a chunk of rows,
+//            the last one to finish (atomic counter, no waiting) sums them
+//            in chunk order and applies D_p^{-T}.
 #include <algorithm>
 
 #include "device.hpp"
 
 namespace {
 
+constexpr int kP = kSolvePanel;
+
+// Inverse of every 64x64 diagonal block of every panel-solved supernode:
+// X = L_pp^{-1} by forward substitution, one lane per column of X kept in
+// registers (loops fully unrolled), L_pp read from LDS as broadcasts.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fwd(
+__global__ __launch_bounds__(64) void k_dinv(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const T *__restrict__ L, int64_t Lsize, double *__restrict__ Dinv, int64_t dsize) {
+    __shared__ double Lp[kP * (kP + 1)];  // [i][t] row-major
+    const int s = list[blockIdx.y];
+    const int b = blockIdx.z;
+    const SnDesc d = sn[s];
+    const int p = blockIdx.x;
+    const int c0 = p * kP;
+    if (c0 >= d.w) return;
+    const int kb = min(kP, d.w - c0);
+    const int c = d.c;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    const int lane = threadIdx.x;
+#pragma unroll 8
+    for (int t = 0; t < kP; t++)
+        Lp[lane * (kP + 1) + t] =
+            (lane < kb && t < kb) ? double(Lb[int64_t(c0 + t) * c + c0 + lane]) : (lane == t ? 1.0 : 0.0);
+    __syncthreads();
+    double x[kP];
+#pragma unroll
+    for (int i = 0; i < kP; i++) {
+        double sum = lane == i ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < i; t++) sum -= Lp[i * (kP + 1) + t] * x[t];
+        x[i] = sum / Lp[i * (kP + 1) + i];
+    }
+    double *D = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+    __syncthreads();  // every read of Lp above precedes the transpose below
+#pragma unroll
+    for (int i = 0; i < kP; i++)  // column-major: D[col * 64 + i] = X[i][col], col = lane
+        Lp[lane * (kP + 1) + i] = (lane < kb && i < kb) ? x[i] : 0.0;
+    __syncthreads();
+#pragma unroll 8
+    for (int col = 0; col < kP; col++) D[col * kP + lane] = Lp[col * (kP + 1) + lane];
+}
+
+// Forward step of one level for supernodes solved in LDS (solve = 1), or
+// only the gather of the right-hand side and the children's update vectors
+// into FV_s for panel-solved supernodes (solve = 0).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_small(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int solve,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ relmap,
     const int32_t *__restrict__ chlist, const T *__restrict__ L, int64_t Lsize,
     const double *__restrict__ B, int64_t ldb, double *__restrict__ Y,
-    double *__restrict__ UV, int64_t n, int64_t relsize, int nrhs,
+    double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     const int32_t *__restrict__ active) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *v = reinterpret_cast<double *>(smem_raw);
@@ -31,42 +85,92 @@ __global__ __launch_bounds__(256) void k_fwd(
     const int b = br / nrhs;
     if (active && !active[b]) return;
     const SnDesc d = sn[s];
-    const int c = d.c, w = d.w, m = d.m;
+    const int c = d.c, w = d.w;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
     const double *bb = B + int64_t(br) * ldb;
-    double *y = Y + int64_t(br) * n;
-    double *uv = UV + int64_t(br) * relsize;
+    double *fvb = FV + int64_t(br) * fvsize;
 
     for (int i = tid; i < c; i += nt) v[i] = i < w ? bb[perm[d.first + i]] : 0.0;
     for (int q = d.chbeg; q < d.chend; q++) {
         const SnDesc cd = sn[chlist[q]];
         const int32_t *rm = relmap + cd.relptr;
-        const double *uc = uv + cd.relptr;
+        const double *uc = fvb + cd.rowptr + cd.w;
         __syncthreads();
-        for (int i = tid; i < cd.m; i += nt) {
-            const int p = rm[i];
-            if (p < w) v[p] -= uc[i]; else v[p] += uc[i];
-        }
+        for (int i = tid; i < cd.m; i += nt) v[rm[i]] += uc[i];
     }
     __syncthreads();
-    for (int j = 0; j < w; j++) {
-        const T *lj = Lb + int64_t(j) * c;
-        const double yj = v[j] / double(lj[j]);
-        __syncthreads();
-        for (int i = j + 1 + tid; i < c; i += nt) {
-            const double l = double(lj[i]);
-            if (i < w) v[i] -= l * yj; else v[i] += l * yj;
+    if (solve) {
+        const T *Lb = L + int64_t(b) * Lsize + d.loff;
+        for (int j = 0; j < w; j++) {
+            const T *lj = Lb + int64_t(j) * c;
+            const double yj = v[j] / double(lj[j]);
+            __syncthreads();
+            for (int i = j + 1 + tid; i < c; i += nt) v[i] -= double(lj[i]) * yj;
+            if (tid == 0) v[j] = yj;
+            __syncthreads();
         }
-        if (tid == 0) v[j] = yj;
-        __syncthreads();
+        double *y = Y + int64_t(br) * n;
+        for (int i = tid; i < w; i += nt) y[d.first + i] = v[i];
+        for (int i = w + tid; i < c; i += nt) fvb[d.rowptr + i] = v[i];
+    } else {
+        for (int i = tid; i < c; i += nt) fvb[d.rowptr + i] = v[i];
     }
-    for (int i = tid; i < w; i += nt) y[d.first + i] = v[i];
-    for (int i = tid; i < m; i += nt) uv[d.relptr + i] = v[w + i];
 }
 
+// Forward panel p of panel-solved supernodes.  Workgroup 0 writes y_p;
+// workgroup t >= 1 updates rows [c0 + kb + 64 (t-1), +64) of FV_s.
 template <typename T>
-__global__ __launch_bounds__(256) void k_bwd(
+__global__ __launch_bounds__(64) void k_fwd_panel(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p,
+    const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv,
+    int64_t dsize, double *__restrict__ Y, double *__restrict__ FV, int64_t n,
+    int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
+    __shared__ double y[kP];
+    const int s = list[blockIdx.y];
+    const int br = blockIdx.z;
+    const int b = br / nrhs;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c0 = p * kP;
+    if (c0 >= d.w) return;
+    const int kb = min(kP, d.w - c0);
+    const int c = d.c;
+    const int tile = blockIdx.x;
+    const int r0 = tile == 0 ? c0 : c0 + kb + (tile - 1) * kP;
+    if (r0 >= c) return;
+    double *fv = FV + int64_t(br) * fvsize + d.rowptr;
+    const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+    const int lane = threadIdx.x;
+    __shared__ double vp[kP];
+    vp[lane] = lane < kb ? fv[c0 + lane] : 0.0;
+    __syncthreads();
+    double yi = 0.0;
+#pragma unroll 16
+    for (int t = 0; t < kP; t++) yi += Dp[t * kP + lane] * vp[t];  // D is zero-padded
+    y[lane] = yi;
+    __syncthreads();
+    if (tile == 0) {
+        if (lane < kb) Y[int64_t(br) * n + d.first + c0 + lane] = yi;
+        return;
+    }
+    const int r = r0 + lane;
+    if (r < c) {
+        const T *Lb = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + r;
+        double acc0 = 0.0, acc1 = 0.0;
+        int t = 0;
+#pragma unroll 8
+        for (; t + 1 < kb; t += 2) {
+            acc0 += double(Lb[int64_t(t) * c]) * y[t];
+            acc1 += double(Lb[int64_t(t + 1) * c]) * y[t + 1];
+        }
+        if (t < kb) acc0 += double(Lb[int64_t(t) * c]) * y[t];
+        fv[r] -= acc0 + acc1;
+    }
+}
+
+// Backward step of one level for supernodes solved in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_small(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
     const T *__restrict__ L, int64_t Lsize, double *__restrict__ X,
@@ -110,6 +214,90 @@ __global__ __launch_bounds__(256) void k_bwd(
     }
 }
 
+// Backward panel p of panel-solved supernodes: partial sums of
+// L[r, c0 + t] z_r over a chunk of kSolveChunk rows below the panel; the
+// last workgroup of the supernode sums the chunks in order and solves with
+// D_p^T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_panel(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int list0, int p,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
+    const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv, int64_t dsize,
+    double *__restrict__ X, int64_t ldb, double *__restrict__ Y, int64_t n,
+    double *__restrict__ PART, int64_t psize, int32_t *__restrict__ cnt, int nbr, int nrhs,
+    const int32_t *__restrict__ active) {
+    __shared__ double red[4][kP];
+    __shared__ double rhs[kP];
+    __shared__ int last;
+    const int s = list[blockIdx.y];
+    const int br = blockIdx.z;
+    const int b = br / nrhs;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c0 = p * kP;
+    if (c0 >= d.w) return;
+    const int kb = min(kP, d.w - c0);
+    const int c = d.c, w = d.w;
+    const int rbeg = c0 + kb;
+    const int nch = max(1, (c - rbeg + kSolveChunk - 1) / kSolveChunk);
+    const int chunk = blockIdx.x;
+    if (chunk >= nch) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    double *y = Y + int64_t(br) * n;
+    const int32_t *R = rows + d.rowptr;
+    const int r = rbeg + chunk * kSolveChunk + tid;
+    const double zr = r < c ? y[r < w ? d.first + r : R[r]] : 0.0;
+    double pr[kP];
+#pragma unroll
+    for (int t = 0; t < kP; t++)
+        pr[t] = (r < c && t < kb) ? double(Lb[int64_t(c0 + t) * c + r]) * zr : 0.0;
+#pragma unroll
+    for (int t = 0; t < kP; t++) {
+        double v = pr[t];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wv][t] = v;
+    }
+    __syncthreads();
+    double *part = PART + int64_t(br) * psize + d.part;
+    if (tid < kb) part[chunk * kP + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    __threadfence();
+    __syncthreads();
+    int32_t *ctr = cnt + int64_t(list0 + blockIdx.y) * nbr + br;
+    if (tid == 0) last = atomicAdd(ctr, 1) == nch - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (tid < kb) {
+        double sum = 0.0;
+        for (int q = 0; q < nch; q++) sum += part[q * kP + tid];
+        rhs[tid] = y[d.first + c0 + tid] - sum;
+    }
+    __syncthreads();
+    if (tid < kb) {
+        const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+        double xt = 0.0;
+        for (int i = 0; i < kb; i++) xt += Dp[tid * kP + i] * rhs[i];
+        y[d.first + c0 + tid] = xt;
+        X[int64_t(br) * ldb + perm[d.first + c0 + tid]] = xt;
+    }
+    if (tid == 0) *ctr = 0;
+}
+
+template <typename T>
+hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
+    if (P->npan == 0) return hipSuccess;
+    DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const int64_t maxp = (P->max_width + kP - 1) / kP;
+    N->prof.begin(KK_Dinv, 0.0, 0.0, st);
+    hipLaunchKernelGGL(k_dinv<T>, dim3(unsigned(maxp), unsigned(P->npan), unsigned(N->batch)),
+                       dim3(64), 0, st, D->sn, D->slv_pan, L, P->Lsize, N->dinv, P->dinv_size);
+    N->prof.end(st);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
                       int64_t ldb, hipStream_t st, const int32_t *active) {
@@ -117,50 +305,119 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
     for (const SLaunch &l : D->ssched)
         if (size_t(l.maxc) * sizeof(double) > size_t(g_max_lds)) return hipErrorInvalidValue;
     const T *L = static_cast<const T *>(N->L);
-    const unsigned gy = unsigned(N->batch) * unsigned(nrhs);
+    const int nbr = N->batch * nrhs;
+    const unsigned gy = unsigned(nbr);
+    const int64_t fvsize = int64_t(P->rows.size());
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(gy);
     for (const SLaunch &l : D->ssched) {
-        prof.begin(KK_Fwd, l.flops * nr, (l.words * sz + l.vbytes) * nr, st);
-        hipLaunchKernelGGL(k_fwd<T>, dim3(unsigned(l.nlist), gy), dim3(256),
-                           size_t(l.maxc) * sizeof(double), st, D->sn, D->lvl_sn + l.list0,
-                           D->perm, D->relmap, D->chlist, L, P->Lsize, b, ldb, N->ws_y,
-                           N->ws_u, P->n, P->relsize, nrhs, active);
-        prof.end(st);
+        if (l.nsmall > 0) {
+            prof.begin(KK_Fwd, l.f_small * nr, (l.w_small * sz + l.v_small) * nr, st);
+            hipLaunchKernelGGL(k_fwd_small<T>, dim3(unsigned(l.nsmall), gy), dim3(256),
+                               size_t(l.maxc_small) * sizeof(double), st, D->sn,
+                               D->slv_small + l.small0, 1, D->perm, D->relmap, D->chlist, L,
+                               P->Lsize, b, ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, active);
+            prof.end(st);
+        }
+        if (l.npan > 0) {
+            prof.begin(KK_Fwd, 0.0, l.v_pan * nr, st);
+            hipLaunchKernelGGL(k_fwd_small<T>, dim3(unsigned(l.npan), gy), dim3(256),
+                               size_t(l.maxc_pan) * sizeof(double), st, D->sn,
+                               D->slv_pan + l.pan0, 0, D->perm, D->relmap, D->chlist, L,
+                               P->Lsize, b, ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, active);
+            prof.end(st);
+            for (size_t q = 0; q < l.panels.size(); q++) {
+                const SPanel &pp = l.panels[q];
+                prof.begin(KK_FwdPanel, pp.flops * nr, (pp.words * sz + pp.vbytes) * nr, st);
+                hipLaunchKernelGGL(k_fwd_panel<T>,
+                                   dim3(unsigned(1 + pp.fwd_tiles), unsigned(l.npan), gy),
+                                   dim3(64), 0, st, D->sn, D->slv_pan + l.pan0, int(q), L,
+                                   P->Lsize, N->dinv, P->dinv_size, N->ws_y, N->ws_u, P->n,
+                                   fvsize, nrhs, active);
+                prof.end(st);
+            }
+        }
     }
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
-        prof.begin(KK_Bwd, l.flops * nr, (l.words * sz + l.vbytes) * nr, st);
-        hipLaunchKernelGGL(k_bwd<T>, dim3(unsigned(l.nlist), gy), dim3(256),
-                           size_t(l.maxc) * sizeof(double), st, D->sn, D->lvl_sn + l.list0,
-                           D->perm, D->rows, L, P->Lsize, b, ldb, N->ws_y, P->n, nrhs,
-                           active);
-        prof.end(st);
+        if (l.npan > 0) {
+            for (size_t q = l.panels.size(); q-- > 0;) {
+                const SPanel &pp = l.panels[q];
+                prof.begin(KK_BwdPanel, pp.flops * nr, (pp.words * sz + pp.vbytes) * nr, st);
+                hipLaunchKernelGGL(k_bwd_panel<T>,
+                                   dim3(unsigned(pp.bwd_chunks), unsigned(l.npan), gy),
+                                   dim3(256), 0, st, D->sn, D->slv_pan + l.pan0, l.pan0,
+                                   int(q), D->perm, D->rows, L, P->Lsize, N->dinv,
+                                   P->dinv_size, b, ldb, N->ws_y, P->n, N->ws_part,
+                                   P->part_size, N->ws_cnt, nbr, nrhs, active);
+                prof.end(st);
+            }
+        }
+        if (l.nsmall > 0) {
+            prof.begin(KK_Bwd, l.f_small * nr, (l.w_small * sz + l.v_small) * nr, st);
+            hipLaunchKernelGGL(k_bwd_small<T>, dim3(unsigned(l.nsmall), gy), dim3(256),
+                               size_t(l.maxc_small) * sizeof(double), st, D->sn,
+                               D->slv_small + l.small0, D->perm, D->rows, L, P->Lsize, b, ldb,
+                               N->ws_y, P->n, nrhs, active);
+            prof.end(st);
+        }
     }
     return hipGetLastError();
 }
 
 template <typename T>
 void set_solve_lds(int big) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd<T>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd<T>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_small<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_small<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 }  // namespace
 
+// Solve schedule per level, with the algorithmic work of each launch (per
+// matrix and right-hand side).
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
     D->ssched.clear();
     for (int32_t l = 0; l < P->nlevels; l++) {
-        SLaunch s{l, P->lvl_ptr[l], P->lvl_ptr[l + 1] - P->lvl_ptr[l], P->lvl_maxc[l],
-                  0.0, 0.0, 0.0};
-        for (int32_t e = s.list0; e < s.list0 + s.nlist; e++) {
-            const SnDesc &d = P->sn[P->lvl_sn[e]];
+        SLaunch s{};
+        s.level = l;
+        s.small0 = P->slv_small_ptr[l];
+        s.nsmall = P->slv_small_ptr[l + 1] - s.small0;
+        s.pan0 = P->slv_pan_ptr[l];
+        s.npan = P->slv_pan_ptr[l + 1] - s.pan0;
+        s.maxc_small = P->slv_small_maxc[l];
+        s.maxc_pan = P->slv_pan_maxc[l];
+        s.maxc = std::max(s.maxc_small, s.maxc_pan);
+        for (int32_t e = s.small0; e < s.small0 + s.nsmall; e++) {
+            const SnDesc &d = P->sn[P->slv_small[e]];
             const double lw = double(d.c) * d.w - double(d.w) * (d.w - 1) / 2;
-            s.flops += 2.0 * lw;
-            s.words += lw;
-            s.vbytes += 8.0 * (2.0 * d.c + d.m) + 4.0 * d.c;
+            s.f_small += 2.0 * lw;
+            s.w_small += lw;
+            s.v_small += 8.0 * (2.0 * d.c + d.m) + 4.0 * d.c;
+        }
+        for (int32_t e = s.pan0; e < s.pan0 + s.npan; e++) {
+            const SnDesc &d = P->sn[P->slv_pan[e]];
+            s.v_pan += 8.0 * (2.0 * d.c) + 4.0 * d.c;
+        }
+        const int np = (P->slv_pan_maxw[l] + kP - 1) / kP;
+        for (int q = 0; q < np; q++) {
+            SPanel pp{};
+            for (int32_t e = s.pan0; e < s.pan0 + s.npan; e++) {
+                const SnDesc &d = P->sn[P->slv_pan[e]];
+                const int c0 = q * kP;
+                if (c0 >= d.w) continue;
+                const int kb = std::min(kP, d.w - c0);
+                const int64_t below = d.c - c0 - kb;
+                pp.fwd_tiles = std::max<int64_t>(pp.fwd_tiles, (below + kP - 1) / kP);
+                pp.bwd_chunks = std::max<int64_t>(
+                    pp.bwd_chunks, std::max<int64_t>(1, (below + kSolveChunk - 1) / kSolveChunk));
+                const double lw = double(below) * kb;
+                pp.flops += 2.0 * lw + 2.0 * kb * kb;
+                pp.words += lw;
+                pp.vbytes += 8.0 * (below + 2.0 * kb) + 8.0 * kb * kb;
+            }
+            s.panels.push_back(pp);
         }
         D->ssched.push_back(s);
     }
@@ -171,6 +428,11 @@ hipError_t spchol_solve_init() {
     set_solve_lds<float>(g_max_lds);
     (void)hipGetLastError();
     return hipSuccess;
+}
+
+hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
+    if (N->dtype == SC_F64) return dinv_impl<double>(P, N, st);
+    return dinv_impl<float>(P, N, st);
 }
 
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
