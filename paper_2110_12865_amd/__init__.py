@@ -70,6 +70,9 @@ class PlanStats(ctypes.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime with the same soname as the system
+    # one; load it first so that this library and torch share one runtime
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libspchol.so is not built (%s); run "
                           "`python paper_2110_12865_amd/build.py`" % LIB_PATH)

@@ -204,8 +204,10 @@ __global__ __launch_bounds__(256) void k_assemble(
     }
     __syncthreads();
     if (tj < w) {
+        // rows below the diagonal only: entries above the diagonal of a
+        // front's diagonal block are never read as factor values
         T *dst = L + d.loff + int64_t(tj) * c;
-        for (int i = tid; i < c; i += nt) dst[i] = i >= tj ? col[i] : T(0);
+        for (int i = tj + tid; i < c; i += nt) dst[i] = col[i];
     } else {
         T *dst = U + d.uoff + int64_t(tj - w) * m - w;
         for (int i = tj + tid; i < c; i += nt) dst[i] = col[i];
@@ -215,12 +217,12 @@ __global__ __launch_bounds__(256) void k_assemble(
 // Factor and invert the kb x kb diagonal block (kb <= 64) whose top-left
 // corner is (r0, r0) in a column-major L block, with one wave (lanes 0..63
 // of the calling workgroup; other lanes must not call).  Lane i keeps row i
-// in registers; the right-looking updates read the pivot column with
-// readlane, so the loops are fully unrolled.  The factor is written back
-// (zeros above the diagonal) and through LDS (Ls, 64 x 65 scalars) the
+// in registers (loops fully unrolled); each pivot column is broadcast
+// through LDS.  The factor is written back (zeros above the diagonal); the
 // inverse X = L^{-1} is formed column by column (lane c owns column c) and
-// stored row-major in PIg (PIg[i * 64 + c] = X[i][c]).  A pivot that fails
-// d > 0 is recorded (smallest 1-based step wins) and replaced by 1.
+// stored column-major in PIg (PIg[c * 64 + i] = X[i][c]).  Ls holds
+// 64 x 65 + 64 scalars.  A pivot that fails d > 0 is recorded (smallest
+// 1-based step wins) and replaced by 1.
 template <typename T>
 __device__ inline T lane_bcast(T v, int src);
 template <>
@@ -237,13 +239,24 @@ __device__ inline float lane_bcast<float>(float v, int src) {
 }
 
 template <typename T>
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
 __device__ void wave_diag_factor(T *Lb, int c, int r0, int kb, T *Ls, T *PIg, int col0,
                                  int32_t *info_b) {
     const int lane = threadIdx.x & 63;
+    constexpr int LD = kTile + 1;
+    T *cb = Ls + kTile * LD;  // broadcast buffer for the current column
     T a[kTile];
 #pragma unroll
     for (int t = 0; t < kTile; t++)
-        a[t] = (t < kb && lane < kb) ? Lb[int64_t(r0 + t) * c + r0 + lane] : T(0);
+        a[t] = (t < kb && lane < kb) ? Lb[int64_t(r0 + t) * c + r0 + lane] : (lane == t ? T(1) : T(0));
+    // Right-looking.  Entries above the diagonal (lane < t) are updated too
+    // and never read back into the lower triangle; they are dropped below.
 #pragma unroll
     for (int j = 0; j < kTile; j++) {
         if (j < kb) {
@@ -251,41 +264,38 @@ __device__ void wave_diag_factor(T *Lb, int c, int r0, int kb, T *Ls, T *PIg, in
             const bool bad = !(djj > T(0));
             if (bad) djj = T(1);
             const T ljj = dsqrt(djj);
-            if (lane == j) {
-                a[j] = ljj;
-                if (bad) atomicMin(info_b, col0 + j + 1);
-            } else if (lane > j) {
-                a[j] = a[j] / ljj;
-            }
+            const T rinv = T(1) / ljj;
+            if (lane == j && bad) atomicMin(info_b, col0 + j + 1);
+            a[j] = lane == j ? ljj : a[j] * rinv;
+            cb[lane] = a[j];
+            wave_sync<T>();
 #pragma unroll
-            for (int t = j + 1; t < kTile; t++) {
-                const T ltj = lane_bcast(a[j], t);
-                if (lane >= t) a[t] -= a[j] * ltj;
-            }
+            for (int t = j + 1; t < kTile; t++) a[t] -= a[j] * cb[t];
+            wave_sync<T>();
         }
     }
 #pragma unroll
     for (int t = 0; t < kTile; t++) {
         if (t < kb && lane < kb) Lb[int64_t(r0 + t) * c + r0 + lane] = lane >= t ? a[t] : T(0);
-        Ls[lane * (kTile + 1) + t] = lane >= t ? a[t] : T(0);
+        Ls[lane * LD + t] = lane >= t ? a[t] : T(0);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync<T>();
+    // X = L^{-1}: lane c owns column c; rows of L are LDS broadcasts.
     T x[kTile];
 #pragma unroll
     for (int i = 0; i < kTile; i++) {
-        if (i < kb) {
-            T sum = lane == i ? T(1) : T(0);
+        T sum = lane == i ? T(1) : T(0);
 #pragma unroll
-            for (int t = 0; t < i; t++) sum -= Ls[i * (kTile + 1) + t] * x[t];
-            x[i] = sum / Ls[i * (kTile + 1) + i];
-        } else {
-            x[i] = T(0);
-        }
+        for (int t = 0; t < i; t++) sum -= Ls[i * LD + t] * x[t];
+        x[i] = sum * (T(1) / Ls[i * LD + i]);
     }
+    wave_sync<T>();
+    // column-major inverse through an LDS transpose: PIg[col * 64 + i] = X[i][col]
 #pragma unroll
-    for (int i = 0; i < kTile; i++) PIg[i * kTile + lane] = (lane < kb) ? x[i] : T(0);
+    for (int i = 0; i < kTile; i++) Ls[lane * LD + i] = (lane < kb && i < kb) ? x[i] : T(0);
+    wave_sync<T>();
+#pragma unroll 8
+    for (int col = 0; col < kTile; col++) PIg[col * kTile + lane] = Ls[col * LD + lane];
 }
 
 // C[j][i] += sum_t sA[t][j] * sB[t][i] for the wave's 32 x 32 quadrant of a
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(64) void k_potrf(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
     T *__restrict__ L, int64_t Lsize, T *__restrict__ PI, int64_t pistride,
     int32_t *__restrict__ info) {
-    __shared__ T Ls[kTile * (kTile + 1)];
+    __shared__ T Ls[kTile * (kTile + 1) + kTile];
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
     const SnDesc d = sn[s];
@@ -370,10 +380,19 @@ __global__ __launch_bounds__(256) void k_trsm(
     const T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.y) * kTile * kTile;
     const int tid = threadIdx.x;
     const int kbr = (kb + 3) & ~3;
-    for (int e = tid; e < kbr * kTile; e += 256) {
-        const int t = e / kTile, i = e - t * kTile;
-        sX[e] = (t < kb && r0 + i < c) ? Lb[int64_t(k + t) * c + r0 + i] : T(0);
-        sP[e] = (t < kb && i < kb) ? PIg[i * kTile + t] : T(0);
+    const int li = tid & 63, lt = tid >> 6;
+    const bool rowok = r0 + li < c;
+    T rX[16], rP[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const int t = lt + 4 * q;
+        rX[q] = (t < kb && rowok) ? Lb[int64_t(k + t) * c + r0 + li] : T(0);
+        rP[q] = PIg[t * kTile + li];  // zero-padded, column-major inverse
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        sX[(lt + 4 * q) * kTile + li] = rX[q];
+        sP[(lt + 4 * q) * kTile + li] = rP[q];
     }
     __syncthreads();
     typename Mma<T>::acc_t acc[2][2];
@@ -451,20 +470,35 @@ __global__ __launch_bounds__(256) void k_syrk(
     T *Lb = L + int64_t(b) * Lsize + d.loff;
     T *Ub = U + int64_t(b) * Usize + d.uoff;
     const int tid = threadIdx.x;
+    const int li = tid & 63, lt = tid >> 6;
+    const bool rowok = row0 + li < c, colok = col0 + li < R.cend;
+    // panel chunk kc: thread (li, lt) holds rows row0 + li / col0 + li of
+    // panel columns k0 + kc + lt + 4q, q < 16, in registers
+    T rI[16], rJ[16];
+    auto load_chunk = [&](int kc) {
+        const int kb = min(kTile, R.kw - kc);
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int t = lt + 4 * q;
+            const T *pc = Lb + int64_t(R.k0 + kc + t) * c;
+            rI[q] = (t < kb && rowok) ? pc[row0 + li] : T(0);
+            rJ[q] = (t < kb && colok) ? pc[col0 + li] : T(0);
+        }
+    };
     typename Mma<T>::acc_t acc[2][2];
     acc_zero<T>(acc);
+    load_chunk(0);
     for (int kc = 0; kc < R.kw; kc += kTile) {
         const int kb = min(kTile, R.kw - kc);
         const int kbr = (kb + 3) & ~3;
-        if (kc > 0) __syncthreads();
-        for (int e = tid; e < kbr * kTile; e += 256) {
-            const int t = e / kTile, i = e - t * kTile;
-            const bool tk = t < kb;
-            const T *pc = Lb + int64_t(R.k0 + kc + t) * c;
-            sI[e] = (tk && row0 + i < c) ? pc[row0 + i] : T(0);
-            sJ[e] = (tk && col0 + i < R.cend) ? pc[col0 + i] : T(0);
+        if (kc > 0) __syncthreads();  // the previous chunk's products are done
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            sI[(lt + 4 * q) * kTile + li] = rI[q];
+            sJ[(lt + 4 * q) * kTile + li] = rJ[q];
         }
         __syncthreads();
+        if (kc + kTile < R.kw) load_chunk(kc + kTile);  // in flight during the MFMAs
         tile_mma(sJ, sI, kbr, acc);
     }
 #pragma unroll

@@ -228,6 +228,7 @@ __global__ __launch_bounds__(256) void k_bwd_panel(
     const int32_t *__restrict__ active) {
     __shared__ double red[4][kP];
     __shared__ double rhs[kP];
+    __shared__ double Dt[kP * (kP + 1)];
     __shared__ int last;
     const int s = list[blockIdx.y];
     const int br = blockIdx.z;
@@ -269,16 +270,31 @@ __global__ __launch_bounds__(256) void k_bwd_panel(
     __syncthreads();
     if (!last) return;
     __threadfence();
+    {
+        // the inverse block, coalesced into LDS: Dt[t][i] = Dp[t * 64 + i]
+        const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+#pragma unroll
+        for (int q = 0; q < kP * kP / 256; q++) {
+            const int e = q * 256 + tid;
+            Dt[(e >> 6) * (kP + 1) + (e & 63)] = Dp[e];
+        }
+    }
     if (tid < kb) {
-        double sum = 0.0;
-        for (int q = 0; q < nch; q++) sum += part[q * kP + tid];
-        rhs[tid] = y[d.first + c0 + tid] - sum;
+        double s0 = 0.0, s1 = 0.0;
+        int q = 0;
+        for (; q + 1 < nch; q += 2) {
+            s0 += part[q * kP + tid];
+            s1 += part[(q + 1) * kP + tid];
+        }
+        if (q < nch) s0 += part[q * kP + tid];
+        rhs[tid] = y[d.first + c0 + tid] - (s0 + s1);
     }
     __syncthreads();
     if (tid < kb) {
-        const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+        // x_t = sum_i (L_pp^{-1})[i][t] rhs_i; column t of the inverse is Dt[t][.]
         double xt = 0.0;
-        for (int i = 0; i < kb; i++) xt += Dp[tid * kP + i] * rhs[i];
+#pragma unroll 16
+        for (int i = 0; i < kP; i++) xt += Dt[tid * (kP + 1) + i] * (i < kb ? rhs[i] : 0.0);
         y[d.first + c0 + tid] = xt;
         X[int64_t(br) * ldb + perm[d.first + c0 + tid]] = xt;
     }
