@@ -16,6 +16,9 @@ Workloads (--workload):
   grid3d64              3D 7-point 64^3 (n = 262144), nested dissection,
                         one value set, one right-hand side, FP64
   grid2d32              2D 5-point 32 x 32, natural order, FP64
+  uneven8               uneven batch: 2D 16^2, 32^2, 64^2, 128^2 and 3D 8^3,
+                        12^3, 16^3, 24^3, 32 value sets each (256 systems),
+                        one group plan; FP32 + refinement versus FP64
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 
@@ -50,6 +53,8 @@ def make_workload(name):
         return W.config(1), "grid3d_7pt_64^3_nd", "f64"
     if name == "grid2d32":
         return W.config(0), "grid2d_5pt_32x32_natural", "f64"
+    if name == "uneven8":
+        return W.config(3), "uneven_8_patterns_x32_grid2d_grid3d_nd", "mixed"
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -142,6 +147,31 @@ def cpu_baseline(w, flops_full, nnzL_full, budget_flops=2.0e10):
     }
 
 
+def cpu_baseline_group(ws, budget_s=8.0):
+    """The CPU oracle on whole value sets of every pattern of a group (one
+    set of all patterns after another, until the time budget is spent)."""
+    import oracle
+    syms = [oracle.symbolic(w.pattern.n, w.pattern.colptr, w.pattern.rowind, w.perm)
+            for w in ws]
+    t0 = time.perf_counter()
+    sets = 0
+    while sets < ws[0].batch:
+        for w, sym in zip(ws, syms):
+            p = w.pattern
+            Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[sets], sym)
+            oracle.solve(sym, Lx, w.b[sets])
+        sets += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    flops = sum(s.flops() for s in syms) * sets
+    return {"value": sets * len(ws) / dt, "unit": "factor+solve/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d value set(s) of each of the %d patterns, factor + solve, FP64 "
+                      "direct; %.2f s measured" % (sets, len(ws), dt),
+            "oracle_gflops": flops / dt / 1e9}
+
+
 def kernel_table(prof, steps):
     kern = {}
     total_bytes = 0.0
@@ -186,7 +216,7 @@ def run_form(S, plan, w, dtype, refine, steps, warmup, profile):
         nonlocal stats
         num.factor(vals)
         if refine:
-            rc, stats = num.refine_solve(vals, b0, x, tol=TOL, maxit=30)
+            rc, stats = num.refine_solve(vals, b0, x, tol=TOL, maxit=30, method="pcg")
         else:
             b.copy_(b0)
             num.solve(b)
@@ -229,23 +259,43 @@ def main():
 
     import paper_2110_12865_amd as S
 
+    import workloads as W
     w, wname, form = make_workload(args.workload)
+    members = None
+    if isinstance(w, list):
+        # uneven batch: one group plan over all patterns
+        members = w
+        vals, b = W.group_arrays(members)
+        w = W.Workload(wname, None, None, vals, b, members[0].seed)
+        nnz = sum(m.pattern.nnz for m in members)
+        n = sum(m.pattern.n for m in members)
+    else:
+        n, nnz = w.pattern.n, w.pattern.nnz
     p = w.pattern
-    log("workload %s n=%d nnzA=%d batch=%d nrhs=%d" % (wname, p.n, p.nnz, w.batch, w.nrhs))
+    log("workload %s n=%d nnzA=%d batch=%d nrhs=%d" % (wname, n, nnz, w.batch, w.nrhs))
     t = time.perf_counter()
-    plan = S.analyze(p.colptr, p.rowind, w.perm)
+    if members is not None:
+        plan = S.analyze_group([(m.pattern.colptr, m.pattern.rowind, m.perm) for m in members])
+    else:
+        plan = S.analyze(p.colptr, p.rowind, w.perm)
     info = plan.info()
+    nblk = info["nblocks"]
     log("analyze %.2f s: nnzL=%d supernodes=%d levels=%d flops=%.3e" % (
         time.perf_counter() - t, info["nnzL"], info["nsuper"], info["nlevels"], info["flops"]))
     prof_on = not args.no_profile
     out = {"metric": METRIC, "unit": "factor+solve/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic"}
-    cfg = {"workload": wname, "n": p.n, "nnzA": p.nnz, "nnzL": info["nnzL"],
+    cfg = {"workload": wname, "n": n, "nnzA": nnz, "nnzL": info["nnzL"],
            "batch": w.batch, "nrhs": w.nrhs,
-           "ordering": "geometric nested dissection" if w.perm is not None else "natural",
+           "ordering": ("geometric nested dissection"
+                        if members is not None or w.perm is not None else "natural"),
            "flops_sum_c2_per_system": info["flops"], "supernodes": info["nsuper"],
            "levels": info["nlevels"]}
+    if members is not None:
+        cfg["patterns"] = [m.name for m in members]
+        cfg["matrices_per_step"] = w.batch * nblk
+        cfg["flops_sum_c2_per_system"] = info["flops"] / nblk
     if form == "mixed":
         # FP64 form first (reference of the comparison), then the headline form
         t64, st64, x64, prof64 = run_form(S, plan, w, "f64", True, args.steps, args.warmup,
@@ -255,11 +305,12 @@ def main():
                                         prof_on)
         log("fp32+refinement form: %.3f ms/step" % (t32 * 1e3 / args.steps))
         ms = t32 * 1e3 / args.steps
-        out.update({"value": w.batch / (t32 / args.steps), "ms_per_step": ms,
+        nmat = w.batch * nblk
+        out.update({"value": nmat / (t32 / args.steps), "ms_per_step": ms,
                     "dtype": "f32 factor, f64 residual/update"})
         iters = [s["iters"] for s in st32]
         clauses = [s["clause"] for s in st32]
-        out["fp64_form"] = {"value": w.batch / (t64 / args.steps),
+        out["fp64_form"] = {"value": nmat / (t64 / args.steps),
                             "ms_per_step": t64 * 1e3 / args.steps,
                             "iters_max": max(s["iters"] for s in st64),
                             "relres_max": max(s["relres"] for s in st64),
@@ -272,9 +323,16 @@ def main():
                              "fwd_err_vs_fp64_form_max": float(max(
                                  np.abs(x32[s] - x64[s]).max() / np.abs(x64[s]).max()
                                  for s in range(w.batch)))}
-        # independent residual check on two systems
-        rr = max(relres_host(p, w.values[s], x32[s, r], w.b[s, r])
-                 for s in (0, w.batch - 1) for r in range(w.nrhs))
+        # independent residual check on the first and last value sets
+        if members is None:
+            rr = max(relres_host(p, w.values[s], x32[s, r], w.b[s, r])
+                     for s in (0, w.batch - 1) for r in range(w.nrhs))
+        else:
+            col0, val0 = plan.export_blocks()
+            rr = max(relres_host(m.pattern, w.values[s, val0[k]:val0[k + 1]],
+                                 x32[s, r, col0[k]:col0[k + 1]], w.b[s, r, col0[k]:col0[k + 1]])
+                     for k, m in enumerate(members) for s in (0, w.batch - 1)
+                     for r in range(w.nrhs))
         out["relres_check_host"] = rr
         pdtype = "f32"
     else:
@@ -293,7 +351,10 @@ def main():
         out["roofline"] = roofline(prof, pdtype)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)...")
-        out["cpu_baseline"] = cpu_baseline(w, info["flops"], info["nnzL"])
+        if members is not None:
+            out["cpu_baseline"] = cpu_baseline_group(members)
+        else:
+            out["cpu_baseline"] = cpu_baseline(w, info["flops"], info["nnzL"])
     print(json.dumps(out), flush=True)
     return 0
 

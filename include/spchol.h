@@ -82,6 +82,8 @@ typedef struct {
     int64_t max_width;  /* widest supernode (columns)                     */
     double flops;       /* sum_j c_j^2 over the exact column counts c_j   */
     int64_t etree_height; /* height of the column elimination tree        */
+    int64_t nblocks;    /* independent diagonal blocks: the patterns of a
+                           group plan, 1 for a plan from sc_analyze        */
 } sc_plan_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -106,7 +108,36 @@ sc_status sc_analyze(int64_t n, const int64_t *colptr_host,
                      const int32_t *rowind_host, const int32_t *perm_host,
                      const sc_options *opt, sc_plan_t **plan_out);
 
+/*
+ * Group plan for an uneven batch: npat patterns (sizes n[k], lower CSC
+ * colptr_host[k], rowind_host[k], optional perm_host[k], each with the
+ * conventions above) analysed as the one block-diagonal matrix
+ * diag(A_0, ..., A_{npat-1}), so that every level of every pattern runs in
+ * the same launches (the paper's grouping of independent work, Sec. 4.3).
+ * Layout of the group: pattern k owns columns [col0_k, col0_k + n[k]) and
+ * values [val0_k, val0_k + nnz_k), concatenated in pattern order
+ * (sc_plan_export_blocks gives the offsets); a value set of the group is
+ * the concatenation of one value set of every pattern, a right-hand side
+ * the concatenation of one vector of every pattern.  sc_factor_info and
+ * sc_refine_solve report every pattern of every batch element on its own.
+ * perm_host may be NULL (all natural) or have NULL entries.
+ * Errors: as sc_analyze (checked per pattern), SC_EINVAL for npat < 1.
+ */
+sc_status sc_analyze_group(int32_t npat, const int64_t *n_host,
+                           const int64_t *const *colptr_host,
+                           const int32_t *const *rowind_host,
+                           const int32_t *const *perm_host, const sc_options *opt,
+                           sc_plan_t **plan_out);
+
 sc_status sc_plan_info(const sc_plan_t *plan, sc_plan_stats *out);
+
+/*
+ * Block offsets of a plan (host memory, nblocks + 1 entries each, either
+ * pointer may be NULL): col0_host[k] first column of block k (same in the
+ * original and permuted numbering), val0_host[k] first value index.
+ */
+sc_status sc_plan_export_blocks(const sc_plan_t *plan, int64_t *col0_host,
+                                int64_t *val0_host);
 
 /*
  * Exact symbolic result in the permuted numbering, for checking: perm[n],
@@ -156,10 +187,13 @@ sc_status sc_factor(const sc_plan_t *plan, sc_numeric_t *num,
                     const double *values_dev, int64_t ldv, void *stream);
 
 /*
- * Per-matrix breakdown flags: info_host[b] = 0 if factor b is complete,
- * else the smallest 1-based elimination step whose pivot failed d > 0
- * (the factor beyond that step is unspecified).  Synchronizes the stream.
- * Returns SC_ENOTSPD if any info_host[b] != 0.
+ * Per-matrix breakdown flags, info_host[b * nblocks + k] for block k of
+ * batch element b (nblocks = 1 unless the plan is a group plan): 0 if that
+ * factor is complete, else the smallest 1-based elimination step of the
+ * block (permuted numbering, counted from the block's first column) whose
+ * pivot failed d > 0; the factor of that block beyond that step is
+ * unspecified, the other blocks are unaffected.  Synchronizes the stream.
+ * Returns SC_ENOTSPD if any entry != 0.
  */
 sc_status sc_factor_info(const sc_numeric_t *num, int32_t *info_host,
                          void *stream);
@@ -173,7 +207,8 @@ sc_status sc_factor_info(const sc_numeric_t *num, int32_t *info_host,
 sc_status sc_solve(const sc_plan_t *plan, sc_numeric_t *num, double *b_dev,
                    int32_t nrhs, int64_t ldb, void *stream);
 
-/* Outcome of sc_refine_solve for one (matrix, right-hand side). */
+/* Outcome of sc_refine_solve for one system: one (matrix, right-hand side,
+   block) with block = the pattern of a group plan. */
 typedef struct {
     int32_t iters;   /* corrections applied                               */
     int32_t clause;  /* 1: relres <= tol; 2: ||r||_2 <= 2 u ||A||_inf
@@ -185,17 +220,28 @@ typedef struct {
     double xnorm;    /* ||x||_2                                           */
 } sc_refine_stats;
 
+/* Refinement methods of sc_refine_solve. */
+enum { SC_REFINE_CLASSICAL = 0, SC_REFINE_PCG = 1 };
+
 /*
  * Solve A x = b by iterative refinement with the factor in `num` (FP32 or
- * FP64): x = solve(b); then while some system fails the stop rule and
- * fewer than maxit corrections were applied: r = b - A x in FP64 (A from
- * values_dev, the same values that were factored), d = solve(r) (FP64
- * arithmetic on the stored factor), x += d.  Stop rule per system:
+ * FP64) as the approximate inverse M^{-1}.  Both methods start from
+ * x = solve(b) and run every vector operation in FP64 (A from values_dev,
+ * the same values that were factored; solves use FP64 arithmetic on the
+ * stored factor).
+ *   SC_REFINE_CLASSICAL: while some system fails the stop rule and fewer
+ *     than maxit corrections were applied: r = b - A x, x += solve(r).
+ *   SC_REFINE_PCG: conjugate gradients on A preconditioned by the factor,
+ *     at most maxit steps; the stop rule is tested on the true residual
+ *     b - A x after each step.  Converges when the factor's precision is
+ *     too low for classical refinement (kappa(A) u_factor > 1).
+ * Stop rule per system (matrix b, right-hand side r, block k; norms over
+ * the block's rows, ||A||_inf of the block):
  * ||r||_2 <= tol ||b||_2, or ||r||_2 <= 2 u ||A||_inf ||x||_2 (the residual
- * has reached what FP64 can resolve).  A matrix stops taking corrections
- * once all its right-hand sides pass.
+ * has reached what FP64 can resolve).  A system that passes takes no
+ * further corrections and keeps its record.
  * b_dev: float64 [batch][nrhs][ldb] (unchanged); x_dev: same shape, output.
- * stats_host (nullable): [batch * nrhs] outcomes.  Synchronizes the stream
+ * stats_host (nullable): [batch][nrhs][nblocks] outcomes.  Synchronizes the stream
  * once per refinement step.  Returns SC_ENOCONV if some system did not meet
  * the rule (x then holds the last iterate).  Errors: SC_EINVAL, SC_ENOMEM,
  * SC_EDEVICE.
@@ -203,7 +249,7 @@ typedef struct {
 sc_status sc_refine_solve(const sc_plan_t *plan, sc_numeric_t *num,
                           const double *values_dev, int64_t ldv,
                           const double *b_dev, double *x_dev, int32_t nrhs,
-                          int64_t ldb, double tol, int32_t maxit,
+                          int64_t ldb, double tol, int32_t maxit, int32_t method,
                           sc_refine_stats *stats_host, void *stream);
 
 /*

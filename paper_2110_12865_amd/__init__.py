@@ -9,6 +9,9 @@ names follow the C ABI in include/spchol.h:
     num.factor(values)                          # values: cuda f64 [batch, nnzA]
     num.solve(b)                                # b: cuda f64 [batch, nrhs, n], in place
 
+    group = analyze_group([(colptr, rowind, perm), ...])   # uneven batch:
+    # one block-diagonal plan over several patterns (see sc_analyze_group)
+
 Importing this package fails loudly if the library has not been built
 (``python paper_2110_12865_amd/build.py``); there is no CPU fallback.
 """
@@ -26,13 +29,15 @@ LIB_PATH = os.path.join(_HERE, "libspchol.so")
 SC_OK, SC_EINVAL, SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD, SC_ENOCONV = \
     0, -1, -2, -3, -4, -5, -6
 SC_F64, SC_F32 = 0, 1
+SC_REFINE_CLASSICAL, SC_REFINE_PCG = 0, 1
+_METHODS = {"classical": SC_REFINE_CLASSICAL, "pcg": SC_REFINE_PCG}
 _DTYPES = {"f64": SC_F64, "f32": SC_F32}
 
 # names exported by the library, in the order of the header
 EXPORTS = [
-    "sc_status_string", "sc_options_default", "sc_analyze", "sc_plan_info",
-    "sc_plan_export_symbolic", "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create",
-    "sc_numeric_destroy", "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
+    "sc_status_string", "sc_options_default", "sc_analyze", "sc_analyze_group",
+    "sc_plan_info", "sc_plan_export_blocks", "sc_plan_export_symbolic",
+    "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create", "sc_numeric_destroy", "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
     "sc_numeric_get_columns", "sc_numeric_profile", "sc_numeric_profile_read",
 ]
 
@@ -66,7 +71,8 @@ class PlanStats(ctypes.Structure):
                 ("nsuper", ctypes.c_int64), ("nlevels", ctypes.c_int64),
                 ("L_store", ctypes.c_int64), ("U_store", ctypes.c_int64),
                 ("max_front", ctypes.c_int64), ("max_width", ctypes.c_int64),
-                ("flops", ctypes.c_double), ("etree_height", ctypes.c_int64)]
+                ("flops", ctypes.c_double), ("etree_height", ctypes.c_int64),
+                ("nblocks", ctypes.c_int64)]
 
 
 def _load():
@@ -82,7 +88,9 @@ def _load():
         "sc_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "sc_options_default": ([P], ctypes.c_int),
         "sc_analyze": ([I64, P, P, P, P, P], ctypes.c_int),
+        "sc_analyze_group": ([I32, P, P, P, P, P, P], ctypes.c_int),
         "sc_plan_info": ([P, P], ctypes.c_int),
+        "sc_plan_export_blocks": ([P, P, P], ctypes.c_int),
         "sc_plan_export_symbolic": ([P, P, P, P, P], ctypes.c_int),
         "sc_plan_export_supernodes": ([P, P, P, P, P, P], ctypes.c_int),
         "sc_plan_destroy": ([P], None),
@@ -91,7 +99,7 @@ def _load():
         "sc_factor": ([P, P, P, I64, P], ctypes.c_int),
         "sc_factor_info": ([P, P, P], ctypes.c_int),
         "sc_solve": ([P, P, P, I32, I64, P], ctypes.c_int),
-        "sc_refine_solve": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, P, P],
+        "sc_refine_solve": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, I32, P, P],
                             ctypes.c_int),
         "sc_numeric_get_columns": ([P, P, I32, I64, P, P], ctypes.c_int),
         "sc_numeric_profile": ([P, I32], ctypes.c_int),
@@ -158,10 +166,11 @@ class Plan:
                                None if options is None else ctypes.byref(options),
                                ctypes.byref(h)), "sc_analyze")
         self._h = h
+        self.nblocks = 1
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:  # (the module may be torn down first at exit)
             _lib.sc_plan_destroy(h)
             self._h = None
 
@@ -196,13 +205,54 @@ class Plan:
                "sc_plan_export_supernodes")
         return first, parent, level, rowptr, rows
 
+    def export_blocks(self):
+        """(col0, val0): column and value offsets of the blocks, nblocks + 1 each."""
+        col0 = np.empty(self.nblocks + 1, np.int64)
+        val0 = np.empty(self.nblocks + 1, np.int64)
+        _check(_lib.sc_plan_export_blocks(self._h, _ptr(col0), _ptr(val0)),
+               "sc_plan_export_blocks")
+        return col0, val0
+
     def numeric(self, batch: int = 1, dtype: str = "f64") -> "Numeric":
         return Numeric(self, batch, dtype)
+
+
+class GroupPlan(Plan):
+    """One plan over several patterns, the block-diagonal matrix of all of
+    them (see sc_analyze_group).  Values and vectors of the group are the
+    concatenations of the patterns' values and vectors (export_blocks gives
+    the offsets)."""
+
+    def __init__(self, patterns, options: Optional[Options] = None):
+        npat = len(patterns)
+        if npat < 1:
+            raise ValueError("no patterns")
+        cps = [np.ascontiguousarray(p[0], dtype=np.int64) for p in patterns]
+        ris = [np.ascontiguousarray(p[1], dtype=np.int32) for p in patterns]
+        pms = [None if len(p) < 3 or p[2] is None else np.ascontiguousarray(p[2], dtype=np.int32)
+               for p in patterns]
+        ns = np.array([len(c) - 1 for c in cps], np.int64)
+        VP = ctypes.c_void_p * npat
+        cpa = VP(*[c.ctypes.data for c in cps])
+        ria = VP(*[r.ctypes.data for r in ris])
+        pma = VP(*[0 if q is None else q.ctypes.data for q in pms])
+        h = ctypes.c_void_p()
+        _check(_lib.sc_analyze_group(npat, _ptr(ns), cpa, ria, pma,
+                                     None if options is None else ctypes.byref(options),
+                                     ctypes.byref(h)), "sc_analyze_group")
+        self._h = h
+        self.n = int(ns.sum())
+        self.nblocks = npat
 
 
 def analyze(colptr, rowind, perm=None, n=None, **opts) -> Plan:
     n = len(colptr) - 1 if n is None else n
     return Plan(n, colptr, rowind, perm, default_options(**opts) if opts else None)
+
+
+def analyze_group(patterns, **opts) -> GroupPlan:
+    """patterns: sequence of (colptr, rowind) or (colptr, rowind, perm)."""
+    return GroupPlan(patterns, default_options(**opts) if opts else None)
 
 
 class Numeric:
@@ -219,7 +269,7 @@ class Numeric:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.sc_numeric_destroy(h)
             self._h = None
 
@@ -233,11 +283,14 @@ class Numeric:
                               int(values.shape[1]), _stream_handle(stream)), "sc_factor")
 
     def info(self, stream=None) -> np.ndarray:
-        out = np.empty(self.batch, np.int32)
+        """Breakdown steps: [batch] for a plan of one pattern, [batch, nblocks]
+        for a group plan (0 = factor complete)."""
+        nb = self.plan.nblocks
+        out = np.empty(self.batch * nb, np.int32)
         st = _lib.sc_factor_info(self._h, _ptr(out), _stream_handle(stream))
         if st not in (SC_OK, SC_ENOTSPD):
             raise SpcholError(st, "sc_factor_info")
-        return out
+        return out if nb == 1 else out.reshape(self.batch, nb)
 
     def solve(self, b, stream=None):
         """b: device float64 tensor [batch, nrhs, n]; overwritten by x."""
@@ -247,19 +300,21 @@ class Numeric:
                              int(b.shape[2]), _stream_handle(stream)), "sc_solve")
         return b
 
-    def refine_solve(self, values, b, x, tol: float = 1e-10, maxit: int = 10, stream=None):
+    def refine_solve(self, values, b, x, tol: float = 1e-10, maxit: int = 10,
+                     method: str = "classical", stream=None):
         """x <- refined solution of A x = b (see sc_refine_solve).  values:
         the factored float64 values [batch, nnzA]; b, x: float64
         [batch, nrhs, n] device tensors.  Returns (status, stats) where stats
-        is a list of dicts per (matrix, rhs)."""
+        is a list of dicts per system, ordered (matrix, rhs, block)."""
         if b.shape != x.shape or b.dim() != 3 or b.shape[0] != self.batch:
             raise ValueError("b and x must be [batch, nrhs, n]")
-        nsys = self.batch * int(b.shape[1])
+        nsys = self.batch * int(b.shape[1]) * self.plan.nblocks
         st = (RefineStats * nsys)()
         rc = _lib.sc_refine_solve(self.plan._h, self._h, _dev_ptr(values, "float64"),
                                   int(values.shape[1]), _dev_ptr(b, "float64"),
                                   _dev_ptr(x, "float64"), int(b.shape[1]), int(b.shape[2]),
-                                  float(tol), int(maxit), st, _stream_handle(stream))
+                                  float(tol), int(maxit), _METHODS[method], st,
+                                  _stream_handle(stream))
         if rc not in (SC_OK, SC_ENOCONV):
             raise SpcholError(rc, "sc_refine_solve")
         return rc, [{k: getattr(st[i], k) for k, _ in RefineStats._fields_}

@@ -42,8 +42,10 @@ bool accept_merge(const sc_options &o, int64_t W, int64_t Z, int64_t E) {
 
 sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                             const int32_t *rowind, const int32_t *perm_in,
-                            const sc_options &opt, sc_plan **out) {
-    if (!colptr || !rowind || !out || n < 1) return SC_EINVAL;
+                            const sc_options &opt, int32_t nblk, const int64_t *blk_col0,
+                            const int64_t *blk_val0, sc_plan **out) {
+    if (!colptr || !rowind || !out || n < 1 || nblk < 1) return SC_EINVAL;
+    if (nblk > 1 && (!blk_col0 || !blk_val0)) return SC_EINVAL;
     if (n > INT32_MAX - 1) return SC_EINVAL;
     // ---- validation of the lower-CSC pattern -----------------------------
     if (colptr[0] != 0) return SC_EPATTERN;
@@ -63,11 +65,42 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         P->n = n;
         P->nnzA = nnzA;
         P->opt = opt;
+        P->nblk = nblk;
+        if (nblk == 1) {
+            P->blk_col0 = {0, n};
+            P->blk_val0 = {0, nnzA};
+        } else {
+            P->blk_col0.assign(blk_col0, blk_col0 + nblk + 1);
+            P->blk_val0.assign(blk_val0, blk_val0 + nblk + 1);
+        }
+        if (P->blk_col0[0] != 0 || P->blk_col0[nblk] != n || P->blk_val0[0] != 0 ||
+            P->blk_val0[nblk] != nnzA) {
+            delete P;
+            return SC_EINVAL;
+        }
+        P->colblk.assign(n, 0);
+        for (int32_t k = 0; k < nblk; k++) {
+            if (P->blk_col0[k + 1] <= P->blk_col0[k] ||
+                colptr[P->blk_col0[k]] != P->blk_val0[k]) {
+                delete P;
+                return SC_EINVAL;
+            }
+            for (int64_t j = P->blk_col0[k]; j < P->blk_col0[k + 1]; j++) P->colblk[j] = k;
+        }
+        for (int64_t c = 0; c < n; c++)
+            for (int64_t p = colptr[c]; p < colptr[c + 1]; p++)
+                if (P->colblk[rowind[p]] != P->colblk[c]) {
+                    delete P;
+                    return SC_EPATTERN;
+                }
         P->perm.resize(n);
         P->pinv.assign(n, -1);
         for (int64_t k = 0; k < n; k++) {
             int32_t o = perm_in ? perm_in[k] : int32_t(k);
-            if (o < 0 || o >= n || P->pinv[o] != -1) { delete P; return SC_EPATTERN; }
+            if (o < 0 || o >= n || P->pinv[o] != -1 || P->colblk[o] != P->colblk[k]) {
+                delete P;
+                return SC_EPATTERN;
+            }
             P->perm[k] = o;
             P->pinv[o] = int32_t(k);
         }
@@ -272,6 +305,9 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             if (q != rowptr[s + 1]) throw std::bad_alloc();
             int32_t pc = parent[d.first + d.w - 1];
             d.parent = pc < 0 ? -1 : P->col2sn[pc];
+            // no entry joins two blocks, so a supernode never spans two
+            d.blk = P->colblk[d.first];
+            d.bcol0 = int32_t(P->blk_col0[d.blk]);
         }
         // children (ascending), levels
         std::vector<int32_t> chp(ns + 1, 0);
@@ -412,6 +448,28 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             P->max_lvl_big = std::max(P->max_lvl_big, P->lvl_big_ptr[l + 1] - P->lvl_big_ptr[l]);
             P->lvl_ptr[l + 1] = int32_t(P->lvl_sn.size());
         }
+        // assembly tables of the large fronts
+        P->lvl_colent_off.assign(nlev, 0);
+        P->big_chmap_off.assign(P->lvl_big.size(), 0);
+        for (int32_t l = 0; l < nlev; l++) {
+            P->lvl_colent_off[l] = int64_t(P->big_colent.size());
+            for (int32_t e = P->lvl_big_ptr[l]; e < P->lvl_big_ptr[l + 1]; e++) {
+                const SnDesc &d = P->sn[P->lvl_big[e]];
+                for (int32_t t = 0; t < d.c; t++) P->big_colent.push_back(e - P->lvl_big_ptr[l]);
+                const int32_t nch = d.chend - d.chbeg;
+                P->big_chmap_off[e] = int64_t(P->big_chmap.size());
+                const size_t base = P->big_chmap.size();
+                P->big_chmap.resize(base + size_t(d.c) * nch, -1);
+                for (int32_t q = 0; q < nch; q++) {
+                    const SnDesc &cd = P->sn[P->chlist[d.chbeg + q]];
+                    for (int32_t jc = 0; jc < cd.m; jc++) {
+                        const int32_t tj = P->relmap[cd.relptr + jc];
+                        P->big_chmap[base + size_t(tj) * nch + q] = jc;
+                    }
+                }
+            }
+        }
+
         // solve schedule and per-supernode solve workspaces
         P->slv_small_ptr.assign(nlev + 1, 0);
         P->slv_pan_ptr.assign(nlev + 1, 0);

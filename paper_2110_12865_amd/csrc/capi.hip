@@ -39,7 +39,8 @@ void free_devplan(DevPlan *D) {
     void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
                     D->avidx, D->perm, D->lvl_small, D->lvl_big, D->lvl_sn,
                     D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
-                    D->slv_small, D->slv_pan};
+                    D->slv_small, D->slv_pan, D->big_colent, D->big_chmap_off,
+                    D->big_chmap, D->colblk, D->blk_col0};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete D;
@@ -71,11 +72,16 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->lvl_big, P->lvl_big);
     if (e == hipSuccess) e = upload(&D->lvl_sn, P->lvl_sn);
     if (e == hipSuccess) e = upload(&D->big_colstart, P->big_colstart);
+    if (e == hipSuccess) e = upload(&D->big_colent, P->big_colent);
+    if (e == hipSuccess) e = upload(&D->big_chmap_off, P->big_chmap_off);
+    if (e == hipSuccess) e = upload(&D->big_chmap, P->big_chmap);
     if (e == hipSuccess) e = upload(&D->slv_small, P->slv_small);
     if (e == hipSuccess) e = upload(&D->slv_pan, P->slv_pan);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
     if (e == hipSuccess) e = upload(&D->csr_col, P->csr_col);
     if (e == hipSuccess) e = upload(&D->csr_vidx, P->csr_vidx);
+    if (e == hipSuccess) e = upload(&D->colblk, P->colblk);
+    if (e == hipSuccess) e = upload(&D->blk_col0, P->blk_col0);
     if (e != hipSuccess) {
         free_devplan(D);
         return e == hipErrorOutOfMemory ? SC_ENOMEM : SC_EDEVICE;
@@ -121,21 +127,29 @@ hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
 }
 
 void free_refine_ws(RefineWs &W) {
-    void *ptrs[] = {W.r, W.anorm, W.stat, W.conv, W.active, W.count};
+    void *ptrs[] = {W.r, W.sc, W.part, W.anorm, W.stat, W.conv, W.active, W.count};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     W = RefineWs{};
 }
 
+// Refinement workspaces: vectors per (matrix, right-hand side), scalars
+// per system (matrix, right-hand side, block).
 hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
     RefineWs &W = N->rws;
     const int32_t nsys = N->batch * nrhs;
+    const size_t nseg = size_t(nsys) * N->plan->nblk;
     if (W.r && W.nsys >= nsys && W.ldb >= ldb) return hipSuccess;
     free_refine_ws(W);
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&W.r), sizeof(double) * nsys * ldb);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.anorm), sizeof(double) * N->batch);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.stat), sizeof(double) * 6 * nsys);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.conv), sizeof(int32_t) * nsys);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&W.r), 5 * sizeof(double) * nsys * ldb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.sc), 3 * sizeof(double) * nseg);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&W.part), 32 * 3 * sizeof(double) * nseg);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&W.anorm),
+                      sizeof(double) * N->batch * N->plan->nblk);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.stat), sizeof(double) * 6 * nseg);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.conv), sizeof(int32_t) * nseg);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.active), sizeof(int32_t) * N->batch);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.count), sizeof(int32_t));
     if (e != hipSuccess) {
@@ -181,7 +195,66 @@ sc_status sc_analyze(int64_t n, const int64_t *colptr_host, const int32_t *rowin
     sc_options_default(&o);
     if (opt) o = *opt;
     if (o.relax_cols < 0 || o.small_front < 0 || !(o.relax_zeros >= 0.0)) return SC_EINVAL;
-    return spchol_build_plan(n, colptr_host, rowind_host, perm_host, o, plan_out);
+    return spchol_build_plan(n, colptr_host, rowind_host, perm_host, o, 1, nullptr, nullptr,
+                             plan_out);
+}
+
+sc_status sc_analyze_group(int32_t npat, const int64_t *n_host, const int64_t *const *colptr_host,
+                           const int32_t *const *rowind_host, const int32_t *const *perm_host,
+                           const sc_options *opt, sc_plan_t **plan_out) {
+    if (!plan_out) return SC_EINVAL;
+    *plan_out = nullptr;
+    if (npat < 1 || !n_host || !colptr_host || !rowind_host) return SC_EINVAL;
+    sc_options o;
+    sc_options_default(&o);
+    if (opt) o = *opt;
+    if (o.relax_cols < 0 || o.small_front < 0 || !(o.relax_zeros >= 0.0)) return SC_EINVAL;
+    std::vector<int64_t> col0(npat + 1, 0), val0(npat + 1, 0);
+    for (int32_t k = 0; k < npat; k++) {
+        const int64_t nk = n_host[k];
+        if (nk < 1 || !colptr_host[k] || !rowind_host[k]) return SC_EINVAL;
+        if (nk > INT32_MAX - 1 - col0[k]) return SC_EINVAL;
+        const int64_t *cp = colptr_host[k];
+        if (cp[0] != 0) return SC_EPATTERN;
+        for (int64_t j = 0; j < nk; j++)
+            if (cp[j + 1] < cp[j]) return SC_EPATTERN;
+        // rows of pattern k must stay inside it once shifted into the group
+        for (int64_t q = 0; q < cp[nk]; q++)
+            if (rowind_host[k][q] < 0 || rowind_host[k][q] >= nk) return SC_EPATTERN;
+        if (perm_host && perm_host[k])
+            for (int64_t j = 0; j < nk; j++)
+                if (perm_host[k][j] < 0 || perm_host[k][j] >= nk) return SC_EPATTERN;
+        col0[k + 1] = col0[k] + nk;
+        val0[k + 1] = val0[k] + cp[nk];
+    }
+    const int64_t n = col0[npat];
+    std::vector<int64_t> colptr;
+    std::vector<int32_t> rowind, perm;
+    try {
+        colptr.resize(n + 1);
+        rowind.resize(val0[npat]);
+        perm.resize(n);
+    } catch (const std::bad_alloc &) {
+        return SC_ENOMEM;
+    }
+    for (int32_t k = 0; k < npat; k++) {
+        const int64_t nk = n_host[k], c0 = col0[k], v0 = val0[k];
+        for (int64_t j = 0; j < nk; j++) colptr[c0 + j] = v0 + colptr_host[k][j];
+        for (int64_t q = 0; q < val0[k + 1] - v0; q++)
+            rowind[v0 + q] = int32_t(c0 + rowind_host[k][q]);
+        for (int64_t j = 0; j < nk; j++)
+            perm[c0 + j] = int32_t(c0 + (perm_host && perm_host[k] ? perm_host[k][j] : j));
+    }
+    colptr[n] = val0[npat];
+    return spchol_build_plan(n, colptr.data(), rowind.data(), perm.data(), o, npat, col0.data(),
+                             val0.data(), plan_out);
+}
+
+sc_status sc_plan_export_blocks(const sc_plan_t *P, int64_t *col0_host, int64_t *val0_host) {
+    if (!P) return SC_EINVAL;
+    if (col0_host) std::memcpy(col0_host, P->blk_col0.data(), sizeof(int64_t) * (P->nblk + 1));
+    if (val0_host) std::memcpy(val0_host, P->blk_val0.data(), sizeof(int64_t) * (P->nblk + 1));
+    return SC_OK;
 }
 
 sc_status sc_plan_info(const sc_plan_t *P, sc_plan_stats *out) {
@@ -198,6 +271,7 @@ sc_status sc_plan_info(const sc_plan_t *P, sc_plan_stats *out) {
     out->max_width = P->max_width;
     out->flops = P->flops;
     out->etree_height = P->etree_height;
+    out->nblocks = P->nblk;
     return SC_OK;
 }
 
@@ -264,14 +338,15 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
     const size_t sz = dtype == SC_F64 ? 8 : 4;
     hipError_t e = hipMalloc(&N->L, std::max<size_t>(size_t(batch) * P->Lsize * sz, 8));
     if (e == hipSuccess) e = hipMalloc(&N->U, std::max<size_t>(size_t(batch) * P->Usize * sz, 8));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&N->info), sizeof(int32_t) * batch);
+    const size_t ninfo = size_t(batch) * P->nblk;
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&N->info), sizeof(int32_t) * ninfo);
     if (e == hipSuccess)
         e = hipMalloc(&N->pinv,
                       std::max<size_t>(size_t(batch) * P->max_lvl_big * kTile * kTile * sz, 8));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&N->dinv),
                       std::max<size_t>(size_t(batch) * P->dinv_size * sizeof(double), 8));
-    if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * batch);
+    if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * ninfo);
     if (e != hipSuccess) {
         sc_numeric_destroy(N);
         return map_err(e);
@@ -304,14 +379,15 @@ sc_status sc_factor(const sc_plan_t *P, sc_numeric_t *N, const double *values_de
 sc_status sc_factor_info(const sc_numeric_t *N, int32_t *info_host, void *stream) {
     if (!N || !info_host) return SC_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(info_host, N->info, sizeof(int32_t) * N->batch,
+    const int64_t ninfo = int64_t(N->batch) * N->plan->nblk;
+    hipError_t e = hipMemcpyAsync(info_host, N->info, sizeof(int32_t) * ninfo,
                                   hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return map_err(e);
     bool bad = false;
-    for (int32_t b = 0; b < N->batch; b++) {
-        if (info_host[b] == INT_MAX) info_host[b] = 0;
-        if (info_host[b] != 0) bad = true;
+    for (int64_t q = 0; q < ninfo; q++) {
+        if (info_host[q] == INT_MAX) info_host[q] = 0;
+        if (info_host[q] != 0) bad = true;
     }
     return bad ? SC_ENOTSPD : SC_OK;
 }
@@ -330,10 +406,11 @@ sc_status sc_solve(const sc_plan_t *P, sc_numeric_t *N, double *b_dev, int32_t n
 
 sc_status sc_refine_solve(const sc_plan_t *P, sc_numeric_t *N, const double *values_dev,
                           int64_t ldv, const double *b_dev, double *x_dev, int32_t nrhs,
-                          int64_t ldb, double tol, int32_t maxit, sc_refine_stats *stats_host,
-                          void *stream) {
+                          int64_t ldb, double tol, int32_t maxit, int32_t method,
+                          sc_refine_stats *stats_host, void *stream) {
     if (!P || !N || N->plan != P || !values_dev || !b_dev || !x_dev || nrhs < 1 ||
-        ldb < P->n || ldv < P->nnzA || maxit < 0 || !(tol >= 0.0))
+        ldb < P->n || ldv < P->nnzA || maxit < 0 || !(tol >= 0.0) ||
+        (method != SC_REFINE_CLASSICAL && method != SC_REFINE_PCG))
         return SC_EINVAL;
     if (b_dev == x_dev) return SC_EINVAL;
     int dev = 0;
@@ -342,10 +419,10 @@ sc_status sc_refine_solve(const sc_plan_t *P, sc_numeric_t *N, const double *val
     hipError_t e = ensure_solve_ws(P, N, nrhs);
     if (e == hipSuccess) e = ensure_refine_ws(N, nrhs, ldb);
     if (e != hipSuccess) return map_err(e);
-    const int32_t nsys = N->batch * nrhs;
+    const int32_t nsys = N->batch * nrhs * P->nblk;
     std::vector<double> stat(size_t(6) * nsys);
     int32_t nact = 0;
-    e = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, maxit,
+    e = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, maxit, method,
                           stat.data(), &nact, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return map_err(e);
     bool fail = false;

@@ -63,11 +63,16 @@ struct DevPlan {
     int32_t *lvl_big = nullptr;
     int32_t *lvl_sn = nullptr;
     int64_t *big_colstart = nullptr;  // per big entry: first column index in its level
+    int32_t *big_colent = nullptr;    // per level column: entry in the level's big list
+    int64_t *big_chmap_off = nullptr; // per big entry: offset into big_chmap
+    int32_t *big_chmap = nullptr;     // (front, column, child) -> child column or -1
     int32_t *slv_small = nullptr;     // solve schedule lists
     int32_t *slv_pan = nullptr;
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int32_t *csr_col = nullptr;
     int64_t *csr_vidx = nullptr;
+    int32_t *colblk = nullptr;        // block of every column
+    int64_t *blk_col0 = nullptr;      // nblk + 1 block column offsets
     std::vector<FLaunch> fsched;
     std::vector<SLaunch> ssched;
 };
@@ -115,7 +120,9 @@ struct Profiler {
 struct RefineWs {
     int32_t nsys = 0;
     int64_t ldb = 0;
-    double *r = nullptr;        // residual / correction, nsys * ldb
+    double *r = nullptr;        // 5 vectors of nsys * ldb (residual, correction, CG)
+    double *sc = nullptr;       // per-system scalars, 3 * nsys
+    double *part = nullptr;     // reduction partials, nsys * 32 * 3
     double *anorm = nullptr;    // batch
     double *stat = nullptr;     // nsys * 6
     int32_t *conv = nullptr;    // nsys
@@ -153,8 +160,8 @@ hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b,
 hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
                              int64_t ldv, const double *b, double *x, int32_t nrhs,
-                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
-                             int32_t *nactive_out, hipStream_t st);
+                             int64_t ldb, double tol, int32_t maxit, int32_t method,
+                             double *stat_host, int32_t *nactive_out, hipStream_t st);
 hipError_t spchol_kernels_init();
 
 // Largest dynamic LDS allocation per workgroup on the current device.

@@ -21,6 +21,7 @@
 // matrix cores (MFMA 16x16x4, FP64 or FP32).
 #include <algorithm>
 #include <climits>
+#include <cmath>
 
 #include "device.hpp"
 
@@ -63,154 +64,148 @@ __device__ inline T *front_col(T *Lb, T *Ub, int c, int w, int m, int j) {
     return j < w ? Lb + int64_t(j) * c : Ub + int64_t(j - w) * m - w;
 }
 
-// Right-looking Cholesky of the first w columns of a c x c front held in
-// LDS (column-major, leading dimension ld), including the Schur update of
-// the trailing block.  A pivot that fails d > 0 is recorded (1-based step,
-// smallest wins) and replaced by 1 so no NaN spreads.
-template <typename T>
-__device__ void lds_partial_chol(T *F, int ld, int c, int w, int col0,
-                                 int32_t *info_b) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int j = 0; j < w; j++) {
-        T djj = F[j * ld + j];
-        __syncthreads();
-        const bool bad = !(djj > T(0));
-        if (bad) djj = T(1);
-        const T ljj = dsqrt(djj);
-        if (tid == 0) {
-            F[j * ld + j] = ljj;
-            if (bad) atomicMin(info_b, col0 + j + 1);
-        }
-        for (int i = j + 1 + tid; i < c; i += nt) F[j * ld + i] /= ljj;
-        __syncthreads();
-        const int r = c - j - 1;
-        const T *cj = F + j * ld + j + 1;
-        for (int e = tid; e < r * r; e += nt) {
-            const int tt = e / r, ii = e - tt * r;
-            if (ii >= tt) F[(j + 1 + tt) * ld + j + 1 + ii] -= cj[ii] * cj[tt];
-        }
-        __syncthreads();
-    }
-}
-
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
-// ---------------------------------------------------------------------------
-// small fronts: the whole front in LDS, one workgroup per supernode
-// ---------------------------------------------------------------------------
+__device__ inline void wave_fence_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Small fronts, one wave per (front, matrix): the whole front sits in LDS
+// (c_max x c_max scalars per wave, `per` fronts per workgroup); the wave
+// scatters A's columns, adds the children's update blocks, factors the first
+// w columns right-looking and writes L's block and the update block back.
 template <typename T>
-__global__ __launch_bounds__(256) void k_front_small(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
+__global__ __launch_bounds__(256) void k_front_wave(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int per,
+    int cmax, const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
     const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
-    const int64_t *__restrict__ avidx, const double *__restrict__ vals,
-    int64_t ldv, T *__restrict__ L, int64_t Lsize, T *__restrict__ U,
-    int64_t Usize, int32_t *__restrict__ info) {
+    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
+    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
+    int32_t *__restrict__ info, int nblk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *F = reinterpret_cast<T *>(smem_raw);
-    const int s = list[blockIdx.x];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv >= per) return;
+    const int e = blockIdx.x * per + wv;
+    if (e >= nlist) return;
+    T *F = reinterpret_cast<T *>(smem_raw) + size_t(wv) * cmax * cmax;
+    const int s = list[e];
     const int b = blockIdx.y;
     const SnDesc d = sn[s];
     const int c = d.c, w = d.w, m = d.m;
-    const int tid = threadIdx.x, nt = blockDim.x;
     L += int64_t(b) * Lsize;
     U += int64_t(b) * Usize;
     vals += int64_t(b) * ldv;
-
-    for (int e = tid; e < c * c; e += nt) F[e] = T(0);
-    __syncthreads();
+    for (int q = lane; q < c * c; q += 64) F[q] = T(0);
+    wave_fence_sync();
     const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
-    for (int64_t e = a0 + tid; e < a1; e += nt) F[aoff[e]] = T(vals[avidx[e]]);
+    for (int64_t q = a0 + lane; q < a1; q += 64) F[aoff[q]] = T(vals[avidx[q]]);
     for (int q = d.chbeg; q < d.chend; q++) {
         const SnDesc cd = sn[chlist[q]];
         const int32_t *rm = relmap + cd.relptr;
         const T *Uc = U + cd.uoff;
-        const int mc = cd.m;
-        __syncthreads();
-        for (int e = tid; e < mc * mc; e += nt) {
-            const int j = e / mc, i = e - j * mc;
-            if (i >= j) F[rm[j] * c + rm[i]] += Uc[e];
+        const int mc = cd.m;  // at most c
+        wave_fence_sync();
+        if (mc <= 64) {  // lane i holds the map of child row i
+            const int rmi = lane < mc ? rm[lane] : 0;
+#pragma unroll 4
+            for (int jc = 0; jc < mc; jc++) {
+                const int tcol = __builtin_amdgcn_readlane(rmi, jc) * c;
+                if (lane >= jc && lane < mc) F[tcol + rmi] += Uc[int64_t(jc) * mc + lane];
+            }
+        } else {
+            for (int jc = 0; jc < mc; jc++) {
+                const int tcol = rm[jc] * c;
+                for (int i = jc + lane; i < mc; i += 64) F[tcol + rm[i]] += Uc[int64_t(jc) * mc + i];
+            }
         }
     }
-    __syncthreads();
-    lds_partial_chol(F, c, c, w, d.first, info + b);
+    wave_fence_sync();
+    for (int j = 0; j < w; j++) {
+        T djj = F[j * c + j];
+        const bool bad = !(djj > T(0));
+        if (bad) djj = T(1);
+        const T ljj = dsqrt(djj);
+        wave_fence_sync();
+        if (lane == 0) {
+            F[j * c + j] = ljj;
+            if (bad) atomicMin(info + int64_t(b) * nblk + d.blk, d.first - d.bcol0 + j + 1);
+        }
+        for (int i = j + 1 + lane; i < c; i += 64) F[j * c + i] /= ljj;
+        wave_fence_sync();
+        const T *cj = F + j * c;
+        for (int t = j + 1; t < c; t++) {
+            const T ltj = cj[t];
+            for (int i = t + lane; i < c; i += 64) F[t * c + i] -= cj[i] * ltj;
+        }
+        wave_fence_sync();
+    }
     T *Ls = L + d.loff;
-    for (int e = tid; e < c * w; e += nt) {
-        const int j = e / c, i = e - j * c;
-        Ls[e] = i >= j ? F[e] : T(0);
-    }
+    for (int j = 0; j < w; j++)
+        for (int i = j + lane; i < c; i += 64) Ls[int64_t(j) * c + i] = F[j * c + i];
     T *Us = U + d.uoff;
-    for (int e = tid; e < m * m; e += nt) {
-        const int j = e / m, i = e - j * m;
-        if (i >= j) Us[e] = F[(w + j) * c + w + i];
-    }
+    for (int j = 0; j < m; j++)
+        for (int i = j + lane; i < m; i += 64) Us[int64_t(j) * m + i] = F[(w + j) * c + w + i];
 }
 
-// ---------------------------------------------------------------------------
-// large fronts: assembly, one workgroup per target column
-// ---------------------------------------------------------------------------
+// Large fronts: assembly with one wave per target column, `per` columns per
+// workgroup (c_max scalars of LDS per wave).
 template <typename T>
-__global__ __launch_bounds__(256) void k_assemble(
+__global__ __launch_bounds__(256) void k_assemble_wave(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int64_t *__restrict__ colstart, int nlist,
+    const int64_t *__restrict__ colstart, const int32_t *__restrict__ colent,
+    const int64_t *__restrict__ chmap_off, const int32_t *__restrict__ chmap,
+    int64_t ncols, int per, int cmax,
     const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
     const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
-    const int64_t *__restrict__ avidx, const double *__restrict__ vals,
-    int64_t ldv, T *__restrict__ L, int64_t Lsize, T *__restrict__ U,
-    int64_t Usize) {
+    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
+    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *col = reinterpret_cast<T *>(smem_raw);
-    const int64_t g = blockIdx.x;
-    int lo = 0, hi = nlist - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (colstart[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    const int s = list[lo];
-    const int tj = int(g - colstart[lo]);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv >= per) return;
+    const int64_t g = int64_t(blockIdx.x) * per + wv;
+    if (g >= ncols) return;
+    T *col = reinterpret_cast<T *>(smem_raw) + size_t(wv) * cmax;
+    const int ent = colent[g];
+    const int s = list[ent];
+    const int tj = int(g - colstart[ent]);
     const int b = blockIdx.y;
     const SnDesc d = sn[s];
     const int c = d.c, w = d.w, m = d.m;
-    const int tid = threadIdx.x, nt = blockDim.x;
     L += int64_t(b) * Lsize;
     U += int64_t(b) * Usize;
     vals += int64_t(b) * ldv;
-
-    for (int i = tid; i < c; i += nt) col[i] = T(0);
-    __syncthreads();
+    for (int i = tj + lane; i < c; i += 64) col[i] = T(0);
+    wave_fence_sync();
     if (tj < w) {
         const int j = d.first + tj;
         const int64_t base = int64_t(tj) * c;
-        for (int64_t e = acolptr[j] + tid; e < acolptr[j + 1]; e += nt)
-            col[aoff[e] - base] = T(vals[avidx[e]]);
+        for (int64_t q = acolptr[j] + lane; q < acolptr[j + 1]; q += 64)
+            col[aoff[q] - base] = T(vals[avidx[q]]);
     }
-    for (int q = d.chbeg; q < d.chend; q++) {
-        const SnDesc cd = sn[chlist[q]];
+    const int nch = d.chend - d.chbeg;
+    const int32_t *cm = chmap + chmap_off[ent] + int64_t(tj) * nch;
+    for (int q = 0; q < nch; q++) {
+        const int jc = cm[q];  // the child's column that lands in column tj
+        if (jc < 0) continue;
+        const SnDesc cd = sn[chlist[d.chbeg + q]];
         const int32_t *rm = relmap + cd.relptr;
         const int mc = cd.m;
-        int l2 = 0, h2 = mc;  // first child row mapped at or below tj
-        while (l2 < h2) {
-            const int mid = (l2 + h2) >> 1;
-            if (rm[mid] < tj) l2 = mid + 1; else h2 = mid;
-        }
-        __syncthreads();
-        if (l2 < mc && rm[l2] == tj) {
-            const T *uc = U + cd.uoff + int64_t(l2) * mc;
-            for (int i = l2 + tid; i < mc; i += nt) col[rm[i]] += uc[i];
-        }
+        wave_fence_sync();
+        const T *uc = U + cd.uoff + int64_t(jc) * mc;
+        for (int i = jc + lane; i < mc; i += 64) col[rm[i]] += uc[i];
     }
-    __syncthreads();
+    wave_fence_sync();
     if (tj < w) {
-        // rows below the diagonal only: entries above the diagonal of a
-        // front's diagonal block are never read as factor values
         T *dst = L + d.loff + int64_t(tj) * c;
-        for (int i = tj + tid; i < c; i += nt) dst[i] = col[i];
+        for (int i = tj + lane; i < c; i += 64) dst[i] = col[i];
     } else {
         T *dst = U + d.uoff + int64_t(tj - w) * m - w;
-        for (int i = tj + tid; i < c; i += nt) dst[i] = col[i];
+        for (int i = tj + lane; i < c; i += 64) dst[i] = col[i];
     }
 }
 
@@ -347,7 +342,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_potrf(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
     T *__restrict__ L, int64_t Lsize, T *__restrict__ PI, int64_t pistride,
-    int32_t *__restrict__ info) {
+    int32_t *__restrict__ info, int nblk) {
     __shared__ T Ls[kTile * (kTile + 1) + kTile];
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
@@ -356,7 +351,8 @@ __global__ __launch_bounds__(64) void k_potrf(
     const int kb = min(kTile, d.w - k);
     T *Lb = L + int64_t(b) * Lsize + d.loff;
     T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.x) * kTile * kTile;
-    wave_diag_factor(Lb, d.c, k, kb, Ls, PIg, d.first + k, info + b);
+    wave_diag_factor(Lb, d.c, k, kb, Ls, PIg, d.first - d.bcol0 + k,
+                     info + int64_t(b) * nblk + d.blk);
 }
 
 // Panel rows below the diagonal block: X <- X L_kk^{-T} = X (L_kk^{-1})^T,
@@ -519,13 +515,13 @@ __global__ __launch_bounds__(256) void k_syrk(
 
 template <typename T>
 void set_lds_limits(int big) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_front_small<T>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble<T>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_syrk<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trsm<T>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_front_wave<T>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_wave<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
@@ -633,9 +629,9 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
     const int64_t pistride = int64_t(P->max_lvl_big) * kTile * kTile;
     const int B = N->batch;
     {
-        const int64_t nb = (B + 255) / 256;
-        hipLaunchKernelGGL(k_fill_i32, dim3(unsigned(nb)), dim3(256), 0, st,
-                           N->info, int64_t(B), int32_t(INT_MAX));
+        const int64_t ninfo = int64_t(B) * P->nblk;
+        hipLaunchKernelGGL(k_fill_i32, dim3(unsigned((ninfo + 255) / 256)), dim3(256), 0, st,
+                           N->info, ninfo, int32_t(INT_MAX));
     }
     for (const FLaunch &f : D->fsched)
         if (size_t(f.lds) * sizeof(T) > size_t(g_max_lds)) return hipErrorInvalidValue;
@@ -645,23 +641,34 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         static const int kinds[] = {KK_SmallFront, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk};
         prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, st);
         switch (f.kind) {
-        case FLaunch::Small:
-            hipLaunchKernelGGL(k_front_small<T>, dim3(unsigned(f.gridx), B), dim3(256),
-                               size_t(f.lds) * sizeof(T), st, D->sn, D->lvl_small + f.list0,
-                               D->relmap, D->chlist, D->acolptr, D->aoff, D->avidx,
-                               vals, ldv, L, P->Lsize, U, P->Usize, N->info);
+        case FLaunch::Small: {
+            // one wave per front; as many fronts per workgroup as LDS allows
+            const size_t per_lds = size_t(f.lds) * sizeof(T);
+            const int per = int(std::max<size_t>(1, std::min<size_t>(4, g_max_lds / per_lds)));
+            const int cmax = int(std::lround(std::sqrt(double(f.lds))));
+            hipLaunchKernelGGL(k_front_wave<T>, dim3(unsigned((f.nlist + per - 1) / per), B),
+                               dim3(64 * per), per_lds * per, st, D->sn, D->lvl_small + f.list0,
+                               f.nlist, per, cmax, D->relmap, D->chlist, D->acolptr, D->aoff,
+                               D->avidx, vals, ldv, L, P->Lsize, U, P->Usize, N->info,
+                               P->nblk);
             break;
-        case FLaunch::Assemble:
-            hipLaunchKernelGGL(k_assemble<T>, dim3(unsigned(f.gridx), B), dim3(256),
-                               size_t(f.lds) * sizeof(T), st, D->sn, D->lvl_big + f.list0,
-                               D->big_colstart + f.list0, f.nlist, D->relmap, D->chlist,
-                               D->acolptr, D->aoff, D->avidx, vals, ldv, L, P->Lsize, U,
-                               P->Usize);
+        }
+        case FLaunch::Assemble: {
+            const size_t per_lds = size_t(f.lds) * sizeof(T);
+            const int per = int(std::max<size_t>(1, std::min<size_t>(4, g_max_lds / per_lds)));
+            hipLaunchKernelGGL(k_assemble_wave<T>,
+                               dim3(unsigned((f.gridx + per - 1) / per), B), dim3(64 * per),
+                               per_lds * per, st, D->sn, D->lvl_big + f.list0,
+                               D->big_colstart + f.list0, D->big_colent + P->lvl_colent_off[f.level],
+                               D->big_chmap_off + f.list0, D->big_chmap, int64_t(f.gridx), per,
+                               f.lds, D->relmap, D->chlist, D->acolptr, D->aoff, D->avidx,
+                               vals, ldv, L, P->Lsize, U, P->Usize);
             break;
+        }
         case FLaunch::Potrf:
             hipLaunchKernelGGL(k_potrf<T>, dim3(unsigned(f.gridx), B), dim3(64), 0, st,
                                D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize, PI, pistride,
-                               N->info);
+                               N->info, P->nblk);
             break;
         case FLaunch::Trsm:
             hipLaunchKernelGGL(k_trsm<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),

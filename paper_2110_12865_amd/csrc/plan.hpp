@@ -25,8 +25,10 @@ struct SnDesc {
     int64_t dinv;    // offset of the inverted 64x64 diagonal blocks (solve
                      // by panels), -1 when the supernode is solved in LDS
     int64_t part;    // offset of the backward-solve partial sums
+    int32_t blk;     // diagonal block (pattern of a group plan) it belongs to
+    int32_t bcol0;   // first column of that block
 };
-static_assert(sizeof(SnDesc) == 80, "SnDesc layout");
+static_assert(sizeof(SnDesc) == 88, "SnDesc layout");
 
 // A supernode is solved by 64-column panels across many workgroups when it
 // is wide or tall; otherwise one workgroup solves it out of LDS.
@@ -39,6 +41,13 @@ struct DevPlan;  // device copies, defined by the HIP side
 struct sc_plan {
     int64_t n = 0, nnzA = 0;
     sc_options opt{};
+
+    // independent diagonal blocks (the patterns of a group plan; one block
+    // otherwise): block k owns columns [blk_col0[k], blk_col0[k+1]) in both
+    // numberings and values [blk_val0[k], blk_val0[k+1])
+    int32_t nblk = 1;
+    std::vector<int64_t> blk_col0, blk_val0;  // nblk + 1
+    std::vector<int32_t> colblk;              // n: block of each column
 
     // permutation (perm[new] = old) and its inverse
     std::vector<int32_t> perm, pinv;
@@ -95,6 +104,13 @@ struct sc_plan {
     std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts
     std::vector<int64_t> big_colstart;    // per big entry: first column in its level
     int32_t max_lvl_big = 0;              // most large fronts in one level
+    // assembly tables of large fronts: for every target column of a level,
+    // its entry in the level's list; for every (front, target column,
+    // child), the child's column that lands there (-1 if none)
+    std::vector<int32_t> big_colent;      // sum over levels of the level's columns
+    std::vector<int64_t> lvl_colent_off;  // nlevels
+    std::vector<int64_t> big_chmap_off;   // per big entry
+    std::vector<int32_t> big_chmap;
 
     mutable DevPlan *dev = nullptr;
     mutable int dev_id = -1;
@@ -102,6 +118,10 @@ struct sc_plan {
 
 // Host symbolic pass (analyze.cpp).  Returns SC_OK or an error; on success
 // *out owns a fully built plan.
+// nblk > 1 declares the pattern block diagonal with the given column and
+// value offsets (nblk + 1 entries each); the permutation must keep every
+// block's columns inside the block.
 sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                             const int32_t *rowind, const int32_t *perm,
-                            const sc_options &opt, sc_plan **out);
+                            const sc_options &opt, int32_t nblk, const int64_t *blk_col0,
+                            const int64_t *blk_val0, sc_plan **out);

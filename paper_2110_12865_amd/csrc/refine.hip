@@ -7,11 +7,15 @@
 //                       or ||r||_2 <= 2 u ||A||_inf ||x||_2  (FP64 floor)
 //         d = solve(r);  x += d
 //
-// Every system (matrix of the batch, right-hand side) is tested on its own;
-// a matrix stops taking corrections once all its right-hand sides pass.
+// Every system (matrix of the batch, right-hand side, diagonal block) is
+// tested on its own and takes no corrections once it passes; the blocks are
+// the patterns of a group plan (one block otherwise), and a system's norms
+// run over its block's rows only.  Vector kernels index systems as
+// seg = (matrix * nrhs + rhs) * nblk + block.
 // The residual uses both triangles of A by rows (one lane per row, entries
 // in a fixed order) and all reductions use a fixed tree, so results are
 // bit-reproducible.
+#include <algorithm>
 #include <cfloat>
 
 #include "device.hpp"
@@ -36,15 +40,27 @@ __global__ __launch_bounds__(256) void k_resid(
     R[int64_t(br) * ldb + i] = B[int64_t(br) * ldb + i] - t;
 }
 
-// ||A||_inf of every matrix: max over rows of sum |A_ij|
-__global__ __launch_bounds__(256) void k_anorm(
+// Block of vector element i (colblk is null for a plan of one block).
+__device__ inline int seg_of(int br, int nblk, const int32_t *colblk, int64_t i) {
+    return br * nblk + (colblk ? colblk[i] : 0);
+}
+
+// ||A_k||_inf of every (matrix, block): max over the block's rows of
+// sum |A_ij|, in 32 slices (partial maxima in part[bk * 32 + slice]), then
+// the max of the slices (the maximum does not depend on the order).
+__global__ __launch_bounds__(256) void k_anorm_part(
     const int64_t *__restrict__ ptr, const int64_t *__restrict__ vidx,
-    const double *__restrict__ vals, int64_t ldv, int64_t n, double *__restrict__ anorm) {
+    const double *__restrict__ vals, int64_t ldv, const int64_t *__restrict__ col0, int nblk,
+    double *__restrict__ part) {
     __shared__ double red[256];
-    const int b = blockIdx.x;
+    const int bk = blockIdx.y, slice = blockIdx.x;
+    const int b = bk / nblk, k = bk - b * nblk;
+    const int64_t r0 = col0[k], nr = col0[k + 1] - r0;
+    const int64_t len = (nr + 31) / 32;
+    const int64_t i0 = r0 + slice * len, i1 = min(r0 + nr, i0 + len);
     const double *v = vals + int64_t(b) * ldv;
     double m = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         double s = 0.0;
         for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) s += fabs(v[vidx[e]]);
         m = fmax(m, s);
@@ -55,63 +71,124 @@ __global__ __launch_bounds__(256) void k_anorm(
         if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) anorm[b] = red[0];
+    if (threadIdx.x == 0) part[int64_t(bk) * 32 + slice] = red[0];
 }
 
-// Stop test for every system: sums of squares of r, b, x by a fixed tree,
-// then the two clauses.  stat layout per system: [iters, clause, relres,
-// rnorm, bnorm, xnorm].  conv[br] = 1 once the system passes.
-__global__ __launch_bounds__(256) void k_check(
-    const double *__restrict__ R, const double *__restrict__ B,
-    const double *__restrict__ X, int64_t ldb, int64_t n, int nrhs,
-    const double *__restrict__ anorm, double tol, int iter,
-    const int32_t *__restrict__ active, int32_t *__restrict__ conv,
-    double *__restrict__ stat) {
-    __shared__ double sr[256], sb[256], sx[256];
-    const int br = blockIdx.x;
-    const int b = br / nrhs;
-    if (active && !active[b]) return;
-    const double *r = R + int64_t(br) * ldb;
-    const double *bb = B + int64_t(br) * ldb;
-    const double *x = X + int64_t(br) * ldb;
-    double a = 0.0, c = 0.0, d = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        a += r[i] * r[i];
-        c += bb[i] * bb[i];
-        d += x[i] * x[i];
-    }
-    sr[threadIdx.x] = a;
-    sb[threadIdx.x] = c;
-    sx[threadIdx.x] = d;
+__global__ void k_anorm_final(const double *__restrict__ part, int nbk,
+                              double *__restrict__ anorm) {
+    const int bk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bk >= nbk) return;
+    double m = 0.0;
+    for (int q = 0; q < 32; q++) m = fmax(m, part[int64_t(bk) * 32 + q]);
+    anorm[bk] = m;
+}
+
+// Per-system reductions in two stages: kRB workgroups per system each sum
+// a contiguous slice of the system's rows (fixed tree), then the consumer
+// adds the kRB partials in slice order, so every result is bit-reproducible.
+constexpr int kRB = 32;
+
+__device__ inline double block_sum(double v, double *red) {
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            sr[threadIdx.x] += sr[threadIdx.x + w];
-            sb[threadIdx.x] += sb[threadIdx.x + w];
-            sx[threadIdx.x] += sx[threadIdx.x + w];
-        }
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double rn = sqrt(sr[0]), bn = sqrt(sb[0]), xn = sqrt(sx[0]);
-        const double relres = bn > 0.0 ? rn / bn : rn;
-        int clause = 0;
-        if (relres <= tol) clause = 1;
-        else if (rn <= 2.0 * DBL_EPSILON * 0.5 * anorm[b] * xn) clause = 2;
-        double *st = stat + int64_t(br) * 6;
-        st[0] = iter;
-        st[1] = clause;
-        st[2] = relres;
-        st[3] = rn;
-        st[4] = bn;
-        st[5] = xn;
-        conv[br] = clause != 0;
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// nq = 3: partial sums of r.r, b.b, x.x (A = r, B = b, C = x);
+// nq = 1: partial sum of A.B.  part[(seg * kRB + slice) * 3 + q].
+__global__ __launch_bounds__(256) void k_sums(
+    const double *__restrict__ A, const double *__restrict__ Bv, const double *__restrict__ C,
+    int nq, int64_t ldb, const int64_t *__restrict__ col0, int nblk, int nrhs,
+    const int32_t *__restrict__ active, const int32_t *__restrict__ skip,
+    double *__restrict__ part) {
+    __shared__ double red[256];
+    const int sg = blockIdx.y, slice = blockIdx.x;
+    const int br = sg / nblk, k = sg - br * nblk;
+    if (active && !active[br / nrhs]) return;
+    if (skip && skip[sg]) return;
+    const int64_t r0 = col0[k], nr = col0[k + 1] - r0;
+    const int64_t len = (nr + kRB - 1) / kRB;
+    const int64_t i0 = r0 + slice * len, i1 = min(r0 + nr, i0 + len);
+    const double *a = A + int64_t(br) * ldb;
+    const double *bb = Bv + int64_t(br) * ldb;
+    const double *cc = nq == 3 ? C + int64_t(br) * ldb : nullptr;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double ai = a[i], bi = bb[i];
+        if (nq == 3) {
+            const double ci = cc[i];
+            s0 += ai * ai;
+            s1 += bi * bi;
+            s2 += ci * ci;
+        } else {
+            s0 += ai * bi;
+        }
+    }
+    double *o = part + (int64_t(sg) * kRB + slice) * 3;
+    const double t0 = block_sum(s0, red);
+    if (nq == 3) {
+        const double t1 = block_sum(s1, red);
+        const double t2 = block_sum(s2, red);
+        if (threadIdx.x == 0) { o[0] = t0; o[1] = t1; o[2] = t2; }
+    } else if (threadIdx.x == 0) {
+        o[0] = t0;
     }
 }
 
-// active[b] = some right-hand side of matrix b has not passed;
+// out[seg] = sum of the kRB partial dot products of system seg
+__global__ void k_sums_final(const double *__restrict__ part, int nseg, int per_matrix,
+                             const int32_t *__restrict__ active, double *__restrict__ out) {
+    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sg >= nseg || !active[sg / per_matrix]) return;
+    double t = 0.0;
+    for (int q = 0; q < kRB; q++) t += part[(int64_t(sg) * kRB + q) * 3];
+    out[sg] = t;
+}
+
+// Stop test for every system from the partial sums of r.r, b.b and x.x.
+// stat layout per system: [iters, clause, relres, rnorm, bnorm, xnorm].
+// conv[seg] = 1 once the system passes; a system that passed earlier (and
+// is no longer updated) keeps its record.
+__global__ void k_check(const double *__restrict__ part, int nseg, int nrhs, int nblk,
+                        const double *__restrict__ anorm, double tol, int iter,
+                        const int32_t *__restrict__ active, int32_t *__restrict__ conv,
+                        double *__restrict__ stat) {
+    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sg >= nseg) return;
+    const int b = sg / (nrhs * nblk), k = sg % nblk;
+    if (!active[b] || conv[sg]) return;
+    double a = 0.0, c = 0.0, d = 0.0;
+    for (int q = 0; q < kRB; q++) {
+        const double *o = part + (int64_t(sg) * kRB + q) * 3;
+        a += o[0];
+        c += o[1];
+        d += o[2];
+    }
+    const double rn = sqrt(a), bn = sqrt(c), xn = sqrt(d);
+    const double relres = bn > 0.0 ? rn / bn : rn;
+    int clause = 0;
+    if (relres <= tol) clause = 1;
+    else if (rn <= 2.0 * DBL_EPSILON * 0.5 * anorm[b * nblk + k] * xn) clause = 2;
+    double *st = stat + int64_t(sg) * 6;
+    st[0] = iter;
+    st[1] = clause;
+    st[2] = relres;
+    st[3] = rn;
+    st[4] = bn;
+    st[5] = xn;
+    conv[sg] = clause != 0;
+}
+
+// active[b] = some system of matrix b has not passed;
 // count[0] = number of active matrices
-__global__ void k_active(const int32_t *__restrict__ conv, int batch, int nrhs,
+__global__ void k_active(const int32_t *__restrict__ conv, int batch, int per_matrix,
                          int32_t *__restrict__ active, int32_t *__restrict__ count) {
     __shared__ int32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
@@ -119,7 +196,7 @@ __global__ void k_active(const int32_t *__restrict__ conv, int batch, int nrhs,
     for (int b = threadIdx.x; b < batch; b += blockDim.x) {
         if (!active[b]) continue;
         int all = 1;
-        for (int r = 0; r < nrhs; r++) all &= conv[b * nrhs + r];
+        for (int q = 0; q < per_matrix; q++) all &= conv[b * per_matrix + q];
         active[b] = !all;
         if (!all) atomicAdd(&cnt, 1);
     }
@@ -127,12 +204,15 @@ __global__ void k_active(const int32_t *__restrict__ conv, int batch, int nrhs,
     if (threadIdx.x == 0) count[0] = cnt;
 }
 
+// x += d on the systems that have not passed
 __global__ void k_axpy(double *__restrict__ X, const double *__restrict__ D, int64_t ldb,
-                       int64_t n, int nrhs, const int32_t *__restrict__ active) {
+                       int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
+                       const int32_t *__restrict__ active, const int32_t *__restrict__ conv) {
     const int br = blockIdx.y;
-    if (active && !active[br / nrhs]) return;
+    if (!active[br / nrhs]) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) X[int64_t(br) * ldb + i] += D[int64_t(br) * ldb + i];
+    if (i >= n || conv[seg_of(br, nblk, colblk, i)]) return;
+    X[int64_t(br) * ldb + i] += D[int64_t(br) * ldb + i];
 }
 
 __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
@@ -140,18 +220,85 @@ __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Y = A X for every system of an active matrix
+__global__ __launch_bounds__(256) void k_spmv(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const int64_t *__restrict__ vidx, const double *__restrict__ vals, int64_t ldv,
+    const double *__restrict__ X, double *__restrict__ Y, int64_t ldb, int64_t n, int nrhs,
+    const int32_t *__restrict__ active) {
+    const int br = blockIdx.y;
+    const int b = br / nrhs;
+    if (!active[b]) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *v = vals + int64_t(b) * ldv;
+    const double *x = X + int64_t(br) * ldb;
+    double t = 0.0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) t += v[vidx[e]] * x[col[e]];
+    Y[int64_t(br) * ldb + i] = t;
+}
+
+__global__ void k_copy_sys(const double *__restrict__ X, double *__restrict__ Y, int64_t ldb,
+                           int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    const int br = blockIdx.y;
+    if (!active[br / nrhs]) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) Y[int64_t(br) * ldb + i] = X[int64_t(br) * ldb + i];
+}
+
+// CG step on systems that have not passed: alpha = rz / pq,
+// x += alpha p, r -= alpha q (a system with pq <= 0 is left unchanged)
+__global__ void k_cg_xr(double *__restrict__ X, double *__restrict__ R,
+                        const double *__restrict__ Pv, const double *__restrict__ Q, int64_t ldb,
+                        int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
+                        const int32_t *__restrict__ active, const int32_t *__restrict__ conv,
+                        const double *__restrict__ rz, const double *__restrict__ pq) {
+    const int br = blockIdx.y;
+    if (!active[br / nrhs]) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int sg = seg_of(br, nblk, colblk, i);
+    if (conv[sg]) return;
+    const double den = pq[sg];
+    if (!(den > 0.0)) return;
+    const double alpha = rz[sg] / den;
+    const int64_t o = int64_t(br) * ldb + i;
+    X[o] += alpha * Pv[o];
+    R[o] -= alpha * Q[o];
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ void k_cg_p(double *__restrict__ Pv, const double *__restrict__ Z, int64_t ldb,
+                       int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
+                       const int32_t *__restrict__ active, const int32_t *__restrict__ conv,
+                       const double *__restrict__ rz_old, const double *__restrict__ rz_new) {
+    const int br = blockIdx.y;
+    if (!active[br / nrhs]) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int sg = seg_of(br, nblk, colblk, i);
+    if (conv[sg]) return;
+    const double beta = rz_old[sg] > 0.0 ? rz_new[sg] / rz_old[sg] : 0.0;
+    const int64_t o = int64_t(br) * ldb + i;
+    Pv[o] = Z[o] + beta * Pv[o];
+}
+
 }  // namespace
 
-hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
-                             int64_t ldv, const double *b, double *x, int32_t nrhs,
-                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
-                             int32_t *nactive_out, hipStream_t st) {
+namespace {
+
+hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
+                            int64_t ldv, const double *b, double *x, int32_t nrhs,
+                            int64_t ldb, double tol, int32_t maxit, double *stat_host,
+                            int32_t *nactive_out, hipStream_t st) {
     DevPlan *D = P->dev;
     RefineWs &W = N->rws;
-    const int batch = N->batch;
-    const int nsys = batch * nrhs;
+    const int batch = N->batch, nblk = P->nblk;
+    const int nsys = batch * nrhs, nseg = nsys * nblk, per = nrhs * nblk;
     const int64_t n = P->n;
+    const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
     const dim3 vgrid(unsigned((n + 255) / 256), unsigned(nsys));
+    const dim3 sgrid(unsigned((nseg + 255) / 256));
     hipError_t e;
     // x0 = solve(b)
     e = hipMemcpy2DAsync(x, ldb * sizeof(double), b, ldb * sizeof(double), n * sizeof(double),
@@ -159,17 +306,22 @@ hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
                        int32_t(1));
+    hipLaunchKernelGGL(k_set_i32, sgrid, dim3(256), 0, st, W.conv, nseg, int32_t(0));
     e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_anorm, dim3(batch), dim3(256), 0, st, D->csr_ptr, D->csr_vidx, vals,
-                       ldv, n, W.anorm);
+    hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
+                       D->csr_vidx, vals, ldv, D->blk_col0, nblk, W.part);
+    hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
+                       W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     for (int it = 0;; it++) {
         hipLaunchKernelGGL(k_resid, vgrid, dim3(256), 0, st, D->csr_ptr, D->csr_col,
                            D->csr_vidx, vals, ldv, b, x, W.r, ldb, n, nrhs, W.active);
-        hipLaunchKernelGGL(k_check, dim3(nsys), dim3(256), 0, st, W.r, b, x, ldb, n, nrhs,
-                           W.anorm, tol, it, W.active, W.conv, W.stat);
-        hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, nrhs, W.active,
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, 3, ldb,
+                           D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
+        hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
+                           tol, it, W.active, W.conv, W.stat);
+        hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
         e = hipMemcpyAsync(&nact, W.count, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -177,11 +329,113 @@ hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals
         if (nact == 0 || it >= maxit) break;
         e = spchol_solve_run(P, N, W.r, nrhs, ldb, st, W.active);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_axpy, vgrid, dim3(256), 0, st, x, W.r, ldb, n, nrhs, W.active);
+        hipLaunchKernelGGL(k_axpy, vgrid, dim3(256), 0, st, x, W.r, ldb, n, nrhs, nblk, colblk,
+                           W.active, W.conv);
     }
     *nactive_out = nact;
-    e = hipMemcpyAsync(stat_host, W.stat, sizeof(double) * 6 * nsys, hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(stat_host, W.stat, sizeof(double) * 6 * nseg, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipGetLastError();
     return e;
+}
+
+// Preconditioned conjugate gradients on A (FP64 vectors and products) with
+// the stored factor as preconditioner; the stop rule is tested on the true
+// residual b - A x after every step.  Every system runs its own recurrence
+// (its own step lengths), so the blocks of a group plan stay independent.
+hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64_t ldv,
+                      const double *b, double *x, int32_t nrhs, int64_t ldb, double tol,
+                      int32_t maxit, double *stat_host, int32_t *nactive_out, hipStream_t st) {
+    DevPlan *D = P->dev;
+    RefineWs &W = N->rws;
+    const int batch = N->batch, nblk = P->nblk;
+    const int nsys = batch * nrhs, nseg = nsys * nblk, per = nrhs * nblk;
+    const int64_t n = P->n;
+    const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
+    const dim3 vgrid(unsigned((n + 255) / 256), unsigned(nsys));
+    const dim3 sgrid(unsigned((nseg + 255) / 256));
+    const size_t vsz = size_t(nsys) * ldb;
+    double *r = W.r, *z = W.r + vsz, *pv = W.r + 2 * vsz, *q = W.r + 3 * vsz, *rt = W.r + 4 * vsz;
+    double *rz0 = W.sc, *rz1 = W.sc + nseg, *pq = W.sc + 2 * nseg;
+    hipError_t e = hipMemcpy2DAsync(x, ldb * sizeof(double), b, ldb * sizeof(double),
+                                    n * sizeof(double), nsys, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
+                       int32_t(1));
+    hipLaunchKernelGGL(k_set_i32, sgrid, dim3(256), 0, st, W.conv, nseg, int32_t(0));
+    e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr);  // x0 = M^{-1} b
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
+                       D->csr_vidx, vals, ldv, D->blk_col0, nblk, W.part);
+    hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
+                       W.part, batch * nblk, W.anorm);
+    int32_t nact = batch;
+    auto check = [&](int it) -> hipError_t {
+        hipLaunchKernelGGL(k_resid, vgrid, dim3(256), 0, st, D->csr_ptr, D->csr_col,
+                           D->csr_vidx, vals, ldv, b, x, rt, ldb, n, nrhs, W.active);
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, rt, b, x, 3, ldb,
+                           D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
+        hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
+                           tol, it, W.active, W.conv, W.stat);
+        hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
+                           W.count);
+        hipError_t e2 = hipMemcpyAsync(&nact, W.count, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       st);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+        return e2;
+    };
+    // dot products <a, c> of every system into out[seg]
+    auto dots = [&](const double *a, const double *c, double *out) {
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, nullptr, 1, ldb,
+                           D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
+        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
+                           out);
+    };
+    e = check(0);
+    if (e != hipSuccess) return e;
+    if (nact > 0 && maxit > 0) {
+        hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, rt, r, ldb, n, nrhs, W.active);
+        hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, r, z, ldb, n, nrhs, W.active);
+        e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
+        if (e != hipSuccess) return e;
+        dots(r, z, rz0);
+        hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, z, pv, ldb, n, nrhs, W.active);
+        double *rz = rz0, *rzn = rz1;
+        for (int it = 1; it <= maxit; it++) {
+            hipLaunchKernelGGL(k_spmv, vgrid, dim3(256), 0, st, D->csr_ptr, D->csr_col,
+                               D->csr_vidx, vals, ldv, pv, q, ldb, n, nrhs, W.active);
+            dots(pv, q, pq);
+            hipLaunchKernelGGL(k_cg_xr, vgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
+                               nblk, colblk, W.active, W.conv, rz, pq);
+            e = check(it);
+            if (e != hipSuccess) return e;
+            if (nact == 0 || it == maxit) break;
+            hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, r, z, ldb, n, nrhs,
+                               W.active);
+            e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
+            if (e != hipSuccess) return e;
+            dots(r, z, rzn);
+            hipLaunchKernelGGL(k_cg_p, vgrid, dim3(256), 0, st, pv, z, ldb, n, nrhs, nblk,
+                               colblk, W.active, W.conv, rz, rzn);
+            std::swap(rz, rzn);
+        }
+    }
+    *nactive_out = nact;
+    e = hipMemcpyAsync(stat_host, W.stat, sizeof(double) * 6 * nseg, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    return e;
+}
+
+}  // namespace
+
+hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals, int64_t ldv,
+                             const double *b, double *x, int32_t nrhs, int64_t ldb, double tol,
+                             int32_t maxit, int32_t method, double *stat_host,
+                             int32_t *nactive_out, hipStream_t st) {
+    if (method == 1)
+        return refine_pcg(P, N, vals, ldv, b, x, nrhs, ldb, tol, maxit, stat_host, nactive_out,
+                          st);
+    return refine_classical(P, N, vals, ldv, b, x, nrhs, ldb, tol, maxit, stat_host,
+                            nactive_out, st);
 }

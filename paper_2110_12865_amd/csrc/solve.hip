@@ -67,17 +67,14 @@ __global__ __launch_bounds__(64) void k_dinv(
     for (int col = 0; col < kP; col++) D[col * kP + lane] = Lp[col * (kP + 1) + lane];
 }
 
-// Forward step of one level for supernodes solved in LDS (solve = 1), or
-// only the gather of the right-hand side and the children's update vectors
-// into FV_s for panel-solved supernodes (solve = 0).
-template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_small(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int solve,
+// Gather of the right-hand side and the children's update vectors into
+// FV_s for the panel-solved supernodes of a level (their triangular solve
+// runs in k_fwd_panel).  Item = (supernode, matrix and right-hand side).
+__global__ __launch_bounds__(256) void k_fwd_gather(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ relmap,
-    const int32_t *__restrict__ chlist, const T *__restrict__ L, int64_t Lsize,
-    const double *__restrict__ B, int64_t ldb, double *__restrict__ Y,
-    double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
-    const int32_t *__restrict__ active) {
+    const int32_t *__restrict__ chlist, const double *__restrict__ B, int64_t ldb,
+    double *__restrict__ FV, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *v = reinterpret_cast<double *>(smem_raw);
     const int s = list[blockIdx.x];
@@ -99,21 +96,196 @@ __global__ __launch_bounds__(256) void k_fwd_small(
         for (int i = tid; i < cd.m; i += nt) v[rm[i]] += uc[i];
     }
     __syncthreads();
-    if (solve) {
-        const T *Lb = L + int64_t(b) * Lsize + d.loff;
-        for (int j = 0; j < w; j++) {
-            const T *lj = Lb + int64_t(j) * c;
-            const double yj = v[j] / double(lj[j]);
-            __syncthreads();
-            for (int i = j + 1 + tid; i < c; i += nt) v[i] -= double(lj[i]) * yj;
-            if (tid == 0) v[j] = yj;
-            __syncthreads();
+    for (int i = tid; i < c; i += nt) fvb[d.rowptr + i] = v[i];
+}
+
+__device__ inline void wave_sync_solve() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double bcast_lane(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<unsigned int>(lo)));
+}
+
+constexpr int kWaveSlots = 8;  // rows per lane: c <= 512 for wave-solved supernodes
+
+// Forward step of one level for supernodes solved by one wave each (w <= 64,
+// c <= 512), NR right-hand sides of one matrix at a time: the right-hand
+// side and the children's update vectors are gathered in LDS, then lane i
+// keeps rows i + 64k in registers and the pivot value is broadcast with
+// readlane.  Item = (supernode, matrix); four waves per workgroup.
+template <typename T, int NR, int SL>
+__global__ __launch_bounds__(256) void k_fwd_wave(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
+    int r0, const int32_t *__restrict__ perm, const int32_t *__restrict__ relmap,
+    const int32_t *__restrict__ chlist, const T *__restrict__ L, int64_t Lsize,
+    const double *__restrict__ B, int64_t ldb, double *__restrict__ Y,
+    double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs, int cmax,
+    const int32_t *__restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + wv;
+    if (item >= nitems) return;
+    const int s = list[item % nlist];
+    const int b = item / nlist;
+    if (active && !active[b]) return;
+    double *v = reinterpret_cast<double *>(smem_raw) + size_t(wv) * NR * cmax;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w;
+    const int br0 = b * nrhs + r0;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const double *bb = B + int64_t(br0 + r) * ldb;
+        for (int i = lane; i < c; i += 64) v[r * cmax + i] = i < w ? bb[perm[d.first + i]] : 0.0;
+    }
+    for (int q = d.chbeg; q < d.chend; q++) {
+        const SnDesc cd = sn[chlist[q]];
+        const int32_t *rm = relmap + cd.relptr;
+        wave_sync_solve();
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const double *uc = FV + int64_t(br0 + r) * fvsize + cd.rowptr + cd.w;
+            for (int i = lane; i < cd.m; i += 64) v[r * cmax + rm[i]] += uc[i];
         }
-        double *y = Y + int64_t(br) * n;
-        for (int i = tid; i < w; i += nt) y[d.first + i] = v[i];
-        for (int i = w + tid; i < c; i += nt) fvb[d.rowptr + i] = v[i];
-    } else {
-        for (int i = tid; i < c; i += nt) fvb[d.rowptr + i] = v[i];
+    }
+    wave_sync_solve();
+    double x[SL][NR];
+#pragma unroll
+    for (int k = 0; k < SL; k++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const int i = lane + 64 * k;
+            x[k][r] = i < c ? v[r * cmax + i] : 0.0;
+        }
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        // eight columns of L in flight at once
+        T lc[8][SL];
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++)
+#pragma unroll
+            for (int k = 0; k < SL; k++) {
+                const int i = lane + 64 * k;
+                lc[jj][k] = (j0 + jj < w && i < c) ? Lb[int64_t(j0 + jj) * c + i] : T(0);
+            }
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) {
+            const int j = j0 + jj;
+            if (j < w) {
+                const double ljj = bcast_lane(double(lc[jj][0]), j);
+                double yj[NR];
+#pragma unroll
+                for (int r = 0; r < NR; r++) yj[r] = bcast_lane(x[0][r], j) / ljj;
+                if (lane == j) {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) x[0][r] = yj[r];
+                }
+#pragma unroll
+                for (int k = 0; k < SL; k++) {
+                    const int i = lane + 64 * k;
+                    if (i > j && i < c) {
+                        const double l = double(lc[jj][k]);
+#pragma unroll
+                        for (int r = 0; r < NR; r++) x[k][r] -= l * yj[r];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double *y = Y + int64_t(br0 + r) * n;
+        double *fv = FV + int64_t(br0 + r) * fvsize + d.rowptr;
+#pragma unroll
+        for (int k = 0; k < SL; k++) {
+            const int i = lane + 64 * k;
+            if (i < w) y[d.first + i] = x[k][r];
+            else if (i < c) fv[i] = x[k][r];
+        }
+    }
+}
+
+// Backward step of one level for wave-solved supernodes: lane i keeps rows
+// i + 64k of the solution; each column's dot product is a wave reduction
+// (fixed butterfly order) and the lane owning the pivot row applies it.
+template <typename T, int NR, int SL>
+__global__ __launch_bounds__(256) void k_bwd_wave(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
+    int r0, const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
+    const T *__restrict__ L, int64_t Lsize, double *__restrict__ X, int64_t ldb,
+    double *__restrict__ Y, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = blockIdx.x * 4 + wv;
+    if (item >= nitems) return;
+    const int s = list[item % nlist];
+    const int b = item / nlist;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w;
+    const int br0 = b * nrhs + r0;
+    const int32_t *R = rows + d.rowptr;
+    double x[SL][NR];
+#pragma unroll
+    for (int k = 0; k < SL; k++) {
+        const int i = lane + 64 * k;
+        const int64_t pos = i < w ? d.first + i : (i < c ? R[i] : 0);
+#pragma unroll
+        for (int r = 0; r < NR; r++) x[k][r] = i < c ? Y[int64_t(br0 + r) * n + pos] : 0.0;
+    }
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    for (int j1 = w - 1; j1 >= 0; j1 -= 8) {
+        // columns j1, j1-1, ..., j1-7 in flight at once
+        T lc[8][SL];
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++)
+#pragma unroll
+            for (int k = 0; k < SL; k++) {
+                const int i = lane + 64 * k;
+                lc[jj][k] = (j1 - jj >= 0 && i < c) ? Lb[int64_t(j1 - jj) * c + i] : T(0);
+            }
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) {
+            const int j = j1 - jj;
+            if (j >= 0) {
+                double t[NR];
+#pragma unroll
+                for (int r = 0; r < NR; r++) t[r] = 0.0;
+#pragma unroll
+                for (int k = 0; k < SL; k++) {
+                    const int i = lane + 64 * k;
+                    if (i > j && i < c) {
+                        const double l = double(lc[jj][k]);
+#pragma unroll
+                        for (int r = 0; r < NR; r++) t[r] += l * x[k][r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) t[r] += __shfl_xor(t[r], off);
+                }
+                if (lane == j) {
+                    const double ljj = double(lc[jj][0]);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) x[0][r] = (x[0][r] - t[r]) / ljj;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double *y = Y + int64_t(br0 + r) * n;
+        double *xo = X + int64_t(br0 + r) * ldb;
+        if (lane < w) {
+            y[d.first + lane] = x[0][r];
+            xo[perm[d.first + lane]] = x[0][r];
+        }
     }
 }
 
@@ -168,71 +340,24 @@ __global__ __launch_bounds__(64) void k_fwd_panel(
     }
 }
 
-// Backward step of one level for supernodes solved in LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_small(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
-    const T *__restrict__ L, int64_t Lsize, double *__restrict__ X,
-    int64_t ldb, double *__restrict__ Y, int64_t n, int nrhs,
-    const int32_t *__restrict__ active) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *v = reinterpret_cast<double *>(smem_raw);
-    __shared__ double red[4];
-    const int s = list[blockIdx.x];
-    const int br = blockIdx.y;
-    const int b = br / nrhs;
-    if (active && !active[b]) return;
-    const SnDesc d = sn[s];
-    const int c = d.c, w = d.w;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6;
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    double *y = Y + int64_t(br) * n;
-    double *x = X + int64_t(br) * ldb;
-    const int32_t *R = rows + d.rowptr;
-    for (int i = tid; i < c; i += nt) v[i] = y[i < w ? d.first + i : R[i]];
-    __syncthreads();
-    for (int j = w - 1; j >= 0; j--) {
-        const T *lj = Lb + int64_t(j) * c;
-        double t = 0.0;
-        for (int i = j + 1 + tid; i < c; i += nt) t += double(lj[i]) * v[i];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-        if (lane == 0) red[wv] = t;
-        __syncthreads();
-        if (tid == 0) {
-            double tot = 0.0;
-            for (int q = 0; q < (nt >> 6); q++) tot += red[q];
-            v[j] = (v[j] - tot) / double(lj[j]);
-        }
-        __syncthreads();
-    }
-    for (int i = tid; i < w; i += nt) {
-        y[d.first + i] = v[i];
-        x[perm[d.first + i]] = v[i];
-    }
-}
-
-// Backward panel p of panel-solved supernodes: partial sums of
-// L[r, c0 + t] z_r over a chunk of kSolveChunk rows below the panel; the
-// last workgroup of the supernode sums the chunks in order and solves with
-// D_p^T.
-template <typename T>
+// Backward panel p of panel-solved supernodes, NR right-hand sides of one
+// matrix per workgroup: partial sums of L[r, c0 + t] z_r over a chunk of
+// kSolveChunk rows below the panel (wave g owns columns g + 4k, each thread
+// four rows); the last workgroup of the (supernode, matrix) sums the chunks
+// in order and solves with D_p^T.
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_bwd_panel(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int list0, int p,
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int list0, int p, int r0,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
     const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv, int64_t dsize,
     double *__restrict__ X, int64_t ldb, double *__restrict__ Y, int64_t n,
-    double *__restrict__ PART, int64_t psize, int32_t *__restrict__ cnt, int nbr, int nrhs,
+    double *__restrict__ PART, int64_t psize, int32_t *__restrict__ cnt, int batch, int nrhs,
     const int32_t *__restrict__ active) {
-    __shared__ double red[4][kP];
-    __shared__ double rhs[kP];
+    __shared__ double rhs[NR][kP];
     __shared__ double Dt[kP * (kP + 1)];
     __shared__ int last;
     const int s = list[blockIdx.y];
-    const int br = blockIdx.z;
-    const int b = br / nrhs;
+    const int b = blockIdx.z;
     if (active && !active[b]) return;
     const SnDesc d = sn[s];
     const int c0 = p * kP;
@@ -243,29 +368,60 @@ __global__ __launch_bounds__(256) void k_bwd_panel(
     const int nch = max(1, (c - rbeg + kSolveChunk - 1) / kSolveChunk);
     const int chunk = blockIdx.x;
     if (chunk >= nch) return;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, cg = tid >> 6;
+    const int br0 = b * nrhs + r0;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    double *y = Y + int64_t(br) * n;
     const int32_t *R = rows + d.rowptr;
-    const int r = rbeg + chunk * kSolveChunk + tid;
-    const double zr = r < c ? y[r < w ? d.first + r : R[r]] : 0.0;
-    double pr[kP];
+    const int rb = rbeg + chunk * kSolveChunk;
+    double z[4][NR];
 #pragma unroll
-    for (int t = 0; t < kP; t++)
-        pr[t] = (r < c && t < kb) ? double(Lb[int64_t(c0 + t) * c + r]) * zr : 0.0;
+    for (int q = 0; q < 4; q++) {
+        const int r = rb + 64 * q + lane;
+        const int64_t pos = r < c ? (r < w ? d.first + r : R[r]) : 0;
 #pragma unroll
-    for (int t = 0; t < kP; t++) {
-        double v = pr[t];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[wv][t] = v;
+        for (int k = 0; k < NR; k++) z[q][k] = r < c ? Y[int64_t(br0 + k) * n + pos] : 0.0;
     }
-    __syncthreads();
-    double *part = PART + int64_t(br) * psize + d.part;
-    if (tid < kb) part[chunk * kP + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    double acc[16][NR];
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+#pragma unroll
+        for (int k = 0; k < NR; k++) acc[j][k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int t = cg + 4 * j;
+        if (t < kb) {
+            const T *lc = Lb + int64_t(c0 + t) * c;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int r = rb + 64 * q + lane;
+                const double l = r < c ? double(lc[r]) : 0.0;
+#pragma unroll
+                for (int k = 0; k < NR; k++) acc[j][k] += l * z[q][k];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            double v = acc[j][k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            acc[j][k] = v;
+        }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int t = cg + 4 * j;
+            if (t < kb)
+#pragma unroll
+                for (int k = 0; k < NR; k++)
+                    PART[int64_t(br0 + k) * psize + d.part + chunk * kP + t] = acc[j][k];
+        }
+    }
     __threadfence();
     __syncthreads();
-    int32_t *ctr = cnt + int64_t(list0 + blockIdx.y) * nbr + br;
+    int32_t *ctr = cnt + int64_t(list0 + blockIdx.y) * batch + b;
     if (tid == 0) last = atomicAdd(ctr, 1) == nch - 1;
     __syncthreads();
     if (!last) return;
@@ -280,23 +436,30 @@ __global__ __launch_bounds__(256) void k_bwd_panel(
         }
     }
     if (tid < kb) {
-        double s0 = 0.0, s1 = 0.0;
-        int q = 0;
-        for (; q + 1 < nch; q += 2) {
-            s0 += part[q * kP + tid];
-            s1 += part[(q + 1) * kP + tid];
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            const double *part = PART + int64_t(br0 + k) * psize + d.part;
+            double s0 = 0.0;
+            for (int q = 0; q < nch; q++) s0 += part[q * kP + tid];
+            rhs[k][tid] = Y[int64_t(br0 + k) * n + d.first + c0 + tid] - s0;
         }
-        if (q < nch) s0 += part[q * kP + tid];
-        rhs[tid] = y[d.first + c0 + tid] - (s0 + s1);
     }
     __syncthreads();
     if (tid < kb) {
         // x_t = sum_i (L_pp^{-1})[i][t] rhs_i; column t of the inverse is Dt[t][.]
-        double xt = 0.0;
-#pragma unroll 16
-        for (int i = 0; i < kP; i++) xt += Dt[tid * (kP + 1) + i] * (i < kb ? rhs[i] : 0.0);
-        y[d.first + c0 + tid] = xt;
-        X[int64_t(br) * ldb + perm[d.first + c0 + tid]] = xt;
+        double xt[NR];
+#pragma unroll
+        for (int k = 0; k < NR; k++) xt[k] = 0.0;
+        for (int i = 0; i < kb; i++) {
+            const double dti = Dt[tid * (kP + 1) + i];
+#pragma unroll
+            for (int k = 0; k < NR; k++) xt[k] += dti * rhs[k][i];
+        }
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            Y[int64_t(br0 + k) * n + d.first + c0 + tid] = xt[k];
+            X[int64_t(br0 + k) * ldb + perm[d.first + c0 + tid]] = xt[k];
+        }
     }
     if (tid == 0) *ctr = 0;
 }
@@ -318,8 +481,12 @@ template <typename T>
 hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
                       int64_t ldb, hipStream_t st, const int32_t *active) {
     DevPlan *D = P->dev;
-    for (const SLaunch &l : D->ssched)
-        if (size_t(l.maxc) * sizeof(double) > size_t(g_max_lds)) return hipErrorInvalidValue;
+    for (const SLaunch &l : D->ssched) {
+        if (size_t(l.maxc_pan) * sizeof(double) > size_t(g_max_lds)) return hipErrorInvalidValue;
+        if (size_t(16) * l.maxc_small * sizeof(double) > size_t(g_max_lds))
+            return hipErrorInvalidValue;
+        if (l.maxc_small > 64 * kWaveSlots) return hipErrorInvalidValue;
+    }
     const T *L = static_cast<const T *>(N->L);
     const int nbr = N->batch * nrhs;
     const unsigned gy = unsigned(nbr);
@@ -328,19 +495,39 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
     const double sz = double(sizeof(T)), nr = double(gy);
     for (const SLaunch &l : D->ssched) {
         if (l.nsmall > 0) {
-            prof.begin(KK_Fwd, l.f_small * nr, (l.w_small * sz + l.v_small) * nr, st);
-            hipLaunchKernelGGL(k_fwd_small<T>, dim3(unsigned(l.nsmall), gy), dim3(256),
-                               size_t(l.maxc_small) * sizeof(double), st, D->sn,
-                               D->slv_small + l.small0, 1, D->perm, D->relmap, D->chlist, L,
-                               P->Lsize, b, ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, active);
+            prof.begin(KK_Fwd, l.f_small * nr, (l.w_small * sz * N->batch + l.v_small * nr), st);
+            const int nitems = l.nsmall * N->batch;
+            for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                const int nrr = std::min(4, nrhs - r0);
+                const size_t lds = size_t(4) * nrr * l.maxc_small * sizeof(double);
+                const dim3 g(unsigned((nitems + 3) / 4));
+                const int32_t *lst = D->slv_small + l.small0;
+                const int sl = l.maxc_small <= 64 ? 1 : l.maxc_small <= 128 ? 2
+                             : l.maxc_small <= 256 ? 4 : 8;
+#define SPCHOL_FWD(NRV, SLV)                                                                \
+    hipLaunchKernelGGL((k_fwd_wave<T, NRV, SLV>), g, dim3(256), lds, st, D->sn, lst,        \
+                       l.nsmall, nitems, r0, D->perm, D->relmap, D->chlist, L, P->Lsize, b,  \
+                       ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, l.maxc_small, active)
+#define SPCHOL_FWD_SL(NRV)                                                                  \
+    if (sl == 1) SPCHOL_FWD(NRV, 1);                                                        \
+    else if (sl == 2) SPCHOL_FWD(NRV, 2);                                                   \
+    else if (sl == 4) SPCHOL_FWD(NRV, 4);                                                   \
+    else SPCHOL_FWD(NRV, 8)
+                if (nrr == 1) { SPCHOL_FWD_SL(1); }
+                else if (nrr == 2) { SPCHOL_FWD_SL(2); }
+                else if (nrr == 3) { SPCHOL_FWD_SL(3); }
+                else { SPCHOL_FWD_SL(4); }
+#undef SPCHOL_FWD_SL
+#undef SPCHOL_FWD
+            }
             prof.end(st);
         }
         if (l.npan > 0) {
             prof.begin(KK_Fwd, 0.0, l.v_pan * nr, st);
-            hipLaunchKernelGGL(k_fwd_small<T>, dim3(unsigned(l.npan), gy), dim3(256),
+            hipLaunchKernelGGL(k_fwd_gather, dim3(unsigned(l.npan), gy), dim3(256),
                                size_t(l.maxc_pan) * sizeof(double), st, D->sn,
-                               D->slv_pan + l.pan0, 0, D->perm, D->relmap, D->chlist, L,
-                               P->Lsize, b, ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, active);
+                               D->slv_pan + l.pan0, D->perm, D->relmap, D->chlist, b, ldb,
+                               N->ws_u, fvsize, nrhs, active);
             prof.end(st);
             for (size_t q = 0; q < l.panels.size(); q++) {
                 const SPanel &pp = l.panels[q];
@@ -359,33 +546,75 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
         if (l.npan > 0) {
             for (size_t q = l.panels.size(); q-- > 0;) {
                 const SPanel &pp = l.panels[q];
-                prof.begin(KK_BwdPanel, pp.flops * nr, (pp.words * sz + pp.vbytes) * nr, st);
-                hipLaunchKernelGGL(k_bwd_panel<T>,
-                                   dim3(unsigned(pp.bwd_chunks), unsigned(l.npan), gy),
-                                   dim3(256), 0, st, D->sn, D->slv_pan + l.pan0, l.pan0,
-                                   int(q), D->perm, D->rows, L, P->Lsize, N->dinv,
-                                   P->dinv_size, b, ldb, N->ws_y, P->n, N->ws_part,
-                                   P->part_size, N->ws_cnt, nbr, nrhs, active);
+                prof.begin(KK_BwdPanel, pp.flops * nr,
+                           pp.words * sz * N->batch + pp.vbytes * nr, st);
+                for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                    const int nrr = std::min(4, nrhs - r0);
+                    const dim3 g(unsigned(pp.bwd_chunks), unsigned(l.npan), unsigned(N->batch));
+#define SPCHOL_BWDP(NRV)                                                                       \
+    hipLaunchKernelGGL((k_bwd_panel<T, NRV>), g, dim3(256), 0, st, D->sn, D->slv_pan + l.pan0, \
+                       l.pan0, int(q), r0, D->perm, D->rows, L, P->Lsize, N->dinv, P->dinv_size, \
+                       b, ldb, N->ws_y, P->n, N->ws_part, P->part_size, N->ws_cnt, N->batch,    \
+                       nrhs, active)
+                    if (nrr == 1) SPCHOL_BWDP(1);
+                    else if (nrr == 2) SPCHOL_BWDP(2);
+                    else if (nrr == 3) SPCHOL_BWDP(3);
+                    else SPCHOL_BWDP(4);
+#undef SPCHOL_BWDP
+                }
                 prof.end(st);
             }
         }
         if (l.nsmall > 0) {
-            prof.begin(KK_Bwd, l.f_small * nr, (l.w_small * sz + l.v_small) * nr, st);
-            hipLaunchKernelGGL(k_bwd_small<T>, dim3(unsigned(l.nsmall), gy), dim3(256),
-                               size_t(l.maxc_small) * sizeof(double), st, D->sn,
-                               D->slv_small + l.small0, D->perm, D->rows, L, P->Lsize, b, ldb,
-                               N->ws_y, P->n, nrhs, active);
+            prof.begin(KK_Bwd, l.f_small * nr, (l.w_small * sz * N->batch + l.v_small * nr), st);
+            const int nitems = l.nsmall * N->batch;
+            for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                const int nrr = std::min(4, nrhs - r0);
+                const dim3 g(unsigned((nitems + 3) / 4));
+                const int32_t *lst = D->slv_small + l.small0;
+                const int sl = l.maxc_small <= 64 ? 1 : l.maxc_small <= 128 ? 2
+                             : l.maxc_small <= 256 ? 4 : 8;
+#define SPCHOL_BWD(NRV, SLV)                                                                 \
+    hipLaunchKernelGGL((k_bwd_wave<T, NRV, SLV>), g, dim3(256), 0, st, D->sn, lst, l.nsmall, \
+                       nitems, r0, D->perm, D->rows, L, P->Lsize, b, ldb, N->ws_y, P->n,     \
+                       nrhs, active)
+#define SPCHOL_BWD_SL(NRV)                                                                   \
+    if (sl == 1) SPCHOL_BWD(NRV, 1);                                                         \
+    else if (sl == 2) SPCHOL_BWD(NRV, 2);                                                    \
+    else if (sl == 4) SPCHOL_BWD(NRV, 4);                                                    \
+    else SPCHOL_BWD(NRV, 8)
+                if (nrr == 1) { SPCHOL_BWD_SL(1); }
+                else if (nrr == 2) { SPCHOL_BWD_SL(2); }
+                else if (nrr == 3) { SPCHOL_BWD_SL(3); }
+                else { SPCHOL_BWD_SL(4); }
+#undef SPCHOL_BWD_SL
+#undef SPCHOL_BWD
+            }
             prof.end(st);
         }
     }
     return hipGetLastError();
 }
 
+template <typename T, int NR>
+void set_fwd_wave_lds(int big) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 1>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 4>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 8>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+
 template <typename T>
 void set_solve_lds(int big) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_small<T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_small<T>),
+    set_fwd_wave_lds<T, 1>(big);
+    set_fwd_wave_lds<T, 2>(big);
+    set_fwd_wave_lds<T, 3>(big);
+    set_fwd_wave_lds<T, 4>(big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_gather),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 

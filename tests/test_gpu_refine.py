@@ -16,7 +16,7 @@ from tests.gpu_helpers import log, oracle_run
 pytestmark = pytest.mark.gpu
 
 
-def _refine(w, dtype, tol=1e-10, maxit=10):
+def _refine(w, dtype, tol=1e-10, maxit=10, method="classical"):
     import paper_2110_12865_amd as S
     p = w.pattern
     plan = S.analyze(p.colptr, p.rowind, w.perm)
@@ -26,15 +26,16 @@ def _refine(w, dtype, tol=1e-10, maxit=10):
     assert np.all(num.info() == 0)
     b = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
     x = torch.empty_like(b)
-    rc, stats = num.refine_solve(vals, b, x, tol=tol, maxit=maxit)
+    rc, stats = num.refine_solve(vals, b, x, tol=tol, maxit=maxit, method=method)
     return rc, stats, x.cpu().numpy()
 
 
+@pytest.mark.parametrize("method", ["classical", "pcg"])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_refine_matches_fp64_oracle(dtype):
+def test_refine_matches_fp64_oracle(dtype, method):
     import paper_2110_12865_amd as S
     w = W.small_grid((14, 14, 14), "nd", seed=61, batch=3, nrhs=2)
-    rc, stats, x = _refine(w, dtype)
+    rc, stats, x = _refine(w, dtype, method=method)
     assert rc == S.SC_OK
     p = w.pattern
     for s in range(w.batch):
@@ -66,13 +67,14 @@ def test_refine_reports_no_convergence():
     assert 1e-10 < stats[0]["relres"] < 1e-4
 
 
-def test_refine_ill_conditioned_mesh_reaches_floor():
+@pytest.mark.parametrize("method", ["classical", "pcg"])
+def test_refine_ill_conditioned_mesh_reaches_floor(method):
     """Cotangent stiffness + 1e-3 lumped mass (the 512^2 mesh construction at
     64^2): kappa ~ 1e7-1e8.  Every system must stop by one of the two
     clauses, within a few corrections."""
     import paper_2110_12865_amd as S
     w = W.trimesh_workload(64, 4, 3, seed=63)
-    rc, stats, x = _refine(w, "f32", maxit=20)
+    rc, stats, x = _refine(w, "f32", maxit=20, method=method)
     for st in stats:
         log("mesh: iters %d clause %d relres %.2e" % (st["iters"], st["clause"], st["relres"]))
     assert rc == S.SC_OK
@@ -92,3 +94,25 @@ def test_refine_batch_matches_single_bitwise():
     rc1, stats1, x1 = _refine(w1, "f32")
     assert np.array_equal(xb[1], x1[0])
     assert stats[1]["iters"] == stats1[0]["iters"]
+
+
+def test_pcg_converges_where_classical_stalls():
+    """The 512^2 mesh construction at 256^2 keeps kappa ~ 2.5e9 (the mass
+    term scales as 1/n), so kappa * u_32 >> 1: classical refinement with the
+    FP32 factor stalls, preconditioned CG reaches the stop rule."""
+    import paper_2110_12865_amd as S
+    w = W.trimesh_workload(256, 2, 1, seed=65)
+    rc_c, st_c, _ = _refine(w, "f32", maxit=15, method="classical")
+    rc_p, st_p, x = _refine(w, "f32", maxit=40, method="pcg")
+    for a, b in zip(st_c, st_p):
+        log("256^2 mesh: classical relres %.2e clause %d | pcg iters %d relres %.2e clause %d"
+            % (a["relres"], a["clause"], b["iters"], b["relres"], b["clause"]))
+    assert rc_p == S.SC_OK
+    assert all(s["clause"] in (1, 2) for s in st_p)
+    p = w.pattern
+    for s in range(w.batch):
+        sym, Lx, _, xo = oracle_run(w, s)
+        relres_o, _ = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[s], xo, w.b[s])
+        relres_g, _ = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[s], x[s], w.b[s])
+        log("  set %d: direct FP64 relres %.2e, pcg relres %.2e" % (s, relres_o[0], relres_g[0]))
+        assert relres_g[0] <= max(10 * relres_o[0], 1e-10)

@@ -379,3 +379,16 @@ def random_spd(n: int, density: float, seed: int, batch: int = 1,
     p = rng.permutation(n).astype(np.int32) if perm else None
     return Workload(name="random_%d" % n, pattern=pat, perm=p, values=vals,
                     b=b, seed=seed)
+
+
+def group_arrays(ws: Sequence[Workload]) -> Tuple[np.ndarray, np.ndarray]:
+    """Value sets and right-hand sides of several workloads with the same
+    batch and nrhs laid out as one block-diagonal group: set b is the
+    concatenation of every pattern's set b, vector (b, r) the concatenation
+    of every pattern's vector (b, r), in pattern order."""
+    batch, nrhs = ws[0].batch, ws[0].nrhs
+    if any(w.batch != batch or w.nrhs != nrhs for w in ws):
+        raise ValueError("group members need the same batch and nrhs")
+    vals = np.concatenate([w.values for w in ws], axis=1)
+    b = np.concatenate([w.b for w in ws], axis=2)
+    return np.ascontiguousarray(vals), np.ascontiguousarray(b)
