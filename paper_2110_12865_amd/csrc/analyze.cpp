@@ -474,6 +474,9 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         P->slv_small_ptr.assign(nlev + 1, 0);
         P->slv_pan_ptr.assign(nlev + 1, 0);
         P->slv_small_maxc.assign(nlev, 0);
+        P->slv_lane_n.assign(nlev, 0);
+        P->slv_lane_maxc.assign(nlev, 0);
+        if (int64_t(P->rows.size()) >= INT32_MAX) throw std::bad_alloc();
         P->slv_pan_maxw.assign(nlev, 0);
         P->slv_pan_maxc.assign(nlev, 0);
         for (int32_t s = 0; s < ns; s++) { P->sn[s].dinv = -1; P->sn[s].part = 0; }
@@ -490,13 +493,42 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                     P->slv_pan_maxw[l] = std::max(P->slv_pan_maxw[l], d.w);
                     P->slv_pan_maxc[l] = std::max(P->slv_pan_maxc[l], d.c);
                     P->npan++;
-                } else {
+                } else if (d.c <= kLaneMaxC) {
+                    P->slv_small.push_back(s);
+                    P->slv_lane_n[l]++;
+                    P->slv_lane_maxc[l] = std::max(P->slv_lane_maxc[l], d.c);
+                }
+            }
+            for (int32_t s : bya[l]) {  // the rest of the level's small supernodes
+                const SnDesc &d = P->sn[s];
+                if (!solve_by_panels(d) && d.c > kLaneMaxC) {
                     P->slv_small.push_back(s);
                     P->slv_small_maxc[l] = std::max(P->slv_small_maxc[l], d.c);
                 }
             }
             P->slv_small_ptr[l + 1] = int32_t(P->slv_small.size());
             P->slv_pan_ptr[l + 1] = int32_t(P->slv_pan.size());
+        }
+        // forward-solve gather map (children in chlist order)
+        P->gptr.assign(P->rows.size() + 1, 0);
+        for (int32_t s = 0; s < ns; s++) {
+            const SnDesc &d = P->sn[s];
+            if (d.m == 0) continue;
+            const SnDesc &pd = P->sn[d.parent];
+            for (int32_t i = 0; i < d.m; i++) P->gptr[pd.rowptr + P->relmap[d.relptr + i] + 1]++;
+        }
+        for (size_t q = 0; q + 1 < P->gptr.size(); q++) P->gptr[q + 1] += P->gptr[q];
+        P->gidx.assign(P->gptr.back(), 0);
+        {
+            std::vector<int32_t> fill(P->gptr.begin(), P->gptr.end() - 1);
+            for (int32_t s = 0; s < ns; s++)
+                for (int32_t q = P->sn[s].chbeg; q < P->sn[s].chend; q++) {
+                    const SnDesc &cd = P->sn[P->chlist[q]];
+                    for (int32_t i = 0; i < cd.m; i++) {
+                        const int64_t slot = P->sn[s].rowptr + P->relmap[cd.relptr + i];
+                        P->gidx[fill[slot]++] = int32_t(cd.rowptr + cd.w + i);
+                    }
+                }
         }
     } catch (const std::bad_alloc &) {
         delete P;

@@ -14,7 +14,8 @@
 
 const char *const kKernelNames[KK_Count] = {
     "front_small", "assemble", "potrf", "trsm", "syrk_mfma", "diag_inverse",
-    "solve_fwd", "solve_fwd_panel", "solve_bwd", "solve_bwd_panel"};
+    "solve_fwd", "solve_fwd_panel", "solve_bwd", "solve_bwd_panel", "spmv_residual",
+    "refine_vector"};
 
 void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
@@ -40,7 +41,7 @@ void free_devplan(DevPlan *D) {
                     D->avidx, D->perm, D->lvl_small, D->lvl_big, D->lvl_sn,
                     D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
                     D->slv_small, D->slv_pan, D->big_colent, D->big_chmap_off,
-                    D->big_chmap, D->colblk, D->blk_col0};
+                    D->big_chmap, D->colblk, D->blk_col0, D->gptr, D->gidx};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete D;
@@ -81,6 +82,8 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->csr_col, P->csr_col);
     if (e == hipSuccess) e = upload(&D->csr_vidx, P->csr_vidx);
     if (e == hipSuccess) e = upload(&D->colblk, P->colblk);
+    if (e == hipSuccess) e = upload(&D->gptr, P->gptr);
+    if (e == hipSuccess) e = upload(&D->gidx, P->gidx);
     if (e == hipSuccess) e = upload(&D->blk_col0, P->blk_col0);
     if (e != hipSuccess) {
         free_devplan(D);
@@ -127,7 +130,7 @@ hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
 }
 
 void free_refine_ws(RefineWs &W) {
-    void *ptrs[] = {W.r, W.sc, W.part, W.anorm, W.stat, W.conv, W.active, W.count};
+    void *ptrs[] = {W.r, W.sc, W.part, W.anorm, W.vc, W.stat, W.conv, W.active, W.count};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     W = RefineWs{};
@@ -148,6 +151,9 @@ hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.anorm),
                       sizeof(double) * N->batch * N->plan->nblk);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&W.vc),
+                      sizeof(double) * N->batch * std::max<int64_t>(N->plan->csr_ptr.back(), 1));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.stat), sizeof(double) * 6 * nseg);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.conv), sizeof(int32_t) * nseg);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.active), sizeof(int32_t) * N->batch);

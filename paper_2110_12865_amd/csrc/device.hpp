@@ -43,7 +43,9 @@ struct SPanel {  // one 64-column panel step of a level's panel-solved supernode
 
 struct SLaunch {  // one level of a triangular solve
     int32_t level = 0;
-    int32_t small0 = 0, nsmall = 0;  // supernodes solved in LDS
+    int32_t lane0 = 0, nlane = 0, maxc_lane = 0;  // supernodes solved one per lane
+    double f_lane = 0.0, w_lane = 0.0, v_lane = 0.0;
+    int32_t small0 = 0, nsmall = 0;  // supernodes solved one per wave
     int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
     int32_t maxc_small = 0, maxc_pan = 0, maxc = 0;
     double f_small = 0.0, w_small = 0.0, v_small = 0.0, v_pan = 0.0;
@@ -71,6 +73,8 @@ struct DevPlan {
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int32_t *csr_col = nullptr;
     int64_t *csr_vidx = nullptr;
+    int32_t *gptr = nullptr;          // forward-solve gather map
+    int32_t *gidx = nullptr;
     int32_t *colblk = nullptr;        // block of every column
     int64_t *blk_col0 = nullptr;      // nblk + 1 block column offsets
     std::vector<FLaunch> fsched;
@@ -80,7 +84,7 @@ struct DevPlan {
 // Kernel kinds for per-launch timing.
 enum KernelKind : int {
     KK_SmallFront = 0, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk, KK_Dinv,
-    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Count
+    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Spmv, KK_Vec, KK_Count
 };
 extern const char *const kKernelNames[KK_Count];
 
@@ -121,11 +125,13 @@ struct RefineWs {
     int32_t nsys = 0;
     int64_t ldb = 0;
     double *r = nullptr;        // 5 vectors of nsys * ldb (residual, correction, CG)
-    double *sc = nullptr;       // per-system scalars, 3 * nsys
-    double *part = nullptr;     // reduction partials, nsys * 32 * 3
-    double *anorm = nullptr;    // batch
-    double *stat = nullptr;     // nsys * 6
-    int32_t *conv = nullptr;    // nsys
+    // per system (matrix, right-hand side, block): nseg = nsys * nblk
+    double *sc = nullptr;       // scalars, 3 * nseg
+    double *part = nullptr;     // reduction partials, nseg * 32 * 3
+    double *anorm = nullptr;    // batch * nblk
+    double *vc = nullptr;       // values of A in row order, batch * nnz(both triangles)
+    double *stat = nullptr;     // nseg * 6
+    int32_t *conv = nullptr;    // nseg
     int32_t *active = nullptr;  // batch
     int32_t *count = nullptr;   // 1
 };

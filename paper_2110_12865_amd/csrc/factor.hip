@@ -152,6 +152,142 @@ __global__ __launch_bounds__(256) void k_front_wave(
         for (int i = j + lane; i < m; i += 64) Us[int64_t(j) * m + i] = F[(w + j) * c + w + i];
 }
 
+// Broadcast lane `src` (wave-uniform) of v to the whole wave.
+__device__ inline double rl(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<unsigned int>(lo));
+}
+__device__ inline float rl(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+// Small fronts (c <= CM <= 64) held in registers, one wave per (front,
+// matrix), four waves per workgroup: lane i keeps row i of the front,
+// f[k] = F[i][k] for k <= i (entries above the diagonal are scratch).
+//   assembly  A's entries are loaded lane-parallel and handed to their row
+//             with readlane; a child's update block is read row-wise
+//             through the inverse of its relative map (an LDS table).
+//   factor    right-looking: the pivot and the column of L are broadcast
+//             with readlane; after each step the registers shift left by
+//             one so that the current column is always f[0] (every
+//             register index is a compile-time constant).
+template <typename T, int CM>
+__global__ __launch_bounds__(256) void k_front_reg(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist,
+    const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
+    const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
+    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
+    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
+    int32_t *__restrict__ info, int nblk) {
+    __shared__ int32_t inv_all[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int e = blockIdx.x * 4 + wv;
+    if (e >= nlist) return;
+    int32_t *inv = inv_all[wv];
+    const int s = list[e];
+    const int b = blockIdx.y;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w, m = d.m;
+    L += int64_t(b) * Lsize;
+    U += int64_t(b) * Usize;
+    vals += int64_t(b) * ldv;
+
+    T f[CM];
+#pragma unroll
+    for (int k = 0; k < CM; k++) f[k] = T(0);
+
+    // A's columns of the front: entries [a0, a1), sorted by column
+    const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
+    // first entry of column `lane`, relative to a0
+    const int acol = lane < w ? int(acolptr[d.first + lane] - a0) : int(a1 - a0);
+    for (int64_t base = a0; base < a1; base += 64) {
+        const int64_t q = base + lane;
+        int row = -1;
+        T val = T(0);
+        if (q < a1) {
+            row = aoff[q] % c;
+            val = T(vals[avidx[q]]);
+        }
+        const int rb = int(base - a0);                       // this round: entries
+        const int re = int((base + 64 < a1 ? base + 64 : a1) - a0);  // [rb, re)
+#pragma unroll
+        for (int k = 0; k < CM; k++) {
+            // column k's entries in this round (none once k >= w)
+            const int lo = k < w ? __builtin_amdgcn_readlane(acol, k) : re;
+            const int hi = k + 1 < w ? __builtin_amdgcn_readlane(acol, (k + 1) & 63) : int(a1 - a0);
+            const int t0 = (lo > rb ? lo : rb) - rb;
+            const int t1 = (hi < re ? hi : re) - rb;
+            for (int t = t0; t < t1; t++) {
+                const int r = __builtin_amdgcn_readlane(row, t);
+                const T v = rl(val, t);
+                if (lane == r) f[k] += v;
+            }
+        }
+    }
+
+    // children's update blocks
+    for (int q = d.chbeg; q < d.chend; q++) {
+        const SnDesc cd = sn[chlist[q]];
+        const int mc = cd.m;
+        const T *Uc = U + cd.uoff;
+        inv[lane] = -1;
+        wave_fence_sync();
+        if (lane < mc) inv[relmap[cd.relptr + lane]] = lane;
+        wave_fence_sync();
+        const int pi = inv[lane];  // child row landing in front row `lane`, or -1
+        wave_fence_sync();
+        // eight target columns at a time: all loads issued before any use
+        // (addresses of absent entries are clamped to the block's first)
+#pragma unroll
+        for (int k0 = 0; k0 < CM; k0 += 8) {
+            int qk[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) qk[t] = __builtin_amdgcn_readlane(pi, k0 + t);
+            if ((qk[0] & qk[1] & qk[2] & qk[3] & qk[4] & qk[5] & qk[6] & qk[7]) == -1)
+                continue;  // no column of this child lands here
+            T v[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const bool ok = qk[t] >= 0 && pi >= qk[t];
+                v[t] = Uc[ok ? int64_t(qk[t]) * mc + pi : 0];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                if (qk[t] >= 0 && pi >= qk[t]) f[k0 + t] += v[t];
+        }
+    }
+
+    // partial factorization of the first w columns
+    const int64_t infoidx = int64_t(b) * nblk + d.blk;
+    T *Lb = L + d.loff;
+    for (int j = 0; j < w; j++) {
+        T djj = rl(f[0], j);
+        const bool bad = !(djj > T(0));
+        if (bad) {
+            djj = T(1);
+            if (lane == 0) atomicMin(info + infoidx, d.first - d.bcol0 + j + 1);
+        }
+        const T ljj = dsqrt(djj);
+        const T rinv = T(1) / ljj;
+        const T lij = lane == j ? ljj : (lane > j ? f[0] * rinv : T(0));
+        if (lane < c) Lb[int64_t(j) * c + lane] = lij;
+        // columns j + k >= c are scratch: their updates are never read
+#pragma unroll
+        for (int k = 1; k < CM; k++) f[k] -= lij * rl(lij, (j + k) & 63);
+#pragma unroll
+        for (int k = 0; k + 1 < CM; k++) f[k] = f[k + 1];
+        f[CM - 1] = T(0);
+    }
+    // f[k] now holds column w + k: the update block
+    T *Us = U + d.uoff;
+#pragma unroll
+    for (int k = 0; k < CM; k++)
+        if (k < m && lane >= w + k && lane < c) Us[int64_t(k) * m + lane - w] = f[k];
+}
+
 // Large fronts: assembly with one wave per target column, `per` columns per
 // workgroup (c_max scalars of LDS per wave).
 template <typename T>
@@ -642,10 +778,26 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, st);
         switch (f.kind) {
         case FLaunch::Small: {
-            // one wave per front; as many fronts per workgroup as LDS allows
+            const int cmax = int(std::lround(std::sqrt(double(f.lds))));
+            if (cmax <= 64) {
+                // fronts in registers, one wave each, four per workgroup
+                const dim3 grid(unsigned((f.nlist + 3) / 4), B);
+#define SPCHOL_FRONT_REG(CM)                                                                \
+    hipLaunchKernelGGL((k_front_reg<T, CM>), grid, dim3(256), 0, st, D->sn,                  \
+                       D->lvl_small + f.list0, f.nlist, D->relmap, D->chlist, D->acolptr,    \
+                       D->aoff, D->avidx, vals, ldv, L, P->Lsize, U, P->Usize, N->info,      \
+                       P->nblk)
+                if (cmax <= 16) SPCHOL_FRONT_REG(16);
+                else if (cmax <= 32) SPCHOL_FRONT_REG(32);
+                else if (cmax <= 48) SPCHOL_FRONT_REG(48);
+                else if (cmax <= 56) SPCHOL_FRONT_REG(56);
+                else SPCHOL_FRONT_REG(64);
+#undef SPCHOL_FRONT_REG
+                break;
+            }
+            // wider fronts: one wave per front out of LDS
             const size_t per_lds = size_t(f.lds) * sizeof(T);
             const int per = int(std::max<size_t>(1, std::min<size_t>(4, g_max_lds / per_lds)));
-            const int cmax = int(std::lround(std::sqrt(double(f.lds))));
             hipLaunchKernelGGL(k_front_wave<T>, dim3(unsigned((f.nlist + per - 1) / per), B),
                                dim3(64 * per), per_lds * per, st, D->sn, D->lvl_small + f.list0,
                                f.nlist, per, cmax, D->relmap, D->chlist, D->acolptr, D->aoff,

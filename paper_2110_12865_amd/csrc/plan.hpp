@@ -34,6 +34,8 @@ static_assert(sizeof(SnDesc) == 88, "SnDesc layout");
 // is wide or tall; otherwise one workgroup solves it out of LDS.
 constexpr int kSolvePanel = 64;
 constexpr int kSolveChunk = 256;  // rows per workgroup in the backward panel step
+// Supernodes with at most this many rows are solved one per lane.
+constexpr int kLaneMaxC = 32;
 inline bool solve_by_panels(const SnDesc &d) { return d.w > kSolvePanel || d.c > 512; }
 
 struct DevPlan;  // device copies, defined by the HIP side
@@ -98,6 +100,13 @@ struct sc_plan {
     // solve schedule: per level, supernodes solved in LDS and by panels
     std::vector<int32_t> slv_small_ptr, slv_small, slv_pan_ptr, slv_pan;
     std::vector<int32_t> slv_small_maxc, slv_pan_maxw, slv_pan_maxc;
+    // the first slv_lane_n[l] entries of a level's slv_small list have at
+    // most kLaneMaxC rows (solved one per lane); slv_small_maxc covers the rest
+    std::vector<int32_t> slv_lane_n, slv_lane_maxc;
+    // forward-solve gather map: the update-vector entries of the children
+    // that land in row i of supernode s are FV[gidx[g]] for g in
+    // [gptr[rowptr_s + i], gptr[rowptr_s + i + 1]), children in order
+    std::vector<int32_t> gptr, gidx;
     int64_t dinv_size = 0;   // scalars of inverted diagonal blocks
     int64_t part_size = 0;   // partial sums per right-hand side
     int32_t npan = 0;        // supernodes solved by panels

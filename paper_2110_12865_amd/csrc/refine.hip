@@ -22,22 +22,47 @@
 
 namespace {
 
-// r = b - A x for every (matrix, rhs) with active[matrix] != 0
-__global__ __launch_bounds__(256) void k_resid(
-    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+// The values of A in the order of its row structure (both triangles), one
+// copy per matrix: vc[b * nnzf + e] = values[b][vidx[e]].  Made once per
+// refinement call so that every later product reads A contiguously.
+__global__ __launch_bounds__(256) void k_gather_rows(
     const int64_t *__restrict__ vidx, const double *__restrict__ vals, int64_t ldv,
-    const double *__restrict__ B, const double *__restrict__ X, double *__restrict__ R,
-    int64_t ldb, int64_t n, int nrhs, const int32_t *__restrict__ active) {
-    const int br = blockIdx.y;
-    const int b = br / nrhs;
+    int64_t nnzf, double *__restrict__ vc) {
+    const int b = blockIdx.y;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < nnzf) vc[int64_t(b) * nnzf + e] = vals[int64_t(b) * ldv + vidx[e]];
+}
+
+// Y = B - A X (mode 1) or Y = A X (mode 0) for every right-hand side of the
+// matrices with active[matrix] != 0: one lane per row of A (values vc in
+// row order, entries in a fixed order), all NR right-hand sides of the
+// matrix at once so every value of A is read once per matrix.  Workgroups
+// of consecutive matrices cover the same rows, so the shared row structure
+// is reused from cache.
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+    const double *__restrict__ vc, int64_t nnzf,
+    const double *__restrict__ B, const double *__restrict__ X, double *__restrict__ Y,
+    int64_t ldb, int64_t n, int nrhs, int r0, int mode, const int32_t *__restrict__ active) {
+    const int b = blockIdx.x;
     if (active && !active[b]) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *v = vals + int64_t(b) * ldv;
-    const double *x = X + int64_t(br) * ldb;
-    double t = 0.0;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) t += v[vidx[e]] * x[col[e]];
-    R[int64_t(br) * ldb + i] = B[int64_t(br) * ldb + i] - t;
+    const double *v = vc + int64_t(b) * nnzf;
+    const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
+    double t[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) t[r] = 0.0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) {
+        const double a = v[e];
+        const int64_t j = col[e];
+#pragma unroll
+        for (int r = 0; r < NR; r++) t[r] += a * X[base + r * ldb + j];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+        Y[base + r * ldb + i] = mode ? B[base + r * ldb + i] - t[r] : t[r];
 }
 
 // Block of vector element i (colblk is null for a plan of one block).
@@ -49,20 +74,19 @@ __device__ inline int seg_of(int br, int nblk, const int32_t *colblk, int64_t i)
 // sum |A_ij|, in 32 slices (partial maxima in part[bk * 32 + slice]), then
 // the max of the slices (the maximum does not depend on the order).
 __global__ __launch_bounds__(256) void k_anorm_part(
-    const int64_t *__restrict__ ptr, const int64_t *__restrict__ vidx,
-    const double *__restrict__ vals, int64_t ldv, const int64_t *__restrict__ col0, int nblk,
-    double *__restrict__ part) {
+    const int64_t *__restrict__ ptr, const double *__restrict__ vc, int64_t nnzf,
+    const int64_t *__restrict__ col0, int nblk, double *__restrict__ part) {
     __shared__ double red[256];
     const int bk = blockIdx.y, slice = blockIdx.x;
     const int b = bk / nblk, k = bk - b * nblk;
     const int64_t r0 = col0[k], nr = col0[k + 1] - r0;
     const int64_t len = (nr + 31) / 32;
     const int64_t i0 = r0 + slice * len, i1 = min(r0 + nr, i0 + len);
-    const double *v = vals + int64_t(b) * ldv;
+    const double *v = vc + int64_t(b) * nnzf;
     double m = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         double s = 0.0;
-        for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) s += fabs(v[vidx[e]]);
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) s += fabs(v[e]);
         m = fmax(m, s);
     }
     red[threadIdx.x] = m;
@@ -220,28 +244,10 @@ __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Y = A X for every system of an active matrix
-__global__ __launch_bounds__(256) void k_spmv(
-    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-    const int64_t *__restrict__ vidx, const double *__restrict__ vals, int64_t ldv,
-    const double *__restrict__ X, double *__restrict__ Y, int64_t ldb, int64_t n, int nrhs,
-    const int32_t *__restrict__ active) {
-    const int br = blockIdx.y;
-    const int b = br / nrhs;
-    if (!active[b]) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double *v = vals + int64_t(b) * ldv;
-    const double *x = X + int64_t(br) * ldb;
-    double t = 0.0;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) t += v[vidx[e]] * x[col[e]];
-    Y[int64_t(br) * ldb + i] = t;
-}
-
 __global__ void k_copy_sys(const double *__restrict__ X, double *__restrict__ Y, int64_t ldb,
                            int64_t n, int nrhs, const int32_t *__restrict__ active) {
     const int br = blockIdx.y;
-    if (!active[br / nrhs]) return;
+    if (active && !active[br / nrhs]) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) Y[int64_t(br) * ldb + i] = X[int64_t(br) * ldb + i];
 }
@@ -287,12 +293,47 @@ __global__ void k_cg_p(double *__restrict__ Pv, const double *__restrict__ Z, in
 
 namespace {
 
+// Algorithmic HBM bytes of the refinement kernels (used for per-launch
+// timing only).  A x over nmat matrices with nrhs vectors each: every value
+// of A (both triangles, row order) once per matrix, the shared column
+// indices and row pointers once, nvec vectors of n per right-hand side.
+double spmv_bytes(const sc_plan *P, double nmat, int nrhs, int nvec) {
+    const double nnz = double(P->csr_ptr[P->n]);
+    return nmat * (8.0 * nnz + double(nrhs) * nvec * 8.0 * double(P->n)) + 4.0 * nnz +
+           8.0 * double(P->n);
+}
+double vec_bytes(const sc_plan *P, double nsys, int nvec) {
+    return nsys * double(P->n) * 8.0 * nvec;
+}
+
+// Y = B - A X (mode 1) or A X (mode 0) for all right-hand sides of the
+// active matrices, up to four right-hand sides per pass.
+void apply_A(const sc_plan *P, const double *vc, const double *B,
+             const double *X, double *Y, int64_t ldb, int batch, int nrhs, int mode,
+             const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const int64_t nnzf = P->csr_ptr[P->n];
+    const dim3 grid(unsigned(batch), unsigned((P->n + 255) / 256));
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int nr = std::min(4, nrhs - r0);
+#define SPCHOL_APPLY(NR)                                                                   \
+    hipLaunchKernelGGL(k_apply<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->csr_col, vc,     \
+                       nnzf, B, X, Y, ldb, P->n, nrhs, r0, mode, active)
+        if (nr == 1) SPCHOL_APPLY(1);
+        else if (nr == 2) SPCHOL_APPLY(2);
+        else if (nr == 3) SPCHOL_APPLY(3);
+        else SPCHOL_APPLY(4);
+#undef SPCHOL_APPLY
+    }
+}
+
 hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                             int64_t ldv, const double *b, double *x, int32_t nrhs,
                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
                             int32_t *nactive_out, hipStream_t st) {
     DevPlan *D = P->dev;
     RefineWs &W = N->rws;
+    Profiler &prof = N->prof;
     const int batch = N->batch, nblk = P->nblk;
     const int nsys = batch * nrhs, nseg = nsys * nblk, per = nrhs * nblk;
     const int64_t n = P->n;
@@ -301,24 +342,28 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
     const dim3 sgrid(unsigned((nseg + 255) / 256));
     hipError_t e;
     // x0 = solve(b)
-    e = hipMemcpy2DAsync(x, ldb * sizeof(double), b, ldb * sizeof(double), n * sizeof(double),
-                         nsys, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, b, x, ldb, n, nrhs, nullptr);
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
                        int32_t(1));
     hipLaunchKernelGGL(k_set_i32, sgrid, dim3(256), 0, st, W.conv, nseg, int32_t(0));
     e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr);
     if (e != hipSuccess) return e;
+    const int64_t nnzf = P->csr_ptr[n];
+    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nnzf + 255) / 256), unsigned(batch)),
+                       dim3(256), 0, st, D->csr_vidx, vals, ldv, nnzf, W.vc);
     hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
-                       D->csr_vidx, vals, ldv, D->blk_col0, nblk, W.part);
+                       W.vc, nnzf, D->blk_col0, nblk, W.part);
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     for (int it = 0;; it++) {
-        hipLaunchKernelGGL(k_resid, vgrid, dim3(256), 0, st, D->csr_ptr, D->csr_col,
-                           D->csr_vidx, vals, ldv, b, x, W.r, ldb, n, nrhs, W.active);
+        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
+        apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st);
+        prof.end(st);
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, 3, ldb,
                            D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
+        prof.end(st);
         hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
                            tol, it, W.active, W.conv, W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
@@ -329,8 +374,10 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
         if (nact == 0 || it >= maxit) break;
         e = spchol_solve_run(P, N, W.r, nrhs, ldb, st, W.active);
         if (e != hipSuccess) return e;
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
         hipLaunchKernelGGL(k_axpy, vgrid, dim3(256), 0, st, x, W.r, ldb, n, nrhs, nblk, colblk,
                            W.active, W.conv);
+        prof.end(st);
     }
     *nactive_out = nact;
     e = hipMemcpyAsync(stat_host, W.stat, sizeof(double) * 6 * nseg, hipMemcpyDeviceToHost, st);
@@ -348,6 +395,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                       int32_t maxit, double *stat_host, int32_t *nactive_out, hipStream_t st) {
     DevPlan *D = P->dev;
     RefineWs &W = N->rws;
+    Profiler &prof = N->prof;
     const int batch = N->batch, nblk = P->nblk;
     const int nsys = batch * nrhs, nseg = nsys * nblk, per = nrhs * nblk;
     const int64_t n = P->n;
@@ -357,24 +405,29 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     const size_t vsz = size_t(nsys) * ldb;
     double *r = W.r, *z = W.r + vsz, *pv = W.r + 2 * vsz, *q = W.r + 3 * vsz, *rt = W.r + 4 * vsz;
     double *rz0 = W.sc, *rz1 = W.sc + nseg, *pq = W.sc + 2 * nseg;
-    hipError_t e = hipMemcpy2DAsync(x, ldb * sizeof(double), b, ldb * sizeof(double),
-                                    n * sizeof(double), nsys, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, b, x, ldb, n, nrhs, nullptr);
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
                        int32_t(1));
     hipLaunchKernelGGL(k_set_i32, sgrid, dim3(256), 0, st, W.conv, nseg, int32_t(0));
     e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr);  // x0 = M^{-1} b
     if (e != hipSuccess) return e;
+    const int64_t nnzf = P->csr_ptr[n];
+    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nnzf + 255) / 256), unsigned(batch)),
+                       dim3(256), 0, st, D->csr_vidx, vals, ldv, nnzf, W.vc);
     hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
-                       D->csr_vidx, vals, ldv, D->blk_col0, nblk, W.part);
+                       W.vc, nnzf, D->blk_col0, nblk, W.part);
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     auto check = [&](int it) -> hipError_t {
-        hipLaunchKernelGGL(k_resid, vgrid, dim3(256), 0, st, D->csr_ptr, D->csr_col,
-                           D->csr_vidx, vals, ldv, b, x, rt, ldb, n, nrhs, W.active);
+        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
+        apply_A(P, W.vc, b, x, rt, ldb, batch, nrhs, 1, W.active, st);
+        prof.end(st);
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, rt, b, x, 3, ldb,
                            D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
+        prof.end(st);
         hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
                            tol, it, W.active, W.conv, W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
@@ -386,37 +439,52 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     };
     // dot products <a, c> of every system into out[seg]
     auto dots = [&](const double *a, const double *c, double *out) {
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, nullptr, 1, ldb,
                            D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
+        prof.end(st);
         hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
                            out);
     };
     e = check(0);
     if (e != hipSuccess) return e;
     if (nact > 0 && maxit > 0) {
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
         hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, rt, r, ldb, n, nrhs, W.active);
+        prof.end(st);
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
         hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, r, z, ldb, n, nrhs, W.active);
+        prof.end(st);
         e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
         if (e != hipSuccess) return e;
         dots(r, z, rz0);
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
         hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, z, pv, ldb, n, nrhs, W.active);
+        prof.end(st);
         double *rz = rz0, *rzn = rz1;
         for (int it = 1; it <= maxit; it++) {
-            hipLaunchKernelGGL(k_spmv, vgrid, dim3(256), 0, st, D->csr_ptr, D->csr_col,
-                               D->csr_vidx, vals, ldv, pv, q, ldb, n, nrhs, W.active);
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st);
+            apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);
+            prof.end(st);
             dots(pv, q, pq);
+            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 6), st);
             hipLaunchKernelGGL(k_cg_xr, vgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
                                nblk, colblk, W.active, W.conv, rz, pq);
+            prof.end(st);
             e = check(it);
             if (e != hipSuccess) return e;
             if (nact == 0 || it == maxit) break;
+            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
             hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, r, z, ldb, n, nrhs,
                                W.active);
+            prof.end(st);
             e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
             if (e != hipSuccess) return e;
             dots(r, z, rzn);
+            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
             hipLaunchKernelGGL(k_cg_p, vgrid, dim3(256), 0, st, pv, z, ldb, n, nrhs, nblk,
                                colblk, W.active, W.conv, rz, rzn);
+            prof.end(st);
             std::swap(rz, rzn);
         }
     }

@@ -289,6 +289,109 @@ __global__ __launch_bounds__(256) void k_bwd_wave(
     }
 }
 
+// Forward step of one level for supernodes with c <= CM rows, one lane per
+// (supernode, matrix, right-hand side): lane-private registers hold the
+// front vector; the right-hand side and the children's update vectors are
+// pulled through the gather map (no shared scatter), and the triangular
+// solve runs in registers (every index a compile-time constant; rows and
+// columns beyond the supernode are masked, their loads clamped in bounds).
+template <typename T, int CM>
+__global__ __launch_bounds__(256) void k_fwd_lane(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ gptr,
+    const int32_t *__restrict__ gidx, const T *__restrict__ L, int64_t Lsize,
+    const double *__restrict__ B, int64_t ldb, double *__restrict__ Y, double *__restrict__ FV,
+    int64_t n, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= nitems) return;
+    const int br = item / nlist;
+    const int b = br / nrhs;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[list[item - br * nlist]];
+    const int c = d.c, w = d.w;
+    const double *bb = B + int64_t(br) * ldb;
+    double *fv = FV + int64_t(br) * fvsize;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    double x[CM];
+#pragma unroll
+    for (int i = 0; i < CM; i++) {
+        double a = 0.0;
+        if (i < c) {
+            if (i < w) a = bb[perm[d.first + i]];
+            const int g1 = gptr[d.rowptr + i + 1];
+            for (int g = gptr[d.rowptr + i]; g < g1; g++) a += fv[gidx[g]];
+        }
+        x[i] = a;
+    }
+    // row by row: x_i -= sum_{j < min(i, w)} L_ij y_j (ascending j), then the
+    // pivot division for the supernode's own columns
+#pragma unroll
+    for (int i = 1; i < CM; i++) {
+        if (i - 1 < w) x[i - 1] /= double(Lb[(i - 1) * c + i - 1]);
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < i; j++) {
+            const bool ok = j < w && i < c;
+            const double l = double(Lb[ok ? j * c + i : 0]);
+            t += ok ? l * x[j] : 0.0;
+        }
+        x[i] -= t;
+    }
+    if (CM - 1 < w) x[CM - 1] /= double(Lb[(CM - 1) * c + CM - 1]);
+    double *y = Y + int64_t(br) * n + d.first;
+#pragma unroll
+    for (int i = 0; i < CM; i++) {
+        if (i < w) y[i] = x[i];
+        else if (i < c) fv[d.rowptr + i] = x[i];
+    }
+}
+
+// Backward step of one level for supernodes with c <= CM rows, one lane per
+// (supernode, matrix, right-hand side): rows below the supernode's columns
+// are read from the solved ancestors, then columns are solved from the
+// last to the first (dot products in ascending row order).
+template <typename T, int CM>
+__global__ __launch_bounds__(256) void k_bwd_lane(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
+    const T *__restrict__ L, int64_t Lsize, double *__restrict__ X, int64_t ldb,
+    double *__restrict__ Y, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= nitems) return;
+    const int br = item / nlist;
+    const int b = br / nrhs;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[list[item - br * nlist]];
+    const int c = d.c, w = d.w;
+    const double *y = Y + int64_t(br) * n;
+    const int32_t *R = rows + d.rowptr;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    double x[CM];
+#pragma unroll
+    for (int i = 0; i < CM; i++) x[i] = i < w ? y[d.first + i] : (i < c ? y[R[i]] : 0.0);
+#pragma unroll
+    for (int j = CM - 1; j >= 0; j--) {
+        asm volatile("" ::: "memory");  // one column of L in flight at a time
+        const bool cj = j < w;
+        double t = 0.0;
+#pragma unroll
+        for (int i = j + 1; i < CM; i++) {
+            const bool ok = cj && i < c;
+            const double l = double(Lb[ok ? j * c + i : 0]);
+            t += ok ? l * x[i] : 0.0;
+        }
+        if (cj) x[j] = (x[j] - t) / double(Lb[j * c + j]);
+    }
+    double *yo = Y + int64_t(br) * n + d.first;
+    double *xo = X + int64_t(br) * ldb;
+#pragma unroll
+    for (int i = 0; i < CM; i++)
+        if (i < w) {
+            yo[i] = x[i];
+            xo[perm[d.first + i]] = x[i];
+        }
+}
+
 // Forward panel p of panel-solved supernodes.  Workgroup 0 writes y_p;
 // workgroup t >= 1 updates rows [c0 + kb + 64 (t-1), +64) of FV_s.
 template <typename T>
@@ -494,6 +597,19 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(gy);
     for (const SLaunch &l : D->ssched) {
+        if (l.nlane > 0) {
+            prof.begin(KK_Fwd, l.f_lane * nr, (l.w_lane * sz * N->batch + l.v_lane * nr), st);
+            const int nitems = l.nlane * nbr;
+            const dim3 g(unsigned((nitems + 255) / 256));
+#define SPCHOL_FWDL(CM)                                                                      \
+    hipLaunchKernelGGL((k_fwd_lane<T, CM>), g, dim3(256), 0, st, D->sn,                       \
+                       D->slv_small + l.lane0, l.nlane, nitems, D->perm, D->gptr, D->gidx, L, \
+                       P->Lsize, b, ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, active)
+            if (l.maxc_lane <= 16) SPCHOL_FWDL(16);
+            else SPCHOL_FWDL(32);
+#undef SPCHOL_FWDL
+            prof.end(st);
+        }
         if (l.nsmall > 0) {
             prof.begin(KK_Fwd, l.f_small * nr, (l.w_small * sz * N->batch + l.v_small * nr), st);
             const int nitems = l.nsmall * N->batch;
@@ -592,6 +708,19 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
             }
             prof.end(st);
         }
+        if (l.nlane > 0) {
+            prof.begin(KK_Bwd, l.f_lane * nr, (l.w_lane * sz * N->batch + l.v_lane * nr), st);
+            const int nitems = l.nlane * nbr;
+            const dim3 g(unsigned((nitems + 255) / 256));
+#define SPCHOL_BWDL(CM)                                                                      \
+    hipLaunchKernelGGL((k_bwd_lane<T, CM>), g, dim3(256), 0, st, D->sn,                       \
+                       D->slv_small + l.lane0, l.nlane, nitems, D->perm, D->rows, L,          \
+                       P->Lsize, b, ldb, N->ws_y, P->n, nrhs, active)
+            if (l.maxc_lane <= 16) SPCHOL_BWDL(16);
+            else SPCHOL_BWDL(32);
+#undef SPCHOL_BWDL
+            prof.end(st);
+        }
     }
     return hipGetLastError();
 }
@@ -627,8 +756,18 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
     for (int32_t l = 0; l < P->nlevels; l++) {
         SLaunch s{};
         s.level = l;
-        s.small0 = P->slv_small_ptr[l];
+        s.lane0 = P->slv_small_ptr[l];
+        s.nlane = P->slv_lane_n[l];
+        s.maxc_lane = P->slv_lane_maxc[l];
+        s.small0 = s.lane0 + s.nlane;
         s.nsmall = P->slv_small_ptr[l + 1] - s.small0;
+        for (int32_t e = s.lane0; e < s.lane0 + s.nlane; e++) {
+            const SnDesc &d = P->sn[P->slv_small[e]];
+            const double lw = double(d.c) * d.w - double(d.w) * (d.w - 1) / 2;
+            s.f_lane += 2.0 * lw;
+            s.w_lane += lw;
+            s.v_lane += 8.0 * (2.0 * d.c + d.m) + 4.0 * d.c;
+        }
         s.pan0 = P->slv_pan_ptr[l];
         s.npan = P->slv_pan_ptr[l + 1] - s.pan0;
         s.maxc_small = P->slv_small_maxc[l];

@@ -135,7 +135,9 @@ def test_group_refinement_per_system(method):
                                   st["relres"], relres[r], err))
                 assert st["clause"] in (1, 2)
                 assert relres[r] <= 1e-10
-                assert abs(st["relres"] - relres[r]) <= 1e-3 * relres[r] + 1e-16
+                # the two residuals differ by the rounding of b - A x in another
+                # summation order, about u ||A|| ||x|| / ||b|| <= 1e-14 here
+                assert abs(st["relres"] - relres[r]) <= 1e-3 * relres[r] + 1e-14
                 assert err <= 1e-10
 
 
