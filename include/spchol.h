@@ -66,6 +66,11 @@ typedef struct {
     int32_t small_front;  /* fronts with at most this many rows run in one
                              workgroup; larger ones use the tiled kernels
                              (0 = library default)                         */
+    int32_t soa_min_batch; /* numeric objects with at least this many
+                             matrices solve in the batch-interleaved layout
+                             (one matrix per lane; L is copied once per
+                             factorization); 0 = library default (off),
+                             a negative value never                         */
 } sc_options;
 
 /* Sizes of a plan (per matrix of a batch). */

@@ -50,7 +50,8 @@ class SpcholError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("relax", ctypes.c_int32), ("relax_cols", ctypes.c_int32),
-                ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32)]
+                ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32),
+                ("soa_min_batch", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

@@ -471,11 +471,8 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         }
 
         // solve schedule and per-supernode solve workspaces
-        P->slv_small_ptr.assign(nlev + 1, 0);
+        P->slv_cls_ptr.assign(size_t(nlev) * kSolveClasses + 1, 0);
         P->slv_pan_ptr.assign(nlev + 1, 0);
-        P->slv_small_maxc.assign(nlev, 0);
-        P->slv_lane_n.assign(nlev, 0);
-        P->slv_lane_maxc.assign(nlev, 0);
         if (int64_t(P->rows.size()) >= INT32_MAX) throw std::bad_alloc();
         P->slv_pan_maxw.assign(nlev, 0);
         P->slv_pan_maxc.assign(nlev, 0);
@@ -483,31 +480,53 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         for (int32_t l = 0; l < nlev; l++) {
             for (int32_t s : bya[l]) {
                 SnDesc &d = P->sn[s];
-                if (solve_by_panels(d)) {
-                    const int64_t np = (d.w + kSolvePanel - 1) / kSolvePanel;
-                    d.dinv = P->dinv_size;
-                    P->dinv_size += np * kSolvePanel * kSolvePanel;
-                    d.part = P->part_size;
-                    P->part_size += ((d.c + kSolveChunk - 1) / kSolveChunk) * kSolvePanel;
-                    P->slv_pan.push_back(s);
-                    P->slv_pan_maxw[l] = std::max(P->slv_pan_maxw[l], d.w);
-                    P->slv_pan_maxc[l] = std::max(P->slv_pan_maxc[l], d.c);
-                    P->npan++;
-                } else if (d.c <= kLaneMaxC) {
-                    P->slv_small.push_back(s);
-                    P->slv_lane_n[l]++;
-                    P->slv_lane_maxc[l] = std::max(P->slv_lane_maxc[l], d.c);
-                }
+                if (!solve_by_panels(d)) continue;
+                const int64_t np = (d.w + kSolvePanel - 1) / kSolvePanel;
+                d.dinv = P->dinv_size;
+                P->dinv_size += np * kSolvePanel * kSolvePanel;
+                d.part = P->part_size;
+                P->part_size += ((d.c + kSolveChunk - 1) / kSolveChunk) * kSolvePanel;
+                P->slv_pan.push_back(s);
+                P->slv_pan_maxw[l] = std::max(P->slv_pan_maxw[l], d.w);
+                P->slv_pan_maxc[l] = std::max(P->slv_pan_maxc[l], d.c);
+                P->npan++;
             }
-            for (int32_t s : bya[l]) {  // the rest of the level's small supernodes
-                const SnDesc &d = P->sn[s];
-                if (!solve_by_panels(d) && d.c > kLaneMaxC) {
-                    P->slv_small.push_back(s);
-                    P->slv_small_maxc[l] = std::max(P->slv_small_maxc[l], d.c);
+            for (int k = 0; k < kSolveClasses; k++) {
+                for (int32_t s : bya[l]) {
+                    const SnDesc &d = P->sn[s];
+                    if (!solve_by_panels(d) && solve_class(d.c) == k) P->slv_small.push_back(s);
                 }
+                P->slv_cls_ptr[size_t(l) * kSolveClasses + k + 1] = int32_t(P->slv_small.size());
             }
-            P->slv_small_ptr[l + 1] = int32_t(P->slv_small.size());
             P->slv_pan_ptr[l + 1] = int32_t(P->slv_pan.size());
+        }
+        // batch-interleaved solve items and the chunks of the L copy
+        P->soa_it_ptr.assign(nlev + 1, 0);
+        P->soa_psize = 0;
+        {
+            std::vector<std::pair<int64_t, int64_t>> iv;
+            for (int32_t l = 0; l < nlev; l++) {
+                for (int32_t e = P->slv_cls_ptr[size_t(l) * kSolveClasses];
+                     e < P->slv_cls_ptr[size_t(l + 1) * kSolveClasses]; e++) {
+                    const int32_t s = P->slv_small[e];
+                    SnDesc &d = P->sn[s];
+                    d.part = P->soa_psize;
+                    for (int32_t r0 = d.w; r0 < d.c; r0 += kSoaRows) {
+                        P->soa_it_s.push_back(s);
+                        P->soa_it_r0.push_back(r0);
+                        P->soa_psize += d.w;
+                    }
+                    iv.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
+                }
+                P->soa_it_ptr[l + 1] = int32_t(P->soa_it_s.size());
+            }
+            std::sort(iv.begin(), iv.end());
+            int64_t covered = 0;  // every scalar below this is already covered
+            for (const auto &q : iv) {
+                int64_t k = std::max(q.first, covered);
+                for (; k < q.second; k += kSoaChunk) P->soa_chunks.push_back(k);
+                covered = std::max(covered, k);
+            }
         }
         // forward-solve gather map (children in chlist order)
         P->gptr.assign(P->rows.size() + 1, 0);

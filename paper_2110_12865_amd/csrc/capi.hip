@@ -15,7 +15,7 @@
 const char *const kKernelNames[KK_Count] = {
     "front_small", "assemble", "potrf", "trsm", "syrk_mfma", "diag_inverse",
     "solve_fwd", "solve_fwd_panel", "solve_bwd", "solve_bwd_panel", "spmv_residual",
-    "refine_vector"};
+    "refine_vector", "solve_permute"};
 
 void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
@@ -38,10 +38,11 @@ hipError_t upload(V **dst, const std::vector<V> &src) {
 void free_devplan(DevPlan *D) {
     if (!D) return;
     void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
-                    D->avidx, D->perm, D->lvl_small, D->lvl_big, D->lvl_sn,
+                    D->avidx, D->perm, D->pinv, D->lvl_small, D->lvl_big, D->lvl_sn,
                     D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
                     D->slv_small, D->slv_pan, D->big_colent, D->big_chmap_off,
-                    D->big_chmap, D->colblk, D->blk_col0, D->gptr, D->gidx};
+                    D->big_chmap, D->colblk, D->blk_col0, D->gptr, D->gidx,
+                    D->soa_it_s, D->soa_it_r0, D->soa_chunks};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete D;
@@ -69,6 +70,7 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->aoff, P->aoff);
     if (e == hipSuccess) e = upload(&D->avidx, P->avidx);
     if (e == hipSuccess) e = upload(&D->perm, P->perm);
+    if (e == hipSuccess) e = upload(&D->pinv, P->pinv);
     if (e == hipSuccess) e = upload(&D->lvl_small, P->lvl_small);
     if (e == hipSuccess) e = upload(&D->lvl_big, P->lvl_big);
     if (e == hipSuccess) e = upload(&D->lvl_sn, P->lvl_sn);
@@ -84,6 +86,9 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->colblk, P->colblk);
     if (e == hipSuccess) e = upload(&D->gptr, P->gptr);
     if (e == hipSuccess) e = upload(&D->gidx, P->gidx);
+    if (e == hipSuccess) e = upload(&D->soa_it_s, P->soa_it_s);
+    if (e == hipSuccess) e = upload(&D->soa_it_r0, P->soa_it_r0);
+    if (e == hipSuccess) e = upload(&D->soa_chunks, P->soa_chunks);
     if (e == hipSuccess) e = upload(&D->blk_col0, P->blk_col0);
     if (e != hipSuccess) {
         free_devplan(D);
@@ -102,18 +107,20 @@ sc_status map_err(hipError_t e) {
     return SC_EDEVICE;
 }
 
-// Solve workspaces for nrhs right-hand sides per matrix.
+// Solve workspaces for nrhs right-hand sides per matrix (rounded up to
+// whole groups of 64 matrices in the batch-interleaved form).
 hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
     if (nrhs <= N->ws_nrhs) return hipSuccess;
-    void *old[] = {N->ws_y, N->ws_u, N->ws_part, N->ws_cnt};
+    void *old[] = {N->ws_y, N->ws_u, N->ws_part, N->ws_ps};
     for (void *q : old)
         if (q) (void)hipFree(q);
     N->ws_y = nullptr;
     N->ws_u = nullptr;
     N->ws_part = nullptr;
-    N->ws_cnt = nullptr;
+    N->ws_ps = nullptr;
     N->ws_nrhs = 0;
-    const size_t cnt = size_t(N->batch) * nrhs;
+    const size_t nb = N->soa ? size_t((N->batch + 63) / 64) * 64 : size_t(N->batch);
+    const size_t cnt = nb * nrhs;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&N->ws_y),
                              std::max<size_t>(cnt * P->n * sizeof(double), 8));
     if (e == hipSuccess)
@@ -122,9 +129,9 @@ hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&N->ws_part),
                       std::max<size_t>(cnt * P->part_size * sizeof(double), 8));
-    const size_t cbytes = std::max<size_t>(cnt * P->npan * sizeof(int32_t), 8);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&N->ws_cnt), cbytes);
-    if (e == hipSuccess) e = hipMemset(N->ws_cnt, 0, cbytes);
+    if (e == hipSuccess && N->soa)
+        e = hipMalloc(reinterpret_cast<void **>(&N->ws_ps),
+                      std::max<size_t>(cnt * P->soa_psize * sizeof(double), 8));
     if (e == hipSuccess) N->ws_nrhs = nrhs;
     return e;
 }
@@ -190,6 +197,7 @@ sc_status sc_options_default(sc_options *opt) {
     opt->relax_cols = 4;
     opt->relax_zeros = 0.05;
     opt->small_front = 64;
+    opt->soa_min_batch = kSoaMinBatch;
     return SC_OK;
 }
 
@@ -341,6 +349,8 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
     N->batch = batch;
     N->dtype = dtype;
     N->device = P->dev_id;
+    const int32_t soa_min = P->opt.soa_min_batch == 0 ? kSoaMinBatch : P->opt.soa_min_batch;
+    N->soa = soa_min > 0 && batch >= soa_min;
     const size_t sz = dtype == SC_F64 ? 8 : 4;
     hipError_t e = hipMalloc(&N->L, std::max<size_t>(size_t(batch) * P->Lsize * sz, 8));
     if (e == hipSuccess) e = hipMalloc(&N->U, std::max<size_t>(size_t(batch) * P->Usize * sz, 8));
@@ -352,6 +362,8 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&N->dinv),
                       std::max<size_t>(size_t(batch) * P->dinv_size * sizeof(double), 8));
+    if (e == hipSuccess && N->soa)
+        e = hipMalloc(&N->Ls, std::max<size_t>(size_t((batch + 63) / 64) * 64 * P->Lsize * sz, 8));
     if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * ninfo);
     if (e != hipSuccess) {
         sc_numeric_destroy(N);
@@ -366,7 +378,7 @@ void sc_numeric_destroy(sc_numeric_t *N) {
     if (N->L) (void)hipFree(N->L);
     if (N->U) (void)hipFree(N->U);
     if (N->info) (void)hipFree(N->info);
-    void *ws[] = {N->pinv, N->dinv, N->ws_y, N->ws_u, N->ws_part, N->ws_cnt};
+    void *ws[] = {N->pinv, N->dinv, N->ws_y, N->ws_u, N->ws_part, N->ws_ps, N->Ls};
     for (void *q : ws)
         if (q) (void)hipFree(q);
     free_refine_ws(N->rws);

@@ -35,20 +35,32 @@ struct FLaunch {
 
 struct SPanel {  // one 64-column panel step of a level's panel-solved supernodes
     int64_t fwd_tiles = 0;   // 64-row tiles below the panel (max over supernodes)
-    int64_t bwd_chunks = 0;  // row chunks of the backward step (max, >= 1)
+    int64_t bwd_chunks = 0;  // kSolveChunk-row chunks below the panel (max)
     double flops = 0.0;      // per right-hand side
     double words = 0.0;      // factor scalars read per right-hand side
-    double vbytes = 0.0;     // vector and inverse-block bytes per right-hand side
+    double vbytes = 0.0;     // vector bytes per right-hand side
+    double dbytes = 0.0;     // inverse-block bytes per matrix
+};
+
+struct SClass {  // supernodes of one row class in one level
+    int32_t list0 = 0, n = 0;  // entries of slv_small
+    double flops = 0.0;        // per right-hand side
+    double words = 0.0;        // factor scalars read
+    double vbytes = 0.0;       // vector and index bytes per right-hand side
 };
 
 struct SLaunch {  // one level of a triangular solve
     int32_t level = 0;
-    int32_t lane0 = 0, nlane = 0, maxc_lane = 0;  // supernodes solved one per lane
-    double f_lane = 0.0, w_lane = 0.0, v_lane = 0.0;
-    int32_t small0 = 0, nsmall = 0;  // supernodes solved one per wave
+    SClass cls[kSolveClasses];
+    // batch-interleaved form: all supernodes of the level not solved by
+    // panels, and their row-block items
+    int32_t all0 = 0, nall = 0;
+    int32_t it0 = 0, nit = 0;
+    double f_diag = 0.0, w_diag = 0.0, v_diag = 0.0;  // diagonal blocks
+    double f_rows = 0.0, w_rows = 0.0, v_rows = 0.0;  // rows below them
     int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
-    int32_t maxc_small = 0, maxc_pan = 0, maxc = 0;
-    double f_small = 0.0, w_small = 0.0, v_small = 0.0, v_pan = 0.0;
+    int32_t maxc_pan = 0;
+    double v_pan = 0.0;
     std::vector<SPanel> panels;
 };
 
@@ -61,6 +73,7 @@ struct DevPlan {
     int32_t *aoff = nullptr;
     int64_t *avidx = nullptr;
     int32_t *perm = nullptr;
+    int32_t *pinv = nullptr;
     int32_t *lvl_small = nullptr;
     int32_t *lvl_big = nullptr;
     int32_t *lvl_sn = nullptr;
@@ -73,6 +86,9 @@ struct DevPlan {
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int32_t *csr_col = nullptr;
     int64_t *csr_vidx = nullptr;
+    int32_t *soa_it_s = nullptr;      // batch-interleaved solve items
+    int32_t *soa_it_r0 = nullptr;
+    int64_t *soa_chunks = nullptr;    // chunk starts of the interleaved L copy
     int32_t *gptr = nullptr;          // forward-solve gather map
     int32_t *gidx = nullptr;
     int32_t *colblk = nullptr;        // block of every column
@@ -84,7 +100,7 @@ struct DevPlan {
 // Kernel kinds for per-launch timing.
 enum KernelKind : int {
     KK_SmallFront = 0, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk, KK_Dinv,
-    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Spmv, KK_Vec, KK_Count
+    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Spmv, KK_Vec, KK_Perm, KK_Count
 };
 extern const char *const kKernelNames[KK_Count];
 
@@ -146,11 +162,18 @@ struct sc_numeric {
     int32_t *info = nullptr; // batch
     void *pinv = nullptr;    // batch * max_lvl_big * 64 * 64: panel inverses (factor)
     double *dinv = nullptr;  // batch * dinv_size: inverted diagonal blocks
-    double *ws_y = nullptr;  // batch * nrhs * n: y, then z (permuted)
-    double *ws_u = nullptr;  // batch * nrhs * sum(c_s): front vectors
+    // solve workspaces, right-hand sides interleaved (index * nrhs + r)
+    double *ws_y = nullptr;  // batch * n * nrhs: P b, then y, then z
+    double *ws_u = nullptr;  // batch * sum(c_s) * nrhs: front vectors
     double *ws_part = nullptr;  // batch * nrhs * part_size
-    int32_t *ws_cnt = nullptr;  // npan * batch * nrhs arrival counters
     int32_t ws_nrhs = 0;
+    // batch-interleaved solves (batch >= soa_min): L copied to groups of 64
+    // matrices with the matrix index fastest, refreshed after each factor;
+    // the vectors above then use the same interleaving
+    bool soa = false;
+    void *Ls = nullptr;         // ceil(batch / 64) * Lsize * 64 scalars
+    bool ls_ok = false;
+    double *ws_ps = nullptr;    // ceil(batch / 64) * 64 * soa_psize * nrhs partial sums
     Profiler prof;
     RefineWs rws;
 };

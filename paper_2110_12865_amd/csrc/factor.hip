@@ -346,87 +346,93 @@ __global__ __launch_bounds__(256) void k_assemble_wave(
 }
 
 // Factor and invert the kb x kb diagonal block (kb <= 64) whose top-left
-// corner is (r0, r0) in a column-major L block, with one wave (lanes 0..63
-// of the calling workgroup; other lanes must not call).  Lane i keeps row i
-// in registers (loops fully unrolled); each pivot column is broadcast
-// through LDS.  The factor is written back (zeros above the diagonal); the
-// inverse X = L^{-1} is formed column by column (lane c owns column c) and
-// stored column-major in PIg (PIg[c * 64 + i] = X[i][c]).  Ls holds
-// 64 x 65 + 64 scalars.  A pivot that fails d > 0 is recorded (smallest
-// 1-based step wins) and replaced by 1.
-template <typename T>
-__device__ inline T lane_bcast(T v, int src);
-template <>
-__device__ inline double lane_bcast<double>(double v, int src) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
-    const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                                (static_cast<unsigned int>(lo)));
-}
-template <>
-__device__ inline float lane_bcast<float>(float v, int src) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
-}
+// corner is (r0, r0) of a column-major L block, with one workgroup of 256
+// threads.  The block sits in LDS (S, row-major, stride 65) next to the
+// inverse X = L^{-1} (X, same layout), built in the same sweep: step j
+// scales column j of L by 1 / L_jj and row j of X by the same, then
+// subtracts L_ij L_tj from the trailing entries (i >= t > j) and L_ij X_jc
+// from the rows i > j of X.  Thread (lane, wave g) owns row `lane` for the
+// trailing update and column `lane` of X, columns / rows congruent to g
+// mod 4.  The loops are not unrolled: the kernel body stays far below the
+// instruction cache.  The factor is written back (zeros above the
+// diagonal) and the inverse to PIg column-major (PIg[c * 64 + i] = X[i][c]).
+// A pivot that fails d > 0 is recorded (smallest 1-based step wins) and
+// replaced by 1.
+constexpr int kDiagLd = kTile + 1;
+constexpr int kDiagLds = 2 * kTile * kDiagLd + kTile;  // S, X, diagonal
 
 template <typename T>
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T>
-__device__ void wave_diag_factor(T *Lb, int c, int r0, int kb, T *Ls, T *PIg, int col0,
-                                 int32_t *info_b) {
-    const int lane = threadIdx.x & 63;
-    constexpr int LD = kTile + 1;
-    T *cb = Ls + kTile * LD;  // broadcast buffer for the current column
-    T a[kTile];
+__device__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, int col0,
+                               int32_t *info_b) {
+    T *S = lds, *X = lds + kTile * kDiagLd, *dg = lds + 2 * kTile * kDiagLd;
+    const int tid = threadIdx.x, li = tid & 63, g = tid >> 6;
+    {
+        // 16 loads per thread in flight at once (consecutive threads: rows)
+        T v[16];
 #pragma unroll
-    for (int t = 0; t < kTile; t++)
-        a[t] = (t < kb && lane < kb) ? Lb[int64_t(r0 + t) * c + r0 + lane] : (lane == t ? T(1) : T(0));
-    // Right-looking.  Entries above the diagonal (lane < t) are updated too
-    // and never read back into the lower triangle; they are dropped below.
+        for (int q = 0; q < 16; q++) {
+            const int e = tid + 256 * q, t = e >> 6, i = e & 63;
+            v[q] = (i < kb && t < kb) ? Lb[int64_t(r0 + t) * c + r0 + i] : (i == t ? T(1) : T(0));
+        }
 #pragma unroll
-    for (int j = 0; j < kTile; j++) {
-        if (j < kb) {
-            T djj = lane_bcast(a[j], j);
-            const bool bad = !(djj > T(0));
-            if (bad) djj = T(1);
-            const T ljj = dsqrt(djj);
-            const T rinv = T(1) / ljj;
-            if (lane == j && bad) atomicMin(info_b, col0 + j + 1);
-            a[j] = lane == j ? ljj : a[j] * rinv;
-            cb[lane] = a[j];
-            wave_sync<T>();
-#pragma unroll
-            for (int t = j + 1; t < kTile; t++) a[t] -= a[j] * cb[t];
-            wave_sync<T>();
+        for (int q = 0; q < 16; q++) {
+            const int e = tid + 256 * q, t = e >> 6, i = e & 63;
+            S[i * kDiagLd + t] = v[q];
+            X[i * kDiagLd + t] = i == t ? T(1) : T(0);
         }
     }
+    __syncthreads();
+    for (int j = 0; j < kb; j++) {
+        T djj = S[j * kDiagLd + j];
+        const bool bad = !(djj > T(0));
+        if (bad) djj = T(1);
+        const T ljj = dsqrt(djj);
+        const T rinv = T(1) / ljj;
+        // S[j][j] itself is never overwritten (the diagonal goes to dg), so
+        // no barrier is needed between its reads and the writes below
+        if (g == 0) {
+            if (li == j) {
+                dg[j] = ljj;
+                if (bad) atomicMin(info_b, col0 + j + 1);
+            } else if (li > j && li < kb) {
+                S[li * kDiagLd + j] *= rinv;
+            }
+        } else if (g == 1) {
+            X[j * kDiagLd + li] *= rinv;  // row j of X is final
+        }
+        __syncthreads();
+        // all reads of a step are issued before its writes (the updated
+        // entries and the operands are disjoint), 16 entries per thread
+        {
+            const bool rowok = li > j && li < kb, colok = li <= j;
+            const T lij = rowok ? S[li * kDiagLd + j] : T(0);
+            const T xj = colok ? X[j * kDiagLd + li] : T(0);
+            T sv[16], sc[16], xv[16], xc[16];
 #pragma unroll
-    for (int t = 0; t < kTile; t++) {
-        if (t < kb && lane < kb) Lb[int64_t(r0 + t) * c + r0 + lane] = lane >= t ? a[t] : T(0);
-        Ls[lane * LD + t] = lane >= t ? a[t] : T(0);
+            for (int q = 0; q < 16; q++) {
+                const int t = j + 1 + g + 4 * q;
+                const bool ok = rowok && t <= li, okx = colok && t < kb;
+                sv[q] = ok ? S[li * kDiagLd + t] : T(0);
+                sc[q] = ok ? S[t * kDiagLd + j] : T(0);
+                xv[q] = okx ? X[t * kDiagLd + li] : T(0);
+                xc[q] = okx ? S[t * kDiagLd + j] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int t = j + 1 + g + 4 * q;
+                if (rowok && t <= li) S[li * kDiagLd + t] = sv[q] - lij * sc[q];
+                if (colok && t < kb) X[t * kDiagLd + li] = xv[q] - xc[q] * xj;
+            }
+        }
+        __syncthreads();
     }
-    wave_sync<T>();
-    // X = L^{-1}: lane c owns column c; rows of L are LDS broadcasts.
-    T x[kTile];
-#pragma unroll
-    for (int i = 0; i < kTile; i++) {
-        T sum = lane == i ? T(1) : T(0);
-#pragma unroll
-        for (int t = 0; t < i; t++) sum -= Ls[i * LD + t] * x[t];
-        x[i] = sum * (T(1) / Ls[i * LD + i]);
+#pragma unroll 4
+    for (int q = 0; q < 16; q++) {
+        const int e = tid + 256 * q, t = e >> 6, i = e & 63;
+        if (i < kb && t < kb)
+            Lb[int64_t(r0 + t) * c + r0 + i] = i > t ? S[i * kDiagLd + t] : (i == t ? dg[t] : T(0));
+        PIg[e] = (i < kb && t < kb && i >= t) ? X[i * kDiagLd + t] : T(0);
     }
-    wave_sync<T>();
-    // column-major inverse through an LDS transpose: PIg[col * 64 + i] = X[i][col]
-#pragma unroll
-    for (int i = 0; i < kTile; i++) Ls[lane * LD + i] = (lane < kb && i < kb) ? x[i] : T(0);
-    wave_sync<T>();
-#pragma unroll 8
-    for (int col = 0; col < kTile; col++) PIg[col * kTile + lane] = Ls[col * LD + lane];
 }
 
 // C[j][i] += sum_t sA[t][j] * sB[t][i] for the wave's 32 x 32 quadrant of a
@@ -473,13 +479,14 @@ __device__ inline void tile_pos(int a, int q, int r, int &j, int &i) {
 }
 
 // Diagonal block of panel k of each large front: factor and invert (one
-// wave per front).
+// workgroup per front and matrix).
 template <typename T>
-__global__ __launch_bounds__(64) void k_potrf(
+__global__ __launch_bounds__(256) void k_potrf(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
     T *__restrict__ L, int64_t Lsize, T *__restrict__ PI, int64_t pistride,
     int32_t *__restrict__ info, int nblk) {
-    __shared__ T Ls[kTile * (kTile + 1) + kTile];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
     const SnDesc d = sn[s];
@@ -487,8 +494,8 @@ __global__ __launch_bounds__(64) void k_potrf(
     const int kb = min(kTile, d.w - k);
     T *Lb = L + int64_t(b) * Lsize + d.loff;
     T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.x) * kTile * kTile;
-    wave_diag_factor(Lb, d.c, k, kb, Ls, PIg, d.first - d.bcol0 + k,
-                     info + int64_t(b) * nblk + d.blk);
+    wg_diag_factor(Lb, d.c, k, kb, lds, PIg, d.first - d.bcol0 + k,
+                   info + int64_t(b) * nblk + d.blk);
 }
 
 // Panel rows below the diagonal block: X <- X L_kk^{-T} = X (L_kk^{-1})^T,
@@ -659,6 +666,8 @@ void set_lds_limits(int big) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_wave<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_potrf<T>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 // Flops of the partial factorization of the first w columns of a c-row
@@ -818,7 +827,8 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
             break;
         }
         case FLaunch::Potrf:
-            hipLaunchKernelGGL(k_potrf<T>, dim3(unsigned(f.gridx), B), dim3(64), 0, st,
+            hipLaunchKernelGGL(k_potrf<T>, dim3(unsigned(f.gridx), B), dim3(256),
+                               size_t(kDiagLds) * sizeof(T), st,
                                D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize, PI, pistride,
                                N->info, P->nblk);
             break;
@@ -861,6 +871,7 @@ hipError_t spchol_kernels_init() {
 
 hipError_t spchol_factor_run(const sc_plan *P, sc_numeric *N, const double *vals,
                              int64_t ldv, hipStream_t st) {
+    N->ls_ok = false;  // the interleaved copy of L is stale from here on
     if (N->dtype == SC_F64) return factor_impl<double>(P, N, vals, ldv, st);
     return factor_impl<float>(P, N, vals, ldv, st);
 }

@@ -34,9 +34,25 @@ static_assert(sizeof(SnDesc) == 88, "SnDesc layout");
 // is wide or tall; otherwise one workgroup solves it out of LDS.
 constexpr int kSolvePanel = 64;
 constexpr int kSolveChunk = 256;  // rows per workgroup in the backward panel step
-// Supernodes with at most this many rows are solved one per lane.
-constexpr int kLaneMaxC = 32;
+// Supernodes that are not solved by panels fall into row classes; a class
+// fixes the number of lanes that cooperate on one (supernode, matrix) and
+// the rows each lane keeps: c <= 16 and c <= 32 use 16 and 32 lanes (several
+// supernodes per wave), the others one wave with 1, 2, 4 or 8 rows per lane.
+constexpr int kSolveClasses = 6;
+constexpr int kSolveClassMaxC[kSolveClasses] = {16, 32, 64, 128, 256, 512};
+inline int solve_class(int c) {
+    int k = 0;
+    while (k + 1 < kSolveClasses && c > kSolveClassMaxC[k]) k++;
+    return k;
+}
 inline bool solve_by_panels(const SnDesc &d) { return d.w > kSolvePanel || d.c > 512; }
+// Batch-interleaved solves (groups of 64 matrices, one matrix per lane):
+// rows below a supernode's diagonal block are cut into blocks of kSoaRows
+// rows, one work item each; L is copied to the interleaved layout in
+// chunks of kSoaChunk scalars.
+constexpr int kSoaRows = 64;
+constexpr int kSoaChunk = 128;
+constexpr int kSoaMinBatch = -1;  // default of sc_options::soa_min_batch (off)
 
 struct DevPlan;  // device copies, defined by the HIP side
 
@@ -98,15 +114,22 @@ struct sc_plan {
     std::vector<int32_t> lvl_ptr, lvl_sn;  // all supernodes of each level
     std::vector<int32_t> lvl_maxc;
     // solve schedule: per level, supernodes solved in LDS and by panels
-    std::vector<int32_t> slv_small_ptr, slv_small, slv_pan_ptr, slv_pan;
-    std::vector<int32_t> slv_small_maxc, slv_pan_maxw, slv_pan_maxc;
-    // the first slv_lane_n[l] entries of a level's slv_small list have at
-    // most kLaneMaxC rows (solved one per lane); slv_small_maxc covers the rest
-    std::vector<int32_t> slv_lane_n, slv_lane_maxc;
+    // slv_small holds the level's other supernodes by row class: class k of
+    // level l is slv_small[slv_cls_ptr[l * kSolveClasses + k] ..
+    // slv_cls_ptr[l * kSolveClasses + k + 1]), supernodes ascending
+    std::vector<int32_t> slv_cls_ptr, slv_small, slv_pan_ptr, slv_pan;
+    std::vector<int32_t> slv_pan_maxw, slv_pan_maxc;
     // forward-solve gather map: the update-vector entries of the children
     // that land in row i of supernode s are FV[gidx[g]] for g in
     // [gptr[rowptr_s + i], gptr[rowptr_s + i + 1]), children in order
     std::vector<int32_t> gptr, gidx;
+    // batch-interleaved solves: per level, the row blocks (supernode, first
+    // row) of the supernodes not solved by panels; the partial sums of a
+    // supernode's row blocks start at its SnDesc::part (w per block);
+    // chunk starts of the L copy
+    std::vector<int32_t> soa_it_ptr, soa_it_s, soa_it_r0;
+    int64_t soa_psize = 0;
+    std::vector<int64_t> soa_chunks;
     int64_t dinv_size = 0;   // scalars of inverted diagonal blocks
     int64_t part_size = 0;   // partial sums per right-hand side
     int32_t npan = 0;        // supernodes solved by panels

@@ -25,6 +25,7 @@
 namespace {
 
 constexpr int kP = kSolvePanel;
+constexpr int kMaxRhsPanel = 4;  // right-hand sides per pass of the panel gather
 
 // Inverse of every 64x64 diagonal block of every panel-solved supernode:
 // X = L_pp^{-1} by forward substitution, one lane per column of X kept in
@@ -67,398 +68,351 @@ __global__ __launch_bounds__(64) void k_dinv(
     for (int col = 0; col < kP; col++) D[col * kP + lane] = Lp[col * (kP + 1) + lane];
 }
 
-// Gather of the right-hand side and the children's update vectors into
-// FV_s for the panel-solved supernodes of a level (their triangular solve
-// runs in k_fwd_panel).  Item = (supernode, matrix and right-hand side).
-__global__ __launch_bounds__(256) void k_fwd_gather(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ relmap,
-    const int32_t *__restrict__ chlist, const double *__restrict__ B, int64_t ldb,
-    double *__restrict__ FV, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *v = reinterpret_cast<double *>(smem_raw);
-    const int s = list[blockIdx.x];
-    const int br = blockIdx.y;
-    const int b = br / nrhs;
-    if (active && !active[b]) return;
-    const SnDesc d = sn[s];
-    const int c = d.c, w = d.w;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const double *bb = B + int64_t(br) * ldb;
-    double *fvb = FV + int64_t(br) * fvsize;
-
-    for (int i = tid; i < c; i += nt) v[i] = i < w ? bb[perm[d.first + i]] : 0.0;
-    for (int q = d.chbeg; q < d.chend; q++) {
-        const SnDesc cd = sn[chlist[q]];
-        const int32_t *rm = relmap + cd.relptr;
-        const double *uc = fvb + cd.rowptr + cd.w;
-        __syncthreads();
-        for (int i = tid; i < cd.m; i += nt) v[rm[i]] += uc[i];
-    }
-    __syncthreads();
-    for (int i = tid; i < c; i += nt) fvb[d.rowptr + i] = v[i];
-}
-
 __device__ inline void wave_sync_solve() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline double bcast_lane(double v, int src) {
-    const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
-    const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) |
-                                (static_cast<unsigned int>(lo)));
+// Value of lane `src` of the calling lane's segment of G lanes (a segment
+// lies inside one wave; G == 64 is the whole wave and src is then uniform).
+template <int G>
+__device__ inline double seg_bcast(double v, int src) {
+    if constexpr (G == 64) {
+        const long long u = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
+        const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
+        return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                    (static_cast<unsigned int>(lo)));
+    } else {
+        return __shfl(v, src, G);
+    }
 }
 
-constexpr int kWaveSlots = 8;  // rows per lane: c <= 512 for wave-solved supernodes
+// Ys[(b n + k) nrhs + r] = B[(b nrhs + r) ldb + perm[k]]: the permuted
+// right-hand sides, interleaved so that one row of every right-hand side is
+// one contiguous record.
+__global__ __launch_bounds__(256) void k_perm_in(
+    const int32_t *__restrict__ perm, const double *__restrict__ B, int64_t ldb,
+    double *__restrict__ Ys, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t src = perm[k];
+    double *dst = Ys + (int64_t(b) * n + k) * nrhs;
+    for (int r = 0; r < nrhs; r++) dst[r] = B[(int64_t(b) * nrhs + r) * ldb + src];
+}
 
-// Forward step of one level for supernodes solved by one wave each (w <= 64,
-// c <= 512), NR right-hand sides of one matrix at a time: the right-hand
-// side and the children's update vectors are gathered in LDS, then lane i
-// keeps rows i + 64k in registers and the pivot value is broadcast with
-// readlane.  Item = (supernode, matrix); four waves per workgroup.
-template <typename T, int NR, int SL>
-__global__ __launch_bounds__(256) void k_fwd_wave(
+// X[(b nrhs + r) ldb + i] = Ys[(b n + pinv[i]) nrhs + r]: writes in the
+// caller's order (coalesced), reads gathered.
+__global__ __launch_bounds__(256) void k_perm_out(
+    const int32_t *__restrict__ pinv, const double *__restrict__ Ys, double *__restrict__ X,
+    int64_t ldb, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *src = Ys + (int64_t(b) * n + pinv[i]) * nrhs;
+    for (int r = 0; r < nrhs; r++) X[(int64_t(b) * nrhs + r) * ldb + i] = src[r];
+}
+
+// Forward step of one level for the supernodes of one row class: a segment
+// of G lanes per (supernode, matrix), lane i keeping rows i + G k (k < SL),
+// right-hand sides r0 .. r0 + NR - 1.
+//   gather    row i of the front vector: the right-hand side (i < w) plus
+//             the children's update entries landing on row i (gather map,
+//             children in order);
+//   triangle  the w x w diagonal block by columns: the owner of column j
+//             scales by 1 / L_jj and its value is broadcast in the segment;
+//   update    rows i >= w subtract L_ij y_j (ascending j), y read from LDS,
+//             L's columns read by consecutive lanes (coalesced).
+// Requires w <= G (w <= 64 for G == 64) and c <= G * SL.
+template <typename T, int G, int SL, int NR>
+__global__ __launch_bounds__(256) void k_fwd_seg(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
-    int r0, const int32_t *__restrict__ perm, const int32_t *__restrict__ relmap,
-    const int32_t *__restrict__ chlist, const T *__restrict__ L, int64_t Lsize,
-    const double *__restrict__ B, int64_t ldb, double *__restrict__ Y,
-    double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs, int cmax,
-    const int32_t *__restrict__ active) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + wv;
+    int r0, const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const T *__restrict__ L, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
+    int64_t n, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
+    constexpr int NSEG = 256 / G;
+    constexpr int WM = G < 64 ? G : 64;  // widest supernode of the class
+    __shared__ double ys[NSEG][WM][NR];
+    const int tid = threadIdx.x, seg = tid / G, li = tid % G;
+    const int item = blockIdx.x * NSEG + seg;
     if (item >= nitems) return;
-    const int s = list[item % nlist];
     const int b = item / nlist;
     if (active && !active[b]) return;
-    double *v = reinterpret_cast<double *>(smem_raw) + size_t(wv) * NR * cmax;
-    const SnDesc d = sn[s];
+    const SnDesc d = sn[list[item - b * nlist]];
     const int c = d.c, w = d.w;
-    const int br0 = b * nrhs + r0;
-#pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const double *bb = B + int64_t(br0 + r) * ldb;
-        for (int i = lane; i < c; i += 64) v[r * cmax + i] = i < w ? bb[perm[d.first + i]] : 0.0;
-    }
-    for (int q = d.chbeg; q < d.chend; q++) {
-        const SnDesc cd = sn[chlist[q]];
-        const int32_t *rm = relmap + cd.relptr;
-        wave_sync_solve();
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            const double *uc = FV + int64_t(br0 + r) * fvsize + cd.rowptr + cd.w;
-            for (int i = lane; i < cd.m; i += 64) v[r * cmax + rm[i]] += uc[i];
-        }
-    }
-    wave_sync_solve();
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    const double *yb = Ys + int64_t(b) * n * nrhs + r0;
+    const double *fb = FV + int64_t(b) * fvsize * nrhs + r0;
+
     double x[SL][NR];
 #pragma unroll
-    for (int k = 0; k < SL; k++)
+    for (int k = 0; k < SL; k++) {
+        const int i = li + G * k;
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            const int i = lane + 64 * k;
-            x[k][r] = i < c ? v[r * cmax + i] : 0.0;
-        }
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    for (int j0 = 0; j0 < w; j0 += 8) {
-        // eight columns of L in flight at once
-        T lc[8][SL];
+        for (int r = 0; r < NR; r++) x[k][r] = 0.0;
+        if (i < c) {
+            if (i < w) {
 #pragma unroll
-        for (int jj = 0; jj < 8; jj++)
-#pragma unroll
-            for (int k = 0; k < SL; k++) {
-                const int i = lane + 64 * k;
-                lc[jj][k] = (j0 + jj < w && i < c) ? Lb[int64_t(j0 + jj) * c + i] : T(0);
+                for (int r = 0; r < NR; r++) x[k][r] = yb[int64_t(d.first + i) * nrhs + r];
             }
+            const int g1 = gptr[d.rowptr + i + 1];
+            for (int g = gptr[d.rowptr + i]; g < g1; g++) {
+                const double *u = fb + int64_t(gidx[g]) * nrhs;
+#pragma unroll
+                for (int r = 0; r < NR; r++) x[k][r] += u[r];
+            }
+        }
+    }
+    // diagonal block (rows < w live in slot 0)
+    const double rinv = li < w ? 1.0 / double(Lb[li * c + li]) : 0.0;
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        T lc[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) {
+            const int j = j0 + jj;
+            lc[jj] = (j < w && li > j && li < w) ? Lb[j * c + li] : T(0);
+        }
 #pragma unroll
         for (int jj = 0; jj < 8; jj++) {
             const int j = j0 + jj;
             if (j < w) {
-                const double ljj = bcast_lane(double(lc[jj][0]), j);
-                double yj[NR];
+                double y[NR];
 #pragma unroll
-                for (int r = 0; r < NR; r++) yj[r] = bcast_lane(x[0][r], j) / ljj;
-                if (lane == j) {
+                for (int r = 0; r < NR; r++) y[r] = seg_bcast<G>(x[0][r] * rinv, j);
+                if (li == j) {
 #pragma unroll
-                    for (int r = 0; r < NR; r++) x[0][r] = yj[r];
-                }
+                    for (int r = 0; r < NR; r++) x[0][r] = y[r];
+                } else if (li > j && li < w) {
+                    const double l = double(lc[jj]);
 #pragma unroll
-                for (int k = 0; k < SL; k++) {
-                    const int i = lane + 64 * k;
-                    if (i > j && i < c) {
-                        const double l = double(lc[jj][k]);
-#pragma unroll
-                        for (int r = 0; r < NR; r++) x[k][r] -= l * yj[r];
-                    }
+                    for (int r = 0; r < NR; r++) x[0][r] -= l * y[r];
                 }
             }
         }
     }
+    if (li < w) {
+        double *yo = Ys + (int64_t(b) * n + d.first + li) * nrhs + r0;
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        double *y = Y + int64_t(br0 + r) * n;
-        double *fv = FV + int64_t(br0 + r) * fvsize + d.rowptr;
-#pragma unroll
-        for (int k = 0; k < SL; k++) {
-            const int i = lane + 64 * k;
-            if (i < w) y[d.first + i] = x[k][r];
-            else if (i < c) fv[i] = x[k][r];
+        for (int r = 0; r < NR; r++) {
+            ys[seg][li][r] = x[0][r];
+            yo[r] = x[0][r];
         }
     }
-}
-
-// Backward step of one level for wave-solved supernodes: lane i keeps rows
-// i + 64k of the solution; each column's dot product is a wave reduction
-// (fixed butterfly order) and the lane owning the pivot row applies it.
-template <typename T, int NR, int SL>
-__global__ __launch_bounds__(256) void k_bwd_wave(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
-    int r0, const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
-    const T *__restrict__ L, int64_t Lsize, double *__restrict__ X, int64_t ldb,
-    double *__restrict__ Y, int64_t n, int nrhs, const int32_t *__restrict__ active) {
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = blockIdx.x * 4 + wv;
-    if (item >= nitems) return;
-    const int s = list[item % nlist];
-    const int b = item / nlist;
-    if (active && !active[b]) return;
-    const SnDesc d = sn[s];
-    const int c = d.c, w = d.w;
-    const int br0 = b * nrhs + r0;
-    const int32_t *R = rows + d.rowptr;
-    double x[SL][NR];
+    wave_sync_solve();
+    // rows below the diagonal block, JC columns of L in flight at once
+    constexpr int JC = SL >= 4 ? 4 : 8;
+    for (int j0 = 0; j0 < w; j0 += JC) {
+        T lc[JC][SL];
 #pragma unroll
-    for (int k = 0; k < SL; k++) {
-        const int i = lane + 64 * k;
-        const int64_t pos = i < w ? d.first + i : (i < c ? R[i] : 0);
-#pragma unroll
-        for (int r = 0; r < NR; r++) x[k][r] = i < c ? Y[int64_t(br0 + r) * n + pos] : 0.0;
-    }
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    for (int j1 = w - 1; j1 >= 0; j1 -= 8) {
-        // columns j1, j1-1, ..., j1-7 in flight at once
-        T lc[8][SL];
-#pragma unroll
-        for (int jj = 0; jj < 8; jj++)
+        for (int jj = 0; jj < JC; jj++)
 #pragma unroll
             for (int k = 0; k < SL; k++) {
-                const int i = lane + 64 * k;
-                lc[jj][k] = (j1 - jj >= 0 && i < c) ? Lb[int64_t(j1 - jj) * c + i] : T(0);
+                const int i = li + G * k, j = j0 + jj;
+                lc[jj][k] = (j < w && i >= w && i < c) ? Lb[j * c + i] : T(0);
             }
 #pragma unroll
-        for (int jj = 0; jj < 8; jj++) {
-            const int j = j1 - jj;
-            if (j >= 0) {
-                double t[NR];
+        for (int jj = 0; jj < JC; jj++) {
+            const int j = j0 + jj;
+            if (j < w) {
+                double y[NR];
 #pragma unroll
-                for (int r = 0; r < NR; r++) t[r] = 0.0;
+                for (int r = 0; r < NR; r++) y[r] = ys[seg][j][r];
 #pragma unroll
                 for (int k = 0; k < SL; k++) {
-                    const int i = lane + 64 * k;
-                    if (i > j && i < c) {
+                    const int i = li + G * k;
+                    if (i >= w && i < c) {
                         const double l = double(lc[jj][k]);
 #pragma unroll
-                        for (int r = 0; r < NR; r++) t[r] += l * x[k][r];
+                        for (int r = 0; r < NR; r++) x[k][r] -= l * y[r];
                     }
-                }
-#pragma unroll
-                for (int r = 0; r < NR; r++) {
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) t[r] += __shfl_xor(t[r], off);
-                }
-                if (lane == j) {
-                    const double ljj = double(lc[jj][0]);
-#pragma unroll
-                    for (int r = 0; r < NR; r++) x[0][r] = (x[0][r] - t[r]) / ljj;
                 }
             }
         }
     }
+    double *fo = FV + (int64_t(b) * fvsize + d.rowptr) * nrhs + r0;
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        double *y = Y + int64_t(br0 + r) * n;
-        double *xo = X + int64_t(br0 + r) * ldb;
-        if (lane < w) {
-            y[d.first + lane] = x[0][r];
-            xo[perm[d.first + lane]] = x[0][r];
+    for (int k = 0; k < SL; k++) {
+        const int i = li + G * k;
+        if (i >= w && i < c) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) fo[int64_t(i) * nrhs + r] = x[k][r];
         }
     }
 }
 
-// Forward step of one level for supernodes with c <= CM rows, one lane per
-// (supernode, matrix, right-hand side): lane-private registers hold the
-// front vector; the right-hand side and the children's update vectors are
-// pulled through the gather map (no shared scatter), and the triangular
-// solve runs in registers (every index a compile-time constant; rows and
-// columns beyond the supernode are masked, their loads clamped in bounds).
-template <typename T, int CM>
-__global__ __launch_bounds__(256) void k_fwd_lane(
+// Backward step of one level for the supernodes of one row class: a segment
+// of G lanes per (supernode, matrix), lane j owning column j of the
+// supernode (w <= G).  The rows of L's block are staged through LDS in
+// chunks of kBwdRows (read from HBM by consecutive lanes), with the solved
+// values x_i of those rows:
+//   below     rows i >= w (ancestors' values) in blocks of kSoaRows rows:
+//             acc_j -= (sum over the block, ascending i, of L_ij x_i);
+//   diagonal  rows i = w-1 .. 0: the owner of column i finishes
+//             x_i = acc_i / L_ii and broadcasts it; columns j < i subtract
+//             L_ij x_i.
+constexpr int kBwdRows = 16;
+template <typename T, int G, int NR>
+__global__ __launch_bounds__(256) void k_bwd_seg(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ gptr,
-    const int32_t *__restrict__ gidx, const T *__restrict__ L, int64_t Lsize,
-    const double *__restrict__ B, int64_t ldb, double *__restrict__ Y, double *__restrict__ FV,
-    int64_t n, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
-    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    int r0, const int32_t *__restrict__ rows, const T *__restrict__ L, int64_t Lsize,
+    double *__restrict__ Ys, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    constexpr int NSEG = 256 / G;
+    constexpr int NG = G / kBwdRows;  // column groups of the staging
+    __shared__ T Ls[NSEG][kBwdRows][G + 1];
+    __shared__ double xs[NSEG][kBwdRows][NR];
+    const int tid = threadIdx.x, seg = tid / G, li = tid % G;
+    const int item = blockIdx.x * NSEG + seg;
     if (item >= nitems) return;
-    const int br = item / nlist;
-    const int b = br / nrhs;
+    const int b = item / nlist;
     if (active && !active[b]) return;
-    const SnDesc d = sn[list[item - br * nlist]];
+    const SnDesc d = sn[list[item - b * nlist]];
     const int c = d.c, w = d.w;
-    const double *bb = B + int64_t(br) * ldb;
-    double *fv = FV + int64_t(br) * fvsize;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    double x[CM];
-#pragma unroll
-    for (int i = 0; i < CM; i++) {
-        double a = 0.0;
-        if (i < c) {
-            if (i < w) a = bb[perm[d.first + i]];
-            const int g1 = gptr[d.rowptr + i + 1];
-            for (int g = gptr[d.rowptr + i]; g < g1; g++) a += fv[gidx[g]];
-        }
-        x[i] = a;
-    }
-    // row by row: x_i -= sum_{j < min(i, w)} L_ij y_j (ascending j), then the
-    // pivot division for the supernode's own columns
-#pragma unroll
-    for (int i = 1; i < CM; i++) {
-        if (i - 1 < w) x[i - 1] /= double(Lb[(i - 1) * c + i - 1]);
-        double t = 0.0;
-#pragma unroll
-        for (int j = 0; j < i; j++) {
-            const bool ok = j < w && i < c;
-            const double l = double(Lb[ok ? j * c + i : 0]);
-            t += ok ? l * x[j] : 0.0;
-        }
-        x[i] -= t;
-    }
-    if (CM - 1 < w) x[CM - 1] /= double(Lb[(CM - 1) * c + CM - 1]);
-    double *y = Y + int64_t(br) * n + d.first;
-#pragma unroll
-    for (int i = 0; i < CM; i++) {
-        if (i < w) y[i] = x[i];
-        else if (i < c) fv[d.rowptr + i] = x[i];
-    }
-}
-
-// Backward step of one level for supernodes with c <= CM rows, one lane per
-// (supernode, matrix, right-hand side): rows below the supernode's columns
-// are read from the solved ancestors, then columns are solved from the
-// last to the first (dot products in ascending row order).
-template <typename T, int CM>
-__global__ __launch_bounds__(256) void k_bwd_lane(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
-    const T *__restrict__ L, int64_t Lsize, double *__restrict__ X, int64_t ldb,
-    double *__restrict__ Y, int64_t n, int nrhs, const int32_t *__restrict__ active) {
-    const int item = blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= nitems) return;
-    const int br = item / nlist;
-    const int b = br / nrhs;
-    if (active && !active[b]) return;
-    const SnDesc d = sn[list[item - br * nlist]];
-    const int c = d.c, w = d.w;
-    const double *y = Y + int64_t(br) * n;
+    double *yb = Ys + int64_t(b) * n * nrhs + r0;
     const int32_t *R = rows + d.rowptr;
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    double x[CM];
+    const int sr = li % kBwdRows, sg = li / kBwdRows;  // staging: row, column group
+
+    double acc[NR];
 #pragma unroll
-    for (int i = 0; i < CM; i++) x[i] = i < w ? y[d.first + i] : (i < c ? y[R[i]] : 0.0);
+    for (int r = 0; r < NR; r++)
+        acc[r] = li < w ? yb[int64_t(d.first + li) * nrhs + r] : 0.0;
+    const double rinv = li < w ? 1.0 / double(Lb[li * c + li]) : 0.0;
+    // rows below in blocks of kSoaRows: each block's sum (ascending rows)
+    // is formed on its own and then subtracted, the same order as the
+    // batch-interleaved kernels, so both layouts give identical bits
+    for (int rb = w; rb < c; rb += kSoaRows) {
+        const int re = min(c, rb + kSoaRows);
+        double p[NR];
 #pragma unroll
-    for (int j = CM - 1; j >= 0; j--) {
-        asm volatile("" ::: "memory");  // one column of L in flight at a time
-        const bool cj = j < w;
-        double t = 0.0;
+        for (int r = 0; r < NR; r++) p[r] = 0.0;
+        for (int i0 = rb; i0 < re; i0 += kBwdRows) {
+            const int i = i0 + sr;
+            if (i < re) {
+                for (int j = sg; j < w; j += NG) Ls[seg][sr][j] = Lb[j * c + i];
+                if (sg == 0) {
+                    const double *xi = yb + int64_t(R[i]) * nrhs;
 #pragma unroll
-        for (int i = j + 1; i < CM; i++) {
-            const bool ok = cj && i < c;
-            const double l = double(Lb[ok ? j * c + i : 0]);
-            t += ok ? l * x[i] : 0.0;
+                    for (int r = 0; r < NR; r++) xs[seg][sr][r] = xi[r];
+                }
+            }
+            wave_sync_solve();
+            const int nr = min(kBwdRows, re - i0);
+            if (li < w) {
+                for (int t = 0; t < nr; t++) {
+                    const double l = double(Ls[seg][t][li]);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) p[r] += l * xs[seg][t][r];
+                }
+            }
+            wave_sync_solve();
         }
-        if (cj) x[j] = (x[j] - t) / double(Lb[j * c + j]);
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] -= p[r];
     }
-    double *yo = Y + int64_t(br) * n + d.first;
-    double *xo = X + int64_t(br) * ldb;
+    for (int i1 = w; i1 > 0; i1 -= kBwdRows) {
+        const int i0 = max(0, i1 - kBwdRows);
+        const int i = i0 + sr;
+        if (i < i1)
+            for (int j = sg; j < i; j += NG) Ls[seg][sr][j] = Lb[j * c + i];
+        wave_sync_solve();
+        for (int t = i1 - 1; t >= i0; t--) {
+            double xv[NR];
 #pragma unroll
-    for (int i = 0; i < CM; i++)
-        if (i < w) {
-            yo[i] = x[i];
-            xo[perm[d.first + i]] = x[i];
+            for (int r = 0; r < NR; r++) xv[r] = seg_bcast<G>(acc[r] * rinv, t);
+            if (li == t) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[r] = xv[r];
+            } else if (li < t) {
+                const double l = double(Ls[seg][t - i0][li]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[r] -= l * xv[r];
+            }
         }
+        wave_sync_solve();
+    }
+    if (li < w) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) yb[int64_t(d.first + li) * nrhs + r] = acc[r];
+    }
 }
 
-// Forward panel p of panel-solved supernodes.  Workgroup 0 writes y_p;
-// workgroup t >= 1 updates rows [c0 + kb + 64 (t-1), +64) of FV_s.
-template <typename T>
-__global__ __launch_bounds__(64) void k_fwd_panel(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p,
-    const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv,
-    int64_t dsize, double *__restrict__ Y, double *__restrict__ FV, int64_t n,
-    int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
-    __shared__ double y[kP];
-    const int s = list[blockIdx.y];
-    const int br = blockIdx.z;
-    const int b = br / nrhs;
+// Position of entry (matrix b, row, right-hand side r) in a solve vector
+// set with `rows` rows per matrix.  Row-major per matrix (rows, then
+// right-hand sides) or, batch-interleaved, groups of 64 matrices with the
+// matrix index fastest, so that lane b of a wave reads consecutive words.
+template <bool SOA>
+__device__ __host__ inline int64_t vix(int b, int64_t row, int r, int64_t rows, int nrhs) {
+    if constexpr (SOA)
+        return ((int64_t(b >> 6) * rows + row) * nrhs + r) * 64 + (b & 63);
+    else
+        return (int64_t(b) * rows + row) * nrhs + r;
+}
+
+// Front vectors of the panel-solved supernodes of a level, then y_0 of
+// their first panel.  Row i of FV_s is the right-hand side (i < w) plus the
+// children's update entries (gather map, children in order); y_0 =
+// D_0^{-1} v_0 with the zero-padded inverse block D_0 (column-major).
+// Item = (supernode, matrix); 256 threads; right-hand sides in blocks of
+// kMaxRhsPanel.
+template <bool SOA>
+__global__ __launch_bounds__(256) void k_pan_gather(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const double *__restrict__ Dinv, int64_t dsize, double *__restrict__ Ys,
+    double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    const int32_t *__restrict__ active) {
+    __shared__ double v0[kP][kMaxRhsPanel];
+    const int s = list[blockIdx.x];
+    const int b = blockIdx.y;
     if (active && !active[b]) return;
     const SnDesc d = sn[s];
-    const int c0 = p * kP;
-    if (c0 >= d.w) return;
-    const int kb = min(kP, d.w - c0);
-    const int c = d.c;
-    const int tile = blockIdx.x;
-    const int r0 = tile == 0 ? c0 : c0 + kb + (tile - 1) * kP;
-    if (r0 >= c) return;
-    double *fv = FV + int64_t(br) * fvsize + d.rowptr;
-    const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
-    const int lane = threadIdx.x;
-    __shared__ double vp[kP];
-    vp[lane] = lane < kb ? fv[c0 + lane] : 0.0;
-    __syncthreads();
-    double yi = 0.0;
-#pragma unroll 16
-    for (int t = 0; t < kP; t++) yi += Dp[t * kP + lane] * vp[t];  // D is zero-padded
-    y[lane] = yi;
-    __syncthreads();
-    if (tile == 0) {
-        if (lane < kb) Y[int64_t(br) * n + d.first + c0 + lane] = yi;
-        return;
-    }
-    const int r = r0 + lane;
-    if (r < c) {
-        const T *Lb = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + r;
-        double acc0 = 0.0, acc1 = 0.0;
-        int t = 0;
-#pragma unroll 8
-        for (; t + 1 < kb; t += 2) {
-            acc0 += double(Lb[int64_t(t) * c]) * y[t];
-            acc1 += double(Lb[int64_t(t + 1) * c]) * y[t + 1];
+    const int kb = min(kP, d.w);
+    const double *D = Dinv + int64_t(b) * dsize + d.dinv;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
+        const int nr = min(kMaxRhsPanel, nrhs - r0);
+        for (int i = threadIdx.x; i < d.c; i += blockDim.x) {
+            const int g0 = gptr[d.rowptr + i], g1 = gptr[d.rowptr + i + 1];
+            for (int r = 0; r < nr; r++) {
+                double a = i < d.w ? Ys[vix<SOA>(b, d.first + i, r0 + r, n, nrhs)] : 0.0;
+                for (int g = g0; g < g1; g++) a += FV[vix<SOA>(b, gidx[g], r0 + r, fvsize, nrhs)];
+                FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)] = a;
+                if (i < kP) v0[i][r] = a;
+            }
         }
-        if (t < kb) acc0 += double(Lb[int64_t(t) * c]) * y[t];
-        fv[r] -= acc0 + acc1;
+        __syncthreads();
+        const int t = threadIdx.x;
+        if (t < kb) {
+            double y[kMaxRhsPanel] = {};
+#pragma unroll 16
+            for (int i = 0; i < kb; i++) {
+                const double di = D[int64_t(i) * kP + t];
+#pragma unroll
+                for (int r = 0; r < kMaxRhsPanel; r++)
+                    if (r < nr) y[r] += di * v0[i][r];
+            }
+            for (int r = 0; r < nr; r++) Ys[vix<SOA>(b, d.first + t, r0 + r, n, nrhs)] = y[r];
+        }
+        __syncthreads();
     }
 }
 
-// Backward panel p of panel-solved supernodes, NR right-hand sides of one
-// matrix per workgroup: partial sums of L[r, c0 + t] z_r over a chunk of
-// kSolveChunk rows below the panel (wave g owns columns g + 4k, each thread
-// four rows); the last workgroup of the (supernode, matrix) sums the chunks
-// in order and solves with D_p^T.
-template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_bwd_panel(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int list0, int p, int r0,
-    const int32_t *__restrict__ perm, const int32_t *__restrict__ rows,
-    const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv, int64_t dsize,
-    double *__restrict__ X, int64_t ldb, double *__restrict__ Y, int64_t n,
-    double *__restrict__ PART, int64_t psize, int32_t *__restrict__ cnt, int batch, int nrhs,
-    const int32_t *__restrict__ active) {
-    __shared__ double rhs[NR][kP];
-    __shared__ double Dt[kP * (kP + 1)];
-    __shared__ int last;
+// Forward panel p of panel-solved supernodes, right-hand sides r0 ..
+// r0 + NR - 1: workgroup t updates rows [c0 + kb + 64 t, +64) of FV_s with
+// y_p (stored by the previous step).  Workgroup 0 covers the rows of panel
+// p + 1 when there is one; it then also forms y_{p+1} = D_{p+1}^{-1} v_{p+1}
+// (every contribution to v_{p+1} is in once this update is done).
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(64) void k_fwd_panel(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
+    const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv,
+    int64_t dsize, double *__restrict__ Ys, double *__restrict__ FV, int64_t n,
+    int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
+    __shared__ double yv[kP][NR];
+    __shared__ double vn[kP][NR];
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
     if (active && !active[b]) return;
@@ -466,105 +420,565 @@ __global__ __launch_bounds__(256) void k_bwd_panel(
     const int c0 = p * kP;
     if (c0 >= d.w) return;
     const int kb = min(kP, d.w - c0);
-    const int c = d.c, w = d.w;
-    const int rbeg = c0 + kb;
-    const int nch = max(1, (c - rbeg + kSolveChunk - 1) / kSolveChunk);
-    const int chunk = blockIdx.x;
-    if (chunk >= nch) return;
-    const int tid = threadIdx.x, lane = tid & 63, cg = tid >> 6;
-    const int br0 = b * nrhs + r0;
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    const int32_t *R = rows + d.rowptr;
-    const int rb = rbeg + chunk * kSolveChunk;
-    double z[4][NR];
+    const int c = d.c;
+    const int tile = blockIdx.x;
+    const int rt = c0 + kb + tile * kP;
+    if (rt >= c) return;
+    const int lane = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int r = rb + 64 * q + lane;
-        const int64_t pos = r < c ? (r < w ? d.first + r : R[r]) : 0;
+    for (int r = 0; r < NR; r++)
+        yv[lane][r] = lane < kb ? Ys[vix<SOA>(b, d.first + c0 + lane, r0 + r, n, nrhs)] : 0.0;
+    __syncthreads();
+    const int row = rt + lane;
+    double v[NR];
 #pragma unroll
-        for (int k = 0; k < NR; k++) z[q][k] = r < c ? Y[int64_t(br0 + k) * n + pos] : 0.0;
+    for (int r = 0; r < NR; r++) v[r] = 0.0;
+    if (row < c) {
+        const T *Lr = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + row;
+#pragma unroll
+        for (int r = 0; r < NR; r++) v[r] = FV[vix<SOA>(b, d.rowptr + row, r0 + r, fvsize, nrhs)];
+#pragma unroll 8
+        for (int t = 0; t < kb; t++) {
+            const double l = double(Lr[int64_t(t) * c]);
+#pragma unroll
+            for (int r = 0; r < NR; r++) v[r] -= l * yv[t][r];
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++) FV[vix<SOA>(b, d.rowptr + row, r0 + r, fvsize, nrhs)] = v[r];
     }
-    double acc[16][NR];
+    const int c1 = c0 + kP;  // next panel
+    if (tile != 0 || c1 >= d.w) return;
+    const int kb1 = min(kP, d.w - c1);
 #pragma unroll
-    for (int j = 0; j < 16; j++)
+    for (int r = 0; r < NR; r++) vn[lane][r] = lane < kb1 ? v[r] : 0.0;
+    __syncthreads();
+    if (lane < kb1) {
+        const double *D = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p + 1) * kP * kP;
+        double y[NR];
 #pragma unroll
-        for (int k = 0; k < NR; k++) acc[j][k] = 0.0;
+        for (int r = 0; r < NR; r++) y[r] = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < kP; i++) {
+            const double di = D[int64_t(i) * kP + lane];
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
-        const int t = cg + 4 * j;
-        if (t < kb) {
-            const T *lc = Lb + int64_t(c0 + t) * c;
+            for (int r = 0; r < NR; r++) y[r] += di * vn[i][r];
+        }
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int r = rb + 64 * q + lane;
-                const double l = r < c ? double(lc[r]) : 0.0;
+        for (int r = 0; r < NR; r++) Ys[vix<SOA>(b, d.first + c1 + lane, r0 + r, n, nrhs)] = y[r];
+    }
+}
+
+// Backward panel p, step 1: partial sums of L[i, c0 + t] x_i over a chunk of
+// kSolveChunk rows below the panel, right-hand sides r0 .. r0 + NR - 1.
+// Wave g takes rows [64 g, +64) of the chunk in blocks of 16 staged through
+// LDS (L read by consecutive lanes along its columns), lane t owns column
+// c0 + t; the four waves' sums are added in wave order.
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(256) void k_bwd_pan_part(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
+    const int32_t *__restrict__ rows, const T *__restrict__ L, int64_t Lsize,
+    const double *__restrict__ Ys, int64_t n, double *__restrict__ PART, int64_t psize,
+    int nrhs, const int32_t *__restrict__ active) {
+    constexpr int RB = 16;
+    __shared__ T Ls[4][RB][kP + 1];
+    __shared__ double xs[4][RB][NR];
+    __shared__ double red[4][kP][NR];
+    const int s = list[blockIdx.y];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c0 = p * kP;
+    if (c0 >= d.w) return;
+    const int kb = min(kP, d.w - c0);
+    const int c = d.c;
+    const int rbeg = c0 + kb;
+    const int chunk = blockIdx.x;
+    const int rb = rbeg + chunk * kSolveChunk;
+    if (rb >= c) return;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int sr = lane & (RB - 1), sg = lane >> 4;  // staging: row, column group
+    const T *Lb = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c;
+    const int32_t *R = rows + d.rowptr;
+    double acc[NR];
 #pragma unroll
-                for (int k = 0; k < NR; k++) acc[j][k] += l * z[q][k];
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    const int w0 = rb + 64 * wv, w1 = min(c, w0 + 64);
+    for (int i0 = w0; i0 < w1; i0 += RB) {
+        const int i = i0 + sr;
+        if (i < w1) {
+            for (int t = sg; t < kb; t += 4) Ls[wv][sr][t] = Lb[int64_t(t) * c + i];
+            if (sg == 0) {
+                const int64_t pos = i < d.w ? d.first + i : R[i];
+#pragma unroll
+                for (int r = 0; r < NR; r++) xs[wv][sr][r] = Ys[vix<SOA>(b, pos, r0 + r, n, nrhs)];
             }
         }
+        wave_sync_solve();  // each wave stages and reads its own rows
+        const int nr = min(RB, w1 - i0);
+        if (lane < kb) {
+            for (int q = 0; q < nr; q++) {
+                const double l = double(Ls[wv][q][lane]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[r] += l * xs[wv][q][r];
+            }
+        }
+        wave_sync_solve();
     }
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-#pragma unroll
-        for (int k = 0; k < NR; k++) {
-            double v = acc[j][k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-            acc[j][k] = v;
-        }
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
-            const int t = cg + 4 * j;
-            if (t < kb)
-#pragma unroll
-                for (int k = 0; k < NR; k++)
-                    PART[int64_t(br0 + k) * psize + d.part + chunk * kP + t] = acc[j][k];
-        }
-    }
-    __threadfence();
+    for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
     __syncthreads();
-    int32_t *ctr = cnt + int64_t(list0 + blockIdx.y) * batch + b;
-    if (tid == 0) last = atomicAdd(ctr, 1) == nch - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    {
-        // the inverse block, coalesced into LDS: Dt[t][i] = Dp[t * 64 + i]
-        const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+    if (wv == 0 && lane < kb) {
 #pragma unroll
-        for (int q = 0; q < kP * kP / 256; q++) {
-            const int e = q * 256 + tid;
-            Dt[(e >> 6) * (kP + 1) + (e & 63)] = Dp[e];
+        for (int r = 0; r < NR; r++) {
+            const double v = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
+            PART[vix<SOA>(b, d.part + int64_t(chunk) * kP + lane, r0 + r, psize, nrhs)] = v;
         }
     }
-    if (tid < kb) {
+}
+
+// Backward panel p, step 2: x_p = D_p^T (y_p - sum of the chunks' partial
+// sums, in chunk order), right-hand sides r0 .. r0 + NR - 1.  Item =
+// (supernode, matrix); one wave, lane t owns column c0 + t.
+template <int NR, bool SOA>
+__global__ __launch_bounds__(64) void k_bwd_pan_fin(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
+    const double *__restrict__ Dinv, int64_t dsize, double *__restrict__ Ys, int64_t n,
+    const double *__restrict__ PART, int64_t psize, int nrhs,
+    const int32_t *__restrict__ active) {
+    __shared__ double Dt[kP * (kP + 1)];
+    __shared__ double rhs[kP][NR];
+    const int s = list[blockIdx.x];
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c0 = p * kP;
+    if (c0 >= d.w) return;
+    const int kb = min(kP, d.w - c0);
+    const int rbeg = c0 + kb;
+    const int nch = (d.c - rbeg + kSolveChunk - 1) / kSolveChunk;
+    const int t = threadIdx.x;
+    // the inverse block, coalesced into LDS: Dt[j][i] = D[j * 64 + i]
+    const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+    for (int e0 = 0; e0 < kP * kP; e0 += 16 * 64) {
+        double v[16];  // 16 loads per thread in flight at once
 #pragma unroll
-        for (int k = 0; k < NR; k++) {
-            const double *part = PART + int64_t(br0 + k) * psize + d.part;
-            double s0 = 0.0;
-            for (int q = 0; q < nch; q++) s0 += part[q * kP + tid];
-            rhs[k][tid] = Y[int64_t(br0 + k) * n + d.first + c0 + tid] - s0;
+        for (int q = 0; q < 16; q++) v[q] = Dp[e0 + q * 64 + t];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int e = e0 + q * 64 + t;
+            Dt[(e >> 6) * (kP + 1) + (e & 63)] = v[q];
         }
     }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double s0 = 0.0;
+        if (t < kb)
+            for (int q = 0; q < nch; q++)
+                s0 += PART[vix<SOA>(b, d.part + int64_t(q) * kP + t, r0 + r, psize, nrhs)];
+        rhs[t][r] = t < kb ? Ys[vix<SOA>(b, d.first + c0 + t, r0 + r, n, nrhs)] - s0 : 0.0;
+    }
     __syncthreads();
-    if (tid < kb) {
+    if (t < kb) {
         // x_t = sum_i (L_pp^{-1})[i][t] rhs_i; column t of the inverse is Dt[t][.]
         double xt[NR];
 #pragma unroll
-        for (int k = 0; k < NR; k++) xt[k] = 0.0;
+        for (int r = 0; r < NR; r++) xt[r] = 0.0;
+#pragma unroll 8
         for (int i = 0; i < kb; i++) {
-            const double dti = Dt[tid * (kP + 1) + i];
+            const double dti = Dt[t * (kP + 1) + i];
 #pragma unroll
-            for (int k = 0; k < NR; k++) xt[k] += dti * rhs[k][i];
+            for (int r = 0; r < NR; r++) xt[r] += dti * rhs[i][r];
         }
 #pragma unroll
-        for (int k = 0; k < NR; k++) {
-            Y[int64_t(br0 + k) * n + d.first + c0 + tid] = xt[k];
-            X[int64_t(br0 + k) * ldb + perm[d.first + c0 + tid]] = xt[k];
+        for (int r = 0; r < NR; r++) Ys[vix<SOA>(b, d.first + c0 + t, r0 + r, n, nrhs)] = xt[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batch-interleaved solves.  A group of 64 matrices shares one wave, lane =
+// matrix: every lane runs the same sequential substitution on its own
+// values, so every load of L or of a vector is 64 consecutive words and no
+// value ever crosses lanes.  L (non-panel supernodes) is copied to
+// Ls[((b / 64) Lsize + k) 64 + b % 64] once per factorization; the solve
+// vectors use vix<true>.
+
+// Ls <- L for kSoaChunk consecutive scalars from `chunks[x]` and the 64
+// matrices of group y, through an LDS tile (both sides coalesced).
+template <typename T>
+__global__ __launch_bounds__(256) void k_to_soa(
+    const T *__restrict__ L, int64_t Lsize, const int64_t *__restrict__ chunks, int batch,
+    T *__restrict__ Ls) {
+    __shared__ T tile[64][kSoaChunk + 1];
+    const int64_t k0 = chunks[blockIdx.x];
+    const int bg = blockIdx.y;
+    const int t = threadIdx.x;
+    const int kk = t % kSoaChunk, bh = t / kSoaChunk;  // 256 / kSoaChunk row phases
+    constexpr int NPH = 256 / kSoaChunk;
+    for (int q0 = 0; q0 < 64; q0 += 16 * NPH) {
+        T v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int bl = q0 + bh + NPH * q;
+            const int b = bg * 64 + bl;
+            v[q] = (bl < 64 && b < batch && k0 + kk < Lsize) ? L[int64_t(b) * Lsize + k0 + kk] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int bl = q0 + bh + NPH * q;
+            if (bl < 64) tile[bl][kk] = v[q];
         }
     }
-    if (tid == 0) *ctr = 0;
+    __syncthreads();
+    T *out = Ls + (int64_t(bg) * Lsize + k0) * 64;
+#pragma unroll 8
+    for (int q = 0; q < kSoaChunk * 64 / 256; q++) {
+        const int e = t + 256 * q;
+        const int k = e >> 6, bl = e & 63;
+        if (k0 + k < Lsize) out[e] = tile[bl][k];
+    }
+}
+
+// Ys[vix<true>(b, k, r)] = B[(b nrhs + r) ldb + perm[k]], 64 rows x 64
+// matrices per workgroup through LDS (writes coalesced).
+__global__ __launch_bounds__(256) void k_perm_in_soa(
+    const int32_t *__restrict__ perm, const double *__restrict__ B, int64_t ldb,
+    double *__restrict__ Ys, int64_t n, int nrhs, int batch) {
+    __shared__ double tile[64][65];
+    const int64_t k0 = int64_t(blockIdx.x) * 64;
+    const int bg = blockIdx.y;
+    const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
+    for (int r = 0; r < nrhs; r++) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int bl = hi + 4 * q;
+            const int b = bg * 64 + bl;
+            const int64_t k = k0 + lo;
+            v[q] = (b < batch && k < n) ? B[(int64_t(b) * nrhs + r) * ldb + perm[k]] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) tile[hi + 4 * q][lo] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int kk = hi + 4 * q;
+            if (k0 + kk < n) Ys[((int64_t(bg) * n + k0 + kk) * nrhs + r) * 64 + lo] = tile[lo][kk];
+        }
+        __syncthreads();
+    }
+}
+
+// X[(b nrhs + r) ldb + i] = Ys[vix<true>(b, pinv[i], r)] for the active
+// matrices, 64 rows x 64 matrices per workgroup through LDS.
+__global__ __launch_bounds__(256) void k_perm_out_soa(
+    const int32_t *__restrict__ pinv, const double *__restrict__ Ys, double *__restrict__ X,
+    int64_t ldb, int64_t n, int nrhs, int batch, const int32_t *__restrict__ active) {
+    __shared__ double tile[64][65];
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
+    const int bg = blockIdx.y;
+    const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
+    for (int r = 0; r < nrhs; r++) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int64_t i = i0 + hi + 4 * q;
+            v[q] = i < n ? Ys[((int64_t(bg) * n + pinv[i]) * nrhs + r) * 64 + lo] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) tile[hi + 4 * q][lo] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int bl = hi + 4 * q;
+            const int b = bg * 64 + bl;
+            const int64_t i = i0 + lo;
+            if (b < batch && i < n && (!active || active[b]))
+                X[(int64_t(b) * nrhs + r) * ldb + i] = tile[lo][bl];
+        }
+        __syncthreads();
+    }
+}
+
+// Row i of the gathered front vector of supernode d (right-hand side for
+// i < w, plus the children's update entries, children in order), right-hand
+// sides r0 .. r0 + NR - 1, for this lane's matrix.
+template <int NR>
+__device__ inline void soa_gather(const SnDesc &d, int i, const int32_t *__restrict__ gptr,
+                                  const int32_t *__restrict__ gidx, const double *yb,
+                                  const double *fb, int nrhs, double (&a)[NR]) {
+#pragma unroll
+    for (int r = 0; r < NR; r++) a[r] = i < d.w ? yb[(int64_t(d.first + i) * nrhs + r) * 64] : 0.0;
+    const int g1 = gptr[d.rowptr + i + 1];
+    for (int g = gptr[d.rowptr + i]; g < g1; g++) {
+        const double *u = fb + int64_t(gidx[g]) * nrhs * 64;
+#pragma unroll
+        for (int r = 0; r < NR; r++) a[r] += u[r * 64];
+    }
+}
+
+constexpr int kSoaCols = 16;  // columns per chunk of the interleaved kernels
+// rows per step of the row loops (their loads in flight together)
+template <typename T> struct SoaRows { static constexpr int value = sizeof(T) == 4 ? 4 : 2; };
+
+// Forward, diagonal blocks: one wave per (supernode, group of 64 matrices).
+// Columns in chunks of 16: the chunk's rows are solved in registers
+// (y_j = (v_j - sum_{k<j} L_jk y_k) / L_jj, ascending), y stored, and the
+// later rows of the diagonal block (i < w) updated in FV.
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_fwd_soa_diag(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
+    int64_t n, int64_t fvsize, int nrhs, int r0) {
+    const SnDesc d = sn[list[blockIdx.x]];
+    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int c = d.c, w = d.w;
+    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
+    double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    double *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
+    for (int j0 = 0; j0 < w; j0 += kSoaCols) {
+        const int jn = min(kSoaCols, w - j0);
+        double v[kSoaCols][NR];
+#pragma unroll
+        for (int jj = 0; jj < kSoaCols; jj++) {
+            const int i = j0 + jj;
+            if (jj < jn) {
+                if (j0 == 0) {
+                    soa_gather<NR>(d, i, gptr, gidx, yb, fb, nrhs, v[jj]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) v[jj][r] = fb[(int64_t(d.rowptr + i) * nrhs + r) * 64];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; r++) v[jj][r] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < kSoaCols; jj++) {
+            if (jj < jn) {
+                const int i = j0 + jj;
+#pragma unroll
+                for (int kk = 0; kk < jj; kk++) {
+                    const double l = double(Lb[(int64_t(j0 + kk) * c + i) * 64]);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) v[jj][r] -= l * v[kk][r];
+                }
+                const double rinv = 1.0 / double(Lb[(int64_t(i) * c + i) * 64]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    v[jj][r] *= rinv;
+                    yb[(int64_t(d.first + i) * nrhs + r) * 64] = v[jj][r];
+                }
+            }
+        }
+        // rows of the diagonal block below this chunk
+        for (int i = j0 + kSoaCols; i < w; i++) {
+            double a[NR];
+            if (j0 == 0) {
+                soa_gather<NR>(d, i, gptr, gidx, yb, fb, nrhs, a);
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[r] = fb[(int64_t(d.rowptr + i) * nrhs + r) * 64];
+            }
+#pragma unroll
+            for (int jj = 0; jj < kSoaCols; jj++) {
+                if (jj < jn) {
+                    const double l = double(Lb[(int64_t(j0 + jj) * c + i) * 64]);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) a[r] -= l * v[jj][r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) fb[(int64_t(d.rowptr + i) * nrhs + r) * 64] = a[r];
+        }
+    }
+}
+
+// Forward, rows below the diagonal blocks: one wave per (row block of
+// kSoaRows rows, group): u_i = v_i - sum_j L_ij y_j over the supernode's
+// columns in chunks of 16 (ascending j), stored in FV as the update vector.
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_fwd_soa_rows(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
+    const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
+    const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
+    double *__restrict__ Ys, double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    int r0) {
+    const SnDesc d = sn[it_s[blockIdx.x]];
+    const int rb = it_r0[blockIdx.x];
+    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int c = d.c, w = d.w;
+    const int re = min(c, rb + kSoaRows);
+    constexpr int RU = SoaRows<T>::value;
+    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
+    const double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    double *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
+    for (int j0 = 0; j0 < w; j0 += kSoaCols) {
+        const int jn = min(kSoaCols, w - j0);
+        double y[kSoaCols][NR];
+#pragma unroll
+        for (int jj = 0; jj < kSoaCols; jj++)
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                y[jj][r] = jj < jn ? yb[(int64_t(d.first + j0 + jj) * nrhs + r) * 64] : 0.0;
+        // RU rows at a time, every load of the group issued before any use
+        for (int i0 = rb; i0 < re; i0 += RU) {
+            double a[RU][NR];
+            T l[RU][kSoaCols];
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int i = i0 + u;
+                if (i < re) {
+                    if (j0 == 0) {
+                        soa_gather<NR>(d, i, gptr, gidx, yb, fb, nrhs, a[u]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < NR; r++)
+                            a[u][r] = fb[(int64_t(d.rowptr + i) * nrhs + r) * 64];
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < kSoaCols; jj++)
+                    l[u][jj] = (i < re && jj < jn) ? Lb[(int64_t(j0 + jj) * c + i) * 64] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+#pragma unroll
+                for (int jj = 0; jj < kSoaCols; jj++)
+#pragma unroll
+                    for (int r = 0; r < NR; r++) a[u][r] -= double(l[u][jj]) * y[jj][r];
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+                if (i0 + u < re)
+#pragma unroll
+                    for (int r = 0; r < NR; r++)
+                        fb[(int64_t(d.rowptr + i0 + u) * nrhs + r) * 64] = a[u][r];
+        }
+    }
+}
+
+// Backward, rows below the diagonal blocks: one wave per (row block,
+// group): partial sums p_j = sum_i L_ij x_i over the block's rows (x from
+// the solved ancestors), columns in chunks of 16, stored at
+// part + (block index) w + j.
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_bwd_soa_rows(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
+    const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
+    const T *__restrict__ Ls, int64_t Lsize, const double *__restrict__ Ys,
+    double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    const SnDesc d = sn[it_s[blockIdx.x]];
+    const int rb = it_r0[blockIdx.x];
+    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int c = d.c, w = d.w;
+    const int re = min(c, rb + kSoaRows);
+    const int kblk = (rb - w) / kSoaRows;
+    constexpr int RU = SoaRows<T>::value;
+    const int32_t *R = rows + d.rowptr;
+    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
+    const double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    double *pb = PS + ((int64_t(bg) * psize + d.part + int64_t(kblk) * w) * nrhs + r0) * 64 + lane;
+    for (int j0 = 0; j0 < w; j0 += kSoaCols) {
+        const int jn = min(kSoaCols, w - j0);
+        double acc[kSoaCols][NR];
+#pragma unroll
+        for (int jj = 0; jj < kSoaCols; jj++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[jj][r] = 0.0;
+        for (int i0 = rb; i0 < re; i0 += RU) {
+            double x[RU][NR];
+            T l[RU][kSoaCols];
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int i = i0 + u;
+                const double *xi = yb + int64_t(i < re ? R[i] : 0) * nrhs * 64;
+#pragma unroll
+                for (int r = 0; r < NR; r++) x[u][r] = i < re ? xi[r * 64] : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < kSoaCols; jj++)
+                    l[u][jj] = (i < re && jj < jn) ? Lb[(int64_t(j0 + jj) * c + i) * 64] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+#pragma unroll
+                for (int jj = 0; jj < kSoaCols; jj++)
+#pragma unroll
+                    for (int r = 0; r < NR; r++) acc[jj][r] += double(l[u][jj]) * x[u][r];
+        }
+#pragma unroll
+        for (int jj = 0; jj < kSoaCols; jj++)
+            if (jj < jn)
+#pragma unroll
+                for (int r = 0; r < NR; r++) pb[(int64_t(j0 + jj) * nrhs + r) * 64] = acc[jj][r];
+    }
+}
+
+// Backward, diagonal blocks: one wave per (supernode, group).  Column
+// chunks of 16 from the last: rhs_j = y_j - (row-block partial sums, in
+// block order) - (the supernode's own later rows, descending), then the
+// chunk's triangle from its last column (x_j = rhs_j / L_jj, subtracted
+// from the earlier columns of the chunk).  Every column sees the same
+// sequence of operations as in the row-major kernels.
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_bwd_soa_diag(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys,
+    const double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    const SnDesc d = sn[list[blockIdx.x]];
+    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int c = d.c, w = d.w;
+    const int nblk = (c - w + kSoaRows - 1) / kSoaRows;
+    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
+    double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    const double *pb = PS + ((int64_t(bg) * psize + d.part) * nrhs + r0) * 64 + lane;
+    for (int j0 = ((w - 1) / kSoaCols) * kSoaCols; j0 >= 0; j0 -= kSoaCols) {
+        const int jn = min(kSoaCols, w - j0);
+        double acc[kSoaCols][NR];
+#pragma unroll
+        for (int jj = 0; jj < kSoaCols; jj++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                double a = 0.0;
+                if (jj < jn) {
+                    a = yb[(int64_t(d.first + j0 + jj) * nrhs + r) * 64];
+                    for (int k = 0; k < nblk; k++)
+                        a -= pb[(int64_t(k) * w + j0 + jj) * nrhs * 64 + r * 64];
+                }
+                acc[jj][r] = a;
+            }
+        for (int i = w - 1; i >= j0 + kSoaCols; i--) {  // descending, as in the other layout
+            double x[NR];
+#pragma unroll
+            for (int r = 0; r < NR; r++) x[r] = yb[(int64_t(d.first + i) * nrhs + r) * 64];
+#pragma unroll
+            for (int jj = 0; jj < kSoaCols; jj++) {
+                if (jj < jn) {
+                    const double l = double(Lb[(int64_t(j0 + jj) * c + i) * 64]);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) acc[jj][r] -= l * x[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int jj = kSoaCols - 1; jj >= 0; jj--) {
+            if (jj < jn) {
+                const int j = j0 + jj;
+                const double rinv = 1.0 / double(Lb[(int64_t(j) * c + j) * 64]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    acc[jj][r] *= rinv;
+                    yb[(int64_t(d.first + j) * nrhs + r) * 64] = acc[jj][r];
+                }
+#pragma unroll
+                for (int kk = 0; kk < jj; kk++) {
+                    const double l = double(Lb[(int64_t(j0 + kk) * c + j) * 64]);
+#pragma unroll
+                    for (int r = 0; r < NR; r++) acc[kk][r] -= l * acc[jj][r];
+                }
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -580,206 +994,308 @@ hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
     return hipGetLastError();
 }
 
+// One launch of the segment kernels for row class k.
+template <typename T, int NR>
+void launch_fwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_plan *P,
+                      const sc_numeric *N, const SClass &cl, int nitems, int r0, int nrhs,
+                      int64_t fvsize, const int32_t *active) {
+    const T *L = static_cast<const T *>(N->L);
+    const int32_t *lst = D->slv_small + cl.list0;
+#define SPCHOL_FWDS(G, SL)                                                                   \
+    hipLaunchKernelGGL((k_fwd_seg<T, G, SL, NR>), g, dim3(256), 0, st, D->sn, lst, cl.n,      \
+                       nitems, r0, D->gptr, D->gidx, L, P->Lsize, N->ws_y, N->ws_u, P->n,     \
+                       fvsize, nrhs, active)
+    switch (k) {
+    case 0: SPCHOL_FWDS(16, 1); break;
+    case 1: SPCHOL_FWDS(32, 1); break;
+    case 2: SPCHOL_FWDS(64, 1); break;
+    case 3: SPCHOL_FWDS(64, 2); break;
+    case 4: SPCHOL_FWDS(64, 4); break;
+    default: SPCHOL_FWDS(64, 8); break;
+    }
+#undef SPCHOL_FWDS
+}
+
+template <typename T, int NR>
+void launch_bwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_plan *P,
+                      const sc_numeric *N, const SClass &cl, int nitems, int r0, int nrhs,
+                      const int32_t *active) {
+    const T *L = static_cast<const T *>(N->L);
+    const int32_t *lst = D->slv_small + cl.list0;
+#define SPCHOL_BWDS(G)                                                                       \
+    hipLaunchKernelGGL((k_bwd_seg<T, G, NR>), g, dim3(256), 0, st, D->sn, lst, cl.n, nitems,  \
+                       r0, D->rows, L, P->Lsize, N->ws_y, P->n, nrhs, active)
+    if (k == 0) SPCHOL_BWDS(16);
+    else if (k == 1) SPCHOL_BWDS(32);
+    else SPCHOL_BWDS(64);
+#undef SPCHOL_BWDS
+}
+
+inline int class_lanes(int k) { return k == 0 ? 16 : k == 1 ? 32 : 64; }
+
+// Panel-solved supernodes of one level, forward (gather with y_0, then one
+// launch per panel) and backward (per panel from the last: partial sums
+// below the panel, then the panel's own solve), in either vector layout.
+template <typename T, bool SOA>
+void panels_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                    const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const int B = N->batch;
+    const int64_t fvsize = int64_t(P->rows.size());
+    Profiler &prof = N->prof;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    prof.begin(KK_FwdPanel, 0.0, l.v_pan * nr * nb, st);
+    hipLaunchKernelGGL(k_pan_gather<SOA>, dim3(unsigned(l.npan), unsigned(B)), dim3(256), 0, st,
+                       D->sn, D->slv_pan + l.pan0, D->gptr, D->gidx, N->dinv, P->dinv_size,
+                       N->ws_y, N->ws_u, P->n, fvsize, nrhs, active);
+    prof.end(st);
+    for (size_t q = 0; q < l.panels.size(); q++) {
+        const SPanel &pp = l.panels[q];
+        if (pp.fwd_tiles == 0) continue;
+        prof.begin(KK_FwdPanel, pp.flops * nr * nb,
+                   (pp.words * sz + pp.dbytes + pp.vbytes * nr) * nb, st);
+        const dim3 g(unsigned(pp.fwd_tiles), unsigned(l.npan), unsigned(B));
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_FWDP(NRV)                                                                       \
+    hipLaunchKernelGGL((k_fwd_panel<T, NRV, SOA>), g, dim3(64), 0, st, D->sn,                  \
+                       D->slv_pan + l.pan0, int(q), r0, L, P->Lsize, N->dinv, P->dinv_size,     \
+                       N->ws_y, N->ws_u, P->n, fvsize, nrhs, active)
+            if (nrr == 1) SPCHOL_FWDP(1);
+            else if (nrr == 2) SPCHOL_FWDP(2);
+            else if (nrr == 3) SPCHOL_FWDP(3);
+            else SPCHOL_FWDP(4);
+#undef SPCHOL_FWDP
+        }
+        prof.end(st);
+    }
+}
+
+template <typename T, bool SOA>
+void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                     const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const int B = N->batch;
+    Profiler &prof = N->prof;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    for (size_t q = l.panels.size(); q-- > 0;) {
+        const SPanel &pp = l.panels[q];
+        prof.begin(KK_BwdPanel, pp.flops * nr * nb,
+                   (pp.words * sz + pp.dbytes + pp.vbytes * nr) * nb, st);
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+            const dim3 gp(unsigned(pp.bwd_chunks), unsigned(l.npan), unsigned(B));
+            const dim3 gf(unsigned(l.npan), unsigned(B));
+#define SPCHOL_BWDP(NRV)                                                                         \
+    do {                                                                                         \
+        if (pp.bwd_chunks > 0)                                                                   \
+            hipLaunchKernelGGL((k_bwd_pan_part<T, NRV, SOA>), gp, dim3(256), 0, st, D->sn,       \
+                               D->slv_pan + l.pan0, int(q), r0, D->rows, L, P->Lsize, N->ws_y,   \
+                               P->n, N->ws_part, P->part_size, nrhs, active);                    \
+        hipLaunchKernelGGL((k_bwd_pan_fin<NRV, SOA>), gf, dim3(64), 0, st, D->sn,                \
+                           D->slv_pan + l.pan0, int(q), r0, N->dinv, P->dinv_size, N->ws_y,      \
+                           P->n, N->ws_part, P->part_size, nrhs, active);                        \
+    } while (0)
+            if (nrr == 1) SPCHOL_BWDP(1);
+            else if (nrr == 2) SPCHOL_BWDP(2);
+            else if (nrr == 3) SPCHOL_BWDP(3);
+            else SPCHOL_BWDP(4);
+#undef SPCHOL_BWDP
+        }
+        prof.end(st);
+    }
+}
+
+// Batch-interleaved solve (groups of 64 matrices, lane = matrix).
+template <typename T>
+hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, int64_t ldb,
+                     hipStream_t st, const int32_t *active) {
+    DevPlan *D = P->dev;
+    const int B = N->batch;
+    const unsigned G = unsigned((B + 63) / 64);
+    const int64_t fvsize = int64_t(P->rows.size());
+    const T *Ls = static_cast<const T *>(N->Ls);
+    Profiler &prof = N->prof;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    if (!N->ls_ok) {
+        const size_t nch = P->soa_chunks.size();
+        prof.begin(KK_Perm, 0.0, 2.0 * sz * nb * double(nch) * kSoaChunk, st);
+        if (nch > 0)
+            hipLaunchKernelGGL(k_to_soa<T>, dim3(unsigned(nch), G), dim3(256), 0, st,
+                               static_cast<const T *>(N->L), P->Lsize, D->soa_chunks, B,
+                               static_cast<T *>(N->Ls));
+        prof.end(st);
+        N->ls_ok = true;
+    }
+    const dim3 pgrid(unsigned((P->n + 63) / 64), G);
+    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_in_soa, pgrid, dim3(256), 0, st, D->perm, b, ldb, N->ws_y, P->n,
+                       nrhs, B);
+    prof.end(st);
+    for (const SLaunch &l : D->ssched) {
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_SOAF(NRV)                                                                        \
+    do {                                                                                        \
+        if (l.nall > 0)                                                                         \
+            hipLaunchKernelGGL((k_fwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, \
+                               st, D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls,          \
+                               P->Lsize, N->ws_y, N->ws_u, P->n, fvsize, nrhs, r0);              \
+        if (l.nit > 0)                                                                          \
+            hipLaunchKernelGGL((k_fwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0,  \
+                               st, D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->gptr,   \
+                               D->gidx, Ls, P->Lsize, N->ws_y, N->ws_u, P->n, fvsize, nrhs, r0); \
+    } while (0)
+            if (l.nall == 0) break;
+            if (r0 == 0)
+                prof.begin(KK_Fwd, (l.f_diag + l.f_rows) * nr * nb,
+                           ((l.w_diag + l.w_rows) * sz + (l.v_diag + l.v_rows) * nr) * nb, st);
+            if (nrr == 1) SPCHOL_SOAF(1);
+            else if (nrr == 2) SPCHOL_SOAF(2);
+            else if (nrr == 3) SPCHOL_SOAF(3);
+            else SPCHOL_SOAF(4);
+#undef SPCHOL_SOAF
+            if (r0 + 4 >= nrhs) prof.end(st);
+        }
+        if (l.npan > 0) panels_forward<T, true>(l, P, N, nrhs, nullptr, st);
+    }
+    for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
+        const SLaunch &l = *it;
+        if (l.npan > 0) panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_SOAB(NRV)                                                                        \
+    do {                                                                                        \
+        if (l.nit > 0)                                                                          \
+            hipLaunchKernelGGL((k_bwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0,  \
+                               st, D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->rows,   \
+                               Ls, P->Lsize, N->ws_y, N->ws_ps, P->soa_psize, P->n, nrhs, r0);   \
+        hipLaunchKernelGGL((k_bwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st, \
+                           D->sn, D->slv_small + l.all0, Ls, P->Lsize, N->ws_y, N->ws_ps,       \
+                           P->soa_psize, P->n, nrhs, r0);                                        \
+    } while (0)
+            if (l.nall == 0) break;
+            if (r0 == 0)
+                prof.begin(KK_Bwd, (l.f_diag + l.f_rows) * nr * nb,
+                           ((l.w_diag + l.w_rows) * sz + (l.v_diag + l.v_rows) * nr) * nb, st);
+            if (nrr == 1) SPCHOL_SOAB(1);
+            else if (nrr == 2) SPCHOL_SOAB(2);
+            else if (nrr == 3) SPCHOL_SOAB(3);
+            else SPCHOL_SOAB(4);
+#undef SPCHOL_SOAB
+            if (r0 + 4 >= nrhs) prof.end(st);
+        }
+    }
+    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_out_soa, pgrid, dim3(256), 0, st, D->pinv, N->ws_y, b, ldb, P->n,
+                       nrhs, B, active);
+    prof.end(st);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
                       int64_t ldb, hipStream_t st, const int32_t *active) {
     DevPlan *D = P->dev;
-    for (const SLaunch &l : D->ssched) {
-        if (size_t(l.maxc_pan) * sizeof(double) > size_t(g_max_lds)) return hipErrorInvalidValue;
-        if (size_t(16) * l.maxc_small * sizeof(double) > size_t(g_max_lds))
-            return hipErrorInvalidValue;
-        if (l.maxc_small > 64 * kWaveSlots) return hipErrorInvalidValue;
-    }
     const T *L = static_cast<const T *>(N->L);
-    const int nbr = N->batch * nrhs;
-    const unsigned gy = unsigned(nbr);
+    const int B = N->batch;
     const int64_t fvsize = int64_t(P->rows.size());
     Profiler &prof = N->prof;
-    const double sz = double(sizeof(T)), nr = double(gy);
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    const dim3 pgrid(unsigned((P->n + 255) / 256), unsigned(B));
+    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_in, pgrid, dim3(256), 0, st, D->perm, b, ldb, N->ws_y, P->n, nrhs,
+                       active);
+    prof.end(st);
+    // forward: levels ascending
     for (const SLaunch &l : D->ssched) {
-        if (l.nlane > 0) {
-            prof.begin(KK_Fwd, l.f_lane * nr, (l.w_lane * sz * N->batch + l.v_lane * nr), st);
-            const int nitems = l.nlane * nbr;
-            const dim3 g(unsigned((nitems + 255) / 256));
-#define SPCHOL_FWDL(CM)                                                                      \
-    hipLaunchKernelGGL((k_fwd_lane<T, CM>), g, dim3(256), 0, st, D->sn,                       \
-                       D->slv_small + l.lane0, l.nlane, nitems, D->perm, D->gptr, D->gidx, L, \
-                       P->Lsize, b, ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, active)
-            if (l.maxc_lane <= 16) SPCHOL_FWDL(16);
-            else SPCHOL_FWDL(32);
-#undef SPCHOL_FWDL
-            prof.end(st);
-        }
-        if (l.nsmall > 0) {
-            prof.begin(KK_Fwd, l.f_small * nr, (l.w_small * sz * N->batch + l.v_small * nr), st);
-            const int nitems = l.nsmall * N->batch;
+        for (int k = 0; k < kSolveClasses; k++) {
+            const SClass &cl = l.cls[k];
+            if (cl.n == 0) continue;
+            prof.begin(KK_Fwd, cl.flops * nr * nb, cl.words * sz * nb + cl.vbytes * nr * nb, st);
+            const int nitems = cl.n * B;
+            const int nseg = 256 / class_lanes(k);
+            const dim3 g(unsigned((nitems + nseg - 1) / nseg));
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
-                const size_t lds = size_t(4) * nrr * l.maxc_small * sizeof(double);
-                const dim3 g(unsigned((nitems + 3) / 4));
-                const int32_t *lst = D->slv_small + l.small0;
-                const int sl = l.maxc_small <= 64 ? 1 : l.maxc_small <= 128 ? 2
-                             : l.maxc_small <= 256 ? 4 : 8;
-#define SPCHOL_FWD(NRV, SLV)                                                                \
-    hipLaunchKernelGGL((k_fwd_wave<T, NRV, SLV>), g, dim3(256), lds, st, D->sn, lst,        \
-                       l.nsmall, nitems, r0, D->perm, D->relmap, D->chlist, L, P->Lsize, b,  \
-                       ldb, N->ws_y, N->ws_u, P->n, fvsize, nrhs, l.maxc_small, active)
-#define SPCHOL_FWD_SL(NRV)                                                                  \
-    if (sl == 1) SPCHOL_FWD(NRV, 1);                                                        \
-    else if (sl == 2) SPCHOL_FWD(NRV, 2);                                                   \
-    else if (sl == 4) SPCHOL_FWD(NRV, 4);                                                   \
-    else SPCHOL_FWD(NRV, 8)
-                if (nrr == 1) { SPCHOL_FWD_SL(1); }
-                else if (nrr == 2) { SPCHOL_FWD_SL(2); }
-                else if (nrr == 3) { SPCHOL_FWD_SL(3); }
-                else { SPCHOL_FWD_SL(4); }
-#undef SPCHOL_FWD_SL
-#undef SPCHOL_FWD
+                if (nrr == 1) launch_fwd_class<T, 1>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
+                else if (nrr == 2) launch_fwd_class<T, 2>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
+                else if (nrr == 3) launch_fwd_class<T, 3>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
+                else launch_fwd_class<T, 4>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
             }
             prof.end(st);
         }
-        if (l.npan > 0) {
-            prof.begin(KK_Fwd, 0.0, l.v_pan * nr, st);
-            hipLaunchKernelGGL(k_fwd_gather, dim3(unsigned(l.npan), gy), dim3(256),
-                               size_t(l.maxc_pan) * sizeof(double), st, D->sn,
-                               D->slv_pan + l.pan0, D->perm, D->relmap, D->chlist, b, ldb,
-                               N->ws_u, fvsize, nrhs, active);
-            prof.end(st);
-            for (size_t q = 0; q < l.panels.size(); q++) {
-                const SPanel &pp = l.panels[q];
-                prof.begin(KK_FwdPanel, pp.flops * nr, (pp.words * sz + pp.vbytes) * nr, st);
-                hipLaunchKernelGGL(k_fwd_panel<T>,
-                                   dim3(unsigned(1 + pp.fwd_tiles), unsigned(l.npan), gy),
-                                   dim3(64), 0, st, D->sn, D->slv_pan + l.pan0, int(q), L,
-                                   P->Lsize, N->dinv, P->dinv_size, N->ws_y, N->ws_u, P->n,
-                                   fvsize, nrhs, active);
-                prof.end(st);
-            }
-        }
+        if (l.npan > 0) panels_forward<T, false>(l, P, N, nrhs, active, st);
     }
+    // backward: levels descending
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
-        if (l.npan > 0) {
-            for (size_t q = l.panels.size(); q-- > 0;) {
-                const SPanel &pp = l.panels[q];
-                prof.begin(KK_BwdPanel, pp.flops * nr,
-                           pp.words * sz * N->batch + pp.vbytes * nr, st);
-                for (int r0 = 0; r0 < nrhs; r0 += 4) {
-                    const int nrr = std::min(4, nrhs - r0);
-                    const dim3 g(unsigned(pp.bwd_chunks), unsigned(l.npan), unsigned(N->batch));
-#define SPCHOL_BWDP(NRV)                                                                       \
-    hipLaunchKernelGGL((k_bwd_panel<T, NRV>), g, dim3(256), 0, st, D->sn, D->slv_pan + l.pan0, \
-                       l.pan0, int(q), r0, D->perm, D->rows, L, P->Lsize, N->dinv, P->dinv_size, \
-                       b, ldb, N->ws_y, P->n, N->ws_part, P->part_size, N->ws_cnt, N->batch,    \
-                       nrhs, active)
-                    if (nrr == 1) SPCHOL_BWDP(1);
-                    else if (nrr == 2) SPCHOL_BWDP(2);
-                    else if (nrr == 3) SPCHOL_BWDP(3);
-                    else SPCHOL_BWDP(4);
-#undef SPCHOL_BWDP
-                }
-                prof.end(st);
-            }
-        }
-        if (l.nsmall > 0) {
-            prof.begin(KK_Bwd, l.f_small * nr, (l.w_small * sz * N->batch + l.v_small * nr), st);
-            const int nitems = l.nsmall * N->batch;
+        if (l.npan > 0) panels_backward<T, false>(l, P, N, nrhs, active, st);
+        for (int k = kSolveClasses - 1; k >= 0; k--) {
+            const SClass &cl = l.cls[k];
+            if (cl.n == 0) continue;
+            prof.begin(KK_Bwd, cl.flops * nr * nb, cl.words * sz * nb + cl.vbytes * nr * nb, st);
+            const int nitems = cl.n * B;
+            const int nseg = 256 / class_lanes(k);
+            const dim3 g(unsigned((nitems + nseg - 1) / nseg));
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
-                const dim3 g(unsigned((nitems + 3) / 4));
-                const int32_t *lst = D->slv_small + l.small0;
-                const int sl = l.maxc_small <= 64 ? 1 : l.maxc_small <= 128 ? 2
-                             : l.maxc_small <= 256 ? 4 : 8;
-#define SPCHOL_BWD(NRV, SLV)                                                                 \
-    hipLaunchKernelGGL((k_bwd_wave<T, NRV, SLV>), g, dim3(256), 0, st, D->sn, lst, l.nsmall, \
-                       nitems, r0, D->perm, D->rows, L, P->Lsize, b, ldb, N->ws_y, P->n,     \
-                       nrhs, active)
-#define SPCHOL_BWD_SL(NRV)                                                                   \
-    if (sl == 1) SPCHOL_BWD(NRV, 1);                                                         \
-    else if (sl == 2) SPCHOL_BWD(NRV, 2);                                                    \
-    else if (sl == 4) SPCHOL_BWD(NRV, 4);                                                    \
-    else SPCHOL_BWD(NRV, 8)
-                if (nrr == 1) { SPCHOL_BWD_SL(1); }
-                else if (nrr == 2) { SPCHOL_BWD_SL(2); }
-                else if (nrr == 3) { SPCHOL_BWD_SL(3); }
-                else { SPCHOL_BWD_SL(4); }
-#undef SPCHOL_BWD_SL
-#undef SPCHOL_BWD
+                if (nrr == 1) launch_bwd_class<T, 1>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
+                else if (nrr == 2) launch_bwd_class<T, 2>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
+                else if (nrr == 3) launch_bwd_class<T, 3>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
+                else launch_bwd_class<T, 4>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
             }
-            prof.end(st);
-        }
-        if (l.nlane > 0) {
-            prof.begin(KK_Bwd, l.f_lane * nr, (l.w_lane * sz * N->batch + l.v_lane * nr), st);
-            const int nitems = l.nlane * nbr;
-            const dim3 g(unsigned((nitems + 255) / 256));
-#define SPCHOL_BWDL(CM)                                                                      \
-    hipLaunchKernelGGL((k_bwd_lane<T, CM>), g, dim3(256), 0, st, D->sn,                       \
-                       D->slv_small + l.lane0, l.nlane, nitems, D->perm, D->rows, L,          \
-                       P->Lsize, b, ldb, N->ws_y, P->n, nrhs, active)
-            if (l.maxc_lane <= 16) SPCHOL_BWDL(16);
-            else SPCHOL_BWDL(32);
-#undef SPCHOL_BWDL
             prof.end(st);
         }
     }
+    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_out, pgrid, dim3(256), 0, st, D->pinv, N->ws_y, b, ldb, P->n, nrhs,
+                       active);
+    prof.end(st);
     return hipGetLastError();
-}
-
-template <typename T, int NR>
-void set_fwd_wave_lds(int big) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 1>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 2>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 4>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_wave<T, NR, 8>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-}
-
-template <typename T>
-void set_solve_lds(int big) {
-    set_fwd_wave_lds<T, 1>(big);
-    set_fwd_wave_lds<T, 2>(big);
-    set_fwd_wave_lds<T, 3>(big);
-    set_fwd_wave_lds<T, 4>(big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_gather),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 }  // namespace
 
 // Solve schedule per level, with the algorithmic work of each launch (per
-// matrix and right-hand side).
+// matrix; vector bytes per right-hand side).
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
     D->ssched.clear();
     for (int32_t l = 0; l < P->nlevels; l++) {
         SLaunch s{};
         s.level = l;
-        s.lane0 = P->slv_small_ptr[l];
-        s.nlane = P->slv_lane_n[l];
-        s.maxc_lane = P->slv_lane_maxc[l];
-        s.small0 = s.lane0 + s.nlane;
-        s.nsmall = P->slv_small_ptr[l + 1] - s.small0;
-        for (int32_t e = s.lane0; e < s.lane0 + s.nlane; e++) {
+        for (int k = 0; k < kSolveClasses; k++) {
+            SClass &cl = s.cls[k];
+            cl.list0 = P->slv_cls_ptr[size_t(l) * kSolveClasses + k];
+            cl.n = P->slv_cls_ptr[size_t(l) * kSolveClasses + k + 1] - cl.list0;
+            for (int32_t e = cl.list0; e < cl.list0 + cl.n; e++) {
+                const SnDesc &d = P->sn[P->slv_small[e]];
+                const double lw = double(d.c) * d.w - double(d.w) * (d.w - 1) / 2;
+                cl.flops += 2.0 * lw;
+                cl.words += lw;
+                // the front vector in and out (8 B each) and its row indices
+                cl.vbytes += 8.0 * (2.0 * d.c) + 4.0 * d.c;
+            }
+        }
+        s.all0 = P->slv_cls_ptr[size_t(l) * kSolveClasses];
+        s.nall = P->slv_cls_ptr[size_t(l + 1) * kSolveClasses] - s.all0;
+        s.it0 = P->soa_it_ptr[l];
+        s.nit = P->soa_it_ptr[l + 1] - s.it0;
+        for (int32_t e = s.all0; e < s.all0 + s.nall; e++) {
             const SnDesc &d = P->sn[P->slv_small[e]];
-            const double lw = double(d.c) * d.w - double(d.w) * (d.w - 1) / 2;
-            s.f_lane += 2.0 * lw;
-            s.w_lane += lw;
-            s.v_lane += 8.0 * (2.0 * d.c + d.m) + 4.0 * d.c;
+            const double tri = double(d.w) * (d.w + 1) / 2, rect = double(d.m) * d.w;
+            s.f_diag += 2.0 * tri;
+            s.w_diag += tri;
+            s.v_diag += 8.0 * 2.0 * d.w + 4.0 * d.w;
+            s.f_rows += 2.0 * rect;
+            s.w_rows += rect;
+            s.v_rows += 8.0 * 2.0 * d.m + 4.0 * d.m;
         }
         s.pan0 = P->slv_pan_ptr[l];
         s.npan = P->slv_pan_ptr[l + 1] - s.pan0;
-        s.maxc_small = P->slv_small_maxc[l];
         s.maxc_pan = P->slv_pan_maxc[l];
-        s.maxc = std::max(s.maxc_small, s.maxc_pan);
-        for (int32_t e = s.small0; e < s.small0 + s.nsmall; e++) {
-            const SnDesc &d = P->sn[P->slv_small[e]];
-            const double lw = double(d.c) * d.w - double(d.w) * (d.w - 1) / 2;
-            s.f_small += 2.0 * lw;
-            s.w_small += lw;
-            s.v_small += 8.0 * (2.0 * d.c + d.m) + 4.0 * d.c;
-        }
         for (int32_t e = s.pan0; e < s.pan0 + s.npan; e++) {
             const SnDesc &d = P->sn[P->slv_pan[e]];
             s.v_pan += 8.0 * (2.0 * d.c) + 4.0 * d.c;
@@ -794,12 +1310,12 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
                 const int kb = std::min(kP, d.w - c0);
                 const int64_t below = d.c - c0 - kb;
                 pp.fwd_tiles = std::max<int64_t>(pp.fwd_tiles, (below + kP - 1) / kP);
-                pp.bwd_chunks = std::max<int64_t>(
-                    pp.bwd_chunks, std::max<int64_t>(1, (below + kSolveChunk - 1) / kSolveChunk));
+                pp.bwd_chunks = std::max<int64_t>(pp.bwd_chunks, (below + kSolveChunk - 1) / kSolveChunk);
                 const double lw = double(below) * kb;
                 pp.flops += 2.0 * lw + 2.0 * kb * kb;
                 pp.words += lw;
-                pp.vbytes += 8.0 * (below + 2.0 * kb) + 8.0 * kb * kb;
+                pp.vbytes += 8.0 * (below + 2.0 * kb);
+                pp.dbytes += 8.0 * kb * kb;
             }
             s.panels.push_back(pp);
         }
@@ -807,12 +1323,7 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
     }
 }
 
-hipError_t spchol_solve_init() {
-    set_solve_lds<double>(g_max_lds);
-    set_solve_lds<float>(g_max_lds);
-    (void)hipGetLastError();
-    return hipSuccess;
-}
+hipError_t spchol_solve_init() { return hipSuccess; }
 
 hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
     if (N->dtype == SC_F64) return dinv_impl<double>(P, N, st);
@@ -821,6 +1332,10 @@ hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
 
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
                             int64_t ldb, hipStream_t st, const int32_t *active) {
+    if (N->soa) {
+        if (N->dtype == SC_F64) return solve_soa<double>(P, N, b, nrhs, ldb, st, active);
+        return solve_soa<float>(P, N, b, nrhs, ldb, st, active);
+    }
     if (N->dtype == SC_F64) return solve_impl<double>(P, N, b, nrhs, ldb, st, active);
     return solve_impl<float>(P, N, b, nrhs, ldb, st, active);
 }
