@@ -251,6 +251,9 @@ def main():
     ap.add_argument("--workload", default="trimesh512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events")
+    ap.add_argument("--soa-min-batch", type=int, default=None,
+                    help="batch size from which solves use the batch-interleaved layout "
+                         "(library default when omitted, negative: never)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
@@ -274,10 +277,12 @@ def main():
     p = w.pattern
     log("workload %s n=%d nnzA=%d batch=%d nrhs=%d" % (wname, n, nnz, w.batch, w.nrhs))
     t = time.perf_counter()
+    opts = {} if args.soa_min_batch is None else {"soa_min_batch": args.soa_min_batch}
     if members is not None:
-        plan = S.analyze_group([(m.pattern.colptr, m.pattern.rowind, m.perm) for m in members])
+        plan = S.analyze_group([(m.pattern.colptr, m.pattern.rowind, m.perm) for m in members],
+                               **opts)
     else:
-        plan = S.analyze(p.colptr, p.rowind, w.perm)
+        plan = S.analyze(p.colptr, p.rowind, w.perm, **opts)
     info = plan.info()
     nblk = info["nblocks"]
     log("analyze %.2f s: nnzL=%d supernodes=%d levels=%d flops=%.3e" % (

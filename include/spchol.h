@@ -69,8 +69,8 @@ typedef struct {
     int32_t soa_min_batch; /* numeric objects with at least this many
                              matrices solve in the batch-interleaved layout
                              (one matrix per lane; L is copied once per
-                             factorization); 0 = library default (off),
-                             a negative value never                         */
+                             factorization); 0 = library default (64, a
+                             whole group of lanes), a negative value never                         */
 } sc_options;
 
 /* Sizes of a plan (per matrix of a batch). */

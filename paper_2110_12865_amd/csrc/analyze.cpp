@@ -502,6 +502,7 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         }
         // batch-interleaved solve items and the chunks of the L copy
         P->soa_it_ptr.assign(nlev + 1, 0);
+        P->grow_ptr.assign(nlev + 1, 0);
         P->soa_psize = 0;
         {
             std::vector<std::pair<int64_t, int64_t>> iv;
@@ -519,6 +520,15 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                     iv.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
                 }
                 P->soa_it_ptr[l + 1] = int32_t(P->soa_it_s.size());
+                for (int32_t e = P->slv_cls_ptr[size_t(l) * kSolveClasses];
+                     e < P->slv_cls_ptr[size_t(l + 1) * kSolveClasses]; e++) {
+                    const SnDesc &d = P->sn[P->slv_small[e]];
+                    for (int32_t i = 0; i < d.c; i++) {
+                        P->grow_q.push_back(int32_t(d.rowptr + i));
+                        P->grow_y.push_back(i < d.w ? d.first + i : -1);
+                    }
+                }
+                P->grow_ptr[l + 1] = int32_t(P->grow_q.size());
             }
             std::sort(iv.begin(), iv.end());
             int64_t covered = 0;  // every scalar below this is already covered

@@ -42,7 +42,7 @@ void free_devplan(DevPlan *D) {
                     D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
                     D->slv_small, D->slv_pan, D->big_colent, D->big_chmap_off,
                     D->big_chmap, D->colblk, D->blk_col0, D->gptr, D->gidx,
-                    D->soa_it_s, D->soa_it_r0, D->soa_chunks};
+                    D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete D;
@@ -89,6 +89,8 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->soa_it_s, P->soa_it_s);
     if (e == hipSuccess) e = upload(&D->soa_it_r0, P->soa_it_r0);
     if (e == hipSuccess) e = upload(&D->soa_chunks, P->soa_chunks);
+    if (e == hipSuccess) e = upload(&D->grow_q, P->grow_q);
+    if (e == hipSuccess) e = upload(&D->grow_y, P->grow_y);
     if (e == hipSuccess) e = upload(&D->blk_col0, P->blk_col0);
     if (e != hipSuccess) {
         free_devplan(D);

@@ -56,6 +56,8 @@ struct SLaunch {  // one level of a triangular solve
     // panels, and their row-block items
     int32_t all0 = 0, nall = 0;
     int32_t it0 = 0, nit = 0;
+    int32_t grow0 = 0, ngrow = 0;     // gather rows of those supernodes
+    double v_gather = 0.0;            // their bytes per right-hand side
     double f_diag = 0.0, w_diag = 0.0, v_diag = 0.0;  // diagonal blocks
     double f_rows = 0.0, w_rows = 0.0, v_rows = 0.0;  // rows below them
     int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
@@ -89,6 +91,8 @@ struct DevPlan {
     int32_t *soa_it_s = nullptr;      // batch-interleaved solve items
     int32_t *soa_it_r0 = nullptr;
     int64_t *soa_chunks = nullptr;    // chunk starts of the interleaved L copy
+    int32_t *grow_q = nullptr;        // forward gather rows
+    int32_t *grow_y = nullptr;
     int32_t *gptr = nullptr;          // forward-solve gather map
     int32_t *gidx = nullptr;
     int32_t *colblk = nullptr;        // block of every column

@@ -345,93 +345,103 @@ __global__ __launch_bounds__(256) void k_assemble_wave(
     }
 }
 
+// Value of lane `src` (wave-uniform) broadcast to the whole wave.
+template <typename T>
+__device__ inline T lane_bcast(T v, int src);
+template <>
+__device__ inline double lane_bcast<double>(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane(int(u >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                (static_cast<unsigned int>(lo)));
+}
+template <>
+__device__ inline float lane_bcast<float>(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Factor and invert the kb x kb diagonal block (kb <= 64) whose top-left
 // corner is (r0, r0) of a column-major L block, with one workgroup of 256
-// threads.  The block sits in LDS (S, row-major, stride 65) next to the
-// inverse X = L^{-1} (X, same layout), built in the same sweep: step j
-// scales column j of L by 1 / L_jj and row j of X by the same, then
-// subtracts L_ij L_tj from the trailing entries (i >= t > j) and L_ij X_jc
-// from the rows i > j of X.  Thread (lane, wave g) owns row `lane` for the
-// trailing update and column `lane` of X, columns / rows congruent to g
-// mod 4.  The loops are not unrolled: the kernel body stays far below the
-// instruction cache.  The factor is written back (zeros above the
-// diagonal) and the inverse to PIg column-major (PIg[c * 64 + i] = X[i][c]).
-// A pivot that fails d > 0 is recorded (smallest 1-based step wins) and
-// replaced by 1.
-constexpr int kDiagLd = kTile + 1;
-constexpr int kDiagLds = 2 * kTile * kDiagLd + kTile;  // S, X, diagonal
+// threads.  Lane i of wave g keeps row i of columns 16 g .. 16 g + 15, of
+// the block (f) and of its inverse X = L^{-1} (x), in registers.  Step j:
+// the wave owning column j forms the pivot and column j of L and publishes
+// it; lane j publishes its (unscaled) row of X; after one barrier every
+// thread subtracts L_ij L_tj from its columns t > j and L_ij X_jc from its
+// row of X (rows i > j), and lane j scales its row of X by 1 / L_jj (X_jc
+// L_ij / L_jj is formed as (L_ij / L_jj) X_jc).  The
+// published vectors are double-buffered, so a step needs one barrier.  A
+// pivot that fails d > 0 is recorded (smallest 1-based step wins) and
+// replaced by 1.  The factor is written back (zeros above the diagonal) and
+// the inverse to PIg column-major (PIg[col * 64 + i] = X[i][col]).
+constexpr int kDiagLds = 4 * kTile + 2;  // two column buffers, two X-row buffers, 1/L_jj x 2
 
 template <typename T>
-__device__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, int col0,
+__device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, int col0,
                                int32_t *info_b) {
-    T *S = lds, *X = lds + kTile * kDiagLd, *dg = lds + 2 * kTile * kDiagLd;
+    T *cb = lds, *xr = lds + 2 * kTile, *rv = lds + 4 * kTile;
     const int tid = threadIdx.x, li = tid & 63, g = tid >> 6;
-    {
-        // 16 loads per thread in flight at once (consecutive threads: rows)
-        T v[16];
+    T f[16], x[16];
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int e = tid + 256 * q, t = e >> 6, i = e & 63;
-            v[q] = (i < kb && t < kb) ? Lb[int64_t(r0 + t) * c + r0 + i] : (i == t ? T(1) : T(0));
-        }
+    for (int tt = 0; tt < 16; tt++) {
+        const int col = 16 * g + tt;
+        f[tt] = (li < kb && col < kb) ? Lb[int64_t(r0 + col) * c + r0 + li] : (li == col ? T(1) : T(0));
+        x[tt] = li == col ? T(1) : T(0);
+    }
+    for (int J = 0; J < 4; J++) {
+        if (16 * J >= kb) break;
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int e = tid + 256 * q, t = e >> 6, i = e & 63;
-            S[i * kDiagLd + t] = v[q];
-            X[i * kDiagLd + t] = i == t ? T(1) : T(0);
+        for (int jj = 0; jj < 16; jj++) {
+            const int j = 16 * J + jj;
+            if (j < kb) {
+                const int buf = j & 1;
+                if (g == J) {
+                    T djj = lane_bcast(f[jj], j);
+                    const bool bad = !(djj > T(0));
+                    if (bad) djj = T(1);
+                    const T ljj = dsqrt(djj);
+                    const T rinv = T(1) / ljj;
+                    const T lij = li == j ? ljj : (li > j ? f[jj] * rinv : T(0));
+                    f[jj] = lij;
+                    cb[buf * kTile + li] = lij;
+                    if (li == j) {
+                        rv[buf] = rinv;
+                        if (bad) atomicMin(info_b, col0 + j + 1);
+                    }
+                }
+                if (li == j) {
+#pragma unroll
+                    for (int tt = 0; tt < 16; tt++) xr[buf * kTile + 16 * g + tt] = x[tt];
+                }
+                __syncthreads();
+                // branch-free: masked multipliers instead of conditional
+                // updates (a conditional update compiles to a branch and a
+                // memory wait per entry)
+                const T rinv = rv[buf];
+                const T lij = cb[buf * kTile + li];
+                const T lx = li > j ? lij * rinv : T(0);
+                const T sx = li == j ? rinv : T(1);
+                T cv[16], xv[16];
+#pragma unroll
+                for (int tt = 0; tt < 16; tt++) {
+                    cv[tt] = cb[buf * kTile + 16 * g + tt];
+                    xv[tt] = xr[buf * kTile + 16 * g + tt];
+                }
+#pragma unroll
+                for (int tt = 0; tt < 16; tt++) {
+                    const T m = 16 * g + tt > j ? lij : T(0);
+                    f[tt] = fma(-m, cv[tt], f[tt]);
+                    x[tt] = fma(-lx, xv[tt], x[tt] * sx);
+                }
+            }
         }
     }
-    __syncthreads();
-    for (int j = 0; j < kb; j++) {
-        T djj = S[j * kDiagLd + j];
-        const bool bad = !(djj > T(0));
-        if (bad) djj = T(1);
-        const T ljj = dsqrt(djj);
-        const T rinv = T(1) / ljj;
-        // S[j][j] itself is never overwritten (the diagonal goes to dg), so
-        // no barrier is needed between its reads and the writes below
-        if (g == 0) {
-            if (li == j) {
-                dg[j] = ljj;
-                if (bad) atomicMin(info_b, col0 + j + 1);
-            } else if (li > j && li < kb) {
-                S[li * kDiagLd + j] *= rinv;
-            }
-        } else if (g == 1) {
-            X[j * kDiagLd + li] *= rinv;  // row j of X is final
-        }
-        __syncthreads();
-        // all reads of a step are issued before its writes (the updated
-        // entries and the operands are disjoint), 16 entries per thread
-        {
-            const bool rowok = li > j && li < kb, colok = li <= j;
-            const T lij = rowok ? S[li * kDiagLd + j] : T(0);
-            const T xj = colok ? X[j * kDiagLd + li] : T(0);
-            T sv[16], sc[16], xv[16], xc[16];
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const int t = j + 1 + g + 4 * q;
-                const bool ok = rowok && t <= li, okx = colok && t < kb;
-                sv[q] = ok ? S[li * kDiagLd + t] : T(0);
-                sc[q] = ok ? S[t * kDiagLd + j] : T(0);
-                xv[q] = okx ? X[t * kDiagLd + li] : T(0);
-                xc[q] = okx ? S[t * kDiagLd + j] : T(0);
-            }
-#pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const int t = j + 1 + g + 4 * q;
-                if (rowok && t <= li) S[li * kDiagLd + t] = sv[q] - lij * sc[q];
-                if (colok && t < kb) X[t * kDiagLd + li] = xv[q] - xc[q] * xj;
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll 4
-    for (int q = 0; q < 16; q++) {
-        const int e = tid + 256 * q, t = e >> 6, i = e & 63;
-        if (i < kb && t < kb)
-            Lb[int64_t(r0 + t) * c + r0 + i] = i > t ? S[i * kDiagLd + t] : (i == t ? dg[t] : T(0));
-        PIg[e] = (i < kb && t < kb && i >= t) ? X[i * kDiagLd + t] : T(0);
+    for (int tt = 0; tt < 16; tt++) {
+        const int col = 16 * g + tt;
+        const bool in = li < kb && col < kb;
+        if (in) Lb[int64_t(r0 + col) * c + r0 + li] = li >= col ? f[tt] : T(0);
+        PIg[col * kTile + li] = (in && li >= col) ? x[tt] : T(0);
     }
 }
 

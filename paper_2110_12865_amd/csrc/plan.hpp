@@ -50,9 +50,9 @@ inline bool solve_by_panels(const SnDesc &d) { return d.w > kSolvePanel || d.c >
 // rows below a supernode's diagonal block are cut into blocks of kSoaRows
 // rows, one work item each; L is copied to the interleaved layout in
 // chunks of kSoaChunk scalars.
-constexpr int kSoaRows = 64;
+constexpr int kSoaRows = 16;
 constexpr int kSoaChunk = 128;
-constexpr int kSoaMinBatch = -1;  // default of sc_options::soa_min_batch (off)
+constexpr int kSoaMinBatch = 64;  // default of sc_options::soa_min_batch: whole lane groups
 
 struct DevPlan;  // device copies, defined by the HIP side
 
@@ -128,6 +128,10 @@ struct sc_plan {
     // supernode's row blocks start at its SnDesc::part (w per block);
     // chunk starts of the L copy
     std::vector<int32_t> soa_it_ptr, soa_it_s, soa_it_r0;
+    // forward gather rows of those supernodes, per level: front-vector
+    // position rowptr_s + i and the right-hand-side row first_s + i (or -1
+    // below the diagonal block); level l owns [grow_ptr[l], grow_ptr[l+1])
+    std::vector<int32_t> grow_ptr, grow_q, grow_y;
     int64_t soa_psize = 0;
     std::vector<int64_t> soa_chunks;
     int64_t dinv_size = 0;   // scalars of inverted diagonal blocks

@@ -27,6 +27,16 @@ namespace {
 constexpr int kP = kSolvePanel;
 constexpr int kMaxRhsPanel = 4;  // right-hand sides per pass of the panel gather
 
+// p[idx] when ok, else 0, as an unconditional load of an in-bounds address
+// (p[0] when !ok) and a select.  A load under a condition cannot be hoisted
+// by the compiler and becomes a branch with its own wait for memory, which
+// serializes the loads of a loop; every optional load below uses this.
+template <typename V>
+__device__ __forceinline__ V ldz(const V *p, int64_t idx, bool ok) {
+    const V v = p[ok ? idx : 0];
+    return ok ? v : V(0);
+}
+
 // Inverse of every 64x64 diagonal block of every panel-solved supernode:
 // X = L_pp^{-1} by forward substitution, one lane per column of X kept in
 // registers (loops fully unrolled), L_pp read from LDS as broadcasts.
@@ -66,6 +76,18 @@ __global__ __launch_bounds__(64) void k_dinv(
     __syncthreads();
 #pragma unroll 8
     for (int col = 0; col < kP; col++) D[col * kP + lane] = Lp[col * (kP + 1) + lane];
+}
+
+// Position of entry (matrix b, row, right-hand side r) in a solve vector
+// set with `rows` rows per matrix.  Row-major per matrix (rows, then
+// right-hand sides) or, batch-interleaved, groups of 64 matrices with the
+// matrix index fastest, so that lane b of a wave reads consecutive words.
+template <bool SOA>
+__device__ __host__ inline int64_t vix(int b, int64_t row, int r, int64_t rows, int nrhs) {
+    if constexpr (SOA)
+        return ((int64_t(b >> 6) * rows + row) * nrhs + r) * 64 + (b & 63);
+    else
+        return (int64_t(b) * rows + row) * nrhs + r;
 }
 
 __device__ inline void wave_sync_solve() {
@@ -117,12 +139,48 @@ __global__ __launch_bounds__(256) void k_perm_out(
     for (int r = 0; r < nrhs; r++) X[(int64_t(b) * nrhs + r) * ldb + i] = src[r];
 }
 
+// Front vectors of one level's supernodes (those not solved by panels):
+// row q = rowptr_s + i of FV is the right-hand side (i < w, row y =
+// first_s + i) plus the children's update entries (gather map, children in
+// order), right-hand sides r0 .. r0 + NR - 1.  One thread per (row,
+// matrix), so the short dependent chains of the gather overlap across the
+// whole grid instead of stalling the solve kernels.
+template <bool SOA, int NR>
+__global__ __launch_bounds__(256) void k_gather(
+    const int32_t *__restrict__ grow_q, const int32_t *__restrict__ grow_y, int nrow,
+    const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const double *__restrict__ Ys, double *__restrict__ FV, int64_t n, int64_t fvsize,
+    int nrhs, int r0, int batch, const int32_t *__restrict__ active) {
+    int row, b;
+    if constexpr (SOA) {
+        row = blockIdx.x * 4 + (threadIdx.x >> 6);
+        b = blockIdx.y * 64 + (threadIdx.x & 63);  // whole groups are allocated
+        if (row >= nrow) return;
+    } else {
+        const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+        if (t >= int64_t(nrow) * batch) return;
+        b = int(t / nrow);
+        row = int(t - int64_t(b) * nrow);
+        if (active && !active[b]) return;
+    }
+    const int q = grow_q[row], y = grow_y[row];
+    const int g0 = gptr[q], g1 = gptr[q + 1];
+    double a[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) a[r] = ldz(Ys, vix<SOA>(b, y, r0 + r, n, nrhs), y >= 0);
+    for (int g = g0; g < g1; g++) {
+        const int src = gidx[g];
+#pragma unroll
+        for (int r = 0; r < NR; r++) a[r] += FV[vix<SOA>(b, src, r0 + r, fvsize, nrhs)];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) FV[vix<SOA>(b, q, r0 + r, fvsize, nrhs)] = a[r];
+}
+
 // Forward step of one level for the supernodes of one row class: a segment
 // of G lanes per (supernode, matrix), lane i keeping rows i + G k (k < SL),
 // right-hand sides r0 .. r0 + NR - 1.
-//   gather    row i of the front vector: the right-hand side (i < w) plus
-//             the children's update entries landing on row i (gather map,
-//             children in order);
+//   front     row i of the front vector, gathered beforehand (k_gather);
 //   triangle  the w x w diagonal block by columns: the owner of column j
 //             scales by 1 / L_jj and its value is broadcast in the segment;
 //   update    rows i >= w subtract L_ij y_j (ascending j), y read from LDS,
@@ -154,27 +212,18 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
         const int i = li + G * k;
 #pragma unroll
         for (int r = 0; r < NR; r++) x[k][r] = 0.0;
-        if (i < c) {
-            if (i < w) {
 #pragma unroll
-                for (int r = 0; r < NR; r++) x[k][r] = yb[int64_t(d.first + i) * nrhs + r];
-            }
-            const int g1 = gptr[d.rowptr + i + 1];
-            for (int g = gptr[d.rowptr + i]; g < g1; g++) {
-                const double *u = fb + int64_t(gidx[g]) * nrhs;
-#pragma unroll
-                for (int r = 0; r < NR; r++) x[k][r] += u[r];
-            }
-        }
+        for (int r = 0; r < NR; r++) x[k][r] = ldz(fb, int64_t(d.rowptr + i) * nrhs + r, i < c);
     }
     // diagonal block (rows < w live in slot 0)
-    const double rinv = li < w ? 1.0 / double(Lb[li * c + li]) : 0.0;
+    const double dgl = double(ldz(Lb, int64_t(li) * c + li, li < w));
+    const double rinv = li < w ? 1.0 / dgl : 0.0;
     for (int j0 = 0; j0 < w; j0 += 8) {
         T lc[8];
 #pragma unroll
         for (int jj = 0; jj < 8; jj++) {
             const int j = j0 + jj;
-            lc[jj] = (j < w && li > j && li < w) ? Lb[j * c + li] : T(0);
+            lc[jj] = ldz(Lb, int64_t(j) * c + li, j < w && li > j && li < w);
         }
 #pragma unroll
         for (int jj = 0; jj < 8; jj++) {
@@ -212,7 +261,7 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
 #pragma unroll
             for (int k = 0; k < SL; k++) {
                 const int i = li + G * k, j = j0 + jj;
-                lc[jj][k] = (j < w && i >= w && i < c) ? Lb[j * c + i] : T(0);
+                lc[jj][k] = ldz(Lb, int64_t(j) * c + i, j < w && i >= w && i < c);
             }
 #pragma unroll
         for (int jj = 0; jj < JC; jj++) {
@@ -279,8 +328,8 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++)
-        acc[r] = li < w ? yb[int64_t(d.first + li) * nrhs + r] : 0.0;
-    const double rinv = li < w ? 1.0 / double(Lb[li * c + li]) : 0.0;
+        acc[r] = ldz(yb, int64_t(d.first + li) * nrhs + r, li < w);
+    const double rinv = li < w ? 1.0 / double(Lb[li < w ? int64_t(li) * c + li : 0]) : 0.0;
     // rows below in blocks of kSoaRows: each block's sum (ascending rows)
     // is formed on its own and then subtracted, the same order as the
     // batch-interleaved kernels, so both layouts give identical bits
@@ -291,12 +340,25 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
         for (int r = 0; r < NR; r++) p[r] = 0.0;
         for (int i0 = rb; i0 < re; i0 += kBwdRows) {
             const int i = i0 + sr;
-            if (i < re) {
-                for (int j = sg; j < w; j += NG) Ls[seg][sr][j] = Lb[j * c + i];
-                if (sg == 0) {
-                    const double *xi = yb + int64_t(R[i]) * nrhs;
+            {
+                // every column of this lane's staging share in flight at once
+                T v[kBwdRows];
 #pragma unroll
-                    for (int r = 0; r < NR; r++) xs[seg][sr][r] = xi[r];
+                for (int q = 0; q < kBwdRows; q++) {
+                    const int j = sg + NG * q;
+                    v[q] = ldz(Lb, int64_t(j) * c + i, i < re && j < w);
+                }
+#pragma unroll
+                for (int q = 0; q < kBwdRows; q++) {
+                    const int j = sg + NG * q;
+                    if (j < w) Ls[seg][sr][j] = v[q];
+                }
+                const bool xo = sg == 0 && i < re;
+                const int ri = ldz(R, i, xo);
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    const double xv = ldz(yb, int64_t(ri) * nrhs + r, xo);
+                    if (xo) xs[seg][sr][r] = xv;
                 }
             }
             wave_sync_solve();
@@ -316,8 +378,19 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
     for (int i1 = w; i1 > 0; i1 -= kBwdRows) {
         const int i0 = max(0, i1 - kBwdRows);
         const int i = i0 + sr;
-        if (i < i1)
-            for (int j = sg; j < i; j += NG) Ls[seg][sr][j] = Lb[j * c + i];
+        {
+            T v[kBwdRows];
+#pragma unroll
+            for (int q = 0; q < kBwdRows; q++) {
+                const int j = sg + NG * q;
+                v[q] = ldz(Lb, int64_t(j) * c + i, i < i1 && j < i);
+            }
+#pragma unroll
+            for (int q = 0; q < kBwdRows; q++) {
+                const int j = sg + NG * q;
+                if (i < i1 && j < i) Ls[seg][sr][j] = v[q];
+            }
+        }
         wave_sync_solve();
         for (int t = i1 - 1; t >= i0; t--) {
             double xv[NR];
@@ -338,18 +411,6 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
 #pragma unroll
         for (int r = 0; r < NR; r++) yb[int64_t(d.first + li) * nrhs + r] = acc[r];
     }
-}
-
-// Position of entry (matrix b, row, right-hand side r) in a solve vector
-// set with `rows` rows per matrix.  Row-major per matrix (rows, then
-// right-hand sides) or, batch-interleaved, groups of 64 matrices with the
-// matrix index fastest, so that lane b of a wave reads consecutive words.
-template <bool SOA>
-__device__ __host__ inline int64_t vix(int b, int64_t row, int r, int64_t rows, int nrhs) {
-    if constexpr (SOA)
-        return ((int64_t(b >> 6) * rows + row) * nrhs + r) * 64 + (b & 63);
-    else
-        return (int64_t(b) * rows + row) * nrhs + r;
 }
 
 // Front vectors of the panel-solved supernodes of a level, then y_0 of
@@ -377,7 +438,7 @@ __global__ __launch_bounds__(256) void k_pan_gather(
         for (int i = threadIdx.x; i < d.c; i += blockDim.x) {
             const int g0 = gptr[d.rowptr + i], g1 = gptr[d.rowptr + i + 1];
             for (int r = 0; r < nr; r++) {
-                double a = i < d.w ? Ys[vix<SOA>(b, d.first + i, r0 + r, n, nrhs)] : 0.0;
+                double a = ldz(Ys, vix<SOA>(b, d.first + i, r0 + r, n, nrhs), i < d.w);
                 for (int g = g0; g < g1; g++) a += FV[vix<SOA>(b, gidx[g], r0 + r, fvsize, nrhs)];
                 FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)] = a;
                 if (i < kP) v0[i][r] = a;
@@ -427,24 +488,26 @@ __global__ __launch_bounds__(64) void k_fwd_panel(
     const int lane = threadIdx.x;
 #pragma unroll
     for (int r = 0; r < NR; r++)
-        yv[lane][r] = lane < kb ? Ys[vix<SOA>(b, d.first + c0 + lane, r0 + r, n, nrhs)] : 0.0;
+        yv[lane][r] = ldz(Ys, vix<SOA>(b, d.first + c0 + lane, r0 + r, n, nrhs), lane < kb);
     __syncthreads();
     const int row = rt + lane;
+    const bool rok = row < c;
+    const int rowc = rok ? row : rt;  // rows past the front read row rt (in bounds)
     double v[NR];
+    {
+        const T *Lr = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + rowc;
 #pragma unroll
-    for (int r = 0; r < NR; r++) v[r] = 0.0;
-    if (row < c) {
-        const T *Lr = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + row;
-#pragma unroll
-        for (int r = 0; r < NR; r++) v[r] = FV[vix<SOA>(b, d.rowptr + row, r0 + r, fvsize, nrhs)];
+        for (int r = 0; r < NR; r++) v[r] = FV[vix<SOA>(b, d.rowptr + rowc, r0 + r, fvsize, nrhs)];
 #pragma unroll 8
         for (int t = 0; t < kb; t++) {
             const double l = double(Lr[int64_t(t) * c]);
 #pragma unroll
             for (int r = 0; r < NR; r++) v[r] -= l * yv[t][r];
         }
+        if (rok) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) FV[vix<SOA>(b, d.rowptr + row, r0 + r, fvsize, nrhs)] = v[r];
+            for (int r = 0; r < NR; r++) FV[vix<SOA>(b, d.rowptr + row, r0 + r, fvsize, nrhs)] = v[r];
+        }
     }
     const int c1 = c0 + kP;  // next panel
     if (tile != 0 || c1 >= d.w) return;
@@ -505,12 +568,24 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
     const int w0 = rb + 64 * wv, w1 = min(c, w0 + 64);
     for (int i0 = w0; i0 < w1; i0 += RB) {
         const int i = i0 + sr;
-        if (i < w1) {
-            for (int t = sg; t < kb; t += 4) Ls[wv][sr][t] = Lb[int64_t(t) * c + i];
-            if (sg == 0) {
-                const int64_t pos = i < d.w ? d.first + i : R[i];
+        {
+            T v[16];
 #pragma unroll
-                for (int r = 0; r < NR; r++) xs[wv][sr][r] = Ys[vix<SOA>(b, pos, r0 + r, n, nrhs)];
+            for (int q = 0; q < 16; q++) {
+                const int t = sg + 4 * q;
+                v[q] = ldz(Lb, int64_t(t) * c + i, i < w1 && t < kb);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int t = sg + 4 * q;
+                if (i < w1 && t < kb) Ls[wv][sr][t] = v[q];
+            }
+            const bool xo = sg == 0 && i < w1;
+            const int64_t pos = i < d.w ? d.first + i : ldz(R, i, xo && i >= d.w);
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const double xv = ldz(Ys, vix<SOA>(b, pos, r0 + r, n, nrhs), xo);
+                if (xo) xs[wv][sr][r] = xv;
             }
         }
         wave_sync_solve();  // each wave stages and reads its own rows
@@ -572,10 +647,10 @@ __global__ __launch_bounds__(64) void k_bwd_pan_fin(
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         double s0 = 0.0;
-        if (t < kb)
-            for (int q = 0; q < nch; q++)
-                s0 += PART[vix<SOA>(b, d.part + int64_t(q) * kP + t, r0 + r, psize, nrhs)];
-        rhs[t][r] = t < kb ? Ys[vix<SOA>(b, d.first + c0 + t, r0 + r, n, nrhs)] - s0 : 0.0;
+        for (int q = 0; q < nch; q++)
+            s0 += ldz(PART, vix<SOA>(b, d.part + int64_t(q) * kP + t, r0 + r, psize, nrhs), t < kb);
+        rhs[t][r] = t < kb ? ldz(Ys, vix<SOA>(b, d.first + c0 + t, r0 + r, n, nrhs), t < kb) - s0
+                           : 0.0;
     }
     __syncthreads();
     if (t < kb) {
@@ -620,7 +695,7 @@ __global__ __launch_bounds__(256) void k_to_soa(
         for (int q = 0; q < 16; q++) {
             const int bl = q0 + bh + NPH * q;
             const int b = bg * 64 + bl;
-            v[q] = (bl < 64 && b < batch && k0 + kk < Lsize) ? L[int64_t(b) * Lsize + k0 + kk] : T(0);
+            v[q] = ldz(L, int64_t(b) * Lsize + k0 + kk, bl < 64 && b < batch && k0 + kk < Lsize);
         }
 #pragma unroll
         for (int q = 0; q < 16; q++) {
@@ -638,81 +713,62 @@ __global__ __launch_bounds__(256) void k_to_soa(
     }
 }
 
-// Ys[vix<true>(b, k, r)] = B[(b nrhs + r) ldb + perm[k]], 64 rows x 64
-// matrices per workgroup through LDS (writes coalesced).
+// Ys[vix<true>(b, pinv[i], r)] = B[(b nrhs + r) ldb + i] through an LDS
+// tile of 64 rows x 64 matrices: read along rows of each right-hand side
+// (lanes = rows), written along matrices (lanes = matrices), so both sides
+// move whole cache lines.
 __global__ __launch_bounds__(256) void k_perm_in_soa(
-    const int32_t *__restrict__ perm, const double *__restrict__ B, int64_t ldb,
+    const int32_t *__restrict__ pinv, const double *__restrict__ B, int64_t ldb,
     double *__restrict__ Ys, int64_t n, int nrhs, int batch) {
     __shared__ double tile[64][65];
-    const int64_t k0 = int64_t(blockIdx.x) * 64;
     const int bg = blockIdx.y;
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
     const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
     for (int r = 0; r < nrhs; r++) {
         double v[16];
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            const int bl = hi + 4 * q;
-            const int b = bg * 64 + bl;
-            const int64_t k = k0 + lo;
-            v[q] = (b < batch && k < n) ? B[(int64_t(b) * nrhs + r) * ldb + perm[k]] : 0.0;
+            const int b = bg * 64 + hi + 4 * q;
+            v[q] = ldz(B, (int64_t(b) * nrhs + r) * ldb + i0 + lo, b < batch && i0 + lo < n);
         }
 #pragma unroll
         for (int q = 0; q < 16; q++) tile[hi + 4 * q][lo] = v[q];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            const int kk = hi + 4 * q;
-            if (k0 + kk < n) Ys[((int64_t(bg) * n + k0 + kk) * nrhs + r) * 64 + lo] = tile[lo][kk];
+            const int64_t i = i0 + hi + 4 * q;
+            if (i < n) Ys[((int64_t(bg) * n + pinv[i]) * nrhs + r) * 64 + lo] = tile[lo][hi + 4 * q];
         }
         __syncthreads();
     }
 }
 
 // X[(b nrhs + r) ldb + i] = Ys[vix<true>(b, pinv[i], r)] for the active
-// matrices, 64 rows x 64 matrices per workgroup through LDS.
+// matrices, through the same kind of tile.
 __global__ __launch_bounds__(256) void k_perm_out_soa(
     const int32_t *__restrict__ pinv, const double *__restrict__ Ys, double *__restrict__ X,
     int64_t ldb, int64_t n, int nrhs, int batch, const int32_t *__restrict__ active) {
     __shared__ double tile[64][65];
-    const int64_t i0 = int64_t(blockIdx.x) * 64;
     const int bg = blockIdx.y;
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
     const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
     for (int r = 0; r < nrhs; r++) {
         double v[16];
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const int64_t i = i0 + hi + 4 * q;
-            v[q] = i < n ? Ys[((int64_t(bg) * n + pinv[i]) * nrhs + r) * 64 + lo] : 0.0;
+            v[q] = ldz(Ys, ((int64_t(bg) * n + ldz(pinv, i, i < n)) * nrhs + r) * 64 + lo, i < n);
         }
 #pragma unroll
         for (int q = 0; q < 16; q++) tile[hi + 4 * q][lo] = v[q];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            const int bl = hi + 4 * q;
-            const int b = bg * 64 + bl;
-            const int64_t i = i0 + lo;
-            if (b < batch && i < n && (!active || active[b]))
-                X[(int64_t(b) * nrhs + r) * ldb + i] = tile[lo][bl];
+            const int b = bg * 64 + hi + 4 * q;
+            const bool on = b < batch && i0 + lo < n && (!active || ldz(active, b, b < batch) != 0);
+            if (on) X[(int64_t(b) * nrhs + r) * ldb + i0 + lo] = tile[lo][hi + 4 * q];
         }
         __syncthreads();
-    }
-}
-
-// Row i of the gathered front vector of supernode d (right-hand side for
-// i < w, plus the children's update entries, children in order), right-hand
-// sides r0 .. r0 + NR - 1, for this lane's matrix.
-template <int NR>
-__device__ inline void soa_gather(const SnDesc &d, int i, const int32_t *__restrict__ gptr,
-                                  const int32_t *__restrict__ gidx, const double *yb,
-                                  const double *fb, int nrhs, double (&a)[NR]) {
-#pragma unroll
-    for (int r = 0; r < NR; r++) a[r] = i < d.w ? yb[(int64_t(d.first + i) * nrhs + r) * 64] : 0.0;
-    const int g1 = gptr[d.rowptr + i + 1];
-    for (int g = gptr[d.rowptr + i]; g < g1; g++) {
-        const double *u = fb + int64_t(gidx[g]) * nrhs * 64;
-#pragma unroll
-        for (int r = 0; r < NR; r++) a[r] += u[r * 64];
     }
 }
 
@@ -724,8 +780,8 @@ template <typename T> struct SoaRows { static constexpr int value = sizeof(T) ==
 // Columns in chunks of 16: the chunk's rows are solved in registers
 // (y_j = (v_j - sum_{k<j} L_jk y_k) / L_jj, ascending), y stored, and the
 // later rows of the diagonal block (i < w) updated in FV.
-template <typename T, int NR>
-__global__ __launch_bounds__(64) void k_fwd_soa_diag(
+template <typename T, int NR, int JW>
+__device__ __forceinline__ void k_fwd_soa_diag_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
     const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
@@ -736,70 +792,85 @@ __global__ __launch_bounds__(64) void k_fwd_soa_diag(
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
     double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
     double *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
-    for (int j0 = 0; j0 < w; j0 += kSoaCols) {
-        const int jn = min(kSoaCols, w - j0);
-        double v[kSoaCols][NR];
+    for (int j0 = 0; j0 < w; j0 += JW) {
+        const int jn = min(JW, w - j0);
+        double v[JW][NR];
 #pragma unroll
-        for (int jj = 0; jj < kSoaCols; jj++) {
+        for (int jj = 0; jj < JW; jj++) {
             const int i = j0 + jj;
-            if (jj < jn) {
-                if (j0 == 0) {
-                    soa_gather<NR>(d, i, gptr, gidx, yb, fb, nrhs, v[jj]);
-                } else {
 #pragma unroll
-                    for (int r = 0; r < NR; r++) v[jj][r] = fb[(int64_t(d.rowptr + i) * nrhs + r) * 64];
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < NR; r++) v[jj][r] = 0.0;
-            }
+            for (int r = 0; r < NR; r++)
+                v[jj][r] = ldz(fb, (int64_t(d.rowptr + i) * nrhs + r) * 64, jj < jn);
         }
 #pragma unroll
-        for (int jj = 0; jj < kSoaCols; jj++) {
-            if (jj < jn) {
-                const int i = j0 + jj;
+        for (int jj = 0; jj < JW; jj++) {
+            const int i = j0 + jj;
+            const bool ok = jj < jn;
+            T lrow[JW];  // row i of the chunk's triangle, diagonal included
 #pragma unroll
-                for (int kk = 0; kk < jj; kk++) {
-                    const double l = double(Lb[(int64_t(j0 + kk) * c + i) * 64]);
+            for (int kk = 0; kk <= jj; kk++) lrow[kk] = ldz(Lb, (int64_t(j0 + kk) * c + i) * 64, ok);
 #pragma unroll
-                    for (int r = 0; r < NR; r++) v[jj][r] -= l * v[kk][r];
-                }
-                const double rinv = 1.0 / double(Lb[(int64_t(i) * c + i) * 64]);
+            for (int kk = 0; kk < jj; kk++)
 #pragma unroll
-                for (int r = 0; r < NR; r++) {
-                    v[jj][r] *= rinv;
-                    yb[(int64_t(d.first + i) * nrhs + r) * 64] = v[jj][r];
-                }
+                for (int r = 0; r < NR; r++) v[jj][r] -= double(lrow[kk]) * v[kk][r];
+            const double rinv = ok ? 1.0 / double(lrow[jj]) : 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                v[jj][r] *= rinv;
+                if (ok) yb[(int64_t(d.first + i) * nrhs + r) * 64] = v[jj][r];
             }
         }
-        // rows of the diagonal block below this chunk
-        for (int i = j0 + kSoaCols; i < w; i++) {
-            double a[NR];
-            if (j0 == 0) {
-                soa_gather<NR>(d, i, gptr, gidx, yb, fb, nrhs, a);
-            } else {
+        // rows of the diagonal block below this chunk, RU at a time with
+        // every load of the group issued first
+        constexpr int RU = SoaRows<T>::value;
+        for (int i0 = j0 + JW; i0 < w; i0 += RU) {
+            double a[RU][NR];
+            T l[RU][JW];
 #pragma unroll
-                for (int r = 0; r < NR; r++) a[r] = fb[(int64_t(d.rowptr + i) * nrhs + r) * 64];
+            for (int u = 0; u < RU; u++) {
+                const int i = i0 + u;
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    a[u][r] = ldz(fb, (int64_t(d.rowptr + i) * nrhs + r) * 64, i < w);
+#pragma unroll
+                for (int jj = 0; jj < JW; jj++)
+                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, i < w && jj < jn);
             }
 #pragma unroll
-            for (int jj = 0; jj < kSoaCols; jj++) {
-                if (jj < jn) {
-                    const double l = double(Lb[(int64_t(j0 + jj) * c + i) * 64]);
+            for (int u = 0; u < RU; u++)
 #pragma unroll
-                    for (int r = 0; r < NR; r++) a[r] -= l * v[jj][r];
-                }
-            }
+                for (int jj = 0; jj < JW; jj++)
 #pragma unroll
-            for (int r = 0; r < NR; r++) fb[(int64_t(d.rowptr + i) * nrhs + r) * 64] = a[r];
+                    for (int r = 0; r < NR; r++) a[u][r] -= double(l[u][jj]) * v[jj][r];
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+                if (i0 + u < w)
+#pragma unroll
+                    for (int r = 0; r < NR; r++)
+                        fb[(int64_t(d.rowptr + i0 + u) * nrhs + r) * 64] = a[u][r];
         }
     }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_fwd_soa_diag(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
+    int64_t n, int64_t fvsize, int nrhs, int r0) {
+    // column-chunk width by the supernode's width (uniform per wave), so
+    // narrow supernodes issue no masked loads for absent columns
+    const int w = sn[list[blockIdx.x]].w;
+    if (w <= 4) k_fwd_soa_diag_body<T, NR, 4>(sn, list, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else if (w <= 8) k_fwd_soa_diag_body<T, NR, 8>(sn, list, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else k_fwd_soa_diag_body<T, NR, 16>(sn, list, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
 }
 
 // Forward, rows below the diagonal blocks: one wave per (row block of
 // kSoaRows rows, group): u_i = v_i - sum_j L_ij y_j over the supernode's
 // columns in chunks of 16 (ascending j), stored in FV as the update vector.
-template <typename T, int NR>
-__global__ __launch_bounds__(64) void k_fwd_soa_rows(
+template <typename T, int NR, int JW>
+__device__ __forceinline__ void k_fwd_soa_rows_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
     const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
@@ -814,38 +885,32 @@ __global__ __launch_bounds__(64) void k_fwd_soa_rows(
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
     const double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
     double *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
-    for (int j0 = 0; j0 < w; j0 += kSoaCols) {
-        const int jn = min(kSoaCols, w - j0);
-        double y[kSoaCols][NR];
+    for (int j0 = 0; j0 < w; j0 += JW) {
+        const int jn = min(JW, w - j0);
+        double y[JW][NR];
 #pragma unroll
-        for (int jj = 0; jj < kSoaCols; jj++)
+        for (int jj = 0; jj < JW; jj++)
 #pragma unroll
             for (int r = 0; r < NR; r++)
-                y[jj][r] = jj < jn ? yb[(int64_t(d.first + j0 + jj) * nrhs + r) * 64] : 0.0;
+                y[jj][r] = ldz(yb, (int64_t(d.first + j0 + jj) * nrhs + r) * 64, jj < jn);
         // RU rows at a time, every load of the group issued before any use
         for (int i0 = rb; i0 < re; i0 += RU) {
             double a[RU][NR];
-            T l[RU][kSoaCols];
+            T l[RU][JW];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
                 const int i = i0 + u;
-                if (i < re) {
-                    if (j0 == 0) {
-                        soa_gather<NR>(d, i, gptr, gidx, yb, fb, nrhs, a[u]);
-                    } else {
 #pragma unroll
-                        for (int r = 0; r < NR; r++)
-                            a[u][r] = fb[(int64_t(d.rowptr + i) * nrhs + r) * 64];
-                    }
-                }
+                for (int r = 0; r < NR; r++)
+                    a[u][r] = ldz(fb, (int64_t(d.rowptr + i) * nrhs + r) * 64, i < re);
 #pragma unroll
-                for (int jj = 0; jj < kSoaCols; jj++)
-                    l[u][jj] = (i < re && jj < jn) ? Lb[(int64_t(j0 + jj) * c + i) * 64] : T(0);
+                for (int jj = 0; jj < JW; jj++)
+                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, i < re && jj < jn);
             }
 #pragma unroll
             for (int u = 0; u < RU; u++)
 #pragma unroll
-                for (int jj = 0; jj < kSoaCols; jj++)
+                for (int jj = 0; jj < JW; jj++)
 #pragma unroll
                     for (int r = 0; r < NR; r++) a[u][r] -= double(l[u][jj]) * y[jj][r];
 #pragma unroll
@@ -858,12 +923,27 @@ __global__ __launch_bounds__(64) void k_fwd_soa_rows(
     }
 }
 
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_fwd_soa_rows(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
+    const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
+    const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
+    double *__restrict__ Ys, double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    int r0) {
+    // column-chunk width by the supernode's width (uniform per wave), so
+    // narrow supernodes issue no masked loads for absent columns
+    const int w = sn[it_s[blockIdx.x]].w;
+    if (w <= 4) k_fwd_soa_rows_body<T, NR, 4>(sn, it_s, it_r0, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else if (w <= 8) k_fwd_soa_rows_body<T, NR, 8>(sn, it_s, it_r0, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else k_fwd_soa_rows_body<T, NR, 16>(sn, it_s, it_r0, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+}
+
 // Backward, rows below the diagonal blocks: one wave per (row block,
 // group): partial sums p_j = sum_i L_ij x_i over the block's rows (x from
 // the solved ancestors), columns in chunks of 16, stored at
 // part + (block index) w + j.
-template <typename T, int NR>
-__global__ __launch_bounds__(64) void k_bwd_soa_rows(
+template <typename T, int NR, int JW>
+__device__ __forceinline__ void k_bwd_soa_rows_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
     const T *__restrict__ Ls, int64_t Lsize, const double *__restrict__ Ys,
@@ -876,42 +956,59 @@ __global__ __launch_bounds__(64) void k_bwd_soa_rows(
     const int kblk = (rb - w) / kSoaRows;
     constexpr int RU = SoaRows<T>::value;
     const int32_t *R = rows + d.rowptr;
+    // the block's row indices, one per lane, broadcast with readlane below
+    const int rmine = rb + lane < re ? R[rb + lane] : 0;
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
     const double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
     double *pb = PS + ((int64_t(bg) * psize + d.part + int64_t(kblk) * w) * nrhs + r0) * 64 + lane;
-    for (int j0 = 0; j0 < w; j0 += kSoaCols) {
-        const int jn = min(kSoaCols, w - j0);
-        double acc[kSoaCols][NR];
+    for (int j0 = 0; j0 < w; j0 += JW) {
+        const int jn = min(JW, w - j0);
+        double acc[JW][NR];
 #pragma unroll
-        for (int jj = 0; jj < kSoaCols; jj++)
+        for (int jj = 0; jj < JW; jj++)
 #pragma unroll
             for (int r = 0; r < NR; r++) acc[jj][r] = 0.0;
         for (int i0 = rb; i0 < re; i0 += RU) {
             double x[RU][NR];
-            T l[RU][kSoaCols];
+            T l[RU][JW];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
                 const int i = i0 + u;
-                const double *xi = yb + int64_t(i < re ? R[i] : 0) * nrhs * 64;
+                const int ri = i < re ? __builtin_amdgcn_readlane(rmine, i - rb) : 0;
+                const double *xi = yb + int64_t(ri) * nrhs * 64;
 #pragma unroll
-                for (int r = 0; r < NR; r++) x[u][r] = i < re ? xi[r * 64] : 0.0;
+                for (int r = 0; r < NR; r++) x[u][r] = ldz(xi, r * 64, i < re);
 #pragma unroll
-                for (int jj = 0; jj < kSoaCols; jj++)
-                    l[u][jj] = (i < re && jj < jn) ? Lb[(int64_t(j0 + jj) * c + i) * 64] : T(0);
+                for (int jj = 0; jj < JW; jj++)
+                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, i < re && jj < jn);
             }
 #pragma unroll
             for (int u = 0; u < RU; u++)
 #pragma unroll
-                for (int jj = 0; jj < kSoaCols; jj++)
+                for (int jj = 0; jj < JW; jj++)
 #pragma unroll
                     for (int r = 0; r < NR; r++) acc[jj][r] += double(l[u][jj]) * x[u][r];
         }
 #pragma unroll
-        for (int jj = 0; jj < kSoaCols; jj++)
+        for (int jj = 0; jj < JW; jj++)
             if (jj < jn)
 #pragma unroll
                 for (int r = 0; r < NR; r++) pb[(int64_t(j0 + jj) * nrhs + r) * 64] = acc[jj][r];
     }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_bwd_soa_rows(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
+    const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
+    const T *__restrict__ Ls, int64_t Lsize, const double *__restrict__ Ys,
+    double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    // column-chunk width by the supernode's width (uniform per wave), so
+    // narrow supernodes issue no masked loads for absent columns
+    const int w = sn[it_s[blockIdx.x]].w;
+    if (w <= 4) k_bwd_soa_rows_body<T, NR, 4>(sn, it_s, it_r0, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else if (w <= 8) k_bwd_soa_rows_body<T, NR, 8>(sn, it_s, it_r0, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else k_bwd_soa_rows_body<T, NR, 16>(sn, it_s, it_r0, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
 }
 
 // Backward, diagonal blocks: one wave per (supernode, group).  Column
@@ -920,8 +1017,8 @@ __global__ __launch_bounds__(64) void k_bwd_soa_rows(
 // chunk's triangle from its last column (x_j = rhs_j / L_jj, subtracted
 // from the earlier columns of the chunk).  Every column sees the same
 // sequence of operations as in the row-major kernels.
-template <typename T, int NR>
-__global__ __launch_bounds__(64) void k_bwd_soa_diag(
+template <typename T, int NR, int JW>
+__device__ __forceinline__ void k_bwd_soa_diag_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys,
     const double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
@@ -932,53 +1029,81 @@ __global__ __launch_bounds__(64) void k_bwd_soa_diag(
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
     double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
     const double *pb = PS + ((int64_t(bg) * psize + d.part) * nrhs + r0) * 64 + lane;
-    for (int j0 = ((w - 1) / kSoaCols) * kSoaCols; j0 >= 0; j0 -= kSoaCols) {
-        const int jn = min(kSoaCols, w - j0);
-        double acc[kSoaCols][NR];
+    constexpr int RU = SoaRows<T>::value;
+    for (int j0 = ((w - 1) / JW) * JW; j0 >= 0; j0 -= JW) {
+        const int jn = min(JW, w - j0);
+        double acc[JW][NR];
 #pragma unroll
-        for (int jj = 0; jj < kSoaCols; jj++)
+        for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                acc[jj][r] = ldz(yb, (int64_t(d.first + j0 + jj) * nrhs + r) * 64, jj < jn);
+        for (int k = 0; k < nblk; k++) {  // row-block partial sums, in block order
+            double p[JW][NR];
+#pragma unroll
+            for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    p[jj][r] = ldz(pb, ((int64_t(k) * w + j0 + jj) * nrhs + r) * 64, jj < jn);
+#pragma unroll
+            for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) acc[jj][r] -= p[jj][r];
+        }
+        // the supernode's own later rows, descending as in the other layout,
+        // RU rows with their loads in flight together
+        for (int i1 = w - 1; i1 >= j0 + JW; i1 -= RU) {
+            double x[RU][NR];
+            T l[RU][JW];
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int i = i1 - u;
+                const bool ok = i >= j0 + JW;
+#pragma unroll
+                for (int r = 0; r < NR; r++) x[u][r] = ldz(yb, (int64_t(d.first + i) * nrhs + r) * 64, ok);
+#pragma unroll
+                for (int jj = 0; jj < JW; jj++)
+                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, ok && jj < jn);
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+#pragma unroll
+                for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+                    for (int r = 0; r < NR; r++) acc[jj][r] -= double(l[u][jj]) * x[u][r];
+        }
+#pragma unroll
+        for (int jj = JW - 1; jj >= 0; jj--) {
+            const int j = j0 + jj;
+            const bool ok = jj < jn;
+            T lrow[JW];  // row j of the chunk's triangle, diagonal included
+#pragma unroll
+            for (int kk = 0; kk <= jj; kk++) lrow[kk] = ldz(Lb, (int64_t(j0 + kk) * c + j) * 64, ok);
+            const double rinv = ok ? 1.0 / double(lrow[jj]) : 0.0;
 #pragma unroll
             for (int r = 0; r < NR; r++) {
-                double a = 0.0;
-                if (jj < jn) {
-                    a = yb[(int64_t(d.first + j0 + jj) * nrhs + r) * 64];
-                    for (int k = 0; k < nblk; k++)
-                        a -= pb[(int64_t(k) * w + j0 + jj) * nrhs * 64 + r * 64];
-                }
-                acc[jj][r] = a;
+                acc[jj][r] *= rinv;
+                if (ok) yb[(int64_t(d.first + j) * nrhs + r) * 64] = acc[jj][r];
             }
-        for (int i = w - 1; i >= j0 + kSoaCols; i--) {  // descending, as in the other layout
-            double x[NR];
 #pragma unroll
-            for (int r = 0; r < NR; r++) x[r] = yb[(int64_t(d.first + i) * nrhs + r) * 64];
+            for (int kk = 0; kk < jj; kk++)
 #pragma unroll
-            for (int jj = 0; jj < kSoaCols; jj++) {
-                if (jj < jn) {
-                    const double l = double(Lb[(int64_t(j0 + jj) * c + i) * 64]);
-#pragma unroll
-                    for (int r = 0; r < NR; r++) acc[jj][r] -= l * x[r];
-                }
-            }
-        }
-#pragma unroll
-        for (int jj = kSoaCols - 1; jj >= 0; jj--) {
-            if (jj < jn) {
-                const int j = j0 + jj;
-                const double rinv = 1.0 / double(Lb[(int64_t(j) * c + j) * 64]);
-#pragma unroll
-                for (int r = 0; r < NR; r++) {
-                    acc[jj][r] *= rinv;
-                    yb[(int64_t(d.first + j) * nrhs + r) * 64] = acc[jj][r];
-                }
-#pragma unroll
-                for (int kk = 0; kk < jj; kk++) {
-                    const double l = double(Lb[(int64_t(j0 + kk) * c + j) * 64]);
-#pragma unroll
-                    for (int r = 0; r < NR; r++) acc[kk][r] -= l * acc[jj][r];
-                }
-            }
+                for (int r = 0; r < NR; r++) acc[kk][r] -= double(lrow[kk]) * acc[jj][r];
         }
     }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_bwd_soa_diag(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys,
+    const double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    // column-chunk width by the supernode's width (uniform per wave), so
+    // narrow supernodes issue no masked loads for absent columns
+    const int w = sn[list[blockIdx.x]].w;
+    if (w <= 4) k_bwd_soa_diag_body<T, NR, 4>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else if (w <= 8) k_bwd_soa_diag_body<T, NR, 8>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else k_bwd_soa_diag_body<T, NR, 16>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
 }
 
 template <typename T>
@@ -992,6 +1117,33 @@ hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
                        dim3(64), 0, st, D->sn, D->slv_pan, L, P->Lsize, N->dinv, P->dinv_size);
     N->prof.end(st);
     return hipGetLastError();
+}
+
+// Gather of the front vectors of one level (rows of the supernodes not
+// solved by panels), every right-hand side.
+template <bool SOA>
+void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                   const int32_t *active, hipStream_t st) {
+    if (l.ngrow == 0) return;
+    const DevPlan *D = P->dev;
+    const int B = N->batch;
+    const int64_t fvsize = int64_t(P->rows.size());
+    N->prof.begin(KK_Fwd, 0.0, l.v_gather * double(nrhs) * double(B), st);
+    const dim3 g = SOA ? dim3(unsigned((l.ngrow + 3) / 4), unsigned((B + 63) / 64))
+                       : dim3(unsigned((int64_t(l.ngrow) * B + 255) / 256));
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_GATHER(NRV)                                                                     \
+    hipLaunchKernelGGL((k_gather<SOA, NRV>), g, dim3(256), 0, st, D->grow_q + l.grow0,          \
+                       D->grow_y + l.grow0, l.ngrow, D->gptr, D->gidx, N->ws_y, N->ws_u, P->n,  \
+                       fvsize, nrhs, r0, B, active)
+        if (nrr == 1) SPCHOL_GATHER(1);
+        else if (nrr == 2) SPCHOL_GATHER(2);
+        else if (nrr == 3) SPCHOL_GATHER(3);
+        else SPCHOL_GATHER(4);
+#undef SPCHOL_GATHER
+    }
+    N->prof.end(st);
 }
 
 // One launch of the segment kernels for row class k.
@@ -1131,10 +1283,11 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
     }
     const dim3 pgrid(unsigned((P->n + 63) / 64), G);
     prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in_soa, pgrid, dim3(256), 0, st, D->perm, b, ldb, N->ws_y, P->n,
+    hipLaunchKernelGGL(k_perm_in_soa, pgrid, dim3(256), 0, st, D->pinv, b, ldb, N->ws_y, P->n,
                        nrhs, B);
     prof.end(st);
     for (const SLaunch &l : D->ssched) {
+        launch_gather<true>(l, P, N, nrhs, nullptr, st);
         for (int r0 = 0; r0 < nrhs; r0 += 4) {
             const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
@@ -1211,6 +1364,7 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
     prof.end(st);
     // forward: levels ascending
     for (const SLaunch &l : D->ssched) {
+        launch_gather<false>(l, P, N, nrhs, active, st);
         for (int k = 0; k < kSolveClasses; k++) {
             const SClass &cl = l.cls[k];
             if (cl.n == 0) continue;
@@ -1283,6 +1437,14 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
         s.nall = P->slv_cls_ptr[size_t(l + 1) * kSolveClasses] - s.all0;
         s.it0 = P->soa_it_ptr[l];
         s.nit = P->soa_it_ptr[l + 1] - s.it0;
+        s.grow0 = P->grow_ptr[l];
+        s.ngrow = P->grow_ptr[l + 1] - s.grow0;
+        for (int32_t q = s.grow0; q < s.grow0 + s.ngrow; q++) {
+            const int32_t row = P->grow_q[q];
+            s.v_gather += 8.0 * (1.0 + (P->grow_y[q] >= 0 ? 1.0 : 0.0) +
+                                 double(P->gptr[row + 1] - P->gptr[row])) +
+                          12.0 + 4.0 * double(P->gptr[row + 1] - P->gptr[row]);
+        }
         for (int32_t e = s.all0; e < s.all0 + s.nall; e++) {
             const SnDesc &d = P->sn[P->slv_small[e]];
             const double tri = double(d.w) * (d.w + 1) / 2, rect = double(d.m) * d.w;
