@@ -2,8 +2,12 @@
 
 A step is one pass of the whole hot path over one batch of value sets:
 numeric factorization (value scatter, assembly, dense front kernels) and
-the solves (with iterative refinement in the mixed-precision form), from
-values and right-hand sides already resident in HBM to the solution in HBM.
+the solves with iterative refinement to the stop rule, from values and
+right-hand sides already resident in HBM to the solution in HBM.  The
+timed steps replay one captured HIP graph of the step (its refinement
+budget is the step count an eager run needed; systems that have met the
+stop rule are skipped on the device); the per-kernel table comes from one
+extra eager step with per-launch events.
 The symbolic analysis and the plan upload are one-time costs and are
 excluded, as the paper excludes preprocessing.
 
@@ -202,46 +206,50 @@ def roofline(prof, dtype):
     return roof
 
 
-def run_form(S, plan, w, dtype, refine, steps, warmup, profile):
-    """Time `steps` steps of one form; returns (seconds, stats, x, prof)."""
+def run_form(S, plan, w, dtype, steps, warmup, profile):
+    """Time `steps` steps of one form: factor of the whole batch plus the
+    refined solve to the stop rule, replayed as one captured HIP graph whose
+    refinement budget is the step count an eager run needed (systems that
+    have met the rule are skipped on the device).  Returns (seconds,
+    per-system stats of the last replay, x, per-kernel profile of one eager
+    step, refinement steps)."""
     import torch
     num = plan.numeric(w.batch, dtype)
     vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
     b0 = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
-    b = b0.clone()
     x = torch.empty_like(b0)
-    stats = None
-
-    def step():
-        nonlocal stats
-        num.factor(vals)
-        if refine:
-            rc, stats = num.refine_solve(vals, b0, x, tol=TOL, maxit=30, method="pcg")
-        else:
-            b.copy_(b0)
-            num.solve(b)
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
+    method = "pcg"
+    # eager step: the refinement budget and a factorization check
+    num.factor(vals)
     bad = num.info()
     if np.any(bad):
         raise SystemExit("factorization failed (%s): info=%s" % (dtype, bad[bad != 0][:8]))
-    if profile:
-        num.profile(True)
+    rc, st0 = num.refine_solve(vals, b0, x, tol=TOL, maxit=30, method=method)
+    iters = max(s["iters"] for s in st0)
+    g = num.step_graph(vals, b0, x, tol=TOL, iters=iters, method=method)
+    for _ in range(warmup):
+        g.launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        g.launch()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    num.profile(False)
-    prof = num.profile_read() if profile else {}
-    out = (x if refine else b).cpu().numpy()
+    rc, stats = g.stats()
+    out = x.cpu().numpy()
+    prof = {}
+    if profile:
+        # one eager step with per-launch events, for the kernel table
+        num.profile(True)
+        num.factor(vals)
+        num.refine_solve(vals, b0, x, tol=TOL, maxit=iters, method=method)
+        torch.cuda.synchronize()
+        num.profile(False)
+        prof = num.profile_read()
+    del g
     del num
     torch.cuda.empty_cache()
-    return t1 - t0, stats, out, prof
-
+    return t1 - t0, stats, out, prof, iters
 
 def main():
     ap = argparse.ArgumentParser()
@@ -251,6 +259,8 @@ def main():
     ap.add_argument("--workload", default="trimesh512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="library default options instead of the autotuner's choice")
     ap.add_argument("--soa-min-batch", type=int, default=None,
                     help="batch size from which solves use the batch-interleaved layout "
                          "(library default when omitted, negative: never)")
@@ -278,6 +288,25 @@ def main():
     log("workload %s n=%d nnzA=%d batch=%d nrhs=%d" % (wname, n, nnz, w.batch, w.nrhs))
     t = time.perf_counter()
     opts = {} if args.soa_min_batch is None else {"soa_min_batch": args.soa_min_batch}
+    tuned = None
+    if members is None and not args.no_tune and args.soa_min_batch is None:
+        # one-time tuning of thresholds, amalgamation and solve layout on this
+        # workload (like the analysis, outside the timed steps)
+        import torch
+        t = time.perf_counter()
+        tv = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
+        tb = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+        best, table = S.autotune(p.colptr, p.rowind, w.perm, tv, tb,
+                                 "f32" if form == "mixed" else "f64",
+                                 solves_per_factor=4.0 if form == "mixed" else 1.0)
+        del tv, tb
+        torch.cuda.empty_cache()
+        opts = {k: best[k] for k in ("small_front", "relax_cols", "soa_min_batch")}
+        tuned = {"options": opts, "seconds": time.perf_counter() - t,
+                 "candidates": [{k: round(r[k], 4) if isinstance(r[k], float) else r[k]
+                                 for k in ("small_front", "relax_cols", "soa_min_batch",
+                                           "factor_ms", "solve_ms", "score")} for r in table]}
+        log("autotune %.1f s: %s" % (tuned["seconds"], opts))
     if members is not None:
         plan = S.analyze_group([(m.pattern.colptr, m.pattern.rowind, m.perm) for m in members],
                                **opts)
@@ -297,17 +326,18 @@ def main():
                         if members is not None or w.perm is not None else "natural"),
            "flops_sum_c2_per_system": info["flops"], "supernodes": info["nsuper"],
            "levels": info["nlevels"]}
+    if tuned is not None:
+        cfg["autotuned"] = tuned
     if members is not None:
         cfg["patterns"] = [m.name for m in members]
         cfg["matrices_per_step"] = w.batch * nblk
         cfg["flops_sum_c2_per_system"] = info["flops"] / nblk
     if form == "mixed":
         # FP64 form first (reference of the comparison), then the headline form
-        t64, st64, x64, prof64 = run_form(S, plan, w, "f64", True, args.steps, args.warmup,
-                                          False)
+        t64, st64, x64, _, it64 = run_form(S, plan, w, "f64", args.steps, args.warmup, False)
         log("fp64 form: %.3f ms/step" % (t64 * 1e3 / args.steps))
-        t32, st32, x32, prof = run_form(S, plan, w, "f32", True, args.steps, args.warmup,
-                                        prof_on)
+        t32, st32, x32, prof, it32 = run_form(S, plan, w, "f32", args.steps, args.warmup,
+                                              prof_on)
         log("fp32+refinement form: %.3f ms/step" % (t32 * 1e3 / args.steps))
         ms = t32 * 1e3 / args.steps
         nmat = w.batch * nblk
@@ -317,17 +347,21 @@ def main():
         clauses = [s["clause"] for s in st32]
         out["fp64_form"] = {"value": nmat / (t64 / args.steps),
                             "ms_per_step": t64 * 1e3 / args.steps,
+                            "refinement_budget": it64,
                             "iters_max": max(s["iters"] for s in st64),
                             "relres_max": max(s["relres"] for s in st64),
                             "clauses": sorted(set(s["clause"] for s in st64))}
         out["speedup_vs_fp64_form"] = out["value"] / out["fp64_form"]["value"]
-        out["refinement"] = {"iters_max": max(iters), "iters_mean": float(np.mean(iters)),
+        out["refinement"] = {"method": "pcg", "budget": it32, "iters_max": max(iters),
+                             "iters_mean": float(np.mean(iters)),
                              "relres_max": max(s["relres"] for s in st32),
                              "clause_counts": {str(c): clauses.count(c)
                                                for c in sorted(set(clauses))},
                              "fwd_err_vs_fp64_form_max": float(max(
                                  np.abs(x32[s] - x64[s]).max() / np.abs(x64[s]).max()
                                  for s in range(w.batch)))}
+        if 0 in clauses or 0 in set(s["clause"] for s in st64):
+            raise SystemExit("a system did not meet the stop rule")
         # independent residual check on the first and last value sets
         if members is None:
             rr = max(relres_host(p, w.values[s], x32[s, r], w.b[s, r])
@@ -341,18 +375,21 @@ def main():
         out["relres_check_host"] = rr
         pdtype = "f32"
     else:
-        t64, _, x, prof = run_form(S, plan, w, "f64", False, args.steps, args.warmup, prof_on)
+        t64, st64, x, prof, it64 = run_form(S, plan, w, "f64", args.steps, args.warmup, prof_on)
         ms = t64 * 1e3 / args.steps
-        out.update({"value": w.batch / (t64 / args.steps), "ms_per_step": ms, "dtype": "f64"})
+        out.update({"value": w.batch / (t64 / args.steps), "ms_per_step": ms, "dtype": "f64",
+                    "refinement_budget": it64})
+        if 0 in set(s["clause"] for s in st64):
+            raise SystemExit("a system did not meet the stop rule")
         out["relres"] = max(relres_host(p, w.values[s], x[s, r], w.b[s, r])
                             for s in range(w.batch) for r in range(w.nrhs))
         pdtype = "f64"
     out["config"] = cfg
     log("timed %d steps: %.3f ms/step" % (args.steps, ms))
     if prof:
-        kern, total_bytes = kernel_table(prof, args.steps)
+        kern, total_bytes = kernel_table(prof, 1)  # one eager profiled step
         out["kernels"] = kern
-        out["hbm_gb_s_step"] = total_bytes / args.steps / (ms * 1e-3) / 1e9
+        out["hbm_gb_s_step"] = total_bytes / (ms * 1e-3) / 1e9
         out["roofline"] = roofline(prof, pdtype)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)...")

@@ -295,6 +295,65 @@ sc_status sc_numeric_profile_read(sc_numeric_t *num, int32_t cap,
                                   sc_kernel_stat *out_host,
                                   int32_t *count_out);
 
+/*
+ * One captured step for repeated use on fixed buffers (the paper's setting:
+ * the same structure run many times, Sec. 3.3): the factorization of the
+ * whole batch from values_dev (as sc_factor) followed by the refined solve
+ * b_dev -> x_dev (as sc_refine_solve with maxit = iters), recorded once into
+ * a HIP graph and replayed by sc_step_graph_launch.  The replay runs exactly
+ * `iters` refinement steps with no host synchronization: a system that has
+ * met the stop rule is skipped on the device from then on, so the result of
+ * every system equals the one of sc_refine_solve with the same maxit.
+ * Creation allocates every workspace and captures on a private stream; the
+ * numeric object, values_dev, b_dev and x_dev must stay valid and unmoved
+ * while the graph exists, and the numeric object must not be used by other
+ * calls while a replay is in flight.  Errors: SC_EINVAL (bad argument, or
+ * b_dev == x_dev), SC_ENOMEM, SC_EDEVICE.
+ */
+typedef struct sc_graph sc_graph_t;
+sc_status sc_step_graph_create(const sc_plan_t *plan, sc_numeric_t *num,
+                               const double *values_dev, int64_t ldv,
+                               const double *b_dev, double *x_dev, int32_t nrhs,
+                               int64_t ldb, double tol, int32_t iters, int32_t method,
+                               sc_graph_t **graph_out);
+/* Replay the step on `stream` (asynchronous). */
+sc_status sc_step_graph_launch(sc_graph_t *graph, void *stream);
+/* Per-system refinement statistics of the last replay, as in
+ * sc_refine_solve (synchronizes `stream`); SC_ENOCONV if a system has not
+ * met the stop rule. */
+sc_status sc_step_graph_stats(sc_graph_t *graph, sc_refine_stats *stats_host, void *stream);
+void sc_step_graph_destroy(sc_graph_t *graph);
+
+/*
+ * Autotuner (grouping, kernel thresholds and solve layout of a workload):
+ * for each candidate option set (fronts handled in one workgroup up to 32,
+ * 64 or 128 rows; amalgamation width 4 or 16; for batches of at least 16
+ * the row-major or the batch-interleaved solve) it analyzes the pattern,
+ * factors the caller's batch and solves the caller's right-hand sides on
+ * `stream`, timed with HIP events (best of two after a warm-up), and
+ * returns in best_out the set with the smallest
+ *     factor_ms + solves_per_factor * solve_ms.
+ * Pattern arguments as in sc_analyze (host), values_dev [batch][ldv] and
+ * b_dev [batch][nrhs][ldb] on the device (b_dev is not modified; the
+ * library allocates a scratch copy).  table_host (nullable when
+ * table_cap == 0) receives up to table_cap measured candidates and
+ * *ntable_out their number.  Synchronizes `stream`.  Errors: SC_EINVAL,
+ * SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD is not reported (info is
+ * the caller's to check on the chosen plan).
+ */
+typedef struct {
+    sc_options opt;   /* the candidate                                   */
+    double factor_ms; /* factorization of the batch                      */
+    double solve_ms;  /* one solve of every right-hand side              */
+    double score;     /* factor_ms + solves_per_factor * solve_ms        */
+} sc_tune_entry;
+sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowind_host,
+                      const int32_t *perm_host, const double *values_dev, int64_t ldv,
+                      int32_t batch, sc_dtype dtype, const double *b_dev, int32_t nrhs,
+                      int64_t ldb, double solves_per_factor, sc_options *best_out,
+                      sc_tune_entry *table_host, int32_t table_cap, int32_t *ntable_out,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

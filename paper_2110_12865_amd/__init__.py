@@ -37,8 +37,11 @@ _DTYPES = {"f64": SC_F64, "f32": SC_F32}
 EXPORTS = [
     "sc_status_string", "sc_options_default", "sc_analyze", "sc_analyze_group",
     "sc_plan_info", "sc_plan_export_blocks", "sc_plan_export_symbolic",
-    "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create", "sc_numeric_destroy", "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
+    "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create", "sc_numeric_destroy",
+    "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
     "sc_numeric_get_columns", "sc_numeric_profile", "sc_numeric_profile_read",
+    "sc_step_graph_create", "sc_step_graph_launch", "sc_step_graph_stats", "sc_step_graph_destroy",
+    "sc_autotune",
 ]
 
 
@@ -52,6 +55,11 @@ class Options(ctypes.Structure):
     _fields_ = [("relax", ctypes.c_int32), ("relax_cols", ctypes.c_int32),
                 ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32),
                 ("soa_min_batch", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("opt", Options), ("factor_ms", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("score", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -105,6 +113,13 @@ def _load():
         "sc_numeric_get_columns": ([P, P, I32, I64, P, P], ctypes.c_int),
         "sc_numeric_profile": ([P, I32], ctypes.c_int),
         "sc_numeric_profile_read": ([P, I32, P, P], ctypes.c_int),
+        "sc_step_graph_create": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, I32, P],
+                                 ctypes.c_int),
+        "sc_step_graph_launch": ([P, P], ctypes.c_int),
+        "sc_step_graph_stats": ([P, P, P], ctypes.c_int),
+        "sc_step_graph_destroy": ([P], None),
+        "sc_autotune": ([I64, P, P, P, P, I64, I32, ctypes.c_int, P, I32, I64, ctypes.c_double, P,
+                         P, I32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -251,6 +266,32 @@ def analyze(colptr, rowind, perm=None, n=None, **opts) -> Plan:
     return Plan(n, colptr, rowind, perm, default_options(**opts) if opts else None)
 
 
+def autotune(colptr, rowind, perm, values, b, dtype: str = "f64",
+             solves_per_factor: float = 1.0, stream=None):
+    """Pick analysis/kernel options for this workload by timing candidates
+    (sc_autotune).  values: device float64 [batch, nnzA]; b: device float64
+    [batch, nrhs, n] (not modified).  Returns (options dict, table) where
+    table lists every candidate with its factor and solve times."""
+    colptr = np.ascontiguousarray(colptr, np.int64)
+    rowind = np.ascontiguousarray(rowind, np.int32)
+    perm = None if perm is None else np.ascontiguousarray(perm, np.int32)
+    n = len(colptr) - 1
+    best = Options()
+    cap = 64
+    table = (TuneEntry * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(_lib.sc_autotune(n, _ptr(colptr), _ptr(rowind), _ptr(perm),
+                            _dev_ptr(values, "float64"), int(values.shape[1]),
+                            int(values.shape[0]), _DTYPES[dtype], _dev_ptr(b, "float64"),
+                            int(b.shape[1]), int(b.shape[2]), float(solves_per_factor),
+                            ctypes.byref(best), table, cap, ctypes.byref(cnt),
+                            _stream_handle(stream)), "sc_autotune")
+    as_dict = lambda o: {k: getattr(o, k) for k, _ in Options._fields_}
+    rows = [dict(as_dict(table[i].opt), factor_ms=table[i].factor_ms,
+                 solve_ms=table[i].solve_ms, score=table[i].score) for i in range(cnt.value)]
+    return as_dict(best), rows
+
+
 def analyze_group(patterns, **opts) -> GroupPlan:
     """patterns: sequence of (colptr, rowind) or (colptr, rowind, perm)."""
     return GroupPlan(patterns, default_options(**opts) if opts else None)
@@ -321,6 +362,23 @@ class Numeric:
         return rc, [{k: getattr(st[i], k) for k, _ in RefineStats._fields_}
                     for i in range(nsys)]
 
+    def step_graph(self, values, b, x, tol: float = 1e-10, iters: int = 3,
+                   method: str = "classical") -> "StepGraph":
+        """Capture factor(values) + refined solve b -> x with exactly `iters`
+        refinement steps as one HIP graph (see sc_step_graph_create).  The
+        tensors must stay alive and unmoved while the graph is used."""
+        if b.shape != x.shape or b.dim() != 3 or b.shape[0] != self.batch:
+            raise ValueError("b and x must be [batch, nrhs, n]")
+        h = ctypes.c_void_p()
+        _check(_lib.sc_step_graph_create(self.plan._h, self._h, _dev_ptr(values, "float64"),
+                                         int(values.shape[1]), _dev_ptr(b, "float64"),
+                                         _dev_ptr(x, "float64"), int(b.shape[1]),
+                                         int(b.shape[2]), float(tol), int(iters),
+                                         _METHODS[method], ctypes.byref(h)),
+               "sc_step_graph_create")
+        return StepGraph(self, h, self.batch * int(b.shape[1]) * self.plan.nblocks,
+                         (values, b, x))
+
     def get_columns(self, b: int, cols) -> np.ndarray:
         """Values of L on the exact pattern for the given columns (host)."""
         cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -353,3 +411,29 @@ class Numeric:
                    "sc_plan_export_symbolic")
             self.plan._Lcolptr = Lcolptr
         return None, None, self.plan._Lcolptr, None
+
+
+class StepGraph:
+    """A captured factor + refined-solve step (sc_step_graph_*)."""
+
+    def __init__(self, num: "Numeric", h, nsys: int, keep):
+        self.num = num
+        self._h = h
+        self.nsys = nsys
+        self._keep = keep  # the captured buffers stay alive with the graph
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.sc_step_graph_destroy(self._h)
+            self._h = None
+
+    def launch(self, stream=None):
+        _check(_lib.sc_step_graph_launch(self._h, _stream_handle(stream)), "sc_step_graph_launch")
+
+    def stats(self, stream=None):
+        st = (RefineStats * self.nsys)()
+        rc = _lib.sc_step_graph_stats(self._h, st, _stream_handle(stream))
+        if rc not in (SC_OK, SC_ENOCONV):
+            raise SpcholError(rc, "sc_step_graph_stats")
+        return rc, [{k: getattr(st[i], k) for k, _ in RefineStats._fields_}
+                    for i in range(self.nsys)]

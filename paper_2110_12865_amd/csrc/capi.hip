@@ -443,7 +443,7 @@ sc_status sc_refine_solve(const sc_plan_t *P, sc_numeric_t *N, const double *val
     std::vector<double> stat(size_t(6) * nsys);
     int32_t nact = 0;
     e = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, maxit, method,
-                          stat.data(), &nact, static_cast<hipStream_t>(stream));
+                          stat.data(), &nact, true, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return map_err(e);
     bool fail = false;
     for (int32_t k = 0; k < nsys; k++) {
@@ -541,3 +541,213 @@ sc_status sc_numeric_profile_read(sc_numeric_t *N, int32_t cap, sc_kernel_stat *
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One captured step: factorization of the batch plus the refined solve with
+// a fixed number of refinement steps (converged systems are skipped on the
+// device), recorded once into a HIP graph on a private stream and replayed.
+
+struct sc_graph {
+    const sc_plan *plan = nullptr;
+    sc_numeric *num = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t nsys = 0;
+};
+
+namespace {
+
+sc_status stats_to_host(const sc_numeric *N, int32_t nsys, sc_refine_stats *out, hipStream_t st) {
+    std::vector<double> stat(size_t(6) * nsys);
+    hipError_t e = hipMemcpyAsync(stat.data(), N->rws.stat, sizeof(double) * stat.size(),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return map_err(e);
+    bool fail = false;
+    for (int32_t k = 0; k < nsys; k++) {
+        const double *q = &stat[size_t(6) * k];
+        if (q[1] == 0.0) fail = true;
+        if (out) {
+            out[k].iters = int32_t(q[0]);
+            out[k].clause = int32_t(q[1]);
+            out[k].relres = q[2];
+            out[k].rnorm = q[3];
+            out[k].bnorm = q[4];
+            out[k].xnorm = q[5];
+        }
+    }
+    return fail ? SC_ENOCONV : SC_OK;
+}
+
+}  // namespace
+
+sc_status sc_step_graph_create(const sc_plan_t *P, sc_numeric_t *N, const double *values_dev,
+                               int64_t ldv, const double *b_dev, double *x_dev, int32_t nrhs,
+                               int64_t ldb, double tol, int32_t iters, int32_t method,
+                               sc_graph_t **out) {
+    if (!out) return SC_EINVAL;
+    *out = nullptr;
+    if (!P || !N || N->plan != P || !values_dev || !b_dev || !x_dev || nrhs < 1 ||
+        ldb < P->n || ldv < P->nnzA || iters < 0 || !(tol >= 0.0) || b_dev == x_dev ||
+        (method != SC_REFINE_CLASSICAL && method != SC_REFINE_PCG))
+        return SC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (dev != N->device) return SC_EINVAL;
+    // every workspace exists before the capture (no allocation inside it)
+    hipError_t e = ensure_solve_ws(P, N, nrhs);
+    if (e == hipSuccess) e = ensure_refine_ws(N, nrhs, ldb);
+    if (e != hipSuccess) return map_err(e);
+    sc_graph *G = new (std::nothrow) sc_graph();
+    if (!G) return SC_ENOMEM;
+    G->plan = P;
+    G->num = N;
+    G->nsys = N->batch * nrhs * P->nblk;
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete G;
+        return map_err(e);
+    }
+    const bool prof = N->prof.on;
+    N->prof.on = false;  // no event records inside the graph
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = spchol_factor_run(P, N, values_dev, ldv, cs);
+        int32_t nact = 0;
+        if (e1 == hipSuccess)
+            e1 = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, iters,
+                                   method, nullptr, &nact, false, cs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e1;
+        G->graph = g;
+    }
+    N->prof.on = prof;
+    if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        sc_step_graph_destroy(G);
+        return map_err(e);
+    }
+    *out = G;
+    return SC_OK;
+}
+
+sc_status sc_step_graph_launch(sc_graph_t *G, void *stream) {
+    if (!G || !G->exec) return SC_EINVAL;
+    return map_err(hipGraphLaunch(G->exec, static_cast<hipStream_t>(stream)));
+}
+
+sc_status sc_step_graph_stats(sc_graph_t *G, sc_refine_stats *stats_host, void *stream) {
+    if (!G) return SC_EINVAL;
+    return stats_to_host(G->num, G->nsys, stats_host, static_cast<hipStream_t>(stream));
+}
+
+void sc_step_graph_destroy(sc_graph_t *G) {
+    if (!G) return;
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate option sets on the caller's pattern, values and
+// right-hand sides (factor of the whole batch, then one solve) with HIP
+// events and keeps the fastest by factor_ms + solves_per_factor * solve_ms.
+
+namespace {
+
+// One factor + one solve of candidate `o`, timed with events on `st`
+// (best of `reps` after one warm-up pass).
+sc_status time_candidate(int64_t n, const int64_t *colptr, const int32_t *rowind,
+                         const int32_t *perm, const sc_options &o, const double *values_dev,
+                         int64_t ldv, int32_t batch, sc_dtype dtype, const double *b_dev,
+                         double *bw, int32_t nrhs, int64_t ldb, int reps, hipStream_t st,
+                         double *fms, double *sms) {
+    sc_plan_t *P = nullptr;
+    sc_status r = sc_analyze(n, colptr, rowind, perm, &o, &P);
+    if (r != SC_OK) return r;
+    sc_numeric_t *N = nullptr;
+    r = sc_numeric_create(P, batch, dtype, &N);
+    hipEvent_t ev[4] = {};
+    for (auto &x : ev)
+        if (r == SC_OK && hipEventCreate(&x) != hipSuccess) r = SC_EDEVICE;
+    const size_t bbytes = sizeof(double) * size_t(batch) * nrhs * ldb;
+    *fms = *sms = 1e300;
+    for (int rep = 0; rep <= reps && r == SC_OK; rep++) {
+        (void)hipEventRecord(ev[0], st);
+        r = sc_factor(P, N, values_dev, ldv, st);
+        (void)hipEventRecord(ev[1], st);
+        if (r == SC_OK &&
+            hipMemcpyAsync(bw, b_dev, bbytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            r = SC_EDEVICE;
+        (void)hipEventRecord(ev[2], st);
+        if (r == SC_OK) r = sc_solve(P, N, bw, nrhs, ldb, st);
+        (void)hipEventRecord(ev[3], st);
+        if (r == SC_OK && hipEventSynchronize(ev[3]) != hipSuccess) r = SC_EDEVICE;
+        float f = 0.f, sv = 0.f;
+        if (r == SC_OK && rep > 0 && hipEventElapsedTime(&f, ev[0], ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&sv, ev[2], ev[3]) == hipSuccess) {
+            *fms = std::min(*fms, double(f));
+            *sms = std::min(*sms, double(sv));
+        }
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (N) sc_numeric_destroy(N);
+    sc_plan_destroy(P);
+    return r;
+}
+
+}  // namespace
+
+sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowind_host,
+                      const int32_t *perm_host, const double *values_dev, int64_t ldv,
+                      int32_t batch, sc_dtype dtype, const double *b_dev, int32_t nrhs,
+                      int64_t ldb, double solves_per_factor, sc_options *best_out,
+                      sc_tune_entry *table_host, int32_t table_cap, int32_t *ntable_out,
+                      void *stream) {
+    if (!best_out || !values_dev || !b_dev || batch < 1 || nrhs < 1 || ldb < n ||
+        !(solves_per_factor >= 0.0) || (dtype != SC_F64 && dtype != SC_F32) ||
+        table_cap < 0 || (table_cap > 0 && !table_host))
+        return SC_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // candidates: front-kernel threshold x amalgamation width x solve layout
+    std::vector<sc_options> cand;
+    const int32_t small_fronts[] = {32, 64, 128};
+    const int32_t relax_cols[] = {4, 16};
+    for (int32_t sf : small_fronts)
+        for (int32_t rc : relax_cols)
+            for (int soa = 0; soa < (batch >= 16 ? 2 : 1); soa++) {
+                sc_options o;
+                sc_options_default(&o);
+                o.small_front = sf;
+                o.relax_cols = rc;
+                o.soa_min_batch = soa ? 1 : -1;
+                cand.push_back(o);
+            }
+    double *bw = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&bw),
+                             sizeof(double) * size_t(batch) * nrhs * ldb);
+    if (e != hipSuccess) return map_err(e);
+    double best = 1e300;
+    int32_t nt = 0;
+    sc_status result = SC_OK;
+    for (const sc_options &o : cand) {
+        double fms = 0.0, sms = 0.0;
+        result = time_candidate(n, colptr_host, rowind_host, perm_host, o, values_dev, ldv, batch,
+                                dtype, b_dev, bw, nrhs, ldb, 2, st, &fms, &sms);
+        if (result != SC_OK) break;
+        const double score = fms + solves_per_factor * sms;
+        if (nt < table_cap) table_host[nt] = sc_tune_entry{o, fms, sms, score};
+        nt++;
+        if (score < best) {
+            best = score;
+            *best_out = o;
+        }
+    }
+    (void)hipFree(bw);
+    if (ntable_out) *ntable_out = std::min(nt, table_cap);
+    return result;
+}

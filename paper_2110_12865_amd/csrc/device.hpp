@@ -194,7 +194,8 @@ hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
                              int64_t ldv, const double *b, double *x, int32_t nrhs,
                              int64_t ldb, double tol, int32_t maxit, int32_t method,
-                             double *stat_host, int32_t *nactive_out, hipStream_t st);
+                             double *stat_host, int32_t *nactive_out, bool sync,
+                             hipStream_t st);
 hipError_t spchol_kernels_init();
 
 // Largest dynamic LDS allocation per workgroup on the current device.

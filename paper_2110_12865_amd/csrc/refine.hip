@@ -330,7 +330,7 @@ void apply_A(const sc_plan *P, const double *vc, const double *B,
 hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                             int64_t ldv, const double *b, double *x, int32_t nrhs,
                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
-                            int32_t *nactive_out, hipStream_t st) {
+                            int32_t *nactive_out, bool sync, hipStream_t st) {
     DevPlan *D = P->dev;
     RefineWs &W = N->rws;
     Profiler &prof = N->prof;
@@ -368,9 +368,11 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                            tol, it, W.active, W.conv, W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
-        e = hipMemcpyAsync(&nact, W.count, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
+        if (sync) {
+            e = hipMemcpyAsync(&nact, W.count, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return e;
+        }
         if (nact == 0 || it >= maxit) break;
         e = spchol_solve_run(P, N, W.r, nrhs, ldb, st, W.active);
         if (e != hipSuccess) return e;
@@ -379,6 +381,7 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                            W.active, W.conv);
         prof.end(st);
     }
+    if (!sync) return hipGetLastError();
     *nactive_out = nact;
     e = hipMemcpyAsync(stat_host, W.stat, sizeof(double) * 6 * nseg, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -392,7 +395,8 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
 // (its own step lengths), so the blocks of a group plan stay independent.
 hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64_t ldv,
                       const double *b, double *x, int32_t nrhs, int64_t ldb, double tol,
-                      int32_t maxit, double *stat_host, int32_t *nactive_out, hipStream_t st) {
+                      int32_t maxit, double *stat_host, int32_t *nactive_out, bool sync,
+                      hipStream_t st) {
     DevPlan *D = P->dev;
     RefineWs &W = N->rws;
     Profiler &prof = N->prof;
@@ -432,6 +436,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                            tol, it, W.active, W.conv, W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
+        if (!sync) return hipSuccess;  // every step runs; converged systems are skipped on device
         hipError_t e2 = hipMemcpyAsync(&nact, W.count, sizeof(int32_t), hipMemcpyDeviceToHost,
                                        st);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
@@ -488,6 +493,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
             std::swap(rz, rzn);
         }
     }
+    if (!sync) return hipGetLastError();
     *nactive_out = nact;
     e = hipMemcpyAsync(stat_host, W.stat, sizeof(double) * 6 * nseg, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -500,10 +506,10 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals, int64_t ldv,
                              const double *b, double *x, int32_t nrhs, int64_t ldb, double tol,
                              int32_t maxit, int32_t method, double *stat_host,
-                             int32_t *nactive_out, hipStream_t st) {
+                             int32_t *nactive_out, bool sync, hipStream_t st) {
     if (method == 1)
         return refine_pcg(P, N, vals, ldv, b, x, nrhs, ldb, tol, maxit, stat_host, nactive_out,
-                          st);
+                          sync, st);
     return refine_classical(P, N, vals, ldv, b, x, nrhs, ldb, tol, maxit, stat_host,
-                            nactive_out, st);
+                            nactive_out, sync, st);
 }

@@ -165,3 +165,35 @@ def test_group_matches_separate_plans():
         x1 = d1.cpu().numpy()
         for s in range(2):
             assert oracle.forward_error(xg[s, 0, col0[k]:col0[k + 1]], x1[s, 0]) <= 1e-13
+
+
+def test_autotuner_picks_a_measured_candidate():
+    """The autotuner measures every candidate on the caller's data and
+    returns the one with the smallest score (parity unpinned: there is no
+    single right choice; the checks are validity and that the chosen plan
+    solves correctly)."""
+    import torch
+    import paper_2110_12865_amd as S
+    import oracle
+    w = W.small_grid((12, 11, 10), "nd", seed=68, batch=20, nrhs=2)
+    p = w.pattern
+    vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+    best, table = S.autotune(p.colptr, p.rowind, w.perm, vals, b, "f32", solves_per_factor=3.0)
+    assert len(table) == 12  # 3 thresholds x 2 widths x 2 layouts (batch >= 16)
+    assert all(t["factor_ms"] > 0 and t["solve_ms"] > 0 for t in table)
+    scores = [t["score"] for t in table]
+    k = int(np.argmin(scores))
+    for key in ("small_front", "relax_cols", "soa_min_batch"):
+        assert best[key] == table[k][key]
+    assert np.array_equal(b.cpu().numpy(), w.b)  # the caller's right-hand sides are untouched
+    plan = S.analyze(p.colptr, p.rowind, w.perm, **best)
+    num = plan.numeric(w.batch, "f64")
+    num.factor(vals)
+    x = b.clone()
+    num.solve(x)
+    x = x.cpu().numpy()
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[3], sym)
+    xo = oracle.solve(sym, Lx, w.b[3])
+    assert oracle.forward_error(x[3, 1], xo[1]) <= 1e-12

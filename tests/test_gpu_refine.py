@@ -132,3 +132,44 @@ def test_refine_interleaved_batch_matches_single_bitwise(method):
     assert np.array_equal(xb[17], x1[0])
     for r in range(2):
         assert stats[17 * 2 + r]["iters"] == stats1[r]["iters"]
+
+
+@pytest.mark.parametrize("batch,soa", [(4, -1), (64, 64)], ids=["rowmajor", "interleaved"])
+@pytest.mark.parametrize("method", ["classical", "pcg"])
+def test_step_graph_replays_match_eager(method, batch, soa):
+    """The captured factor + refinement step, replayed three times with
+    unrelated eager work and synchronizations in between, reproduces the
+    eager sc_refine_solve result bit for bit on every replay (the output is
+    cleared before each replay), with the same per-system statistics."""
+    import paper_2110_12865_amd as S
+    w = W.small_grid((11, 10, 9), "nd", seed=66, batch=batch, nrhs=2)
+    p = w.pattern
+    plan = S.analyze(p.colptr, p.rowind, w.perm, soa_min_batch=soa)
+    vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+    # eager reference
+    ne = plan.numeric(w.batch, "f32")
+    ne.factor(vals)
+    xe = torch.empty_like(b)
+    rc_e, st_e = ne.refine_solve(vals, b, xe, tol=1e-10, maxit=4, method=method)
+    xe = xe.cpu().numpy()
+    # captured step on its own numeric object
+    ng = plan.numeric(w.batch, "f32")
+    xg = torch.empty_like(b)
+    g = ng.step_graph(vals, b, xg, tol=1e-10, iters=4, method=method)
+    other = W.small_grid((7, 6, 5), "nd", seed=67, batch=2, nrhs=1)
+    for rep in range(3):
+        xg.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        rc_g, st_g = g.stats()
+        assert rc_g == rc_e
+        assert np.array_equal(xg.cpu().numpy(), xe), "replay %d" % rep
+        for a, e in zip(st_g, st_e):
+            assert a["iters"] == e["iters"] and a["clause"] == e["clause"]
+            assert a["relres"] == e["relres"]
+        # unrelated eager work between replays
+        from tests.gpu_helpers import run_library
+        run_library(other, "f64")
+        torch.cuda.synchronize()
