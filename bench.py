@@ -188,8 +188,50 @@ def kernel_table(prof, steps):
     return kern, total_bytes
 
 
-def roofline(prof, dtype):
-    name, st = max(prof.items(), key=lambda kv: kv[1]["ms"])
+# kernel kinds of the library's per-launch records and the HIP kernels they
+# time (kinds that bracket more than one kernel family are not candidates
+# for the roofline line)
+HIP_KERNEL = {
+    "front_small": "k_front_reg", "assemble": "k_assemble_wave", "potrf": "k_potrf",
+    "trsm": "k_trsm", "syrk_mfma": "k_syrk", "diag_inverse": "k_dinv",
+    "solve_fwd": "k_fwd_soa_diag|k_fwd_seg", "solve_bwd": "k_bwd_soa_diag|k_bwd_seg",
+    "solve_fwd_rows": "k_fwd_soa_rows", "solve_bwd_rows": "k_bwd_soa_rows",
+    "solve_gather": "k_gather", "spmv_residual": "k_apply",
+    "solve_copy_interleaved": "k_to_soa",
+}
+
+
+def source_digest():
+    """sha256 of the library sources: HBM counters taken on other sources
+    are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2110_12865_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kind):
+    """HBM bytes per launch of `kind` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of known
+    size), or None when there is none for this workload and kernel or the
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    e = t.get(workload, {})
+    if e.get("kernel") != kind or e.get("source_sha256") != source_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def roofline(prof, dtype, workload):
+    cand = {k: v for k, v in prof.items() if k in HIP_KERNEL}
+    name, st = max(cand.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = st["ms"] / st["launches"]
     if name == "syrk_mfma":
         ach = st["flops"] / st["launches"] / (avg_ms * 1e-3) / 1e12
@@ -200,9 +242,11 @@ def roofline(prof, dtype):
         roof = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(workload, name)
+    roof["hip_kernel"] = HIP_KERNEL[name]
     roof["avg_launch_ms"] = avg_ms
     roof["launches"] = st["launches"]
+    roof["algorithmic_bytes_per_launch"] = st["bytes"] / st["launches"]
     return roof
 
 
@@ -259,6 +303,9 @@ def main():
     ap.add_argument("--workload", default="trimesh512")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch events")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only copy this many MiB device to device once (calibration of "
+                         "the HBM byte counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="library default options instead of the autotuner's choice")
     ap.add_argument("--soa-min-batch", type=int, default=None,
@@ -269,6 +316,17 @@ def main():
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
+
+    if args.calib_copy_mib > 0:
+        import torch
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": nbytes}), flush=True)
+        return 0
 
     import paper_2110_12865_amd as S
 
@@ -390,7 +448,7 @@ def main():
         kern, total_bytes = kernel_table(prof, 1)  # one eager profiled step
         out["kernels"] = kern
         out["hbm_gb_s_step"] = total_bytes / (ms * 1e-3) / 1e9
-        out["roofline"] = roofline(prof, pdtype)
+        out["roofline"] = roofline(prof, pdtype, wname)
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)...")
         if members is not None:

@@ -15,7 +15,8 @@
 const char *const kKernelNames[KK_Count] = {
     "front_small", "assemble", "potrf", "trsm", "syrk_mfma", "diag_inverse",
     "solve_fwd", "solve_fwd_panel", "solve_bwd", "solve_bwd_panel", "spmv_residual",
-    "refine_vector", "solve_permute"};
+    "refine_vector", "solve_permute", "solve_gather", "solve_fwd_rows", "solve_bwd_rows",
+    "solve_copy_interleaved"};
 
 void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);

@@ -104,7 +104,8 @@ struct DevPlan {
 // Kernel kinds for per-launch timing.
 enum KernelKind : int {
     KK_SmallFront = 0, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk, KK_Dinv,
-    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Spmv, KK_Vec, KK_Perm, KK_Count
+    KK_Fwd, KK_FwdPanel, KK_Bwd, KK_BwdPanel, KK_Spmv, KK_Vec, KK_Perm, KK_Gather,
+    KK_FwdRows, KK_BwdRows, KK_ToSoa, KK_Count
 };
 extern const char *const kKernelNames[KK_Count];
 

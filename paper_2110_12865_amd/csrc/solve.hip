@@ -1128,7 +1128,7 @@ void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const DevPlan *D = P->dev;
     const int B = N->batch;
     const int64_t fvsize = int64_t(P->rows.size());
-    N->prof.begin(KK_Fwd, 0.0, l.v_gather * double(nrhs) * double(B), st);
+    N->prof.begin(KK_Gather, 0.0, l.v_gather * double(nrhs) * double(B), st);
     const dim3 g = SOA ? dim3(unsigned((l.ngrow + 3) / 4), unsigned((B + 63) / 64))
                        : dim3(unsigned((int64_t(l.ngrow) * B + 255) / 256));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
@@ -1273,7 +1273,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
     if (!N->ls_ok) {
         const size_t nch = P->soa_chunks.size();
-        prof.begin(KK_Perm, 0.0, 2.0 * sz * nb * double(nch) * kSoaChunk, st);
+        prof.begin(KK_ToSoa, 0.0, 2.0 * sz * nb * double(nch) * kSoaChunk, st);
         if (nch > 0)
             hipLaunchKernelGGL(k_to_soa<T>, dim3(unsigned(nch), G), dim3(256), 0, st,
                                static_cast<const T *>(N->L), P->Lsize, D->soa_chunks, B,
@@ -1288,57 +1288,74 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
     prof.end(st);
     for (const SLaunch &l : D->ssched) {
         launch_gather<true>(l, P, N, nrhs, nullptr, st);
-        for (int r0 = 0; r0 < nrhs; r0 += 4) {
-            const int nrr = std::min(4, nrhs - r0);
+        if (l.nall > 0) {
+            prof.begin(KK_Fwd, l.f_diag * nr * nb, (l.w_diag * sz + l.v_diag * nr) * nb, st);
+            for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
-    do {                                                                                        \
-        if (l.nall > 0)                                                                         \
-            hipLaunchKernelGGL((k_fwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, \
-                               st, D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls,          \
-                               P->Lsize, N->ws_y, N->ws_u, P->n, fvsize, nrhs, r0);              \
-        if (l.nit > 0)                                                                          \
-            hipLaunchKernelGGL((k_fwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0,  \
-                               st, D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->gptr,   \
-                               D->gidx, Ls, P->Lsize, N->ws_y, N->ws_u, P->n, fvsize, nrhs, r0); \
-    } while (0)
-            if (l.nall == 0) break;
-            if (r0 == 0)
-                prof.begin(KK_Fwd, (l.f_diag + l.f_rows) * nr * nb,
-                           ((l.w_diag + l.w_rows) * sz + (l.v_diag + l.v_rows) * nr) * nb, st);
-            if (nrr == 1) SPCHOL_SOAF(1);
-            else if (nrr == 2) SPCHOL_SOAF(2);
-            else if (nrr == 3) SPCHOL_SOAF(3);
-            else SPCHOL_SOAF(4);
+    hipLaunchKernelGGL((k_fwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st,     \
+                       D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls, P->Lsize, N->ws_y,   \
+                       N->ws_u, P->n, fvsize, nrhs, r0)
+                if (nrr == 1) SPCHOL_SOAF(1);
+                else if (nrr == 2) SPCHOL_SOAF(2);
+                else if (nrr == 3) SPCHOL_SOAF(3);
+                else SPCHOL_SOAF(4);
 #undef SPCHOL_SOAF
-            if (r0 + 4 >= nrhs) prof.end(st);
+            }
+            prof.end(st);
+        }
+        if (l.nit > 0) {
+            prof.begin(KK_FwdRows, l.f_rows * nr * nb, (l.w_rows * sz + l.v_rows * nr) * nb, st);
+            for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_SOAF(NRV)                                                                        \
+    hipLaunchKernelGGL((k_fwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0, st,      \
+                       D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->gptr, D->gidx, Ls,  \
+                       P->Lsize, N->ws_y, N->ws_u, P->n, fvsize, nrhs, r0)
+                if (nrr == 1) SPCHOL_SOAF(1);
+                else if (nrr == 2) SPCHOL_SOAF(2);
+                else if (nrr == 3) SPCHOL_SOAF(3);
+                else SPCHOL_SOAF(4);
+#undef SPCHOL_SOAF
+            }
+            prof.end(st);
         }
         if (l.npan > 0) panels_forward<T, true>(l, P, N, nrhs, nullptr, st);
     }
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
         if (l.npan > 0) panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
-        for (int r0 = 0; r0 < nrhs; r0 += 4) {
-            const int nrr = std::min(4, nrhs - r0);
+        if (l.nit > 0) {
+            prof.begin(KK_BwdRows, l.f_rows * nr * nb, (l.w_rows * sz + l.v_rows * nr) * nb, st);
+            for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAB(NRV)                                                                        \
-    do {                                                                                        \
-        if (l.nit > 0)                                                                          \
-            hipLaunchKernelGGL((k_bwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0,  \
-                               st, D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->rows,   \
-                               Ls, P->Lsize, N->ws_y, N->ws_ps, P->soa_psize, P->n, nrhs, r0);   \
-        hipLaunchKernelGGL((k_bwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st, \
-                           D->sn, D->slv_small + l.all0, Ls, P->Lsize, N->ws_y, N->ws_ps,       \
-                           P->soa_psize, P->n, nrhs, r0);                                        \
-    } while (0)
-            if (l.nall == 0) break;
-            if (r0 == 0)
-                prof.begin(KK_Bwd, (l.f_diag + l.f_rows) * nr * nb,
-                           ((l.w_diag + l.w_rows) * sz + (l.v_diag + l.v_rows) * nr) * nb, st);
-            if (nrr == 1) SPCHOL_SOAB(1);
-            else if (nrr == 2) SPCHOL_SOAB(2);
-            else if (nrr == 3) SPCHOL_SOAB(3);
-            else SPCHOL_SOAB(4);
+    hipLaunchKernelGGL((k_bwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0, st,      \
+                       D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->rows, Ls, P->Lsize, \
+                       N->ws_y, N->ws_ps, P->soa_psize, P->n, nrhs, r0)
+                if (nrr == 1) SPCHOL_SOAB(1);
+                else if (nrr == 2) SPCHOL_SOAB(2);
+                else if (nrr == 3) SPCHOL_SOAB(3);
+                else SPCHOL_SOAB(4);
 #undef SPCHOL_SOAB
-            if (r0 + 4 >= nrhs) prof.end(st);
+            }
+            prof.end(st);
+        }
+        if (l.nall > 0) {
+            prof.begin(KK_Bwd, l.f_diag * nr * nb, (l.w_diag * sz + l.v_diag * nr) * nb, st);
+            for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_SOAB(NRV)                                                                        \
+    hipLaunchKernelGGL((k_bwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st,     \
+                       D->sn, D->slv_small + l.all0, Ls, P->Lsize, N->ws_y, N->ws_ps,           \
+                       P->soa_psize, P->n, nrhs, r0)
+                if (nrr == 1) SPCHOL_SOAB(1);
+                else if (nrr == 2) SPCHOL_SOAB(2);
+                else if (nrr == 3) SPCHOL_SOAB(3);
+                else SPCHOL_SOAB(4);
+#undef SPCHOL_SOAB
+            }
+            prof.end(st);
         }
     }
     prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
