@@ -14,9 +14,18 @@ arrays and adds the error measures used to compare results, all in FP64:
   forward error  ||x - x_o||_inf / ||x_o||_inf
   factor error   max_j ||L[:, j] - L_o[:, j]||_inf / ||L_o[:, j]||_inf
 
+and the gradients of a loss through the solve (``solve_gradients``): for
+x = A^{-1} b and upstream gradient g_x, differentiating A x = b gives
+dx = A^{-1} (db - dA x), so g_b = A^{-T} g_x = lambda (A symmetric: one more
+solve with the same factor) and dL/dA_ij = -lambda_i x_j; a stored lower
+entry v_k stands for A_ij and A_ji, hence -(lambda_i x_j + lambda_j x_i)
+off the diagonal and -lambda_i x_i on it (summed over right-hand sides).
+
 Parity status: every function here is pinned by tests/test_oracle.py
 (dense LAPACK Cholesky, closed forms of the 1D Laplacian, exact results for
-diagonal matrices, brute-force boolean elimination for the pattern).
+diagonal matrices, brute-force boolean elimination for the pattern; the
+gradients by central finite differences and by the closed-form inverse of
+the 1D Laplacian).
 """
 from __future__ import annotations
 
@@ -227,3 +236,23 @@ def L_dense(sym: Symbolic, Lx) -> np.ndarray:
         for q in range(sym.Lcolptr[j], sym.Lcolptr[j + 1]):
             L[sym.Lrowind[q], j] = Lx[q]
     return L
+
+
+def solve_gradients(n, colptr, rowind, values, sym: Symbolic, Lx, x, gx):
+    """Gradients of a loss L(x), x = A^{-1} b, with respect to the stored
+    lower-triangle values of A and to b, given x [nrhs, n] and the upstream
+    gradient gx = dL/dx [nrhs, n].  Returns (g_values [nnz], g_b [nrhs, n]).
+    lambda = A^{-1} gx (A = A^T), g_b = lambda, and for a stored entry (i, j):
+    -(lambda_i x_j + lambda_j x_i) if i != j, -lambda_i x_i if i == j, summed
+    over the right-hand sides."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, n)
+    gx = np.asarray(gx, dtype=np.float64).reshape(-1, n)
+    lam = solve(sym, Lx, gx).reshape(-1, n)
+    colptr = np.asarray(colptr, np.int64)
+    rows = np.asarray(rowind, np.int64)
+    cols = np.repeat(np.arange(n, dtype=np.int64), np.diff(colptr))
+    g = np.zeros(rows.size)
+    for r in range(x.shape[0]):
+        t = lam[r, rows] * x[r, cols]
+        g -= np.where(rows == cols, t, t + lam[r, cols] * x[r, rows])
+    return g, lam

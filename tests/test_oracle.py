@@ -291,3 +291,85 @@ def test_golden_fixture_reproduces():
     assert np.array_equal(s.Lrowind, fx["Lrowind"])
     assert np.array_equal(Lx, fx["Lx"])
     assert np.array_equal(x.ravel(), fx["x"])
+
+
+# ---------------------------------------------------------------------------
+# gradients through the solve (loss 0.5 ||x - x*||^2)
+
+
+def _loss_and_grad(p, perm, vals, b, xstar):
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, perm)
+    Lx, info = oracle.factor(p.n, p.colptr, p.rowind, vals, sym)
+    assert info == 0
+    x = oracle.solve(sym, Lx, b)
+    loss = 0.5 * float(np.sum((x - xstar) ** 2))
+    gv, gb = oracle.solve_gradients(p.n, p.colptr, p.rowind, vals, sym, Lx, x, x - xstar)
+    return loss, gv, gb
+
+
+def test_gradients_match_central_differences():
+    """Pin: central differences of the loss, h = 1e-6 max(1, |v|), on 40
+    value entries (diagonal and off-diagonal) and on every entry of b."""
+    w = W.block_vector_workload((3, 3, 2), batch=1, nrhs=2, seed=71)
+    p = w.pattern
+    xs = w.extra["xstar"][0]
+    v0, b0 = w.values[0], w.b[0]
+    loss, gv, gb = _loss_and_grad(p, w.perm, v0, b0, xs)
+    rng = np.random.default_rng(3)
+    ks = rng.choice(p.nnz, size=40, replace=False)
+    for k in ks:
+        h = 1e-6 * max(1.0, abs(v0[k]))
+        vp, vm = v0.copy(), v0.copy()
+        vp[k] += h
+        vm[k] -= h
+        fd = (_loss_and_grad(p, w.perm, vp, b0, xs)[0] - _loss_and_grad(p, w.perm, vm, b0, xs)[0]) / (2 * h)
+        assert abs(fd - gv[k]) <= 1e-6 * max(1.0, abs(gv[k]))
+    for r in range(b0.shape[0]):
+        for i in range(0, p.n, 5):
+            bp, bm = b0.copy(), b0.copy()
+            bp[r, i] += 1e-6
+            bm[r, i] -= 1e-6
+            fd = (_loss_and_grad(p, w.perm, v0, bp, xs)[0] - _loss_and_grad(p, w.perm, v0, bm, xs)[0]) / 2e-6
+            assert abs(fd - gb[r, i]) <= 1e-6 * max(1.0, abs(gb[r, i]))
+
+
+def test_gradients_1d_laplacian_closed_form():
+    """Pin: for A = tridiag(-1, 2, -1) the inverse is known in closed form,
+    A^{-1}_ij = min(i, j) (n + 1 - max(i, j)) / (n + 1) (1-based), so
+    x = A^{-1} b, lambda = A^{-1} g and the value gradients -lambda_i x_j -
+    lambda_j x_i (off-diagonal), -lambda_i x_i (diagonal) follow without any
+    factorization."""
+    n = 9
+    e = np.stack([np.arange(n - 1), np.arange(1, n)], 1)
+    p = W.lower_csc_from_edges(n, e)
+    vals = np.where(p.rows == p.cols, 2.0, -1.0)
+    rng = np.random.default_rng(4)
+    b = rng.uniform(-1, 1, size=(1, n))
+    g = rng.uniform(-1, 1, size=(1, n))
+    i1 = np.arange(1, n + 1)
+    Ainv = np.minimum.outer(i1, i1) * (n + 1 - np.maximum.outer(i1, i1)) / (n + 1)
+    x = b @ Ainv
+    lam = g @ Ainv
+    sym = oracle.symbolic(n, p.colptr, p.rowind, None)
+    Lx, info = oracle.factor(n, p.colptr, p.rowind, vals, sym)
+    gv, gb = oracle.solve_gradients(n, p.colptr, p.rowind, vals, sym, Lx, x, g)
+    assert np.allclose(gb, lam, rtol=0, atol=1e-13)
+    ref = np.where(p.rows == p.cols, -lam[0, p.rows] * x[0, p.cols],
+                   -(lam[0, p.rows] * x[0, p.cols] + lam[0, p.cols] * x[0, p.rows]))
+    assert np.allclose(gv, ref, rtol=0, atol=1e-13)
+
+
+def test_block_vector_generator_is_spd_and_dominant():
+    """The block-vector systems are symmetric, strictly diagonally dominant
+    (hence SPD), with 3 x 3 blocks; the 40^3 size has nnz(A) = 2,068,800."""
+    w = W.block_vector_workload((3, 3, 3), batch=2, nrhs=1, seed=72)
+    p = w.pattern
+    A = np.zeros((p.n, p.n))
+    A[p.rows, p.cols] = w.values[1]
+    A[p.cols, p.rows] = w.values[1]
+    off = np.abs(A).sum(1) - np.abs(np.diag(A))
+    assert np.all(np.diag(A) - off >= 0.01 - 1e-12)
+    assert np.linalg.eigvalsh(A).min() > 0
+    assert p.nnz == 27 * 6 + 3 * 3 * 3 * 2 * 9  # 6 per diagonal block, 9 per edge
+    nv, e = W.grid_edges((40, 40, 40))
+    assert 6 * nv + 9 * len(e) == 2068800

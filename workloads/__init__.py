@@ -37,6 +37,7 @@ __all__ = [
     "config",
     "small_grid",
     "random_spd",
+    "block_vector_workload",
 ]
 
 
@@ -302,6 +303,9 @@ def config(idx: int, batch: Optional[int] = None) -> List[Workload] | Workload:
        mass, 64 value sets (weights re-jittered by U(0.9, 1.1)), 3 RHS each
     3: uneven batch: 2D 16^2, 32^2, 64^2, 128^2 and 3D 8^3, 12^3, 16^3, 24^3,
        32 value sets each (returns a list of 8 workloads)
+    4: block vector Laplacian, 3 x 3 rotated SPD blocks on a 40^3 grid
+       (n = 192000), 16 value sets, 1 RHS, targets x* ~ N(0, 1) in
+       extra["xstar"] for the loss 0.5 ||x - x*||^2
     """
     seed = 1000 + idx
     if idx == 0:
@@ -326,6 +330,8 @@ def config(idx: int, batch: Optional[int] = None) -> List[Workload] | Workload:
             out.append(_grid_workload(name, dims, "nd", nb, 1, seed,
                                       rng_vals=rv, rng_rhs=rr))
         return out
+    if idx == 4:
+        return block_vector_workload((40, 40, 40), batch or 16, 1, seed)
     raise ValueError("unknown configuration %r" % (idx,))
 
 
@@ -392,3 +398,93 @@ def group_arrays(ws: Sequence[Workload]) -> Tuple[np.ndarray, np.ndarray]:
     vals = np.concatenate([w.values for w in ws], axis=1)
     b = np.concatenate([w.b for w in ws], axis=2)
     return np.ascontiguousarray(vals), np.ascontiguousarray(b)
+
+
+def _rotations(rng: np.random.Generator, m: int) -> np.ndarray:
+    """m rotation matrices, uniform on SO(3): normalized Gaussian quaternions."""
+    q = rng.standard_normal((m, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((m, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - z * w)
+    R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w)
+    R[:, 2, 1] = 2 * (y * z + x * w)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def block_vector_workload(dims, batch: int = 1, nrhs: int = 1, seed: int = 1004) -> Workload:
+    """Block vector Laplacian: 3 unknowns per grid vertex, 7-point (3D) or
+    5-point (2D) stencil of 3 x 3 blocks.
+
+    For every edge (i, j) and value set: B_ij = R diag(U(0.5, 1.5)^3) R^T with
+    R uniform on SO(3); the off-diagonal block is A_ij = -B_ij; the diagonal
+    block's off-diagonal entries are sums over the neighbours of B's
+    off-diagonal entries, negated; every scalar diagonal entry is the sum of
+    the absolute off-diagonal entries of its row plus U(0.01, 0.1) (strict
+    diagonal dominance, hence SPD).  Unknown 3 v + c belongs to vertex v;
+    the permutation is the geometric nested dissection of the vertices with
+    each vertex's three unknowns kept together.  extra["xstar"] holds
+    targets N(0, 1) [batch, nrhs, n] for the loss 0.5 ||x - x*||^2."""
+    nv, e = grid_edges(dims)
+    n = 3 * nv
+    ei, ej = e[:, 0], e[:, 1]  # ei < ej
+    # pattern: lower triangle of every diagonal block and full off-diagonal blocks
+    r3, c3 = np.tril_indices(3)
+    drow = (3 * np.arange(nv)[:, None] + r3[None, :]).ravel()
+    dcol = (3 * np.arange(nv)[:, None] + c3[None, :]).ravel()
+    br, bc = np.meshgrid(np.arange(3), np.arange(3), indexing="ij")
+    orow = (3 * ej[:, None] + br.ravel()[None, :]).ravel()  # block row j > block column i
+    ocol = (3 * ei[:, None] + bc.ravel()[None, :]).ravel()
+    rows = np.concatenate([drow, orow]).astype(np.int64)
+    cols = np.concatenate([dcol, ocol]).astype(np.int64)
+    order = np.lexsort((rows, cols))
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(colptr, cols + 1, 1)
+    colptr = np.cumsum(colptr)
+    pat = SymPattern(n=n, colptr=colptr, rowind=rows[order].astype(np.int32),
+                     rows=rows[order], cols=cols[order])
+    inv = np.empty_like(order)
+    inv[order] = np.arange(order.size)  # position in storage of each generated entry
+    nd = drow.size
+    ss = _streams(seed, 4)
+    vss = ss[1].spawn(batch)
+    rss = ss[2].spawn(batch)
+    xss = ss[3].spawn(batch)
+    vals = np.zeros((batch, pat.nnz))
+    for s in range(batch):
+        g = np.random.Generator(np.random.PCG64(vss[s]))
+        R = _rotations(g, ei.size)
+        dd = g.uniform(0.5, 1.5, size=(ei.size, 3))
+        B = np.einsum("eab,eb,ecb->eac", R, dd, R)  # R diag(d) R^T per edge
+        D = np.zeros((nv, 3, 3))
+        np.add.at(D, ei, B)
+        np.add.at(D, ej, B)
+        # scalar row sums of |off-diagonal| entries (both triangles)
+        rs = np.zeros(n)
+        absB = np.abs(B)
+        np.add.at(rs, (3 * ei[:, None] + np.arange(3)).ravel(), absB.sum(2).ravel())
+        np.add.at(rs, (3 * ej[:, None] + np.arange(3)).ravel(), absB.sum(1).ravel())
+        Dm = -D  # diagonal blocks: negated sums of the neighbours' blocks
+        offd = np.abs(Dm) * (1 - np.eye(3))[None]
+        rs += offd.sum(2).ravel()
+        shift = g.uniform(0.01, 0.1, size=n)
+        diag = rs + shift
+        Dm[:, np.arange(3), np.arange(3)] = diag.reshape(nv, 3)
+        v = np.empty(pat.nnz)
+        v[inv[:nd]] = Dm[:, r3, c3].ravel()
+        v[inv[nd:]] = (-B[:, br.ravel(), bc.ravel()]).ravel()
+        vals[s] = v
+    b = np.stack([rhs(n, nrhs, np.random.Generator(np.random.PCG64(q))) for q in rss])
+    xstar = np.stack([np.random.Generator(np.random.PCG64(q)).standard_normal((nrhs, n))
+                      for q in xss])
+    vperm = grid_nd_perm(dims)
+    perm = (3 * vperm.astype(np.int64)[:, None] + np.arange(3)[None, :]).ravel().astype(np.int32)
+    name = "blockvec3_%s_nd" % "x".join(map(str, dims))
+    return Workload(name=name, pattern=pat, perm=perm, values=vals, b=b, seed=seed,
+                    extra={"dims": tuple(dims), "order": "nd", "xstar": xstar})
