@@ -23,6 +23,10 @@ Workloads (--workload):
   uneven8               uneven batch: 2D 16^2, 32^2, 64^2, 128^2 and 3D 8^3,
                         12^3, 16^3, 24^3, 32 value sets each (256 systems),
                         one group plan; FP32 + refinement versus FP64
+  blockvec40            3 x 3 block vector Laplacian on a 40^3 grid
+                        (n = 192000), 16 value sets, FP64: factor, solve and
+                        the gradient of 0.5 ||x - x*||^2 in the values and b
+                        (one more solve plus the value-gradient pass)
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 
@@ -59,6 +63,8 @@ def make_workload(name):
         return W.config(0), "grid2d_5pt_32x32_natural", "f64"
     if name == "uneven8":
         return W.config(3), "uneven_8_patterns_x32_grid2d_grid3d_nd", "mixed"
+    if name == "blockvec40":
+        return W.config(4), "blockvec3_40^3_nd_batch16_adjoint", "adjoint"
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -295,6 +301,45 @@ def run_form(S, plan, w, dtype, steps, warmup, profile):
     torch.cuda.empty_cache()
     return t1 - t0, stats, out, prof, iters
 
+def run_adjoint(S, plan, w, steps, warmup, profile):
+    """Time `steps` steps of factor + solve + adjoint (the gradient of
+    0.5 ||x - x*||^2 in the values and in b) over the batch."""
+    import torch
+    num = plan.numeric(w.batch, "f64")
+    vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
+    b0 = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+    xs = torch.from_numpy(np.ascontiguousarray(w.extra["xstar"])).cuda()
+    x = torch.empty_like(b0)
+    gx = torch.empty_like(b0)
+
+    def step():
+        num.factor(vals)
+        x.copy_(b0)
+        num.solve(x)
+        torch.sub(x, xs, out=gx)
+        return num.adjoint(x, gx)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    bad = num.info()
+    if np.any(bad):
+        raise SystemExit("factorization failed: info=%s" % bad[bad != 0][:8])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gv, gb = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {}
+    if profile:
+        num.profile(True)
+        step()
+        torch.cuda.synchronize()
+        num.profile(False)
+        prof = num.profile_read()
+    return t1 - t0, x.cpu().numpy(), gv.cpu().numpy(), gb.cpu().numpy(), prof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,16 +396,16 @@ def main():
         # one-time tuning of thresholds, amalgamation and solve layout on this
         # workload (like the analysis, outside the timed steps)
         import torch
-        t = time.perf_counter()
+        tt = time.perf_counter()
         tv = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
         tb = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
         best, table = S.autotune(p.colptr, p.rowind, w.perm, tv, tb,
                                  "f32" if form == "mixed" else "f64",
-                                 solves_per_factor=4.0 if form == "mixed" else 1.0)
+                                 solves_per_factor={"mixed": 4.0, "adjoint": 2.0}.get(form, 1.0))
         del tv, tb
         torch.cuda.empty_cache()
         opts = {k: best[k] for k in ("small_front", "relax_cols", "soa_min_batch")}
-        tuned = {"options": opts, "seconds": time.perf_counter() - t,
+        tuned = {"options": opts, "seconds": time.perf_counter() - tt,
                  "candidates": [{k: round(r[k], 4) if isinstance(r[k], float) else r[k]
                                  for k in ("small_front", "relax_cols", "soa_min_batch",
                                            "factor_ms", "solve_ms", "score")} for r in table]}
@@ -432,6 +477,22 @@ def main():
                      for r in range(w.nrhs))
         out["relres_check_host"] = rr
         pdtype = "f32"
+    elif form == "adjoint":
+        t, x, gv, gb, prof = run_adjoint(S, plan, w, args.steps, args.warmup, prof_on)
+        ms = t * 1e3 / args.steps
+        out.update({"value": w.batch / (t / args.steps), "ms_per_step": ms, "dtype": "f64",
+                    "unit": "factor+solve+gradient/s"})
+        # the gradient of value set 0 against the closed form at sampled entries
+        lam = gb[0, 0]
+        xs = x[0, 0]
+        ks = np.random.default_rng(0).choice(p.nnz, size=1000, replace=False)
+        ref = np.where(p.rows[ks] == p.cols[ks], -lam[p.rows[ks]] * xs[p.cols[ks]],
+                       -(lam[p.rows[ks]] * xs[p.cols[ks]] + lam[p.cols[ks]] * xs[p.rows[ks]]))
+        out["gradient_check_max_rel"] = float(np.max(np.abs(gv[0, ks] - ref) /
+                                                     np.maximum(np.abs(ref), 1e-300)))
+        out["relres"] = max(relres_host(p, w.values[s], x[s, r], w.b[s, r])
+                            for s in (0, w.batch - 1) for r in range(w.nrhs))
+        pdtype = "f64"
     else:
         t64, st64, x, prof, it64 = run_form(S, plan, w, "f64", args.steps, args.warmup, prof_on)
         ms = t64 * 1e3 / args.steps

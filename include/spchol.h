@@ -296,6 +296,26 @@ sc_status sc_numeric_profile_read(sc_numeric_t *num, int32_t cap,
                                   int32_t *count_out);
 
 /*
+ * Adjoint of the solve (gradients of a loss L(x) through x = A^{-1} b, the
+ * closed form of differentiating the solve; the paper differentiates its
+ * unrolled expression graph symbolically, Sec. 4.8): with the factor of
+ * the last sc_factor on this numeric object,
+ *     lambda = A^{-1} g_x                      -> gb_dev (dL/db)
+ *     dL/dv_k = -sum_r (lambda_i x_j + lambda_j x_i)   stored entry (i, j), i > j
+ *     dL/dv_k = -sum_r lambda_i x_i                    diagonal entry
+ *                                              -> gvalues_dev [batch][ldv]
+ * x_dev, gx_dev and gb_dev are [batch][nrhs][ldb] float64 (device), x the
+ * solution of the forward solve, gx the upstream gradient dL/dx; gb_dev may
+ * alias gx_dev (overwritten) but not x_dev.  The arithmetic is FP64; with an
+ * FP32 factor lambda carries the factor's accuracy.  One extra solve plus
+ * one pass over the stored entries; asynchronous on `stream`.  Errors:
+ * SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_adjoint(const sc_plan_t *plan, sc_numeric_t *num, const double *x_dev,
+                     const double *gx_dev, double *gvalues_dev, int64_t ldv, double *gb_dev,
+                     int32_t nrhs, int64_t ldb, void *stream);
+
+/*
  * One captured step for repeated use on fixed buffers (the paper's setting:
  * the same structure run many times, Sec. 3.3): the factorization of the
  * whole batch from values_dev (as sc_factor) followed by the refined solve

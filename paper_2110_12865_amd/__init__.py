@@ -41,7 +41,7 @@ EXPORTS = [
     "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
     "sc_numeric_get_columns", "sc_numeric_profile", "sc_numeric_profile_read",
     "sc_step_graph_create", "sc_step_graph_launch", "sc_step_graph_stats", "sc_step_graph_destroy",
-    "sc_autotune",
+    "sc_autotune", "sc_adjoint",
 ]
 
 
@@ -120,6 +120,7 @@ def _load():
         "sc_step_graph_destroy": ([P], None),
         "sc_autotune": ([I64, P, P, P, P, I64, I32, ctypes.c_int, P, I32, I64, ctypes.c_double, P,
                          P, I32, P, P], ctypes.c_int),
+        "sc_adjoint": ([P, P, P, P, P, I64, P, I32, I64, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -362,6 +363,23 @@ class Numeric:
         return rc, [{k: getattr(st[i], k) for k, _ in RefineStats._fields_}
                     for i in range(nsys)]
 
+    def adjoint(self, x, gx, stream=None):
+        """(dL/dvalues [batch, nnzA], dL/db [batch, nrhs, n]) for x = A^{-1} b
+        solved with the stored factor and the upstream gradient gx = dL/dx
+        (see sc_adjoint)."""
+        import torch
+        if x.shape != gx.shape or x.dim() != 3 or x.shape[0] != self.batch:
+            raise ValueError("x and gx must be [batch, nrhs, n]")
+        gx = gx.contiguous()
+        gv = torch.empty((self.batch, self.plan.info()["nnzA"]), dtype=torch.float64,
+                         device=x.device)
+        gb = torch.empty_like(gx)
+        _check(_lib.sc_adjoint(self.plan._h, self._h, _dev_ptr(x, "float64"),
+                               _dev_ptr(gx, "float64"), _dev_ptr(gv, "float64"),
+                               int(gv.shape[1]), _dev_ptr(gb, "float64"), int(x.shape[1]),
+                               int(x.shape[2]), _stream_handle(stream)), "sc_adjoint")
+        return gv, gb
+
     def step_graph(self, values, b, x, tol: float = 1e-10, iters: int = 3,
                    method: str = "classical") -> "StepGraph":
         """Capture factor(values) + refined solve b -> x with exactly `iters`
@@ -437,3 +455,42 @@ class StepGraph:
             raise SpcholError(rc, "sc_step_graph_stats")
         return rc, [{k: getattr(st[i], k) for k, _ in RefineStats._fields_}
                     for i in range(self.nsys)]
+
+
+def _autograd_function():
+    import torch
+
+    class SolveFn(torch.autograd.Function):
+        """x = A^{-1} b for a batch on a fixed pattern, differentiable in the
+        stored values of A and in b.  forward factors `values` into `num`
+        and solves; backward runs the adjoint with the same factor (one more
+        solve, sc_adjoint), so `num` must not be refactored in between."""
+
+        @staticmethod
+        def forward(ctx, values, b, num):
+            num.factor(values.detach())
+            x = b.detach().clone()
+            num.solve(x)
+            ctx.num = num
+            ctx.save_for_backward(x)
+            return x
+
+        @staticmethod
+        def backward(ctx, gx):
+            (x,) = ctx.saved_tensors
+            gv, gb = ctx.num.adjoint(x, gx)
+            return gv, gb, None
+
+    return SolveFn
+
+
+def solve_fn(num: "Numeric", values, b):
+    """Differentiable solve: x = A(values)^{-1} b with autograd support in
+    values [batch, nnzA] and b [batch, nrhs, n] (float64 device tensors)."""
+    global SolveFn
+    if SolveFn is None:
+        SolveFn = _autograd_function()
+    return SolveFn.apply(values, b, num)
+
+
+SolveFn = None

@@ -409,6 +409,13 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                 }
         }
 
+        // ---- row and column of every stored entry (caller's numbering),
+        // for the value gradients of the adjoint ---------------------------
+        P->val_row.assign(rowind, rowind + colptr[n]);
+        P->val_col.resize(size_t(colptr[n]));
+        for (int64_t c = 0; c < n; c++)
+            for (int64_t p = colptr[c]; p < colptr[c + 1]; p++) P->val_col[p] = int32_t(c);
+
         // ---- level schedule ----------------------------------------------
         int32_t small_front = opt.small_front > 0 ? opt.small_front : 64;
         P->opt.small_front = small_front;

@@ -43,7 +43,8 @@ void free_devplan(DevPlan *D) {
                     D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
                     D->slv_small, D->slv_pan, D->big_colent, D->big_chmap_off,
                     D->big_chmap, D->colblk, D->blk_col0, D->gptr, D->gidx,
-                    D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y};
+                    D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
+                    D->val_row, D->val_col};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete D;
@@ -92,6 +93,8 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->soa_chunks, P->soa_chunks);
     if (e == hipSuccess) e = upload(&D->grow_q, P->grow_q);
     if (e == hipSuccess) e = upload(&D->grow_y, P->grow_y);
+    if (e == hipSuccess) e = upload(&D->val_row, P->val_row);
+    if (e == hipSuccess) e = upload(&D->val_col, P->val_col);
     if (e == hipSuccess) e = upload(&D->blk_col0, P->blk_col0);
     if (e != hipSuccess) {
         free_devplan(D);
@@ -751,4 +754,31 @@ sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowi
     (void)hipFree(bw);
     if (ntable_out) *ntable_out = std::min(nt, table_cap);
     return result;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the solve: lambda = A^{-1} g_x with the stored factor, then the
+// value gradients on the pattern.
+
+sc_status sc_adjoint(const sc_plan_t *P, sc_numeric_t *N, const double *x_dev,
+                     const double *gx_dev, double *gvalues_dev, int64_t ldv, double *gb_dev,
+                     int32_t nrhs, int64_t ldb, void *stream) {
+    if (!P || !N || N->plan != P || !x_dev || !gx_dev || !gvalues_dev || !gb_dev || nrhs < 1 ||
+        ldb < P->n || ldv < P->nnzA || gb_dev == x_dev)
+        return SC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (dev != N->device) return SC_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = ensure_solve_ws(P, N, nrhs);
+    if (e != hipSuccess) return map_err(e);
+    if (gb_dev != gx_dev) {
+        e = hipMemcpyAsync(gb_dev, gx_dev, sizeof(double) * size_t(N->batch) * nrhs * ldb,
+                           hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return map_err(e);
+    }
+    e = spchol_solve_run(P, N, gb_dev, nrhs, ldb, st, nullptr);  // lambda, in place
+    if (e == hipSuccess)
+        e = spchol_adjoint_values(P, N->batch, x_dev, gb_dev, nrhs, ldb, gvalues_dev, ldv, st);
+    return map_err(e);
 }

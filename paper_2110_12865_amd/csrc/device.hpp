@@ -93,6 +93,8 @@ struct DevPlan {
     int64_t *soa_chunks = nullptr;    // chunk starts of the interleaved L copy
     int32_t *grow_q = nullptr;        // forward gather rows
     int32_t *grow_y = nullptr;
+    int32_t *val_row = nullptr;       // (row, column) of every stored entry
+    int32_t *val_col = nullptr;
     int32_t *gptr = nullptr;          // forward-solve gather map
     int32_t *gidx = nullptr;
     int32_t *colblk = nullptr;        // block of every column
@@ -198,6 +200,11 @@ hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals
                              double *stat_host, int32_t *nactive_out, bool sync,
                              hipStream_t st);
 hipError_t spchol_kernels_init();
+// Value gradients of the adjoint: g[b][k] = -sum_r (lam_i x_j + lam_j x_i)
+// for stored entry k = (i, j), i != j, and -sum_r lam_i x_i on the diagonal.
+hipError_t spchol_adjoint_values(const sc_plan *P, int batch, const double *x, const double *lam,
+                                 int32_t nrhs, int64_t ldb, double *g, int64_t ldv,
+                                 hipStream_t st);
 
 // Largest dynamic LDS allocation per workgroup on the current device.
 extern int g_max_lds;

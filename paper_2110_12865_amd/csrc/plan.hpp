@@ -105,6 +105,8 @@ struct sc_plan {
     std::vector<int64_t> csr_ptr;  // n+1
     std::vector<int32_t> csr_col;
     std::vector<int64_t> csr_vidx;
+    // row and column of every stored entry of the caller's lower triangle
+    std::vector<int32_t> val_row, val_col;
 
     // level schedule: supernodes of each level split into fronts done by
     // one workgroup ("small") and fronts done by the tiled kernels ("big")

@@ -501,6 +501,28 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     return e;
 }
 
+// Value gradients of the adjoint, one thread per (stored entry, matrix):
+// entry k = (i, j) of the caller's lower triangle stands for A_ij and A_ji,
+// so g = -sum_r (lam_i x_j + lam_j x_i) off the diagonal and -sum_r lam_i x_i
+// on it (right-hand sides ascending).
+__global__ __launch_bounds__(256) void k_adjoint_values(
+    const int32_t *__restrict__ vrow, const int32_t *__restrict__ vcol, int64_t nnz,
+    const double *__restrict__ X, const double *__restrict__ LAM, int nrhs, int64_t ldb,
+    double *__restrict__ G, int64_t ldv) {
+    const int b = blockIdx.y;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nnz) return;
+    const int64_t i = vrow[k], j = vcol[k];
+    double g = 0.0;
+    for (int r = 0; r < nrhs; r++) {
+        const double *x = X + (int64_t(b) * nrhs + r) * ldb;
+        const double *l = LAM + (int64_t(b) * nrhs + r) * ldb;
+        const double t = l[i] * x[j];
+        g -= i == j ? t : t + l[j] * x[i];
+    }
+    G[int64_t(b) * ldv + k] = g;
+}
+
 }  // namespace
 
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals, int64_t ldv,
@@ -512,4 +534,15 @@ hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals
                           sync, st);
     return refine_classical(P, N, vals, ldv, b, x, nrhs, ldb, tol, maxit, stat_host,
                             nactive_out, sync, st);
+}
+
+hipError_t spchol_adjoint_values(const sc_plan *P, int batch, const double *x, const double *lam,
+                                 int32_t nrhs, int64_t ldb, double *g, int64_t ldv,
+                                 hipStream_t st) {
+    const int64_t nnz = P->nnzA;
+    if (nnz == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adjoint_values, dim3(unsigned((nnz + 255) / 256), unsigned(batch)),
+                       dim3(256), 0, st, P->dev->val_row, P->dev->val_col, nnz, x, lam, nrhs,
+                       ldb, g, ldv);
+    return hipGetLastError();
 }
