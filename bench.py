@@ -410,6 +410,7 @@ def main():
                                  for k in ("small_front", "relax_cols", "soa_min_batch",
                                            "factor_ms", "solve_ms", "score")} for r in table]}
         log("autotune %.1f s: %s" % (tuned["seconds"], opts))
+    t = time.perf_counter()
     if members is not None:
         plan = S.analyze_group([(m.pattern.colptr, m.pattern.rowind, m.perm) for m in members],
                                **opts)
