@@ -198,7 +198,7 @@ def kernel_table(prof, steps):
 # time (kinds that bracket more than one kernel family are not candidates
 # for the roofline line)
 HIP_KERNEL = {
-    "front_small": "k_front_reg", "assemble": "k_assemble_wave", "potrf": "k_potrf",
+    "front_small": "k_front_reg", "assemble": "k_assemble_cols", "potrf": "k_potrf",
     "trsm": "k_trsm", "syrk_mfma": "k_syrk", "diag_inverse": "k_dinv",
     "solve_fwd": "k_fwd_soa_diag|k_fwd_seg", "solve_bwd": "k_bwd_soa_diag|k_bwd_seg",
     "solve_fwd_rows": "k_fwd_soa_rows", "solve_bwd_rows": "k_bwd_soa_rows",

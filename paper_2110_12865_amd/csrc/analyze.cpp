@@ -440,7 +440,6 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                 P->lvl_small_maxc[l] = std::max(P->lvl_small_maxc[l], P->sn[s].c);
             }
             for (int32_t s : byb[l]) {
-                P->big_colstart.push_back(P->lvl_bigcols[l]);
                 P->lvl_big.push_back(s);
                 P->lvl_big_maxc[l] = std::max(P->lvl_big_maxc[l], P->sn[s].c);
                 P->lvl_big_maxw[l] = std::max(P->lvl_big_maxw[l], P->sn[s].w);
@@ -455,25 +454,42 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             P->max_lvl_big = std::max(P->max_lvl_big, P->lvl_big_ptr[l + 1] - P->lvl_big_ptr[l]);
             P->lvl_ptr[l + 1] = int32_t(P->lvl_sn.size());
         }
-        // assembly tables of the large fronts
+        // assembly descriptors of the large fronts
         P->lvl_colent_off.assign(nlev, 0);
-        P->big_chmap_off.assign(P->lvl_big.size(), 0);
         for (int32_t l = 0; l < nlev; l++) {
-            P->lvl_colent_off[l] = int64_t(P->big_colent.size());
+            P->lvl_colent_off[l] = int64_t(P->asm_col.size());
             for (int32_t e = P->lvl_big_ptr[l]; e < P->lvl_big_ptr[l + 1]; e++) {
                 const SnDesc &d = P->sn[P->lvl_big[e]];
-                for (int32_t t = 0; t < d.c; t++) P->big_colent.push_back(e - P->lvl_big_ptr[l]);
                 const int32_t nch = d.chend - d.chbeg;
-                P->big_chmap_off[e] = int64_t(P->big_chmap.size());
-                const size_t base = P->big_chmap.size();
-                P->big_chmap.resize(base + size_t(d.c) * nch, -1);
+                std::vector<std::vector<AsmPiece>> per(d.c);  // per target column
                 for (int32_t q = 0; q < nch; q++) {
                     const SnDesc &cd = P->sn[P->chlist[d.chbeg + q]];
                     for (int32_t jc = 0; jc < cd.m; jc++) {
                         const int32_t tj = P->relmap[cd.relptr + jc];
-                        P->big_chmap[base + size_t(tj) * nch + q] = jc;
+                        for (int32_t i0 = jc; i0 < cd.m; i0 += kAsmPiece)
+                            per[tj].push_back(AsmPiece{cd.uoff + int64_t(jc) * cd.m + i0,
+                                                       cd.relptr + i0,
+                                                       std::min(kAsmPiece, cd.m - i0), 0});
                     }
                 }
+                for (int32_t tj = 0; tj < d.c; tj++) {
+                    AsmCol a{};
+                    a.c = d.c;
+                    a.tj = tj;
+                    a.base = tj * d.c;
+                    a.isU = tj >= d.w;
+                    a.dst = tj < d.w ? d.loff + int64_t(tj) * d.c
+                                     : d.uoff + int64_t(tj - d.w) * d.m - d.w;
+                    if (tj < d.w) {
+                        a.a0 = P->acolptr[d.first + tj];
+                        a.na = int32_t(P->acolptr[d.first + tj + 1] - a.a0);
+                    }
+                    a.ch0 = int32_t(P->asm_pc.size());
+                    a.nch = int32_t(per[tj].size());
+                    P->asm_pc.insert(P->asm_pc.end(), per[tj].begin(), per[tj].end());
+                    P->asm_col.push_back(a);
+                }
+                if (int64_t(P->asm_pc.size()) >= INT32_MAX) throw std::bad_alloc();
             }
         }
 

@@ -40,9 +40,8 @@ void free_devplan(DevPlan *D) {
     if (!D) return;
     void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
                     D->avidx, D->perm, D->pinv, D->lvl_small, D->lvl_big, D->lvl_sn,
-                    D->big_colstart, D->csr_ptr, D->csr_col, D->csr_vidx,
-                    D->slv_small, D->slv_pan, D->big_colent, D->big_chmap_off,
-                    D->big_chmap, D->colblk, D->blk_col0, D->gptr, D->gidx,
+                    D->asm_col, D->csr_ptr, D->csr_col, D->csr_vidx,
+                    D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr, D->gidx,
                     D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
                     D->val_row, D->val_col};
     for (void *p : ptrs)
@@ -76,10 +75,8 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->lvl_small, P->lvl_small);
     if (e == hipSuccess) e = upload(&D->lvl_big, P->lvl_big);
     if (e == hipSuccess) e = upload(&D->lvl_sn, P->lvl_sn);
-    if (e == hipSuccess) e = upload(&D->big_colstart, P->big_colstart);
-    if (e == hipSuccess) e = upload(&D->big_colent, P->big_colent);
-    if (e == hipSuccess) e = upload(&D->big_chmap_off, P->big_chmap_off);
-    if (e == hipSuccess) e = upload(&D->big_chmap, P->big_chmap);
+    if (e == hipSuccess) e = upload(&D->asm_col, P->asm_col);
+    if (e == hipSuccess) e = upload(&D->asm_pc, P->asm_pc);
     if (e == hipSuccess) e = upload(&D->slv_small, P->slv_small);
     if (e == hipSuccess) e = upload(&D->slv_pan, P->slv_pan);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);

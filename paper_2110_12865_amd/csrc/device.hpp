@@ -79,10 +79,8 @@ struct DevPlan {
     int32_t *lvl_small = nullptr;
     int32_t *lvl_big = nullptr;
     int32_t *lvl_sn = nullptr;
-    int64_t *big_colstart = nullptr;  // per big entry: first column index in its level
-    int32_t *big_colent = nullptr;    // per level column: entry in the level's big list
-    int64_t *big_chmap_off = nullptr; // per big entry: offset into big_chmap
-    int32_t *big_chmap = nullptr;     // (front, column, child) -> child column or -1
+    AsmCol *asm_col = nullptr;        // assembly of the large fronts
+    AsmPiece *asm_pc = nullptr;
     int32_t *slv_small = nullptr;     // solve schedule lists
     int32_t *slv_pan = nullptr;
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x

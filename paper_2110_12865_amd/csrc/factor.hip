@@ -288,61 +288,54 @@ __global__ __launch_bounds__(256) void k_front_reg(
         if (k < m && lane >= w + k && lane < c) Us[int64_t(k) * m + lane - w] = f[k];
 }
 
-// Large fronts: assembly with one wave per target column, `per` columns per
-// workgroup (c_max scalars of LDS per wave).
+// Large fronts: assembly with one wave per (target column, matrix), `per`
+// columns per workgroup (c_max scalars of LDS per wave).  The column is
+// built in LDS from zeros, A's entries and then the children's pieces in
+// their order (a front row receives at most one value per child, so each
+// entry sums over the children in order), and written to L or U.  Pieces
+// go four at a time, all their loads issued before the adds.
 template <typename T>
-__global__ __launch_bounds__(256) void k_assemble_wave(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int64_t *__restrict__ colstart, const int32_t *__restrict__ colent,
-    const int64_t *__restrict__ chmap_off, const int32_t *__restrict__ chmap,
-    int64_t ncols, int per, int cmax,
-    const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
-    const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
+__global__ __launch_bounds__(256) void k_assemble_cols(
+    const AsmCol *__restrict__ cols, const AsmPiece *__restrict__ pcs, int64_t ncols, int per,
+    int cmax, const int32_t *__restrict__ relmap, const int32_t *__restrict__ aoff,
     const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
     T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
     if (wv >= per) return;
     const int64_t g = int64_t(blockIdx.x) * per + wv;
     if (g >= ncols) return;
     T *col = reinterpret_cast<T *>(smem_raw) + size_t(wv) * cmax;
-    const int ent = colent[g];
-    const int s = list[ent];
-    const int tj = int(g - colstart[ent]);
-    const int b = blockIdx.y;
-    const SnDesc d = sn[s];
-    const int c = d.c, w = d.w, m = d.m;
-    L += int64_t(b) * Lsize;
-    U += int64_t(b) * Usize;
-    vals += int64_t(b) * ldv;
-    for (int i = tj + lane; i < c; i += 64) col[i] = T(0);
+    const AsmCol a = cols[g];
+    const int64_t b = blockIdx.y;
+    const T *Ub = U + b * Usize;
+    vals += b * ldv;
+    for (int i = a.tj + lane; i < a.c; i += 64) col[i] = T(0);
     wave_fence_sync();
-    if (tj < w) {
-        const int j = d.first + tj;
-        const int64_t base = int64_t(tj) * c;
-        for (int64_t q = acolptr[j] + lane; q < acolptr[j + 1]; q += 64)
-            col[aoff[q] - base] = T(vals[avidx[q]]);
-    }
-    const int nch = d.chend - d.chbeg;
-    const int32_t *cm = chmap + chmap_off[ent] + int64_t(tj) * nch;
-    for (int q = 0; q < nch; q++) {
-        const int jc = cm[q];  // the child's column that lands in column tj
-        if (jc < 0) continue;
-        const SnDesc cd = sn[chlist[d.chbeg + q]];
-        const int32_t *rm = relmap + cd.relptr;
-        const int mc = cd.m;
-        wave_fence_sync();
-        const T *uc = U + cd.uoff + int64_t(jc) * mc;
-        for (int i = jc + lane; i < mc; i += 64) col[rm[i]] += uc[i];
+    for (int q = lane; q < a.na; q += 64) col[aoff[a.a0 + q] - a.base] = T(vals[avidx[a.a0 + q]]);
+    constexpr int kU = 4;
+    for (int k0 = 0; k0 < a.nch; k0 += kU) {
+        int r[kU];
+        T v[kU];
+        bool ok[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            const AsmPiece p = pcs[a.ch0 + min(k0 + u, a.nch - 1)];
+            ok[u] = k0 + u < a.nch && lane < p.cnt;
+            const int64_t o = ok[u] ? lane : 0;
+            r[u] = relmap[p.rmp + o];
+            v[u] = Ub[p.src + o];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+            wave_fence_sync();
+            if (ok[u]) col[r[u]] += v[u];
+        }
     }
     wave_fence_sync();
-    if (tj < w) {
-        T *dst = L + d.loff + int64_t(tj) * c;
-        for (int i = tj + lane; i < c; i += 64) dst[i] = col[i];
-    } else {
-        T *dst = U + d.uoff + int64_t(tj - w) * m - w;
-        for (int i = tj + lane; i < c; i += 64) dst[i] = col[i];
-    }
+    T *dst = (a.isU ? U + b * Usize : L + b * Lsize) + a.dst;
+    for (int i = a.tj + lane; i < a.c; i += 64) dst[i] = col[i];
 }
 
 // Value of lane `src` (wave-uniform) broadcast to the whole wave.
@@ -674,7 +667,7 @@ void set_lds_limits(int big) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_front_wave<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_wave<T>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_cols<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_potrf<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
@@ -827,13 +820,11 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         case FLaunch::Assemble: {
             const size_t per_lds = size_t(f.lds) * sizeof(T);
             const int per = int(std::max<size_t>(1, std::min<size_t>(4, g_max_lds / per_lds)));
-            hipLaunchKernelGGL(k_assemble_wave<T>,
+            hipLaunchKernelGGL(k_assemble_cols<T>,
                                dim3(unsigned((f.gridx + per - 1) / per), B), dim3(64 * per),
-                               per_lds * per, st, D->sn, D->lvl_big + f.list0,
-                               D->big_colstart + f.list0, D->big_colent + P->lvl_colent_off[f.level],
-                               D->big_chmap_off + f.list0, D->big_chmap, int64_t(f.gridx), per,
-                               f.lds, D->relmap, D->chlist, D->acolptr, D->aoff, D->avidx,
-                               vals, ldv, L, P->Lsize, U, P->Usize);
+                               per_lds * per, st, D->asm_col + P->lvl_colent_off[f.level],
+                               D->asm_pc, int64_t(f.gridx), per, f.lds, D->relmap, D->aoff,
+                               D->avidx, vals, ldv, L, P->Lsize, U, P->Usize);
             break;
         }
         case FLaunch::Potrf:

@@ -30,6 +30,35 @@ struct SnDesc {
 };
 static_assert(sizeof(SnDesc) == 88, "SnDesc layout");
 
+// Assembly of one column of a large front: destination of rows tj..c-1
+// (front entry (i, tj) at dst + i in L or, for update columns, in U), the
+// column's entries of A (for L columns) and the pieces of the children's
+// update columns that land in it.
+struct AsmCol {
+    int64_t dst;   // L: loff + tj*c; U: uoff + (tj-w)*m - w
+    int64_t a0;    // first entry of A's column first+tj (permuted), na entries
+    int32_t na;
+    int32_t c;     // rows of the front
+    int32_t tj;    // column inside the front
+    int32_t base;  // tj*c: aoff of row i is base + i
+    int32_t ch0;   // pieces [ch0, ch0 + nch)
+    int32_t nch;
+    int32_t isU;   // 1: update column (destination in U)
+    int32_t pad;
+};
+static_assert(sizeof(AsmCol) == 48, "AsmCol layout");
+// Up to 64 consecutive rows of one child's update column: U[src + k] is
+// added to front row relmap[rmp + k], k < cnt.  A column's pieces follow the
+// children's order, rows ascending inside a child.
+constexpr int kAsmPiece = 64;
+struct AsmPiece {
+    int64_t src;
+    int64_t rmp;
+    int32_t cnt;
+    int32_t pad;
+};
+static_assert(sizeof(AsmPiece) == 24, "AsmPiece layout");
+
 // A supernode is solved by 64-column panels across many workgroups when it
 // is wide or tall; otherwise one workgroup solves it out of LDS.
 constexpr int kSolvePanel = 64;
@@ -140,15 +169,12 @@ struct sc_plan {
     int64_t part_size = 0;   // partial sums per right-hand side
     int32_t npan = 0;        // supernodes solved by panels
     std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts
-    std::vector<int64_t> big_colstart;    // per big entry: first column in its level
     int32_t max_lvl_big = 0;              // most large fronts in one level
-    // assembly tables of large fronts: for every target column of a level,
-    // its entry in the level's list; for every (front, target column,
-    // child), the child's column that lands there (-1 if none)
-    std::vector<int32_t> big_colent;      // sum over levels of the level's columns
+    // assembly of the large fronts: one descriptor per target column (level
+    // l owns [lvl_colent_off[l], + lvl_bigcols[l])) and its pieces
+    std::vector<AsmCol> asm_col;
+    std::vector<AsmPiece> asm_pc;
     std::vector<int64_t> lvl_colent_off;  // nlevels
-    std::vector<int64_t> big_chmap_off;   // per big entry
-    std::vector<int32_t> big_chmap;
 
     mutable DevPlan *dev = nullptr;
     mutable int dev_id = -1;
