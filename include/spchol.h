@@ -70,7 +70,15 @@ typedef struct {
                              matrices solve in the batch-interleaved layout
                              (one matrix per lane; L is copied once per
                              factorization); 0 = library default (64, a
-                             whole group of lanes), a negative value never                         */
+                             whole group of lanes), a negative value never */
+    int32_t soa_seg_max;   /* in the batch-interleaved layout, a level whose
+                             supernodes outside the panel kernels, times the
+                             groups of 64 matrices, number at most this is
+                             solved by the kernels that put one lane on each
+                             row of a supernode instead (the top levels,
+                             where one lane per matrix leaves the chip
+                             idle); 0 = library default (384), a negative
+                             value never */
 } sc_options;
 
 /* Sizes of a plan (per matrix of a batch). */
@@ -206,8 +214,11 @@ sc_status sc_factor_info(const sc_numeric_t *num, int32_t *info_host,
 /*
  * Solve A x = b for every matrix of the batch: b_dev is float64
  * [batch][nrhs][ldb] (ldb >= n, original numbering), overwritten by x.
- * The triangular solves read the stored factor (FP64 or FP32) and compute
- * in FP64.  Asynchronous.  Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
+ * The triangular solves run in the precision of the stored factor: FP64
+ * factors in FP64; FP32 factors with FP32 vectors and arithmetic (b is
+ * rounded to FP32 on entry and x widened on exit), the precision in which
+ * mixed-precision iterative refinement forms its corrections.
+ * Asynchronous.  Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
  */
 sc_status sc_solve(const sc_plan_t *plan, sc_numeric_t *num, double *b_dev,
                    int32_t nrhs, int64_t ldb, void *stream);

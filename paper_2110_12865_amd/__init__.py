@@ -54,7 +54,7 @@ class SpcholError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("relax", ctypes.c_int32), ("relax_cols", ctypes.c_int32),
                 ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32),
-                ("soa_min_batch", ctypes.c_int32)]
+                ("soa_min_batch", ctypes.c_int32), ("soa_seg_max", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):

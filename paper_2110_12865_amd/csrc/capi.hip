@@ -155,7 +155,7 @@ hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
     if (W.r && W.nsys >= nsys && W.ldb >= ldb) return hipSuccess;
     free_refine_ws(W);
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&W.r), 5 * sizeof(double) * nsys * ldb);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.sc), 3 * sizeof(double) * nseg);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.sc), 4 * sizeof(double) * nseg);
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.part), 32 * 3 * sizeof(double) * nseg);
     if (e == hipSuccess)
@@ -201,6 +201,7 @@ sc_status sc_options_default(sc_options *opt) {
     opt->relax_zeros = 0.05;
     opt->small_front = 64;
     opt->soa_min_batch = kSoaMinBatch;
+    opt->soa_seg_max = kSoaSegMax;
     return SC_OK;
 }
 

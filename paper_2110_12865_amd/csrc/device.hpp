@@ -38,15 +38,16 @@ struct SPanel {  // one 64-column panel step of a level's panel-solved supernode
     int64_t bwd_chunks = 0;  // kSolveChunk-row chunks below the panel (max)
     double flops = 0.0;      // per right-hand side
     double words = 0.0;      // factor scalars read per right-hand side
-    double vbytes = 0.0;     // vector bytes per right-hand side
-    double dbytes = 0.0;     // inverse-block bytes per matrix
+    double vwords = 0.0;     // vector entries per right-hand side
+    double dwords = 0.0;     // inverse-block entries per matrix
 };
 
 struct SClass {  // supernodes of one row class in one level
     int32_t list0 = 0, n = 0;  // entries of slv_small
     double flops = 0.0;        // per right-hand side
     double words = 0.0;        // factor scalars read
-    double vbytes = 0.0;       // vector and index bytes per right-hand side
+    double vwords = 0.0;       // vector entries per right-hand side
+    double ibytes = 0.0;       // index bytes per right-hand side
 };
 
 struct SLaunch {  // one level of a triangular solve
@@ -57,12 +58,14 @@ struct SLaunch {  // one level of a triangular solve
     int32_t all0 = 0, nall = 0;
     int32_t it0 = 0, nit = 0;
     int32_t grow0 = 0, ngrow = 0;     // gather rows of those supernodes
-    double v_gather = 0.0;            // their bytes per right-hand side
-    double f_diag = 0.0, w_diag = 0.0, v_diag = 0.0;  // diagonal blocks
-    double f_rows = 0.0, w_rows = 0.0, v_rows = 0.0;  // rows below them
+    // flops, factor scalars, vector entries and index bytes (per right-hand
+    // side) of the gather, the diagonal blocks and the rows below them
+    double vw_gather = 0.0, ib_gather = 0.0;
+    double f_diag = 0.0, w_diag = 0.0, vw_diag = 0.0, ib_diag = 0.0;
+    double f_rows = 0.0, w_rows = 0.0, vw_rows = 0.0, ib_rows = 0.0;
     int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
     int32_t maxc_pan = 0;
-    double v_pan = 0.0;
+    double vw_pan = 0.0, ib_pan = 0.0;
     std::vector<SPanel> panels;
 };
 
@@ -147,7 +150,7 @@ struct RefineWs {
     int64_t ldb = 0;
     double *r = nullptr;        // 5 vectors of nsys * ldb (residual, correction, CG)
     // per system (matrix, right-hand side, block): nseg = nsys * nblk
-    double *sc = nullptr;       // scalars, 3 * nseg
+    double *sc = nullptr;       // scalars, 4 * nseg
     double *part = nullptr;     // reduction partials, nseg * 32 * 3
     double *anorm = nullptr;    // batch * nblk
     double *vc = nullptr;       // values of A in row order, batch * nnz(both triangles)

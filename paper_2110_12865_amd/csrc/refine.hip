@@ -125,7 +125,8 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 // nq = 3: partial sums of r.r, b.b, x.x (A = r, B = b, C = x);
-// nq = 1: partial sum of A.B.  part[(seg * kRB + slice) * 3 + q].
+// nq = 2: partial sums of A.B and B.C; nq = 1: partial sum of A.B.
+// part[(seg * kRB + slice) * 3 + q].
 __global__ __launch_bounds__(256) void k_sums(
     const double *__restrict__ A, const double *__restrict__ Bv, const double *__restrict__ C,
     int nq, int64_t ldb, const int64_t *__restrict__ col0, int nblk, int nrhs,
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_sums(
     const int64_t i0 = r0 + slice * len, i1 = min(r0 + nr, i0 + len);
     const double *a = A + int64_t(br) * ldb;
     const double *bb = Bv + int64_t(br) * ldb;
-    const double *cc = nq == 3 ? C + int64_t(br) * ldb : nullptr;
+    const double *cc = nq >= 2 ? C + int64_t(br) * ldb : nullptr;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
@@ -151,6 +152,9 @@ __global__ __launch_bounds__(256) void k_sums(
             s0 += ai * ai;
             s1 += bi * bi;
             s2 += ci * ci;
+        } else if (nq == 2) {
+            s0 += ai * bi;
+            s1 += bi * cc[i];
         } else {
             s0 += ai * bi;
         }
@@ -161,19 +165,28 @@ __global__ __launch_bounds__(256) void k_sums(
         const double t1 = block_sum(s1, red);
         const double t2 = block_sum(s2, red);
         if (threadIdx.x == 0) { o[0] = t0; o[1] = t1; o[2] = t2; }
+    } else if (nq == 2) {
+        const double t1 = block_sum(s1, red);
+        if (threadIdx.x == 0) { o[0] = t0; o[1] = t1; }
     } else if (threadIdx.x == 0) {
         o[0] = t0;
     }
 }
 
-// out[seg] = sum of the kRB partial dot products of system seg
+// out[seg] = sum of the kRB partial dot products of system seg (component
+// 0), out2[seg] the same for component 1 when out2 is given
 __global__ void k_sums_final(const double *__restrict__ part, int nseg, int per_matrix,
-                             const int32_t *__restrict__ active, double *__restrict__ out) {
+                             const int32_t *__restrict__ active, double *__restrict__ out,
+                             double *__restrict__ out2) {
     const int sg = blockIdx.x * blockDim.x + threadIdx.x;
     if (sg >= nseg || !active[sg / per_matrix]) return;
-    double t = 0.0;
-    for (int q = 0; q < kRB; q++) t += part[(int64_t(sg) * kRB + q) * 3];
+    double t = 0.0, t2 = 0.0;
+    for (int q = 0; q < kRB; q++) {
+        t += part[(int64_t(sg) * kRB + q) * 3];
+        if (out2) t2 += part[(int64_t(sg) * kRB + q) * 3 + 1];
+    }
     out[sg] = t;
+    if (out2) out2[sg] = t2;
 }
 
 // Stop test for every system from the partial sums of r.r, b.b and x.x.
@@ -273,18 +286,21 @@ __global__ void k_cg_xr(double *__restrict__ X, double *__restrict__ R,
     R[o] -= alpha * Q[o];
 }
 
-// p = z + (rz_new / rz_old) p
+// p = z + beta p with beta = z_new.(r_new - r_old) / (z_old.r_old), the form
+// that tolerates a preconditioner applied in lower precision (Golub and Ye,
+// inexact preconditioned CG).  With r_new - r_old = -alpha q and alpha =
+// z_old.r_old / p.q this is beta = -z_new.q / p.q.
 __global__ void k_cg_p(double *__restrict__ Pv, const double *__restrict__ Z, int64_t ldb,
                        int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
                        const int32_t *__restrict__ active, const int32_t *__restrict__ conv,
-                       const double *__restrict__ rz_old, const double *__restrict__ rz_new) {
+                       const double *__restrict__ zq, const double *__restrict__ pq) {
     const int br = blockIdx.y;
     if (!active[br / nrhs]) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int sg = seg_of(br, nblk, colblk, i);
     if (conv[sg]) return;
-    const double beta = rz_old[sg] > 0.0 ? rz_new[sg] / rz_old[sg] : 0.0;
+    const double beta = pq[sg] > 0.0 ? -zq[sg] / pq[sg] : 0.0;
     const int64_t o = int64_t(br) * ldb + i;
     Pv[o] = Z[o] + beta * Pv[o];
 }
@@ -408,7 +424,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     const dim3 sgrid(unsigned((nseg + 255) / 256));
     const size_t vsz = size_t(nsys) * ldb;
     double *r = W.r, *z = W.r + vsz, *pv = W.r + 2 * vsz, *q = W.r + 3 * vsz, *rt = W.r + 4 * vsz;
-    double *rz0 = W.sc, *rz1 = W.sc + nseg, *pq = W.sc + 2 * nseg;
+    double *rz0 = W.sc, *rz1 = W.sc + nseg, *pq = W.sc + 2 * nseg, *zq = W.sc + 3 * nseg;
     hipError_t e;
     hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, b, x, ldb, n, nrhs, nullptr);
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
@@ -449,7 +465,17 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                            D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
         prof.end(st);
         hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
-                           out);
+                           out, nullptr);
+    };
+    // <a, c> into out and <c, d> into out2, in one pass over c
+    auto dots2 = [&](const double *a, const double *c, const double *d, double *out,
+                     double *out2) {
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, d, 2, ldb,
+                           D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
+        prof.end(st);
+        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
+                           out, out2);
     };
     e = check(0);
     if (e != hipSuccess) return e;
@@ -485,10 +511,10 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
             prof.end(st);
             e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
             if (e != hipSuccess) return e;
-            dots(r, z, rzn);
+            dots2(r, z, q, rzn, zq);
             prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
             hipLaunchKernelGGL(k_cg_p, vgrid, dim3(256), 0, st, pv, z, ldb, n, nrhs, nblk,
-                               colblk, W.active, W.conv, rz, rzn);
+                               colblk, W.active, W.conv, zq, pq);
             prof.end(st);
             std::swap(rz, rzn);
         }

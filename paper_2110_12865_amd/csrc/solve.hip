@@ -43,7 +43,7 @@ __device__ __forceinline__ V ldz(const V *p, int64_t idx, bool ok) {
 template <typename T>
 __global__ __launch_bounds__(64) void k_dinv(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const T *__restrict__ L, int64_t Lsize, double *__restrict__ Dinv, int64_t dsize) {
+    const T *__restrict__ L, int64_t Lsize, T *__restrict__ Dinv, int64_t dsize) {
     __shared__ double Lp[kP * (kP + 1)];  // [i][t] row-major
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
@@ -68,14 +68,14 @@ __global__ __launch_bounds__(64) void k_dinv(
         for (int t = 0; t < i; t++) sum -= Lp[i * (kP + 1) + t] * x[t];
         x[i] = sum / Lp[i * (kP + 1) + i];
     }
-    double *D = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+    T *D = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
     __syncthreads();  // every read of Lp above precedes the transpose below
 #pragma unroll
     for (int i = 0; i < kP; i++)  // column-major: D[col * 64 + i] = X[i][col], col = lane
         Lp[lane * (kP + 1) + i] = (lane < kb && i < kb) ? x[i] : 0.0;
     __syncthreads();
 #pragma unroll 8
-    for (int col = 0; col < kP; col++) D[col * kP + lane] = Lp[col * (kP + 1) + lane];
+    for (int col = 0; col < kP; col++) D[col * kP + lane] = T(Lp[col * (kP + 1) + lane]);
 }
 
 // Position of entry (matrix b, row, right-hand side r) in a solve vector
@@ -110,32 +110,41 @@ __device__ inline double seg_bcast(double v, int src) {
         return __shfl(v, src, G);
     }
 }
+template <int G>
+__device__ inline float seg_bcast(float v, int src) {
+    if constexpr (G == 64)
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+    else
+        return __shfl(v, src, G);
+}
 
 // Ys[(b n + k) nrhs + r] = B[(b nrhs + r) ldb + perm[k]]: the permuted
 // right-hand sides, interleaved so that one row of every right-hand side is
 // one contiguous record.
+template <typename T>
 __global__ __launch_bounds__(256) void k_perm_in(
     const int32_t *__restrict__ perm, const double *__restrict__ B, int64_t ldb,
-    double *__restrict__ Ys, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    T *__restrict__ Ys, int64_t n, int nrhs, const int32_t *__restrict__ active) {
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t src = perm[k];
-    double *dst = Ys + (int64_t(b) * n + k) * nrhs;
-    for (int r = 0; r < nrhs; r++) dst[r] = B[(int64_t(b) * nrhs + r) * ldb + src];
+    T *dst = Ys + (int64_t(b) * n + k) * nrhs;
+    for (int r = 0; r < nrhs; r++) dst[r] = T(B[(int64_t(b) * nrhs + r) * ldb + src]);
 }
 
 // X[(b nrhs + r) ldb + i] = Ys[(b n + pinv[i]) nrhs + r]: writes in the
 // caller's order (coalesced), reads gathered.
+template <typename T>
 __global__ __launch_bounds__(256) void k_perm_out(
-    const int32_t *__restrict__ pinv, const double *__restrict__ Ys, double *__restrict__ X,
+    const int32_t *__restrict__ pinv, const T *__restrict__ Ys, double *__restrict__ X,
     int64_t ldb, int64_t n, int nrhs, const int32_t *__restrict__ active) {
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *src = Ys + (int64_t(b) * n + pinv[i]) * nrhs;
+    const T *src = Ys + (int64_t(b) * n + pinv[i]) * nrhs;
     for (int r = 0; r < nrhs; r++) X[(int64_t(b) * nrhs + r) * ldb + i] = src[r];
 }
 
@@ -145,11 +154,11 @@ __global__ __launch_bounds__(256) void k_perm_out(
 // order), right-hand sides r0 .. r0 + NR - 1.  One thread per (row,
 // matrix), so the short dependent chains of the gather overlap across the
 // whole grid instead of stalling the solve kernels.
-template <bool SOA, int NR>
+template <typename T, bool SOA, int NR>
 __global__ __launch_bounds__(256) void k_gather(
     const int32_t *__restrict__ grow_q, const int32_t *__restrict__ grow_y, int nrow,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
-    const double *__restrict__ Ys, double *__restrict__ FV, int64_t n, int64_t fvsize,
+    const T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize,
     int nrhs, int r0, int batch, const int32_t *__restrict__ active) {
     int row, b;
     if constexpr (SOA) {
@@ -165,7 +174,7 @@ __global__ __launch_bounds__(256) void k_gather(
     }
     const int q = grow_q[row], y = grow_y[row];
     const int g0 = gptr[q], g1 = gptr[q + 1];
-    double a[NR];
+    T a[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) a[r] = ldz(Ys, vix<SOA>(b, y, r0 + r, n, nrhs), y >= 0);
     for (int g = g0; g < g1; g++) {
@@ -186,15 +195,15 @@ __global__ __launch_bounds__(256) void k_gather(
 //   update    rows i >= w subtract L_ij y_j (ascending j), y read from LDS,
 //             L's columns read by consecutive lanes (coalesced).
 // Requires w <= G (w <= 64 for G == 64) and c <= G * SL.
-template <typename T, int G, int SL, int NR>
+template <typename T, int G, int SL, int NR, bool SOA>
 __global__ __launch_bounds__(256) void k_fwd_seg(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
     int r0, const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
-    const T *__restrict__ L, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
+    const T *__restrict__ L, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
     int64_t n, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
     constexpr int NSEG = 256 / G;
     constexpr int WM = G < 64 ? G : 64;  // widest supernode of the class
-    __shared__ double ys[NSEG][WM][NR];
+    __shared__ T ys[NSEG][WM][NR];
     const int tid = threadIdx.x, seg = tid / G, li = tid % G;
     const int item = blockIdx.x * NSEG + seg;
     if (item >= nitems) return;
@@ -203,21 +212,18 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
     const SnDesc d = sn[list[item - b * nlist]];
     const int c = d.c, w = d.w;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    const double *yb = Ys + int64_t(b) * n * nrhs + r0;
-    const double *fb = FV + int64_t(b) * fvsize * nrhs + r0;
 
-    double x[SL][NR];
+    T x[SL][NR];
 #pragma unroll
     for (int k = 0; k < SL; k++) {
         const int i = li + G * k;
 #pragma unroll
-        for (int r = 0; r < NR; r++) x[k][r] = 0.0;
-#pragma unroll
-        for (int r = 0; r < NR; r++) x[k][r] = ldz(fb, int64_t(d.rowptr + i) * nrhs + r, i < c);
+        for (int r = 0; r < NR; r++)
+            x[k][r] = ldz(FV, vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs), i < c);
     }
     // diagonal block (rows < w live in slot 0)
-    const double dgl = double(ldz(Lb, int64_t(li) * c + li, li < w));
-    const double rinv = li < w ? 1.0 / dgl : 0.0;
+    const T dgl = T(ldz(Lb, int64_t(li) * c + li, li < w));
+    const T rinv = li < w ? T(1) / dgl : T(0);
     for (int j0 = 0; j0 < w; j0 += 8) {
         T lc[8];
 #pragma unroll
@@ -229,14 +235,14 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
         for (int jj = 0; jj < 8; jj++) {
             const int j = j0 + jj;
             if (j < w) {
-                double y[NR];
+                T y[NR];
 #pragma unroll
                 for (int r = 0; r < NR; r++) y[r] = seg_bcast<G>(x[0][r] * rinv, j);
                 if (li == j) {
 #pragma unroll
                     for (int r = 0; r < NR; r++) x[0][r] = y[r];
                 } else if (li > j && li < w) {
-                    const double l = double(lc[jj]);
+                    const T l = T(lc[jj]);
 #pragma unroll
                     for (int r = 0; r < NR; r++) x[0][r] -= l * y[r];
                 }
@@ -244,11 +250,10 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
         }
     }
     if (li < w) {
-        double *yo = Ys + (int64_t(b) * n + d.first + li) * nrhs + r0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             ys[seg][li][r] = x[0][r];
-            yo[r] = x[0][r];
+            Ys[vix<SOA>(b, d.first + li, r0 + r, n, nrhs)] = x[0][r];
         }
     }
     wave_sync_solve();
@@ -267,14 +272,14 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
         for (int jj = 0; jj < JC; jj++) {
             const int j = j0 + jj;
             if (j < w) {
-                double y[NR];
+                T y[NR];
 #pragma unroll
                 for (int r = 0; r < NR; r++) y[r] = ys[seg][j][r];
 #pragma unroll
                 for (int k = 0; k < SL; k++) {
                     const int i = li + G * k;
                     if (i >= w && i < c) {
-                        const double l = double(lc[jj][k]);
+                        const T l = T(lc[jj][k]);
 #pragma unroll
                         for (int r = 0; r < NR; r++) x[k][r] -= l * y[r];
                     }
@@ -282,13 +287,13 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
             }
         }
     }
-    double *fo = FV + (int64_t(b) * fvsize + d.rowptr) * nrhs + r0;
 #pragma unroll
     for (int k = 0; k < SL; k++) {
         const int i = li + G * k;
         if (i >= w && i < c) {
 #pragma unroll
-            for (int r = 0; r < NR; r++) fo[int64_t(i) * nrhs + r] = x[k][r];
+            for (int r = 0; r < NR; r++)
+                FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)] = x[k][r];
         }
     }
 }
@@ -304,15 +309,15 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
 //             x_i = acc_i / L_ii and broadcasts it; columns j < i subtract
 //             L_ij x_i.
 constexpr int kBwdRows = 16;
-template <typename T, int G, int NR>
+template <typename T, int G, int NR, bool SOA>
 __global__ __launch_bounds__(256) void k_bwd_seg(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int nitems,
     int r0, const int32_t *__restrict__ rows, const T *__restrict__ L, int64_t Lsize,
-    double *__restrict__ Ys, int64_t n, int nrhs, const int32_t *__restrict__ active) {
+    T *__restrict__ Ys, int64_t n, int nrhs, const int32_t *__restrict__ active) {
     constexpr int NSEG = 256 / G;
     constexpr int NG = G / kBwdRows;  // column groups of the staging
     __shared__ T Ls[NSEG][kBwdRows][G + 1];
-    __shared__ double xs[NSEG][kBwdRows][NR];
+    __shared__ T xs[NSEG][kBwdRows][NR];
     const int tid = threadIdx.x, seg = tid / G, li = tid % G;
     const int item = blockIdx.x * NSEG + seg;
     if (item >= nitems) return;
@@ -321,23 +326,22 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
     const SnDesc d = sn[list[item - b * nlist]];
     const int c = d.c, w = d.w;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    double *yb = Ys + int64_t(b) * n * nrhs + r0;
     const int32_t *R = rows + d.rowptr;
     const int sr = li % kBwdRows, sg = li / kBwdRows;  // staging: row, column group
 
-    double acc[NR];
+    T acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++)
-        acc[r] = ldz(yb, int64_t(d.first + li) * nrhs + r, li < w);
-    const double rinv = li < w ? 1.0 / double(Lb[li < w ? int64_t(li) * c + li : 0]) : 0.0;
+        acc[r] = ldz(Ys, vix<SOA>(b, d.first + li, r0 + r, n, nrhs), li < w);
+    const T rinv = li < w ? T(1) / T(Lb[li < w ? int64_t(li) * c + li : 0]) : T(0);
     // rows below in blocks of kSoaRows: each block's sum (ascending rows)
     // is formed on its own and then subtracted, the same order as the
     // batch-interleaved kernels, so both layouts give identical bits
     for (int rb = w; rb < c; rb += kSoaRows) {
         const int re = min(c, rb + kSoaRows);
-        double p[NR];
+        T p[NR];
 #pragma unroll
-        for (int r = 0; r < NR; r++) p[r] = 0.0;
+        for (int r = 0; r < NR; r++) p[r] = T(0);
         for (int i0 = rb; i0 < re; i0 += kBwdRows) {
             const int i = i0 + sr;
             {
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
                 const int ri = ldz(R, i, xo);
 #pragma unroll
                 for (int r = 0; r < NR; r++) {
-                    const double xv = ldz(yb, int64_t(ri) * nrhs + r, xo);
+                    const T xv = ldz(Ys, vix<SOA>(b, ri, r0 + r, n, nrhs), xo);
                     if (xo) xs[seg][sr][r] = xv;
                 }
             }
@@ -365,7 +369,7 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
             const int nr = min(kBwdRows, re - i0);
             if (li < w) {
                 for (int t = 0; t < nr; t++) {
-                    const double l = double(Ls[seg][t][li]);
+                    const T l = T(Ls[seg][t][li]);
 #pragma unroll
                     for (int r = 0; r < NR; r++) p[r] += l * xs[seg][t][r];
                 }
@@ -393,14 +397,14 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
         }
         wave_sync_solve();
         for (int t = i1 - 1; t >= i0; t--) {
-            double xv[NR];
+            T xv[NR];
 #pragma unroll
             for (int r = 0; r < NR; r++) xv[r] = seg_bcast<G>(acc[r] * rinv, t);
             if (li == t) {
 #pragma unroll
                 for (int r = 0; r < NR; r++) acc[r] = xv[r];
             } else if (li < t) {
-                const double l = double(Ls[seg][t - i0][li]);
+                const T l = T(Ls[seg][t - i0][li]);
 #pragma unroll
                 for (int r = 0; r < NR; r++) acc[r] -= l * xv[r];
             }
@@ -409,7 +413,7 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
     }
     if (li < w) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) yb[int64_t(d.first + li) * nrhs + r] = acc[r];
+        for (int r = 0; r < NR; r++) Ys[vix<SOA>(b, d.first + li, r0 + r, n, nrhs)] = acc[r];
     }
 }
 
@@ -419,26 +423,26 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
 // D_0^{-1} v_0 with the zero-padded inverse block D_0 (column-major).
 // Item = (supernode, matrix); 256 threads; right-hand sides in blocks of
 // kMaxRhsPanel.
-template <bool SOA>
+template <typename T, bool SOA>
 __global__ __launch_bounds__(256) void k_pan_gather(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
-    const double *__restrict__ Dinv, int64_t dsize, double *__restrict__ Ys,
-    double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    const T *__restrict__ Dinv, int64_t dsize, T *__restrict__ Ys,
+    T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     const int32_t *__restrict__ active) {
-    __shared__ double v0[kP][kMaxRhsPanel];
+    __shared__ T v0[kP][kMaxRhsPanel];
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     const SnDesc d = sn[s];
     const int kb = min(kP, d.w);
-    const double *D = Dinv + int64_t(b) * dsize + d.dinv;
+    const T *D = Dinv + int64_t(b) * dsize + d.dinv;
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
         const int nr = min(kMaxRhsPanel, nrhs - r0);
         for (int i = threadIdx.x; i < d.c; i += blockDim.x) {
             const int g0 = gptr[d.rowptr + i], g1 = gptr[d.rowptr + i + 1];
             for (int r = 0; r < nr; r++) {
-                double a = ldz(Ys, vix<SOA>(b, d.first + i, r0 + r, n, nrhs), i < d.w);
+                T a = ldz(Ys, vix<SOA>(b, d.first + i, r0 + r, n, nrhs), i < d.w);
                 for (int g = g0; g < g1; g++) a += FV[vix<SOA>(b, gidx[g], r0 + r, fvsize, nrhs)];
                 FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)] = a;
                 if (i < kP) v0[i][r] = a;
@@ -447,10 +451,10 @@ __global__ __launch_bounds__(256) void k_pan_gather(
         __syncthreads();
         const int t = threadIdx.x;
         if (t < kb) {
-            double y[kMaxRhsPanel] = {};
+            T y[kMaxRhsPanel] = {};
 #pragma unroll 16
             for (int i = 0; i < kb; i++) {
-                const double di = D[int64_t(i) * kP + t];
+                const T di = D[int64_t(i) * kP + t];
 #pragma unroll
                 for (int r = 0; r < kMaxRhsPanel; r++)
                     if (r < nr) y[r] += di * v0[i][r];
@@ -469,11 +473,11 @@ __global__ __launch_bounds__(256) void k_pan_gather(
 template <typename T, int NR, bool SOA>
 __global__ __launch_bounds__(64) void k_fwd_panel(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
-    const T *__restrict__ L, int64_t Lsize, const double *__restrict__ Dinv,
-    int64_t dsize, double *__restrict__ Ys, double *__restrict__ FV, int64_t n,
+    const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Dinv,
+    int64_t dsize, T *__restrict__ Ys, T *__restrict__ FV, int64_t n,
     int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
-    __shared__ double yv[kP][NR];
-    __shared__ double vn[kP][NR];
+    __shared__ T yv[kP][NR];
+    __shared__ T vn[kP][NR];
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
     if (active && !active[b]) return;
@@ -493,14 +497,14 @@ __global__ __launch_bounds__(64) void k_fwd_panel(
     const int row = rt + lane;
     const bool rok = row < c;
     const int rowc = rok ? row : rt;  // rows past the front read row rt (in bounds)
-    double v[NR];
+    T v[NR];
     {
         const T *Lr = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + rowc;
 #pragma unroll
         for (int r = 0; r < NR; r++) v[r] = FV[vix<SOA>(b, d.rowptr + rowc, r0 + r, fvsize, nrhs)];
 #pragma unroll 8
         for (int t = 0; t < kb; t++) {
-            const double l = double(Lr[int64_t(t) * c]);
+            const T l = T(Lr[int64_t(t) * c]);
 #pragma unroll
             for (int r = 0; r < NR; r++) v[r] -= l * yv[t][r];
         }
@@ -513,16 +517,16 @@ __global__ __launch_bounds__(64) void k_fwd_panel(
     if (tile != 0 || c1 >= d.w) return;
     const int kb1 = min(kP, d.w - c1);
 #pragma unroll
-    for (int r = 0; r < NR; r++) vn[lane][r] = lane < kb1 ? v[r] : 0.0;
+    for (int r = 0; r < NR; r++) vn[lane][r] = lane < kb1 ? v[r] : T(0);
     __syncthreads();
     if (lane < kb1) {
-        const double *D = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p + 1) * kP * kP;
-        double y[NR];
+        const T *D = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p + 1) * kP * kP;
+        T y[NR];
 #pragma unroll
-        for (int r = 0; r < NR; r++) y[r] = 0.0;
+        for (int r = 0; r < NR; r++) y[r] = T(0);
 #pragma unroll 8
         for (int i = 0; i < kP; i++) {
-            const double di = D[int64_t(i) * kP + lane];
+            const T di = D[int64_t(i) * kP + lane];
 #pragma unroll
             for (int r = 0; r < NR; r++) y[r] += di * vn[i][r];
         }
@@ -540,12 +544,12 @@ template <typename T, int NR, bool SOA>
 __global__ __launch_bounds__(256) void k_bwd_pan_part(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
     const int32_t *__restrict__ rows, const T *__restrict__ L, int64_t Lsize,
-    const double *__restrict__ Ys, int64_t n, double *__restrict__ PART, int64_t psize,
+    const T *__restrict__ Ys, int64_t n, T *__restrict__ PART, int64_t psize,
     int nrhs, const int32_t *__restrict__ active) {
     constexpr int RB = 16;
     __shared__ T Ls[4][RB][kP + 1];
-    __shared__ double xs[4][RB][NR];
-    __shared__ double red[4][kP][NR];
+    __shared__ T xs[4][RB][NR];
+    __shared__ T red[4][kP][NR];
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
     if (active && !active[b]) return;
@@ -562,9 +566,9 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
     const int sr = lane & (RB - 1), sg = lane >> 4;  // staging: row, column group
     const T *Lb = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c;
     const int32_t *R = rows + d.rowptr;
-    double acc[NR];
+    T acc[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+    for (int r = 0; r < NR; r++) acc[r] = T(0);
     const int w0 = rb + 64 * wv, w1 = min(c, w0 + 64);
     for (int i0 = w0; i0 < w1; i0 += RB) {
         const int i = i0 + sr;
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
             const int64_t pos = i < d.w ? d.first + i : ldz(R, i, xo && i >= d.w);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
-                const double xv = ldz(Ys, vix<SOA>(b, pos, r0 + r, n, nrhs), xo);
+                const T xv = ldz(Ys, vix<SOA>(b, pos, r0 + r, n, nrhs), xo);
                 if (xo) xs[wv][sr][r] = xv;
             }
         }
@@ -592,7 +596,7 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
         const int nr = min(RB, w1 - i0);
         if (lane < kb) {
             for (int q = 0; q < nr; q++) {
-                const double l = double(Ls[wv][q][lane]);
+                const T l = T(Ls[wv][q][lane]);
 #pragma unroll
                 for (int r = 0; r < NR; r++) acc[r] += l * xs[wv][q][r];
             }
@@ -605,7 +609,7 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
     if (wv == 0 && lane < kb) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            const double v = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
+            const T v = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
             PART[vix<SOA>(b, d.part + int64_t(chunk) * kP + lane, r0 + r, psize, nrhs)] = v;
         }
     }
@@ -614,14 +618,14 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
 // Backward panel p, step 2: x_p = D_p^T (y_p - sum of the chunks' partial
 // sums, in chunk order), right-hand sides r0 .. r0 + NR - 1.  Item =
 // (supernode, matrix); one wave, lane t owns column c0 + t.
-template <int NR, bool SOA>
+template <typename T, int NR, bool SOA>
 __global__ __launch_bounds__(64) void k_bwd_pan_fin(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
-    const double *__restrict__ Dinv, int64_t dsize, double *__restrict__ Ys, int64_t n,
-    const double *__restrict__ PART, int64_t psize, int nrhs,
+    const T *__restrict__ Dinv, int64_t dsize, T *__restrict__ Ys, int64_t n,
+    const T *__restrict__ PART, int64_t psize, int nrhs,
     const int32_t *__restrict__ active) {
-    __shared__ double Dt[kP * (kP + 1)];
-    __shared__ double rhs[kP][NR];
+    __shared__ T Dt[kP * (kP + 1)];
+    __shared__ T rhs[kP][NR];
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
     if (active && !active[b]) return;
@@ -633,9 +637,9 @@ __global__ __launch_bounds__(64) void k_bwd_pan_fin(
     const int nch = (d.c - rbeg + kSolveChunk - 1) / kSolveChunk;
     const int t = threadIdx.x;
     // the inverse block, coalesced into LDS: Dt[j][i] = D[j * 64 + i]
-    const double *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
+    const T *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
     for (int e0 = 0; e0 < kP * kP; e0 += 16 * 64) {
-        double v[16];  // 16 loads per thread in flight at once
+        T v[16];  // 16 loads per thread in flight at once
 #pragma unroll
         for (int q = 0; q < 16; q++) v[q] = Dp[e0 + q * 64 + t];
 #pragma unroll
@@ -646,21 +650,21 @@ __global__ __launch_bounds__(64) void k_bwd_pan_fin(
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        double s0 = 0.0;
+        T s0 = T(0);
         for (int q = 0; q < nch; q++)
             s0 += ldz(PART, vix<SOA>(b, d.part + int64_t(q) * kP + t, r0 + r, psize, nrhs), t < kb);
         rhs[t][r] = t < kb ? ldz(Ys, vix<SOA>(b, d.first + c0 + t, r0 + r, n, nrhs), t < kb) - s0
-                           : 0.0;
+                           : T(0);
     }
     __syncthreads();
     if (t < kb) {
         // x_t = sum_i (L_pp^{-1})[i][t] rhs_i; column t of the inverse is Dt[t][.]
-        double xt[NR];
+        T xt[NR];
 #pragma unroll
-        for (int r = 0; r < NR; r++) xt[r] = 0.0;
+        for (int r = 0; r < NR; r++) xt[r] = T(0);
 #pragma unroll 8
         for (int i = 0; i < kb; i++) {
-            const double dti = Dt[t * (kP + 1) + i];
+            const T dti = Dt[t * (kP + 1) + i];
 #pragma unroll
             for (int r = 0; r < NR; r++) xt[r] += dti * rhs[i][r];
         }
@@ -717,10 +721,11 @@ __global__ __launch_bounds__(256) void k_to_soa(
 // tile of 64 rows x 64 matrices: read along rows of each right-hand side
 // (lanes = rows), written along matrices (lanes = matrices), so both sides
 // move whole cache lines.
+template <typename T>
 __global__ __launch_bounds__(256) void k_perm_in_soa(
     const int32_t *__restrict__ pinv, const double *__restrict__ B, int64_t ldb,
-    double *__restrict__ Ys, int64_t n, int nrhs, int batch) {
-    __shared__ double tile[64][65];
+    T *__restrict__ Ys, int64_t n, int nrhs, int batch) {
+    __shared__ T tile[64][65];
     const int bg = blockIdx.y;
     const int64_t i0 = int64_t(blockIdx.x) * 64;
     const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
@@ -732,7 +737,7 @@ __global__ __launch_bounds__(256) void k_perm_in_soa(
             v[q] = ldz(B, (int64_t(b) * nrhs + r) * ldb + i0 + lo, b < batch && i0 + lo < n);
         }
 #pragma unroll
-        for (int q = 0; q < 16; q++) tile[hi + 4 * q][lo] = v[q];
+        for (int q = 0; q < 16; q++) tile[hi + 4 * q][lo] = T(v[q]);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 16; q++) {
@@ -745,15 +750,16 @@ __global__ __launch_bounds__(256) void k_perm_in_soa(
 
 // X[(b nrhs + r) ldb + i] = Ys[vix<true>(b, pinv[i], r)] for the active
 // matrices, through the same kind of tile.
+template <typename T>
 __global__ __launch_bounds__(256) void k_perm_out_soa(
-    const int32_t *__restrict__ pinv, const double *__restrict__ Ys, double *__restrict__ X,
+    const int32_t *__restrict__ pinv, const T *__restrict__ Ys, double *__restrict__ X,
     int64_t ldb, int64_t n, int nrhs, int batch, const int32_t *__restrict__ active) {
-    __shared__ double tile[64][65];
+    __shared__ T tile[64][65];
     const int bg = blockIdx.y;
     const int64_t i0 = int64_t(blockIdx.x) * 64;
     const int t = threadIdx.x, lo = t & 63, hi = t >> 6;
     for (int r = 0; r < nrhs; r++) {
-        double v[16];
+        T v[16];
 #pragma unroll
         for (int q = 0; q < 16; q++) {
             const int64_t i = i0 + hi + 4 * q;
@@ -784,17 +790,17 @@ template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_fwd_soa_diag_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
-    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
+    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
     int64_t n, int64_t fvsize, int nrhs, int r0) {
     const SnDesc d = sn[list[blockIdx.x]];
     const int bg = blockIdx.y, lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    double *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
+    T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    T *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
-        double v[JW][NR];
+        T v[JW][NR];
 #pragma unroll
         for (int jj = 0; jj < JW; jj++) {
             const int i = j0 + jj;
@@ -812,8 +818,8 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
 #pragma unroll
             for (int kk = 0; kk < jj; kk++)
 #pragma unroll
-                for (int r = 0; r < NR; r++) v[jj][r] -= double(lrow[kk]) * v[kk][r];
-            const double rinv = ok ? 1.0 / double(lrow[jj]) : 0.0;
+                for (int r = 0; r < NR; r++) v[jj][r] -= T(lrow[kk]) * v[kk][r];
+            const T rinv = ok ? T(1) / T(lrow[jj]) : T(0);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 v[jj][r] *= rinv;
@@ -824,7 +830,7 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
         // every load of the group issued first
         constexpr int RU = SoaRows<T>::value;
         for (int i0 = j0 + JW; i0 < w; i0 += RU) {
-            double a[RU][NR];
+            T a[RU][NR];
             T l[RU][JW];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
@@ -841,7 +847,7 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
 #pragma unroll
-                    for (int r = 0; r < NR; r++) a[u][r] -= double(l[u][jj]) * v[jj][r];
+                    for (int r = 0; r < NR; r++) a[u][r] -= T(l[u][jj]) * v[jj][r];
 #pragma unroll
             for (int u = 0; u < RU; u++)
                 if (i0 + u < w)
@@ -856,7 +862,7 @@ template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_fwd_soa_diag(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
-    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys, double *__restrict__ FV,
+    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
     int64_t n, int64_t fvsize, int nrhs, int r0) {
     // column-chunk width by the supernode's width (uniform per wave), so
     // narrow supernodes issue no masked loads for absent columns
@@ -874,7 +880,7 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
     const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
-    double *__restrict__ Ys, double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     int r0) {
     const SnDesc d = sn[it_s[blockIdx.x]];
     const int rb = it_r0[blockIdx.x];
@@ -883,11 +889,11 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
     const int re = min(c, rb + kSoaRows);
     constexpr int RU = SoaRows<T>::value;
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    const double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    double *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
+    const T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    T *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
-        double y[JW][NR];
+        T y[JW][NR];
 #pragma unroll
         for (int jj = 0; jj < JW; jj++)
 #pragma unroll
@@ -895,7 +901,7 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
                 y[jj][r] = ldz(yb, (int64_t(d.first + j0 + jj) * nrhs + r) * 64, jj < jn);
         // RU rows at a time, every load of the group issued before any use
         for (int i0 = rb; i0 < re; i0 += RU) {
-            double a[RU][NR];
+            T a[RU][NR];
             T l[RU][JW];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
@@ -912,7 +918,7 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
 #pragma unroll
-                    for (int r = 0; r < NR; r++) a[u][r] -= double(l[u][jj]) * y[jj][r];
+                    for (int r = 0; r < NR; r++) a[u][r] -= T(l[u][jj]) * y[jj][r];
 #pragma unroll
             for (int u = 0; u < RU; u++)
                 if (i0 + u < re)
@@ -928,7 +934,7 @@ __global__ __launch_bounds__(64) void k_fwd_soa_rows(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
     const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
-    double *__restrict__ Ys, double *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     int r0) {
     // column-chunk width by the supernode's width (uniform per wave), so
     // narrow supernodes issue no masked loads for absent columns
@@ -946,8 +952,8 @@ template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_bwd_soa_rows_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
-    const T *__restrict__ Ls, int64_t Lsize, const double *__restrict__ Ys,
-    double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    const T *__restrict__ Ls, int64_t Lsize, const T *__restrict__ Ys,
+    T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
     const SnDesc d = sn[it_s[blockIdx.x]];
     const int rb = it_r0[blockIdx.x];
     const int bg = blockIdx.y, lane = threadIdx.x;
@@ -959,23 +965,23 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
     // the block's row indices, one per lane, broadcast with readlane below
     const int rmine = rb + lane < re ? R[rb + lane] : 0;
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    const double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    double *pb = PS + ((int64_t(bg) * psize + d.part + int64_t(kblk) * w) * nrhs + r0) * 64 + lane;
+    const T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    T *pb = PS + ((int64_t(bg) * psize + d.part + int64_t(kblk) * w) * nrhs + r0) * 64 + lane;
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
-        double acc[JW][NR];
+        T acc[JW][NR];
 #pragma unroll
         for (int jj = 0; jj < JW; jj++)
 #pragma unroll
-            for (int r = 0; r < NR; r++) acc[jj][r] = 0.0;
+            for (int r = 0; r < NR; r++) acc[jj][r] = T(0);
         for (int i0 = rb; i0 < re; i0 += RU) {
-            double x[RU][NR];
+            T x[RU][NR];
             T l[RU][JW];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
                 const int i = i0 + u;
                 const int ri = i < re ? __builtin_amdgcn_readlane(rmine, i - rb) : 0;
-                const double *xi = yb + int64_t(ri) * nrhs * 64;
+                const T *xi = yb + int64_t(ri) * nrhs * 64;
 #pragma unroll
                 for (int r = 0; r < NR; r++) x[u][r] = ldz(xi, r * 64, i < re);
 #pragma unroll
@@ -987,7 +993,7 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
 #pragma unroll
-                    for (int r = 0; r < NR; r++) acc[jj][r] += double(l[u][jj]) * x[u][r];
+                    for (int r = 0; r < NR; r++) acc[jj][r] += T(l[u][jj]) * x[u][r];
         }
 #pragma unroll
         for (int jj = 0; jj < JW; jj++)
@@ -1001,8 +1007,8 @@ template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_bwd_soa_rows(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
-    const T *__restrict__ Ls, int64_t Lsize, const double *__restrict__ Ys,
-    double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    const T *__restrict__ Ls, int64_t Lsize, const T *__restrict__ Ys,
+    T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
     // column-chunk width by the supernode's width (uniform per wave), so
     // narrow supernodes issue no masked loads for absent columns
     const int w = sn[it_s[blockIdx.x]].w;
@@ -1020,26 +1026,26 @@ __global__ __launch_bounds__(64) void k_bwd_soa_rows(
 template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_bwd_soa_diag_body(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys,
-    const double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
+    const T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
     const SnDesc d = sn[list[blockIdx.x]];
     const int bg = blockIdx.y, lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int nblk = (c - w + kSoaRows - 1) / kSoaRows;
     const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    double *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    const double *pb = PS + ((int64_t(bg) * psize + d.part) * nrhs + r0) * 64 + lane;
+    T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
+    const T *pb = PS + ((int64_t(bg) * psize + d.part) * nrhs + r0) * 64 + lane;
     constexpr int RU = SoaRows<T>::value;
     for (int j0 = ((w - 1) / JW) * JW; j0 >= 0; j0 -= JW) {
         const int jn = min(JW, w - j0);
-        double acc[JW][NR];
+        T acc[JW][NR];
 #pragma unroll
         for (int jj = 0; jj < JW; jj++)
 #pragma unroll
             for (int r = 0; r < NR; r++)
                 acc[jj][r] = ldz(yb, (int64_t(d.first + j0 + jj) * nrhs + r) * 64, jj < jn);
         for (int k = 0; k < nblk; k++) {  // row-block partial sums, in block order
-            double p[JW][NR];
+            T p[JW][NR];
 #pragma unroll
             for (int jj = 0; jj < JW; jj++)
 #pragma unroll
@@ -1053,7 +1059,7 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
         // the supernode's own later rows, descending as in the other layout,
         // RU rows with their loads in flight together
         for (int i1 = w - 1; i1 >= j0 + JW; i1 -= RU) {
-            double x[RU][NR];
+            T x[RU][NR];
             T l[RU][JW];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
@@ -1070,7 +1076,7 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
 #pragma unroll
-                    for (int r = 0; r < NR; r++) acc[jj][r] -= double(l[u][jj]) * x[u][r];
+                    for (int r = 0; r < NR; r++) acc[jj][r] -= T(l[u][jj]) * x[u][r];
         }
 #pragma unroll
         for (int jj = JW - 1; jj >= 0; jj--) {
@@ -1079,7 +1085,7 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
             T lrow[JW];  // row j of the chunk's triangle, diagonal included
 #pragma unroll
             for (int kk = 0; kk <= jj; kk++) lrow[kk] = ldz(Lb, (int64_t(j0 + kk) * c + j) * 64, ok);
-            const double rinv = ok ? 1.0 / double(lrow[jj]) : 0.0;
+            const T rinv = ok ? T(1) / T(lrow[jj]) : T(0);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 acc[jj][r] *= rinv;
@@ -1088,7 +1094,7 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
 #pragma unroll
             for (int kk = 0; kk < jj; kk++)
 #pragma unroll
-                for (int r = 0; r < NR; r++) acc[kk][r] -= double(lrow[kk]) * acc[jj][r];
+                for (int r = 0; r < NR; r++) acc[kk][r] -= T(lrow[kk]) * acc[jj][r];
         }
     }
 }
@@ -1096,8 +1102,8 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
 template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_bwd_soa_diag(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const T *__restrict__ Ls, int64_t Lsize, double *__restrict__ Ys,
-    const double *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
+    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
+    const T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
     // column-chunk width by the supernode's width (uniform per wave), so
     // narrow supernodes issue no masked loads for absent columns
     const int w = sn[list[blockIdx.x]].w;
@@ -1105,6 +1111,11 @@ __global__ __launch_bounds__(64) void k_bwd_soa_diag(
     else if (w <= 8) k_bwd_soa_diag_body<T, NR, 8>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
     else k_bwd_soa_diag_body<T, NR, 16>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
 }
+
+// Solve workspaces hold vectors in the factor's precision (allocated as
+// doubles, large enough for either).
+template <typename T>
+T *as(double *p) { return reinterpret_cast<T *>(p); }
 
 template <typename T>
 hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
@@ -1114,28 +1125,29 @@ hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
     const int64_t maxp = (P->max_width + kP - 1) / kP;
     N->prof.begin(KK_Dinv, 0.0, 0.0, st);
     hipLaunchKernelGGL(k_dinv<T>, dim3(unsigned(maxp), unsigned(P->npan), unsigned(N->batch)),
-                       dim3(64), 0, st, D->sn, D->slv_pan, L, P->Lsize, N->dinv, P->dinv_size);
+                       dim3(64), 0, st, D->sn, D->slv_pan, L, P->Lsize, as<T>(N->dinv), P->dinv_size);
     N->prof.end(st);
     return hipGetLastError();
 }
 
 // Gather of the front vectors of one level (rows of the supernodes not
 // solved by panels), every right-hand side.
-template <bool SOA>
+template <typename T, bool SOA>
 void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
                    const int32_t *active, hipStream_t st) {
     if (l.ngrow == 0) return;
     const DevPlan *D = P->dev;
     const int B = N->batch;
     const int64_t fvsize = int64_t(P->rows.size());
-    N->prof.begin(KK_Gather, 0.0, l.v_gather * double(nrhs) * double(B), st);
+    N->prof.begin(KK_Gather, 0.0,
+                  (l.vw_gather * double(sizeof(T)) + l.ib_gather) * double(nrhs) * double(B), st);
     const dim3 g = SOA ? dim3(unsigned((l.ngrow + 3) / 4), unsigned((B + 63) / 64))
                        : dim3(unsigned((int64_t(l.ngrow) * B + 255) / 256));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
         const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_GATHER(NRV)                                                                     \
-    hipLaunchKernelGGL((k_gather<SOA, NRV>), g, dim3(256), 0, st, D->grow_q + l.grow0,          \
-                       D->grow_y + l.grow0, l.ngrow, D->gptr, D->gidx, N->ws_y, N->ws_u, P->n,  \
+    hipLaunchKernelGGL((k_gather<T, SOA, NRV>), g, dim3(256), 0, st, D->grow_q + l.grow0,          \
+                       D->grow_y + l.grow0, l.ngrow, D->gptr, D->gidx, as<T>(N->ws_y), as<T>(N->ws_u), P->n,  \
                        fvsize, nrhs, r0, B, active)
         if (nrr == 1) SPCHOL_GATHER(1);
         else if (nrr == 2) SPCHOL_GATHER(2);
@@ -1147,15 +1159,15 @@ void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 }
 
 // One launch of the segment kernels for row class k.
-template <typename T, int NR>
+template <typename T, int NR, bool SOA>
 void launch_fwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_plan *P,
                       const sc_numeric *N, const SClass &cl, int nitems, int r0, int nrhs,
                       int64_t fvsize, const int32_t *active) {
     const T *L = static_cast<const T *>(N->L);
     const int32_t *lst = D->slv_small + cl.list0;
 #define SPCHOL_FWDS(G, SL)                                                                   \
-    hipLaunchKernelGGL((k_fwd_seg<T, G, SL, NR>), g, dim3(256), 0, st, D->sn, lst, cl.n,      \
-                       nitems, r0, D->gptr, D->gidx, L, P->Lsize, N->ws_y, N->ws_u, P->n,     \
+    hipLaunchKernelGGL((k_fwd_seg<T, G, SL, NR, SOA>), g, dim3(256), 0, st, D->sn, lst, cl.n, \
+                       nitems, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->ws_y), as<T>(N->ws_u), P->n,     \
                        fvsize, nrhs, active)
     switch (k) {
     case 0: SPCHOL_FWDS(16, 1); break;
@@ -1168,15 +1180,15 @@ void launch_fwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_
 #undef SPCHOL_FWDS
 }
 
-template <typename T, int NR>
+template <typename T, int NR, bool SOA>
 void launch_bwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_plan *P,
                       const sc_numeric *N, const SClass &cl, int nitems, int r0, int nrhs,
                       const int32_t *active) {
     const T *L = static_cast<const T *>(N->L);
     const int32_t *lst = D->slv_small + cl.list0;
 #define SPCHOL_BWDS(G)                                                                       \
-    hipLaunchKernelGGL((k_bwd_seg<T, G, NR>), g, dim3(256), 0, st, D->sn, lst, cl.n, nitems,  \
-                       r0, D->rows, L, P->Lsize, N->ws_y, P->n, nrhs, active)
+    hipLaunchKernelGGL((k_bwd_seg<T, G, NR, SOA>), g, dim3(256), 0, st, D->sn, lst, cl.n,     \
+                       nitems, r0, D->rows, L, P->Lsize, as<T>(N->ws_y), P->n, nrhs, active)
     if (k == 0) SPCHOL_BWDS(16);
     else if (k == 1) SPCHOL_BWDS(32);
     else SPCHOL_BWDS(64);
@@ -1184,6 +1196,65 @@ void launch_bwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_
 }
 
 inline int class_lanes(int k) { return k == 0 ? 16 : k == 1 ? 32 : 64; }
+
+// Forward and backward steps of one level's supernodes not solved by
+// panels, with the segment kernels (one launch per row class).
+template <typename T, bool SOA>
+void classes_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                     const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const int B = N->batch;
+    const int64_t fvsize = int64_t(P->rows.size());
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    for (int k = 0; k < kSolveClasses; k++) {
+        const SClass &cl = l.cls[k];
+        if (cl.n == 0) continue;
+        N->prof.begin(KK_Fwd, cl.flops * nr * nb,
+                      (cl.words * sz + (cl.vwords * sz + cl.ibytes) * nr) * nb, st);
+        const int nitems = cl.n * B;
+        const int nseg = 256 / class_lanes(k);
+        const dim3 g(unsigned((nitems + nseg - 1) / nseg));
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_FWDC(NRV) \
+    launch_fwd_class<T, NRV, SOA>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active)
+            if (nrr == 1) SPCHOL_FWDC(1);
+            else if (nrr == 2) SPCHOL_FWDC(2);
+            else if (nrr == 3) SPCHOL_FWDC(3);
+            else SPCHOL_FWDC(4);
+#undef SPCHOL_FWDC
+        }
+        N->prof.end(st);
+    }
+}
+
+template <typename T, bool SOA>
+void classes_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                      const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const int B = N->batch;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    for (int k = kSolveClasses - 1; k >= 0; k--) {
+        const SClass &cl = l.cls[k];
+        if (cl.n == 0) continue;
+        N->prof.begin(KK_Bwd, cl.flops * nr * nb,
+                      (cl.words * sz + (cl.vwords * sz + cl.ibytes) * nr) * nb, st);
+        const int nitems = cl.n * B;
+        const int nseg = 256 / class_lanes(k);
+        const dim3 g(unsigned((nitems + nseg - 1) / nseg));
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_BWDC(NRV) \
+    launch_bwd_class<T, NRV, SOA>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active)
+            if (nrr == 1) SPCHOL_BWDC(1);
+            else if (nrr == 2) SPCHOL_BWDC(2);
+            else if (nrr == 3) SPCHOL_BWDC(3);
+            else SPCHOL_BWDC(4);
+#undef SPCHOL_BWDC
+        }
+        N->prof.end(st);
+    }
+}
 
 // Panel-solved supernodes of one level, forward (gather with y_0, then one
 // launch per panel) and backward (per panel from the last: partial sums
@@ -1197,23 +1268,23 @@ void panels_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const int64_t fvsize = int64_t(P->rows.size());
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
-    prof.begin(KK_FwdPanel, 0.0, l.v_pan * nr * nb, st);
-    hipLaunchKernelGGL(k_pan_gather<SOA>, dim3(unsigned(l.npan), unsigned(B)), dim3(256), 0, st,
-                       D->sn, D->slv_pan + l.pan0, D->gptr, D->gidx, N->dinv, P->dinv_size,
-                       N->ws_y, N->ws_u, P->n, fvsize, nrhs, active);
+    prof.begin(KK_FwdPanel, 0.0, (l.vw_pan * sz + l.ib_pan) * nr * nb, st);
+    hipLaunchKernelGGL((k_pan_gather<T, SOA>), dim3(unsigned(l.npan), unsigned(B)), dim3(256), 0, st,
+                       D->sn, D->slv_pan + l.pan0, D->gptr, D->gidx, as<T>(N->dinv), P->dinv_size,
+                       as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active);
     prof.end(st);
     for (size_t q = 0; q < l.panels.size(); q++) {
         const SPanel &pp = l.panels[q];
         if (pp.fwd_tiles == 0) continue;
         prof.begin(KK_FwdPanel, pp.flops * nr * nb,
-                   (pp.words * sz + pp.dbytes + pp.vbytes * nr) * nb, st);
+                   (pp.words * sz + pp.dwords * sz + pp.vwords * sz * nr) * nb, st);
         const dim3 g(unsigned(pp.fwd_tiles), unsigned(l.npan), unsigned(B));
         for (int r0 = 0; r0 < nrhs; r0 += 4) {
             const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_FWDP(NRV)                                                                       \
     hipLaunchKernelGGL((k_fwd_panel<T, NRV, SOA>), g, dim3(64), 0, st, D->sn,                  \
-                       D->slv_pan + l.pan0, int(q), r0, L, P->Lsize, N->dinv, P->dinv_size,     \
-                       N->ws_y, N->ws_u, P->n, fvsize, nrhs, active)
+                       D->slv_pan + l.pan0, int(q), r0, L, P->Lsize, as<T>(N->dinv), P->dinv_size,     \
+                       as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active)
             if (nrr == 1) SPCHOL_FWDP(1);
             else if (nrr == 2) SPCHOL_FWDP(2);
             else if (nrr == 3) SPCHOL_FWDP(3);
@@ -1235,7 +1306,7 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
     for (size_t q = l.panels.size(); q-- > 0;) {
         const SPanel &pp = l.panels[q];
         prof.begin(KK_BwdPanel, pp.flops * nr * nb,
-                   (pp.words * sz + pp.dbytes + pp.vbytes * nr) * nb, st);
+                   (pp.words * sz + pp.dwords * sz + pp.vwords * sz * nr) * nb, st);
         for (int r0 = 0; r0 < nrhs; r0 += 4) {
             const int nrr = std::min(4, nrhs - r0);
             const dim3 gp(unsigned(pp.bwd_chunks), unsigned(l.npan), unsigned(B));
@@ -1244,11 +1315,11 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
     do {                                                                                         \
         if (pp.bwd_chunks > 0)                                                                   \
             hipLaunchKernelGGL((k_bwd_pan_part<T, NRV, SOA>), gp, dim3(256), 0, st, D->sn,       \
-                               D->slv_pan + l.pan0, int(q), r0, D->rows, L, P->Lsize, N->ws_y,   \
-                               P->n, N->ws_part, P->part_size, nrhs, active);                    \
-        hipLaunchKernelGGL((k_bwd_pan_fin<NRV, SOA>), gf, dim3(64), 0, st, D->sn,                \
-                           D->slv_pan + l.pan0, int(q), r0, N->dinv, P->dinv_size, N->ws_y,      \
-                           P->n, N->ws_part, P->part_size, nrhs, active);                        \
+                               D->slv_pan + l.pan0, int(q), r0, D->rows, L, P->Lsize, as<T>(N->ws_y),   \
+                               P->n, as<T>(N->ws_part), P->part_size, nrhs, active);                    \
+        hipLaunchKernelGGL((k_bwd_pan_fin<T, NRV, SOA>), gf, dim3(64), 0, st, D->sn,                \
+                           D->slv_pan + l.pan0, int(q), r0, as<T>(N->dinv), P->dinv_size, as<T>(N->ws_y),      \
+                           P->n, as<T>(N->ws_part), P->part_size, nrhs, active);                        \
     } while (0)
             if (nrr == 1) SPCHOL_BWDP(1);
             else if (nrr == 2) SPCHOL_BWDP(2);
@@ -1282,20 +1353,25 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
         N->ls_ok = true;
     }
     const dim3 pgrid(unsigned((P->n + 63) / 64), G);
-    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in_soa, pgrid, dim3(256), 0, st, D->pinv, b, ldb, N->ws_y, P->n,
+    prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_in_soa<T>, pgrid, dim3(256), 0, st, D->pinv, b, ldb, as<T>(N->ws_y), P->n,
                        nrhs, B);
     prof.end(st);
+    // top levels with few supernodes: one lane per row (segment kernels)
+    const int32_t segmax = P->opt.soa_seg_max == 0 ? kSoaSegMax : P->opt.soa_seg_max;
+    auto by_rows = [&](const SLaunch &l) { return segmax > 0 && int64_t(l.nall) * G <= segmax; };
     for (const SLaunch &l : D->ssched) {
-        launch_gather<true>(l, P, N, nrhs, nullptr, st);
-        if (l.nall > 0) {
-            prof.begin(KK_Fwd, l.f_diag * nr * nb, (l.w_diag * sz + l.v_diag * nr) * nb, st);
+        launch_gather<T, true>(l, P, N, nrhs, nullptr, st);
+        if (by_rows(l)) {
+            classes_forward<T, true>(l, P, N, nrhs, nullptr, st);
+        } else if (l.nall > 0) {
+            prof.begin(KK_Fwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
     hipLaunchKernelGGL((k_fwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st,     \
-                       D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls, P->Lsize, N->ws_y,   \
-                       N->ws_u, P->n, fvsize, nrhs, r0)
+                       D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls, P->Lsize, as<T>(N->ws_y),   \
+                       as<T>(N->ws_u), P->n, fvsize, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAF(1);
                 else if (nrr == 2) SPCHOL_SOAF(2);
                 else if (nrr == 3) SPCHOL_SOAF(3);
@@ -1304,14 +1380,14 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
             }
             prof.end(st);
         }
-        if (l.nit > 0) {
-            prof.begin(KK_FwdRows, l.f_rows * nr * nb, (l.w_rows * sz + l.v_rows * nr) * nb, st);
+        if (l.nit > 0 && !by_rows(l)) {
+            prof.begin(KK_FwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
     hipLaunchKernelGGL((k_fwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0, st,      \
                        D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->gptr, D->gidx, Ls,  \
-                       P->Lsize, N->ws_y, N->ws_u, P->n, fvsize, nrhs, r0)
+                       P->Lsize, as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAF(1);
                 else if (nrr == 2) SPCHOL_SOAF(2);
                 else if (nrr == 3) SPCHOL_SOAF(3);
@@ -1325,14 +1401,18 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
         if (l.npan > 0) panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
+        if (by_rows(l)) {
+            classes_backward<T, true>(l, P, N, nrhs, nullptr, st);
+            continue;
+        }
         if (l.nit > 0) {
-            prof.begin(KK_BwdRows, l.f_rows * nr * nb, (l.w_rows * sz + l.v_rows * nr) * nb, st);
+            prof.begin(KK_BwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAB(NRV)                                                                        \
     hipLaunchKernelGGL((k_bwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0, st,      \
                        D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->rows, Ls, P->Lsize, \
-                       N->ws_y, N->ws_ps, P->soa_psize, P->n, nrhs, r0)
+                       as<T>(N->ws_y), as<T>(N->ws_ps), P->soa_psize, P->n, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAB(1);
                 else if (nrr == 2) SPCHOL_SOAB(2);
                 else if (nrr == 3) SPCHOL_SOAB(3);
@@ -1342,12 +1422,12 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
             prof.end(st);
         }
         if (l.nall > 0) {
-            prof.begin(KK_Bwd, l.f_diag * nr * nb, (l.w_diag * sz + l.v_diag * nr) * nb, st);
+            prof.begin(KK_Bwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAB(NRV)                                                                        \
     hipLaunchKernelGGL((k_bwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st,     \
-                       D->sn, D->slv_small + l.all0, Ls, P->Lsize, N->ws_y, N->ws_ps,           \
+                       D->sn, D->slv_small + l.all0, Ls, P->Lsize, as<T>(N->ws_y), as<T>(N->ws_ps),           \
                        P->soa_psize, P->n, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAB(1);
                 else if (nrr == 2) SPCHOL_SOAB(2);
@@ -1358,8 +1438,8 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
             prof.end(st);
         }
     }
-    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_out_soa, pgrid, dim3(256), 0, st, D->pinv, N->ws_y, b, ldb, P->n,
+    prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_out_soa<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->ws_y), b, ldb, P->n,
                        nrhs, B, active);
     prof.end(st);
     return hipGetLastError();
@@ -1369,60 +1449,28 @@ template <typename T>
 hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
                       int64_t ldb, hipStream_t st, const int32_t *active) {
     DevPlan *D = P->dev;
-    const T *L = static_cast<const T *>(N->L);
     const int B = N->batch;
-    const int64_t fvsize = int64_t(P->rows.size());
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
     const dim3 pgrid(unsigned((P->n + 255) / 256), unsigned(B));
-    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in, pgrid, dim3(256), 0, st, D->perm, b, ldb, N->ws_y, P->n, nrhs,
+    prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_in<T>, pgrid, dim3(256), 0, st, D->perm, b, ldb, as<T>(N->ws_y), P->n, nrhs,
                        active);
     prof.end(st);
     // forward: levels ascending
     for (const SLaunch &l : D->ssched) {
-        launch_gather<false>(l, P, N, nrhs, active, st);
-        for (int k = 0; k < kSolveClasses; k++) {
-            const SClass &cl = l.cls[k];
-            if (cl.n == 0) continue;
-            prof.begin(KK_Fwd, cl.flops * nr * nb, cl.words * sz * nb + cl.vbytes * nr * nb, st);
-            const int nitems = cl.n * B;
-            const int nseg = 256 / class_lanes(k);
-            const dim3 g(unsigned((nitems + nseg - 1) / nseg));
-            for (int r0 = 0; r0 < nrhs; r0 += 4) {
-                const int nrr = std::min(4, nrhs - r0);
-                if (nrr == 1) launch_fwd_class<T, 1>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
-                else if (nrr == 2) launch_fwd_class<T, 2>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
-                else if (nrr == 3) launch_fwd_class<T, 3>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
-                else launch_fwd_class<T, 4>(k, g, st, D, P, N, cl, nitems, r0, nrhs, fvsize, active);
-            }
-            prof.end(st);
-        }
+        launch_gather<T, false>(l, P, N, nrhs, active, st);
+        classes_forward<T, false>(l, P, N, nrhs, active, st);
         if (l.npan > 0) panels_forward<T, false>(l, P, N, nrhs, active, st);
     }
     // backward: levels descending
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
         if (l.npan > 0) panels_backward<T, false>(l, P, N, nrhs, active, st);
-        for (int k = kSolveClasses - 1; k >= 0; k--) {
-            const SClass &cl = l.cls[k];
-            if (cl.n == 0) continue;
-            prof.begin(KK_Bwd, cl.flops * nr * nb, cl.words * sz * nb + cl.vbytes * nr * nb, st);
-            const int nitems = cl.n * B;
-            const int nseg = 256 / class_lanes(k);
-            const dim3 g(unsigned((nitems + nseg - 1) / nseg));
-            for (int r0 = 0; r0 < nrhs; r0 += 4) {
-                const int nrr = std::min(4, nrhs - r0);
-                if (nrr == 1) launch_bwd_class<T, 1>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
-                else if (nrr == 2) launch_bwd_class<T, 2>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
-                else if (nrr == 3) launch_bwd_class<T, 3>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
-                else launch_bwd_class<T, 4>(k, g, st, D, P, N, cl, nitems, r0, nrhs, active);
-            }
-            prof.end(st);
-        }
+        classes_backward<T, false>(l, P, N, nrhs, active, st);
     }
-    prof.begin(KK_Perm, 0.0, nb * nr * 16.0 * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_out, pgrid, dim3(256), 0, st, D->pinv, N->ws_y, b, ldb, P->n, nrhs,
+    prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
+    hipLaunchKernelGGL(k_perm_out<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->ws_y), b, ldb, P->n, nrhs,
                        active);
     prof.end(st);
     return hipGetLastError();
@@ -1446,8 +1494,9 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
                 const double lw = double(d.c) * d.w - double(d.w) * (d.w - 1) / 2;
                 cl.flops += 2.0 * lw;
                 cl.words += lw;
-                // the front vector in and out (8 B each) and its row indices
-                cl.vbytes += 8.0 * (2.0 * d.c) + 4.0 * d.c;
+                // the front vector in and out and its row indices
+                cl.vwords += 2.0 * d.c;
+                cl.ibytes += 4.0 * d.c;
             }
         }
         s.all0 = P->slv_cls_ptr[size_t(l) * kSolveClasses];
@@ -1458,26 +1507,29 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
         s.ngrow = P->grow_ptr[l + 1] - s.grow0;
         for (int32_t q = s.grow0; q < s.grow0 + s.ngrow; q++) {
             const int32_t row = P->grow_q[q];
-            s.v_gather += 8.0 * (1.0 + (P->grow_y[q] >= 0 ? 1.0 : 0.0) +
-                                 double(P->gptr[row + 1] - P->gptr[row])) +
-                          12.0 + 4.0 * double(P->gptr[row + 1] - P->gptr[row]);
+            s.vw_gather += 1.0 + (P->grow_y[q] >= 0 ? 1.0 : 0.0) +
+                           double(P->gptr[row + 1] - P->gptr[row]);
+            s.ib_gather += 12.0 + 4.0 * double(P->gptr[row + 1] - P->gptr[row]);
         }
         for (int32_t e = s.all0; e < s.all0 + s.nall; e++) {
             const SnDesc &d = P->sn[P->slv_small[e]];
             const double tri = double(d.w) * (d.w + 1) / 2, rect = double(d.m) * d.w;
             s.f_diag += 2.0 * tri;
             s.w_diag += tri;
-            s.v_diag += 8.0 * 2.0 * d.w + 4.0 * d.w;
+            s.vw_diag += 2.0 * d.w;
+            s.ib_diag += 4.0 * d.w;
             s.f_rows += 2.0 * rect;
             s.w_rows += rect;
-            s.v_rows += 8.0 * 2.0 * d.m + 4.0 * d.m;
+            s.vw_rows += 2.0 * d.m;
+            s.ib_rows += 4.0 * d.m;
         }
         s.pan0 = P->slv_pan_ptr[l];
         s.npan = P->slv_pan_ptr[l + 1] - s.pan0;
         s.maxc_pan = P->slv_pan_maxc[l];
         for (int32_t e = s.pan0; e < s.pan0 + s.npan; e++) {
             const SnDesc &d = P->sn[P->slv_pan[e]];
-            s.v_pan += 8.0 * (2.0 * d.c) + 4.0 * d.c;
+            s.vw_pan += 2.0 * d.c;
+            s.ib_pan += 4.0 * d.c;
         }
         const int np = (P->slv_pan_maxw[l] + kP - 1) / kP;
         for (int q = 0; q < np; q++) {
@@ -1493,8 +1545,8 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
                 const double lw = double(below) * kb;
                 pp.flops += 2.0 * lw + 2.0 * kb * kb;
                 pp.words += lw;
-                pp.vbytes += 8.0 * (below + 2.0 * kb);
-                pp.dbytes += 8.0 * kb * kb;
+                pp.vwords += below + 2.0 * kb;
+                pp.dwords += double(kb) * kb;
             }
             s.panels.push_back(pp);
         }

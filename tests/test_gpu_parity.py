@@ -171,8 +171,9 @@ def test_multiple_rhs():
 
 
 def test_fp32_factor_accuracy():
-    """FP32 factor (FP32 accumulation) and FP64 solve arithmetic: the factor
-    matches the oracle to FP32 accuracy (no parity claim at FP64 level)."""
+    """FP32 factor (FP32 accumulation) and FP32 solve: the factor and the
+    solution match the oracle to FP32 accuracy (no parity claim at FP64
+    level)."""
     w = W.small_grid((16, 16, 16), "nd", seed=45)
     plan, num, info, x = run_library(w, "f32")
     sym, Lx, _, xo = oracle_run(w)
@@ -258,22 +259,25 @@ def _solve_with(w, dtype, **opts):
     return db.cpu().numpy()
 
 
+@pytest.mark.parametrize("seg_max", [-1, 0, 1 << 30], ids=["lanes-per-matrix", "default", "lanes-per-row"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("name,make", [
     ("grid3d_20x18x16_nd", lambda: W.small_grid((20, 18, 16), "nd", batch=40, nrhs=3, seed=48)),
     ("trimesh_48", lambda: W.trimesh_workload(48, batch=70, nrhs=2, seed=49)),
     ("random_180_dense", lambda: W.random_spd(180, 0.4, seed=50, batch=33, nrhs=5)),
 ], ids=["grid3d", "trimesh", "dense"])
-def test_interleaved_layout_bitwise_equal_rowmajor(name, make, dtype):
+def test_interleaved_layout_bitwise_equal_rowmajor(name, make, dtype, seg_max):
     """Batches of at least 32 matrices solve in the batch-interleaved layout
-    (one matrix per lane).  Both layouts perform the same operations in the
-    same order on every entry, so the solutions are bit-identical; a batch
-    that is not a multiple of 64 exercises the partial lane group; the FP64
-    result also matches the oracle."""
+    (one matrix per lane); levels with few supernodes may instead put one
+    lane on each row (soa_seg_max: never, the default split, every level).
+    All kernels perform the same operations in the same order on every
+    entry, so the solutions are bit-identical to the row-major layout's; a
+    batch that is not a multiple of 64 exercises the partial lane group; the
+    FP64 result also matches the oracle."""
     w = make()
-    log("case %s batch=%d nrhs=%d %s" % (name, w.batch, w.nrhs, dtype))
-    x_soa = _solve_with(w, dtype, soa_min_batch=32)    # interleaved
-    x_row = _solve_with(w, dtype, soa_min_batch=-1)    # row-major segments
+    log("case %s batch=%d nrhs=%d %s seg_max=%d" % (name, w.batch, w.nrhs, dtype, seg_max))
+    x_soa = _solve_with(w, dtype, soa_min_batch=32, soa_seg_max=seg_max)  # interleaved
+    x_row = _solve_with(w, dtype, soa_min_batch=-1)                        # row-major segments
     assert np.array_equal(x_soa, x_row)
     if dtype == "f64" and name != "trimesh_48":  # the mesh is too ill-conditioned for 1e-10
         p = w.pattern
