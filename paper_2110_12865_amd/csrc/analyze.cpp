@@ -409,6 +409,30 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                 }
         }
 
+        // sliced by 64 rows for the batched product: entry k of row
+        // 64 s + l at sell_ptr[s] + 64 k + l, rows padded to the longest row
+        // of their slice (padding: column 0, vidx -1)
+        {
+            const int64_t nsl = (n + kSellRows - 1) / kSellRows;
+            P->sell_ptr.assign(nsl + 1, 0);
+            for (int64_t sl = 0; sl < nsl; sl++) {
+                int64_t len = 0;
+                for (int64_t i = sl * kSellRows; i < std::min<int64_t>(n, (sl + 1) * kSellRows); i++)
+                    len = std::max(len, P->csr_ptr[i + 1] - P->csr_ptr[i]);
+                P->sell_ptr[sl + 1] = P->sell_ptr[sl] + kSellRows * len;
+            }
+            P->sell_col.assign(P->sell_ptr[nsl], 0);
+            P->sell_vidx.assign(P->sell_ptr[nsl], -1);
+            for (int64_t i = 0; i < n; i++) {
+                const int64_t base = P->sell_ptr[i / kSellRows] + i % kSellRows;
+                for (int64_t q = P->csr_ptr[i]; q < P->csr_ptr[i + 1]; q++) {
+                    const int64_t e = base + kSellRows * (q - P->csr_ptr[i]);
+                    P->sell_col[e] = P->csr_col[q];
+                    P->sell_vidx[e] = P->csr_vidx[q];
+                }
+            }
+        }
+
         // ---- row and column of every stored entry (caller's numbering),
         // for the value gradients of the adjoint ---------------------------
         P->val_row.assign(rowind, rowind + colptr[n]);

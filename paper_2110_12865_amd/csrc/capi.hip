@@ -40,7 +40,7 @@ void free_devplan(DevPlan *D) {
     if (!D) return;
     void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
                     D->avidx, D->perm, D->pinv, D->lvl_small, D->lvl_big, D->lvl_sn,
-                    D->asm_col, D->csr_ptr, D->csr_col, D->csr_vidx,
+                    D->asm_col, D->csr_ptr, D->sell_ptr, D->sell_col, D->sell_vidx,
                     D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr, D->gidx,
                     D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
                     D->val_row, D->val_col};
@@ -80,8 +80,9 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->slv_small, P->slv_small);
     if (e == hipSuccess) e = upload(&D->slv_pan, P->slv_pan);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
-    if (e == hipSuccess) e = upload(&D->csr_col, P->csr_col);
-    if (e == hipSuccess) e = upload(&D->csr_vidx, P->csr_vidx);
+    if (e == hipSuccess) e = upload(&D->sell_ptr, P->sell_ptr);
+    if (e == hipSuccess) e = upload(&D->sell_col, P->sell_col);
+    if (e == hipSuccess) e = upload(&D->sell_vidx, P->sell_vidx);
     if (e == hipSuccess) e = upload(&D->colblk, P->colblk);
     if (e == hipSuccess) e = upload(&D->gptr, P->gptr);
     if (e == hipSuccess) e = upload(&D->gidx, P->gidx);
@@ -163,7 +164,7 @@ hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
                       sizeof(double) * N->batch * N->plan->nblk);
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.vc),
-                      sizeof(double) * N->batch * std::max<int64_t>(N->plan->csr_ptr.back(), 1));
+                      sizeof(double) * N->batch * std::max<int64_t>(N->plan->sell_ptr.back(), 1));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.stat), sizeof(double) * 6 * nseg);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.conv), sizeof(int32_t) * nseg);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.active), sizeof(int32_t) * N->batch);
@@ -770,12 +771,7 @@ sc_status sc_adjoint(const sc_plan_t *P, sc_numeric_t *N, const double *x_dev,
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = ensure_solve_ws(P, N, nrhs);
     if (e != hipSuccess) return map_err(e);
-    if (gb_dev != gx_dev) {
-        e = hipMemcpyAsync(gb_dev, gx_dev, sizeof(double) * size_t(N->batch) * nrhs * ldb,
-                           hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return map_err(e);
-    }
-    e = spchol_solve_run(P, N, gb_dev, nrhs, ldb, st, nullptr);  // lambda, in place
+    e = spchol_solve_run(P, N, gb_dev, nrhs, ldb, st, nullptr, gx_dev);  // lambda
     if (e == hipSuccess)
         e = spchol_adjoint_values(P, N->batch, x_dev, gb_dev, nrhs, ldb, gvalues_dev, ldv, st);
     return map_err(e);

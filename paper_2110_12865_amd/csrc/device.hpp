@@ -87,8 +87,9 @@ struct DevPlan {
     int32_t *slv_small = nullptr;     // solve schedule lists
     int32_t *slv_pan = nullptr;
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
-    int32_t *csr_col = nullptr;
-    int64_t *csr_vidx = nullptr;
+    int64_t *sell_ptr = nullptr;      // the same rows sliced by kSellRows
+    int32_t *sell_col = nullptr;
+    int64_t *sell_vidx = nullptr;
     int32_t *soa_it_s = nullptr;      // batch-interleaved solve items
     int32_t *soa_it_r0 = nullptr;
     int64_t *soa_chunks = nullptr;    // chunk starts of the interleaved L copy
@@ -190,10 +191,12 @@ struct sc_numeric {
 hipError_t spchol_factor_run(const sc_plan *P, sc_numeric *N,
                              const double *vals, int64_t ldv, hipStream_t st);
 // active (nullable, device): matrices b with active[b] == 0 are left untouched
-// (used by refinement to stop correcting converged matrices).
+// (used by refinement to stop correcting converged matrices).  bin
+// (nullable): the right-hand sides are read from bin instead of b (same
+// layout) and the solutions written to b.
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b,
                             int32_t nrhs, int64_t ldb, hipStream_t st,
-                            const int32_t *active);
+                            const int32_t *active, const double *bin = nullptr);
 hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
                              int64_t ldv, const double *b, double *x, int32_t nrhs,

@@ -84,6 +84,8 @@ constexpr int kSoaChunk = 128;
 constexpr int kSoaMinBatch = 64;  // default of sc_options::soa_min_batch: whole lane groups
 constexpr int kSoaSegMax = 384;   // default of sc_options::soa_seg_max
 
+constexpr int kSellRows = 64;  // rows per slice of the sliced row structure of A
+
 struct DevPlan;  // device copies, defined by the HIP side
 
 struct sc_plan {
@@ -135,6 +137,10 @@ struct sc_plan {
     std::vector<int64_t> csr_ptr;  // n+1
     std::vector<int32_t> csr_col;
     std::vector<int64_t> csr_vidx;
+    // the same entries sliced by kSellRows rows (row-interleaved per slice)
+    std::vector<int64_t> sell_ptr;  // slices + 1
+    std::vector<int32_t> sell_col;
+    std::vector<int64_t> sell_vidx;
     // row and column of every stored entry of the caller's lower triangle
     std::vector<int32_t> val_row, val_col;
 

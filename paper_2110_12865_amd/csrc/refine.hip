@@ -22,41 +22,48 @@
 
 namespace {
 
-// The values of A in the order of its row structure (both triangles), one
-// copy per matrix: vc[b * nnzf + e] = values[b][vidx[e]].  Made once per
-// refinement call so that every later product reads A contiguously.
+// The values of A in the order of its sliced row structure (both
+// triangles), one copy per matrix: vc[b * nsell + e] = values[b][vidx[e]]
+// (0 for padding).  Made once per refinement call so that every later
+// product reads A contiguously.
 __global__ __launch_bounds__(256) void k_gather_rows(
     const int64_t *__restrict__ vidx, const double *__restrict__ vals, int64_t ldv,
-    int64_t nnzf, double *__restrict__ vc) {
+    int64_t nsell, double *__restrict__ vc) {
     const int b = blockIdx.y;
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e < nnzf) vc[int64_t(b) * nnzf + e] = vals[int64_t(b) * ldv + vidx[e]];
+    if (e >= nsell) return;
+    const int64_t v = vidx[e];
+    vc[int64_t(b) * nsell + e] = v >= 0 ? vals[int64_t(b) * ldv + v] : 0.0;
 }
 
 // Y = B - A X (mode 1) or Y = A X (mode 0) for every right-hand side of the
-// matrices with active[matrix] != 0: one lane per row of A (values vc in
-// row order, entries in a fixed order), all NR right-hand sides of the
-// matrix at once so every value of A is read once per matrix.  Workgroups
-// of consecutive matrices cover the same rows, so the shared row structure
-// is reused from cache.
+// matrices with active[matrix] != 0: one lane per row of A, entries in row
+// order from the sliced layout (entry k of the 64 rows of a wave's slice is
+// one contiguous load of values and of column indices), all NR right-hand
+// sides of the matrix at once so every value of A is read once per matrix.
+// Workgroups of consecutive matrices cover the same rows, so the shared row
+// structure is reused from cache.
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply(
-    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-    const double *__restrict__ vc, int64_t nnzf,
+    const int64_t *__restrict__ ptr, const int64_t *__restrict__ sptr,
+    const int32_t *__restrict__ col, const double *__restrict__ vc, int64_t nsell,
     const double *__restrict__ B, const double *__restrict__ X, double *__restrict__ Y,
     int64_t ldb, int64_t n, int nrhs, int r0, int mode, const int32_t *__restrict__ active) {
     const int b = blockIdx.x;
     if (active && !active[b]) return;
     const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *v = vc + int64_t(b) * nnzf;
+    const int64_t e0 = sptr[i / kSellRows] + i % kSellRows;
+    const int len = int(ptr[i + 1] - ptr[i]);
+    const double *v = vc + int64_t(b) * nsell + e0;
+    const int32_t *cl = col + e0;
     const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
     double t[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) t[r] = 0.0;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) {
-        const double a = v[e];
-        const int64_t j = col[e];
+    for (int k = 0; k < len; k++) {
+        const double a = v[int64_t(k) * kSellRows];
+        const int64_t j = cl[int64_t(k) * kSellRows];
 #pragma unroll
         for (int r = 0; r < NR; r++) t[r] += a * X[base + r * ldb + j];
     }
@@ -74,19 +81,22 @@ __device__ inline int seg_of(int br, int nblk, const int32_t *colblk, int64_t i)
 // sum |A_ij|, in 32 slices (partial maxima in part[bk * 32 + slice]), then
 // the max of the slices (the maximum does not depend on the order).
 __global__ __launch_bounds__(256) void k_anorm_part(
-    const int64_t *__restrict__ ptr, const double *__restrict__ vc, int64_t nnzf,
-    const int64_t *__restrict__ col0, int nblk, double *__restrict__ part) {
+    const int64_t *__restrict__ ptr, const int64_t *__restrict__ sptr,
+    const double *__restrict__ vc, int64_t nsell, const int64_t *__restrict__ col0, int nblk,
+    double *__restrict__ part) {
     __shared__ double red[256];
     const int bk = blockIdx.y, slice = blockIdx.x;
     const int b = bk / nblk, k = bk - b * nblk;
     const int64_t r0 = col0[k], nr = col0[k + 1] - r0;
     const int64_t len = (nr + 31) / 32;
     const int64_t i0 = r0 + slice * len, i1 = min(r0 + nr, i0 + len);
-    const double *v = vc + int64_t(b) * nnzf;
+    const double *v = vc + int64_t(b) * nsell;
     double m = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const int64_t e0 = sptr[i / kSellRows] + i % kSellRows;
+        const int len = int(ptr[i + 1] - ptr[i]);
         double s = 0.0;
-        for (int64_t e = ptr[i]; e < ptr[i + 1]; e++) s += fabs(v[e]);
+        for (int k = 0; k < len; k++) s += fabs(v[e0 + int64_t(k) * kSellRows]);
         m = fmax(m, s);
     }
     red[threadIdx.x] = m;
@@ -328,13 +338,13 @@ void apply_A(const sc_plan *P, const double *vc, const double *B,
              const double *X, double *Y, int64_t ldb, int batch, int nrhs, int mode,
              const int32_t *active, hipStream_t st) {
     const DevPlan *D = P->dev;
-    const int64_t nnzf = P->csr_ptr[P->n];
+    const int64_t nsell = P->sell_ptr.back();
     const dim3 grid(unsigned(batch), unsigned((P->n + 255) / 256));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
         const int nr = std::min(4, nrhs - r0);
 #define SPCHOL_APPLY(NR)                                                                   \
-    hipLaunchKernelGGL(k_apply<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->csr_col, vc,     \
-                       nnzf, B, X, Y, ldb, P->n, nrhs, r0, mode, active)
+    hipLaunchKernelGGL(k_apply<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->sell_ptr,        \
+                       D->sell_col, vc, nsell, B, X, Y, ldb, P->n, nrhs, r0, mode, active)
         if (nr == 1) SPCHOL_APPLY(1);
         else if (nr == 2) SPCHOL_APPLY(2);
         else if (nr == 3) SPCHOL_APPLY(3);
@@ -358,17 +368,16 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
     const dim3 sgrid(unsigned((nseg + 255) / 256));
     hipError_t e;
     // x0 = solve(b)
-    hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, b, x, ldb, n, nrhs, nullptr);
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
                        int32_t(1));
     hipLaunchKernelGGL(k_set_i32, sgrid, dim3(256), 0, st, W.conv, nseg, int32_t(0));
-    e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr);
+    e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr, b);
     if (e != hipSuccess) return e;
-    const int64_t nnzf = P->csr_ptr[n];
-    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nnzf + 255) / 256), unsigned(batch)),
-                       dim3(256), 0, st, D->csr_vidx, vals, ldv, nnzf, W.vc);
+    const int64_t nsell = P->sell_ptr.back();
+    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nsell + 255) / 256), unsigned(batch)),
+                       dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, W.vc);
     hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
-                       W.vc, nnzf, D->blk_col0, nblk, W.part);
+                       D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
@@ -426,26 +435,26 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     double *r = W.r, *z = W.r + vsz, *pv = W.r + 2 * vsz, *q = W.r + 3 * vsz, *rt = W.r + 4 * vsz;
     double *rz0 = W.sc, *rz1 = W.sc + nseg, *pq = W.sc + 2 * nseg, *zq = W.sc + 3 * nseg;
     hipError_t e;
-    hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, b, x, ldb, n, nrhs, nullptr);
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
                        int32_t(1));
     hipLaunchKernelGGL(k_set_i32, sgrid, dim3(256), 0, st, W.conv, nseg, int32_t(0));
-    e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr);  // x0 = M^{-1} b
+    e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr, b);  // x0 = M^{-1} b
     if (e != hipSuccess) return e;
-    const int64_t nnzf = P->csr_ptr[n];
-    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nnzf + 255) / 256), unsigned(batch)),
-                       dim3(256), 0, st, D->csr_vidx, vals, ldv, nnzf, W.vc);
+    const int64_t nsell = P->sell_ptr.back();
+    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nsell + 255) / 256), unsigned(batch)),
+                       dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, W.vc);
     hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
-                       W.vc, nnzf, D->blk_col0, nblk, W.part);
+                       D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
-    auto check = [&](int it) -> hipError_t {
+    // true residual b - A x into res, stop test
+    auto check = [&](int it, double *res) -> hipError_t {
         prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
-        apply_A(P, W.vc, b, x, rt, ldb, batch, nrhs, 1, W.active, st);
+        apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st);
         prof.end(st);
         prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
-        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, rt, b, x, 3, ldb,
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, res, b, x, 3, ldb,
                            D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
         prof.end(st);
         hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
@@ -477,21 +486,12 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
                            out, out2);
     };
-    e = check(0);
+    e = check(0, r);  // r_0 = b - A x_0
     if (e != hipSuccess) return e;
     if (nact > 0 && maxit > 0) {
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
-        hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, rt, r, ldb, n, nrhs, W.active);
-        prof.end(st);
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
-        hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, r, z, ldb, n, nrhs, W.active);
-        prof.end(st);
-        e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
+        e = spchol_solve_run(P, N, pv, nrhs, ldb, st, W.active, r);  // p_1 = z_0 = M^{-1} r_0
         if (e != hipSuccess) return e;
-        dots(r, z, rz0);
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
-        hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, z, pv, ldb, n, nrhs, W.active);
-        prof.end(st);
+        dots(r, pv, rz0);
         double *rz = rz0, *rzn = rz1;
         for (int it = 1; it <= maxit; it++) {
             prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st);
@@ -502,14 +502,10 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
             hipLaunchKernelGGL(k_cg_xr, vgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
                                nblk, colblk, W.active, W.conv, rz, pq);
             prof.end(st);
-            e = check(it);
+            e = check(it, rt);
             if (e != hipSuccess) return e;
             if (nact == 0 || it == maxit) break;
-            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 2), st);
-            hipLaunchKernelGGL(k_copy_sys, vgrid, dim3(256), 0, st, r, z, ldb, n, nrhs,
-                               W.active);
-            prof.end(st);
-            e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active);
+            e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active, r);
             if (e != hipSuccess) return e;
             dots2(r, z, q, rzn, zq);
             prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);

@@ -1333,8 +1333,8 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
 
 // Batch-interleaved solve (groups of 64 matrices, lane = matrix).
 template <typename T>
-hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, int64_t ldb,
-                     hipStream_t st, const int32_t *active) {
+hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double *b,
+                     int32_t nrhs, int64_t ldb, hipStream_t st, const int32_t *active) {
     DevPlan *D = P->dev;
     const int B = N->batch;
     const unsigned G = unsigned((B + 63) / 64);
@@ -1354,7 +1354,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
     }
     const dim3 pgrid(unsigned((P->n + 63) / 64), G);
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in_soa<T>, pgrid, dim3(256), 0, st, D->pinv, b, ldb, as<T>(N->ws_y), P->n,
+    hipLaunchKernelGGL(k_perm_in_soa<T>, pgrid, dim3(256), 0, st, D->pinv, bin, ldb, as<T>(N->ws_y), P->n,
                        nrhs, B);
     prof.end(st);
     // top levels with few supernodes: one lane per row (segment kernels)
@@ -1446,15 +1446,15 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs, i
 }
 
 template <typename T>
-hipError_t solve_impl(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
-                      int64_t ldb, hipStream_t st, const int32_t *active) {
+hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double *b,
+                      int32_t nrhs, int64_t ldb, hipStream_t st, const int32_t *active) {
     DevPlan *D = P->dev;
     const int B = N->batch;
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
     const dim3 pgrid(unsigned((P->n + 255) / 256), unsigned(B));
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in<T>, pgrid, dim3(256), 0, st, D->perm, b, ldb, as<T>(N->ws_y), P->n, nrhs,
+    hipLaunchKernelGGL(k_perm_in<T>, pgrid, dim3(256), 0, st, D->perm, bin, ldb, as<T>(N->ws_y), P->n, nrhs,
                        active);
     prof.end(st);
     // forward: levels ascending
@@ -1562,11 +1562,13 @@ hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
 }
 
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
-                            int64_t ldb, hipStream_t st, const int32_t *active) {
+                            int64_t ldb, hipStream_t st, const int32_t *active,
+                            const double *bin) {
+    if (!bin) bin = b;
     if (N->soa) {
-        if (N->dtype == SC_F64) return solve_soa<double>(P, N, b, nrhs, ldb, st, active);
-        return solve_soa<float>(P, N, b, nrhs, ldb, st, active);
+        if (N->dtype == SC_F64) return solve_soa<double>(P, N, bin, b, nrhs, ldb, st, active);
+        return solve_soa<float>(P, N, bin, b, nrhs, ldb, st, active);
     }
-    if (N->dtype == SC_F64) return solve_impl<double>(P, N, b, nrhs, ldb, st, active);
-    return solve_impl<float>(P, N, b, nrhs, ldb, st, active);
+    if (N->dtype == SC_F64) return solve_impl<double>(P, N, bin, b, nrhs, ldb, st, active);
+    return solve_impl<float>(P, N, bin, b, nrhs, ldb, st, active);
 }
