@@ -77,7 +77,7 @@ typedef struct {
                              solved by the kernels that put one lane on each
                              row of a supernode instead (the top levels,
                              where one lane per matrix leaves the chip
-                             idle); 0 = library default (384), a negative
+                             idle); 0 = library default (96), a negative
                              value never */
 } sc_options;
 

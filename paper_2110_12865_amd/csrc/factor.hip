@@ -164,36 +164,54 @@ __device__ inline float rl(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-// Small fronts (c <= CM <= 64) held in registers, one wave per (front,
-// matrix), four waves per workgroup: lane i keeps row i of the front,
-// f[k] = F[i][k] for k <= i (entries above the diagonal are scratch).
+// Value of lane `src` of the calling lane's segment of G lanes (G == 64:
+// the whole wave, src wave-uniform).
+template <int G, typename T>
+__device__ inline T seg_bc(T v, int src) {
+    if constexpr (G == 64)
+        return rl(v, src);
+    else
+        return __shfl(v, src, G);
+}
+
+// Small fronts (c <= CM <= G) held in registers, one segment of G lanes per
+// (front, matrix): a wave covers one front for 64 / G consecutive matrices
+// (the same structure, so control flow is uniform), four fronts per
+// workgroup.  Lane i of a segment keeps row i of the front, f[k] = F[i][k]
+// for k <= i (entries above the diagonal are scratch).
 //   assembly  A's entries are loaded lane-parallel and handed to their row
-//             with readlane; a child's update block is read row-wise
-//             through the inverse of its relative map (an LDS table).
+//             by broadcasts inside the segment; a child's update block is
+//             read row-wise through the inverse of its relative map (an
+//             LDS table shared by the segments).
 //   factor    right-looking: the pivot and the column of L are broadcast
-//             with readlane; after each step the registers shift left by
+//             in the segment; after each step the registers shift left by
 //             one so that the current column is always f[0] (every
 //             register index is a compile-time constant).
-template <typename T, int CM>
+template <typename T, int CM, int G>
 __global__ __launch_bounds__(256) void k_front_reg(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist,
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int batch,
     const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
     const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
     const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
     T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
     int32_t *__restrict__ info, int nblk) {
+    static_assert(CM <= G && (G == 16 || G == 32 || G == 64), "segment shape");
+    constexpr int NSEG = 64 / G;
     __shared__ int32_t inv_all[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int e = blockIdx.x * 4 + wv;
     if (e >= nlist) return;
+    const int li = lane % G, sg = lane / G;
+    const int b = blockIdx.y * NSEG + sg;
+    const bool bok = b < batch;
+    const int64_t bb = bok ? b : int64_t(blockIdx.y) * NSEG;  // in-bounds matrix for loads
     int32_t *inv = inv_all[wv];
     const int s = list[e];
-    const int b = blockIdx.y;
     const SnDesc d = sn[s];
     const int c = d.c, w = d.w, m = d.m;
-    L += int64_t(b) * Lsize;
-    U += int64_t(b) * Usize;
-    vals += int64_t(b) * ldv;
+    L += bb * Lsize;
+    U += bb * Usize;
+    vals += bb * ldv;
 
     T f[CM];
 #pragma unroll
@@ -201,10 +219,10 @@ __global__ __launch_bounds__(256) void k_front_reg(
 
     // A's columns of the front: entries [a0, a1), sorted by column
     const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
-    // first entry of column `lane`, relative to a0
-    const int acol = lane < w ? int(acolptr[d.first + lane] - a0) : int(a1 - a0);
-    for (int64_t base = a0; base < a1; base += 64) {
-        const int64_t q = base + lane;
+    // first entry of column li, relative to a0
+    const int acol = li < w ? int(acolptr[d.first + li] - a0) : int(a1 - a0);
+    for (int64_t base = a0; base < a1; base += G) {
+        const int64_t q = base + li;
         int row = -1;
         T val = T(0);
         if (q < a1) {
@@ -212,18 +230,18 @@ __global__ __launch_bounds__(256) void k_front_reg(
             val = T(vals[avidx[q]]);
         }
         const int rb = int(base - a0);                       // this round: entries
-        const int re = int((base + 64 < a1 ? base + 64 : a1) - a0);  // [rb, re)
+        const int re = int((base + G < a1 ? base + G : a1) - a0);  // [rb, re)
 #pragma unroll
         for (int k = 0; k < CM; k++) {
             // column k's entries in this round (none once k >= w)
             const int lo = k < w ? __builtin_amdgcn_readlane(acol, k) : re;
-            const int hi = k + 1 < w ? __builtin_amdgcn_readlane(acol, (k + 1) & 63) : int(a1 - a0);
+            const int hi = k + 1 < w ? __builtin_amdgcn_readlane(acol, (k + 1) % G) : int(a1 - a0);
             const int t0 = (lo > rb ? lo : rb) - rb;
             const int t1 = (hi < re ? hi : re) - rb;
             for (int t = t0; t < t1; t++) {
-                const int r = __builtin_amdgcn_readlane(row, t);
-                const T v = rl(val, t);
-                if (lane == r) f[k] += v;
+                const int r = __builtin_amdgcn_readlane(row, t);  // same in every segment
+                const T v = seg_bc<G>(val, t);
+                if (li == r) f[k] += v;
             }
         }
     }
@@ -233,11 +251,11 @@ __global__ __launch_bounds__(256) void k_front_reg(
         const SnDesc cd = sn[chlist[q]];
         const int mc = cd.m;
         const T *Uc = U + cd.uoff;
-        inv[lane] = -1;
+        if (sg == 0) inv[li] = -1;
         wave_fence_sync();
-        if (lane < mc) inv[relmap[cd.relptr + lane]] = lane;
+        if (sg == 0 && li < mc) inv[relmap[cd.relptr + li]] = li;
         wave_fence_sync();
-        const int pi = inv[lane];  // child row landing in front row `lane`, or -1
+        const int pi = inv[li];  // child row landing in front row li, or -1
         wave_fence_sync();
         // eight target columns at a time: all loads issued before any use
         // (addresses of absent entries are clamped to the block's first)
@@ -245,7 +263,7 @@ __global__ __launch_bounds__(256) void k_front_reg(
         for (int k0 = 0; k0 < CM; k0 += 8) {
             int qk[8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) qk[t] = __builtin_amdgcn_readlane(pi, k0 + t);
+            for (int t = 0; t < 8; t++) qk[t] = __builtin_amdgcn_readlane(pi, (k0 + t) % G);
             if ((qk[0] & qk[1] & qk[2] & qk[3] & qk[4] & qk[5] & qk[6] & qk[7]) == -1)
                 continue;  // no column of this child lands here
             T v[8];
@@ -261,22 +279,22 @@ __global__ __launch_bounds__(256) void k_front_reg(
     }
 
     // partial factorization of the first w columns
-    const int64_t infoidx = int64_t(b) * nblk + d.blk;
+    const int64_t infoidx = bb * nblk + d.blk;
     T *Lb = L + d.loff;
     for (int j = 0; j < w; j++) {
-        T djj = rl(f[0], j);
+        T djj = seg_bc<G>(f[0], j);
         const bool bad = !(djj > T(0));
         if (bad) {
             djj = T(1);
-            if (lane == 0) atomicMin(info + infoidx, d.first - d.bcol0 + j + 1);
+            if (li == 0 && bok) atomicMin(info + infoidx, d.first - d.bcol0 + j + 1);
         }
         const T ljj = dsqrt(djj);
         const T rinv = T(1) / ljj;
-        const T lij = lane == j ? ljj : (lane > j ? f[0] * rinv : T(0));
-        if (lane < c) Lb[int64_t(j) * c + lane] = lij;
+        const T lij = li == j ? ljj : (li > j ? f[0] * rinv : T(0));
+        if (li < c && bok) Lb[int64_t(j) * c + li] = lij;
         // columns j + k >= c are scratch: their updates are never read
 #pragma unroll
-        for (int k = 1; k < CM; k++) f[k] -= lij * rl(lij, (j + k) & 63);
+        for (int k = 1; k < CM; k++) f[k] -= lij * seg_bc<G>(lij, (j + k) % G);
 #pragma unroll
         for (int k = 0; k + 1 < CM; k++) f[k] = f[k + 1];
         f[CM - 1] = T(0);
@@ -285,7 +303,7 @@ __global__ __launch_bounds__(256) void k_front_reg(
     T *Us = U + d.uoff;
 #pragma unroll
     for (int k = 0; k < CM; k++)
-        if (k < m && lane >= w + k && lane < c) Us[int64_t(k) * m + lane - w] = f[k];
+        if (k < m && li >= w + k && li < c && bok) Us[int64_t(k) * m + li - w] = f[k];
 }
 
 // Large fronts: assembly with one wave per (target column, matrix), `per`
@@ -792,18 +810,19 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         case FLaunch::Small: {
             const int cmax = int(std::lround(std::sqrt(double(f.lds))));
             if (cmax <= 64) {
-                // fronts in registers, one wave each, four per workgroup
-                const dim3 grid(unsigned((f.nlist + 3) / 4), B);
-#define SPCHOL_FRONT_REG(CM)                                                                \
-    hipLaunchKernelGGL((k_front_reg<T, CM>), grid, dim3(256), 0, st, D->sn,                  \
-                       D->lvl_small + f.list0, f.nlist, D->relmap, D->chlist, D->acolptr,    \
-                       D->aoff, D->avidx, vals, ldv, L, P->Lsize, U, P->Usize, N->info,      \
-                       P->nblk)
-                if (cmax <= 16) SPCHOL_FRONT_REG(16);
-                else if (cmax <= 32) SPCHOL_FRONT_REG(32);
-                else if (cmax <= 48) SPCHOL_FRONT_REG(48);
-                else if (cmax <= 56) SPCHOL_FRONT_REG(56);
-                else SPCHOL_FRONT_REG(64);
+                // fronts in registers, one segment of G lanes per (front,
+                // matrix), 64 / G matrices per wave, four fronts per workgroup
+#define SPCHOL_FRONT_REG(CM, G)                                                             \
+    hipLaunchKernelGGL((k_front_reg<T, CM, G>),                                              \
+                       dim3(unsigned((f.nlist + 3) / 4), unsigned((B + 64 / G - 1) / (64 / G))), \
+                       dim3(256), 0, st, D->sn, D->lvl_small + f.list0, f.nlist, int(B),     \
+                       D->relmap, D->chlist, D->acolptr, D->aoff, D->avidx, vals, ldv, L,    \
+                       P->Lsize, U, P->Usize, N->info, P->nblk)
+                if (cmax <= 16) SPCHOL_FRONT_REG(16, 16);
+                else if (cmax <= 32) SPCHOL_FRONT_REG(32, 32);
+                else if (cmax <= 48) SPCHOL_FRONT_REG(48, 64);
+                else if (cmax <= 56) SPCHOL_FRONT_REG(56, 64);
+                else SPCHOL_FRONT_REG(64, 64);
 #undef SPCHOL_FRONT_REG
                 break;
             }

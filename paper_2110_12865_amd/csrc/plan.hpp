@@ -82,7 +82,7 @@ inline bool solve_by_panels(const SnDesc &d) { return d.w > kSolvePanel || d.c >
 constexpr int kSoaRows = 16;
 constexpr int kSoaChunk = 128;
 constexpr int kSoaMinBatch = 64;  // default of sc_options::soa_min_batch: whole lane groups
-constexpr int kSoaSegMax = 384;   // default of sc_options::soa_seg_max
+constexpr int kSoaSegMax = 96;    // default of sc_options::soa_seg_max
 
 constexpr int kSellRows = 64;  // rows per slice of the sliced row structure of A
 

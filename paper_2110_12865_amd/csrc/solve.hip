@@ -674,6 +674,234 @@ __global__ __launch_bounds__(64) void k_bwd_pan_fin(
 }
 
 // ---------------------------------------------------------------------------
+// Panel-solved supernodes with one workgroup per (supernode, matrix): the
+// whole front vector lives in LDS and the workgroup walks the 64-column
+// panels itself, so a level takes one launch per direction instead of a
+// few per panel.  The arithmetic is that of the multi-launch panel kernels
+// above, operation for operation (gather with the children in order,
+// D_p^{-1} products by ascending index, row updates by ascending column,
+// backward partial sums by chunks of kSolveChunk rows split over four
+// waves and added in wave order, then in chunk order), so both give the
+// same bits.  Used for batches, where (supernodes x matrices) workgroups
+// fill the chip; a front of c rows needs c * NR scalars of LDS.
+constexpr int kSnThreads = 512;   // backward: eight waves, two row chunks at a time
+constexpr int kSnWaves = kSnThreads / 64;
+constexpr int kSnRB = 16;         // rows per staging block of the backward sums
+constexpr int kSnThreadsF = 256;  // forward
+
+// Forward: small workgroups (several per CU hide each other's latency).
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
+    const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Dinv, int64_t dsize,
+    T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    const int32_t *__restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T(*v)[NR] = reinterpret_cast<T(*)[NR]>(smem_raw);  // front vector, c rows
+    const int s = list[blockIdx.x];
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < c; i += kSnThreadsF) {
+        const int g0 = gptr[d.rowptr + i], g1 = gptr[d.rowptr + i + 1];
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            T a = ldz(Ys, vix<SOA>(b, d.first + i, r0 + r, n, nrhs), i < w);
+            for (int g = g0; g < g1; g++) a += FV[vix<SOA>(b, gidx[g], r0 + r, fvsize, nrhs)];
+            v[i][r] = a;
+        }
+    }
+    __syncthreads();
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    const T *Db = Dinv + int64_t(b) * dsize + d.dinv;
+    for (int c0 = 0; c0 < w; c0 += kP) {
+        const int kb = min(kP, w - c0);
+        // y_p = D_p^{-1} v_p (the first panel sums over its kb rows, later
+        // ones over all 64 with zeros past kb, as the panel kernels do)
+        T y[NR];
+        if (tid < kb) {
+            const T *D = Db + int64_t(c0 / kP) * kP * kP;
+            const int ni = c0 == 0 ? kb : kP;
+#pragma unroll
+            for (int r = 0; r < NR; r++) y[r] = T(0);
+#pragma unroll 16
+            for (int i = 0; i < ni; i++) {
+                const T di = D[int64_t(i) * kP + tid];
+#pragma unroll
+                for (int r = 0; r < NR; r++) y[r] += di * (i < kb ? v[c0 + i][r] : T(0));
+            }
+        }
+        __syncthreads();
+        if (tid < kb) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                v[c0 + tid][r] = y[r];
+                Ys[vix<SOA>(b, d.first + c0 + tid, r0 + r, n, nrhs)] = y[r];
+            }
+        }
+        __syncthreads();
+        // rows below the panel
+        for (int i = c0 + kb + tid; i < c; i += kSnThreadsF) {
+            T a[NR];
+#pragma unroll
+            for (int r = 0; r < NR; r++) a[r] = v[i][r];
+            const T *Lr = Lb + int64_t(c0) * c + i;
+#pragma unroll 16
+            for (int t = 0; t < kb; t++) {
+                const T l = Lr[int64_t(t) * c];
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[r] -= l * v[c0 + t][r];
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) v[i][r] = a[r];
+        }
+        __syncthreads();
+    }
+    for (int i = w + tid; i < c; i += kSnThreadsF) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)] = v[i][r];
+    }
+}
+
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(kSnThreads) void k_bwd_sn(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
+    const int32_t *__restrict__ rows, const T *__restrict__ L, int64_t Lsize,
+    const T *__restrict__ Dinv, int64_t dsize, T *__restrict__ Ys, int64_t n, int nrhs,
+    const int32_t *__restrict__ active) {
+    constexpr int RB = kSnRB;
+    constexpr int NB = 64 / RB;  // staging blocks per wave's 64 rows
+    static_assert(kSnWaves * RB >= kP && kSolveChunk == 4 * 64, "LDS sharing and chunk split");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T stage[kSnWaves * RB * (kP + 1)];  // rows of L while summing, then D_p
+    __shared__ T red[kSnWaves][kP][NR];
+    __shared__ T rhs[kP][NR];
+    T(*Ls)[RB][kP + 1] = reinterpret_cast<T(*)[RB][kP + 1]>(stage);
+    T *Dt = stage;
+    T(*xs)[NR] = reinterpret_cast<T(*)[NR]>(smem_raw);  // x of the front's rows
+    const int s = list[blockIdx.x];
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int sr = lane & (RB - 1), sg = lane >> 4;  // staging: row, column group
+    const int32_t *R = rows + d.rowptr;
+    for (int i = w + tid; i < c; i += kSnThreads) {
+        const int ri = R[i];
+#pragma unroll
+        for (int r = 0; r < NR; r++) xs[i][r] = Ys[vix<SOA>(b, ri, r0 + r, n, nrhs)];
+    }
+    __syncthreads();
+    const T *Lsn = L + int64_t(b) * Lsize + d.loff;
+    const T *Db = Dinv + int64_t(b) * dsize + d.dinv;
+    for (int c0 = ((w - 1) / kP) * kP; c0 >= 0; c0 -= kP) {
+        const int kb = min(kP, w - c0);
+        const int rbeg = c0 + kb;
+        const T *Lb = Lsn + int64_t(c0) * c;
+        // partial sums of L[i, c0 + t] x_i by chunks of kSolveChunk rows:
+        // waves 4h .. 4h + 3 take chunk 2k + h, 64 rows each, the four
+        // waves' sums are added in wave order and the chunks in order
+        // the inverse block and y_p, in flight with the first rows of L
+        const T *Dp = Db + int64_t(c0 / kP) * kP * kP;
+        constexpr int DPT = kP * kP / kSnThreads;
+        T dreg[DPT];
+#pragma unroll
+        for (int q = 0; q < DPT; q++) dreg[q] = Dp[q * kSnThreads + tid];
+        T yp[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            yp[r] = ldz(Ys, vix<SOA>(b, d.first + c0 + lane, r0 + r, n, nrhs), wv == 0 && lane < kb);
+        T s0[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) s0[r] = T(0);
+        for (int rb2 = rbeg; rb2 < c; rb2 += 2 * kSolveChunk) {
+            const int h = wv >> 2;
+            const int w0 = rb2 + h * kSolveChunk + 64 * (wv & 3), w1 = min(c, w0 + 64);
+            T acc[NR];
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[r] = T(0);
+            // every row block of this wave's 64 rows in flight at once
+            T lv[NB][16];
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                const int i = w0 + k * RB + sr;
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    const int t = sg + 4 * q;
+                    lv[k][q] = ldz(Lb, int64_t(t) * c + i, i < w1 && t < kb);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                const int i0 = w0 + k * RB;
+                const int i = i0 + sr;
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    const int t = sg + 4 * q;
+                    if (i < w1 && t < kb) Ls[wv][sr][t] = lv[k][q];
+                }
+                wave_sync_solve();  // each wave stages and reads its own rows
+                const int nr = min(RB, w1 - i0);
+                if (lane < kb) {
+                    for (int q = 0; q < nr; q++) {
+                        const T l = Ls[wv][q][lane];
+#pragma unroll
+                        for (int r = 0; r < NR; r++) acc[r] += l * xs[i0 + q][r];
+                    }
+                }
+                wave_sync_solve();
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
+            __syncthreads();
+            if (wv == 0 && lane < kb) {
+#pragma unroll
+                for (int r = 0; r < NR; r++)
+                    s0[r] += ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
+                if (rb2 + kSolveChunk < c) {
+#pragma unroll
+                    for (int r = 0; r < NR; r++)
+                        s0[r] += ((red[4][lane][r] + red[5][lane][r]) + red[6][lane][r]) + red[7][lane][r];
+                }
+            }
+            __syncthreads();
+        }
+        // x_p = D_p^{-T} (y_p - partial sums)
+#pragma unroll
+        for (int q = 0; q < DPT; q++) {
+            const int e = q * kSnThreads + tid;
+            Dt[(e >> 6) * (kP + 1) + (e & 63)] = dreg[q];
+        }
+        if (wv == 0) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) rhs[lane][r] = lane < kb ? yp[r] - s0[r] : T(0);
+        }
+        __syncthreads();
+        if (wv == 0 && lane < kb) {
+            T xt[NR];
+#pragma unroll
+            for (int r = 0; r < NR; r++) xt[r] = T(0);
+#pragma unroll 8
+            for (int i = 0; i < kb; i++) {
+                const T dti = Dt[lane * (kP + 1) + i];
+#pragma unroll
+                for (int r = 0; r < NR; r++) xt[r] += dti * rhs[i][r];
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                xs[c0 + lane][r] = xt[r];
+                Ys[vix<SOA>(b, d.first + c0 + lane, r0 + r, n, nrhs)] = xt[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batch-interleaved solves.  A group of 64 matrices shares one wave, lane =
 // matrix: every lane runs the same sequential substitution on its own
 // values, so every load of L or of a vector is 64 consecutive words and no
@@ -1331,6 +1559,86 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
     }
 }
 
+// Panel-solved supernodes of a level with one workgroup per (supernode,
+// matrix), when the batch fills the chip and the front vector fits in LDS.
+constexpr int kSnMinBatch = 16;
+template <typename T>
+size_t sn_static_lds(int nr) {
+    return sizeof(T) * (size_t(kSnWaves) * kSnRB * (kP + 1) + (kSnWaves + 1) * size_t(kP) * nr);
+}
+template <typename T>
+bool sn_fits(const SLaunch &l, const sc_numeric *N, int nrhs) {
+    const int nr = std::min(kMaxRhsPanel, nrhs);
+    const size_t front = size_t(l.maxc_pan) * nr * sizeof(T);
+    return N->batch >= kSnMinBatch && front + sn_static_lds<T>(nr) <= size_t(g_max_lds);
+}
+
+template <typename T, bool SOA>
+void sn_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const int B = N->batch;
+    const int64_t fvsize = int64_t(P->rows.size());
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    double f = 0.0, wds = 0.0, dw = 0.0, vw = 0.0;
+    for (const SPanel &pp : l.panels) {
+        f += pp.flops;
+        wds += pp.words;
+        dw += pp.dwords;
+        vw += pp.vwords;
+    }
+    N->prof.begin(KK_FwdPanel, f * nr * nb,
+                  ((wds + dw) * sz + (vw * sz + l.vw_pan * sz + l.ib_pan) * nr) * nb, st);
+    const dim3 g(unsigned(l.npan), unsigned(B));
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
+        const int nrr = std::min(kMaxRhsPanel, nrhs - r0);
+        const size_t lds = size_t(l.maxc_pan) * nrr * sizeof(T);
+#define SPCHOL_FWDSN(NRV)                                                                      \
+    hipLaunchKernelGGL((k_fwd_sn<T, NRV, SOA>), g, dim3(kSnThreadsF), lds, st, D->sn,            \
+                       D->slv_pan + l.pan0, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->dinv),   \
+                       P->dinv_size, as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active)
+        if (nrr == 1) SPCHOL_FWDSN(1);
+        else if (nrr == 2) SPCHOL_FWDSN(2);
+        else if (nrr == 3) SPCHOL_FWDSN(3);
+        else SPCHOL_FWDSN(4);
+#undef SPCHOL_FWDSN
+    }
+    N->prof.end(st);
+}
+
+template <typename T, bool SOA>
+void sn_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                 const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const int B = N->batch;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    double f = 0.0, wds = 0.0, dw = 0.0, vw = 0.0;
+    for (const SPanel &pp : l.panels) {
+        f += pp.flops;
+        wds += pp.words;
+        dw += pp.dwords;
+        vw += pp.vwords;
+    }
+    N->prof.begin(KK_BwdPanel, f * nr * nb, ((wds + dw) * sz + vw * sz * nr) * nb, st);
+    const dim3 g(unsigned(l.npan), unsigned(B));
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
+        const int nrr = std::min(kMaxRhsPanel, nrhs - r0);
+        const size_t lds = size_t(l.maxc_pan) * nrr * sizeof(T);
+#define SPCHOL_BWDSN(NRV)                                                                      \
+    hipLaunchKernelGGL((k_bwd_sn<T, NRV, SOA>), g, dim3(kSnThreads), lds, st, D->sn,             \
+                       D->slv_pan + l.pan0, r0, D->rows, L, P->Lsize, as<T>(N->dinv),            \
+                       P->dinv_size, as<T>(N->ws_y), P->n, nrhs, active)
+        if (nrr == 1) SPCHOL_BWDSN(1);
+        else if (nrr == 2) SPCHOL_BWDSN(2);
+        else if (nrr == 3) SPCHOL_BWDSN(3);
+        else SPCHOL_BWDSN(4);
+#undef SPCHOL_BWDSN
+    }
+    N->prof.end(st);
+}
+
 // Batch-interleaved solve (groups of 64 matrices, lane = matrix).
 template <typename T>
 hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double *b,
@@ -1396,11 +1704,17 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             }
             prof.end(st);
         }
-        if (l.npan > 0) panels_forward<T, true>(l, P, N, nrhs, nullptr, st);
+        if (l.npan > 0) {
+            if (sn_fits<T>(l, N, nrhs)) sn_forward<T, true>(l, P, N, nrhs, nullptr, st);
+            else panels_forward<T, true>(l, P, N, nrhs, nullptr, st);
+        }
     }
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
-        if (l.npan > 0) panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
+        if (l.npan > 0) {
+            if (sn_fits<T>(l, N, nrhs)) sn_backward<T, true>(l, P, N, nrhs, nullptr, st);
+            else panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
+        }
         if (by_rows(l)) {
             classes_backward<T, true>(l, P, N, nrhs, nullptr, st);
             continue;
@@ -1461,12 +1775,18 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
     for (const SLaunch &l : D->ssched) {
         launch_gather<T, false>(l, P, N, nrhs, active, st);
         classes_forward<T, false>(l, P, N, nrhs, active, st);
-        if (l.npan > 0) panels_forward<T, false>(l, P, N, nrhs, active, st);
+        if (l.npan > 0) {
+            if (sn_fits<T>(l, N, nrhs)) sn_forward<T, false>(l, P, N, nrhs, active, st);
+            else panels_forward<T, false>(l, P, N, nrhs, active, st);
+        }
     }
     // backward: levels descending
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
-        if (l.npan > 0) panels_backward<T, false>(l, P, N, nrhs, active, st);
+        if (l.npan > 0) {
+            if (sn_fits<T>(l, N, nrhs)) sn_backward<T, false>(l, P, N, nrhs, active, st);
+            else panels_backward<T, false>(l, P, N, nrhs, active, st);
+        }
         classes_backward<T, false>(l, P, N, nrhs, active, st);
     }
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
@@ -1554,7 +1874,31 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
     }
 }
 
-hipError_t spchol_solve_init() { return hipSuccess; }
+template <typename T, int NR>
+void sn_lds_limits() {
+    const int dyn = g_max_lds - int(sn_static_lds<T>(NR));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_sn<T, NR, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, g_max_lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fwd_sn<T, NR, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, g_max_lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_sn<T, NR, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bwd_sn<T, NR, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+}
+
+hipError_t spchol_solve_init() {
+    sn_lds_limits<double, 1>();
+    sn_lds_limits<double, 2>();
+    sn_lds_limits<double, 3>();
+    sn_lds_limits<double, 4>();
+    sn_lds_limits<float, 1>();
+    sn_lds_limits<float, 2>();
+    sn_lds_limits<float, 3>();
+    sn_lds_limits<float, 4>();
+    (void)hipGetLastError();  // an attribute the runtime refuses keeps the default
+    return hipSuccess;
+}
 
 hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
     if (N->dtype == SC_F64) return dinv_impl<double>(P, N, st);
