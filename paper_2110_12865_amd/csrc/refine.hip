@@ -72,6 +72,43 @@ __global__ __launch_bounds__(256) void k_apply(
         Y[base + r * ldb + i] = mode ? B[base + r * ldb + i] - t[r] : t[r];
 }
 
+// Y1 = B - A X1 and Y2 = A X2 in one pass over A (each sum in the order
+// k_apply uses), for the matrices with active[matrix] != 0.
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply2(
+    const int64_t *__restrict__ ptr, const int64_t *__restrict__ sptr,
+    const int32_t *__restrict__ col, const double *__restrict__ vc, int64_t nsell,
+    const double *__restrict__ B, const double *__restrict__ X1, double *__restrict__ Y1,
+    const double *__restrict__ X2, double *__restrict__ Y2, int64_t ldb, int64_t n, int nrhs,
+    int r0, const int32_t *__restrict__ active) {
+    const int b = blockIdx.x;
+    if (active && !active[b]) return;
+    const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e0 = sptr[i / kSellRows] + i % kSellRows;
+    const int len = int(ptr[i + 1] - ptr[i]);
+    const double *v = vc + int64_t(b) * nsell + e0;
+    const int32_t *cl = col + e0;
+    const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
+    double t1[NR], t2[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) t1[r] = t2[r] = 0.0;
+    for (int k = 0; k < len; k++) {
+        const double a = v[int64_t(k) * kSellRows];
+        const int64_t j = cl[int64_t(k) * kSellRows];
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            t1[r] += a * X1[base + r * ldb + j];
+            t2[r] += a * X2[base + r * ldb + j];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        Y1[base + r * ldb + i] = B[base + r * ldb + i] - t1[r];
+        Y2[base + r * ldb + i] = t2[r];
+    }
+}
+
 // Block of vector element i (colblk is null for a plan of one block).
 __device__ inline int seg_of(int br, int nblk, const int32_t *colblk, int64_t i) {
     return br * nblk + (colblk ? colblk[i] : 0);
@@ -134,7 +171,8 @@ __device__ inline double block_sum(double v, double *red) {
     return t;
 }
 
-// nq = 3: partial sums of r.r, b.b, x.x (A = r, B = b, C = x);
+// nq = 3: partial sums of r.r, b.b, x.x (A = r, B = b, C = x); nq = 4: r.r
+// and x.x only (slots 0 and 2; b.b does not change between tests);
 // nq = 2: partial sums of A.B and B.C; nq = 1: partial sum of A.B.
 // part[(seg * kRB + slice) * 3 + q].
 __global__ __launch_bounds__(256) void k_sums(
@@ -151,12 +189,19 @@ __global__ __launch_bounds__(256) void k_sums(
     const int64_t len = (nr + kRB - 1) / kRB;
     const int64_t i0 = r0 + slice * len, i1 = min(r0 + nr, i0 + len);
     const double *a = A + int64_t(br) * ldb;
-    const double *bb = Bv + int64_t(br) * ldb;
+    const double *bb = nq == 4 ? A + int64_t(br) * ldb : Bv + int64_t(br) * ldb;
     const double *cc = nq >= 2 ? C + int64_t(br) * ldb : nullptr;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        const double ai = a[i], bi = bb[i];
+        const double ai = a[i];
+        if (nq == 4) {
+            const double ci = cc[i];
+            s0 += ai * ai;
+            s2 += ci * ci;
+            continue;
+        }
+        const double bi = bb[i];
         if (nq == 3) {
             const double ci = cc[i];
             s0 += ai * ai;
@@ -171,7 +216,10 @@ __global__ __launch_bounds__(256) void k_sums(
     }
     double *o = part + (int64_t(sg) * kRB + slice) * 3;
     const double t0 = block_sum(s0, red);
-    if (nq == 3) {
+    if (nq == 4) {
+        const double t2 = block_sum(s2, red);
+        if (threadIdx.x == 0) { o[0] = t0; o[2] = t2; }
+    } else if (nq == 3) {
         const double t1 = block_sum(s1, red);
         const double t2 = block_sum(s2, red);
         if (threadIdx.x == 0) { o[0] = t0; o[1] = t1; o[2] = t2; }
@@ -203,6 +251,8 @@ __global__ void k_sums_final(const double *__restrict__ part, int nseg, int per_
 // stat layout per system: [iters, clause, relres, rnorm, bnorm, xnorm].
 // conv[seg] = 1 once the system passes; a system that passed earlier (and
 // is no longer updated) keeps its record.
+// iter > 0 takes ||b||_2 from the record of the first test (part holds no
+// b.b then).
 __global__ void k_check(const double *__restrict__ part, int nseg, int nrhs, int nblk,
                         const double *__restrict__ anorm, double tol, int iter,
                         const int32_t *__restrict__ active, int32_t *__restrict__ conv,
@@ -215,10 +265,11 @@ __global__ void k_check(const double *__restrict__ part, int nseg, int nrhs, int
     for (int q = 0; q < kRB; q++) {
         const double *o = part + (int64_t(sg) * kRB + q) * 3;
         a += o[0];
-        c += o[1];
+        if (iter == 0) c += o[1];
         d += o[2];
     }
-    const double rn = sqrt(a), bn = sqrt(c), xn = sqrt(d);
+    const double rn = sqrt(a), xn = sqrt(d);
+    const double bn = iter == 0 ? sqrt(c) : stat[int64_t(sg) * 6 + 4];
     const double relres = bn > 0.0 ? rn / bn : rn;
     int clause = 0;
     if (relres <= tol) clause = 1;
@@ -353,6 +404,26 @@ void apply_A(const sc_plan *P, const double *vc, const double *B,
     }
 }
 
+// Y1 = B - A X1 and Y2 = A X2 with one read of A.
+void apply_A2(const sc_plan *P, const double *vc, const double *B, const double *X1, double *Y1,
+              const double *X2, double *Y2, int64_t ldb, int batch, int nrhs,
+              const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const int64_t nsell = P->sell_ptr.back();
+    const dim3 grid(unsigned(batch), unsigned((P->n + 255) / 256));
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int nr = std::min(4, nrhs - r0);
+#define SPCHOL_APPLY2(NR)                                                                  \
+    hipLaunchKernelGGL(k_apply2<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->sell_ptr,       \
+                       D->sell_col, vc, nsell, B, X1, Y1, X2, Y2, ldb, P->n, nrhs, r0, active)
+        if (nr == 1) SPCHOL_APPLY2(1);
+        else if (nr == 2) SPCHOL_APPLY2(2);
+        else if (nr == 3) SPCHOL_APPLY2(3);
+        else SPCHOL_APPLY2(4);
+#undef SPCHOL_APPLY2
+    }
+}
+
 hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                             int64_t ldv, const double *b, double *x, int32_t nrhs,
                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
@@ -385,9 +456,9 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
         prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
         apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st);
         prof.end(st);
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
-        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, 3, ldb,
-                           D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, it == 0 ? 3 : 4,
+                           ldb, D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
         prof.end(st);
         hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
                            tol, it, W.active, W.conv, W.stat);
@@ -448,14 +519,20 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
-    // true residual b - A x into res, stop test
-    auto check = [&](int it, double *res) -> hipError_t {
-        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
-        apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st);
+    // true residual b - A x into res, stop test; with pnext, q = A pnext in
+    // the same pass over A
+    auto check = [&](int it, double *res, const double *pnext) -> hipError_t {
+        if (pnext) {
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 5), st);
+            apply_A2(P, W.vc, b, x, res, pnext, q, ldb, batch, nrhs, W.active, st);
+        } else {
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
+            apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st);
+        }
         prof.end(st);
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 3), st);
-        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, res, b, x, 3, ldb,
-                           D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
+        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
+        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, res, b, x, it == 0 ? 3 : 4,
+                           ldb, D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
         prof.end(st);
         hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
                            tol, it, W.active, W.conv, W.stat);
@@ -486,25 +563,30 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
                            out, out2);
     };
-    e = check(0, r);  // r_0 = b - A x_0
+    e = check(0, r, nullptr);  // r_0 = b - A x_0
     if (e != hipSuccess) return e;
     if (nact > 0 && maxit > 0) {
         e = spchol_solve_run(P, N, pv, nrhs, ldb, st, W.active, r);  // p_1 = z_0 = M^{-1} r_0
         if (e != hipSuccess) return e;
         dots(r, pv, rz0);
         double *rz = rz0, *rzn = rz1;
+        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st);
+        apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);  // q_1 = A p_1
+        prof.end(st);
         for (int it = 1; it <= maxit; it++) {
-            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st);
-            apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);
-            prof.end(st);
             dots(pv, q, pq);
             prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 6), st);
             hipLaunchKernelGGL(k_cg_xr, vgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
                                nblk, colblk, W.active, W.conv, rz, pq);
             prof.end(st);
-            e = check(it, rt);
-            if (e != hipSuccess) return e;
-            if (nact == 0 || it == maxit) break;
+            if (it == maxit) {
+                e = check(it, rt, nullptr);
+                if (e != hipSuccess) return e;
+                break;
+            }
+            // the next direction comes before this step's test, so that the
+            // test's product and q = A p share one pass over A (a system that
+            // passes the test is frozen from here on; its new p is unused)
             e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active, r);
             if (e != hipSuccess) return e;
             dots2(r, z, q, rzn, zq);
@@ -513,6 +595,9 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                                colblk, W.active, W.conv, zq, pq);
             prof.end(st);
             std::swap(rz, rzn);
+            e = check(it, rt, pv);
+            if (e != hipSuccess) return e;
+            if (nact == 0) break;
         }
     }
     if (!sync) return hipGetLastError();
