@@ -718,7 +718,7 @@ sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowi
     hipStream_t st = static_cast<hipStream_t>(stream);
     // candidates: front-kernel threshold x amalgamation width x solve layout
     std::vector<sc_options> cand;
-    const int32_t small_fronts[] = {32, 64, 128};
+    const int32_t small_fronts[] = {32, 64, 128, 192};
     const int32_t relax_cols[] = {4, 16};
     for (int32_t sf : small_fronts)
         for (int32_t rc : relax_cols)

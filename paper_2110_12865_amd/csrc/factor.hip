@@ -75,83 +75,6 @@ __device__ inline void wave_fence_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Small fronts, one wave per (front, matrix): the whole front sits in LDS
-// (c_max x c_max scalars per wave, `per` fronts per workgroup); the wave
-// scatters A's columns, adds the children's update blocks, factors the first
-// w columns right-looking and writes L's block and the update block back.
-template <typename T>
-__global__ __launch_bounds__(256) void k_front_wave(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int per,
-    int cmax, const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
-    const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
-    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
-    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
-    int32_t *__restrict__ info, int nblk) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (wv >= per) return;
-    const int e = blockIdx.x * per + wv;
-    if (e >= nlist) return;
-    T *F = reinterpret_cast<T *>(smem_raw) + size_t(wv) * cmax * cmax;
-    const int s = list[e];
-    const int b = blockIdx.y;
-    const SnDesc d = sn[s];
-    const int c = d.c, w = d.w, m = d.m;
-    L += int64_t(b) * Lsize;
-    U += int64_t(b) * Usize;
-    vals += int64_t(b) * ldv;
-    for (int q = lane; q < c * c; q += 64) F[q] = T(0);
-    wave_fence_sync();
-    const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
-    for (int64_t q = a0 + lane; q < a1; q += 64) F[aoff[q]] = T(vals[avidx[q]]);
-    for (int q = d.chbeg; q < d.chend; q++) {
-        const SnDesc cd = sn[chlist[q]];
-        const int32_t *rm = relmap + cd.relptr;
-        const T *Uc = U + cd.uoff;
-        const int mc = cd.m;  // at most c
-        wave_fence_sync();
-        if (mc <= 64) {  // lane i holds the map of child row i
-            const int rmi = lane < mc ? rm[lane] : 0;
-#pragma unroll 4
-            for (int jc = 0; jc < mc; jc++) {
-                const int tcol = __builtin_amdgcn_readlane(rmi, jc) * c;
-                if (lane >= jc && lane < mc) F[tcol + rmi] += Uc[int64_t(jc) * mc + lane];
-            }
-        } else {
-            for (int jc = 0; jc < mc; jc++) {
-                const int tcol = rm[jc] * c;
-                for (int i = jc + lane; i < mc; i += 64) F[tcol + rm[i]] += Uc[int64_t(jc) * mc + i];
-            }
-        }
-    }
-    wave_fence_sync();
-    for (int j = 0; j < w; j++) {
-        T djj = F[j * c + j];
-        const bool bad = !(djj > T(0));
-        if (bad) djj = T(1);
-        const T ljj = dsqrt(djj);
-        wave_fence_sync();
-        if (lane == 0) {
-            F[j * c + j] = ljj;
-            if (bad) atomicMin(info + int64_t(b) * nblk + d.blk, d.first - d.bcol0 + j + 1);
-        }
-        for (int i = j + 1 + lane; i < c; i += 64) F[j * c + i] /= ljj;
-        wave_fence_sync();
-        const T *cj = F + j * c;
-        for (int t = j + 1; t < c; t++) {
-            const T ltj = cj[t];
-            for (int i = t + lane; i < c; i += 64) F[t * c + i] -= cj[i] * ltj;
-        }
-        wave_fence_sync();
-    }
-    T *Ls = L + d.loff;
-    for (int j = 0; j < w; j++)
-        for (int i = j + lane; i < c; i += 64) Ls[int64_t(j) * c + i] = F[j * c + i];
-    T *Us = U + d.uoff;
-    for (int j = 0; j < m; j++)
-        for (int i = j + lane; i < m; i += 64) Us[int64_t(j) * m + i] = F[(w + j) * c + w + i];
-}
-
 // Broadcast lane `src` (wave-uniform) of v to the whole wave.
 __device__ inline double rl(double v, int src) {
     const long long u = __double_as_longlong(v);
@@ -162,6 +85,107 @@ __device__ inline double rl(double v, int src) {
 }
 __device__ inline float rl(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
+// Fronts of 64 < c <= kFrontWgMaxC rows, one workgroup of 256 threads per
+// (front, matrix): the front's lower triangle is packed in LDS (column t
+// from t c - t (t - 1) / 2, rows t .. c - 1).  A's entries are placed, the
+// children's update blocks added (children in order; a child's entries
+// land on distinct positions), the first w columns factored right-looking
+// (each step scales column j and updates the whole trailing triangle, the
+// rest of L's columns and the update block alike), and L's block and the
+// update block written back.
+constexpr int kFrontWgMaxC = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_front_wg(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
+    const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
+    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
+    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
+    int32_t *__restrict__ info, int nblk) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *F = reinterpret_cast<T *>(smem_raw);
+    __shared__ int32_t rm[kFrontWgMaxC];  // relative map of the current child
+    const int s = list[blockIdx.x];
+    const int b = blockIdx.y;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w, m = d.m;
+    L += int64_t(b) * Lsize;
+    U += int64_t(b) * Usize;
+    vals += int64_t(b) * ldv;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    auto cb = [c](int t) { return t * c - t * (t - 1) / 2; };  // packed offset of (t, t)
+    const int ntri = c * (c + 1) / 2;
+    for (int q = tid; q < ntri; q += 256) F[q] = T(0);
+    __syncthreads();
+    const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
+    for (int64_t q = a0 + tid; q < a1; q += 256) {
+        const int o = aoff[q];  // (column - first) c + row position
+        const int j = o / c, i = o - j * c;
+        F[cb(j) + i - j] = T(vals[avidx[q]]);
+    }
+    for (int q = d.chbeg; q < d.chend; q++) {
+        const SnDesc cd = sn[chlist[q]];
+        const int mc = cd.m;
+        __syncthreads();  // the previous child's additions (and map reads) are done
+        for (int i = tid; i < mc; i += 256) rm[i] = relmap[cd.relptr + i];
+        __syncthreads();
+        const T *Uc = U + cd.uoff;
+        // the child's block as mc x mc column-major, upper part skipped;
+        // four entries per thread in flight at once
+        const int ne = mc * mc;
+        int jc = tid / mc, ic = tid - jc * mc;
+        for (int e0 = 0; e0 < ne; e0 += 4 * 256) {
+            T v[4];
+            int pos[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const bool ok = e0 + u * 256 + tid < ne && ic >= jc;
+                v[u] = Uc[ok ? int64_t(jc) * mc + ic : 0];
+                pos[u] = ok ? cb(rm[jc]) + rm[ic] - rm[jc] : -1;
+                ic += 256;
+                while (ic >= mc) { ic -= mc; jc++; }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (pos[u] >= 0) F[pos[u]] += v[u];
+        }
+    }
+    __syncthreads();
+    const int64_t infoidx = int64_t(b) * nblk + d.blk;
+    for (int j = 0; j < w; j++) {
+        const int cj = cb(j);
+        T djj = F[cj];
+        const bool bad = !(djj > T(0));
+        if (bad) djj = T(1);
+        const T ljj = dsqrt(djj), rinv = T(1) / ljj;
+        __syncthreads();  // every thread has read the pivot
+        if (tid == 0) {
+            F[cj] = ljj;
+            if (bad) atomicMin(info + infoidx, d.first - d.bcol0 + j + 1);
+        }
+        for (int i = j + 1 + tid; i < c; i += 256) F[cj + i - j] *= rinv;
+        __syncthreads();
+        // trailing triangle: wave wv takes columns j + 1 + wv + 4 u, lanes rows
+        for (int t = j + 1 + wv; t < c; t += 4) {
+            const T ltj = F[cj + t - j];
+            const int ct = cb(t);
+            for (int i = t + lane; i < c; i += 64) F[ct + i - t] -= F[cj + i - j] * ltj;
+        }
+        __syncthreads();
+    }
+    T *Ls = L + d.loff;
+    for (int j = wv; j < w; j += 4) {
+        const int cj = cb(j);
+        for (int i = lane; i < c; i += 64) Ls[int64_t(j) * c + i] = i >= j ? F[cj + i - j] : T(0);
+    }
+    T *Us = U + d.uoff;
+    for (int t = wv; t < m; t += 4) {
+        const int ct = cb(w + t);
+        for (int i = t + lane; i < m; i += 64) Us[int64_t(t) * m + i] = F[ct + i - t];
+    }
 }
 
 // Value of lane `src` of the calling lane's segment of G lanes (G == 64:
@@ -683,7 +707,7 @@ void set_lds_limits(int big) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trsm<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_front_wave<T>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_front_wg<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_assemble_cols<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
@@ -717,8 +741,11 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
     for (int32_t l = 0; l < P->nlevels; l++) {
         const int32_t s0 = P->lvl_small_ptr[l], s1 = P->lvl_small_ptr[l + 1];
         if (s1 > s0) {
-            FLaunch f{FLaunch::Small, l, 0, 0, 0, s0, s1 - s0, s1 - s0,
-                      P->lvl_small_maxc[l] * P->lvl_small_maxc[l], 0.0, 0.0, 0.0};
+            // k = the level's widest front; lds = its packed triangle (in
+            // scalars) when it is too tall for registers
+            const int cm = P->lvl_small_maxc[l];
+            FLaunch f{FLaunch::Small, l, cm, 0, 0, s0, s1 - s0, s1 - s0,
+                      cm <= 64 ? 0 : cm * (cm + 1) / 2, 0.0, 0.0, 0.0};
             for (int32_t e = s0; e < s1; e++) {
                 const SnDesc &d = P->sn[P->lvl_small[e]];
                 f.flops += front_flops(d.c, d.w);
@@ -808,7 +835,7 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, st);
         switch (f.kind) {
         case FLaunch::Small: {
-            const int cmax = int(std::lround(std::sqrt(double(f.lds))));
+            const int cmax = f.k;
             if (cmax <= 64) {
                 // fronts in registers, one segment of G lanes per (front,
                 // matrix), 64 / G matrices per wave, four fronts per workgroup
@@ -826,14 +853,12 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
 #undef SPCHOL_FRONT_REG
                 break;
             }
-            // wider fronts: one wave per front out of LDS
-            const size_t per_lds = size_t(f.lds) * sizeof(T);
-            const int per = int(std::max<size_t>(1, std::min<size_t>(4, g_max_lds / per_lds)));
-            hipLaunchKernelGGL(k_front_wave<T>, dim3(unsigned((f.nlist + per - 1) / per), B),
-                               dim3(64 * per), per_lds * per, st, D->sn, D->lvl_small + f.list0,
-                               f.nlist, per, cmax, D->relmap, D->chlist, D->acolptr, D->aoff,
-                               D->avidx, vals, ldv, L, P->Lsize, U, P->Usize, N->info,
-                               P->nblk);
+            // wider fronts: one workgroup per (front, matrix), packed in LDS
+            if (cmax > kFrontWgMaxC) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_front_wg<T>, dim3(unsigned(f.nlist), B), dim3(256),
+                               size_t(cmax) * (cmax + 1) / 2 * sizeof(T), st, D->sn,
+                               D->lvl_small + f.list0, D->relmap, D->chlist, D->acolptr, D->aoff,
+                               D->avidx, vals, ldv, L, P->Lsize, U, P->Usize, N->info, P->nblk);
             break;
         }
         case FLaunch::Assemble: {

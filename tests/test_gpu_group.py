@@ -180,7 +180,7 @@ def test_autotuner_picks_a_measured_candidate():
     vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
     b = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
     best, table = S.autotune(p.colptr, p.rowind, w.perm, vals, b, "f32", solves_per_factor=3.0)
-    assert len(table) == 12  # 3 thresholds x 2 widths x 2 layouts (batch >= 16)
+    assert len(table) == 16  # 4 thresholds x 2 widths x 2 layouts (batch >= 16)
     assert all(t["factor_ms"] > 0 and t["solve_ms"] > 0 for t in table)
     scores = [t["score"] for t in table]
     k = int(np.argmin(scores))

@@ -37,9 +37,12 @@ def _cases():
          {"small_front": 1}),
         ("grid2d_40x40_tiled_only", lambda: W.small_grid((40, 40), "natural", seed=18),
          {"small_front": 1}),
-        # bigger fronts in the one-workgroup LDS kernel
+        # bigger fronts in the one-workgroup LDS kernel (packed triangle)
         ("grid3d_12^3_lds_big", lambda: W.small_grid((12, 12, 12), "nd", seed=19),
          {"small_front": 100}),
+        ("random_200_lds_whole", lambda: W.random_spd(200, 0.5, seed=23), {"small_front": 200}),
+        ("grid3d_16x15x14_lds_192", lambda: W.small_grid((16, 15, 14), "nd", seed=24),
+         {"small_front": 192}),
         # fundamental supernodes only
         ("grid3d_9^3_norelax", lambda: W.small_grid((9, 9, 9), "nd", seed=20), {"relax": 0}),
         ("n1", lambda: W.random_spd(1, 0.0, seed=21), {}),
@@ -99,9 +102,11 @@ def test_diagonal_matrix_bit_exact():
     assert np.allclose(x[0, 0], w.b[0, 0] / d, rtol=2e-16 * 4, atol=0)
 
 
-@pytest.mark.parametrize("opts", [{}, {"small_front": 1}], ids=["lds", "tiled"])
-def test_not_spd_info_matches_oracle(opts):
-    w = W.small_grid((20, 20), "nd", seed=31)
+@pytest.mark.parametrize("dims,opts", [((20, 20), {}), ((20, 20), {"small_front": 1}),
+                                       ((11, 11, 11), {"small_front": 180})],
+                         ids=["registers", "tiled", "workgroup"])
+def test_not_spd_info_matches_oracle(dims, opts):
+    w = W.small_grid(dims, "nd", seed=31)
     p = w.pattern
     vals = w.values.copy()
     # break two pivots; the smallest failing elimination step must be reported
@@ -170,12 +175,13 @@ def test_multiple_rhs():
         assert oracle.forward_error(x[0, r], xo[r]) <= TOL_X
 
 
-def test_fp32_factor_accuracy():
+@pytest.mark.parametrize("opts", [{}, {"small_front": 192}], ids=["default", "workgroup"])
+def test_fp32_factor_accuracy(opts):
     """FP32 factor (FP32 accumulation) and FP32 solve: the factor and the
     solution match the oracle to FP32 accuracy (no parity claim at FP64
     level)."""
     w = W.small_grid((16, 16, 16), "nd", seed=45)
-    plan, num, info, x = run_library(w, "f32")
+    plan, num, info, x = run_library(w, "f32", opts=opts)
     sym, Lx, _, xo = oracle_run(w)
     Lg = num.get_columns(0, all_columns(w.pattern.n))
     ferr = oracle.factor_error(sym.Lcolptr, Lg, Lx)
