@@ -64,7 +64,9 @@ typedef struct {
     double relax_zeros;   /* otherwise merge while the fraction of stored
                              zeros of the merged block stays below this   */
     int32_t small_front;  /* fronts with at most this many rows run in one
-                             workgroup; larger ones use the tiled kernels
+                             workgroup (up to 256 rows, and only if the
+                             front fits the workgroup's LDS in FP64);
+                             larger ones use the tiled kernels
                              (0 = library default)                         */
     int32_t soa_min_batch; /* numeric objects with at least this many
                              matrices solve in the batch-interleaved layout

@@ -447,7 +447,8 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         for (int32_t s = 0; s < ns; s++) {
             const SnDesc &d = P->sn[s];
             bya[d.level].push_back(s);
-            if (d.c <= small_front) bys[d.level].push_back(s);
+            if (d.c <= small_front && (d.c <= 64 || front_wg_fits(d.c, d.w)))
+                bys[d.level].push_back(s);
             else byb[d.level].push_back(s);
         }
         P->lvl_small_ptr.assign(nlev + 1, 0);

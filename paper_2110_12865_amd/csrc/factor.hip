@@ -87,107 +87,6 @@ __device__ inline float rl(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-// Fronts of 64 < c <= kFrontWgMaxC rows, one workgroup of 256 threads per
-// (front, matrix): the front's lower triangle is packed in LDS (column t
-// from t c - t (t - 1) / 2, rows t .. c - 1).  A's entries are placed, the
-// children's update blocks added (children in order; a child's entries
-// land on distinct positions), the first w columns factored right-looking
-// (each step scales column j and updates the whole trailing triangle, the
-// rest of L's columns and the update block alike), and L's block and the
-// update block written back.
-constexpr int kFrontWgMaxC = 256;
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_front_wg(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
-    const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
-    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
-    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
-    int32_t *__restrict__ info, int nblk) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *F = reinterpret_cast<T *>(smem_raw);
-    __shared__ int32_t rm[kFrontWgMaxC];  // relative map of the current child
-    const int s = list[blockIdx.x];
-    const int b = blockIdx.y;
-    const SnDesc d = sn[s];
-    const int c = d.c, w = d.w, m = d.m;
-    L += int64_t(b) * Lsize;
-    U += int64_t(b) * Usize;
-    vals += int64_t(b) * ldv;
-    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    auto cb = [c](int t) { return t * c - t * (t - 1) / 2; };  // packed offset of (t, t)
-    const int ntri = c * (c + 1) / 2;
-    for (int q = tid; q < ntri; q += 256) F[q] = T(0);
-    __syncthreads();
-    const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
-    for (int64_t q = a0 + tid; q < a1; q += 256) {
-        const int o = aoff[q];  // (column - first) c + row position
-        const int j = o / c, i = o - j * c;
-        F[cb(j) + i - j] = T(vals[avidx[q]]);
-    }
-    for (int q = d.chbeg; q < d.chend; q++) {
-        const SnDesc cd = sn[chlist[q]];
-        const int mc = cd.m;
-        __syncthreads();  // the previous child's additions (and map reads) are done
-        for (int i = tid; i < mc; i += 256) rm[i] = relmap[cd.relptr + i];
-        __syncthreads();
-        const T *Uc = U + cd.uoff;
-        // the child's block as mc x mc column-major, upper part skipped;
-        // four entries per thread in flight at once
-        const int ne = mc * mc;
-        int jc = tid / mc, ic = tid - jc * mc;
-        for (int e0 = 0; e0 < ne; e0 += 4 * 256) {
-            T v[4];
-            int pos[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const bool ok = e0 + u * 256 + tid < ne && ic >= jc;
-                v[u] = Uc[ok ? int64_t(jc) * mc + ic : 0];
-                pos[u] = ok ? cb(rm[jc]) + rm[ic] - rm[jc] : -1;
-                ic += 256;
-                while (ic >= mc) { ic -= mc; jc++; }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-                if (pos[u] >= 0) F[pos[u]] += v[u];
-        }
-    }
-    __syncthreads();
-    const int64_t infoidx = int64_t(b) * nblk + d.blk;
-    for (int j = 0; j < w; j++) {
-        const int cj = cb(j);
-        T djj = F[cj];
-        const bool bad = !(djj > T(0));
-        if (bad) djj = T(1);
-        const T ljj = dsqrt(djj), rinv = T(1) / ljj;
-        __syncthreads();  // every thread has read the pivot
-        if (tid == 0) {
-            F[cj] = ljj;
-            if (bad) atomicMin(info + infoidx, d.first - d.bcol0 + j + 1);
-        }
-        for (int i = j + 1 + tid; i < c; i += 256) F[cj + i - j] *= rinv;
-        __syncthreads();
-        // trailing triangle: wave wv takes columns j + 1 + wv + 4 u, lanes rows
-        for (int t = j + 1 + wv; t < c; t += 4) {
-            const T ltj = F[cj + t - j];
-            const int ct = cb(t);
-            for (int i = t + lane; i < c; i += 64) F[ct + i - t] -= F[cj + i - j] * ltj;
-        }
-        __syncthreads();
-    }
-    T *Ls = L + d.loff;
-    for (int j = wv; j < w; j += 4) {
-        const int cj = cb(j);
-        for (int i = lane; i < c; i += 64) Ls[int64_t(j) * c + i] = i >= j ? F[cj + i - j] : T(0);
-    }
-    T *Us = U + d.uoff;
-    for (int t = wv; t < m; t += 4) {
-        const int ct = cb(w + t);
-        for (int i = t + lane; i < m; i += 64) Us[int64_t(t) * m + i] = F[ct + i - t];
-    }
-}
-
 // Value of lane `src` of the calling lane's segment of G lanes (G == 64:
 // the whole wave, src wave-uniform).
 template <int G, typename T>
@@ -523,6 +422,132 @@ __device__ inline void tile_pos(int a, int q, int r, int &j, int &i) {
     i = (wv >> 1) * 32 + 16 * q + (lane & 15);
 }
 
+// Fronts of 64 < c <= kFrontWgMaxC rows, one workgroup of 256 threads per
+// (front, matrix).  The front's lower triangle is packed in LDS (column t
+// from t c - t (t - 1) / 2, rows t .. c - 1): A's entries are placed and the
+// children's update blocks added (children in order; a child's entries land
+// on distinct positions).  The first w columns are factored right-looking
+// among themselves; L's block is written out and its rows below the
+// diagonal block are copied, per 64-row tile, to a [k][64] layout; the update
+// block is then the assembled values minus L21 L21^T, formed tile by tile on
+// the matrix cores and written straight to U.
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_front_wg(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int32_t *__restrict__ relmap, const int32_t *__restrict__ chlist,
+    const int64_t *__restrict__ acolptr, const int32_t *__restrict__ aoff,
+    const int64_t *__restrict__ avidx, const double *__restrict__ vals, int64_t ldv,
+    T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize,
+    int32_t *__restrict__ info, int nblk) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *F = reinterpret_cast<T *>(smem_raw);
+    __shared__ int32_t rm[kFrontWgMaxC];  // relative map of the current child
+    const int s = list[blockIdx.x];
+    const int b = blockIdx.y;
+    const SnDesc d = sn[s];
+    const int c = d.c, w = d.w, m = d.m;
+    L += int64_t(b) * Lsize;
+    U += int64_t(b) * Usize;
+    vals += int64_t(b) * ldv;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    auto cb = [c](int t) { return t * c - t * (t - 1) / 2; };  // packed offset of (t, t)
+    const int ntri = c * (c + 1) / 2;
+    const int wr = (w + 3) & ~3;                  // K of the products, padded
+    const int nt = (m + kTile - 1) / kTile;       // 64-row tiles of the update block
+    T *Lt = F + ntri;                             // [tile][k][64] rows of L21
+    for (int q = tid; q < ntri; q += 256) F[q] = T(0);
+    __syncthreads();
+    const int64_t a0 = acolptr[d.first], a1 = acolptr[d.first + w];
+    for (int64_t q = a0 + tid; q < a1; q += 256) {
+        const int o = aoff[q];  // (column - first) c + row position
+        const int j = o / c, i = o - j * c;
+        F[cb(j) + i - j] = T(vals[avidx[q]]);
+    }
+    for (int q = d.chbeg; q < d.chend; q++) {
+        const SnDesc cd = sn[chlist[q]];
+        const int mc = cd.m;
+        __syncthreads();  // the previous child's additions (and map reads) are done
+        for (int i = tid; i < mc; i += 256) rm[i] = relmap[cd.relptr + i];
+        __syncthreads();
+        const T *Uc = U + cd.uoff;
+        // the child's block as mc x mc column-major, upper part skipped;
+        // four entries per thread in flight at once
+        const int ne = mc * mc;
+        int jc = tid / mc, ic = tid - jc * mc;
+        for (int e0 = 0; e0 < ne; e0 += 4 * 256) {
+            T v[4];
+            int pos[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const bool ok = e0 + u * 256 + tid < ne && ic >= jc;
+                v[u] = Uc[ok ? int64_t(jc) * mc + ic : 0];
+                pos[u] = ok ? cb(rm[jc]) + rm[ic] - rm[jc] : -1;
+                ic += 256;
+                while (ic >= mc) { ic -= mc; jc++; }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (pos[u] >= 0) F[pos[u]] += v[u];
+        }
+    }
+    __syncthreads();
+    // the first w columns, right-looking among themselves
+    const int64_t infoidx = int64_t(b) * nblk + d.blk;
+    for (int j = 0; j < w; j++) {
+        const int cj = cb(j);
+        T djj = F[cj];
+        const bool bad = !(djj > T(0));
+        if (bad) djj = T(1);
+        const T ljj = dsqrt(djj), rinv = T(1) / ljj;
+        __syncthreads();  // every thread has read the pivot
+        if (tid == 0) {
+            F[cj] = ljj;
+            if (bad) atomicMin(info + infoidx, d.first - d.bcol0 + j + 1);
+        }
+        for (int i = j + 1 + tid; i < c; i += 256) F[cj + i - j] *= rinv;
+        __syncthreads();
+        for (int t = j + 1 + wv; t < w; t += 4) {
+            const T ltj = F[cj + t - j];
+            const int ct = cb(t);
+            for (int i = t + lane; i < c; i += 64) F[ct + i - t] -= F[cj + i - j] * ltj;
+        }
+        __syncthreads();
+    }
+    // L's block out; rows w .. c - 1 of its columns into the tiles
+    T *Ls = L + d.loff;
+    for (int j = wv; j < w; j += 4) {
+        const int cj = cb(j);
+        for (int i = lane; i < c; i += 64) Ls[int64_t(j) * c + i] = i >= j ? F[cj + i - j] : T(0);
+    }
+    for (int e = tid; e < nt * wr * kTile; e += 256) {
+        const int tile = e / (wr * kTile), r = e - tile * wr * kTile;
+        const int k = r / kTile, i = tile * kTile + (r & (kTile - 1));
+        Lt[e] = (k < w && i < m) ? F[cb(k) + w + i - k] : T(0);
+    }
+    __syncthreads();
+    // update block: U[i][t] = F[w + i][w + t] - sum_k L21[i][k] L21[t][k]
+    T *Us = U + d.uoff;
+    for (int TI = 0; TI < nt; TI++)
+        for (int TJ = 0; TJ <= TI; TJ++) {
+            typename Mma<T>::acc_t acc[2][2];
+            acc_zero<T>(acc);
+            tile_mma(Lt + TJ * wr * kTile, Lt + TI * wr * kTile, wr, acc);
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int q = 0; q < 2; q++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        int jj, ii;
+                        tile_pos<T>(a, q, r, jj, ii);
+                        const int col = TJ * kTile + jj, row = TI * kTile + ii;
+                        if (row < m && col <= row)
+                            Us[int64_t(col) * m + row] = F[cb(w + col) + row - col] - acc[a][q][r];
+                    }
+        }
+}
+
 // Diagonal block of panel k of each large front: factor and invert (one
 // workgroup per front and matrix).
 template <typename T>
@@ -744,8 +769,12 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
             // k = the level's widest front; lds = its packed triangle (in
             // scalars) when it is too tall for registers
             const int cm = P->lvl_small_maxc[l];
-            FLaunch f{FLaunch::Small, l, cm, 0, 0, s0, s1 - s0, s1 - s0,
-                      cm <= 64 ? 0 : cm * (cm + 1) / 2, 0.0, 0.0, 0.0};
+            int wlds = 0;
+            if (cm > 64)
+                for (int32_t e = s0; e < s1; e++)
+                    wlds = std::max(wlds, front_wg_lds(P->sn[P->lvl_small[e]].c,
+                                                       P->sn[P->lvl_small[e]].w));
+            FLaunch f{FLaunch::Small, l, cm, 0, 0, s0, s1 - s0, s1 - s0, wlds, 0.0, 0.0, 0.0};
             for (int32_t e = s0; e < s1; e++) {
                 const SnDesc &d = P->sn[P->lvl_small[e]];
                 f.flops += front_flops(d.c, d.w);
@@ -856,7 +885,7 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
             // wider fronts: one workgroup per (front, matrix), packed in LDS
             if (cmax > kFrontWgMaxC) return hipErrorInvalidValue;
             hipLaunchKernelGGL(k_front_wg<T>, dim3(unsigned(f.nlist), B), dim3(256),
-                               size_t(cmax) * (cmax + 1) / 2 * sizeof(T), st, D->sn,
+                               size_t(f.lds) * sizeof(T), st, D->sn,
                                D->lvl_small + f.list0, D->relmap, D->chlist, D->acolptr, D->aoff,
                                D->avidx, vals, ldv, L, P->Lsize, U, P->Usize, N->info, P->nblk);
             break;

@@ -86,6 +86,21 @@ constexpr int kSoaSegMax = 96;    // default of sc_options::soa_seg_max
 
 constexpr int kSellRows = 64;  // rows per slice of the sliced row structure of A
 
+// Fronts of 64 < c rows factored by one workgroup keep their packed lower
+// triangle and the 64-row tiles of L21 ([k][64], k padded to 4) in LDS;
+// scalars needed for a front of c rows and width w.  A front goes there only
+// if that fits the 160 KiB of LDS of a gfx950 workgroup in FP64 (with 1 KiB
+// of the kernel's own), so a plan serves both precisions.
+constexpr int kFrontWgMaxC = 256;
+constexpr int kLdsBytes = 160 * 1024;
+inline int front_wg_lds(int c, int w) {
+    const int m = c - w;
+    return c * (c + 1) / 2 + ((m + 63) / 64) * 64 * ((w + 3) & ~3);
+}
+inline bool front_wg_fits(int c, int w) {
+    return c <= kFrontWgMaxC && int64_t(front_wg_lds(c, w)) * 8 + 1024 <= kLdsBytes;
+}
+
 struct DevPlan;  // device copies, defined by the HIP side
 
 struct sc_plan {
