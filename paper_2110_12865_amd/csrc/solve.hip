@@ -689,7 +689,9 @@ constexpr int kSnWaves = kSnThreads / 64;
 constexpr int kSnRB = 16;         // rows per staging block of the backward sums
 constexpr int kSnThreadsF = 256;  // forward
 
-// Forward: small workgroups (several per CU hide each other's latency).
+// Forward: small workgroups (several per CU hide each other's latency);
+// every thread holds a share of the next panel's inverse block in flight
+// while the current panel is processed.
 template <typename T, int NR, bool SOA>
 __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
@@ -697,14 +699,21 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
     const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Dinv, int64_t dsize,
     T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     const int32_t *__restrict__ active) {
+    constexpr int DPT = kP * kP / kSnThreadsF;  // inverse-block entries per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T(*v)[NR] = reinterpret_cast<T(*)[NR]>(smem_raw);  // front vector, c rows
+    T *Ds = reinterpret_cast<T *>(smem_raw);               // D_p, as stored
+    T(*v)[NR] = reinterpret_cast<T(*)[NR]>(Ds + kP * kP);  // front vector, c rows
     const int s = list[blockIdx.x];
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     const SnDesc d = sn[s];
     const int c = d.c, w = d.w;
     const int tid = threadIdx.x;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    const T *Db = Dinv + int64_t(b) * dsize + d.dinv;
+    T dreg[DPT];
+#pragma unroll
+    for (int q = 0; q < DPT; q++) dreg[q] = Db[q * kSnThreadsF + tid];
     for (int i = tid; i < c; i += kSnThreadsF) {
         const int g0 = gptr[d.rowptr + i], g1 = gptr[d.rowptr + i + 1];
 #pragma unroll
@@ -714,22 +723,26 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
             v[i][r] = a;
         }
     }
-    __syncthreads();
-    const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    const T *Db = Dinv + int64_t(b) * dsize + d.dinv;
     for (int c0 = 0; c0 < w; c0 += kP) {
         const int kb = min(kP, w - c0);
+#pragma unroll
+        for (int q = 0; q < DPT; q++) Ds[q * kSnThreadsF + tid] = dreg[q];
+        __syncthreads();  // D_p staged, v complete
+        if (c0 + kP < w) {
+            const T *Dn = Db + int64_t(c0 / kP + 1) * kP * kP;
+#pragma unroll
+            for (int q = 0; q < DPT; q++) dreg[q] = Dn[q * kSnThreadsF + tid];
+        }
         // y_p = D_p^{-1} v_p (the first panel sums over its kb rows, later
         // ones over all 64 with zeros past kb, as the panel kernels do)
         T y[NR];
         if (tid < kb) {
-            const T *D = Db + int64_t(c0 / kP) * kP * kP;
             const int ni = c0 == 0 ? kb : kP;
 #pragma unroll
             for (int r = 0; r < NR; r++) y[r] = T(0);
 #pragma unroll 16
             for (int i = 0; i < ni; i++) {
-                const T di = D[int64_t(i) * kP + tid];
+                const T di = Ds[i * kP + tid];
 #pragma unroll
                 for (int r = 0; r < NR; r++) y[r] += di * (i < kb ? v[c0 + i][r] : T(0));
             }
@@ -1570,7 +1583,8 @@ template <typename T>
 bool sn_fits(const SLaunch &l, const sc_numeric *N, int nrhs) {
     const int nr = std::min(kMaxRhsPanel, nrhs);
     const size_t front = size_t(l.maxc_pan) * nr * sizeof(T);
-    return N->batch >= kSnMinBatch && front + sn_static_lds<T>(nr) <= size_t(g_max_lds);
+    return N->batch >= kSnMinBatch && front + sn_static_lds<T>(nr) <= size_t(g_max_lds) &&
+           front + kP * kP * sizeof(T) <= size_t(g_max_lds);
 }
 
 template <typename T, bool SOA>
@@ -1593,7 +1607,7 @@ void sn_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const dim3 g(unsigned(l.npan), unsigned(B));
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
         const int nrr = std::min(kMaxRhsPanel, nrhs - r0);
-        const size_t lds = size_t(l.maxc_pan) * nrr * sizeof(T);
+        const size_t lds = (size_t(l.maxc_pan) * nrr + kP * kP) * sizeof(T);
 #define SPCHOL_FWDSN(NRV)                                                                      \
     hipLaunchKernelGGL((k_fwd_sn<T, NRV, SOA>), g, dim3(kSnThreadsF), lds, st, D->sn,            \
                        D->slv_pan + l.pan0, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->dinv),   \
