@@ -308,6 +308,8 @@ __device__ inline float lane_bcast<float>(float v, int src) {
 // pivot that fails d > 0 is recorded (smallest 1-based step wins) and
 // replaced by 1.  The factor is written back (zeros above the diagonal) and
 // the inverse to PIg column-major (PIg[col * 64 + i] = X[i][col]).
+// Widest front held in registers; wider small fronts take the workgroup kernel.
+constexpr int kFrontRegMaxC = 64;
 constexpr int kDiagLds = 4 * kTile + 2;  // two column buffers, two X-row buffers, 1/L_jj x 2
 
 template <typename T>
@@ -770,7 +772,7 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
             // scalars) when it is too tall for registers
             const int cm = P->lvl_small_maxc[l];
             int wlds = 0;
-            if (cm > 64)
+            if (cm > kFrontRegMaxC)
                 for (int32_t e = s0; e < s1; e++)
                     wlds = std::max(wlds, front_wg_lds(P->sn[P->lvl_small[e]].c,
                                                        P->sn[P->lvl_small[e]].w));
@@ -865,7 +867,7 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         switch (f.kind) {
         case FLaunch::Small: {
             const int cmax = f.k;
-            if (cmax <= 64) {
+            if (cmax <= kFrontRegMaxC) {
                 // fronts in registers, one segment of G lanes per (front,
                 // matrix), 64 / G matrices per wave, four fronts per workgroup
 #define SPCHOL_FRONT_REG(CM, G)                                                             \
