@@ -141,7 +141,7 @@ hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
 }
 
 void free_refine_ws(RefineWs &W) {
-    void *ptrs[] = {W.r, W.sc, W.part, W.anorm, W.vc, W.stat, W.conv, W.active, W.count};
+    void *ptrs[] = {W.r, W.sc, W.part, W.part2, W.anorm, W.vc, W.stat, W.conv, W.active, W.count};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     W = RefineWs{};
@@ -159,6 +159,9 @@ hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.sc), 4 * sizeof(double) * nseg);
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.part), 32 * 3 * sizeof(double) * nseg);
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&W.part2),
+                      3 * sizeof(double) * size_t(nsys) * size_t((N->plan->n + 255) / 256));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.anorm),
                       sizeof(double) * N->batch * N->plan->nblk);

@@ -72,21 +72,34 @@ __global__ __launch_bounds__(256) void k_apply(
         Y[base + r * ldb + i] = mode ? B[base + r * ldb + i] - t[r] : t[r];
 }
 
+// Sum of v over the 64 lanes of a wave, by a fixed butterfly; lane 0's
+// result is the one used (other lanes may round differently).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Y1 = B - A X1 and Y2 = A X2 in one pass over A (each sum in the order
-// k_apply uses), for the matrices with active[matrix] != 0.
+// k_apply uses), for the matrices with active[matrix] != 0.  With psum
+// (plans of one block), also the workgroup's partial sums of Y1.Y1, X2.Y2
+// and X1.X1 per right-hand side: psum[((matrix * nrhs + r) * nrb + block
+// of rows) * 3 + {0, 1, 2}], lanes in a fixed butterfly, waves in order.
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply2(
     const int64_t *__restrict__ ptr, const int64_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const double *__restrict__ vc, int64_t nsell,
     const double *__restrict__ B, const double *__restrict__ X1, double *__restrict__ Y1,
     const double *__restrict__ X2, double *__restrict__ Y2, int64_t ldb, int64_t n, int nrhs,
-    int r0, const int32_t *__restrict__ active) {
+    int r0, const int32_t *__restrict__ active, double *__restrict__ psum, int nrb) {
+    __shared__ double red[4][NR][3];
     const int b = blockIdx.x;
     if (active && !active[b]) return;
     const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t e0 = sptr[i / kSellRows] + i % kSellRows;
-    const int len = int(ptr[i + 1] - ptr[i]);
+    const bool in = i < n;
+    const int64_t ic = in ? i : n - 1;  // rows past n compute row n - 1 and add nothing
+    const int64_t e0 = sptr[ic / kSellRows] + ic % kSellRows;
+    const int len = int(ptr[ic + 1] - ptr[ic]);
     const double *v = vc + int64_t(b) * nsell + e0;
     const int32_t *cl = col + e0;
     const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
@@ -102,10 +115,34 @@ __global__ __launch_bounds__(256) void k_apply2(
             t2[r] += a * X2[base + r * ldb + j];
         }
     }
+    double y1[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-        Y1[base + r * ldb + i] = B[base + r * ldb + i] - t1[r];
-        Y2[base + r * ldb + i] = t2[r];
+        y1[r] = B[base + r * ldb + ic] - t1[r];
+        if (in) {
+            Y1[base + r * ldb + i] = y1[r];
+            Y2[base + r * ldb + i] = t2[r];
+        }
+    }
+    if (!psum) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const double x1 = X1[base + r * ldb + ic], x2 = X2[base + r * ldb + ic];
+        const double s0 = wave_sum(in ? y1[r] * y1[r] : 0.0);
+        const double s1 = wave_sum(in ? x2 * t2[r] : 0.0);
+        const double s2 = wave_sum(in ? x1 * x1 : 0.0);
+        if (lane == 0) {
+            red[wv][r][0] = s0;
+            red[wv][r][1] = s1;
+            red[wv][r][2] = s2;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 * NR) {
+        const int r = threadIdx.x / 3, q = threadIdx.x % 3;
+        psum[((int64_t(b) * nrhs + r0 + r) * nrb + blockIdx.y) * 3 + q] =
+            ((red[0][r][q] + red[1][r][q]) + red[2][r][q]) + red[3][r][q];
     }
 }
 
@@ -231,17 +268,17 @@ __global__ __launch_bounds__(256) void k_sums(
     }
 }
 
-// out[seg] = sum of the kRB partial dot products of system seg (component
-// 0), out2[seg] the same for component 1 when out2 is given
-__global__ void k_sums_final(const double *__restrict__ part, int nseg, int per_matrix,
-                             const int32_t *__restrict__ active, double *__restrict__ out,
-                             double *__restrict__ out2) {
+// out[seg] = sum of the nsl partial sums of system seg in slice order
+// (component comp), out2[seg] the same for component comp + 1 when given
+__global__ void k_sums_final(const double *__restrict__ part, int nsl, int comp, int nseg,
+                             int per_matrix, const int32_t *__restrict__ active,
+                             double *__restrict__ out, double *__restrict__ out2) {
     const int sg = blockIdx.x * blockDim.x + threadIdx.x;
     if (sg >= nseg || !active[sg / per_matrix]) return;
     double t = 0.0, t2 = 0.0;
-    for (int q = 0; q < kRB; q++) {
-        t += part[(int64_t(sg) * kRB + q) * 3];
-        if (out2) t2 += part[(int64_t(sg) * kRB + q) * 3 + 1];
+    for (int q = 0; q < nsl; q++) {
+        t += part[(int64_t(sg) * nsl + q) * 3 + comp];
+        if (out2) t2 += part[(int64_t(sg) * nsl + q) * 3 + comp + 1];
     }
     out[sg] = t;
     if (out2) out2[sg] = t2;
@@ -253,7 +290,7 @@ __global__ void k_sums_final(const double *__restrict__ part, int nseg, int per_
 // is no longer updated) keeps its record.
 // iter > 0 takes ||b||_2 from the record of the first test (part holds no
 // b.b then).
-__global__ void k_check(const double *__restrict__ part, int nseg, int nrhs, int nblk,
+__global__ void k_check(const double *__restrict__ part, int nsl, int nseg, int nrhs, int nblk,
                         const double *__restrict__ anorm, double tol, int iter,
                         const int32_t *__restrict__ active, int32_t *__restrict__ conv,
                         double *__restrict__ stat) {
@@ -262,8 +299,8 @@ __global__ void k_check(const double *__restrict__ part, int nseg, int nrhs, int
     const int b = sg / (nrhs * nblk), k = sg % nblk;
     if (!active[b] || conv[sg]) return;
     double a = 0.0, c = 0.0, d = 0.0;
-    for (int q = 0; q < kRB; q++) {
-        const double *o = part + (int64_t(sg) * kRB + q) * 3;
+    for (int q = 0; q < nsl; q++) {
+        const double *o = part + (int64_t(sg) * nsl + q) * 3;
         a += o[0];
         if (iter == 0) c += o[1];
         d += o[2];
@@ -407,7 +444,7 @@ void apply_A(const sc_plan *P, const double *vc, const double *B,
 // Y1 = B - A X1 and Y2 = A X2 with one read of A.
 void apply_A2(const sc_plan *P, const double *vc, const double *B, const double *X1, double *Y1,
               const double *X2, double *Y2, int64_t ldb, int batch, int nrhs,
-              const int32_t *active, hipStream_t st) {
+              const int32_t *active, double *psum, hipStream_t st) {
     const DevPlan *D = P->dev;
     const int64_t nsell = P->sell_ptr.back();
     const dim3 grid(unsigned(batch), unsigned((P->n + 255) / 256));
@@ -415,7 +452,8 @@ void apply_A2(const sc_plan *P, const double *vc, const double *B, const double 
         const int nr = std::min(4, nrhs - r0);
 #define SPCHOL_APPLY2(NR)                                                                  \
     hipLaunchKernelGGL(k_apply2<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->sell_ptr,       \
-                       D->sell_col, vc, nsell, B, X1, Y1, X2, Y2, ldb, P->n, nrhs, r0, active)
+                       D->sell_col, vc, nsell, B, X1, Y1, X2, Y2, ldb, P->n, nrhs, r0, active,  \
+                       psum, int(grid.y))
         if (nr == 1) SPCHOL_APPLY2(1);
         else if (nr == 2) SPCHOL_APPLY2(2);
         else if (nr == 3) SPCHOL_APPLY2(3);
@@ -460,7 +498,7 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, it == 0 ? 3 : 4,
                            ldb, D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
         prof.end(st);
-        hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
+        hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk, W.anorm,
                            tol, it, W.active, W.conv, W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
@@ -520,22 +558,36 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     // true residual b - A x into res, stop test; with pnext, q = A pnext in
-    // the same pass over A
+    // the same pass over A, and for a plan of one block the norms of the test
+    // and p.q of the next step from that pass too (pq_ready)
+    const int nrb = int((n + 255) / 256);
+    bool pq_ready = false;
     auto check = [&](int it, double *res, const double *pnext) -> hipError_t {
+        const bool fuse = pnext && nblk == 1 && it > 0;
         if (pnext) {
             prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 5), st);
-            apply_A2(P, W.vc, b, x, res, pnext, q, ldb, batch, nrhs, W.active, st);
+            apply_A2(P, W.vc, b, x, res, pnext, q, ldb, batch, nrhs, W.active,
+                     fuse ? W.part2 : nullptr, st);
         } else {
             prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
             apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st);
         }
         prof.end(st);
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
-        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, res, b, x, it == 0 ? 3 : 4,
-                           ldb, D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
-        prof.end(st);
-        hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, nseg, nrhs, nblk, W.anorm,
-                           tol, it, W.active, W.conv, W.stat);
+        if (fuse) {
+            hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part2, nrb, nseg, nrhs, nblk,
+                               W.anorm, tol, it, W.active, W.conv, W.stat);
+            hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part2, nrb, 1, nseg, per,
+                               W.active, pq, nullptr);
+            pq_ready = true;
+        } else {
+            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
+            hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, res, b, x,
+                               it == 0 ? 3 : 4, ldb, D->blk_col0, nblk, nrhs, W.active, W.conv,
+                               W.part);
+            prof.end(st);
+            hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk,
+                               W.anorm, tol, it, W.active, W.conv, W.stat);
+        }
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
         if (!sync) return hipSuccess;  // every step runs; converged systems are skipped on device
@@ -550,8 +602,8 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, nullptr, 1, ldb,
                            D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
         prof.end(st);
-        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
-                           out, nullptr);
+        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, kRB, 0, nseg, per,
+                           W.active, out, nullptr);
     };
     // <a, c> into out and <c, d> into out2, in one pass over c
     auto dots2 = [&](const double *a, const double *c, const double *d, double *out,
@@ -560,8 +612,8 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, d, 2, ldb,
                            D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
         prof.end(st);
-        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, nseg, per, W.active,
-                           out, out2);
+        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, kRB, 0, nseg, per,
+                           W.active, out, out2);
     };
     e = check(0, r, nullptr);  // r_0 = b - A x_0
     if (e != hipSuccess) return e;
@@ -574,7 +626,8 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);  // q_1 = A p_1
         prof.end(st);
         for (int it = 1; it <= maxit; it++) {
-            dots(pv, q, pq);
+            if (!pq_ready) dots(pv, q, pq);
+            pq_ready = false;
             prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 6), st);
             hipLaunchKernelGGL(k_cg_xr, vgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
                                nblk, colblk, W.active, W.conv, rz, pq);
