@@ -444,11 +444,14 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         int32_t small_front = opt.small_front > 0 ? opt.small_front : 64;
         P->opt.small_front = small_front;
         std::vector<std::vector<int32_t>> bys(nlev), byb(nlev), bya(nlev);
+        std::vector<char> small_sn(ns, 0);
         for (int32_t s = 0; s < ns; s++) {
             const SnDesc &d = P->sn[s];
             bya[d.level].push_back(s);
-            if (d.c <= small_front && (d.c <= 64 || front_wg_fits(d.c, d.w)))
+            if (d.c <= small_front && (d.c <= 64 || front_wg_fits(d.c, d.w))) {
                 bys[d.level].push_back(s);
+                small_sn[s] = 1;
+            }
             else byb[d.level].push_back(s);
         }
         P->lvl_small_ptr.assign(nlev + 1, 0);
@@ -548,6 +551,10 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             }
             P->slv_pan_ptr[l + 1] = int32_t(P->slv_pan.size());
         }
+        // panel-solved supernodes whose diagonal blocks the tiled factor
+        // does not invert (small fronts): inverted after the factorization
+        for (int32_t s : P->slv_pan)
+            if (small_sn[s]) P->dinv_list.push_back(s);
         // batch-interleaved solve items and the chunks of the L copy
         P->soa_it_ptr.assign(nlev + 1, 0);
         P->grow_ptr.assign(nlev + 1, 0);

@@ -41,8 +41,8 @@ void free_devplan(DevPlan *D) {
     void *ptrs[] = {D->sn, D->rows, D->relmap, D->chlist, D->acolptr, D->aoff,
                     D->avidx, D->perm, D->pinv, D->lvl_small, D->lvl_big, D->lvl_sn,
                     D->asm_col, D->csr_ptr, D->sell_ptr, D->sell_col, D->sell_vidx,
-                    D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr, D->gidx,
-                    D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
+                    D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr,
+                    D->gidx, D->dinv_list, D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
                     D->val_row, D->val_col};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -79,6 +79,7 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->asm_pc, P->asm_pc);
     if (e == hipSuccess) e = upload(&D->slv_small, P->slv_small);
     if (e == hipSuccess) e = upload(&D->slv_pan, P->slv_pan);
+    if (e == hipSuccess) e = upload(&D->dinv_list, P->dinv_list);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
     if (e == hipSuccess) e = upload(&D->sell_ptr, P->sell_ptr);
     if (e == hipSuccess) e = upload(&D->sell_col, P->sell_col);

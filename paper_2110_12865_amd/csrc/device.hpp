@@ -86,6 +86,7 @@ struct DevPlan {
     AsmPiece *asm_pc = nullptr;
     int32_t *slv_small = nullptr;     // solve schedule lists
     int32_t *slv_pan = nullptr;
+    int32_t *dinv_list = nullptr;     // panel-solved small fronts
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int64_t *sell_ptr = nullptr;      // the same rows sliced by kSellRows
     int32_t *sell_col = nullptr;

@@ -313,7 +313,8 @@ constexpr int kFrontRegMaxC = 64;
 constexpr int kDiagLds = 4 * kTile + 2;  // two column buffers, two X-row buffers, 1/L_jj x 2
 
 template <typename T>
-__device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, int col0,
+__device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, T *Dg,
+                                               int col0,
                                int32_t *info_b) {
     T *cb = lds, *xr = lds + 2 * kTile, *rv = lds + 4 * kTile;
     const int tid = threadIdx.x, li = tid & 63, g = tid >> 6;
@@ -377,7 +378,9 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
         const int col = 16 * g + tt;
         const bool in = li < kb && col < kb;
         if (in) Lb[int64_t(r0 + col) * c + r0 + li] = li >= col ? f[tt] : T(0);
-        PIg[col * kTile + li] = (in && li >= col) ? x[tt] : T(0);
+        const T xv = (in && li >= col) ? x[tt] : T(0);
+        PIg[col * kTile + li] = xv;
+        if (Dg) Dg[col * kTile + li] = xv;
     }
 }
 
@@ -551,12 +554,15 @@ __global__ __launch_bounds__(256) void k_front_wg(
 }
 
 // Diagonal block of panel k of each large front: factor and invert (one
-// workgroup per front and matrix).
+// workgroup per front and matrix).  The inverse also goes to the solve's
+// inverted diagonal blocks when the supernode is solved by panels (the
+// factor's 64-column panels are the solve's).
+static_assert(kTile == kSolvePanel, "factor and solve panels coincide");
 template <typename T>
 __global__ __launch_bounds__(256) void k_potrf(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
     T *__restrict__ L, int64_t Lsize, T *__restrict__ PI, int64_t pistride,
-    int32_t *__restrict__ info, int nblk) {
+    T *__restrict__ Dinv, int64_t dsize, int32_t *__restrict__ info, int nblk) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     const int s = list[blockIdx.x];
@@ -566,7 +572,10 @@ __global__ __launch_bounds__(256) void k_potrf(
     const int kb = min(kTile, d.w - k);
     T *Lb = L + int64_t(b) * Lsize + d.loff;
     T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.x) * kTile * kTile;
-    wg_diag_factor(Lb, d.c, k, kb, lds, PIg, d.first - d.bcol0 + k,
+    // a panel-solved supernode keeps the inverse for the solves as well
+    T *Dg = d.dinv >= 0 ? Dinv + int64_t(b) * dsize + d.dinv + int64_t(k / kTile) * kTile * kTile
+                        : nullptr;
+    wg_diag_factor(Lb, d.c, k, kb, lds, PIg, Dg, d.first - d.bcol0 + k,
                    info + int64_t(b) * nblk + d.blk);
 }
 
@@ -906,7 +915,7 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
             hipLaunchKernelGGL(k_potrf<T>, dim3(unsigned(f.gridx), B), dim3(256),
                                size_t(kDiagLds) * sizeof(T), st,
                                D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize, PI, pistride,
-                               N->info, P->nblk);
+                               reinterpret_cast<T *>(N->dinv), P->dinv_size, N->info, P->nblk);
             break;
         case FLaunch::Trsm:
             hipLaunchKernelGGL(k_trsm<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),

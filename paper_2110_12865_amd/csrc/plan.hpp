@@ -188,6 +188,10 @@ struct sc_plan {
     int64_t soa_psize = 0;
     std::vector<int64_t> soa_chunks;
     int64_t dinv_size = 0;   // scalars of inverted diagonal blocks
+    // panel-solved supernodes factored as small fronts (their inverted
+    // diagonal blocks are formed after the factorization; the tiled factor
+    // writes the others as it factors each block)
+    std::vector<int32_t> dinv_list;
     int64_t part_size = 0;   // partial sums per right-hand side
     int32_t npan = 0;        // supernodes solved by panels
     std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts

@@ -1,7 +1,7 @@
 // Forward and backward triangular solves with the supernodal factor
 // (gfx950).  y = L^{-1} P b by levels ascending, z = L^{-T} y by levels
-// descending, x = P^T z.  The factor may be stored in FP64 or FP32; the
-// solves always compute in FP64.
+// descending, x = P^T z.  The solves run in the precision of the stored
+// factor (FP64, or FP32 vectors and arithmetic for an FP32 factor).
 //
 // Every supernode s owns a front vector FV_s of c_s entries: the first w_s
 // hold its right-hand side, the last m_s its negated update vector
@@ -10,14 +10,14 @@
 // fixed order and reductions use fixed trees, so results are
 // bit-reproducible and free of floating-point atomics.
 //
-// Small supernodes are solved by one workgroup out of LDS.  Wide or tall
-// ones are solved by 64-column panels across many workgroups, using the
-// inverted 64x64 diagonal blocks computed after the factorization:
-//   forward  y_p = D_p^{-1} v_p (every workgroup recomputes it), then each
-//            workgroup updates its own 64 rows below the panel;
-//   backward each workgroup forms partial dot products for a chunk of rows,
-//            the last one to finish (atomic counter, no waiting) sums them
-//            in chunk order and applies D_p^{-T}.
+// Small supernodes are solved by segments of a wave (row-major vectors) or
+// one lane per matrix (batch-interleaved vectors).  Wide or tall ones are
+// solved by 64-column panels with the inverted 64x64 diagonal blocks D_p:
+//   forward  y_p = D_p^{-1} v_p, then the rows below the panel are updated;
+//   backward partial dot products of chunks of rows below the panel, added
+//            in chunk order, then D_p^{-T} is applied;
+// either across many workgroups, one launch per step (few matrices), or by
+// one workgroup per (supernode, matrix) walking all its panels (batches).
 #include <algorithm>
 
 #include "device.hpp"
@@ -37,7 +37,8 @@ __device__ __forceinline__ V ldz(const V *p, int64_t idx, bool ok) {
     return ok ? v : V(0);
 }
 
-// Inverse of every 64x64 diagonal block of every panel-solved supernode:
+// Inverse of every 64x64 diagonal block of the panel-solved supernodes that
+// were factored as small fronts (the tiled factor writes the others):
 // X = L_pp^{-1} by forward substitution, one lane per column of X kept in
 // registers (loops fully unrolled), L_pp read from LDS as broadcasts.
 template <typename T>
@@ -1360,13 +1361,15 @@ T *as(double *p) { return reinterpret_cast<T *>(p); }
 
 template <typename T>
 hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
-    if (P->npan == 0) return hipSuccess;
+    if (P->dinv_list.empty()) return hipSuccess;
     DevPlan *D = P->dev;
     const T *L = static_cast<const T *>(N->L);
     const int64_t maxp = (P->max_width + kP - 1) / kP;
     N->prof.begin(KK_Dinv, 0.0, 0.0, st);
-    hipLaunchKernelGGL(k_dinv<T>, dim3(unsigned(maxp), unsigned(P->npan), unsigned(N->batch)),
-                       dim3(64), 0, st, D->sn, D->slv_pan, L, P->Lsize, as<T>(N->dinv), P->dinv_size);
+    hipLaunchKernelGGL(k_dinv<T>,
+                       dim3(unsigned(maxp), unsigned(P->dinv_list.size()), unsigned(N->batch)),
+                       dim3(64), 0, st, D->sn, D->dinv_list, L, P->Lsize, as<T>(N->dinv),
+                       P->dinv_size);
     N->prof.end(st);
     return hipGetLastError();
 }
@@ -1573,8 +1576,13 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
 }
 
 // Panel-solved supernodes of a level with one workgroup per (supernode,
-// matrix), when the batch fills the chip and the front vector fits in LDS.
+// matrix), when the batch fills the chip and the front vector fits in LDS:
+// at least kSnMinBatch matrices and kSnMinGroups workgroups, fronts of at
+// most kSnMaxRows rows (a taller front is a long chain for one workgroup;
+// the multi-launch panel kernels spread it over the chip instead).
 constexpr int kSnMinBatch = 16;
+constexpr int kSnMinGroups = 64;
+constexpr int kSnMaxRows = 1024;
 template <typename T>
 size_t sn_static_lds(int nr) {
     return sizeof(T) * (size_t(kSnWaves) * kSnRB * (kP + 1) + (kSnWaves + 1) * size_t(kP) * nr);
@@ -1583,7 +1591,8 @@ template <typename T>
 bool sn_fits(const SLaunch &l, const sc_numeric *N, int nrhs) {
     const int nr = std::min(kMaxRhsPanel, nrhs);
     const size_t front = size_t(l.maxc_pan) * nr * sizeof(T);
-    return N->batch >= kSnMinBatch && front + sn_static_lds<T>(nr) <= size_t(g_max_lds) &&
+    return N->batch >= kSnMinBatch && int64_t(l.npan) * N->batch >= kSnMinGroups &&
+           l.maxc_pan <= kSnMaxRows && front + sn_static_lds<T>(nr) <= size_t(g_max_lds) &&
            front + kP * kP * sizeof(T) <= size_t(g_max_lds);
 }
 
