@@ -318,6 +318,7 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
                                int32_t *info_b) {
     T *cb = lds, *xr = lds + 2 * kTile, *rv = lds + 4 * kTile;
     const int tid = threadIdx.x, li = tid & 63, g = tid >> 6;
+    const int gu = __builtin_amdgcn_readfirstlane(g);  // the wave's index, as a scalar
     T f[16], x[16];
 #pragma unroll
     for (int tt = 0; tt < 16; tt++) {
@@ -358,17 +359,25 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
                 const T lij = cb[buf * kTile + li];
                 const T lx = li > j ? lij * rinv : T(0);
                 const T sx = li == j ? rinv : T(1);
-                T cv[16], xv[16];
+                // a wave whose columns all precede j has no update of f left,
+                // one whose columns all follow j none of X (row j of X is
+                // zero there): wave-uniform skips
+                if (gu >= J) {
+                    T cv[16];
 #pragma unroll
-                for (int tt = 0; tt < 16; tt++) {
-                    cv[tt] = cb[buf * kTile + 16 * g + tt];
-                    xv[tt] = xr[buf * kTile + 16 * g + tt];
+                    for (int tt = 0; tt < 16; tt++) cv[tt] = cb[buf * kTile + 16 * g + tt];
+#pragma unroll
+                    for (int tt = 0; tt < 16; tt++) {
+                        const T m = 16 * g + tt > j ? lij : T(0);
+                        f[tt] = fma(-m, cv[tt], f[tt]);
+                    }
                 }
+                if (gu <= J) {
+                    T xv[16];
 #pragma unroll
-                for (int tt = 0; tt < 16; tt++) {
-                    const T m = 16 * g + tt > j ? lij : T(0);
-                    f[tt] = fma(-m, cv[tt], f[tt]);
-                    x[tt] = fma(-lx, xv[tt], x[tt] * sx);
+                    for (int tt = 0; tt < 16; tt++) xv[tt] = xr[buf * kTile + 16 * g + tt];
+#pragma unroll
+                    for (int tt = 0; tt < 16; tt++) x[tt] = fma(-lx, xv[tt], x[tt] * sx);
                 }
             }
         }
