@@ -295,30 +295,36 @@ __device__ inline float lane_bcast<float>(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// Widest front held in registers; wider small fronts take the workgroup kernel.
+constexpr int kFrontRegMaxC = 64;
+
 // Factor and invert the kb x kb diagonal block (kb <= 64) whose top-left
 // corner is (r0, r0) of a column-major L block, with one workgroup of 256
 // threads.  Lane i of wave g keeps row i of columns 16 g .. 16 g + 15, of
-// the block (f) and of its inverse X = L^{-1} (x), in registers.  Step j:
-// the wave owning column j forms the pivot and column j of L and publishes
-// it; lane j publishes its (unscaled) row of X; after one barrier every
-// thread subtracts L_ij L_tj from its columns t > j and L_ij X_jc from its
-// row of X (rows i > j), and lane j scales its row of X by 1 / L_jj (X_jc
-// L_ij / L_jj is formed as (L_ij / L_jj) X_jc).  The
-// published vectors are double-buffered, so a step needs one barrier.  A
-// pivot that fails d > 0 is recorded (smallest 1-based step wins) and
-// replaced by 1.  The factor is written back (zeros above the diagonal) and
-// the inverse to PIg column-major (PIg[col * 64 + i] = X[i][col]).
-// Widest front held in registers; wider small fronts take the workgroup kernel.
-constexpr int kFrontRegMaxC = 64;
-constexpr int kDiagLds = 4 * kTile + 2;  // two column buffers, two X-row buffers, 1/L_jj x 2
+// the block (f) and of its inverse X = L^{-1} (x), in registers.  Step j
+// forms the pivot and column j of L (i > j: L_ij = F_ij / L_jj), every
+// later column t takes F_it -= L_ij L_tj, and every row i > j of X takes
+// X_i. -= (L_ij / L_jj) X_j. while row j is scaled by 1 / L_jj.  Columns
+// go in blocks of 16, one per wave: the owning wave runs the block's 16
+// steps back to back (its own columns need nothing from the other waves),
+// publishing each column of L and 1 / L_jj in LDS; after one barrier the
+// other waves replay the 16 steps on their own registers (later columns: f,
+// earlier columns: x).  Every entry sees the same operations in the same
+// order as with a barrier per step.  A pivot that fails d > 0 is recorded
+// (smallest 1-based step wins) and replaced by 1.  The factor is written
+// back (zeros above the diagonal) and the inverse to PIg column-major
+// (PIg[col * 64 + i] = X[i][col]), and to Dg as well when given.
+constexpr int kDiagLds = 2 * 16 * kTile + 2 * 16 + 4 * 16;  // columns x 2 blocks, 1/L_jj, X rows
 
 template <typename T>
 __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, T *Dg,
-                                               int col0,
-                               int32_t *info_b) {
-    T *cb = lds, *xr = lds + 2 * kTile, *rv = lds + 4 * kTile;
+                                               int col0, int32_t *info_b) {
+    T *cbuf = lds;                    // [2][16][64] columns of L, by block parity
+    T *rvb = lds + 2 * 16 * kTile;    // [2][16] 1 / L_jj
+    T *xrw = rvb + 2 * 16;            // [4][16] row j of X, one slot per wave
     const int tid = threadIdx.x, li = tid & 63, g = tid >> 6;
     const int gu = __builtin_amdgcn_readfirstlane(g);  // the wave's index, as a scalar
+    T *xw = xrw + 16 * gu;
     T f[16], x[16];
 #pragma unroll
     for (int tt = 0; tt < 16; tt++) {
@@ -328,12 +334,13 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
     }
     for (int J = 0; J < 4; J++) {
         if (16 * J >= kb) break;
+        T *cbJ = cbuf + (J & 1) * 16 * kTile;
+        T *rvJ = rvb + (J & 1) * 16;
+        if (gu == J) {
 #pragma unroll
-        for (int jj = 0; jj < 16; jj++) {
-            const int j = 16 * J + jj;
-            if (j < kb) {
-                const int buf = j & 1;
-                if (g == J) {
+            for (int jj = 0; jj < 16; jj++) {
+                const int j = 16 * J + jj;
+                if (j < kb) {
                     T djj = lane_bcast(f[jj], j);
                     const bool bad = !(djj > T(0));
                     if (bad) djj = T(1);
@@ -341,43 +348,65 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
                     const T rinv = T(1) / ljj;
                     const T lij = li == j ? ljj : (li > j ? f[jj] * rinv : T(0));
                     f[jj] = lij;
-                    cb[buf * kTile + li] = lij;
+                    cbJ[jj * kTile + li] = lij;
                     if (li == j) {
-                        rv[buf] = rinv;
+                        rvJ[jj] = rinv;
                         if (bad) atomicMin(info_b, col0 + j + 1);
+#pragma unroll
+                        for (int tt = 0; tt < 16; tt++) xw[tt] = x[tt];
                     }
-                }
-                if (li == j) {
-#pragma unroll
-                    for (int tt = 0; tt < 16; tt++) xr[buf * kTile + 16 * g + tt] = x[tt];
-                }
-                __syncthreads();
-                // branch-free: masked multipliers instead of conditional
-                // updates (a conditional update compiles to a branch and a
-                // memory wait per entry)
-                const T rinv = rv[buf];
-                const T lij = cb[buf * kTile + li];
-                const T lx = li > j ? lij * rinv : T(0);
-                const T sx = li == j ? rinv : T(1);
-                // a wave whose columns all precede j has no update of f left,
-                // one whose columns all follow j none of X (row j of X is
-                // zero there): wave-uniform skips
-                if (gu >= J) {
-                    T cv[16];
-#pragma unroll
-                    for (int tt = 0; tt < 16; tt++) cv[tt] = cb[buf * kTile + 16 * g + tt];
+                    wave_fence_sync();
+                    const T lx = li > j ? lij * rinv : T(0);
+                    const T sx = li == j ? rinv : T(1);
+                    T cv[16], xv[16];
 #pragma unroll
                     for (int tt = 0; tt < 16; tt++) {
-                        const T m = 16 * g + tt > j ? lij : T(0);
-                        f[tt] = fma(-m, cv[tt], f[tt]);
+                        cv[tt] = cbJ[jj * kTile + 16 * J + tt];
+                        xv[tt] = xw[tt];
                     }
+#pragma unroll
+                    for (int tt = 0; tt < 16; tt++) {
+                        if (tt > jj) f[tt] = fma(-lij, cv[tt], f[tt]);
+                        x[tt] = fma(-lx, xv[tt], x[tt] * sx);
+                    }
+                    wave_fence_sync();  // row j of X is read before the next step rewrites it
                 }
-                if (gu <= J) {
+            }
+        }
+        __syncthreads();  // the block's columns of L and 1 / L_jj are visible
+        if (gu > J) {
+#pragma unroll
+            for (int jj = 0; jj < 16; jj++) {
+                const int j = 16 * J + jj;
+                if (j < kb) {
+                    const T lij = cbJ[jj * kTile + li];
+                    T cv[16];
+#pragma unroll
+                    for (int tt = 0; tt < 16; tt++) cv[tt] = cbJ[jj * kTile + 16 * g + tt];
+#pragma unroll
+                    for (int tt = 0; tt < 16; tt++) f[tt] = fma(-lij, cv[tt], f[tt]);
+                }
+            }
+        } else if (gu < J) {
+#pragma unroll
+            for (int jj = 0; jj < 16; jj++) {
+                const int j = 16 * J + jj;
+                if (j < kb) {
+                    const T rinv = rvJ[jj];
+                    const T lij = cbJ[jj * kTile + li];
+                    const T lx = li > j ? lij * rinv : T(0);
+                    const T sx = li == j ? rinv : T(1);
+                    if (li == j) {
+#pragma unroll
+                        for (int tt = 0; tt < 16; tt++) xw[tt] = x[tt];
+                    }
+                    wave_fence_sync();
                     T xv[16];
 #pragma unroll
-                    for (int tt = 0; tt < 16; tt++) xv[tt] = xr[buf * kTile + 16 * g + tt];
+                    for (int tt = 0; tt < 16; tt++) xv[tt] = xw[tt];
 #pragma unroll
                     for (int tt = 0; tt < 16; tt++) x[tt] = fma(-lx, xv[tt], x[tt] * sx);
+                    wave_fence_sync();
                 }
             }
         }
