@@ -198,11 +198,13 @@ def kernel_table(prof, steps):
 # time (kinds that bracket more than one kernel family are not candidates
 # for the roofline line)
 HIP_KERNEL = {
-    "front_small": "k_front_reg", "assemble": "k_assemble_cols", "potrf": "k_potrf",
+    "front_small": "k_front_reg|k_front_wg", "assemble": "k_assemble_cols", "potrf": "k_potrf",
     "trsm": "k_trsm", "syrk_mfma": "k_syrk", "diag_inverse": "k_dinv",
     "solve_fwd": "k_fwd_soa_diag|k_fwd_seg", "solve_bwd": "k_bwd_soa_diag|k_bwd_seg",
     "solve_fwd_rows": "k_fwd_soa_rows", "solve_bwd_rows": "k_bwd_soa_rows",
-    "solve_gather": "k_gather", "spmv_residual": "k_apply",
+    "solve_fwd_panel": "k_pan_gather|k_fwd_panel|k_fwd_sn",
+    "solve_bwd_panel": "k_bwd_pan_part|k_bwd_pan_fin|k_bwd_sn",
+    "solve_gather": "k_gather", "spmv_residual": "k_apply|k_apply2",
     "solve_copy_interleaved": "k_to_soa",
 }
 
