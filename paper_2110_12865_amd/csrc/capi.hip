@@ -374,6 +374,9 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
     if (e == hipSuccess && N->soa)
         e = hipMalloc(&N->Ls, std::max<size_t>(size_t((batch + 63) / 64) * 64 * P->Lsize * sz, 8));
     if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * ninfo);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&N->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&N->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
         sc_numeric_destroy(N);
         return map_err(e);
@@ -384,6 +387,7 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
 
 void sc_numeric_destroy(sc_numeric_t *N) {
     if (!N) return;
+    if (N->side) (void)hipStreamDestroy(N->side);  // waits for its work
     if (N->L) (void)hipFree(N->L);
     if (N->U) (void)hipFree(N->U);
     if (N->info) (void)hipFree(N->info);
@@ -391,6 +395,8 @@ void sc_numeric_destroy(sc_numeric_t *N) {
     for (void *q : ws)
         if (q) (void)hipFree(q);
     free_refine_ws(N->rws);
+    if (N->ev_fork) (void)hipEventDestroy(N->ev_fork);
+    if (N->ev_join) (void)hipEventDestroy(N->ev_join);
     delete N;
 }
 

@@ -19,11 +19,14 @@ constexpr int kBlock = 256;
 // One kernel launch of the factor schedule.  The schedule depends only on
 // the pattern, so it is built once per plan and replayed by every call.
 struct FLaunch {
-    enum Kind : int { Small, Assemble, Potrf, Trsm, Syrk } kind;
+    // Fork: the side stream waits for the main stream's work so far; Join:
+    // the main stream waits for the side stream's work so far
+    enum Kind : int { Small, Assemble, Potrf, Trsm, Syrk, Fork, Join } kind;
     int32_t level;
     int32_t k;        // panel start column (Potrf/Trsm/Syrk inner)
     int32_t K0;       // block start column (Syrk)
-    int32_t outer;    // Syrk: 1 = update beyond the block, 0 = inside it
+    int32_t outer;    // Syrk: 0 = inside the block, 1 = beyond it, 2 = the next
+                      // kBlock columns beyond it, 3 = the columns after those
     int32_t list0;    // first entry in the level's list
     int32_t nlist;    // entries
     int64_t gridx;    // workgroups along x
@@ -31,6 +34,7 @@ struct FLaunch {
     double flops;     // algorithmic flops per matrix of the batch
     double words;     // algorithmic scalars of L/U moved per matrix
     double ibytes;    // algorithmic index/value bytes per matrix
+    int32_t side = 0; // 1: launched on the side stream
 };
 
 struct SPanel {  // one 64-column panel step of a level's panel-solved supernodes
@@ -187,6 +191,10 @@ struct sc_numeric {
     double *ws_ps = nullptr;    // ceil(batch / 64) * 64 * soa_psize * nrhs partial sums
     Profiler prof;
     RefineWs rws;
+    // second stream of the factorization (lookahead in the panel chain of
+    // large fronts) and the events that order it against the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 // Launchers (factor.hip / solve.hip).  Return hipSuccess or the first error.

@@ -106,10 +106,12 @@ __device__ inline T seg_bc(T v, int src) {
 //             by broadcasts inside the segment; a child's update block is
 //             read row-wise through the inverse of its relative map (an
 //             LDS table shared by the segments).
-//   factor    right-looking: the pivot and the column of L are broadcast
-//             in the segment; after each step the registers shift left by
-//             one so that the current column is always f[0] (every
-//             register index is a compile-time constant).
+//   factor    right-looking: the pivot is broadcast in the segment and
+//             the column of L goes through LDS (row j + k at slot k, read
+//             16 bytes at a time); after each step the registers shift left
+//             by one so that the current column is always f[0] (every
+//             register index is a compile-time constant).  Columns past
+//             the front's last row are scratch and stop being updated.
 template <typename T, int CM, int G>
 __global__ __launch_bounds__(256) void k_front_reg(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int nlist, int batch,
@@ -120,8 +122,12 @@ __global__ __launch_bounds__(256) void k_front_reg(
     int32_t *__restrict__ info, int nblk) {
     static_assert(CM <= G && (G == 16 || G == 32 || G == 64), "segment shape");
     constexpr int NSEG = 64 / G;
+    constexpr int V = 16 / int(sizeof(T));  // column entries per 16-byte LDS read
     __shared__ int32_t inv_all[4][64];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // per segment: the current column of L, padded so that the segments of a
+    // wave read from different banks
+    __shared__ __align__(16) T cbuf[4][NSEG][G + 4];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int e = blockIdx.x * 4 + wv;
     if (e >= nlist) return;
     const int li = lane % G, sg = lane / G;
@@ -204,6 +210,7 @@ __global__ __launch_bounds__(256) void k_front_reg(
     // partial factorization of the first w columns
     const int64_t infoidx = bb * nblk + d.blk;
     T *Lb = L + d.loff;
+    T *cb = &cbuf[wv][sg][0];
     for (int j = 0; j < w; j++) {
         T djj = seg_bc<G>(f[0], j);
         const bool bad = !(djj > T(0));
@@ -215,12 +222,34 @@ __global__ __launch_bounds__(256) void k_front_reg(
         const T rinv = T(1) / ljj;
         const T lij = li == j ? ljj : (li > j ? f[0] * rinv : T(0));
         if (li < c && bok) Lb[int64_t(j) * c + li] = lij;
-        // columns j + k >= c are scratch: their updates are never read
+        if (li >= j) cb[li - j] = lij;
+        wave_fence_sync();
+        // f[k - 1] <- column j + k minus L_{., j} L_{j + k, j}; registers of
+        // columns j + k >= c (all chunks from the first such one) keep
+        // whatever they hold: those columns are never read
+        // (groups of four reads: all issued before the first product)
 #pragma unroll
-        for (int k = 1; k < CM; k++) f[k] -= lij * seg_bc<G>(lij, (j + k) % G);
+        for (int k0 = 0; k0 < CM; k0 += 4 * V) {
+            if (j + k0 >= c) continue;
+            T v[4 * V];
 #pragma unroll
-        for (int k = 0; k + 1 < CM; k++) f[k] = f[k + 1];
-        f[CM - 1] = T(0);
+            for (int r = 0; r < 4; r++) {
+                if (k0 + r * V >= CM) break;
+                if constexpr (V == 4) {
+                    const float4 q = *reinterpret_cast<const float4 *>(cb + k0 + 4 * r);
+                    v[4 * r] = q.x; v[4 * r + 1] = q.y; v[4 * r + 2] = q.z; v[4 * r + 3] = q.w;
+                } else {
+                    const double2 q = *reinterpret_cast<const double2 *>(cb + k0 + 2 * r);
+                    v[2 * r] = q.x; v[2 * r + 1] = q.y;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4 * V; t++) {
+                const int k = k0 + t;
+                if (k >= 1 && k < CM) f[k - 1] = fma(-lij, v[t], f[k]);
+            }
+        }
+        wave_fence_sync();  // the column is read before the next step rewrites it
     }
     // f[k] now holds column w + k: the update block
     T *Us = U + d.uoff;
@@ -671,7 +700,10 @@ __global__ __launch_bounds__(256) void k_trsm(
 // Update region of a trailing-update launch for one front: columns
 // [cbeg, cend), rows [column, c), with the panel columns [k0, k0 + kw).
 // Inner update (outer = 0): panel k of block K0 updates the rest of its
-// block.  Outer update: the whole block updates everything beyond it.
+// block.  Outer update: the whole block updates everything beyond it
+// (outer = 1), or only the next kBlock columns (2, the next block's panel
+// chain needs them first) or only the columns after those (3, which can run
+// beside that chain).
 struct SyrkRegion {
     int k0, kw, cbeg, cend;
 };
@@ -682,8 +714,8 @@ __host__ __device__ inline bool syrk_region(int w, int c, int K0, int k, int out
     if (outer) {
         r.k0 = K0;
         r.kw = K1 - K0;
-        r.cbeg = K1;
-        r.cend = c;
+        r.cbeg = outer == 3 ? K1 + kBlock : K1;
+        r.cend = outer == 2 ? min(K1 + kBlock, c) : c;
     } else {
         if (k >= K1) return false;
         r.k0 = k;
@@ -844,7 +876,7 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
             fa.ibytes += a_entries(d) * 20.0;
         }
         D->fsched.push_back(fa);
-        auto add_syrk = [&](int K0, int k, int outer) {
+        auto make_syrk = [&](int K0, int k, int outer) {
             FLaunch fs{FLaunch::Syrk, l, k, K0, outer, b0, b1 - b0, 0, 2 * kTile * kTile,
                        0.0, 0.0, 0.0};
             for (int32_t e = b0; e < b1; e++) {
@@ -858,8 +890,22 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
                 fs.flops += 2.0 * R.kw * entries;
                 fs.words += 2.0 * entries + double(d.c - R.cbeg) * R.kw;
             }
+            return fs;
+        };
+        auto add_syrk = [&](int K0, int k, int outer) {
+            const FLaunch fs = make_syrk(K0, k, outer);
             if (fs.gridx > 0) D->fsched.push_back(fs);
         };
+        auto sync = [&](FLaunch::Kind kind) {
+            D->fsched.push_back(FLaunch{kind, l, 0, 0, 0, b0, 0, 0, 0, 0.0, 0.0, 0.0});
+        };
+        // Lookahead: after the panel chain of block K0, the next block's
+        // columns are updated on the main stream and the rest of the front on
+        // the side stream, so the next block's chain runs beside that larger
+        // update.  Updates of the same entries stay ordered: the side stream's
+        // update of block K0 is joined before the main stream's update of
+        // the following block (both write the columns two blocks on).
+        bool pending = false;  // side-stream work not yet joined
         for (int32_t K0 = 0; K0 < P->lvl_big_maxw[l]; K0 += kBlock) {
             for (int32_t k = K0; k < std::min(K0 + kBlock, P->lvl_big_maxw[l]); k += kTile) {
                 FLaunch fp{FLaunch::Potrf, l, k, 0, 0, b0, b1 - b0, b1 - b0, 0, 0.0, 0.0, 0.0};
@@ -885,8 +931,21 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
                 if (ft.gridx > 0) D->fsched.push_back(ft);
                 add_syrk(K0, k, 0);
             }
-            add_syrk(K0, 0, 1);
+            FLaunch rest = make_syrk(K0, 0, 3);
+            if (K0 + kBlock >= P->lvl_big_maxw[l] || rest.gridx == 0) {
+                if (pending) sync(FLaunch::Join);
+                pending = false;
+                add_syrk(K0, 0, 1);
+                continue;
+            }
+            sync(FLaunch::Fork);
+            if (pending) sync(FLaunch::Join);
+            add_syrk(K0, 0, 2);
+            rest.side = 1;
+            D->fsched.push_back(rest);
+            pending = true;
         }
+        if (pending) sync(FLaunch::Join);
     }
 }
 
@@ -909,8 +968,17 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
     Profiler &prof = N->prof;
     const double wsz = double(sizeof(T));
     for (const FLaunch &f : D->fsched) {
+        if (f.kind == FLaunch::Fork || f.kind == FLaunch::Join) {
+            const bool fork = f.kind == FLaunch::Fork;
+            hipError_t e = hipEventRecord(fork ? N->ev_fork : N->ev_join, fork ? st : N->side);
+            if (e == hipSuccess) e = hipStreamWaitEvent(fork ? N->side : st,
+                                                       fork ? N->ev_fork : N->ev_join, 0);
+            if (e != hipSuccess) return e;
+            continue;
+        }
         static const int kinds[] = {KK_SmallFront, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk};
-        prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, st);
+        const hipStream_t fst = f.side ? N->side : st;
+        prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, fst);
         switch (f.kind) {
         case FLaunch::Small: {
             const int cmax = f.k;
@@ -962,11 +1030,13 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
             break;
         case FLaunch::Syrk:
             hipLaunchKernelGGL(k_syrk<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),
-                               size_t(f.lds) * sizeof(T), st, D->sn, D->lvl_big + f.list0,
+                               size_t(f.lds) * sizeof(T), fst, D->sn, D->lvl_big + f.list0,
                                f.K0, f.k, f.outer, L, P->Lsize, U, P->Usize);
             break;
+        default:
+            break;
         }
-        prof.end(st);
+        prof.end(fst);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
