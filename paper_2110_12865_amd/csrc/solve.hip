@@ -225,13 +225,19 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
     // diagonal block (rows < w live in slot 0)
     const T dgl = T(ldz(Lb, int64_t(li) * c + li, li < w));
     const T rinv = li < w ? T(1) / dgl : T(0);
-    for (int j0 = 0; j0 < w; j0 += 8) {
-        T lc[8];
+    // columns in chunks of 8, the next chunk's loads in flight while the
+    // current one is processed; loads are unconditional from clamped
+    // in-bounds addresses (column min(j, w - 1), row 0 for lanes past c) and
+    // only the entries the update uses are read from them
+    const int lrow = li < c ? li : 0;
+    T lc[8];
 #pragma unroll
-        for (int jj = 0; jj < 8; jj++) {
-            const int j = j0 + jj;
-            lc[jj] = ldz(Lb, int64_t(j) * c + li, j < w && li > j && li < w);
-        }
+    for (int jj = 0; jj < 8; jj++) lc[jj] = Lb[int64_t(min(jj, w - 1)) * c + lrow];
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        T ln[8];
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++)
+            ln[jj] = Lb[int64_t(min(j0 + 8 + jj, w - 1)) * c + lrow];
 #pragma unroll
         for (int jj = 0; jj < 8; jj++) {
             const int j = j0 + jj;
@@ -249,6 +255,8 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
                 }
             }
         }
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) lc[jj] = ln[jj];
     }
     if (li < w) {
 #pragma unroll
@@ -259,16 +267,21 @@ __global__ __launch_bounds__(256) void k_fwd_seg(
     }
     wave_sync_solve();
     // rows below the diagonal block, JC columns of L in flight at once
-    constexpr int JC = SL >= 4 ? 4 : 8;
+    constexpr int JC = SL >= 8 ? 8 : 16;
+    int irow[SL];  // the lane's rows below the block, clamped to row 0
+#pragma unroll
+    for (int k = 0; k < SL; k++) {
+        const int i = li + G * k;
+        irow[k] = i >= w && i < c ? i : 0;
+    }
     for (int j0 = 0; j0 < w; j0 += JC) {
         T lc[JC][SL];
 #pragma unroll
-        for (int jj = 0; jj < JC; jj++)
+        for (int jj = 0; jj < JC; jj++) {
+            const T *Lj = Lb + int64_t(min(j0 + jj, w - 1)) * c;
 #pragma unroll
-            for (int k = 0; k < SL; k++) {
-                const int i = li + G * k, j = j0 + jj;
-                lc[jj][k] = ldz(Lb, int64_t(j) * c + i, j < w && i >= w && i < c);
-            }
+            for (int k = 0; k < SL; k++) lc[jj][k] = Lj[irow[k]];
+        }
 #pragma unroll
         for (int jj = 0; jj < JC; jj++) {
             const int j = j0 + jj;
@@ -337,48 +350,69 @@ __global__ __launch_bounds__(256) void k_bwd_seg(
     const T rinv = li < w ? T(1) / T(Lb[li < w ? int64_t(li) * c + li : 0]) : T(0);
     // rows below in blocks of kSoaRows: each block's sum (ascending rows)
     // is formed on its own and then subtracted, the same order as the
-    // batch-interleaved kernels, so both layouts give identical bits
-    for (int rb = w; rb < c; rb += kSoaRows) {
-        const int re = min(c, rb + kSoaRows);
+    // batch-interleaved kernels, so both layouts give identical bits.  The
+    // next block's entries of L and values x are in flight while the
+    // current block is summed, and the row indices one block earlier still.
+    static_assert(kSoaRows == kBwdRows, "one staging round per row block");
+    auto load_l = [&](int i0, T (&v)[kBwdRows]) {
+        const int i = i0 + sr;
+#pragma unroll
+        for (int q = 0; q < kBwdRows; q++) {
+            const int j = sg + NG * q;
+            v[q] = ldz(Lb, int64_t(j) * c + i, i < c && j < w);
+        }
+    };
+    auto load_r = [&](int i0) { return ldz(R, i0 + sr, sg == 0 && i0 + sr < c); };
+    auto load_x = [&](int i0, int ri, T (&xv)[NR]) {
+        const bool xo = sg == 0 && i0 + sr < c;
+#pragma unroll
+        for (int r = 0; r < NR; r++) xv[r] = ldz(Ys, vix<SOA>(b, ri, r0 + r, n, nrhs), xo);
+    };
+    T vc[kBwdRows], xc[NR];
+    int rnext = 0;
+    if (w < c) {
+        load_l(w, vc);
+        load_x(w, load_r(w), xc);
+        rnext = load_r(w + kBwdRows);
+    }
+    for (int rb = w; rb < c; rb += kBwdRows) {
+        T vn[kBwdRows], xn[NR];
+        const bool more = rb + kBwdRows < c;
+        if (more) {
+            load_l(rb + kBwdRows, vn);
+            load_x(rb + kBwdRows, rnext, xn);
+            rnext = load_r(rb + 2 * kBwdRows);
+        }
+#pragma unroll
+        for (int q = 0; q < kBwdRows; q++) {
+            const int j = sg + NG * q;
+            if (j < w) Ls[seg][sr][j] = vc[q];
+        }
+        if (sg == 0 && rb + sr < c) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) xs[seg][sr][r] = xc[r];
+        }
+        wave_sync_solve();
         T p[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) p[r] = T(0);
-        for (int i0 = rb; i0 < re; i0 += kBwdRows) {
-            const int i = i0 + sr;
-            {
-                // every column of this lane's staging share in flight at once
-                T v[kBwdRows];
+        const int nr = min(kBwdRows, c - rb);
+        if (li < w) {
+            for (int t = 0; t < nr; t++) {
+                const T l = T(Ls[seg][t][li]);
 #pragma unroll
-                for (int q = 0; q < kBwdRows; q++) {
-                    const int j = sg + NG * q;
-                    v[q] = ldz(Lb, int64_t(j) * c + i, i < re && j < w);
-                }
-#pragma unroll
-                for (int q = 0; q < kBwdRows; q++) {
-                    const int j = sg + NG * q;
-                    if (j < w) Ls[seg][sr][j] = v[q];
-                }
-                const bool xo = sg == 0 && i < re;
-                const int ri = ldz(R, i, xo);
-#pragma unroll
-                for (int r = 0; r < NR; r++) {
-                    const T xv = ldz(Ys, vix<SOA>(b, ri, r0 + r, n, nrhs), xo);
-                    if (xo) xs[seg][sr][r] = xv;
-                }
+                for (int r = 0; r < NR; r++) p[r] += l * xs[seg][t][r];
             }
-            wave_sync_solve();
-            const int nr = min(kBwdRows, re - i0);
-            if (li < w) {
-                for (int t = 0; t < nr; t++) {
-                    const T l = T(Ls[seg][t][li]);
-#pragma unroll
-                    for (int r = 0; r < NR; r++) p[r] += l * xs[seg][t][r];
-                }
-            }
-            wave_sync_solve();
         }
+        wave_sync_solve();
 #pragma unroll
         for (int r = 0; r < NR; r++) acc[r] -= p[r];
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < kBwdRows; q++) vc[q] = vn[q];
+#pragma unroll
+            for (int r = 0; r < NR; r++) xc[r] = xn[r];
+        }
     }
     for (int i1 = w; i1 > 0; i1 -= kBwdRows) {
         const int i0 = max(0, i1 - kBwdRows);
@@ -757,17 +791,28 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
             }
         }
         __syncthreads();
-        // rows below the panel
+        // rows below the panel, products by ascending column; a full panel
+        // has the row's 64 entries of L in flight before the products
         for (int i = c0 + kb + tid; i < c; i += kSnThreadsF) {
+            const T *Lr = Lb + int64_t(c0) * c + i;
             T a[NR];
 #pragma unroll
             for (int r = 0; r < NR; r++) a[r] = v[i][r];
-            const T *Lr = Lb + int64_t(c0) * c + i;
-#pragma unroll 16
-            for (int t = 0; t < kb; t++) {
-                const T l = Lr[int64_t(t) * c];
+            if (kb == kP) {
+                T l[kP];
 #pragma unroll
-                for (int r = 0; r < NR; r++) a[r] -= l * v[c0 + t][r];
+                for (int t = 0; t < kP; t++) l[t] = Lr[int64_t(t) * c];
+#pragma unroll
+                for (int t = 0; t < kP; t++)
+#pragma unroll
+                    for (int r = 0; r < NR; r++) a[r] -= l[t] * v[c0 + t][r];
+            } else {
+#pragma unroll 16
+                for (int t = 0; t < kb; t++) {
+                    const T l = Lr[int64_t(t) * c];
+#pragma unroll
+                    for (int r = 0; r < NR; r++) a[r] -= l * v[c0 + t][r];
+                }
             }
 #pragma unroll
             for (int r = 0; r < NR; r++) v[i][r] = a[r];
