@@ -732,17 +732,23 @@ __host__ __device__ inline int64_t syrk_pairs(int c, const SyrkRegion &r) {
 }
 
 // Trailing update F[i, j] -= sum_t P[i, t] P[j, t] over the lower 64 x 64
-// tiles of a region, P = panel columns after the TRSM, K in chunks of 64
+// tiles of a region, P = panel columns after the TRSM, K in chunks of KC
 // through LDS; MFMA 16x16x4 with four waves of 32 x 32.  The MFMA's row
 // index runs over matrix columns so that each lane group writes 16
-// consecutive rows of one column (column-major storage).
+// consecutive rows of one column (column-major storage).  The tile's
+// current entries are read at the start, so that their latency overlaps
+// the products.  FP64 takes chunks of 32 (32 KiB of LDS, more workgroups
+// per CU), FP32 chunks of 64.
+template <typename T> struct SyrkKC { static constexpr int value = sizeof(T) == 8 ? 32 : 64; };
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int K0, int k,
     int outer, T *__restrict__ L, int64_t Lsize, T *__restrict__ U, int64_t Usize) {
+    constexpr int KC = SyrkKC<T>::value;
+    constexpr int QN = KC / 4;                // chunk rows per thread and operand
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sI = reinterpret_cast<T *>(smem_raw);  // [t][i] panel rows of tile I
-    T *sJ = sI + kTile * kTile;               // [t][j] panel rows of tile J
+    T *sJ = sI + KC * kTile;                  // [t][j] panel rows of tile J
     const int s = list[blockIdx.y];
     const int b = blockIdx.z;
     const SnDesc d = sn[s];
@@ -763,12 +769,12 @@ __global__ __launch_bounds__(256) void k_syrk(
     const int li = tid & 63, lt = tid >> 6;
     const bool rowok = row0 + li < c, colok = col0 + li < R.cend;
     // panel chunk kc: thread (li, lt) holds rows row0 + li / col0 + li of
-    // panel columns k0 + kc + lt + 4q, q < 16, in registers
-    T rI[16], rJ[16];
+    // panel columns k0 + kc + lt + 4q, q < QN, in registers
+    T rI[QN], rJ[QN];
     auto load_chunk = [&](int kc) {
-        const int kb = min(kTile, R.kw - kc);
+        const int kb = min(KC, R.kw - kc);
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
+        for (int q = 0; q < QN; q++) {
             const int t = lt + 4 * q;
             const T *pc = Lb + int64_t(R.k0 + kc + t) * c;
             rI[q] = (t < kb && rowok) ? pc[row0 + li] : T(0);
@@ -778,17 +784,32 @@ __global__ __launch_bounds__(256) void k_syrk(
     typename Mma<T>::acc_t acc[2][2];
     acc_zero<T>(acc);
     load_chunk(0);
-    for (int kc = 0; kc < R.kw; kc += kTile) {
-        const int kb = min(kTile, R.kw - kc);
+    // the tile's entries (absent ones read from the front's first entry)
+    T cur[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int q = 0; q < 2; q++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                int jj, ii;
+                tile_pos<T>(a, q, r, jj, ii);
+                const int j = col0 + jj, i = row0 + ii;
+                const bool ok = i < c && j < R.cend && i >= j;
+                const T *src = ok ? front_col(Lb, Ub, c, w, m, j) + i : Lb;
+                cur[a][q][r] = *src;
+            }
+    for (int kc = 0; kc < R.kw; kc += KC) {
+        const int kb = min(KC, R.kw - kc);
         const int kbr = (kb + 3) & ~3;
         if (kc > 0) __syncthreads();  // the previous chunk's products are done
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
+        for (int q = 0; q < QN; q++) {
             sI[(lt + 4 * q) * kTile + li] = rI[q];
             sJ[(lt + 4 * q) * kTile + li] = rJ[q];
         }
         __syncthreads();
-        if (kc + kTile < R.kw) load_chunk(kc + kTile);  // in flight during the MFMAs
+        if (kc + KC < R.kw) load_chunk(kc + KC);  // in flight during the MFMAs
         tile_mma(sJ, sI, kbr, acc);
     }
 #pragma unroll
@@ -802,7 +823,7 @@ __global__ __launch_bounds__(256) void k_syrk(
                 const int j = col0 + jj, i = row0 + ii;
                 if (i < c && j < R.cend && i >= j) {
                     T *pcol = front_col(Lb, Ub, c, w, m, j);
-                    pcol[i] -= acc[a][q][r];
+                    pcol[i] = cur[a][q][r] - acc[a][q][r];
                 }
             }
 }
@@ -1030,7 +1051,7 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
             break;
         case FLaunch::Syrk:
             hipLaunchKernelGGL(k_syrk<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),
-                               size_t(f.lds) * sizeof(T), fst, D->sn, D->lvl_big + f.list0,
+                               size_t(2 * SyrkKC<T>::value * kTile) * sizeof(T), fst, D->sn, D->lvl_big + f.list0,
                                f.K0, f.k, f.outer, L, P->Lsize, U, P->Usize);
             break;
         default:
