@@ -329,42 +329,50 @@ constexpr int kFrontRegMaxC = 64;
 
 // Factor and invert the kb x kb diagonal block (kb <= 64) whose top-left
 // corner is (r0, r0) of a column-major L block, with one workgroup of 256
-// threads.  Lane i of wave g keeps row i of columns 16 g .. 16 g + 15, of
-// the block (f) and of its inverse X = L^{-1} (x), in registers.  Step j
-// forms the pivot and column j of L (i > j: L_ij = F_ij / L_jj), every
-// later column t takes F_it -= L_ij L_tj, and every row i > j of X takes
-// X_i. -= (L_ij / L_jj) X_j. while row j is scaled by 1 / L_jj.  Columns
-// go in blocks of 16, one per wave: the owning wave runs the block's 16
-// steps back to back (its own columns need nothing from the other waves),
-// publishing each column of L and 1 / L_jj in LDS; after one barrier the
-// other waves replay the 16 steps on their own registers (later columns: f,
-// earlier columns: x).  Every entry sees the same operations in the same
-// order as with a barrier per step.  A pivot that fails d > 0 is recorded
-// (smallest 1-based step wins) and replaced by 1.  The factor is written
-// back (zeros above the diagonal) and the inverse to PIg column-major
-// (PIg[col * 64 + i] = X[i][col]), and to Dg as well when given.
-constexpr int kDiagLds = 2 * 16 * kTile + 2 * 16 + 4 * 16;  // columns x 2 blocks, 1/L_jj, X rows
+// threads.
+//   factor   lane i of wave g keeps row i of columns 16 g .. 16 g + 15 in
+//            registers (f).  Step j forms the pivot and column j of L
+//            (i > j: L_ij = F_ij / L_jj) and every later column t takes
+//            F_it -= L_ij L_tj.  Columns go in blocks of 16, one per wave:
+//            the owning wave runs the block's 16 steps back to back (its own
+//            columns need nothing from the other waves), publishing each
+//            column of L in LDS; after one barrier the waves of later
+//            columns replay the 16 steps on their registers.  Every entry
+//            sees the same operations in the same order as with a barrier
+//            per step.  A pivot that fails d > 0 is recorded (smallest
+//            1-based step wins) and replaced by 1.
+//   inverse  X = L^{-1} by 16 x 16 blocks once L is complete: wave g inverts
+//            its diagonal block by forward substitution (rows in order,
+//            X_kk = 1 / L_kk, row k broadcast through LDS), then the blocks
+//            below the diagonal by distance d = 1, 2, 3 from it:
+//            X_IJ = -X_II (sum_{K=J}^{I-1} L_IK X_KJ), one block per wave,
+//            the 16 x 16 x 16 products on the matrix cores.
+// Past kb the block is taken as the identity.  The factor is written back
+// (zeros above the diagonal) and the inverse to PIg column-major
+// (PIg[col * 64 + i] = X[i][col], zero outside the kb x kb block), and to Dg
+// as well when given.
+constexpr int kDiagLds = 2 * kTile * kTile + kTile + 4 * 16 * 16;  // L (column buffers first), X, 1/L_jj, T
 
 template <typename T>
 __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *lds, T *PIg, T *Dg,
                                                int col0, int32_t *info_b) {
-    T *cbuf = lds;                    // [2][16][64] columns of L, by block parity
-    T *rvb = lds + 2 * 16 * kTile;    // [2][16] 1 / L_jj
-    T *xrw = rvb + 2 * 16;            // [4][16] row j of X, one slot per wave
+    T *cbuf = lds;                  // factor: [2][16][64] columns of L, by block parity
+    T *Lsh = lds;                   // inverse: L, 64 x 64 column-major
+    T *Xsh = lds + kTile * kTile;   // X, 64 x 64 column-major
+    T *rv = Xsh + kTile * kTile;    // [64] 1 / L_jj (1 past kb)
+    T *Tsh = rv + kTile;            // [4][16][16] one product per wave
     const int tid = threadIdx.x, li = tid & 63, g = tid >> 6;
     const int gu = __builtin_amdgcn_readfirstlane(g);  // the wave's index, as a scalar
-    T *xw = xrw + 16 * gu;
-    T f[16], x[16];
+    T f[16];
 #pragma unroll
     for (int tt = 0; tt < 16; tt++) {
         const int col = 16 * g + tt;
         f[tt] = (li < kb && col < kb) ? Lb[int64_t(r0 + col) * c + r0 + li] : (li == col ? T(1) : T(0));
-        x[tt] = li == col ? T(1) : T(0);
     }
+    if (gu == 0) rv[li] = T(1);
     for (int J = 0; J < 4; J++) {
         if (16 * J >= kb) break;
         T *cbJ = cbuf + (J & 1) * 16 * kTile;
-        T *rvJ = rvb + (J & 1) * 16;
         if (gu == J) {
 #pragma unroll
             for (int jj = 0; jj < 16; jj++) {
@@ -379,30 +387,20 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
                     f[jj] = lij;
                     cbJ[jj * kTile + li] = lij;
                     if (li == j) {
-                        rvJ[jj] = rinv;
+                        rv[j] = rinv;
                         if (bad) atomicMin(info_b, col0 + j + 1);
-#pragma unroll
-                        for (int tt = 0; tt < 16; tt++) xw[tt] = x[tt];
                     }
                     wave_fence_sync();
-                    const T lx = li > j ? lij * rinv : T(0);
-                    const T sx = li == j ? rinv : T(1);
-                    T cv[16], xv[16];
+                    T cv[16];
 #pragma unroll
-                    for (int tt = 0; tt < 16; tt++) {
-                        cv[tt] = cbJ[jj * kTile + 16 * J + tt];
-                        xv[tt] = xw[tt];
-                    }
+                    for (int tt = 0; tt < 16; tt++) cv[tt] = cbJ[jj * kTile + 16 * J + tt];
 #pragma unroll
-                    for (int tt = 0; tt < 16; tt++) {
+                    for (int tt = 0; tt < 16; tt++)
                         if (tt > jj) f[tt] = fma(-lij, cv[tt], f[tt]);
-                        x[tt] = fma(-lx, xv[tt], x[tt] * sx);
-                    }
-                    wave_fence_sync();  // row j of X is read before the next step rewrites it
                 }
             }
         }
-        __syncthreads();  // the block's columns of L and 1 / L_jj are visible
+        __syncthreads();  // the block's columns of L are visible
         if (gu > J) {
 #pragma unroll
             for (int jj = 0; jj < 16; jj++) {
@@ -416,36 +414,92 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
                     for (int tt = 0; tt < 16; tt++) f[tt] = fma(-lij, cv[tt], f[tt]);
                 }
             }
-        } else if (gu < J) {
+        }
+    }
+    __syncthreads();  // every replay has read the column buffers
 #pragma unroll
-            for (int jj = 0; jj < 16; jj++) {
-                const int j = 16 * J + jj;
-                if (j < kb) {
-                    const T rinv = rvJ[jj];
-                    const T lij = cbJ[jj * kTile + li];
-                    const T lx = li > j ? lij * rinv : T(0);
-                    const T sx = li == j ? rinv : T(1);
-                    if (li == j) {
+    for (int tt = 0; tt < 16; tt++) {
+        const int col = 16 * g + tt;
+        if (li < kb && col < kb) Lb[int64_t(r0 + col) * c + r0 + li] = li >= col ? f[tt] : T(0);
+        Lsh[col * kTile + li] = li >= col ? f[tt] : T(0);
+    }
+    // diagonal block g of X: lane 16 g + i keeps row i, x[t] = X[16 g + i][16 g + t]
+    {
+        const int ii = li - 16 * g;
+        const bool mine = ii >= 0 && ii < 16;
+        T *xrow = Tsh + 256 * gu;
+        T x[16];
 #pragma unroll
-                        for (int tt = 0; tt < 16; tt++) xw[tt] = x[tt];
-                    }
-                    wave_fence_sync();
-                    T xv[16];
+        for (int t = 0; t < 16; t++) x[t] = mine && t == ii ? T(1) : T(0);
 #pragma unroll
-                    for (int tt = 0; tt < 16; tt++) xv[tt] = xw[tt];
+        for (int k = 0; k < 16; k++) {
+            if (mine && ii == k) {
+                const T r = rv[16 * g + k];
 #pragma unroll
-                    for (int tt = 0; tt < 16; tt++) x[tt] = fma(-lx, xv[tt], x[tt] * sx);
-                    wave_fence_sync();
+                for (int t = 0; t < 16; t++) {
+                    x[t] *= r;
+                    xrow[t] = x[t];
                 }
             }
+            wave_fence_sync();
+            T xk[16];
+#pragma unroll
+            for (int t = 0; t < 16; t++) xk[t] = xrow[t];
+            if (mine && ii > k) {
+                const T lik = f[k];
+#pragma unroll
+                for (int t = 0; t < 16; t++) x[t] = fma(-lik, xk[t], x[t]);
+            }
+            wave_fence_sync();  // row k is read before the next one is written
         }
+        if (mine) {
+#pragma unroll
+            for (int t = 0; t < 16; t++) Xsh[(16 * g + t) * kTile + li] = x[t];
+        }
+        // zeros above the diagonal blocks
+#pragma unroll
+        for (int tt = 0; tt < 16; tt++)
+            if (li < 16 * g) Xsh[(16 * g + tt) * kTile + li] = T(0);
+    }
+    __syncthreads();
+    const int lk = li >> 4, lm = li & 15;
+    for (int dd = 1; dd < 4; dd++) {
+        if (gu + dd < 4) {
+            const int Jb = gu, Ib = gu + dd;
+            T *Tw = Tsh + 256 * gu;
+            // T = sum_K L_IK X_KJ: C[m][n] = sum_k A(m, k) B(n, k) with
+            // A(m, k) = L[16 I + m][16 K + k], B(n, k) = X[16 K + k][16 J + n]
+            typename Mma<T>::acc_t acc = Mma<T>::zero();
+            for (int Kb = Jb; Kb < Ib; Kb++) {
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 4) {
+                    const T av = Lsh[(16 * Kb + kk + lk) * kTile + 16 * Ib + lm];
+                    const T bv = Xsh[(16 * Jb + lm) * kTile + 16 * Kb + kk + lk];
+                    acc = Mma<T>::mma(av, bv, acc);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) Tw[Mma<T>::row(lk, r) * 16 + lm] = acc[r];
+            wave_fence_sync();
+            // X_IJ = -X_II T: A(m, k) = X[16 I + m][16 I + k], B(n, k) = T[k][n]
+            typename Mma<T>::acc_t acc2 = Mma<T>::zero();
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+                const T av = Xsh[(16 * Ib + kk + lk) * kTile + 16 * Ib + lm];
+                const T bv = Tw[(kk + lk) * 16 + lm];
+                acc2 = Mma<T>::mma(av, bv, acc2);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                Xsh[(16 * Jb + lm) * kTile + 16 * Ib + Mma<T>::row(lk, r)] = -acc2[r];
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int tt = 0; tt < 16; tt++) {
         const int col = 16 * g + tt;
         const bool in = li < kb && col < kb;
-        if (in) Lb[int64_t(r0 + col) * c + r0 + li] = li >= col ? f[tt] : T(0);
-        const T xv = (in && li >= col) ? x[tt] : T(0);
+        const T xv = (in && li >= col) ? Xsh[col * kTile + li] : T(0);
         PIg[col * kTile + li] = xv;
         if (Dg) Dg[col * kTile + li] = xv;
     }
@@ -647,11 +701,16 @@ __global__ __launch_bounds__(256) void k_potrf(
 }
 
 // Panel rows below the diagonal block: X <- X L_kk^{-T} = X (L_kk^{-1})^T,
-// a 64 x 64 x kb product per workgroup on the matrix cores.
+// a 64 x 64 x kb product per 64-row tile on the matrix cores.  A workgroup
+// takes nt consecutive tiles (nt = kTrsmTiles when the launch has tiles
+// enough to fill the chip that way, else 1): the inverse is staged once and
+// the next tile's rows are in flight while the current one is multiplied.
+constexpr int kTrsmTiles = 4;
+constexpr int64_t kTrsmMultiMin = 512;  // tiles of a launch from which nt = kTrsmTiles
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsm(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int k,
-    T *__restrict__ L, int64_t Lsize, const T *__restrict__ PI, int64_t pistride) {
+    T *__restrict__ L, int64_t Lsize, const T *__restrict__ PI, int64_t pistride, int nt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sX = reinterpret_cast<T *>(smem_raw);  // [t][r] panel rows
     T *sP = sX + kTile * kTile;               // [t][j] = inverse[j][t]
@@ -661,40 +720,52 @@ __global__ __launch_bounds__(256) void k_trsm(
     if (k >= d.w) return;
     const int kb = min(kTile, d.w - k);
     const int c = d.c;
-    const int r0 = k + kb + blockIdx.x * kTile;
-    if (r0 >= c) return;
+    const int rfirst = k + kb + blockIdx.x * nt * kTile;
+    if (rfirst >= c) return;
     T *Lb = L + int64_t(b) * Lsize + d.loff;
     const T *PIg = PI + int64_t(b) * pistride + int64_t(blockIdx.y) * kTile * kTile;
     const int tid = threadIdx.x;
     const int kbr = (kb + 3) & ~3;
     const int li = tid & 63, lt = tid >> 6;
-    const bool rowok = r0 + li < c;
-    T rX[16], rP[16];
+    T rX[16];
+    auto load_x = [&](int r0) {
+        const bool rowok = r0 + li < c;
 #pragma unroll
-    for (int q = 0; q < 16; q++) {
-        const int t = lt + 4 * q;
-        rX[q] = (t < kb && rowok) ? Lb[int64_t(k + t) * c + r0 + li] : T(0);
-        rP[q] = PIg[t * kTile + li];  // zero-padded, column-major inverse
+        for (int q = 0; q < 16; q++) {
+            const int t = lt + 4 * q;
+            rX[q] = (t < kb && rowok) ? Lb[int64_t(k + t) * c + r0 + li] : T(0);
+        }
+    };
+    {
+        T rP[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) rP[q] = PIg[(lt + 4 * q) * kTile + li];  // zero-padded
+        load_x(rfirst);
+#pragma unroll
+        for (int q = 0; q < 16; q++) sP[(lt + 4 * q) * kTile + li] = rP[q];
     }
+    for (int u = 0; u < nt; u++) {
+        const int r0 = rfirst + u * kTile;
+        if (r0 >= c) break;
+        if (u > 0) __syncthreads();  // the previous tile's products are done
 #pragma unroll
-    for (int q = 0; q < 16; q++) {
-        sX[(lt + 4 * q) * kTile + li] = rX[q];
-        sP[(lt + 4 * q) * kTile + li] = rP[q];
+        for (int q = 0; q < 16; q++) sX[(lt + 4 * q) * kTile + li] = rX[q];
+        __syncthreads();
+        if (u + 1 < nt && r0 + kTile < c) load_x(r0 + kTile);
+        typename Mma<T>::acc_t acc[2][2];
+        acc_zero<T>(acc);
+        tile_mma(sP, sX, kbr, acc);
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    int j, i;
+                    tile_pos<T>(a, q, r, j, i);
+                    if (j < kb && r0 + i < c) Lb[int64_t(k + j) * c + r0 + i] = acc[a][q][r];
+                }
     }
-    __syncthreads();
-    typename Mma<T>::acc_t acc[2][2];
-    acc_zero<T>(acc);
-    tile_mma(sP, sX, kbr, acc);
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int q = 0; q < 2; q++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                int j, i;
-                tile_pos<T>(a, q, r, j, i);
-                if (j < kb && r0 + i < c) Lb[int64_t(k + j) * c + r0 + i] = acc[a][q][r];
-            }
 }
 
 // Update region of a trailing-update launch for one front: columns
@@ -1044,11 +1115,13 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
                                D->sn, D->lvl_big + f.list0, f.k, L, P->Lsize, PI, pistride,
                                reinterpret_cast<T *>(N->dinv), P->dinv_size, N->info, P->nblk);
             break;
-        case FLaunch::Trsm:
-            hipLaunchKernelGGL(k_trsm<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),
-                               size_t(f.lds) * sizeof(T), st, D->sn, D->lvl_big + f.list0,
-                               f.k, L, P->Lsize, PI, pistride);
+        case FLaunch::Trsm: {
+            const int nt = f.gridx * f.nlist * B >= kTrsmMultiMin ? kTrsmTiles : 1;
+            hipLaunchKernelGGL(k_trsm<T>, dim3(unsigned((f.gridx + nt - 1) / nt), f.nlist, B),
+                               dim3(256), size_t(f.lds) * sizeof(T), st, D->sn,
+                               D->lvl_big + f.list0, f.k, L, P->Lsize, PI, pistride, nt);
             break;
+        }
         case FLaunch::Syrk:
             hipLaunchKernelGGL(k_syrk<T>, dim3(unsigned(f.gridx), f.nlist, B), dim3(256),
                                size_t(2 * SyrkKC<T>::value * kTile) * sizeof(T), fst, D->sn, D->lvl_big + f.list0,
