@@ -722,19 +722,21 @@ __global__ __launch_bounds__(64) void k_bwd_pan_fin(
 constexpr int kSnThreads = 512;   // backward: eight waves, two row chunks at a time
 constexpr int kSnWaves = kSnThreads / 64;
 constexpr int kSnRB = 16;         // rows per staging block of the backward sums
-constexpr int kSnThreadsF = 256;  // forward
+// forward: 512 threads in FP32 (more rows of a panel at once), 256 in FP64
+// (the row's 64 entries of L in flight take twice the registers)
+template <typename T> struct SnThreadsF { static constexpr int value = sizeof(T) == 4 ? 512 : 256; };
 
-// Forward: small workgroups (several per CU hide each other's latency);
-// every thread holds a share of the next panel's inverse block in flight
-// while the current panel is processed.
+// Forward: every thread holds a share of the next panel's inverse block in
+// flight while the current panel is processed.
 template <typename T, int NR, bool SOA>
-__global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
+__global__ __launch_bounds__(SnThreadsF<T>::value) void k_fwd_sn(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
     const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Dinv, int64_t dsize,
     T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     const int32_t *__restrict__ active) {
-    constexpr int DPT = kP * kP / kSnThreadsF;  // inverse-block entries per thread
+    constexpr int NTH = SnThreadsF<T>::value;
+    constexpr int DPT = kP * kP / NTH;  // inverse-block entries per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Ds = reinterpret_cast<T *>(smem_raw);               // D_p, as stored
     T(*v)[NR] = reinterpret_cast<T(*)[NR]>(Ds + kP * kP);  // front vector, c rows
@@ -748,8 +750,8 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
     const T *Db = Dinv + int64_t(b) * dsize + d.dinv;
     T dreg[DPT];
 #pragma unroll
-    for (int q = 0; q < DPT; q++) dreg[q] = Db[q * kSnThreadsF + tid];
-    for (int i = tid; i < c; i += kSnThreadsF) {
+    for (int q = 0; q < DPT; q++) dreg[q] = Db[q * NTH + tid];
+    for (int i = tid; i < c; i += NTH) {
         const int g0 = gptr[d.rowptr + i], g1 = gptr[d.rowptr + i + 1];
 #pragma unroll
         for (int r = 0; r < NR; r++) {
@@ -761,12 +763,12 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
     for (int c0 = 0; c0 < w; c0 += kP) {
         const int kb = min(kP, w - c0);
 #pragma unroll
-        for (int q = 0; q < DPT; q++) Ds[q * kSnThreadsF + tid] = dreg[q];
+        for (int q = 0; q < DPT; q++) Ds[q * NTH + tid] = dreg[q];
         __syncthreads();  // D_p staged, v complete
         if (c0 + kP < w) {
             const T *Dn = Db + int64_t(c0 / kP + 1) * kP * kP;
 #pragma unroll
-            for (int q = 0; q < DPT; q++) dreg[q] = Dn[q * kSnThreadsF + tid];
+            for (int q = 0; q < DPT; q++) dreg[q] = Dn[q * NTH + tid];
         }
         // y_p = D_p^{-1} v_p (the first panel sums over its kb rows, later
         // ones over all 64 with zeros past kb, as the panel kernels do)
@@ -793,7 +795,7 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
         __syncthreads();
         // rows below the panel, products by ascending column; a full panel
         // has the row's 64 entries of L in flight before the products
-        for (int i = c0 + kb + tid; i < c; i += kSnThreadsF) {
+        for (int i = c0 + kb + tid; i < c; i += NTH) {
             const T *Lr = Lb + int64_t(c0) * c + i;
             T a[NR];
 #pragma unroll
@@ -819,7 +821,7 @@ __global__ __launch_bounds__(kSnThreadsF) void k_fwd_sn(
         }
         __syncthreads();
     }
-    for (int i = w + tid; i < c; i += kSnThreadsF) {
+    for (int i = w + tid; i < c; i += NTH) {
 #pragma unroll
         for (int r = 0; r < NR; r++) FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)] = v[i][r];
     }
@@ -1663,7 +1665,7 @@ void sn_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
         const int nrr = std::min(kMaxRhsPanel, nrhs - r0);
         const size_t lds = (size_t(l.maxc_pan) * nrr + kP * kP) * sizeof(T);
 #define SPCHOL_FWDSN(NRV)                                                                      \
-    hipLaunchKernelGGL((k_fwd_sn<T, NRV, SOA>), g, dim3(kSnThreadsF), lds, st, D->sn,            \
+    hipLaunchKernelGGL((k_fwd_sn<T, NRV, SOA>), g, dim3(SnThreadsF<T>::value), lds, st, D->sn,   \
                        D->slv_pan + l.pan0, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->dinv),   \
                        P->dinv_size, as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active)
         if (nrr == 1) SPCHOL_FWDSN(1);
