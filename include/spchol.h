@@ -181,7 +181,11 @@ void sc_plan_destroy(sc_plan_t *plan);
 
 /*
  * Allocate device storage for `batch` factors of the plan's pattern in the
- * given precision (SC_F64, or SC_F32: FP32 factor with FP32 accumulation).
+ * given precision (SC_F64, or SC_F32: FP32 factor with FP32 accumulation),
+ * and a private non-blocking stream with two events on the current device
+ * (the factorization runs part of the trailing updates of large fronts
+ * there, ordered against the caller's stream by those events; a call
+ * still returns with all its work ordered on the caller's stream).
  * Uploads the plan to the current device if not done yet.
  * Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
  */
