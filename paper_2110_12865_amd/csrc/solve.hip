@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256) void k_pan_gather(
 // p + 1 when there is one; it then also forms y_{p+1} = D_{p+1}^{-1} v_{p+1}
 // (every contribution to v_{p+1} is in once this update is done).
 template <typename T, int NR, bool SOA>
-__global__ __launch_bounds__(64) void k_fwd_panel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_fwd_panel(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
     const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Dinv,
     int64_t dsize, T *__restrict__ Ys, T *__restrict__ FV, int64_t n,
@@ -537,11 +537,21 @@ __global__ __launch_bounds__(64) void k_fwd_panel(
         const T *Lr = L + int64_t(b) * Lsize + d.loff + int64_t(c0) * c + rowc;
 #pragma unroll
         for (int r = 0; r < NR; r++) v[r] = FV[vix<SOA>(b, d.rowptr + rowc, r0 + r, fvsize, nrhs)];
-#pragma unroll 8
-        for (int t = 0; t < kb; t++) {
-            const T l = T(Lr[int64_t(t) * c]);
+        if (kb == kP) {  // a full panel: the row's 64 entries in flight at once
+            T l[kP];
 #pragma unroll
-            for (int r = 0; r < NR; r++) v[r] -= l * yv[t][r];
+            for (int t = 0; t < kP; t++) l[t] = Lr[int64_t(t) * c];
+#pragma unroll
+            for (int t = 0; t < kP; t++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) v[r] -= l[t] * yv[t][r];
+        } else {
+#pragma unroll 8
+            for (int t = 0; t < kb; t++) {
+                const T l = T(Lr[int64_t(t) * c]);
+#pragma unroll
+                for (int r = 0; r < NR; r++) v[r] -= l * yv[t][r];
+            }
         }
         if (rok) {
 #pragma unroll
@@ -559,12 +569,13 @@ __global__ __launch_bounds__(64) void k_fwd_panel(
         T y[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) y[r] = T(0);
-#pragma unroll 8
-        for (int i = 0; i < kP; i++) {
-            const T di = D[int64_t(i) * kP + lane];
+        T dv[kP];  // column `lane` of the block's inverse, all in flight
 #pragma unroll
-            for (int r = 0; r < NR; r++) y[r] += di * vn[i][r];
-        }
+        for (int i = 0; i < kP; i++) dv[i] = D[int64_t(i) * kP + lane];
+#pragma unroll
+        for (int i = 0; i < kP; i++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) y[r] += dv[i] * vn[i][r];
 #pragma unroll
         for (int r = 0; r < NR; r++) Ys[vix<SOA>(b, d.first + c1 + lane, r0 + r, n, nrhs)] = y[r];
     }
@@ -605,38 +616,53 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = T(0);
     const int w0 = rb + 64 * wv, w1 = min(c, w0 + 64);
-    for (int i0 = w0; i0 < w1; i0 += RB) {
+    // every row block of this wave's 64 rows in flight at once (entries of
+    // L, then the rows' positions and values x)
+    constexpr int NB = 64 / RB;
+    T lv[NB][16];
+    T xq[NB][NR];
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+        const int i = w0 + k * RB + sr;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int t = sg + 4 * q;
+            lv[k][q] = ldz(Lb, int64_t(t) * c + i, i < w1 && t < kb);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+        const int i = w0 + k * RB + sr;
+        const bool xo = sg == 0 && i < w1;
+        const int64_t pos = i < d.w ? d.first + i : ldz(R, i, xo && i >= d.w);
+#pragma unroll
+        for (int r = 0; r < NR; r++) xq[k][r] = ldz(Ys, vix<SOA>(b, pos, r0 + r, n, nrhs), xo);
+    }
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+        const int i0 = w0 + k * RB;
         const int i = i0 + sr;
-        {
-            T v[16];
+        if (i0 < w1) {
 #pragma unroll
             for (int q = 0; q < 16; q++) {
                 const int t = sg + 4 * q;
-                v[q] = ldz(Lb, int64_t(t) * c + i, i < w1 && t < kb);
+                if (i < w1 && t < kb) Ls[wv][sr][t] = lv[k][q];
             }
+            if (sg == 0 && i < w1) {
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const int t = sg + 4 * q;
-                if (i < w1 && t < kb) Ls[wv][sr][t] = v[q];
+                for (int r = 0; r < NR; r++) xs[wv][sr][r] = xq[k][r];
             }
-            const bool xo = sg == 0 && i < w1;
-            const int64_t pos = i < d.w ? d.first + i : ldz(R, i, xo && i >= d.w);
+            wave_sync_solve();  // each wave stages and reads its own rows
+            const int nr = min(RB, w1 - i0);
+            if (lane < kb) {
+                for (int q = 0; q < nr; q++) {
+                    const T l = T(Ls[wv][q][lane]);
 #pragma unroll
-            for (int r = 0; r < NR; r++) {
-                const T xv = ldz(Ys, vix<SOA>(b, pos, r0 + r, n, nrhs), xo);
-                if (xo) xs[wv][sr][r] = xv;
+                    for (int r = 0; r < NR; r++) acc[r] += l * xs[wv][q][r];
+                }
             }
+            wave_sync_solve();
         }
-        wave_sync_solve();  // each wave stages and reads its own rows
-        const int nr = min(RB, w1 - i0);
-        if (lane < kb) {
-            for (int q = 0; q < nr; q++) {
-                const T l = T(Ls[wv][q][lane]);
-#pragma unroll
-                for (int r = 0; r < NR; r++) acc[r] += l * xs[wv][q][r];
-            }
-        }
-        wave_sync_solve();
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
@@ -654,7 +680,7 @@ __global__ __launch_bounds__(256) void k_bwd_pan_part(
 // sums, in chunk order), right-hand sides r0 .. r0 + NR - 1.  Item =
 // (supernode, matrix); one wave, lane t owns column c0 + t.
 template <typename T, int NR, bool SOA>
-__global__ __launch_bounds__(64) void k_bwd_pan_fin(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_bwd_pan_fin(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int p, int r0,
     const T *__restrict__ Dinv, int64_t dsize, T *__restrict__ Ys, int64_t n,
     const T *__restrict__ PART, int64_t psize, int nrhs,
@@ -673,21 +699,31 @@ __global__ __launch_bounds__(64) void k_bwd_pan_fin(
     const int t = threadIdx.x;
     // the inverse block, coalesced into LDS: Dt[j][i] = D[j * 64 + i]
     const T *Dp = Dinv + int64_t(b) * dsize + d.dinv + int64_t(p) * kP * kP;
-    for (int e0 = 0; e0 < kP * kP; e0 += 16 * 64) {
-        T v[16];  // 16 loads per thread in flight at once
+    {
+        T v[kP];  // the whole block in flight at once, 64 loads per thread
 #pragma unroll
-        for (int q = 0; q < 16; q++) v[q] = Dp[e0 + q * 64 + t];
+        for (int q = 0; q < kP; q++) v[q] = Dp[q * 64 + t];
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int e = e0 + q * 64 + t;
-            Dt[(e >> 6) * (kP + 1) + (e & 63)] = v[q];
-        }
+        for (int q = 0; q < kP; q++) Dt[q * (kP + 1) + t] = v[q];
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) {
+        // the chunks' partial sums 16 at a time, all loads of a group in
+        // flight before they are added (in chunk order)
+        // (clamped in-bounds addresses; only the chunks that exist are added)
+        const int tc = t < kb ? t : 0;
         T s0 = T(0);
-        for (int q = 0; q < nch; q++)
-            s0 += ldz(PART, vix<SOA>(b, d.part + int64_t(q) * kP + t, r0 + r, psize, nrhs), t < kb);
+        for (int q0 = 0; q0 < nch; q0 += 16) {
+            T pv[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int q = q0 + u < nch ? q0 + u : nch - 1;
+                pv[u] = PART[vix<SOA>(b, d.part + int64_t(q) * kP + tc, r0 + r, psize, nrhs)];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++)
+                if (q0 + u < nch) s0 += pv[u];
+        }
         rhs[t][r] = t < kb ? ldz(Ys, vix<SOA>(b, d.first + c0 + t, r0 + r, n, nrhs), t < kb) - s0
                            : T(0);
     }

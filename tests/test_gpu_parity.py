@@ -43,6 +43,9 @@ def _cases():
         ("random_200_lds_whole", lambda: W.random_spd(200, 0.5, seed=23), {"small_front": 200}),
         ("grid3d_16x15x14_lds_192", lambda: W.small_grid((16, 15, 14), "nd", seed=24),
          {"small_front": 192}),
+        # one 700-column front: the trailing update of its first 256-column
+        # block is split between the two streams (lookahead)
+        ("random_700_lookahead", lambda: W.random_spd(700, 0.9, seed=25), {"small_front": 1}),
         # fundamental supernodes only
         ("grid3d_9^3_norelax", lambda: W.small_grid((9, 9, 9), "nd", seed=20), {"relax": 0}),
         ("n1", lambda: W.random_spd(1, 0.0, seed=21), {}),
@@ -70,10 +73,14 @@ def test_factor_solve_parity(name, make, opts):
     ferr = oracle.factor_error(sym.Lcolptr, Lg, Lx)
     xerr = oracle.forward_error(x[0], xo)
     relres, eta = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[0], x[0], w.b[0])
-    log("  factor err %.2e  x err %.2e  relres %.2e" % (ferr, xerr, relres.max()))
+    # the oracle's own residual bounds what FP64 elimination attains on the
+    # system (the dense 700 case: 7.9e-13)
+    orel, _ = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[0], xo, w.b[0])
+    log("  factor err %.2e  x err %.2e  relres %.2e (oracle %.2e)"
+        % (ferr, xerr, relres.max(), orel.max()))
     assert ferr <= TOL_L
     assert xerr <= TOL_X
-    assert relres.max() <= 1e-13
+    assert relres.max() <= max(1e-13, 2.0 * orel.max())
 
 
 def test_golden_fixture():
