@@ -56,6 +56,30 @@ template <> struct Mma<float> {
 __device__ inline double dsqrt(double x) { return sqrt(x); }
 __device__ inline float dsqrt(float x) { return sqrtf(x); }
 
+// Pivot of the diagonal-block factor, on its serial chain: rinv = 1 /
+// sqrt(d) from the hardware estimate refined by Newton steps for the
+// reciprocal square root, rinv <- rinv + rinv (1 - d rinv^2) / 2 (two in
+// FP64, one in FP32), and ljj = d rinv; within a unit or two in the last
+// place of the correctly rounded values, in far fewer dependent operations
+// than a square root followed by a division.
+__device__ inline void pivot_rs(double d, double &ljj, double &rinv) {
+    double r = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; it++) {
+        const double e = fma(-(d * r), r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    rinv = r;
+    ljj = d * r;
+}
+__device__ inline void pivot_rs(float d, float &ljj, float &rinv) {
+    float r = __builtin_amdgcn_rsqf(d);
+    const float e = fmaf(-(d * r), r, 1.0f);
+    r = fmaf(0.5f * r, e, r);
+    rinv = r;
+    ljj = d * r;
+}
+
 // Column j of a front: L columns live in the c x w block, update columns in
 // the m x m block.  Returns a pointer p with the front entry (i, j) at p[i]
 // (only rows i >= j are ever touched for update columns).
@@ -381,8 +405,8 @@ __device__ __forceinline__ void wg_diag_factor(T *Lb, int c, int r0, int kb, T *
                     T djj = lane_bcast(f[jj], j);
                     const bool bad = !(djj > T(0));
                     if (bad) djj = T(1);
-                    const T ljj = dsqrt(djj);
-                    const T rinv = T(1) / ljj;
+                    T ljj, rinv;
+                    pivot_rs(djj, ljj, rinv);
                     const T lij = li == j ? ljj : (li > j ? f[jj] * rinv : T(0));
                     f[jj] = lij;
                     cbJ[jj * kTile + li] = lij;
