@@ -99,7 +99,7 @@ def leading_block(w, s, m):
     return colptr, hi.astype(np.int32), v, w.b[s][:, perm[:m]]
 
 
-def cpu_baseline(w, flops_full, nnzL_full, budget_flops=2.0e10):
+def cpu_baseline(w, flops_full, nnzL_full, budget_flops=5.0e10):
     """The CPU oracle (serial FP64) on a bounded sample of the workload.
 
     Whole systems are used when one costs at most the flop budget (as many
@@ -112,7 +112,7 @@ def cpu_baseline(w, flops_full, nnzL_full, budget_flops=2.0e10):
     n = p.n
     if flops_full <= budget_flops:
         sets = max(1, min(w.batch, int(budget_flops // max(flops_full, 1.0))))
-        sets = min(sets, 8)
+        sets = min(sets, 24)
         t0 = time.perf_counter()
         sym = oracle.symbolic(n, p.colptr, p.rowind, w.perm)
         t1 = time.perf_counter()
@@ -157,7 +157,7 @@ def cpu_baseline(w, flops_full, nnzL_full, budget_flops=2.0e10):
     }
 
 
-def cpu_baseline_group(ws, budget_s=8.0):
+def cpu_baseline_group(ws, budget_s=12.0):
     """The CPU oracle on whole value sets of every pattern of a group (one
     set of all patterns after another, until the time budget is spent)."""
     import oracle
