@@ -360,7 +360,7 @@ def main():
                          "(library default when omitted, negative: never)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
+        print("bench.py measures one GPU only: the library runs on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         return 2
 

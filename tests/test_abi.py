@@ -158,9 +158,9 @@ def check_supernode_invariants(plan, sym):
     assert set(np.unique(level)) == set(range(level.max() + 1))
 
 
-def test_config_sizes_match_survey_estimates():
-    """nnz(A), nnz(L) and flops of configs 0-2 (the generator and the
-    analysis agree with the independent oracle)."""
+def test_workload_sizes_and_fill_match_oracle():
+    """nnz(A) of the 32x32 grid and of the 512x512 mesh, and nnz(L) of both
+    (the generator and the analysis agree with the independent oracle)."""
     import paper_2110_12865_amd as S
     for idx, nnzA in ((0, 3008), (2, 1046529)):
         w = W.config(idx, batch=1)
