@@ -192,8 +192,9 @@ __global__ void k_anorm_final(const double *__restrict__ part, int nbk,
 }
 
 // Per-system reductions in two stages: kRB workgroups per system each sum
-// a contiguous slice of the system's rows (fixed tree), then the consumer
-// adds the kRB partials in slice order, so every result is bit-reproducible.
+// a contiguous slice of the system's rows (fixed tree), then one wave of the
+// consumer adds the partials (lane l: partials l, l + 64, ... in order, then
+// a fixed butterfly), so every result is bit-reproducible.
 constexpr int kRB = 32;
 
 __device__ inline double block_sum(double v, double *red) {
@@ -270,18 +271,24 @@ __global__ __launch_bounds__(256) void k_sums(
 
 // out[seg] = sum of the nsl partial sums of system seg in slice order
 // (component comp), out2[seg] the same for component comp + 1 when given
-__global__ void k_sums_final(const double *__restrict__ part, int nsl, int comp, int nseg,
-                             int per_matrix, const int32_t *__restrict__ active,
-                             double *__restrict__ out, double *__restrict__ out2) {
-    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_sums_final(
+    const double *__restrict__ part, int nsl, int comp, int nseg, int per_matrix,
+    const int32_t *__restrict__ active, double *__restrict__ out, double *__restrict__ out2) {
+    // one wave per system: lane l adds partials l, l + 64, ... in order and
+    // the lanes' sums meet in a fixed butterfly
+    const int sg = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (sg >= nseg || !active[sg / per_matrix]) return;
     double t = 0.0, t2 = 0.0;
-    for (int q = 0; q < nsl; q++) {
+    for (int q = lane; q < nsl; q += 64) {
         t += part[(int64_t(sg) * nsl + q) * 3 + comp];
         if (out2) t2 += part[(int64_t(sg) * nsl + q) * 3 + comp + 1];
     }
-    out[sg] = t;
-    if (out2) out2[sg] = t2;
+    t = wave_sum(t);
+    if (out2) t2 = wave_sum(t2);
+    if (lane == 0) {
+        out[sg] = t;
+        if (out2) out2[sg] = t2;
+    }
 }
 
 // Stop test for every system from the partial sums of r.r, b.b and x.x.
@@ -290,21 +297,26 @@ __global__ void k_sums_final(const double *__restrict__ part, int nsl, int comp,
 // is no longer updated) keeps its record.
 // iter > 0 takes ||b||_2 from the record of the first test (part holds no
 // b.b then).
-__global__ void k_check(const double *__restrict__ part, int nsl, int nseg, int nrhs, int nblk,
-                        const double *__restrict__ anorm, double tol, int iter,
-                        const int32_t *__restrict__ active, int32_t *__restrict__ conv,
-                        double *__restrict__ stat) {
-    const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_check(
+    const double *__restrict__ part, int nsl, int nseg, int nrhs, int nblk,
+    const double *__restrict__ anorm, double tol, int iter, const int32_t *__restrict__ active,
+    int32_t *__restrict__ conv, double *__restrict__ stat) {
+    // one wave per system, partial sums added as in k_sums_final
+    const int sg = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (sg >= nseg) return;
     const int b = sg / (nrhs * nblk), k = sg % nblk;
     if (!active[b] || conv[sg]) return;
     double a = 0.0, c = 0.0, d = 0.0;
-    for (int q = 0; q < nsl; q++) {
+    for (int q = lane; q < nsl; q += 64) {
         const double *o = part + (int64_t(sg) * nsl + q) * 3;
         a += o[0];
         if (iter == 0) c += o[1];
         d += o[2];
     }
+    a = wave_sum(a);
+    c = wave_sum(c);
+    d = wave_sum(d);
+    if (lane != 0) return;
     const double rn = sqrt(a), xn = sqrt(d);
     const double bn = iter == 0 ? sqrt(c) : stat[int64_t(sg) * 6 + 4];
     const double relres = bn > 0.0 ? rn / bn : rn;
@@ -475,6 +487,7 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
     const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
     const dim3 vgrid(unsigned((n + 255) / 256), unsigned(nsys));
     const dim3 sgrid(unsigned((nseg + 255) / 256));
+    const dim3 rgrid(unsigned((nseg + 3) / 4));  // one wave per system
     hipError_t e;
     // x0 = solve(b)
     hipLaunchKernelGGL(k_set_i32, dim3((batch + 255) / 256), dim3(256), 0, st, W.active, batch,
@@ -498,7 +511,7 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, it == 0 ? 3 : 4,
                            ldb, D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
         prof.end(st);
-        hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk, W.anorm,
+        hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk, W.anorm,
                            tol, it, W.active, W.conv, W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
@@ -540,6 +553,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
     const dim3 vgrid(unsigned((n + 255) / 256), unsigned(nsys));
     const dim3 sgrid(unsigned((nseg + 255) / 256));
+    const dim3 rgrid(unsigned((nseg + 3) / 4));  // one wave per system
     const size_t vsz = size_t(nsys) * ldb;
     double *r = W.r, *z = W.r + vsz, *pv = W.r + 2 * vsz, *q = W.r + 3 * vsz, *rt = W.r + 4 * vsz;
     double *rz0 = W.sc, *rz1 = W.sc + nseg, *pq = W.sc + 2 * nseg, *zq = W.sc + 3 * nseg;
@@ -574,9 +588,9 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         }
         prof.end(st);
         if (fuse) {
-            hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part2, nrb, nseg, nrhs, nblk,
+            hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part2, nrb, nseg, nrhs, nblk,
                                W.anorm, tol, it, W.active, W.conv, W.stat);
-            hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part2, nrb, 1, nseg, per,
+            hipLaunchKernelGGL(k_sums_final, rgrid, dim3(256), 0, st, W.part2, nrb, 1, nseg, per,
                                W.active, pq, nullptr);
             pq_ready = true;
         } else {
@@ -585,7 +599,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                                it == 0 ? 3 : 4, ldb, D->blk_col0, nblk, nrhs, W.active, W.conv,
                                W.part);
             prof.end(st);
-            hipLaunchKernelGGL(k_check, sgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk,
+            hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk,
                                W.anorm, tol, it, W.active, W.conv, W.stat);
         }
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
@@ -602,7 +616,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, nullptr, 1, ldb,
                            D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
         prof.end(st);
-        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, kRB, 0, nseg, per,
+        hipLaunchKernelGGL(k_sums_final, rgrid, dim3(256), 0, st, W.part, kRB, 0, nseg, per,
                            W.active, out, nullptr);
     };
     // <a, c> into out and <c, d> into out2, in one pass over c
@@ -612,7 +626,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, a, c, d, 2, ldb,
                            D->blk_col0, nblk, nrhs, W.active, nullptr, W.part);
         prof.end(st);
-        hipLaunchKernelGGL(k_sums_final, sgrid, dim3(256), 0, st, W.part, kRB, 0, nseg, per,
+        hipLaunchKernelGGL(k_sums_final, rgrid, dim3(256), 0, st, W.part, kRB, 0, nseg, per,
                            W.active, out, out2);
     };
     e = check(0, r, nullptr);  // r_0 = b - A x_0
