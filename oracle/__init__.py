@@ -20,12 +20,18 @@ dx = A^{-1} (db - dA x), so g_b = A^{-T} g_x = lambda (A symmetric: one more
 solve with the same factor) and dL/dA_ij = -lambda_i x_j; a stored lower
 entry v_k stands for A_ij and A_ji, hence -(lambda_i x_j + lambda_j x_i)
 off the diagonal and -lambda_i x_i on it (summed over right-hand sides).
+It also estimates kappa_1 = ||A||_1 ||A^{-1}||_1, with ||A^{-1}||_1 from
+Hager's method (Higham's safeguards) over oracle solves, and evaluates the
+stop rule of a refined solution: relres <= tol, or the residual at the FP64
+evaluation floor ||r||_2 <= 2 u ||A||_inf ||x||_2 (u = 2^-53).
 
 Parity status: every function here is pinned by tests/test_oracle.py
 (dense LAPACK Cholesky, closed forms of the 1D Laplacian, exact results for
 diagonal matrices, brute-force boolean elimination for the pattern; the
 gradients by central finite differences and by the closed-form inverse of
-the 1D Laplacian).
+the 1D Laplacian; the error measures and norms by hand-computed 3x3 and 4x4
+cases; the condition estimate by numpy's exact one-norm condition number on
+dense cases and the closed-form ||A^{-1}||_1 of the 1D Laplacian).
 """
 from __future__ import annotations
 
@@ -54,6 +60,7 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+U64 = 2.0 ** -53   # unit roundoff of FP64
 
 
 def _load():
@@ -72,6 +79,8 @@ def _load():
         lib.or_solve.restype = None
         lib.or_spmv.argtypes = [I64, P, P, P, P, P, I64]
         lib.or_spmv.restype = None
+        lib.or_inv_norm1_est.argtypes = [I64, P, P, P, P]
+        lib.or_inv_norm1_est.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -191,6 +200,45 @@ def residual_measures(n, colptr, rowind, values, x, b):
     relres = np.linalg.norm(r, axis=1) / np.maximum(np.linalg.norm(b2, axis=1), 1e-300)
     eta = np.abs(r).max(1) / (an * np.abs(x2).max(1) + np.abs(b2).max(1))
     return relres, eta
+
+
+def stop_clause(n, colptr, rowind, values, x, b, tol):
+    """Per right-hand side, which clause of the stop rule holds: 1 if
+    ||b - A x||_2 <= tol ||b||_2, else 2 if ||b - A x||_2 <= 2 u ||A||_inf
+    ||x||_2 (u = 2^-53), else 0.  x, b: [nrhs, n] (or [n])."""
+    x2 = np.asarray(x, np.float64).reshape(-1, n)
+    b2 = np.asarray(b, np.float64).reshape(-1, n)
+    r = b2 - spmv(n, colptr, rowind, values, x2)
+    rn = np.linalg.norm(r, axis=1)
+    an = norm_inf_sym(n, colptr, rowind, values)
+    c1 = rn <= tol * np.linalg.norm(b2, axis=1)
+    c2 = rn <= 2.0 * U64 * an * np.linalg.norm(x2, axis=1)
+    return np.where(c1, 1, np.where(c2, 2, 0)).astype(np.int32)
+
+
+def inv_norm1_estimate(sym: Symbolic, Lx) -> float:
+    """Lower-bound estimate of ||A^{-1}||_1 by Hager's method with Higham's
+    safeguards (oracle.c, or_inv_norm1_est), from solves with the factor."""
+    lib = _load()
+    v = lib.or_inv_norm1_est(sym.n, _p(sym.Lcolptr), _p(sym.Lrowind),
+                             _p(_c(Lx, np.float64)), _p(sym.perm))
+    if v < 0:
+        raise MemoryError("or_inv_norm1_est")
+    return float(v)
+
+
+def kappa1_estimate(n, colptr, rowind, values, sym: Symbolic, Lx) -> float:
+    """kappa_1(A) = ||A||_1 ||A^{-1}||_1 with the second factor estimated
+    (Hager/Higham); A is symmetric, so ||A||_1 = ||A||_inf."""
+    return norm_inf_sym(n, colptr, rowind, values) * inv_norm1_estimate(sym, Lx)
+
+
+def within_conditioning(xerr: float, tol: float, kappa1: float) -> bool:
+    """Acceptance of a solution's forward error against the oracle: at most
+    `tol`, or, when the system is too ill-conditioned for two correct FP64
+    solvers to agree to `tol`, at most 10 kappa_1 u (the conditioning limit
+    of a backward-stable solve)."""
+    return xerr <= tol or xerr <= 10.0 * kappa1 * U64
 
 
 def forward_error(x, x_ref) -> float:

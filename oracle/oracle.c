@@ -278,3 +278,61 @@ void or_spmv(int64_t n, const int64_t *colptr, const int32_t *rowind,
             }
     }
 }
+
+/*
+ * Estimate of ||A^{-1}||_1 from solves with the factor (Hager 1984, with
+ * Higham's 1988 safeguards as used by LAPACK's one-norm estimators).  It
+ * maximizes the convex function f(x) = ||A^{-1} x||_1 over the unit ball of
+ * the one-norm by a gradient ascent that only visits vertices e_j:
+ *   x = (1/n, ..., 1/n)
+ *   repeat: y = A^{-1} x,  xi = sign(y),  z = A^{-T} xi (A symmetric, so one
+ *           more solve with the same factor);
+ *           if max_j |z_j| <= z^T x (no vertex improves), stop with ||y||_1;
+ *           else x = e_j with j = argmax |z_j| (stop when j repeats)
+ * at most five times; the estimate is a lower bound of ||A^{-1}||_1.  It is
+ * then compared with 2 ||A^{-1} v||_1 / (3n) for the alternating vector
+ * v_i = (-1)^i (1 + i/(n-1)), which catches matrices where the ascent stops
+ * at a poor vertex, and the larger of the two is returned.  Returns -1 on
+ * allocation failure.
+ */
+double or_inv_norm1_est(int64_t n, const int64_t *Lcolptr, const int32_t *Lrowind,
+                        const double *Lx, const int32_t *perm) {
+    if (n <= 0) return 0.0;
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!x || !y) { free(x); free(y); return -1.0; }
+    for (int64_t i = 0; i < n; i++) x[i] = 1.0 / (double)n;
+    double est = 0.0;
+    int64_t jlast = -1;
+    for (int it = 0; it < 5; it++) {
+        memcpy(y, x, sizeof(double) * (size_t)n);
+        or_solve(n, Lcolptr, Lrowind, Lx, perm, y, 1);       /* y = A^{-1} x */
+        double ny = 0.0;
+        for (int64_t i = 0; i < n; i++) ny += fabs(y[i]);
+        if (ny <= est && it > 0) break;                       /* no progress */
+        est = ny;
+        for (int64_t i = 0; i < n; i++) y[i] = y[i] >= 0.0 ? 1.0 : -1.0;
+        or_solve(n, Lcolptr, Lrowind, Lx, perm, y, 1);       /* z = A^{-T} xi */
+        double ztx = 0.0, zmax = -1.0;
+        int64_t j = 0;
+        for (int64_t i = 0; i < n; i++) {
+            ztx += y[i] * x[i];
+            if (fabs(y[i]) > zmax) { zmax = fabs(y[i]); j = i; }
+        }
+        if (zmax <= ztx || j == jlast) break;
+        jlast = j;
+        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+        x[j] = 1.0;
+    }
+    /* alternating-sign test vector */
+    for (int64_t i = 0; i < n; i++) {
+        double mag = 1.0 + (n > 1 ? (double)i / (double)(n - 1) : 0.0);
+        x[i] = (i % 2 == 0) ? mag : -mag;
+    }
+    or_solve(n, Lcolptr, Lrowind, Lx, perm, x, 1);
+    double alt = 0.0;
+    for (int64_t i = 0; i < n; i++) alt += fabs(x[i]);
+    alt = 2.0 * alt / (3.0 * (double)n);
+    free(x); free(y);
+    return alt > est ? alt : est;
+}

@@ -292,14 +292,21 @@ def test_interleaved_layout_bitwise_equal_rowmajor(name, make, dtype, seg_max):
     x_soa = _solve_with(w, dtype, soa_min_batch=32, soa_seg_max=seg_max)  # interleaved
     x_row = _solve_with(w, dtype, soa_min_batch=-1)                        # row-major segments
     assert np.array_equal(x_soa, x_row)
-    if dtype == "f64" and name != "trimesh_48":  # the mesh is too ill-conditioned for 1e-10
+    if dtype == "f64":
+        # the mesh (no Dirichlet rows, kappa ~ 1e6 at this size) may differ
+        # from the oracle by more than 1e-10 between two correct FP64
+        # solvers: there the bound is 10 kappa_1 u (kappa_1 estimated from
+        # oracle solves)
         p = w.pattern
         for s in (0, w.batch - 1):
             sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
             Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[s], sym)
             xo = oracle.solve(sym, Lx, w.b[s])
+            kap = oracle.kappa1_estimate(p.n, p.colptr, p.rowind, w.values[s], sym, Lx)
             for r in range(w.nrhs):
-                assert oracle.forward_error(x_soa[s, r], xo[r]) <= 1e-10
+                err = oracle.forward_error(x_soa[s, r], xo[r])
+                log("  set %d rhs %d: x err %.2e (kappa_1 ~ %.2e)" % (s, r, err, kap))
+                assert oracle.within_conditioning(err, 1e-10, kap)
 
 
 def test_interleaved_copy_refreshed_after_refactor():

@@ -373,3 +373,149 @@ def test_block_vector_generator_is_spd_and_dominant():
     assert p.nnz == 27 * 6 + 3 * 3 * 3 * 2 * 9  # 6 per diagonal block, 9 per edge
     nv, e = W.grid_edges((40, 40, 40))
     assert 6 * nv + 9 * len(e) == 2068800
+
+
+# --- error measures, norms and the stop rule: hand-computed cases ----------
+
+def _lower_csc(dense):
+    """Lower CSC (diagonal first, rows ascending) of a small symmetric matrix,
+    every lower entry stored (explicit zeros included)."""
+    n = dense.shape[0]
+    colptr, rowind, vals = [0], [], []
+    for c in range(n):
+        for r in range(c, n):
+            rowind.append(r)
+            vals.append(dense[r, c])
+        colptr.append(len(rowind))
+    return (np.array(colptr, np.int64), np.array(rowind, np.int32),
+            np.array(vals, np.float64))
+
+
+def test_norm_inf_sym_hand():
+    # |2| + |-3| = 5 in row 0; |-3| + |1| = 4 in row 1.  Reading only the
+    # stored lower triangle would give row 0 = 2 and ||A|| = 4.
+    cp, ri, v = _lower_csc(np.array([[2.0, -3.0], [-3.0, 1.0]]))
+    assert oracle.norm_inf_sym(2, cp, ri, v) == 5.0
+    A = np.array([[4.0, 1.0, 0.0], [1.0, 3.0, -1.0], [0.0, -1.0, 2.0]])
+    cp, ri, v = _lower_csc(A)
+    assert oracle.norm_inf_sym(3, cp, ri, v) == 5.0
+    # a 4x4 whose largest row is the last one (an index slip shows)
+    B = np.array([[1.0, 0.0, 0.0, -2.0], [0.0, 1.0, 0.5, 0.0],
+                  [0.0, 0.5, 1.0, 3.0], [-2.0, 0.0, 3.0, -4.0]])
+    cp, ri, v = _lower_csc(B)
+    assert oracle.norm_inf_sym(4, cp, ri, v) == 9.0
+
+
+def test_residual_measures_hand():
+    # A x = [5, 3, 1] for x = 1; b = [6, 3, 1] leaves r = [1, 0, 0].
+    A = np.array([[4.0, 1.0, 0.0], [1.0, 3.0, -1.0], [0.0, -1.0, 2.0]])
+    cp, ri, v = _lower_csc(A)
+    x = np.ones(3)
+    b = np.array([6.0, 3.0, 1.0])
+    relres, eta = oracle.residual_measures(3, cp, ri, v, x, b)
+    assert relres[0] == pytest.approx(1.0 / math.sqrt(46.0), rel=1e-15)
+    # ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) = 1 / (5 + 6)
+    assert eta[0] == pytest.approx(1.0 / 11.0, rel=1e-15)
+    # two right-hand sides at once, the second exact
+    relres, eta = oracle.residual_measures(3, cp, ri, v, np.stack([x, x]),
+                                           np.stack([b, A @ x]))
+    assert relres[1] == 0.0 and eta[1] == 0.0
+    assert relres[0] == pytest.approx(1.0 / math.sqrt(46.0), rel=1e-15)
+
+
+def test_forward_error_hand():
+    assert oracle.forward_error([1.0, 2.0, 3.0], [1.0, 2.0, 4.0]) == 0.25
+    # normalized by the reference (4), not by the tested vector (3)
+    assert oracle.forward_error([-3.0, 1.0], [-4.0, 1.0]) == 0.25
+    assert oracle.forward_error(np.zeros(4), np.zeros(4)) == 0.0
+
+
+def test_factor_error_hand():
+    # columns of 3, 1 and 2 entries; per column the largest deviation over
+    # the reference column's largest magnitude
+    Lcolptr = np.array([0, 3, 4, 6], np.int64)
+    ref = np.array([2.0, -1.0, 0.5, 4.0, 5.0, -10.0])
+    got = np.array([3.0, -1.0, 0.5, 4.0, 5.0, -10.0])      # column 0: 1 / 2
+    assert oracle.factor_error(Lcolptr, got, ref) == 0.5
+    got = np.array([2.0, -1.0, 0.5, 4.0, 5.0, -12.0])      # last column: 2 / 10
+    assert oracle.factor_error(Lcolptr, got, ref) == pytest.approx(0.2, rel=1e-15)
+    got = np.array([2.0, -1.0, 0.5, 4.5, 5.0, -10.0])      # middle column: 0.5 / 4
+    assert oracle.factor_error(Lcolptr, got, ref) == 0.125
+    assert oracle.factor_error(Lcolptr, ref, ref) == 0.0
+
+
+def test_stop_clause_hand():
+    A = np.array([[4.0, 1.0, 0.0], [1.0, 3.0, -1.0], [0.0, -1.0, 2.0]])
+    cp, ri, v = _lower_csc(A)
+    x = np.ones(3)
+    b = np.array([6.0, 3.0, 1.0])           # ||r||_2 = 1, ||b||_2 = sqrt(46)
+    assert oracle.stop_clause(3, cp, ri, v, x, b, 0.2)[0] == 1      # 1 <= 0.2 * 6.78
+    assert oracle.stop_clause(3, cp, ri, v, x, b, 0.1)[0] == 0      # 1 > 0.678
+    # the floor clause: r = b - A x of size ~ u ||A|| ||x||
+    u = 2.0 ** -53
+    eps_b = A @ x + np.array([8.0 * u, 0.0, 0.0])
+    # ||r||_2 = 8u (to rounding) <= 2 u * 5 * sqrt(3) = 17.3 u, relres ~ 1.4e-16 > 1e-20
+    assert oracle.stop_clause(3, cp, ri, v, x, eps_b, 1e-20)[0] == 2
+    big = A @ x + np.array([64.0 * u, 0.0, 0.0])
+    assert oracle.stop_clause(3, cp, ri, v, x, big, 1e-20)[0] == 0
+
+
+# --- the condition estimate ---------------------------------------------
+
+@pytest.mark.parametrize("case", spd_cases()[:7] + [W.random_spd(50, 0.9, seed=900),
+                                                     W.random_spd(64, 0.15, seed=901)],
+                         ids=lambda w: "%s_n%d" % (w.name, w.pattern.n))
+def test_kappa1_against_numpy_dense(case):
+    """Hager's estimate is a lower bound of ||A^{-1}||_1 that is exact on
+    almost every small matrix; numpy's cond(A, 1) forms the exact value
+    from the dense inverse."""
+    p = case.pattern
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, case.perm)
+    Lx, info = oracle.factor(p.n, p.colptr, p.rowind, case.values[0], sym)
+    assert info == 0
+    est = oracle.kappa1_estimate(p.n, p.colptr, p.rowind, case.values[0], sym, Lx)
+    A = oracle.to_dense_permuted(p.n, p.colptr, p.rowind, case.values[0])
+    exact = np.linalg.cond(A, 1)
+    assert est <= exact * (1 + 1e-10)
+    assert est >= exact / 3.0
+    assert est == pytest.approx(exact, rel=1e-10)
+
+
+def test_kappa1_indefinite_sign_inverse():
+    """A matrix whose inverse has mixed signs (positive off-diagonals), so
+    the first ascent vector is not optimal: still within numpy's value."""
+    rng = np.random.default_rng(77)
+    n = 30
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n) * 0.05
+    cp, ri, v = _lower_csc(A)
+    sym = oracle.symbolic(n, cp, ri)
+    Lx, info = oracle.factor(n, cp, ri, v, sym)
+    assert info == 0
+    est = oracle.kappa1_estimate(n, cp, ri, v, sym, Lx)
+    exact = np.linalg.cond(A, 1)
+    assert exact / 3.0 <= est <= exact * (1 + 1e-10)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10, 101, 2000])
+def test_kappa1_1d_laplacian_closed_form(n):
+    """tridiag(-1, 2, -1): (A^{-1})_ij = min(i,j)(n+1-max(i,j))/(n+1) > 0, so
+    column j sums to j(n+1-j)/2 (1-based) and ||A^{-1}||_1 is its maximum,
+    at j = floor((n+1)/2); ||A||_1 = 4 for n >= 3 (2, 3 for n = 1, 2)."""
+    pat, vals = path_laplacian(n)
+    sym = oracle.symbolic(n, pat.colptr, pat.rowind)
+    Lx, info = oracle.factor(n, pat.colptr, pat.rowind, vals, sym)
+    j = (n + 1) // 2
+    inv1 = j * (n + 1 - j) / 2.0
+    # the solves carry a relative error of about kappa_2 u ~ (4 n^2 / pi^2) u
+    rel = max(1e-14, 10.0 * n * n * 2.0 ** -53)
+    assert oracle.inv_norm1_estimate(sym, Lx) == pytest.approx(inv1, rel=rel)
+    anorm = {1: 2.0, 2: 3.0}.get(n, 4.0)
+    k = oracle.kappa1_estimate(n, pat.colptr, pat.rowind, vals, sym, Lx)
+    assert k == pytest.approx(anorm * inv1, rel=rel)
+
+
+def test_within_conditioning_rule():
+    assert oracle.within_conditioning(1e-11, 1e-10, 1e20)
+    assert not oracle.within_conditioning(1e-6, 1e-10, 1e6)       # 10 k u = 1.1e-9
+    assert oracle.within_conditioning(1e-6, 1e-10, 1e10)          # 10 k u = 1.1e-5
