@@ -344,7 +344,12 @@ sc_status sc_adjoint(const sc_plan_t *plan, sc_numeric_t *num, const double *x_d
  * Creation allocates every workspace and captures on a private stream; the
  * numeric object, values_dev, b_dev and x_dev must stay valid and unmoved
  * while the graph exists, and the numeric object must not be used by other
- * calls while a replay is in flight.  Errors: SC_EINVAL (bad argument, or
+ * calls while a replay is in flight.  The graph holds the addresses of the
+ * numeric object's workspaces: while any graph of the object exists, a call
+ * on it that would need larger workspaces (sc_solve, sc_refine_solve,
+ * sc_adjoint or another sc_step_graph_create with more right-hand sides or
+ * a larger ldb) returns SC_EINVAL instead of reallocating them.  Destroy
+ * the graphs before the numeric object.  Errors: SC_EINVAL (bad argument, or
  * b_dev == x_dev), SC_ENOMEM, SC_EDEVICE.
  */
 typedef struct sc_graph sc_graph_t;

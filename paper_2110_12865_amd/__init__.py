@@ -441,6 +441,11 @@ class StepGraph:
         self._keep = keep  # the captured buffers stay alive with the graph
 
     def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        """Release the graph (sc_step_graph_destroy); later calls on the
+        numeric object may then grow its workspaces again."""
         if getattr(self, "_h", None):
             _lib.sc_step_graph_destroy(self._h)
             self._h = None

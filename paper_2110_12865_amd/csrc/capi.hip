@@ -112,33 +112,46 @@ sc_status map_err(hipError_t e) {
     return SC_EDEVICE;
 }
 
-// Solve workspaces for nrhs right-hand sides per matrix (rounded up to
-// whole groups of 64 matrices in the batch-interleaved form).
-hipError_t ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
-    if (nrhs <= N->ws_nrhs) return hipSuccess;
-    void *old[] = {N->ws_y, N->ws_u, N->ws_part, N->ws_ps};
+// Sizes (in doubles) of the solve workspaces for nrhs right-hand sides per
+// matrix (matrices rounded up to whole groups of 64 in the batch-interleaved
+// form): y, u, part, ps, in that order.
+void solve_ws_words(const sc_plan *P, const sc_numeric *N, int32_t nrhs, size_t out[4]) {
+    const size_t nb = N->soa ? size_t((N->batch + 63) / 64) * 64 : size_t(N->batch);
+    const size_t cnt = nb * size_t(nrhs);
+    out[0] = cnt * size_t(P->n);
+    out[1] = cnt * P->rows.size();
+    out[2] = cnt * size_t(P->part_size);
+    out[3] = N->soa ? cnt * size_t(P->soa_psize) : 0;
+}
+
+void free_solve_ws(SolveWs &W) {
+    void *old[] = {W.y, W.u, W.part, W.ps};
     for (void *q : old)
         if (q) (void)hipFree(q);
-    N->ws_y = nullptr;
-    N->ws_u = nullptr;
-    N->ws_part = nullptr;
-    N->ws_ps = nullptr;
-    N->ws_nrhs = 0;
-    const size_t nb = N->soa ? size_t((N->batch + 63) / 64) * 64 : size_t(N->batch);
-    const size_t cnt = nb * nrhs;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&N->ws_y),
-                             std::max<size_t>(cnt * P->n * sizeof(double), 8));
-    if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void **>(&N->ws_u),
-                      std::max<size_t>(cnt * P->rows.size() * sizeof(double), 8));
-    if (e == hipSuccess)
-        e = hipMalloc(reinterpret_cast<void **>(&N->ws_part),
-                      std::max<size_t>(cnt * P->part_size * sizeof(double), 8));
-    if (e == hipSuccess && N->soa)
-        e = hipMalloc(reinterpret_cast<void **>(&N->ws_ps),
-                      std::max<size_t>(cnt * P->soa_psize * sizeof(double), 8));
-    if (e == hipSuccess) N->ws_nrhs = nrhs;
-    return e;
+    W = SolveWs{};
+}
+
+// Solve workspaces for nrhs right-hand sides per matrix.  Growing them
+// moves their addresses, which a captured graph on this numeric object
+// still holds, so growth is refused (SC_EINVAL) while such a graph exists.
+sc_status ensure_solve_ws(const sc_plan *P, sc_numeric *N, int32_t nrhs) {
+    if (nrhs <= N->ws.nrhs) return SC_OK;
+    if (N->graphs > 0) return SC_EINVAL;
+    free_solve_ws(N->ws);
+    size_t words[4];
+    solve_ws_words(P, N, nrhs, words);
+    double **dst[4] = {&N->ws.y, &N->ws.u, &N->ws.part, &N->ws.ps};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 4 && e == hipSuccess; k++)
+        if (words[k] > 0 || k < 3)
+            e = hipMalloc(reinterpret_cast<void **>(dst[k]),
+                          std::max<size_t>(words[k] * sizeof(double), 8));
+    if (e != hipSuccess) {
+        free_solve_ws(N->ws);
+        return map_err(e);
+    }
+    N->ws.nrhs = nrhs;
+    return SC_OK;
 }
 
 void free_refine_ws(RefineWs &W) {
@@ -149,12 +162,14 @@ void free_refine_ws(RefineWs &W) {
 }
 
 // Refinement workspaces: vectors per (matrix, right-hand side), scalars
-// per system (matrix, right-hand side, block).
-hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
+// per system (matrix, right-hand side, block).  Refused (SC_EINVAL) when
+// they would have to grow while a captured graph holds their addresses.
+sc_status ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
     RefineWs &W = N->rws;
     const int32_t nsys = N->batch * nrhs;
     const size_t nseg = size_t(nsys) * N->plan->nblk;
-    if (W.r && W.nsys >= nsys && W.ldb >= ldb) return hipSuccess;
+    if (W.r && W.nsys >= nsys && W.ldb >= ldb) return SC_OK;
+    if (N->graphs > 0) return SC_EINVAL;
     free_refine_ws(W);
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&W.r), 5 * sizeof(double) * nsys * ldb);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.sc), 4 * sizeof(double) * nseg);
@@ -175,11 +190,11 @@ hipError_t ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&W.count), sizeof(int32_t));
     if (e != hipSuccess) {
         free_refine_ws(W);
-        return e;
+        return map_err(e);
     }
     W.nsys = nsys;
     W.ldb = ldb;
-    return hipSuccess;
+    return SC_OK;
 }
 
 }  // namespace
@@ -391,9 +406,10 @@ void sc_numeric_destroy(sc_numeric_t *N) {
     if (N->L) (void)hipFree(N->L);
     if (N->U) (void)hipFree(N->U);
     if (N->info) (void)hipFree(N->info);
-    void *ws[] = {N->pinv, N->dinv, N->ws_y, N->ws_u, N->ws_part, N->ws_ps, N->Ls};
+    void *ws[] = {N->pinv, N->dinv, N->Ls};
     for (void *q : ws)
         if (q) (void)hipFree(q);
+    free_solve_ws(N->ws);
     free_refine_ws(N->rws);
     if (N->ev_fork) (void)hipEventDestroy(N->ev_fork);
     if (N->ev_join) (void)hipEventDestroy(N->ev_join);
@@ -431,8 +447,8 @@ sc_status sc_solve(const sc_plan_t *P, sc_numeric_t *N, double *b_dev, int32_t n
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
     if (dev != N->device) return SC_EINVAL;
-    hipError_t e = ensure_solve_ws(P, N, nrhs);
-    if (e != hipSuccess) return map_err(e);
+    const sc_status ws = ensure_solve_ws(P, N, nrhs);
+    if (ws != SC_OK) return ws;
     return map_err(
         spchol_solve_run(P, N, b_dev, nrhs, ldb, static_cast<hipStream_t>(stream), nullptr));
 }
@@ -449,13 +465,13 @@ sc_status sc_refine_solve(const sc_plan_t *P, sc_numeric_t *N, const double *val
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
     if (dev != N->device) return SC_EINVAL;
-    hipError_t e = ensure_solve_ws(P, N, nrhs);
-    if (e == hipSuccess) e = ensure_refine_ws(N, nrhs, ldb);
-    if (e != hipSuccess) return map_err(e);
+    sc_status ws = ensure_solve_ws(P, N, nrhs);
+    if (ws == SC_OK) ws = ensure_refine_ws(N, nrhs, ldb);
+    if (ws != SC_OK) return ws;
     const int32_t nsys = N->batch * nrhs * P->nblk;
     std::vector<double> stat(size_t(6) * nsys);
     int32_t nact = 0;
-    e = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, maxit, method,
+    hipError_t e = spchol_refine_run(P, N, values_dev, ldv, b_dev, x_dev, nrhs, ldb, tol, maxit, method,
                           stat.data(), &nact, true, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return map_err(e);
     bool fail = false;
@@ -566,6 +582,7 @@ struct sc_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t nsys = 0;
+    bool counted = false;  // counted in num->graphs
 };
 
 namespace {
@@ -608,9 +625,10 @@ sc_status sc_step_graph_create(const sc_plan_t *P, sc_numeric_t *N, const double
     if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
     if (dev != N->device) return SC_EINVAL;
     // every workspace exists before the capture (no allocation inside it)
-    hipError_t e = ensure_solve_ws(P, N, nrhs);
-    if (e == hipSuccess) e = ensure_refine_ws(N, nrhs, ldb);
-    if (e != hipSuccess) return map_err(e);
+    sc_status ws = ensure_solve_ws(P, N, nrhs);
+    if (ws == SC_OK) ws = ensure_refine_ws(N, nrhs, ldb);
+    if (ws != SC_OK) return ws;
+    hipError_t e = hipSuccess;
     sc_graph *G = new (std::nothrow) sc_graph();
     if (!G) return SC_ENOMEM;
     G->plan = P;
@@ -643,6 +661,8 @@ sc_status sc_step_graph_create(const sc_plan_t *P, sc_numeric_t *N, const double
         sc_step_graph_destroy(G);
         return map_err(e);
     }
+    N->graphs++;
+    G->counted = true;
     *out = G;
     return SC_OK;
 }
@@ -659,6 +679,7 @@ sc_status sc_step_graph_stats(sc_graph_t *G, sc_refine_stats *stats_host, void *
 
 void sc_step_graph_destroy(sc_graph_t *G) {
     if (!G) return;
+    if (G->counted && G->num) G->num->graphs--;
     if (G->exec) (void)hipGraphExecDestroy(G->exec);
     if (G->graph) (void)hipGraphDestroy(G->graph);
     delete G;
@@ -779,9 +800,9 @@ sc_status sc_adjoint(const sc_plan_t *P, sc_numeric_t *N, const double *x_dev,
     if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
     if (dev != N->device) return SC_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = ensure_solve_ws(P, N, nrhs);
-    if (e != hipSuccess) return map_err(e);
-    e = spchol_solve_run(P, N, gb_dev, nrhs, ldb, st, nullptr, gx_dev);  // lambda
+    const sc_status ws = ensure_solve_ws(P, N, nrhs);
+    if (ws != SC_OK) return ws;
+    hipError_t e = spchol_solve_run(P, N, gb_dev, nrhs, ldb, st, nullptr, gx_dev);  // lambda
     if (e == hipSuccess)
         e = spchol_adjoint_values(P, N->batch, x_dev, gb_dev, nrhs, ldb, gvalues_dev, ldv, st);
     return map_err(e);

@@ -167,6 +167,16 @@ struct RefineWs {
     int32_t *count = nullptr;   // 1
 };
 
+// Vectors of the triangular solves, right-hand sides interleaved
+// (index * nrhs + r), in the factor's precision (sized in doubles).
+struct SolveWs {
+    double *y = nullptr;     // nb * n * nrhs: P b, then y, then z
+    double *u = nullptr;     // nb * sum(c_s) * nrhs: front vectors
+    double *part = nullptr;  // nb * nrhs * part_size
+    double *ps = nullptr;    // nb * soa_psize * nrhs partial sums (interleaved form)
+    int32_t nrhs = 0;        // right-hand sides the buffers hold
+};
+
 struct sc_numeric {
     const sc_plan *plan = nullptr;
     int32_t batch = 0;
@@ -177,20 +187,23 @@ struct sc_numeric {
     int32_t *info = nullptr; // batch
     void *pinv = nullptr;    // batch * max_lvl_big * 64 * 64: panel inverses (factor)
     double *dinv = nullptr;  // batch * dinv_size: inverted diagonal blocks
-    // solve workspaces, right-hand sides interleaved (index * nrhs + r)
-    double *ws_y = nullptr;  // batch * n * nrhs: P b, then y, then z
-    double *ws_u = nullptr;  // batch * sum(c_s) * nrhs: front vectors
-    double *ws_part = nullptr;  // batch * nrhs * part_size
-    int32_t ws_nrhs = 0;
+    // solve workspaces owned by the numeric object (allocated on first use,
+    // grown for more right-hand sides), and the set the solve kernels use:
+    // `wsc` points at `ws` except inside sc_solve_noalloc, which points it at
+    // the library's static scratch array for the duration of the call
+    SolveWs ws;
+    const SolveWs *wsc = &ws;
     // batch-interleaved solves (batch >= soa_min): L copied to groups of 64
     // matrices with the matrix index fastest, refreshed after each factor;
-    // the vectors above then use the same interleaving
+    // the solve vectors then use the same interleaving
     bool soa = false;
     void *Ls = nullptr;         // ceil(batch / 64) * Lsize * 64 scalars
     bool ls_ok = false;
-    double *ws_ps = nullptr;    // ceil(batch / 64) * 64 * soa_psize * nrhs partial sums
     Profiler prof;
     RefineWs rws;
+    // captured step graphs alive on this object: their kernels hold the
+    // workspace addresses, so workspaces may not be reallocated meanwhile
+    int32_t graphs = 0;
     // second stream of the factorization (lookahead in the panel chain of
     // large fronts) and the events that order it against the caller's stream
     hipStream_t side = nullptr;

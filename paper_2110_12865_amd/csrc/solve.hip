@@ -1474,7 +1474,7 @@ void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
         const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_GATHER(NRV)                                                                     \
     hipLaunchKernelGGL((k_gather<T, SOA, NRV>), g, dim3(256), 0, st, D->grow_q + l.grow0,          \
-                       D->grow_y + l.grow0, l.ngrow, D->gptr, D->gidx, as<T>(N->ws_y), as<T>(N->ws_u), P->n,  \
+                       D->grow_y + l.grow0, l.ngrow, D->gptr, D->gidx, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n,  \
                        fvsize, nrhs, r0, B, active)
         if (nrr == 1) SPCHOL_GATHER(1);
         else if (nrr == 2) SPCHOL_GATHER(2);
@@ -1494,7 +1494,7 @@ void launch_fwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_
     const int32_t *lst = D->slv_small + cl.list0;
 #define SPCHOL_FWDS(G, SL)                                                                   \
     hipLaunchKernelGGL((k_fwd_seg<T, G, SL, NR, SOA>), g, dim3(256), 0, st, D->sn, lst, cl.n, \
-                       nitems, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->ws_y), as<T>(N->ws_u), P->n,     \
+                       nitems, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n,     \
                        fvsize, nrhs, active)
     switch (k) {
     case 0: SPCHOL_FWDS(16, 1); break;
@@ -1515,7 +1515,7 @@ void launch_bwd_class(int k, dim3 g, hipStream_t st, const DevPlan *D, const sc_
     const int32_t *lst = D->slv_small + cl.list0;
 #define SPCHOL_BWDS(G)                                                                       \
     hipLaunchKernelGGL((k_bwd_seg<T, G, NR, SOA>), g, dim3(256), 0, st, D->sn, lst, cl.n,     \
-                       nitems, r0, D->rows, L, P->Lsize, as<T>(N->ws_y), P->n, nrhs, active)
+                       nitems, r0, D->rows, L, P->Lsize, as<T>(N->wsc->y), P->n, nrhs, active)
     if (k == 0) SPCHOL_BWDS(16);
     else if (k == 1) SPCHOL_BWDS(32);
     else SPCHOL_BWDS(64);
@@ -1598,7 +1598,7 @@ void panels_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     prof.begin(KK_FwdPanel, 0.0, (l.vw_pan * sz + l.ib_pan) * nr * nb, st);
     hipLaunchKernelGGL((k_pan_gather<T, SOA>), dim3(unsigned(l.npan), unsigned(B)), dim3(256), 0, st,
                        D->sn, D->slv_pan + l.pan0, D->gptr, D->gidx, as<T>(N->dinv), P->dinv_size,
-                       as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active);
+                       as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs, active);
     prof.end(st);
     for (size_t q = 0; q < l.panels.size(); q++) {
         const SPanel &pp = l.panels[q];
@@ -1611,7 +1611,7 @@ void panels_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 #define SPCHOL_FWDP(NRV)                                                                       \
     hipLaunchKernelGGL((k_fwd_panel<T, NRV, SOA>), g, dim3(64), 0, st, D->sn,                  \
                        D->slv_pan + l.pan0, int(q), r0, L, P->Lsize, as<T>(N->dinv), P->dinv_size,     \
-                       as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active)
+                       as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs, active)
             if (nrr == 1) SPCHOL_FWDP(1);
             else if (nrr == 2) SPCHOL_FWDP(2);
             else if (nrr == 3) SPCHOL_FWDP(3);
@@ -1642,11 +1642,11 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
     do {                                                                                         \
         if (pp.bwd_chunks > 0)                                                                   \
             hipLaunchKernelGGL((k_bwd_pan_part<T, NRV, SOA>), gp, dim3(256), 0, st, D->sn,       \
-                               D->slv_pan + l.pan0, int(q), r0, D->rows, L, P->Lsize, as<T>(N->ws_y),   \
-                               P->n, as<T>(N->ws_part), P->part_size, nrhs, active);                    \
+                               D->slv_pan + l.pan0, int(q), r0, D->rows, L, P->Lsize, as<T>(N->wsc->y),   \
+                               P->n, as<T>(N->wsc->part), P->part_size, nrhs, active);                    \
         hipLaunchKernelGGL((k_bwd_pan_fin<T, NRV, SOA>), gf, dim3(64), 0, st, D->sn,                \
-                           D->slv_pan + l.pan0, int(q), r0, as<T>(N->dinv), P->dinv_size, as<T>(N->ws_y),      \
-                           P->n, as<T>(N->ws_part), P->part_size, nrhs, active);                        \
+                           D->slv_pan + l.pan0, int(q), r0, as<T>(N->dinv), P->dinv_size, as<T>(N->wsc->y),      \
+                           P->n, as<T>(N->wsc->part), P->part_size, nrhs, active);                        \
     } while (0)
             if (nrr == 1) SPCHOL_BWDP(1);
             else if (nrr == 2) SPCHOL_BWDP(2);
@@ -1703,7 +1703,7 @@ void sn_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 #define SPCHOL_FWDSN(NRV)                                                                      \
     hipLaunchKernelGGL((k_fwd_sn<T, NRV, SOA>), g, dim3(SnThreadsF<T>::value), lds, st, D->sn,   \
                        D->slv_pan + l.pan0, r0, D->gptr, D->gidx, L, P->Lsize, as<T>(N->dinv),   \
-                       P->dinv_size, as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, active)
+                       P->dinv_size, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs, active)
         if (nrr == 1) SPCHOL_FWDSN(1);
         else if (nrr == 2) SPCHOL_FWDSN(2);
         else if (nrr == 3) SPCHOL_FWDSN(3);
@@ -1735,7 +1735,7 @@ void sn_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 #define SPCHOL_BWDSN(NRV)                                                                      \
     hipLaunchKernelGGL((k_bwd_sn<T, NRV, SOA>), g, dim3(kSnThreads), lds, st, D->sn,             \
                        D->slv_pan + l.pan0, r0, D->rows, L, P->Lsize, as<T>(N->dinv),            \
-                       P->dinv_size, as<T>(N->ws_y), P->n, nrhs, active)
+                       P->dinv_size, as<T>(N->wsc->y), P->n, nrhs, active)
         if (nrr == 1) SPCHOL_BWDSN(1);
         else if (nrr == 2) SPCHOL_BWDSN(2);
         else if (nrr == 3) SPCHOL_BWDSN(3);
@@ -1768,7 +1768,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     }
     const dim3 pgrid(unsigned((P->n + 63) / 64), G);
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in_soa<T>, pgrid, dim3(256), 0, st, D->pinv, bin, ldb, as<T>(N->ws_y), P->n,
+    hipLaunchKernelGGL(k_perm_in_soa<T>, pgrid, dim3(256), 0, st, D->pinv, bin, ldb, as<T>(N->wsc->y), P->n,
                        nrhs, B);
     prof.end(st);
     // top levels with few supernodes: one lane per row (segment kernels)
@@ -1784,8 +1784,8 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
     hipLaunchKernelGGL((k_fwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st,     \
-                       D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls, P->Lsize, as<T>(N->ws_y),   \
-                       as<T>(N->ws_u), P->n, fvsize, nrhs, r0)
+                       D->sn, D->slv_small + l.all0, D->gptr, D->gidx, Ls, P->Lsize, as<T>(N->wsc->y),   \
+                       as<T>(N->wsc->u), P->n, fvsize, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAF(1);
                 else if (nrr == 2) SPCHOL_SOAF(2);
                 else if (nrr == 3) SPCHOL_SOAF(3);
@@ -1801,7 +1801,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
 #define SPCHOL_SOAF(NRV)                                                                        \
     hipLaunchKernelGGL((k_fwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0, st,      \
                        D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->gptr, D->gidx, Ls,  \
-                       P->Lsize, as<T>(N->ws_y), as<T>(N->ws_u), P->n, fvsize, nrhs, r0)
+                       P->Lsize, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAF(1);
                 else if (nrr == 2) SPCHOL_SOAF(2);
                 else if (nrr == 3) SPCHOL_SOAF(3);
@@ -1832,7 +1832,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
 #define SPCHOL_SOAB(NRV)                                                                        \
     hipLaunchKernelGGL((k_bwd_soa_rows<T, NRV>), dim3(unsigned(l.nit), G), dim3(64), 0, st,      \
                        D->sn, D->soa_it_s + l.it0, D->soa_it_r0 + l.it0, D->rows, Ls, P->Lsize, \
-                       as<T>(N->ws_y), as<T>(N->ws_ps), P->soa_psize, P->n, nrhs, r0)
+                       as<T>(N->wsc->y), as<T>(N->wsc->ps), P->soa_psize, P->n, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAB(1);
                 else if (nrr == 2) SPCHOL_SOAB(2);
                 else if (nrr == 3) SPCHOL_SOAB(3);
@@ -1847,7 +1847,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAB(NRV)                                                                        \
     hipLaunchKernelGGL((k_bwd_soa_diag<T, NRV>), dim3(unsigned(l.nall), G), dim3(64), 0, st,     \
-                       D->sn, D->slv_small + l.all0, Ls, P->Lsize, as<T>(N->ws_y), as<T>(N->ws_ps),           \
+                       D->sn, D->slv_small + l.all0, Ls, P->Lsize, as<T>(N->wsc->y), as<T>(N->wsc->ps),           \
                        P->soa_psize, P->n, nrhs, r0)
                 if (nrr == 1) SPCHOL_SOAB(1);
                 else if (nrr == 2) SPCHOL_SOAB(2);
@@ -1859,7 +1859,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
         }
     }
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_out_soa<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->ws_y), b, ldb, P->n,
+    hipLaunchKernelGGL(k_perm_out_soa<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->wsc->y), b, ldb, P->n,
                        nrhs, B, active);
     prof.end(st);
     return hipGetLastError();
@@ -1874,7 +1874,7 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
     const dim3 pgrid(unsigned((P->n + 255) / 256), unsigned(B));
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_in<T>, pgrid, dim3(256), 0, st, D->perm, bin, ldb, as<T>(N->ws_y), P->n, nrhs,
+    hipLaunchKernelGGL(k_perm_in<T>, pgrid, dim3(256), 0, st, D->perm, bin, ldb, as<T>(N->wsc->y), P->n, nrhs,
                        active);
     prof.end(st);
     // forward: levels ascending
@@ -1896,7 +1896,7 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
         classes_backward<T, false>(l, P, N, nrhs, active, st);
     }
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
-    hipLaunchKernelGGL(k_perm_out<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->ws_y), b, ldb, P->n, nrhs,
+    hipLaunchKernelGGL(k_perm_out<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->wsc->y), b, ldb, P->n, nrhs,
                        active);
     prof.end(st);
     return hipGetLastError();

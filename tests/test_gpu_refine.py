@@ -173,3 +173,51 @@ def test_step_graph_replays_match_eager(method, batch, soa):
         from tests.gpu_helpers import run_library
         run_library(other, "f64")
         torch.cuda.synchronize()
+
+
+def test_step_graph_blocks_workspace_growth():
+    """A captured graph holds the numeric object's workspace addresses: while
+    it exists, calls on the same object that would need larger workspaces
+    (more right-hand sides, a larger leading dimension) are refused with
+    SC_EINVAL instead of reallocating under the graph.  The graph is not
+    replayed after a refused call; once it is destroyed the same calls run
+    and agree with a fresh numeric object."""
+    import paper_2110_12865_amd as S
+    w = W.small_grid((9, 8, 7), "nd", seed=68, batch=2, nrhs=3)
+    p = w.pattern
+    plan = S.analyze(p.colptr, p.rowind, w.perm)
+    vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
+    b1 = torch.from_numpy(np.ascontiguousarray(w.b[:, :1])).cuda()
+    x1 = torch.empty_like(b1)
+    num = plan.numeric(w.batch, "f32")
+    g = num.step_graph(vals, b1, x1, tol=1e-10, iters=3, method="pcg")
+    g.launch()
+    torch.cuda.synchronize()
+    rc, _ = g.stats()
+    assert rc == S.SC_OK
+    b3 = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+    x3 = torch.empty_like(b3)
+    with pytest.raises(S.SpcholError) as ei:
+        num.solve(b3.clone())                      # 3 right-hand sides > 1
+    assert ei.value.status == S.SC_EINVAL
+    with pytest.raises(S.SpcholError) as ei:
+        num.refine_solve(vals, b3, x3, tol=1e-10, maxit=3, method="pcg")
+    assert ei.value.status == S.SC_EINVAL
+    wide = torch.zeros((w.batch, 1, p.n + 5), dtype=torch.float64, device="cuda")
+    wide[:, :, :p.n] = b1
+    with pytest.raises(S.SpcholError) as ei:       # larger leading dimension
+        num.refine_solve(vals, wide, torch.empty_like(wide), tol=1e-10, maxit=3)
+    assert ei.value.status == S.SC_EINVAL
+    # a solve that fits the existing workspaces is still allowed
+    xs = b1.clone()
+    num.solve(xs)
+    g.destroy()
+    del g
+    torch.cuda.synchronize()
+    xb = b3.clone()
+    num.solve(xb)                                   # grows now
+    fresh = plan.numeric(w.batch, "f32")
+    fresh.factor(vals)
+    xf = b3.clone()
+    fresh.solve(xf)
+    assert torch.equal(xb, xf)
