@@ -81,7 +81,17 @@ typedef struct {
                              where one lane per matrix leaves the chip
                              idle); 0 = library default (96), a negative
                              value never */
+    int32_t ordering;      /* elimination order: SC_ORDER_NATURAL, or
+                             SC_ORDER_GIVEN (default: the caller's perm,
+                             natural when perm is NULL), or SC_ORDER_ND
+                             (built-in nested dissection of the pattern's
+                             graph: separators from breadth-first level
+                             structures rooted at pseudo-peripheral
+                             vertices; perm must be NULL)                  */
 } sc_options;
+
+/* Values of sc_options.ordering. */
+enum { SC_ORDER_NATURAL = 0, SC_ORDER_GIVEN = 1, SC_ORDER_ND = 2 };
 
 /* Sizes of a plan (per matrix of a batch). */
 typedef struct {
@@ -114,10 +124,12 @@ sc_status sc_options_default(sc_options *opt);
  * every dependency sits at a strictly lower level), relative index maps
  * and the value scatter map.  The plan copies what it needs; the inputs
  * may be freed after the call.  Device copies are made on first use.
- * Errors: SC_EINVAL (NULL pointers, n < 1), SC_EPATTERN (unsorted or
- * duplicate rows, a row below the diagonal missing or out of range,
- * missing or misplaced diagonal, colptr not monotone, perm not a
- * permutation), SC_ENOMEM.
+ * The permutation used (given or computed) is reported by
+ * sc_plan_export_symbolic.
+ * Errors: SC_EINVAL (NULL pointers, n < 1, an ordering other than
+ * SC_ORDER_GIVEN with a perm), SC_EPATTERN (unsorted or duplicate rows, a
+ * row below the diagonal missing or out of range, missing or misplaced
+ * diagonal, colptr not monotone, perm not a permutation), SC_ENOMEM.
  */
 sc_status sc_analyze(int64_t n, const int64_t *colptr_host,
                      const int32_t *rowind_host, const int32_t *perm_host,
@@ -286,13 +298,33 @@ sc_status sc_numeric_get_columns(const sc_plan_t *plan,
                                  int64_t ncols, const int32_t *cols_host,
                                  double *out_host);
 
+/*
+ * Copy the whole stored block of supernode s of factor b to the host, for
+ * checking: c x w scalars, column-major (c = rows of the front, w = its
+ * columns, as sc_plan_export_supernodes gives them), as float64.  Rows of
+ * column t of the block are the front's rows t .. c-1 (entries above the
+ * diagonal, rows 0 .. t-1, hold no factor values).  Stored entries outside
+ * the exact pattern of L (amalgamation padding) are included: they come
+ * out as 0.0.  Synchronizes the device.
+ * Errors: SC_EINVAL (bad batch index or supernode), SC_EDEVICE.
+ */
+sc_status sc_numeric_get_block(const sc_plan_t *plan, const sc_numeric_t *num, int32_t b,
+                               int32_t s, double *out_host);
+
 /* Per-kernel totals of timed launches (see sc_numeric_profile). */
 typedef struct {
     char name[32];    /* kernel name                                      */
     int64_t launches; /* launches timed                                   */
     double ms;        /* summed event time of those launches              */
     double flops;     /* algorithmic flops of those launches              */
-    double bytes;     /* algorithmic HBM bytes of those launches          */
+    double bytes;     /* the library's byte model of those launches: front
+                         and update blocks, vectors and indices moved     */
+    double alg_bytes; /* algorithmic bytes of the method: factor launches
+                         the entries of A read (12 B: value and row index)
+                         plus the exact entries of L written; triangular
+                         solves the exact entries of L read once for all
+                         right-hand sides; residual products the entries of
+                         A read (12 B); other launches 0                  */
 } sc_kernel_stat;
 
 /*
@@ -377,7 +409,10 @@ void sc_step_graph_destroy(sc_graph_t *graph);
  *     factor_ms + solves_per_factor * solve_ms.
  * Pattern arguments as in sc_analyze (host), values_dev [batch][ldv] and
  * b_dev [batch][nrhs][ldb] on the device (b_dev is not modified; the
- * library allocates a scratch copy).  table_host (nullable when
+ * library allocates a scratch copy).  When perm_host is NULL the
+ * candidates are also tried with the natural and the built-in nested
+ * dissection orderings (best_out->ordering reports the choice); a given
+ * permutation is always kept.  table_host (nullable when
  * table_cap == 0) receives up to table_cap measured candidates and
  * *ntable_out their number.  Synchronizes `stream`.  Errors: SC_EINVAL,
  * SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD is not reported (info is
@@ -395,6 +430,22 @@ sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowi
                       int64_t ldb, double solves_per_factor, sc_options *best_out,
                       sc_tune_entry *table_host, int32_t table_cap, int32_t *ntable_out,
                       void *stream);
+
+/*
+ * The autotuner for an uneven batch: the same candidates and score as
+ * sc_autotune, each analysed as the group plan of sc_analyze_group (pattern
+ * arguments as there, host memory) and timed on the caller's concatenated
+ * value sets and right-hand sides (values_dev [batch][ldv], b_dev
+ * [batch][nrhs][ldb] with ldb >= the group's order).  Errors as
+ * sc_autotune.
+ */
+sc_status sc_autotune_group(int32_t npat, const int64_t *n_host,
+                            const int64_t *const *colptr_host, const int32_t *const *rowind_host,
+                            const int32_t *const *perm_host, const double *values_dev,
+                            int64_t ldv, int32_t batch, sc_dtype dtype, const double *b_dev,
+                            int32_t nrhs, int64_t ldb, double solves_per_factor,
+                            sc_options *best_out, sc_tune_entry *table_host, int32_t table_cap,
+                            int32_t *ntable_out, void *stream);
 
 #ifdef __cplusplus
 }

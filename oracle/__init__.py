@@ -304,3 +304,142 @@ def solve_gradients(n, colptr, rowind, values, sym: Symbolic, Lx, x, gx):
         t = lam[r, rows] * x[r, cols]
         g -= np.where(rows == cols, t, t + lam[r, cols] * x[r, rows])
     return g, lam
+
+
+def cotan_values(n, colptr, rowind, pos, tris, mass, mass_coeff, clip_lo, clip_hi,
+                 edge_scale=None):
+    """Values (lower CSC order) of A = K + c diag(m) for a triangle mesh,
+    K the cotangent stiffness matrix (the operator the paper assembles in
+    its cotan construction, Sec. 5.3), written out from its definition:
+
+      cot of the angle at corner o of a triangle, opposite edge (p, q):
+          u = x_p - x_o,  v = x_q - x_o,  cot = (u . v) / |u_0 v_1 - u_1 v_0|
+      w_pq = clip(1/2 * sum of cot over the (one or two) triangles with
+                  edge (p, q), clip_lo, clip_hi)
+      per value set s: w^s_pq = clip(w_pq * scale_s[pq], clip_lo, clip_hi)
+                       (skipped when edge_scale is None)
+      K_pq = -w^s_pq (p != q),  K_pp = sum_q w^s_pq,  A = K + c diag(m).
+
+    The sum of a diagonal entry runs over the neighbours q > p in ascending
+    order, then the neighbours q < p in ascending order (a fixed order, so
+    the result is reproducible to the bit); sums of two terms do not depend
+    on order.  Every stored off-diagonal entry must be a mesh edge.
+    pos: [nv, 2] or [batch, nv, 2]; tris: [ntri, 3]; edge_scale:
+    [batch, nedge] in the storage order of the off-diagonal entries, or
+    None.  Returns values [batch, nnz] (batch 1 without scales and with one
+    position set)."""
+    colptr = np.asarray(colptr, np.int64)
+    rowind = np.asarray(rowind, np.int64)
+    tris = np.asarray(tris, np.int64)
+    mass = np.asarray(mass, np.float64)
+    pos = np.asarray(pos, np.float64)
+    nnz = int(colptr[-1])
+    cols = np.repeat(np.arange(n, dtype=np.int64), np.diff(colptr))
+    off = rowind != cols
+    key_store = cols[off] * n + rowind[off]           # (lo, hi), lo = column
+    nedge = key_store.size
+    batch = 1
+    if edge_scale is not None:
+        edge_scale = np.asarray(edge_scale, np.float64).reshape(-1, nedge)
+        batch = edge_scale.shape[0]
+    if pos.ndim == 3:
+        batch = max(batch, pos.shape[0])
+    out = np.zeros((batch, nnz))
+    # the three corners of every triangle and their opposite edges
+    corners = []
+    for c in range(3):
+        o, p, q = tris[:, c], tris[:, (c + 1) % 3], tris[:, (c + 2) % 3]
+        corners.append((o, np.minimum(p, q), np.maximum(p, q)))
+    for s in range(batch):
+        x = pos[s] if pos.ndim == 3 else pos
+        w = np.zeros(nedge)
+        hit = np.zeros(nedge, np.int64)
+        for o, lo, hi in corners:
+            u = x[lo] - x[o]
+            v = x[hi] - x[o]
+            dot = u[:, 0] * v[:, 0] + u[:, 1] * v[:, 1]
+            cross = np.abs(u[:, 0] * v[:, 1] - u[:, 1] * v[:, 0])
+            e = np.searchsorted(key_store, lo * n + hi)
+            if np.any(e >= nedge) or np.any(key_store[np.minimum(e, nedge - 1)] != lo * n + hi):
+                raise ValueError("a triangle edge is not a stored entry")
+            np.add.at(w, e, 0.5 * (dot / cross))
+            np.add.at(hit, e, 1)
+        if np.any(hit == 0) or np.any(hit > 2):
+            raise ValueError("every stored entry must be an edge of one or two triangles")
+        w = np.clip(w, clip_lo, clip_hi)
+        if edge_scale is not None:
+            w = np.clip(w * edge_scale[s], clip_lo, clip_hi)
+        vals = np.zeros(nnz)
+        vals[off] = -w
+        # diagonal: neighbours above (q > p, column p) ascending, then below
+        lo_e = key_store // n
+        hi_e = key_store % n
+        deg = np.zeros(n)
+        np.add.at(deg, lo_e, w)     # column p: its rows q > p, ascending
+        order = np.lexsort((lo_e, hi_e))
+        np.add.at(deg, hi_e[order], w[order])   # row p: columns q < p, ascending
+        diag = ~off
+        vals[diag] = (deg + mass_coeff * mass)[rowind[diag]]
+        out[s] = vals
+    return out
+
+
+def sparse_product(m, n, A, B, transB=False, D=None):
+    """C = A B (transB False) or A B^T (transB True), plus D when given, for
+    CSR matrices given as (rowptr, colind, values): the sparse products the
+    paper evaluates with its generated kernels (Sec. 5.2, Table tab:Lpow).
+    A is m x p; B is p x n (or n x p when transposed); D is m x n.  The
+    product itself is scipy's sparse matrix product in FP64 (a library
+    routine as one step); D is added after it.  Returns C as a scipy CSR
+    matrix with sorted indices (explicit zeros of the pattern kept out)."""
+    import scipy.sparse as sp
+    Ar, Ac, Av = A
+    Br, Bc, Bv = B
+    Am = sp.csr_matrix((np.asarray(Av, np.float64), np.asarray(Ac), np.asarray(Ar)),
+                       shape=(m, int(np.max(Ac)) + 1 if len(Ac) else 0))
+    nb_rows = len(Br) - 1
+    Bm = sp.csr_matrix((np.asarray(Bv, np.float64), np.asarray(Bc), np.asarray(Br)),
+                       shape=(nb_rows, int(np.max(Bc)) + 1 if len(Bc) else 0))
+    if transB:
+        Bm = Bm.T
+    p = max(Am.shape[1], Bm.shape[0])
+    Am = sp.csr_matrix((Am.data, Am.indices, Am.indptr), shape=(m, p))
+    Bm = sp.csr_matrix(Bm.tocsr(), shape=(p, Bm.shape[1]))
+    Bm = sp.csr_matrix((Bm.data, Bm.indices, Bm.indptr), shape=(p, n))
+    C = (Am @ Bm).tocsr()
+    if D is not None:
+        Dr, Dc, Dv = D
+        C = C + sp.csr_matrix((np.asarray(Dv, np.float64), np.asarray(Dc), np.asarray(Dr)),
+                              shape=(m, n))
+    C = C.tocsr()
+    C.sort_indices()
+    return C
+
+
+def sparse_product_pattern(m, n, A_rowptr, A_colind, B_rowptr, B_colind, transB=False,
+                           D_rowptr=None, D_colind=None):
+    """Structural pattern (rowptr, colind) of A B (or A B^T) union D: entry
+    (i, j) is present when some k has A_ik and B_kj (B_jk) stored, whatever
+    the values; written as a plain loop over the rows (small cases)."""
+    Ar = np.asarray(A_rowptr); Ac = np.asarray(A_colind)
+    Br = np.asarray(B_rowptr); Bc = np.asarray(B_colind)
+    if transB:
+        # rows of B^T: the columns of B
+        nbr = len(Br) - 1
+        brows = {}
+        for j in range(nbr):
+            for q in range(Br[j], Br[j + 1]):
+                brows.setdefault(int(Bc[q]), []).append(j)
+    else:
+        brows = {k: [int(c) for c in Bc[Br[k]:Br[k + 1]]] for k in range(len(Br) - 1)}
+    rowptr = [0]
+    colind = []
+    for i in range(m):
+        cols = set()
+        for q in range(Ar[i], Ar[i + 1]):
+            cols.update(brows.get(int(Ac[q]), []))
+        if D_rowptr is not None:
+            cols.update(int(c) for c in D_colind[D_rowptr[i]:D_rowptr[i + 1]])
+        colind.extend(sorted(cols))
+        rowptr.append(len(colind))
+    return np.array(rowptr, np.int64), np.array(colind, np.int32)

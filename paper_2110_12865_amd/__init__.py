@@ -30,6 +30,8 @@ SC_OK, SC_EINVAL, SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD, SC_ENOCONV = \
     0, -1, -2, -3, -4, -5, -6
 SC_F64, SC_F32 = 0, 1
 SC_REFINE_CLASSICAL, SC_REFINE_PCG = 0, 1
+SC_ORDER_NATURAL, SC_ORDER_GIVEN, SC_ORDER_ND = 0, 1, 2
+_ORDERINGS = {"natural": SC_ORDER_NATURAL, "given": SC_ORDER_GIVEN, "nd": SC_ORDER_ND}
 _METHODS = {"classical": SC_REFINE_CLASSICAL, "pcg": SC_REFINE_PCG}
 _DTYPES = {"f64": SC_F64, "f32": SC_F32}
 
@@ -39,9 +41,10 @@ EXPORTS = [
     "sc_plan_info", "sc_plan_export_blocks", "sc_plan_export_symbolic",
     "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create", "sc_numeric_destroy",
     "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
-    "sc_numeric_get_columns", "sc_numeric_profile", "sc_numeric_profile_read",
+    "sc_numeric_get_columns", "sc_numeric_get_block", "sc_numeric_profile",
+    "sc_numeric_profile_read",
     "sc_step_graph_create", "sc_step_graph_launch", "sc_step_graph_stats", "sc_step_graph_destroy",
-    "sc_autotune", "sc_adjoint",
+    "sc_autotune", "sc_adjoint", "sc_autotune_group",
 ]
 
 
@@ -54,7 +57,8 @@ class SpcholError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("relax", ctypes.c_int32), ("relax_cols", ctypes.c_int32),
                 ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32),
-                ("soa_min_batch", ctypes.c_int32), ("soa_seg_max", ctypes.c_int32)]
+                ("soa_min_batch", ctypes.c_int32), ("soa_seg_max", ctypes.c_int32),
+                ("ordering", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -65,7 +69,7 @@ class TuneEntry(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
                 ("ms", ctypes.c_double), ("flops", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("bytes", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
 
 
 class RefineStats(ctypes.Structure):
@@ -111,6 +115,7 @@ def _load():
         "sc_refine_solve": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, I32, P, P],
                             ctypes.c_int),
         "sc_numeric_get_columns": ([P, P, I32, I64, P, P], ctypes.c_int),
+        "sc_numeric_get_block": ([P, P, I32, I32, P], ctypes.c_int),
         "sc_numeric_profile": ([P, I32], ctypes.c_int),
         "sc_numeric_profile_read": ([P, I32, P, P], ctypes.c_int),
         "sc_step_graph_create": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, I32, P],
@@ -121,6 +126,8 @@ def _load():
         "sc_autotune": ([I64, P, P, P, P, I64, I32, ctypes.c_int, P, I32, I64, ctypes.c_double, P,
                          P, I32, P, P], ctypes.c_int),
         "sc_adjoint": ([P, P, P, P, P, I64, P, I32, I64, P], ctypes.c_int),
+        "sc_autotune_group": ([I32, P, P, P, P, P, I64, I32, ctypes.c_int, P, I32, I64,
+                               ctypes.c_double, P, P, I32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -149,6 +156,8 @@ def default_options(**kw) -> Options:
     o = Options()
     _check(_lib.sc_options_default(ctypes.byref(o)), "sc_options_default")
     for k, v in kw.items():
+        if k == "ordering" and isinstance(v, str):
+            v = _ORDERINGS[v]
         setattr(o, k, v)
     return o
 
@@ -293,6 +302,44 @@ def autotune(colptr, rowind, perm, values, b, dtype: str = "f64",
     return as_dict(best), rows
 
 
+def autotune_group(patterns, values, b, dtype: str = "f64", solves_per_factor: float = 1.0,
+                   stream=None):
+    """sc_autotune_group: the autotuner on the group plan of `patterns`
+    (sequence of (colptr, rowind) or (colptr, rowind, perm)); values and b
+    are the concatenated device arrays of the group.  Returns (options dict,
+    table) as autotune()."""
+    keep = []
+    cps, ris, pms, ns = [], [], [], []
+    for pat in patterns:
+        cp = np.ascontiguousarray(pat[0], np.int64)
+        ri = np.ascontiguousarray(pat[1], np.int32)
+        pm = None if len(pat) < 3 or pat[2] is None else np.ascontiguousarray(pat[2], np.int32)
+        keep += [cp, ri, pm]
+        cps.append(cp.ctypes.data)
+        ris.append(ri.ctypes.data)
+        pms.append(pm.ctypes.data if pm is not None else None)
+        ns.append(len(cp) - 1)
+    npat = len(ns)
+    ns = np.array(ns, np.int64)
+    cpa = (ctypes.c_void_p * npat)(*cps)
+    ria = (ctypes.c_void_p * npat)(*ris)
+    pma = (ctypes.c_void_p * npat)(*pms)
+    best = Options()
+    cap = 64
+    table = (TuneEntry * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(_lib.sc_autotune_group(npat, _ptr(ns), cpa, ria, pma, _dev_ptr(values, "float64"),
+                                  int(values.shape[1]), int(values.shape[0]), _DTYPES[dtype],
+                                  _dev_ptr(b, "float64"), int(b.shape[1]), int(b.shape[2]),
+                                  float(solves_per_factor), ctypes.byref(best), table, cap,
+                                  ctypes.byref(cnt), _stream_handle(stream)),
+           "sc_autotune_group")
+    as_dict = lambda o: {k: getattr(o, k) for k, _ in Options._fields_}
+    rows = [dict(as_dict(table[i].opt), factor_ms=table[i].factor_ms,
+                 solve_ms=table[i].solve_ms, score=table[i].score) for i in range(cnt.value)]
+    return as_dict(best), rows
+
+
 def analyze_group(patterns, **opts) -> GroupPlan:
     """patterns: sequence of (colptr, rowind) or (colptr, rowind, perm)."""
     return GroupPlan(patterns, default_options(**opts) if opts else None)
@@ -407,18 +454,31 @@ class Numeric:
                                            _ptr(cols), _ptr(out)), "sc_numeric_get_columns")
         return out
 
+    def get_block(self, b: int, s: int) -> np.ndarray:
+        """The whole stored c x w block of supernode s of factor b (host,
+        float64, [w, c]: row t of the result is column t of the block)."""
+        if not hasattr(self.plan, "_sn"):
+            self.plan._sn = self.plan.export_supernodes()
+        first, _, _, rowptr, _ = self.plan._sn
+        c, w = int(rowptr[s + 1] - rowptr[s]), int(first[s + 1] - first[s])
+        out = np.empty(c * w, np.float64)
+        _check(_lib.sc_numeric_get_block(self.plan._h, self._h, int(b), int(s), _ptr(out)),
+               "sc_numeric_get_block")
+        return out.reshape(w, c)
+
     def profile(self, enable: bool = True):
         """Time every later launch with HIP events (see sc_numeric_profile)."""
         _check(_lib.sc_numeric_profile(self._h, 1 if enable else 0), "sc_numeric_profile")
 
     def profile_read(self) -> dict:
         """Per-kernel totals {name: {launches, ms, flops, bytes}}; clears them."""
-        arr = (KernelStat * 16)()
+        arr = (KernelStat * 32)()
         cnt = ctypes.c_int32()
-        _check(_lib.sc_numeric_profile_read(self._h, 16, arr, ctypes.byref(cnt)),
+        _check(_lib.sc_numeric_profile_read(self._h, 32, arr, ctypes.byref(cnt)),
                "sc_numeric_profile_read")
         return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms,
-                                       "flops": arr[i].flops, "bytes": arr[i].bytes}
+                                       "flops": arr[i].flops, "bytes": arr[i].bytes,
+                                       "alg_bytes": arr[i].alg_bytes}
                 for i in range(cnt.value)}
 
     def _lcolptr(self):

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libspchol.so")
-SOURCES = ["analyze.cpp", "factor.hip", "solve.hip", "refine.hip", "capi.hip"]
+SOURCES = ["analyze.cpp", "order.cpp", "factor.hip", "solve.hip", "refine.hip", "capi.hip",
+           "assemble.hip", "products.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -21,6 +21,7 @@ const char *const kKernelNames[KK_Count] = {
 void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
 hipError_t spchol_solve_init();
+bool spchol_nd_order(int64_t n, const int64_t *colptr, const int32_t *rowind, int32_t *perm_out);
 
 namespace {
 
@@ -104,6 +105,24 @@ sc_status ensure_device(const sc_plan *P) {
     P->dev = D;
     P->dev_id = dev;
     return SC_OK;
+}
+
+// Built-in nested dissection of a pattern (order.cpp), after the checks
+// the ordering needs (the full validation follows in the plan builder).
+sc_status built_in_order(int64_t n, const int64_t *colptr, const int32_t *rowind,
+                         std::vector<int32_t> &perm) {
+    if (n < 1 || n >= INT32_MAX || !colptr || !rowind) return SC_EINVAL;
+    if (colptr[0] != 0) return SC_EPATTERN;
+    for (int64_t j = 0; j < n; j++)
+        if (colptr[j + 1] < colptr[j]) return SC_EPATTERN;
+    for (int64_t q = 0; q < colptr[n]; q++)
+        if (rowind[q] < 0 || rowind[q] >= n) return SC_EPATTERN;
+    try {
+        perm.resize(n);
+    } catch (const std::bad_alloc &) {
+        return SC_ENOMEM;
+    }
+    return spchol_nd_order(n, colptr, rowind, perm.data()) ? SC_OK : SC_ENOMEM;
 }
 
 sc_status map_err(hipError_t e) {
@@ -222,6 +241,7 @@ sc_status sc_options_default(sc_options *opt) {
     opt->small_front = 64;
     opt->soa_min_batch = kSoaMinBatch;
     opt->soa_seg_max = kSoaSegMax;
+    opt->ordering = SC_ORDER_GIVEN;
     return SC_OK;
 }
 
@@ -233,7 +253,15 @@ sc_status sc_analyze(int64_t n, const int64_t *colptr_host, const int32_t *rowin
     sc_options_default(&o);
     if (opt) o = *opt;
     if (o.relax_cols < 0 || o.small_front < 0 || !(o.relax_zeros >= 0.0)) return SC_EINVAL;
-    return spchol_build_plan(n, colptr_host, rowind_host, perm_host, o, 1, nullptr, nullptr,
+    if (o.ordering < SC_ORDER_NATURAL || o.ordering > SC_ORDER_ND) return SC_EINVAL;
+    if (perm_host && o.ordering != SC_ORDER_GIVEN) return SC_EINVAL;
+    if (o.ordering != SC_ORDER_ND)
+        return spchol_build_plan(n, colptr_host, rowind_host, perm_host, o, 1, nullptr, nullptr,
+                                 plan_out);
+    std::vector<int32_t> perm;
+    sc_status st = built_in_order(n, colptr_host, rowind_host, perm);
+    if (st != SC_OK) return st;
+    return spchol_build_plan(n, colptr_host, rowind_host, perm.data(), o, 1, nullptr, nullptr,
                              plan_out);
 }
 
@@ -247,6 +275,10 @@ sc_status sc_analyze_group(int32_t npat, const int64_t *n_host, const int64_t *c
     sc_options_default(&o);
     if (opt) o = *opt;
     if (o.relax_cols < 0 || o.small_front < 0 || !(o.relax_zeros >= 0.0)) return SC_EINVAL;
+    if (o.ordering < SC_ORDER_NATURAL || o.ordering > SC_ORDER_ND) return SC_EINVAL;
+    if (o.ordering != SC_ORDER_GIVEN && perm_host)
+        for (int32_t k = 0; k < npat; k++)
+            if (perm_host[k]) return SC_EINVAL;
     std::vector<int64_t> col0(npat + 1, 0), val0(npat + 1, 0);
     for (int32_t k = 0; k < npat; k++) {
         const int64_t nk = n_host[k];
@@ -280,8 +312,17 @@ sc_status sc_analyze_group(int32_t npat, const int64_t *n_host, const int64_t *c
         for (int64_t j = 0; j < nk; j++) colptr[c0 + j] = v0 + colptr_host[k][j];
         for (int64_t q = 0; q < val0[k + 1] - v0; q++)
             rowind[v0 + q] = int32_t(c0 + rowind_host[k][q]);
-        for (int64_t j = 0; j < nk; j++)
-            perm[c0 + j] = int32_t(c0 + (perm_host && perm_host[k] ? perm_host[k][j] : j));
+        std::vector<int32_t> own;
+        if (o.ordering == SC_ORDER_ND) {
+            const sc_status st = built_in_order(nk, colptr_host[k], rowind_host[k], own);
+            if (st != SC_OK) return st;
+        }
+        for (int64_t j = 0; j < nk; j++) {
+            int64_t pj = j;
+            if (o.ordering == SC_ORDER_ND) pj = own[j];
+            else if (o.ordering == SC_ORDER_GIVEN && perm_host && perm_host[k]) pj = perm_host[k][j];
+            perm[c0 + j] = int32_t(c0 + pj);
+        }
     }
     colptr[n] = val0[npat];
     return spchol_build_plan(n, colptr.data(), rowind.data(), perm.data(), o, npat, col0.data(),
@@ -531,6 +572,25 @@ sc_status sc_numeric_get_columns(const sc_plan_t *P, const sc_numeric_t *N, int3
     return SC_OK;
 }
 
+sc_status sc_numeric_get_block(const sc_plan_t *P, const sc_numeric_t *N, int32_t b, int32_t s,
+                               double *out_host) {
+    if (!P || !N || N->plan != P || b < 0 || b >= N->batch || s < 0 || s >= P->ns || !out_host)
+        return SC_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return SC_EDEVICE;
+    const SnDesc &d = P->sn[s];
+    const size_t sz = N->dtype == SC_F64 ? 8 : 4;
+    const size_t cnt = size_t(d.c) * d.w;
+    std::vector<unsigned char> blk(cnt * sz);
+    const unsigned char *src =
+        static_cast<const unsigned char *>(N->L) + (size_t(b) * P->Lsize + d.loff) * sz;
+    if (hipMemcpy(blk.data(), src, blk.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return SC_EDEVICE;
+    for (size_t q = 0; q < cnt; q++)
+        out_host[q] = sz == 8 ? reinterpret_cast<const double *>(blk.data())[q]
+                              : double(reinterpret_cast<const float *>(blk.data())[q]);
+    return SC_OK;
+}
+
 sc_status sc_numeric_profile(sc_numeric_t *N, int32_t enable) {
     if (!N) return SC_EINVAL;
     N->prof.on = enable != 0;
@@ -559,6 +619,7 @@ sc_status sc_numeric_profile_read(sc_numeric_t *N, int32_t cap, sc_kernel_stat *
         a.ms += ms;
         a.flops += r.flops;
         a.bytes += r.bytes;
+        a.alg_bytes += r.abytes;
     }
     pr.recs.clear();
     pr.used = 0;
@@ -692,15 +753,15 @@ void sc_step_graph_destroy(sc_graph_t *G) {
 
 namespace {
 
-// One factor + one solve of candidate `o`, timed with events on `st`
-// (best of `reps` after one warm-up pass).
-sc_status time_candidate(int64_t n, const int64_t *colptr, const int32_t *rowind,
-                         const int32_t *perm, const sc_options &o, const double *values_dev,
-                         int64_t ldv, int32_t batch, sc_dtype dtype, const double *b_dev,
-                         double *bw, int32_t nrhs, int64_t ldb, int reps, hipStream_t st,
-                         double *fms, double *sms) {
+// One factor + one solve of candidate `o` (plan made by `make_plan`), timed
+// with events on `st` (best of `reps` after one warm-up pass).
+template <typename MakePlan>
+sc_status time_candidate(const MakePlan &make_plan, const sc_options &o,
+                         const double *values_dev, int64_t ldv, int32_t batch, sc_dtype dtype,
+                         const double *b_dev, double *bw, int32_t nrhs, int64_t ldb, int reps,
+                         hipStream_t st, double *fms, double *sms) {
     sc_plan_t *P = nullptr;
-    sc_status r = sc_analyze(n, colptr, rowind, perm, &o, &P);
+    sc_status r = make_plan(o, &P);
     if (r != SC_OK) return r;
     sc_numeric_t *N = nullptr;
     r = sc_numeric_create(P, batch, dtype, &N);
@@ -734,33 +795,36 @@ sc_status time_candidate(int64_t n, const int64_t *colptr, const int32_t *rowind
     return r;
 }
 
-}  // namespace
 
-sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowind_host,
-                      const int32_t *perm_host, const double *values_dev, int64_t ldv,
-                      int32_t batch, sc_dtype dtype, const double *b_dev, int32_t nrhs,
-                      int64_t ldb, double solves_per_factor, sc_options *best_out,
-                      sc_tune_entry *table_host, int32_t table_cap, int32_t *ntable_out,
-                      void *stream) {
-    if (!best_out || !values_dev || !b_dev || batch < 1 || nrhs < 1 || ldb < n ||
-        !(solves_per_factor >= 0.0) || (dtype != SC_F64 && dtype != SC_F32) ||
-        table_cap < 0 || (table_cap > 0 && !table_host))
-        return SC_EINVAL;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    // candidates: front-kernel threshold x amalgamation width x solve layout
+// Candidates: front-kernel threshold x amalgamation width x solve layout
+// (x the built-in ordering against the natural one when no permutation is
+// given).
+std::vector<sc_options> tune_candidates(int32_t batch, bool try_orderings) {
     std::vector<sc_options> cand;
     const int32_t small_fronts[] = {32, 64, 128, 192};
     const int32_t relax_cols[] = {4, 16};
-    for (int32_t sf : small_fronts)
-        for (int32_t rc : relax_cols)
-            for (int soa = 0; soa < (batch >= 16 ? 2 : 1); soa++) {
-                sc_options o;
-                sc_options_default(&o);
-                o.small_front = sf;
-                o.relax_cols = rc;
-                o.soa_min_batch = soa ? 1 : -1;
-                cand.push_back(o);
-            }
+    for (int ord = 0; ord < (try_orderings ? 2 : 1); ord++)
+        for (int32_t sf : small_fronts)
+            for (int32_t rc : relax_cols)
+                for (int soa = 0; soa < (batch >= 16 ? 2 : 1); soa++) {
+                    sc_options o;
+                    sc_options_default(&o);
+                    o.small_front = sf;
+                    o.relax_cols = rc;
+                    o.soa_min_batch = soa ? 1 : -1;
+                    if (try_orderings) o.ordering = ord ? SC_ORDER_ND : SC_ORDER_NATURAL;
+                    cand.push_back(o);
+                }
+    return cand;
+}
+
+// Time every candidate (plans from make_plan) and keep the best score.
+template <typename MakePlan>
+sc_status tune_run(const MakePlan &make_plan, const std::vector<sc_options> &cand,
+                   const double *values_dev, int64_t ldv, int32_t batch, sc_dtype dtype,
+                   const double *b_dev, int32_t nrhs, int64_t ldb, double solves_per_factor,
+                   sc_options *best_out, sc_tune_entry *table_host, int32_t table_cap,
+                   int32_t *ntable_out, hipStream_t st) {
     double *bw = nullptr;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&bw),
                              sizeof(double) * size_t(batch) * nrhs * ldb);
@@ -770,8 +834,8 @@ sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowi
     sc_status result = SC_OK;
     for (const sc_options &o : cand) {
         double fms = 0.0, sms = 0.0;
-        result = time_candidate(n, colptr_host, rowind_host, perm_host, o, values_dev, ldv, batch,
-                                dtype, b_dev, bw, nrhs, ldb, 2, st, &fms, &sms);
+        result = time_candidate(make_plan, o, values_dev, ldv, batch, dtype, b_dev, bw, nrhs,
+                                ldb, 2, st, &fms, &sms);
         if (result != SC_OK) break;
         const double score = fms + solves_per_factor * sms;
         if (nt < table_cap) table_host[nt] = sc_tune_entry{o, fms, sms, score};
@@ -784,6 +848,48 @@ sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowi
     (void)hipFree(bw);
     if (ntable_out) *ntable_out = std::min(nt, table_cap);
     return result;
+}
+
+}  // namespace
+
+sc_status sc_autotune_group(int32_t npat, const int64_t *n_host,
+                            const int64_t *const *colptr_host, const int32_t *const *rowind_host,
+                            const int32_t *const *perm_host, const double *values_dev,
+                            int64_t ldv, int32_t batch, sc_dtype dtype, const double *b_dev,
+                            int32_t nrhs, int64_t ldb, double solves_per_factor,
+                            sc_options *best_out, sc_tune_entry *table_host, int32_t table_cap,
+                            int32_t *ntable_out, void *stream) {
+    if (!best_out || !values_dev || !b_dev || npat < 1 || !n_host || batch < 1 || nrhs < 1 ||
+        !(solves_per_factor >= 0.0) || (dtype != SC_F64 && dtype != SC_F32) ||
+        table_cap < 0 || (table_cap > 0 && !table_host))
+        return SC_EINVAL;
+    int64_t ntot = 0;
+    for (int32_t k = 0; k < npat; k++) ntot += n_host[k];
+    if (ldb < ntot) return SC_EINVAL;
+    auto make = [&](const sc_options &o, sc_plan_t **P) {
+        return sc_analyze_group(npat, n_host, colptr_host, rowind_host, perm_host, &o, P);
+    };
+    return tune_run(make, tune_candidates(batch, false), values_dev, ldv, batch, dtype, b_dev,
+                    nrhs, ldb, solves_per_factor, best_out, table_host, table_cap, ntable_out,
+                    static_cast<hipStream_t>(stream));
+}
+
+sc_status sc_autotune(int64_t n, const int64_t *colptr_host, const int32_t *rowind_host,
+                      const int32_t *perm_host, const double *values_dev, int64_t ldv,
+                      int32_t batch, sc_dtype dtype, const double *b_dev, int32_t nrhs,
+                      int64_t ldb, double solves_per_factor, sc_options *best_out,
+                      sc_tune_entry *table_host, int32_t table_cap, int32_t *ntable_out,
+                      void *stream) {
+    if (!best_out || !values_dev || !b_dev || batch < 1 || nrhs < 1 || ldb < n ||
+        !(solves_per_factor >= 0.0) || (dtype != SC_F64 && dtype != SC_F32) ||
+        table_cap < 0 || (table_cap > 0 && !table_host))
+        return SC_EINVAL;
+    auto make = [&](const sc_options &o, sc_plan_t **P) {
+        return sc_analyze(n, colptr_host, rowind_host, perm_host, &o, P);
+    };
+    return tune_run(make, tune_candidates(batch, perm_host == nullptr), values_dev, ldv, batch,
+                    dtype, b_dev, nrhs, ldb, solves_per_factor, best_out, table_host, table_cap,
+                    ntable_out, static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------------------

@@ -35,6 +35,8 @@ struct FLaunch {
     double words;     // algorithmic scalars of L/U moved per matrix
     double ibytes;    // algorithmic index/value bytes per matrix
     int32_t side = 0; // 1: launched on the side stream
+    double a_entries = 0.0;  // entries of A read per matrix
+    double l_exact = 0.0;    // exact entries of L written per matrix
 };
 
 struct SPanel {  // one 64-column panel step of a level's panel-solved supernodes
@@ -44,6 +46,7 @@ struct SPanel {  // one 64-column panel step of a level's panel-solved supernode
     double words = 0.0;      // factor scalars read per right-hand side
     double vwords = 0.0;     // vector entries per right-hand side
     double dwords = 0.0;     // inverse-block entries per matrix
+    double lx = 0.0;         // exact entries of L in the panel's columns
 };
 
 struct SClass {  // supernodes of one row class in one level
@@ -52,6 +55,7 @@ struct SClass {  // supernodes of one row class in one level
     double words = 0.0;        // factor scalars read
     double vwords = 0.0;       // vector entries per right-hand side
     double ibytes = 0.0;       // index bytes per right-hand side
+    double lx = 0.0;           // exact entries of L of these supernodes
 };
 
 struct SLaunch {  // one level of a triangular solve
@@ -67,6 +71,7 @@ struct SLaunch {  // one level of a triangular solve
     double vw_gather = 0.0, ib_gather = 0.0;
     double f_diag = 0.0, w_diag = 0.0, vw_diag = 0.0, ib_diag = 0.0;
     double f_rows = 0.0, w_rows = 0.0, vw_rows = 0.0, ib_rows = 0.0;
+    double lx_diag = 0.0, lx_rows = 0.0;  // exact entries of L in those parts
     int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
     int32_t maxc_pan = 0;
     double vw_pan = 0.0, ib_pan = 0.0;
@@ -119,11 +124,17 @@ enum KernelKind : int {
 extern const char *const kKernelNames[KK_Count];
 
 // Optional event timing of every launch (off by default).  Each launch is
-// bracketed by two events on the stream it runs on; the algorithmic flops
-// and HBM bytes of the launch are attached so rates can be formed.
+// bracketed by two events on the stream it runs on; its algorithmic flops
+// and two byte counts are attached so rates can be formed: `bytes`, the
+// library's model of what the launch moves (front and update blocks,
+// vectors, indices), and `abytes`, the algorithmic bytes of the method
+// itself (the factor: entries of A read, with their row index, plus the
+// exact entries of L written; a triangular solve: the exact entries of L
+// read once for all right-hand sides; the residual product: entries of A
+// read; other launches: none).
 struct Profiler {
     bool on = false;
-    struct Rec { int kind; hipEvent_t a, b; double flops, bytes; };
+    struct Rec { int kind; hipEvent_t a, b; double flops, bytes, abytes; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
@@ -135,9 +146,9 @@ struct Profiler {
         }
         return pool[used++];
     }
-    void begin(int kind, double flops, double bytes, hipStream_t st) {
+    void begin(int kind, double flops, double bytes, hipStream_t st, double abytes = 0.0) {
         if (!on) return;
-        Rec r{kind, get(), get(), flops, bytes};
+        Rec r{kind, get(), get(), flops, bytes, abytes};
         if (r.a) (void)hipEventRecord(r.a, st);
         recs.push_back(r);
     }

@@ -960,6 +960,20 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
     auto a_entries = [&](const SnDesc &d) {
         return double(P->acolptr[d.first + d.w] - P->acolptr[d.first]);
     };
+    // exact entries of L (amalgamation padding excluded) in column j with
+    // row index below rlim, and in the w columns of a supernode
+    auto exact_rows_below = [&](int32_t j, int64_t rlim) {
+        const int64_t t = int64_t(std::upper_bound(P->ffirst.begin(), P->ffirst.end(), j) -
+                                  P->ffirst.begin()) - 1;
+        const int32_t *a = P->frows.data() + P->frowptr[t] + (j - P->ffirst[t]);
+        const int32_t *b = P->frows.data() + P->frowptr[t + 1];
+        return double(std::lower_bound(a, b, rlim) - a);
+    };
+    auto l_exact = [&](const SnDesc &d) {
+        double c = 0.0;
+        for (int32_t j = d.first; j < d.first + d.w; j++) c += double(P->colcount[j]);
+        return c;
+    };
     for (int32_t l = 0; l < P->nlevels; l++) {
         const int32_t s0 = P->lvl_small_ptr[l], s1 = P->lvl_small_ptr[l + 1];
         if (s1 > s0) {
@@ -977,6 +991,8 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
                 f.flops += front_flops(d.c, d.w);
                 f.words += children_words(d) + double(d.c) * d.w + double(d.m) * (d.m + 1) / 2;
                 f.ibytes += a_entries(d) * 20.0;
+                f.a_entries += a_entries(d);
+                f.l_exact += l_exact(d);
             }
             D->fsched.push_back(f);
         }
@@ -990,6 +1006,7 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
             fa.flops += cw;
             fa.words += cw + double(d.c) * d.w + double(d.m) * (d.m + 1) / 2;
             fa.ibytes += a_entries(d) * 20.0;
+            fa.a_entries += a_entries(d);
         }
         D->fsched.push_back(fa);
         auto make_syrk = [&](int K0, int k, int outer) {
@@ -1031,6 +1048,8 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
                     const int kb = std::min(kTile, d.w - k);
                     fp.flops += front_flops(kb, kb) + double(kb) * kb * kb / 3.0;
                     fp.words += double(kb) * (kb + 1) + double(kb) * kb;
+                    for (int32_t j = d.first + k; j < d.first + k + kb; j++)
+                        fp.l_exact += exact_rows_below(j, int64_t(d.first) + k + kb);
                 }
                 D->fsched.push_back(fp);
                 FLaunch ft{FLaunch::Trsm, l, k, 0, 0, b0, b1 - b0, 0, 2 * kTile * kTile,
@@ -1043,6 +1062,9 @@ void build_schedule(const sc_plan *P, DevPlan *D) {
                     ft.gridx = std::max<int64_t>(ft.gridx, (nrem + kTile - 1) / kTile);
                     ft.flops += 2.0 * double(nrem) * kb * kb;
                     ft.words += 2.0 * double(nrem) * kb + double(kb) * kb;
+                    for (int32_t j = d.first + k; j < d.first + k + kb; j++)
+                        ft.l_exact += double(P->colcount[j]) -
+                                      exact_rows_below(j, int64_t(d.first) + k + kb);
                 }
                 if (ft.gridx > 0) D->fsched.push_back(ft);
                 add_syrk(K0, k, 0);
@@ -1094,7 +1116,8 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         }
         static const int kinds[] = {KK_SmallFront, KK_Assemble, KK_Potrf, KK_Trsm, KK_Syrk};
         const hipStream_t fst = f.side ? N->side : st;
-        prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, fst);
+        prof.begin(kinds[f.kind], f.flops * B, (f.words * wsz + f.ibytes) * B, fst,
+                   (f.a_entries * 12.0 + f.l_exact * wsz) * B);
         switch (f.kind) {
         case FLaunch::Small: {
             const int cmax = f.k;

@@ -504,7 +504,7 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     for (int it = 0;; it++) {
-        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
+        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
         apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st);
         prof.end(st);
         prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
@@ -579,11 +579,11 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     auto check = [&](int it, double *res, const double *pnext) -> hipError_t {
         const bool fuse = pnext && nblk == 1 && it > 0;
         if (pnext) {
-            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 5), st);
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 5), st, 12.0 * double(P->nnzA) * nact);
             apply_A2(P, W.vc, b, x, res, pnext, q, ldb, batch, nrhs, W.active,
                      fuse ? W.part2 : nullptr, st);
         } else {
-            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st);
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
             apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st);
         }
         prof.end(st);
@@ -636,7 +636,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         if (e != hipSuccess) return e;
         dots(r, pv, rz0);
         double *rz = rz0, *rzn = rz1;
-        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st);
+        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st, 12.0 * double(P->nnzA) * nact);
         apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);  // q_1 = A p_1
         prof.end(st);
         for (int it = 1; it <= maxit; it++) {

@@ -1537,7 +1537,8 @@ void classes_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
         const SClass &cl = l.cls[k];
         if (cl.n == 0) continue;
         N->prof.begin(KK_Fwd, cl.flops * nr * nb,
-                      (cl.words * sz + (cl.vwords * sz + cl.ibytes) * nr) * nb, st);
+                      (cl.words * sz + (cl.vwords * sz + cl.ibytes) * nr) * nb, st,
+                      cl.lx * sz * nb);
         const int nitems = cl.n * B;
         const int nseg = 256 / class_lanes(k);
         const dim3 g(unsigned((nitems + nseg - 1) / nseg));
@@ -1565,7 +1566,8 @@ void classes_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrh
         const SClass &cl = l.cls[k];
         if (cl.n == 0) continue;
         N->prof.begin(KK_Bwd, cl.flops * nr * nb,
-                      (cl.words * sz + (cl.vwords * sz + cl.ibytes) * nr) * nb, st);
+                      (cl.words * sz + (cl.vwords * sz + cl.ibytes) * nr) * nb, st,
+                      cl.lx * sz * nb);
         const int nitems = cl.n * B;
         const int nseg = 256 / class_lanes(k);
         const dim3 g(unsigned((nitems + nseg - 1) / nseg));
@@ -1604,7 +1606,8 @@ void panels_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
         const SPanel &pp = l.panels[q];
         if (pp.fwd_tiles == 0) continue;
         prof.begin(KK_FwdPanel, pp.flops * nr * nb,
-                   (pp.words * sz + pp.dwords * sz + pp.vwords * sz * nr) * nb, st);
+                   (pp.words * sz + pp.dwords * sz + pp.vwords * sz * nr) * nb, st,
+                   pp.lx * sz * nb);
         const dim3 g(unsigned(pp.fwd_tiles), unsigned(l.npan), unsigned(B));
         for (int r0 = 0; r0 < nrhs; r0 += 4) {
             const int nrr = std::min(4, nrhs - r0);
@@ -1633,7 +1636,8 @@ void panels_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs
     for (size_t q = l.panels.size(); q-- > 0;) {
         const SPanel &pp = l.panels[q];
         prof.begin(KK_BwdPanel, pp.flops * nr * nb,
-                   (pp.words * sz + pp.dwords * sz + pp.vwords * sz * nr) * nb, st);
+                   (pp.words * sz + pp.dwords * sz + pp.vwords * sz * nr) * nb, st,
+                   pp.lx * sz * nb);
         for (int r0 = 0; r0 < nrhs; r0 += 4) {
             const int nrr = std::min(4, nrhs - r0);
             const dim3 gp(unsigned(pp.bwd_chunks), unsigned(l.npan), unsigned(B));
@@ -1687,15 +1691,17 @@ void sn_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const int B = N->batch;
     const int64_t fvsize = int64_t(P->rows.size());
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
-    double f = 0.0, wds = 0.0, dw = 0.0, vw = 0.0;
+    double f = 0.0, wds = 0.0, dw = 0.0, vw = 0.0, lx = 0.0;
     for (const SPanel &pp : l.panels) {
         f += pp.flops;
         wds += pp.words;
         dw += pp.dwords;
         vw += pp.vwords;
+        lx += pp.lx;
     }
     N->prof.begin(KK_FwdPanel, f * nr * nb,
-                  ((wds + dw) * sz + (vw * sz + l.vw_pan * sz + l.ib_pan) * nr) * nb, st);
+                  ((wds + dw) * sz + (vw * sz + l.vw_pan * sz + l.ib_pan) * nr) * nb, st,
+                  lx * sz * nb);
     const dim3 g(unsigned(l.npan), unsigned(B));
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
         const int nrr = std::min(kMaxRhsPanel, nrhs - r0);
@@ -1720,14 +1726,16 @@ void sn_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const T *L = static_cast<const T *>(N->L);
     const int B = N->batch;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
-    double f = 0.0, wds = 0.0, dw = 0.0, vw = 0.0;
+    double f = 0.0, wds = 0.0, dw = 0.0, vw = 0.0, lx = 0.0;
     for (const SPanel &pp : l.panels) {
         f += pp.flops;
         wds += pp.words;
         dw += pp.dwords;
         vw += pp.vwords;
+        lx += pp.lx;
     }
-    N->prof.begin(KK_BwdPanel, f * nr * nb, ((wds + dw) * sz + vw * sz * nr) * nb, st);
+    N->prof.begin(KK_BwdPanel, f * nr * nb, ((wds + dw) * sz + vw * sz * nr) * nb, st,
+                  lx * sz * nb);
     const dim3 g(unsigned(l.npan), unsigned(B));
     for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsPanel) {
         const int nrr = std::min(kMaxRhsPanel, nrhs - r0);
@@ -1779,7 +1787,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
         if (by_rows(l)) {
             classes_forward<T, true>(l, P, N, nrhs, nullptr, st);
         } else if (l.nall > 0) {
-            prof.begin(KK_Fwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st);
+            prof.begin(KK_Fwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st, l.lx_diag * sz * nb);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
@@ -1795,7 +1803,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             prof.end(st);
         }
         if (l.nit > 0 && !by_rows(l)) {
-            prof.begin(KK_FwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st);
+            prof.begin(KK_FwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st, l.lx_rows * sz * nb);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAF(NRV)                                                                        \
@@ -1826,7 +1834,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             continue;
         }
         if (l.nit > 0) {
-            prof.begin(KK_BwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st);
+            prof.begin(KK_BwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st, l.lx_rows * sz * nb);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAB(NRV)                                                                        \
@@ -1842,7 +1850,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             prof.end(st);
         }
         if (l.nall > 0) {
-            prof.begin(KK_Bwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st);
+            prof.begin(KK_Bwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st, l.lx_diag * sz * nb);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_SOAB(NRV)                                                                        \
@@ -1904,10 +1912,25 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
 
 }  // namespace
 
+// Exact entries of L (amalgamation padding excluded) in column j with row
+// index below rlim.
+static double exact_rows_below(const sc_plan *P, int32_t j, int64_t rlim) {
+    const int64_t t = int64_t(std::upper_bound(P->ffirst.begin(), P->ffirst.end(), j) -
+                              P->ffirst.begin()) - 1;
+    const int32_t *a = P->frows.data() + P->frowptr[t] + (j - P->ffirst[t]);
+    const int32_t *b = P->frows.data() + P->frowptr[t + 1];
+    return double(std::lower_bound(a, b, rlim) - a);
+}
+
 // Solve schedule per level, with the algorithmic work of each launch (per
 // matrix; vector bytes per right-hand side).
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
     D->ssched.clear();
+    auto l_exact = [&](const SnDesc &d, int32_t j0, int32_t j1) {
+        double c = 0.0;
+        for (int32_t j = d.first + j0; j < d.first + j1; j++) c += double(P->colcount[j]);
+        return c;
+    };
     for (int32_t l = 0; l < P->nlevels; l++) {
         SLaunch s{};
         s.level = l;
@@ -1923,6 +1946,7 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
                 // the front vector in and out and its row indices
                 cl.vwords += 2.0 * d.c;
                 cl.ibytes += 4.0 * d.c;
+                cl.lx += l_exact(d, 0, d.w);
             }
         }
         s.all0 = P->slv_cls_ptr[size_t(l) * kSolveClasses];
@@ -1948,6 +1972,11 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
             s.w_rows += rect;
             s.vw_rows += 2.0 * d.m;
             s.ib_rows += 4.0 * d.m;
+            double dg = 0.0;
+            for (int32_t j = d.first; j < d.first + d.w; j++)
+                dg += exact_rows_below(P, j, int64_t(d.first) + d.w);
+            s.lx_diag += dg;
+            s.lx_rows += l_exact(d, 0, d.w) - dg;
         }
         s.pan0 = P->slv_pan_ptr[l];
         s.npan = P->slv_pan_ptr[l + 1] - s.pan0;
@@ -1973,6 +2002,7 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
                 pp.words += lw;
                 pp.vwords += below + 2.0 * kb;
                 pp.dwords += double(kb) * kb;
+                pp.lx += l_exact(d, c0, c0 + kb);
             }
             s.panels.push_back(pp);
         }

@@ -17,9 +17,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "spchol.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sc_[a-z_]+)\s*\(", text)))
+    """Every function declared by the headers under include/."""
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(sc_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
@@ -29,7 +35,8 @@ def test_library_exports_every_declared_function():
     lib = ctypes.CDLL(S.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert sorted(S.EXPORTS) == names
+    from paper_2110_12865_amd import mesh, products
+    assert sorted(S.EXPORTS + mesh.EXPORTS + products.EXPORTS) == names
 
 
 def test_status_strings():
@@ -179,3 +186,129 @@ def test_options_validation():
         S.analyze(p.colptr, p.rowind, w.perm, relax_zeros=-1.0)
     with pytest.raises(S.SpcholError):
         S.analyze(p.colptr, p.rowind, w.perm, small_front=-3)
+
+
+def test_cotan_create_rejects_bad_meshes():
+    """sc_cotan_create validates the mesh against the pattern before any
+    device work: a stored entry that is no mesh edge, a mesh edge that is
+    not stored, an edge of three triangles, a vertex out of range and a
+    degenerate triangle are SC_EPATTERN."""
+    import paper_2110_12865_amd as S
+    from paper_2110_12865_amd.mesh import CotanAssembly
+    tris = np.array([[0, 1, 2], [1, 3, 2]], np.int32)
+    edges = np.array([[0, 1], [0, 2], [1, 2], [1, 3], [2, 3]])
+    pat = W.lower_csc_from_edges(4, edges)
+    bad = {
+        "extra_entry": (W.lower_csc_from_edges(4, np.vstack([edges, [[0, 3]]])), tris),
+        "missing_edge": (W.lower_csc_from_edges(4, edges[:4]), tris),
+        "three_triangles": (W.lower_csc_from_edges(5, np.vstack([edges, [[1, 4], [2, 4]]])),
+                            np.array([[0, 1, 2], [1, 3, 2], [1, 2, 4]], np.int32)),
+        "out_of_range": (pat, np.array([[0, 1, 2], [1, 4, 2]], np.int32)),
+        "degenerate": (pat, np.array([[0, 1, 2], [1, 1, 2]], np.int32)),
+    }
+    # in the three-triangle case edge (1, 2) has the corners 0, 3 and 4
+    for name, (p, t) in bad.items():
+        with pytest.raises(S.SpcholError) as ei:
+            CotanAssembly(p.n, p.colptr, p.rowind, t)
+        assert ei.value.status == S.SC_EPATTERN, name
+
+
+def _csr_random(rng, rows, cols, per_row):
+    rp, ci = [0], []
+    for _ in range(rows):
+        ci.extend(np.sort(rng.choice(cols, size=min(per_row, cols), replace=False)).tolist())
+        rp.append(len(ci))
+    return np.array(rp, np.int64), np.array(ci, np.int32)
+
+
+@pytest.mark.parametrize("transB,with_d", [(False, False), (True, False), (False, True),
+                                           (True, True)])
+def test_product_pattern_bit_exact(transB, with_d):
+    """The host pass of sc_spprod_create: C's pattern equals the oracle's
+    structural pattern of A B (A B^T) union D, entry for entry, and the term
+    count equals the number of (k) pairs."""
+    from paper_2110_12865_amd.products import SparseProduct
+    rng = np.random.default_rng(40 + 2 * transB + with_d)
+    m, p, n = 37, 29, 31
+    A = _csr_random(rng, m, p, 5)
+    B = _csr_random(rng, n, p, 4) if transB else _csr_random(rng, p, n, 4)
+    D = _csr_random(rng, m, n, 3) if with_d else None
+    pr = SparseProduct(m, p, n, A, B, transB, D)
+    rp, ci = oracle.sparse_product_pattern(m, n, A[0], A[1], B[0], B[1], transB,
+                                           *(D if with_d else (None, None)))
+    assert np.array_equal(pr.rowptr, rp)
+    assert np.array_equal(pr.colind, ci)
+    Ad = np.zeros((m, p), int)
+    for i in range(m):
+        Ad[i, A[1][A[0][i]:A[0][i + 1]]] = 1
+    Bd = np.zeros((n, p) if transB else (p, n), int)
+    for i in range(Bd.shape[0]):
+        Bd[i, B[1][B[0][i]:B[0][i + 1]]] = 1
+    assert pr.nterms == int((Ad @ (Bd.T if transB else Bd)).sum())
+
+
+def test_product_rejects_bad_patterns():
+    import paper_2110_12865_amd as S
+    from paper_2110_12865_amd.products import SparseProduct
+    A = (np.array([0, 2, 3], np.int64), np.array([1, 0, 1], np.int32))   # row 0 unsorted
+    B = (np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32))
+    with pytest.raises(S.SpcholError) as ei:
+        SparseProduct(2, 2, 2, A, B)
+    assert ei.value.status == S.SC_EPATTERN
+    A = (np.array([0, 1, 2], np.int64), np.array([0, 2], np.int32))      # column out of range
+    with pytest.raises(S.SpcholError) as ei:
+        SparseProduct(2, 2, 2, A, B)
+    assert ei.value.status == S.SC_EPATTERN
+
+
+@pytest.mark.parametrize("name,w", [
+    ("grid3d_12^3", W.small_grid((12, 12, 12), "nd", seed=61)),
+    ("grid2d_40x30", W.small_grid((40, 30), "nd", seed=62)),
+    ("trimesh_30", W.trimesh_workload(30, batch=1, nrhs=1, seed=63)),
+    ("random_300", W.random_spd(300, 0.02, seed=64)),
+    ("disconnected", W.random_spd(200, 0.0, seed=65)),
+], ids=lambda x: x if isinstance(x, str) else "")
+def test_builtin_nd_ordering_valid(name, w):
+    """ordering = nd: the plan's permutation is a permutation of 0..n-1, the
+    symbolic result equals the oracle's under that permutation bit for bit
+    (parity unpinned for the ordering itself: it has no single right
+    answer), and on grids its fill stays within 1.25x of the geometric
+    nested dissection."""
+    import paper_2110_12865_amd as S
+    p = w.pattern
+    plan = S.analyze(p.colptr, p.rowind, None, ordering="nd")
+    perm, parent, Lcolptr, Lrowind = plan.export_symbolic()
+    assert np.array_equal(np.sort(perm), np.arange(p.n))
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, perm)
+    assert np.array_equal(parent, sym.parent)
+    assert np.array_equal(Lcolptr, sym.Lcolptr)
+    assert np.array_equal(Lrowind, sym.Lrowind)
+    if w.perm is not None:
+        geo = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+        assert sym.nnzL <= 1.25 * geo.nnzL
+    nat = oracle.symbolic(p.n, p.colptr, p.rowind, None)
+    assert sym.nnzL <= nat.nnzL
+
+
+def test_ordering_option_rules():
+    """natural ignores nothing: it equals no permutation; a permutation
+    together with natural or nd ordering is SC_EINVAL; group plans order
+    every pattern on its own."""
+    import paper_2110_12865_amd as S
+    w = W.small_grid((9, 8), "nd", seed=66)
+    p = w.pattern
+    a = S.analyze(p.colptr, p.rowind, None, ordering="natural").export_symbolic()
+    b = S.analyze(p.colptr, p.rowind, None).export_symbolic()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    for o in ("natural", "nd"):
+        with pytest.raises(S.SpcholError) as ei:
+            S.analyze(p.colptr, p.rowind, w.perm, ordering=o)
+        assert ei.value.status == S.SC_EINVAL
+    w2 = W.small_grid((5, 5, 5), "nd", seed=67)
+    g = S.analyze_group([(p.colptr, p.rowind, None), (w2.pattern.colptr, w2.pattern.rowind, None)],
+                        ordering="nd")
+    gperm = g.export_symbolic()[0]
+    one = S.analyze(p.colptr, p.rowind, None, ordering="nd").export_symbolic()[0]
+    two = S.analyze(w2.pattern.colptr, w2.pattern.rowind, None, ordering="nd").export_symbolic()[0]
+    assert np.array_equal(gperm, np.concatenate([one, two + p.n]))

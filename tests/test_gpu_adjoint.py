@@ -105,25 +105,33 @@ def test_autograd_gradcheck_tiny():
 
 
 def test_adjoint_full_size_sampled():
-    """The 40^3 block system (n = 192000, nnz 2,068,800), one value set:
-    the GPU gradient on 200 sampled entries against the closed form
-    evaluated with the GPU's own x and lambda = A^{-1}(x - x*) checked by its
-    residual, and dL/db equal to that lambda."""
+    """The 40^3 block system (n = 192000, nnz 2,068,800) in the benchmark's
+    launch configuration (16 value sets, FP64): for value sets 0 and 15,
+    x and lambda = A^{-1}(x - x*) checked by their residuals with the
+    oracle's product (relres <= 1e-13; strict diagonal dominance bounds
+    kappa_2 by 1.81e3, so the forward error is at most kappa_2 relres
+    <= 2e-10), the GPU gradient on 200 sampled entries against the closed
+    form evaluated with that x and lambda, and dL/db equal to lambda."""
     import torch
     import paper_2110_12865_amd as S
-    w = W.config(4, batch=1)
+    w = W.config(4)
     p = w.pattern
-    log("blockvec 40^3 n=%d nnz=%d" % (p.n, p.nnz))
+    log("blockvec 40^3 n=%d nnz=%d batch=%d" % (p.n, p.nnz, w.batch))
     x, gv, gb = _gpu_grads(w)
-    gx = x[0] - w.extra["xstar"][0]
-    lam = gb[0]
-    # lambda solves A lambda = x - x*
-    r = oracle.spmv(p.n, p.colptr, p.rowind, w.values[0], lam) - gx
-    assert np.linalg.norm(r) / np.linalg.norm(gx) <= 1e-12
     rows = p.rows
     cols = p.cols
-    ks = np.random.default_rng(6).choice(p.nnz, size=200, replace=False)
-    for k in ks:
-        i, j = rows[k], cols[k]
-        ref = -lam[0, i] * x[0, 0, j] if i == j else -(lam[0, i] * x[0, 0, j] + lam[0, j] * x[0, 0, i])
-        assert abs(gv[0, k] - ref) <= 1e-12 * max(1.0, abs(ref))
+    for s in (0, w.batch - 1):
+        rel, _ = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[s], x[s], w.b[s])
+        gx = x[s] - w.extra["xstar"][s]
+        lam = gb[s]
+        r = oracle.spmv(p.n, p.colptr, p.rowind, w.values[s], lam) - gx
+        rl = np.linalg.norm(r) / np.linalg.norm(gx)
+        log("  set %d: relres x %.2e, lambda %.2e" % (s, rel.max(), rl))
+        assert rel.max() <= 1e-13
+        assert rl <= 1e-13
+        ks = np.random.default_rng(6 + s).choice(p.nnz, size=200, replace=False)
+        for k in ks:
+            i, j = rows[k], cols[k]
+            ref = (-lam[0, i] * x[s, 0, j] if i == j
+                   else -(lam[0, i] * x[s, 0, j] + lam[0, j] * x[s, 0, i]))
+            assert abs(gv[s, k] - ref) <= 1e-12 * max(1.0, abs(ref))

@@ -197,3 +197,85 @@ def test_autotuner_picks_a_measured_candidate():
     Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[3], sym)
     xo = oracle.solve(sym, Lx, w.b[3])
     assert oracle.forward_error(x[3, 1], xo[1]) <= 1e-12
+
+
+def test_full_uneven_batch_against_oracle():
+    """The whole uneven batch in the benchmark's launch configuration: 8
+    patterns (2D 16^2 .. 128^2, 3D 8^3 .. 24^3, geometric nested
+    dissection) x 32 value sets in one group plan.  FP64: for value sets 0
+    and 31 of every pattern, the factor (per-column error <= 1e-12) and x
+    (<= 1e-12) against the oracle run on that pattern alone.  FP32 factor +
+    refinement to the stop rule: x of the same systems within 1e-10 of the
+    oracle."""
+    import paper_2110_12865_amd as S
+    ws = W.config(3)
+    plan = _group_plan(ws)
+    col0, _ = plan.export_blocks()
+    vals, b = W.group_arrays(ws)
+    log("uneven batch: %d patterns x %d sets, n = %d" % (len(ws), vals.shape[0], b.shape[2]))
+    dv = torch.from_numpy(vals).cuda()
+    num = plan.numeric(vals.shape[0], "f64")
+    num.factor(dv)
+    assert np.all(num.info() == 0)
+    db = torch.from_numpy(b).cuda()
+    num.solve(db)
+    x64 = db.cpu().numpy()
+    n32 = plan.numeric(vals.shape[0], "f32")
+    n32.factor(dv)
+    assert np.all(n32.info() == 0)
+    db = torch.from_numpy(b).cuda()
+    x32 = torch.empty_like(db)
+    rc, st = n32.refine_solve(dv, db, x32, tol=1e-10, maxit=10, method="classical")
+    assert rc == S.SC_OK
+    x32 = x32.cpu().numpy()
+    for k, w in enumerate(ws):
+        p = w.pattern
+        sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+        cols = np.arange(col0[k], col0[k + 1], dtype=np.int32)
+        for s in (0, w.batch - 1):
+            Lx, inf = oracle.factor(p.n, p.colptr, p.rowind, w.values[s], sym)
+            assert inf == 0
+            xo = oracle.solve(sym, Lx, w.b[s])
+            ferr = oracle.factor_error(sym.Lcolptr, num.get_columns(s, cols), Lx)
+            e64 = oracle.forward_error(x64[s, 0, col0[k]:col0[k + 1]], xo[0])
+            e32 = oracle.forward_error(x32[s, 0, col0[k]:col0[k + 1]], xo[0])
+            log("  %s set %d: factor err %.2e, x err f64 %.2e, f32+refinement %.2e"
+                % (w.name, s, ferr, e64, e32))
+            assert ferr <= 1e-12
+            assert e64 <= 1e-12
+            assert e32 <= 1e-10
+
+
+def test_group_autotune_choice_is_valid():
+    """sc_autotune_group times every candidate on the group plan and returns
+    the one with the smallest score; the chosen options build a group plan
+    whose solutions match the oracle (the choice itself has no single right
+    answer: parity unpinned, validity checked)."""
+    import paper_2110_12865_amd as S
+    ws = _members(batch=3, nrhs=1)
+    vals, b = W.group_arrays(ws)
+    dv = torch.from_numpy(vals).cuda()
+    db = torch.from_numpy(b).cuda()
+    pats = [(w.pattern.colptr, w.pattern.rowind, w.perm) for w in ws]
+    best, table = S.autotune_group(pats, dv, db, "f64", solves_per_factor=2.0)
+    log("group autotune: %d candidates, best %s" % (len(table), best))
+    assert len(table) == 8
+    assert min(r["score"] for r in table) == pytest.approx(
+        [r for r in table if all(r[k] == best[k] for k in ("small_front", "relax_cols",
+                                                           "soa_min_batch"))][0]["score"])
+    assert torch.equal(db, torch.from_numpy(b).cuda())      # b not modified
+    opts = {k: best[k] for k in ("small_front", "relax_cols", "soa_min_batch")}
+    plan = _group_plan(ws, **opts)
+    col0, _ = plan.export_blocks()
+    num = plan.numeric(vals.shape[0], "f64")
+    num.factor(dv)
+    assert np.all(num.info() == 0)
+    num.solve(db)
+    x = db.cpu().numpy()
+    for k, w in enumerate(ws):
+        p = w.pattern
+        sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+        for s in range(w.batch):
+            Lx, _ = oracle.factor(p.n, p.colptr, p.rowind, w.values[s], sym)
+            xo = oracle.solve(sym, Lx, w.b[s])
+            assert oracle.forward_error(x[s, 0, col0[k]:col0[k + 1]], xo[0]) <= 1e-12

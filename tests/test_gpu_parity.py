@@ -198,11 +198,44 @@ def test_fp32_factor_accuracy(opts):
     assert xerr <= 1e-4
 
 
+def _sampled_llt_check(plan, num, w, rows_sel):
+    """(L L^T)_ij against (P A P^T)_ij for every pair of the selected rows
+    (permuted numbering), within the componentwise backward-error bound of
+    Cholesky: |L L^T - P A P^T| <= gamma_{c+1} |L| |L|^T with c the longest
+    column (Higham, Accuracy and Stability of Numerical Algorithms, Thm 10.3),
+    gamma_k = k u / (1 - k u).  Returns the largest ratio error / bound."""
+    import scipy.sparse as sp
+    p = w.pattern
+    n = p.n
+    _, _, Lcolptr, Lrowind = plan.export_symbolic()
+    Lx = num.get_columns(0, all_columns(n))
+    L = sp.csc_matrix((Lx, Lrowind, Lcolptr), shape=(n, n))
+    LR = L[rows_sel, :].tocsr()
+    G = (LR @ LR.T).toarray()
+    absLR = abs(LR)
+    B = (absLR @ absLR.T).toarray()
+    # (P A P^T)_ij = A_{perm i, perm j} from the lower CSC pattern
+    perm = np.asarray(w.perm, np.int64)
+    A = sp.csc_matrix((w.values[0], p.rowind, p.colptr), shape=(n, n))
+    A = (A + sp.tril(A, -1).T).tocsr()
+    orig = perm[rows_sel]
+    Asub = A[orig, :][:, orig].toarray()
+    c = int(np.max(np.diff(Lcolptr)))
+    u = 2.0 ** -53
+    gamma = (c + 1) * u / (1 - (c + 1) * u)
+    err = np.abs(G - Asub)
+    return float(np.max(err / (gamma * B + 1e-300))), float(np.max(err))
+
+
 def test_full_size_grid3d_64_nd():
     """The 64^3 7-point system (n = 262144) in the benchmark's launch
     configuration: the leading 32768 x 32768 block of L against the oracle
     (rows < m of L are the factor of the leading m x m block of P A P^T),
-    the residual of the full solve, and sampled entries of L L^T = P A P^T."""
+    the residual of the full solve, and, for 48 rows of the top separators
+    (the 4096-column root front and the separators below it, where the
+    tiled MFMA kernels and the lookahead run), every entry (L L^T)_ij
+    against (P A P^T)_ij within Cholesky's componentwise backward-error
+    bound."""
     w = W.config(1)
     p = w.pattern
     log("full-size 64^3: factor + solve")
@@ -225,6 +258,14 @@ def test_full_size_grid3d_64_nd():
     ferr = oracle.factor_error(sym.Lcolptr[:m + 1], Lg_lead, Lx[:sym.Lcolptr[m]])
     log("  leading-block factor err %.2e" % ferr)
     assert ferr <= TOL_L
+    del Lg, keep, Lg_lead, sym, Lx
+    rng = np.random.default_rng(201)
+    rows_sel = np.sort(np.concatenate([
+        rng.choice(np.arange(p.n - 4096, p.n), 32, replace=False),       # root front
+        rng.choice(np.arange(p.n - 12288, p.n - 4096), 16, replace=False)]))  # next separators
+    ratio, emax = _sampled_llt_check(plan, num, w, rows_sel)
+    log("  sampled L L^T: max |error| %.2e, max error / bound %.3f" % (emax, ratio))
+    assert ratio <= 1.0
 
 
 @pytest.mark.parametrize("name,make", [
@@ -357,3 +398,42 @@ def test_panel_workgroup_path_bitwise_equal(dtype, soa):
         xo = oracle.solve(sym, Lx, w16.b[15])
         for r in range(w16.nrhs):
             assert oracle.forward_error(x16[15, r], xo[r]) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,make,opts", [
+    ("grid3d_14^3_relaxed", lambda: W.small_grid((14, 14, 14), "nd", seed=210),
+     {"relax_cols": 16, "relax_zeros": 0.3}),
+    ("trimesh_60_relaxed_tiled", lambda: W.trimesh_workload(60, batch=2, nrhs=1, seed=211),
+     {"relax_cols": 16, "relax_zeros": 0.3, "small_front": 1}),
+    ("random_400_relaxed_lds", lambda: W.random_spd(400, 0.02, seed=212),
+     {"relax_cols": 32, "relax_zeros": 0.5, "small_front": 200}),
+], ids=["registers", "tiled", "workgroup"])
+def test_padded_entries_exactly_zero(name, make, opts, dtype):
+    """Amalgamation stores entries outside the exact pattern of L; every
+    product that reaches such an entry has a stored-zero factor, so each
+    comes out exactly 0.0 (reading 4 of the oracle's conventions), in every
+    front kernel family, while the exact entries match the oracle."""
+    w = make()
+    p = w.pattern
+    log("case %s %s opts=%s" % (name, dtype, opts))
+    plan, num, info, x = run_library(w, dtype, opts=opts)
+    assert np.all(info == 0)
+    first, _, _, rowptr, rows = plan.export_supernodes()
+    _, _, Lcolptr, Lrowind = plan.export_symbolic()
+    npad = 0
+    for s in range(len(first) - 1):
+        blk = num.get_block(0, s)
+        R = rows[rowptr[s]:rowptr[s + 1]]
+        for t in range(first[s + 1] - first[s]):
+            j = first[s] + t
+            exact = set(Lrowind[Lcolptr[j]:Lcolptr[j + 1]].tolist())
+            for i in range(t, len(R)):
+                if int(R[i]) not in exact:
+                    npad += 1
+                    assert blk[t, i] == 0.0, (s, t, i)
+    log("  %d padded entries, all 0.0" % npad)
+    assert npad > 0
+    if dtype == "f64":
+        sym, Lx, _, _ = oracle_run(w)
+        assert oracle.factor_error(sym.Lcolptr, num.get_columns(0, all_columns(p.n)), Lx) <= TOL_L

@@ -221,3 +221,39 @@ def test_step_graph_blocks_workspace_growth():
     xf = b3.clone()
     fresh.solve(xf)
     assert torch.equal(xb, xf)
+
+
+def test_full_size_mesh_refined_against_oracle():
+    """The 512^2 mesh in the benchmark's launch configuration (64 value
+    sets, 3 right-hand sides, FP32 factor, PCG refinement to the stop rule):
+    x of value sets 0 and 63 against the FP64 oracle, accepted at 1e-10 or,
+    as the system's conditioning demands (kappa_1 ~ 1e9..1e10), within
+    10 kappa_1 u with kappa_1 estimated from oracle solves; every system's
+    stop clause re-evaluated by the oracle on the host."""
+    import paper_2110_12865_amd as S
+    w = W.config(2)
+    p = w.pattern
+    log("mesh 512^2: batch %d, %d rhs" % (w.batch, w.nrhs))
+    plan = S.analyze(p.colptr, p.rowind, w.perm)
+    num = plan.numeric(w.batch, "f32")
+    vals = torch.from_numpy(np.ascontiguousarray(w.values)).cuda()
+    num.factor(vals)
+    assert np.all(num.info() == 0)
+    b = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+    x = torch.empty_like(b)
+    rc, stats = num.refine_solve(vals, b, x, tol=1e-10, maxit=30, method="pcg")
+    assert rc == S.SC_OK
+    x = x.cpu().numpy()
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    for s in (0, w.batch - 1):
+        Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[s], sym)
+        assert info == 0
+        xo = oracle.solve(sym, Lx, w.b[s])
+        kap = oracle.kappa1_estimate(p.n, p.colptr, p.rowind, w.values[s], sym, Lx)
+        cl = oracle.stop_clause(p.n, p.colptr, p.rowind, w.values[s], x[s], w.b[s], 1e-10)
+        for r in range(w.nrhs):
+            err = oracle.forward_error(x[s, r], xo[r])
+            log("  set %d rhs %d: x err %.2e, kappa_1 ~ %.2e, clause %d (GPU %d)"
+                % (s, r, err, kap, cl[r], stats[s * w.nrhs + r]["clause"]))
+            assert oracle.within_conditioning(err, 1e-10, kap)
+            assert cl[r] in (1, 2)

@@ -519,3 +519,191 @@ def test_within_conditioning_rule():
     assert oracle.within_conditioning(1e-11, 1e-10, 1e20)
     assert not oracle.within_conditioning(1e-6, 1e-10, 1e6)       # 10 k u = 1.1e-9
     assert oracle.within_conditioning(1e-6, 1e-10, 1e10)          # 10 k u = 1.1e-5
+
+
+# --- cotangent assembly ---------------------------------------------------
+
+def _mesh_pattern(nv, tris):
+    e = np.concatenate([np.asarray(tris)[:, [0, 1]], np.asarray(tris)[:, [1, 2]],
+                        np.asarray(tris)[:, [2, 0]]])
+    e = np.unique(np.sort(e, 1), axis=0)
+    return W.lower_csc_from_edges(nv, e)
+
+
+def _regular_grid(k):
+    pos, tris = W.trimesh_geometry(k, np.random.default_rng(0))
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
+    pos = np.stack([ii.ravel(), jj.ravel()], 1).astype(np.float64)   # no jitter
+    return pos, tris
+
+
+def test_cotan_regular_grid_closed_form():
+    """Unjittered grid split along (i,j)-(i+1,j+1): an axis edge sees two
+    45-degree angles (cot 1) inside the mesh and one on the boundary; a
+    diagonal edge sees two right angles (cot 0), clipped up to clip_lo;
+    the diagonal is the sum of the weights plus c m."""
+    k = 6
+    pos, tris = _regular_grid(k)
+    n = k * k
+    pat = _mesh_pattern(n, tris)
+    m = np.linspace(1.0, 2.0, n)
+    v = oracle.cotan_values(n, pat.colptr, pat.rowind, pos, tris, m, 0.25, 0.05, 2.0)[0]
+    rows, cols = pat.rows, pat.cols
+    for q in range(pat.nnz):
+        a, b = int(rows[q]), int(cols[q])
+        if a == b:
+            continue
+        ia, ja, ib, jb = a % k, a // k, b % k, b // k
+        if abs(ia - ib) + abs(ja - jb) == 2:          # diagonal edge
+            assert v[q] == -0.05
+        elif (ia == ib and ia in (0, k - 1)) or (ja == jb and ja in (0, k - 1)):
+            assert v[q] == -0.5                        # boundary axis edge
+        else:
+            assert v[q] == -1.0                        # interior axis edge
+    A = oracle.to_dense_permuted(n, pat.colptr, pat.rowind, v)
+    off = A - np.diag(np.diag(A))
+    assert np.allclose(np.diag(A), -off.sum(1) + 0.25 * m, rtol=0, atol=1e-15)
+
+
+def test_cotan_equilateral_triangle():
+    """One equilateral triangle: every angle is 60 degrees, cot = 1/sqrt(3),
+    so each edge weighs 1/(2 sqrt(3))."""
+    pos = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, math.sqrt(3.0) / 2]])
+    tris = np.array([[0, 1, 2]])
+    pat = _mesh_pattern(3, tris)
+    v = oracle.cotan_values(3, pat.colptr, pat.rowind, pos, tris, np.zeros(3), 0.0,
+                            -10.0, 10.0)[0]
+    off = pat.rows != pat.cols
+    assert np.allclose(v[off], -1.0 / (2.0 * math.sqrt(3.0)), rtol=1e-15, atol=0)
+    assert np.allclose(v[~off], 1.0 / math.sqrt(3.0), rtol=1e-15, atol=0)
+
+
+def test_cotan_against_angles():
+    """A jittered mesh against cot(theta) = 1/tan(theta) of the corner angle
+    theta = atan2(|u x v|, u . v) computed per corner in plain Python."""
+    k = 7
+    rng = np.random.default_rng(3)
+    pos, tris = W.trimesh_geometry(k, rng)
+    n = k * k
+    pat = _mesh_pattern(n, tris)
+    m = rng.uniform(0.5, 1.5, n)
+    v = oracle.cotan_values(n, pat.colptr, pat.rowind, pos, tris, m, 1e-3, -100.0, 100.0)[0]
+    w = {}
+    for t in tris:
+        for c in range(3):
+            o, a, b = int(t[c]), int(t[(c + 1) % 3]), int(t[(c + 2) % 3])
+            ux, uy = pos[a] - pos[o]
+            vx, vy = pos[b] - pos[o]
+            th = math.atan2(abs(ux * vy - uy * vx), ux * vx + uy * vy)
+            key = (min(a, b), max(a, b))
+            w[key] = w.get(key, 0.0) + 0.5 / math.tan(th)
+    deg = np.zeros(n)
+    for q in range(pat.nnz):
+        a, b = int(pat.rows[q]), int(pat.cols[q])
+        if a != b:
+            ref = w[(b, a)]
+            assert v[q] == pytest.approx(-ref, rel=1e-12, abs=1e-14)
+            deg[a] += ref
+            deg[b] += ref
+    for q in range(pat.nnz):
+        a = int(pat.rows[q])
+        if a == int(pat.cols[q]):
+            assert v[q] == pytest.approx(deg[a] + 1e-3 * m[a], rel=1e-12)
+
+
+def test_cotan_edge_scale_and_clip():
+    """Per-set scales multiply the clipped weights and are clipped again;
+    positions per value set give independent systems."""
+    k = 5
+    pos, tris = _regular_grid(k)
+    n = k * k
+    pat = _mesh_pattern(n, tris)
+    nedge = int(np.sum(pat.rows != pat.cols))
+    sc = np.stack([np.full(nedge, 2.0), np.full(nedge, 0.5)])
+    v = oracle.cotan_values(n, pat.colptr, pat.rowind, pos, tris, np.ones(n), 0.0, 0.05, 1.5,
+                            edge_scale=sc)
+    base = oracle.cotan_values(n, pat.colptr, pat.rowind, pos, tris, np.ones(n), 0.0, 0.05, 1.5)[0]
+    off = pat.rows != pat.cols
+    assert np.array_equal(v[0][off], np.maximum(-1.5, 2.0 * base[off]))   # 2 x 1 -> 1.5
+    assert np.array_equal(v[1][off], np.minimum(-0.05, 0.5 * base[off]))  # 0.05/2 -> 0.05
+    # a second position set (scaled mesh: cotangents are scale invariant)
+    v2 = oracle.cotan_values(n, pat.colptr, pat.rowind, np.stack([pos, 3.0 * pos]), tris,
+                             np.ones(n), 0.0, 0.05, 1.5)
+    assert np.array_equal(v2[0], v2[1])
+
+
+# --- sparse products ------------------------------------------------------
+
+def _rand_csr(rng, m, n, per_row):
+    rowptr = [0]
+    cols = []
+    for i in range(m):
+        c = np.sort(rng.choice(n, size=min(per_row, n), replace=False))
+        cols.extend(c.tolist())
+        rowptr.append(len(cols))
+    return (np.array(rowptr, np.int64), np.array(cols, np.int32),
+            rng.uniform(-1, 1, size=len(cols)))
+
+
+def _dense(csr, m, n):
+    r, c, v = csr
+    out = np.zeros((m, n))
+    for i in range(m):
+        for q in range(r[i], r[i + 1]):
+            out[i, c[q]] += v[q]
+    return out
+
+
+@pytest.mark.parametrize("transB", [False, True])
+@pytest.mark.parametrize("with_d", [False, True])
+def test_sparse_product_against_dense(transB, with_d):
+    """Against numpy's dense product (brute force on small matrices), the
+    pattern against a plain loop over the rows."""
+    rng = np.random.default_rng(11 + 2 * transB + with_d)
+    m, p, n = 23, 17, 19
+    A = _rand_csr(rng, m, p, 4)
+    B = _rand_csr(rng, n, p, 5) if transB else _rand_csr(rng, p, n, 5)
+    D = _rand_csr(rng, m, n, 3) if with_d else None
+    C = oracle.sparse_product(m, n, A, B, transB, D)
+    Bd = _dense(B, n, p).T if transB else _dense(B, p, n)
+    ref = _dense(A, m, p) @ Bd + (_dense(D, m, n) if with_d else 0.0)
+    assert np.allclose(C.toarray(), ref, rtol=1e-14, atol=1e-14)
+    rp, ci = oracle.sparse_product_pattern(m, n, A[0], A[1], B[0], B[1], transB,
+                                           D[0] if with_d else None, D[1] if with_d else None)
+    # every structural entry is listed (values may cancel to zero)
+    S = np.zeros((m, n), bool)
+    for i in range(m):
+        S[i, ci[rp[i]:rp[i + 1]]] = True
+    Ad = _dense(A, m, p) != 0
+    Bs = (_dense(B, n, p).T if transB else _dense(B, p, n)) != 0
+    ref_s = (Ad.astype(int) @ Bs.astype(int)) > 0
+    if with_d:
+        ref_s |= _dense(D, m, n) != 0
+    assert np.array_equal(S, ref_s)
+
+
+def test_sparse_power_of_laplacian_annihilates_constants():
+    """K 1 = 0 for the cotangent stiffness (zero row sums), so K^2 1 = K^3 1
+    = 0 up to rounding, and (K M K^T + D) 1 = D 1."""
+    import scipy.sparse as sp
+    k = 12
+    w = W.trimesh_workload(k, batch=1, nrhs=1, seed=13)
+    m = w.extra["mesh"]
+    p = w.pattern
+    v = oracle.cotan_values(p.n, p.colptr, p.rowind, m["pos"], m["tris"], m["mass"], 0.0,
+                            *m["clip"])[0]
+    K = sp.csc_matrix((v, p.rowind, p.colptr), shape=(p.n, p.n))
+    K = (K + sp.tril(K, -1).T).tocsr()
+    Kt = (K.indptr, K.indices, K.data)
+    K2 = oracle.sparse_product(p.n, p.n, Kt, Kt)
+    K3 = oracle.sparse_product(p.n, p.n, (K2.indptr, K2.indices, K2.data), Kt)
+    one = np.ones(p.n)
+    scale = np.abs(K3).sum(1).max()
+    assert np.abs(K2 @ one).max() <= 1e-13 * np.abs(K2).sum(1).max()
+    assert np.abs(K3 @ one).max() <= 1e-13 * scale
+    Mdiag = (np.arange(p.n + 1, dtype=np.int64), np.arange(p.n, dtype=np.int32), m["mass"])
+    T = oracle.sparse_product(p.n, p.n, Kt, Mdiag)
+    rng = np.random.default_rng(5)
+    D = _rand_csr(rng, p.n, p.n, 6)
+    R = oracle.sparse_product(p.n, p.n, (T.indptr, T.indices, T.data), Kt, True, D)
+    assert np.allclose(R @ one, _dense(D, p.n, p.n) @ one, rtol=0, atol=1e-12)

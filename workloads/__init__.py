@@ -34,6 +34,7 @@ __all__ = [
     "laplacian_values",
     "rhs",
     "trimesh_edges_weights",
+    "trimesh_geometry",
     "config",
     "small_grid",
     "random_spd",
@@ -221,17 +222,7 @@ def trimesh_edges_weights(k: int, rng: np.random.Generator):
     Vertex index: i + k*j.
     """
     n = k * k
-    jit = rng.uniform(-0.2, 0.2, size=(n, 2))
-    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
-    pos = np.stack([ii.ravel(), jj.ravel()], 1).astype(np.float64) + jit
-    q = np.arange(k - 1)
-    qi, qj = np.meshgrid(q, q, indexing="xy")
-    v00 = (qi + k * qj).ravel()
-    v10 = v00 + 1
-    v11 = v00 + 1 + k
-    v01 = v00 + k
-    tris = np.concatenate([np.stack([v00, v10, v11], 1),
-                           np.stack([v00, v11, v01], 1)], 0)
+    pos, tris = trimesh_geometry(k, rng)
     ea, eb, cot = [], [], []
     for c in range(3):
         a = tris[:, (c + 1) % 3]
@@ -249,7 +240,26 @@ def trimesh_edges_weights(k: int, rng: np.random.Generator):
     np.add.at(w, inv, 0.5 * cot)
     w = np.clip(w, 0.05, 2.0)
     edges = np.stack([uk // n, uk % n], 1)
-    return n, edges, w
+    return n, edges, w, pos, tris
+
+
+def trimesh_geometry(k: int, rng: np.random.Generator):
+    """Vertex positions [k*k, 2] ((i, j) + U(-0.2, 0.2)^2, vertex i + k*j)
+    and triangles [2 (k-1)^2, 3] of the jittered k x k mesh, every quad
+    split along (i, j)-(i+1, j+1)."""
+    n = k * k
+    jit = rng.uniform(-0.2, 0.2, size=(n, 2))
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="xy")
+    pos = np.stack([ii.ravel(), jj.ravel()], 1).astype(np.float64) + jit
+    q = np.arange(k - 1)
+    qi, qj = np.meshgrid(q, q, indexing="xy")
+    v00 = (qi + k * qj).ravel()
+    v10 = v00 + 1
+    v11 = v00 + 1 + k
+    v01 = v00 + k
+    tris = np.concatenate([np.stack([v00, v10, v11], 1),
+                           np.stack([v00, v11, v01], 1)], 0)
+    return pos, tris
 
 
 def _stiffness_mass_values(pat: SymPattern, edges: np.ndarray, w: np.ndarray,
@@ -339,21 +349,27 @@ def trimesh_workload(k: int, batch: int, nrhs: int, seed: int,
                      mass_coeff: float = 1e-3) -> Workload:
     ss = _streams(seed, 4)
     geo = np.random.Generator(np.random.PCG64(ss[0]))
-    n, edges, w = trimesh_edges_weights(k, geo)
+    n, edges, w, pos, tris = trimesh_edges_weights(k, geo)
     mass = geo.uniform(0.5, 1.5, size=n) / n
     pat = lower_csc_from_edges(n, edges)
     vss = ss[1].spawn(batch)
     rss = ss[2].spawn(batch)
     vals = []
+    scales = np.empty((batch, w.size))
     for s in range(batch):
         r = np.random.Generator(np.random.PCG64(vss[s]))
-        ws = np.clip(w * r.uniform(0.9, 1.1, size=w.size), 0.05, 2.0)
+        scales[s] = r.uniform(0.9, 1.1, size=w.size)
+        ws = np.clip(w * scales[s], 0.05, 2.0)
         vals.append(_stiffness_mass_values(pat, edges, ws, mass, mass_coeff))
     b = np.stack([rhs(n, nrhs, np.random.Generator(np.random.PCG64(s)))
                   for s in rss])
+    # the mesh itself, for assembling the values from the geometry: edge e
+    # is the e-th stored off-diagonal entry (edges sorted by (lo, hi))
+    mesh = {"pos": pos, "tris": tris.astype(np.int32), "mass": mass,
+            "mass_coeff": mass_coeff, "edge_scale": scales, "clip": (0.05, 2.0)}
     return Workload(name="trimesh_%dx%d_nd" % (k, k), pattern=pat,
                     perm=grid_nd_perm((k, k)), values=np.stack(vals), b=b,
-                    seed=seed, extra={"dims": (k, k), "order": "nd"})
+                    seed=seed, extra={"dims": (k, k), "order": "nd", "mesh": mesh})
 
 
 def small_grid(dims, order="nd", batch=1, nrhs=1, seed=7) -> Workload:
