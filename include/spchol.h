@@ -347,7 +347,7 @@ sc_status sc_numeric_profile_read(sc_numeric_t *num, int32_t cap,
 /*
  * Adjoint of the solve (gradients of a loss L(x) through x = A^{-1} b, the
  * closed form of differentiating the solve; the paper differentiates its
- * unrolled expression graph symbolically, Sec. 4.8): with the factor of
+ * unrolled expression graph symbolically, Sec. 4.9): with the factor of
  * the last sc_factor on this numeric object,
  *     lambda = A^{-1} g_x                      -> gb_dev (dL/db)
  *     dL/dv_k = -sum_r (lambda_i x_j + lambda_j x_i)   stored entry (i, j), i > j

@@ -11,7 +11,7 @@
  * Each launch evaluates every entry of C (Sec. 4.3's grouping at the
  * granularity of one wave: 64 consecutive entries share one loop over the
  * longest term list among them), with the position tables interleaved so
- * lane l of a wave reads word l (the coalesced layout of Sec. 4.7).  Chains
+ * lane l of a wave reads word l (the coalesced layout of Sec. 4.8).  Chains
  * are products of products: A^3 = (A^2) A, L M L^T + K = (L diag(M)) L^T +
  * K, the intermediate results stored once and read by every term that uses
  * them (the global decomposition of Sec. 4.2.1).

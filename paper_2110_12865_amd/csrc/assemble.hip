@@ -8,9 +8,10 @@
 // the leaves of every expression into index tables once (Sec. 4.4): per
 // edge its endpoints, its one or two opposite corners and the position of
 // its value; per vertex the position of its diagonal and its incident
-// edges in summation order.  Every arithmetic step is an explicitly rounded
-// intrinsic, so no multiply-add is contracted and the bits do not depend on
-// the compiler.
+// edges in summation order.  Floating-point contraction is switched off for
+// this file (the pragma below), so every product, sum and quotient is
+// rounded on its own and the bits do not depend on the compiler's choice of
+// fused multiply-adds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +24,11 @@
 #include "spchol.h"
 #include "spchol_mesh.h"
 
+// Applies to every expression of the file below; HIP's __dmul_rn and
+// __dadd_rn are plain operators defined in a header outside its reach, so
+// the kernels use the operators directly.
+#pragma clang fp contract(off)
+
 namespace {
 
 struct EdgeDesc {      // one stored off-diagonal entry = one mesh edge
@@ -32,11 +38,11 @@ struct EdgeDesc {      // one stored off-diagonal entry = one mesh edge
 
 __device__ __forceinline__ double cot_at(const double *x, int32_t o, int32_t p, int32_t q) {
     const double ox = x[2 * o], oy = x[2 * o + 1];
-    const double ux = __dsub_rn(x[2 * p], ox), uy = __dsub_rn(x[2 * p + 1], oy);
-    const double vx = __dsub_rn(x[2 * q], ox), vy = __dsub_rn(x[2 * q + 1], oy);
-    const double dot = __dadd_rn(__dmul_rn(ux, vx), __dmul_rn(uy, vy));
-    const double cr = fabs(__dsub_rn(__dmul_rn(ux, vy), __dmul_rn(uy, vx)));
-    return __ddiv_rn(dot, cr);
+    const double ux = x[2 * p] - ox, uy = x[2 * p + 1] - oy;
+    const double vx = x[2 * q] - ox, vy = x[2 * q + 1] - oy;
+    const double dot = ux * vx + uy * vy;
+    const double cr = fabs(ux * vy - uy * vx);
+    return dot / cr;
 }
 
 __device__ __forceinline__ double clip(double w, double lo, double hi) {
@@ -59,11 +65,11 @@ k_cotan_edges(const EdgeDesc *__restrict__ E, const int32_t *__restrict__ eval, 
     for (int32_t s = 0; s < batch; s++) {
         if (s == 0 || pos_stride != 0) {
             const double *x = pos + int64_t(s) * pos_stride;
-            double h = __dmul_rn(0.5, cot_at(x, d.o1, d.p, d.q));
-            if (d.o2 >= 0) h = __dadd_rn(h, __dmul_rn(0.5, cot_at(x, d.o2, d.p, d.q)));
+            double h = 0.5 * cot_at(x, d.o1, d.p, d.q);
+            if (d.o2 >= 0) h = h + 0.5 * cot_at(x, d.o2, d.p, d.q);
             w = clip(h, lo, hi);
         }
-        const double ws = scale ? clip(__dmul_rn(w, scale[int64_t(s) * nedge + e]), lo, hi) : w;
+        const double ws = scale ? clip(w * scale[int64_t(s) * nedge + e], lo, hi) : w;
         vals[int64_t(s) * ldv + k] = -ws;
     }
 }
@@ -78,12 +84,12 @@ k_cotan_diag(const int32_t *__restrict__ vdiag, const int32_t *__restrict__ iptr
     const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= nv) return;
     const int32_t a = iptr[v], b = iptr[v + 1];
-    const double cm = __dmul_rn(coeff, mass[v]);
+    const double cm = coeff * mass[v];
     for (int32_t s = 0; s < batch; s++) {
         const double *row = vals + int64_t(s) * ldv;
         double deg = 0.0;
-        for (int32_t t = a; t < b; t++) deg = __dadd_rn(deg, -row[ival[t]]);
-        vals[int64_t(s) * ldv + vdiag[v]] = __dadd_rn(deg, cm);
+        for (int32_t t = a; t < b; t++) deg = deg - row[ival[t]];
+        vals[int64_t(s) * ldv + vdiag[v]] = deg + cm;
     }
 }
 

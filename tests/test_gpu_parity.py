@@ -435,5 +435,12 @@ def test_padded_entries_exactly_zero(name, make, opts, dtype):
     log("  %d padded entries, all 0.0" % npad)
     assert npad > 0
     if dtype == "f64":
+        # the mesh case is ill-conditioned (kappa_1 ~ 5e7): two correct FP64
+        # factorizations that sum in different orders agree in L only to the
+        # conditioning limit (first-order perturbation of the Cholesky factor,
+        # ||dL|| / ||L|| <~ kappa(A) ||dA|| / ||A||), the same rule as for x
         sym, Lx, _, _ = oracle_run(w)
-        assert oracle.factor_error(sym.Lcolptr, num.get_columns(0, all_columns(p.n)), Lx) <= TOL_L
+        ferr = oracle.factor_error(sym.Lcolptr, num.get_columns(0, all_columns(p.n)), Lx)
+        kap = oracle.kappa1_estimate(p.n, p.colptr, p.rowind, w.values[0], sym, Lx)
+        log("  factor err %.2e (kappa_1 %.2e)" % (ferr, kap))
+        assert oracle.within_conditioning(ferr, TOL_L, kap)
