@@ -47,7 +47,9 @@ typedef enum {
     SC_ENOMEM = -3,   /* host or device allocation failed                   */
     SC_EDEVICE = -4,  /* a HIP runtime call failed                          */
     SC_ENOTSPD = -5,  /* some matrix of the batch has a non-positive pivot  */
-    SC_ENOCONV = -6   /* iterative refinement did not meet its tolerance    */
+    SC_ENOCONV = -6,  /* iterative refinement did not meet its tolerance    */
+    SC_ESCRATCH = -7  /* sc_solve_noalloc: the solve needs more workspace
+                         than the static scratch holds                      */
 } sc_status;
 
 typedef enum { SC_F64 = 0, SC_F32 = 1 } sc_dtype;
@@ -240,6 +242,30 @@ sc_status sc_factor_info(const sc_numeric_t *num, int32_t *info_host,
  */
 sc_status sc_solve(const sc_plan_t *plan, sc_numeric_t *num, double *b_dev,
                    int32_t nrhs, int64_t ldb, void *stream);
+
+/*
+ * sc_solve without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit for bit) as
+ * sc_solve on the same numeric object, but the solve vectors live in a
+ * static device array of SC_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every GPU it runs on until the process ends, instead of the
+ * numeric object's workspaces; the call makes no hipMalloc or hipFree and
+ * calls no allocating routine.  The numeric object must come from
+ * sc_numeric_create on the current device (which sets the device up).
+ * Workspace need: 8 bytes x (matrices, rounded up to 64 in the
+ * batch-interleaved layout) x nrhs x (n + the plan's front rows + the
+ * panel partial sums), each of four vectors rounded up to 256 bytes.
+ * Every call on one GPU shares that GPU's array, and the array keeps the
+ * last call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one GPU (other streams, other threads, other numeric objects)
+ * race, so the caller orders them.  Asynchronous on `stream`.
+ * Errors: SC_EINVAL, SC_ESCRATCH (the workspace would exceed the array;
+ * nothing is launched), SC_EDEVICE.
+ */
+#define SC_NOALLOC_SCRATCH_BYTES (32u << 20)
+sc_status sc_solve_noalloc(const sc_plan_t *plan, sc_numeric_t *num, double *b_dev,
+                           int32_t nrhs, int64_t ldb, void *stream);
 
 /* Outcome of sc_refine_solve for one system: one (matrix, right-hand side,
    block) with block = the pattern of a group plan. */

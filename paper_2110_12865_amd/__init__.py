@@ -26,8 +26,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspchol.so")
 
-SC_OK, SC_EINVAL, SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD, SC_ENOCONV = \
-    0, -1, -2, -3, -4, -5, -6
+SC_OK, SC_EINVAL, SC_EPATTERN, SC_ENOMEM, SC_EDEVICE, SC_ENOTSPD, SC_ENOCONV, SC_ESCRATCH = \
+    0, -1, -2, -3, -4, -5, -6, -7
+SC_NOALLOC_SCRATCH_BYTES = 32 << 20
 SC_F64, SC_F32 = 0, 1
 SC_REFINE_CLASSICAL, SC_REFINE_PCG = 0, 1
 SC_ORDER_NATURAL, SC_ORDER_GIVEN, SC_ORDER_ND = 0, 1, 2
@@ -40,7 +41,7 @@ EXPORTS = [
     "sc_status_string", "sc_options_default", "sc_analyze", "sc_analyze_group",
     "sc_plan_info", "sc_plan_export_blocks", "sc_plan_export_symbolic",
     "sc_plan_export_supernodes", "sc_plan_destroy", "sc_numeric_create", "sc_numeric_destroy",
-    "sc_factor", "sc_factor_info", "sc_solve", "sc_refine_solve",
+    "sc_factor", "sc_factor_info", "sc_solve", "sc_solve_noalloc", "sc_refine_solve",
     "sc_numeric_get_columns", "sc_numeric_get_block", "sc_numeric_profile",
     "sc_numeric_profile_read",
     "sc_step_graph_create", "sc_step_graph_launch", "sc_step_graph_stats", "sc_step_graph_destroy",
@@ -112,6 +113,7 @@ def _load():
         "sc_factor": ([P, P, P, I64, P], ctypes.c_int),
         "sc_factor_info": ([P, P, P], ctypes.c_int),
         "sc_solve": ([P, P, P, I32, I64, P], ctypes.c_int),
+        "sc_solve_noalloc": ([P, P, P, I32, I64, P], ctypes.c_int),
         "sc_refine_solve": ([P, P, P, I64, P, P, I32, I64, ctypes.c_double, I32, I32, P, P],
                             ctypes.c_int),
         "sc_numeric_get_columns": ([P, P, I32, I64, P, P], ctypes.c_int),
@@ -388,6 +390,17 @@ class Numeric:
             raise ValueError("b must be [batch, nrhs, n]")
         _check(_lib.sc_solve(self.plan._h, self._h, _dev_ptr(b, "float64"), int(b.shape[1]),
                              int(b.shape[2]), _stream_handle(stream)), "sc_solve")
+        return b
+
+    def solve_noalloc(self, b, stream=None):
+        """As solve(), through sc_solve_noalloc: no device allocation, the
+        solve vectors in the library's static scratch (SC_ESCRATCH when they
+        do not fit)."""
+        if b.dim() != 3 or b.shape[0] != self.batch:
+            raise ValueError("b must be [batch, nrhs, n]")
+        _check(_lib.sc_solve_noalloc(self.plan._h, self._h, _dev_ptr(b, "float64"),
+                                     int(b.shape[1]), int(b.shape[2]), _stream_handle(stream)),
+               "sc_solve_noalloc")
         return b
 
     def refine_solve(self, values, b, x, tol: float = 1e-10, maxit: int = 10,

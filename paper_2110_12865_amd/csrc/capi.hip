@@ -23,10 +23,20 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
 hipError_t spchol_solve_init();
 bool spchol_nd_order(int64_t n, const int64_t *colptr, const int32_t *rowind, int32_t *perm_out);
 
+// Static scratch of the no-allocation solve (sc_solve_noalloc): its solve
+// vectors live in this file-scope device array instead of the numeric
+// object's workspaces.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code `scratch` only names the host-side
+// shadow of the symbol; host code reaches the array exclusively through the
+// address hipGetSymbolAddress returns for the current device, kept per
+// device in g_scratch_dev at the device's set-up (ensure_device).
+static __device__ __align__(256) unsigned char scratch[SC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 std::mutex g_upload_mutex;
 bool g_kernels_ready[64] = {};
+void *g_scratch_dev[64] = {};  // device address of `scratch` on each device
 
 template <typename V>
 hipError_t upload(V **dst, const std::vector<V> &src) {
@@ -58,6 +68,9 @@ sc_status ensure_device(const sc_plan *P) {
     if (dev >= 0 && dev < 64 && !g_kernels_ready[dev]) {
         if (spchol_kernels_init() != hipSuccess) return SC_EDEVICE;
         if (spchol_solve_init() != hipSuccess) return SC_EDEVICE;
+        void *sp = nullptr;
+        if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return SC_EDEVICE;
+        g_scratch_dev[dev] = sp;
         g_kernels_ready[dev] = true;
     }
     if (P->dev) return P->dev_id == dev ? SC_OK : SC_EINVAL;
@@ -229,6 +242,7 @@ const char *sc_status_string(sc_status s) {
     case SC_EDEVICE: return "HIP runtime error";
     case SC_ENOTSPD: return "matrix not positive definite";
     case SC_ENOCONV: return "refinement did not converge";
+    case SC_ESCRATCH: return "workspace exceeds the no-allocation scratch (SC_NOALLOC_SCRATCH_BYTES)";
     }
     return "unknown status";
 }
@@ -492,6 +506,38 @@ sc_status sc_solve(const sc_plan_t *P, sc_numeric_t *N, double *b_dev, int32_t n
     if (ws != SC_OK) return ws;
     return map_err(
         spchol_solve_run(P, N, b_dev, nrhs, ldb, static_cast<hipStream_t>(stream), nullptr));
+}
+
+sc_status sc_solve_noalloc(const sc_plan_t *P, sc_numeric_t *N, double *b_dev, int32_t nrhs,
+                           int64_t ldb, void *stream) {
+    if (!P || !N || N->plan != P || !b_dev || nrhs < 1 || ldb < P->n) return SC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SC_EDEVICE;
+    if (dev != N->device || dev < 0 || dev >= 64) return SC_EINVAL;
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_upload_mutex);
+        base = g_scratch_dev[dev];
+    }
+    if (!base) return SC_EDEVICE;  // the device was never set up by sc_numeric_create
+    // the four solve vectors of sc_solve, each at a 256-byte boundary
+    size_t words[4];
+    solve_ws_words(P, N, nrhs, words);
+    SolveWs W;
+    double **dst[4] = {&W.y, &W.u, &W.part, &W.ps};
+    size_t off = 0;
+    for (int k = 0; k < 4; k++) {
+        if (words[k] > (SIZE_MAX >> 4)) return SC_ESCRATCH;
+        *dst[k] = reinterpret_cast<double *>(static_cast<unsigned char *>(base) + off);
+        off += (std::max<size_t>(words[k] * sizeof(double), 8) + 255) & ~size_t(255);
+        if (off > size_t(SC_NOALLOC_SCRATCH_BYTES)) return SC_ESCRATCH;
+    }
+    W.nrhs = nrhs;
+    N->wsc = &W;
+    const hipError_t e =
+        spchol_solve_run(P, N, b_dev, nrhs, ldb, static_cast<hipStream_t>(stream), nullptr);
+    N->wsc = &N->ws;
+    return map_err(e);
 }
 
 sc_status sc_refine_solve(const sc_plan_t *P, sc_numeric_t *N, const double *values_dev,
