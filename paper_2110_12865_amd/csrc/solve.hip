@@ -37,6 +37,63 @@ __device__ __forceinline__ V ldz(const V *p, int64_t idx, bool ok) {
     return ok ? v : V(0);
 }
 
+// A supernode's block of the interleaved L, read through a buffer resource:
+// the block's address sits in a wave-uniform descriptor and a record's
+// byte offset in a scalar register, the lane's slot is a constant vector
+// offset, so a load needs no vector address arithmetic.  Offsets are
+// 32-bit; a block of the interleaved layout (at most 512 x 64 entries x
+// 64 lanes) is far below that.
+constexpr int kBufWord3 = 0x00020000;  // raw buffer, gfx9-family data format
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename V>
+struct SoaBlk {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned voff;
+    __device__ __forceinline__ SoaBlk(const V *base, unsigned lane)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<V *>(base), 0, 0x7fffffff, kBufWord3)),
+          voff(lane * unsigned(sizeof(V))) {}
+    // entry k, or entry 0 when !ok (no select; see Soa::ldc)
+    __device__ __forceinline__ V ldc(int64_t k, bool ok) const {
+        const unsigned so = ok ? unsigned(k) * unsigned(64 * sizeof(V)) : 0u;
+        if constexpr (sizeof(V) == 4)
+            return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, voff, so, 0));
+        else
+            return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, so, 0));
+    }
+    __device__ __forceinline__ V ldz(int64_t k, bool ok) const {
+        const V v = ldc(k, ok);
+        return ok ? v : V(0);
+    }
+    __device__ __forceinline__ void st(int64_t k, V v) const {
+        const unsigned so = unsigned(k) * unsigned(64 * sizeof(V));
+        if constexpr (sizeof(V) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, so, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, so, 0);
+    }
+};
+
+// One group of an interleaved array: record k (64 scalars) holds entry k of
+// 64 matrices, lane = matrix.  A lane's entry is reached from the record's
+// wave-uniform address plus the lane's 32-bit byte offset, so an access
+// takes a scalar base and no per-access vector address arithmetic.
+template <typename V>
+struct Soa {
+    V *rec;         // wave-uniform: record 0 of the group
+    unsigned lane;  // 0 .. 63
+    __device__ __forceinline__ V &operator[](int64_t k) const { return (rec + k * 64)[lane]; }
+    // entry k, or 0 when !ok (the load goes to record 0)
+    __device__ __forceinline__ V ldz(int64_t k, bool ok) const {
+        const V v = (rec + (ok ? k : 0) * 64)[lane];
+        return ok ? v : V(0);
+    }
+    // entry k, or entry 0 when !ok (no select): for operands whose product
+    // partner is exactly 0 or whose results are discarded when !ok
+    __device__ __forceinline__ V ldc(int64_t k, bool ok) const {
+        return (rec + (ok ? k : 0) * 64)[lane];
+    }
+};
+
 // Inverse of every 64x64 diagonal block of the panel-solved supernodes that
 // were factored as small fronts (the tiled factor writes the others):
 // X = L_pp^{-1} by forward substitution, one lane per column of X kept in
@@ -1118,11 +1175,13 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
     const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
     int64_t n, int64_t fvsize, int nrhs, int r0) {
     const SnDesc d = sn[list[blockIdx.x]];
-    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int bg = blockIdx.y;
+    const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
-    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    T *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
+    const SoaBlk<T> Lb(Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane);
+    // the supernode's own rows of y and its rows of the front vectors
+    const SoaBlk<T> yb(Ys + ((int64_t(bg) * n + d.first) * nrhs + r0) * 64, lane);
+    const SoaBlk<T> fb(FV + ((int64_t(bg) * fvsize + d.rowptr) * nrhs + r0) * 64, lane);
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
         T v[JW][NR];
@@ -1131,7 +1190,7 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
             const int i = j0 + jj;
 #pragma unroll
             for (int r = 0; r < NR; r++)
-                v[jj][r] = ldz(fb, (int64_t(d.rowptr + i) * nrhs + r) * 64, jj < jn);
+                v[jj][r] = fb.ldz(int64_t(i) * nrhs + r, jj < jn);
         }
 #pragma unroll
         for (int jj = 0; jj < JW; jj++) {
@@ -1139,7 +1198,7 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
             const bool ok = jj < jn;
             T lrow[JW];  // row i of the chunk's triangle, diagonal included
 #pragma unroll
-            for (int kk = 0; kk <= jj; kk++) lrow[kk] = ldz(Lb, (int64_t(j0 + kk) * c + i) * 64, ok);
+            for (int kk = 0; kk <= jj; kk++) lrow[kk] = Lb.ldz(int64_t(j0 + kk) * c + i, ok);
 #pragma unroll
             for (int kk = 0; kk < jj; kk++)
 #pragma unroll
@@ -1148,11 +1207,12 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 v[jj][r] *= rinv;
-                if (ok) yb[(int64_t(d.first + i) * nrhs + r) * 64] = v[jj][r];
+                if (ok) yb.st(int64_t(i) * nrhs + r, v[jj][r]);
             }
         }
         // rows of the diagonal block below this chunk, RU at a time with
-        // every load of the group issued first
+        // every load of the group issued first (v is 0 past jn, so those
+        // entries of L are clamped loads without a select)
         constexpr int RU = SoaRows<T>::value;
         for (int i0 = j0 + JW; i0 < w; i0 += RU) {
             T a[RU][NR];
@@ -1162,10 +1222,10 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
                 const int i = i0 + u;
 #pragma unroll
                 for (int r = 0; r < NR; r++)
-                    a[u][r] = ldz(fb, (int64_t(d.rowptr + i) * nrhs + r) * 64, i < w);
+                    a[u][r] = fb.ldc(int64_t(i) * nrhs + r, i < w);
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
-                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, i < w && jj < jn);
+                    l[u][jj] = Lb.ldc(int64_t(j0 + jj) * c + i, i < w && jj < jn);
             }
 #pragma unroll
             for (int u = 0; u < RU; u++)
@@ -1177,8 +1237,7 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
             for (int u = 0; u < RU; u++)
                 if (i0 + u < w)
 #pragma unroll
-                    for (int r = 0; r < NR; r++)
-                        fb[(int64_t(d.rowptr + i0 + u) * nrhs + r) * 64] = a[u][r];
+                    for (int r = 0; r < NR; r++) fb.st(int64_t(i0 + u) * nrhs + r, a[u][r]);
         }
     }
 }
@@ -1209,13 +1268,17 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
     int r0) {
     const SnDesc d = sn[it_s[blockIdx.x]];
     const int rb = it_r0[blockIdx.x];
-    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int bg = blockIdx.y;
+    const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int re = min(c, rb + kSoaRows);
     constexpr int RU = SoaRows<T>::value;
-    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    const T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    T *fb = FV + (int64_t(bg) * fvsize * nrhs + r0) * 64 + lane;
+    // global loads here (not buffer loads): with the pointers' no-alias
+    // guarantee the next rows' loads of L may be issued before this group's
+    // stores to the front vector
+    const Soa<const T> Lb{Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane};
+    const Soa<const T> yb{Ys + ((int64_t(bg) * n + d.first) * nrhs + r0) * 64, lane};
+    const Soa<T> fb{FV + ((int64_t(bg) * fvsize + d.rowptr) * nrhs + r0) * 64, lane};
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
         T y[JW][NR];
@@ -1223,8 +1286,10 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
         for (int jj = 0; jj < JW; jj++)
 #pragma unroll
             for (int r = 0; r < NR; r++)
-                y[jj][r] = ldz(yb, (int64_t(d.first + j0 + jj) * nrhs + r) * 64, jj < jn);
+                y[jj][r] = yb.ldz(int64_t(j0 + jj) * nrhs + r, jj < jn);
         // RU rows at a time, every load of the group issued before any use
+        // (y is 0 past jn and rows past re are not stored, so the loads of
+        // L and of the front vector are clamped loads without a select)
         for (int i0 = rb; i0 < re; i0 += RU) {
             T a[RU][NR];
             T l[RU][JW];
@@ -1233,10 +1298,10 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
                 const int i = i0 + u;
 #pragma unroll
                 for (int r = 0; r < NR; r++)
-                    a[u][r] = ldz(fb, (int64_t(d.rowptr + i) * nrhs + r) * 64, i < re);
+                    a[u][r] = fb.ldc(int64_t(i) * nrhs + r, i < re);
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
-                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, i < re && jj < jn);
+                    l[u][jj] = Lb.ldc(int64_t(j0 + jj) * c + i, i < re && jj < jn);
             }
 #pragma unroll
             for (int u = 0; u < RU; u++)
@@ -1248,8 +1313,7 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
             for (int u = 0; u < RU; u++)
                 if (i0 + u < re)
 #pragma unroll
-                    for (int r = 0; r < NR; r++)
-                        fb[(int64_t(d.rowptr + i0 + u) * nrhs + r) * 64] = a[u][r];
+                    for (int r = 0; r < NR; r++) fb[int64_t(i0 + u) * nrhs + r] = a[u][r];
         }
     }
 }
@@ -1281,17 +1345,18 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
     T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
     const SnDesc d = sn[it_s[blockIdx.x]];
     const int rb = it_r0[blockIdx.x];
-    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int bg = blockIdx.y;
+    const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int re = min(c, rb + kSoaRows);
     const int kblk = (rb - w) / kSoaRows;
     constexpr int RU = SoaRows<T>::value;
     const int32_t *R = rows + d.rowptr;
     // the block's row indices, one per lane, broadcast with readlane below
-    const int rmine = rb + lane < re ? R[rb + lane] : 0;
-    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    const T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    T *pb = PS + ((int64_t(bg) * psize + d.part + int64_t(kblk) * w) * nrhs + r0) * 64 + lane;
+    const int rmine = rb + int(lane) < re ? R[rb + lane] : 0;
+    const SoaBlk<T> Lb(Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane);
+    const Soa<const T> yb{Ys + (int64_t(bg) * n * nrhs + r0) * 64, lane};
+    const SoaBlk<T> pb(PS + ((int64_t(bg) * psize + d.part + int64_t(kblk) * w) * nrhs + r0) * 64, lane);
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
         T acc[JW][NR];
@@ -1299,6 +1364,8 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
         for (int jj = 0; jj < JW; jj++)
 #pragma unroll
             for (int r = 0; r < NR; r++) acc[jj][r] = T(0);
+        // x is 0 past re and the sums of columns past jn are not stored, so
+        // the loads of L are clamped loads without a select
         for (int i0 = rb; i0 < re; i0 += RU) {
             T x[RU][NR];
             T l[RU][JW];
@@ -1306,12 +1373,11 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
             for (int u = 0; u < RU; u++) {
                 const int i = i0 + u;
                 const int ri = i < re ? __builtin_amdgcn_readlane(rmine, i - rb) : 0;
-                const T *xi = yb + int64_t(ri) * nrhs * 64;
 #pragma unroll
-                for (int r = 0; r < NR; r++) x[u][r] = ldz(xi, r * 64, i < re);
+                for (int r = 0; r < NR; r++) x[u][r] = yb.ldz(int64_t(ri) * nrhs + r, i < re);
 #pragma unroll
                 for (int jj = 0; jj < JW; jj++)
-                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, i < re && jj < jn);
+                    l[u][jj] = Lb.ldc(int64_t(j0 + jj) * c + i, i < re && jj < jn);
             }
 #pragma unroll
             for (int u = 0; u < RU; u++)
@@ -1324,7 +1390,7 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
         for (int jj = 0; jj < JW; jj++)
             if (jj < jn)
 #pragma unroll
-                for (int r = 0; r < NR; r++) pb[(int64_t(j0 + jj) * nrhs + r) * 64] = acc[jj][r];
+                for (int r = 0; r < NR; r++) pb.st(int64_t(j0 + jj) * nrhs + r, acc[jj][r]);
     }
 }
 
@@ -1354,12 +1420,13 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
     const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
     const T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
     const SnDesc d = sn[list[blockIdx.x]];
-    const int bg = blockIdx.y, lane = threadIdx.x;
+    const int bg = blockIdx.y;
+    const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int nblk = (c - w + kSoaRows - 1) / kSoaRows;
-    const T *Lb = Ls + (int64_t(bg) * Lsize + d.loff) * 64 + lane;
-    T *yb = Ys + (int64_t(bg) * n * nrhs + r0) * 64 + lane;
-    const T *pb = PS + ((int64_t(bg) * psize + d.part) * nrhs + r0) * 64 + lane;
+    const SoaBlk<T> Lb(Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane);
+    const SoaBlk<T> yb(Ys + ((int64_t(bg) * n + d.first) * nrhs + r0) * 64, lane);
+    const SoaBlk<T> pb(PS + ((int64_t(bg) * psize + d.part) * nrhs + r0) * 64, lane);
     constexpr int RU = SoaRows<T>::value;
     for (int j0 = ((w - 1) / JW) * JW; j0 >= 0; j0 -= JW) {
         const int jn = min(JW, w - j0);
@@ -1368,14 +1435,14 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
         for (int jj = 0; jj < JW; jj++)
 #pragma unroll
             for (int r = 0; r < NR; r++)
-                acc[jj][r] = ldz(yb, (int64_t(d.first + j0 + jj) * nrhs + r) * 64, jj < jn);
+                acc[jj][r] = yb.ldz(int64_t(j0 + jj) * nrhs + r, jj < jn);
         for (int k = 0; k < nblk; k++) {  // row-block partial sums, in block order
             T p[JW][NR];
 #pragma unroll
             for (int jj = 0; jj < JW; jj++)
 #pragma unroll
                 for (int r = 0; r < NR; r++)
-                    p[jj][r] = ldz(pb, ((int64_t(k) * w + j0 + jj) * nrhs + r) * 64, jj < jn);
+                    p[jj][r] = pb.ldz((int64_t(k) * w + j0 + jj) * nrhs + r, jj < jn);
 #pragma unroll
             for (int jj = 0; jj < JW; jj++)
 #pragma unroll
@@ -1391,10 +1458,10 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
                 const int i = i1 - u;
                 const bool ok = i >= j0 + JW;
 #pragma unroll
-                for (int r = 0; r < NR; r++) x[u][r] = ldz(yb, (int64_t(d.first + i) * nrhs + r) * 64, ok);
+                for (int r = 0; r < NR; r++) x[u][r] = yb.ldz(int64_t(i) * nrhs + r, ok);
 #pragma unroll
-                for (int jj = 0; jj < JW; jj++)
-                    l[u][jj] = ldz(Lb, (int64_t(j0 + jj) * c + i) * 64, ok && jj < jn);
+                for (int jj = 0; jj < JW; jj++)  // x is 0 when !ok; columns past jn unused
+                    l[u][jj] = Lb.ldc(int64_t(j0 + jj) * c + i, ok && jj < jn);
             }
 #pragma unroll
             for (int u = 0; u < RU; u++)
@@ -1409,12 +1476,12 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
             const bool ok = jj < jn;
             T lrow[JW];  // row j of the chunk's triangle, diagonal included
 #pragma unroll
-            for (int kk = 0; kk <= jj; kk++) lrow[kk] = ldz(Lb, (int64_t(j0 + kk) * c + j) * 64, ok);
+            for (int kk = 0; kk <= jj; kk++) lrow[kk] = Lb.ldz(int64_t(j0 + kk) * c + j, ok);
             const T rinv = ok ? T(1) / T(lrow[jj]) : T(0);
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 acc[jj][r] *= rinv;
-                if (ok) yb[(int64_t(d.first + j) * nrhs + r) * 64] = acc[jj][r];
+                if (ok) yb.st(int64_t(j) * nrhs + r, acc[jj][r]);
             }
 #pragma unroll
             for (int kk = 0; kk < jj; kk++)
