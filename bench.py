@@ -300,13 +300,25 @@ HIP_KERNEL = {
 MFMA_FAMILIES = {"syrk_mfma", "trsm"}
 
 
-def source_digest():
-    """sha256 of the library sources: HBM counters taken on other sources
-    are stale."""
+# sources that define each kernel family (HBM counters taken on other
+# versions of them are stale)
+FAMILY_SOURCES = {
+    "factor": ("factor.hip", "device.hpp", "plan.hpp"),
+    "solve": ("solve.hip", "device.hpp", "plan.hpp"),
+    "refine": ("refine.hip", "device.hpp", "plan.hpp"),
+}
+FACTOR_FAMILIES = {"front_small", "assemble", "potrf", "trsm", "syrk_mfma"}
+REFINE_FAMILIES = {"spmv_residual", "refine_vector"}
+
+
+def source_digest(kind):
+    """sha256 of the library sources that define kernel family `kind`."""
     import hashlib
+    group = ("factor" if kind in FACTOR_FAMILIES else
+             "refine" if kind in REFINE_FAMILIES else "solve")
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2110_12865_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in FAMILY_SOURCES[group]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -316,14 +328,14 @@ def measured_traffic(workload, kind):
     """HBM bytes per launch of `kind` from the committed counter summary
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of known
     size), or None when there is none for this workload and kernel or the
-    sources changed since it was taken."""
+    sources of that kernel family changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     e = t.get(workload, {})
-    if e.get("kernel") != kind or e.get("source_sha256") != source_digest():
+    if e.get("kernel") != kind or e.get("source_sha256") != source_digest(kind):
         return None
     return e.get("bytes_per_launch")
 
@@ -501,8 +513,14 @@ def run_workload(name, args, headline):
     p = w.pattern
     log("workload %s n=%d nnzA=%d batch=%d nrhs=%d" % (wname, n, nnz, w.batch, w.nrhs))
     opts = {} if args.soa_min_batch is None else {"soa_min_batch": args.soa_min_batch}
+    # options given for the workload named by --workload: no tuning
+    fixed = args.options is not None and headline
+    if fixed:
+        opts.update(args.options)
     tuned = None
-    if members is not None and not args.no_tune and args.soa_min_batch is None:
+    if fixed:
+        tuned = {"options": dict(opts), "seconds": 0.0, "candidates": [], "given": True}
+    if members is not None and not args.no_tune and args.soa_min_batch is None and not fixed:
         # the uneven batch: the group autotuner on the group plan
         import torch
         tt = time.perf_counter()
@@ -519,7 +537,7 @@ def run_workload(name, args, headline):
                                  for k in ("small_front", "relax_cols", "soa_min_batch",
                                            "factor_ms", "solve_ms", "score")} for r in table]}
         log("group autotune %.1f s: %s" % (tuned["seconds"], opts))
-    if headline and members is None and not args.no_tune and args.soa_min_batch is None:
+    if headline and members is None and not args.no_tune and args.soa_min_batch is None and not fixed:
         # one-time tuning of thresholds, amalgamation and solve layout on this
         # workload (like the analysis, outside the timed steps)
         import torch
@@ -802,6 +820,17 @@ def compact(r):
     return out
 
 
+def _parse_options(text):
+    out = {}
+    for item in text.split(","):
+        k, v = item.split("=")
+        k = k.strip()
+        if k not in ("small_front", "relax_cols", "soa_min_batch", "soa_seg_max", "relax"):
+            raise argparse.ArgumentTypeError("unknown option %r" % k)
+        out[k] = int(v)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -817,6 +846,11 @@ def main():
                          "the HBM byte counters) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="library default options instead of the autotuner's choice")
+    ap.add_argument("--options", type=_parse_options, default=None,
+                    help="fixed plan options instead of the autotuner's choice, e.g. "
+                         "small_front=128,relax_cols=16,soa_min_batch=1 (the autotuner's "
+                         "choice on the default workload; used by the profiling commands so "
+                         "that a profile holds no tuning candidates)")
     ap.add_argument("--soa-min-batch", type=int, default=None,
                     help="batch size from which solves use the batch-interleaved layout "
                          "(library default when omitted, negative: never)")
