@@ -83,6 +83,12 @@ typedef struct {
                              where one lane per matrix leaves the chip
                              idle); 0 = library default (96), a negative
                              value never */
+    int32_t soa_subtree_min; /* in the batch-interleaved layout, the lowest
+                             levels are solved as whole subtrees, one wave
+                             per (subtree, group of 64 matrices), up to the
+                             highest level that still has at least this
+                             many such waves; 0 = library default (4096),
+                             a negative value never (level by level)     */
     int32_t ordering;      /* elimination order: SC_ORDER_NATURAL, or
                              SC_ORDER_GIVEN (default: the caller's perm,
                              natural when perm is NULL), or SC_ORDER_ND

@@ -20,6 +20,7 @@ const char *const kKernelNames[KK_Count] = {
 
 void spchol_build_factor_schedule(const sc_plan *P, DevPlan *D);
 void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D);
+hipError_t spchol_build_subtrees(const sc_plan *P, DevPlan *D);
 hipError_t spchol_solve_init();
 bool spchol_nd_order(int64_t n, const int64_t *colptr, const int32_t *rowind, int32_t *perm_out);
 
@@ -56,6 +57,10 @@ void free_devplan(DevPlan *D) {
                     D->gidx, D->dinv_list, D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
                     D->val_row, D->val_col};
     for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int32_t *p : D->fz_ptr)
+        if (p) (void)hipFree(p);
+    for (int32_t *p : D->fz_sn)
         if (p) (void)hipFree(p);
     delete D;
 }
@@ -115,6 +120,10 @@ sc_status ensure_device(const sc_plan *P) {
     }
     spchol_build_factor_schedule(P, D);
     spchol_build_solve_schedule(P, D);
+    if (spchol_build_subtrees(P, D) != hipSuccess) {
+        free_devplan(D);
+        return SC_ENOMEM;
+    }
     P->dev = D;
     P->dev_id = dev;
     return SC_OK;
@@ -255,6 +264,7 @@ sc_status sc_options_default(sc_options *opt) {
     opt->small_front = 64;
     opt->soa_min_batch = kSoaMinBatch;
     opt->soa_seg_max = kSoaSegMax;
+    opt->soa_subtree_min = kSoaSubtreeMin;
     opt->ordering = SC_ORDER_GIVEN;
     return SC_OK;
 }

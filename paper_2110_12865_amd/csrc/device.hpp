@@ -113,6 +113,13 @@ struct DevPlan {
     int64_t *blk_col0 = nullptr;      // nblk + 1 block column offsets
     std::vector<FLaunch> fsched;
     std::vector<SLaunch> ssched;
+    // bottom subtrees of the batch-interleaved solve, for each level K that
+    // may close them (every level up to K without panel-solved supernodes):
+    // fz_ptr[K][t] .. fz_ptr[K][t + 1] index fz_sn[K], the postorder of the
+    // subtree of root t (a supernode of level <= K whose parent lies above
+    // K); fz_roots[K] roots (device arrays, one pair per K)
+    std::vector<int32_t *> fz_ptr, fz_sn;
+    std::vector<int32_t> fz_roots;
 };
 
 // Kernel kinds for per-launch timing.

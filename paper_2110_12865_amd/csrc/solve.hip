@@ -1170,12 +1170,8 @@ template <typename T> struct SoaRows { static constexpr int value = sizeof(T) ==
 // later rows of the diagonal block (i < w) updated in FV.
 template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_fwd_soa_diag_body(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
-    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
-    int64_t n, int64_t fvsize, int nrhs, int r0) {
-    const SnDesc d = sn[list[blockIdx.x]];
-    const int bg = blockIdx.y;
+    const SnDesc &d, int bg, const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
+    T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs, int r0) {
     const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const SoaBlk<T> Lb(Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane);
@@ -1242,18 +1238,25 @@ __device__ __forceinline__ void k_fwd_soa_diag_body(
     }
 }
 
+// column-chunk width by the supernode's width (uniform per wave), so
+// narrow supernodes issue no masked loads for absent columns
+template <typename T, int NR>
+__device__ __forceinline__ void fwd_soa_diag(const SnDesc &d, int bg, const T *__restrict__ Ls,
+                                             int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
+                                             int64_t n, int64_t fvsize, int nrhs, int r0) {
+    if (d.w <= 4) k_fwd_soa_diag_body<T, NR, 4>(d, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else if (d.w <= 8) k_fwd_soa_diag_body<T, NR, 8>(d, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else k_fwd_soa_diag_body<T, NR, 16>(d, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+}
+
 template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_fwd_soa_diag(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
     const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
     int64_t n, int64_t fvsize, int nrhs, int r0) {
-    // column-chunk width by the supernode's width (uniform per wave), so
-    // narrow supernodes issue no masked loads for absent columns
-    const int w = sn[list[blockIdx.x]].w;
-    if (w <= 4) k_fwd_soa_diag_body<T, NR, 4>(sn, list, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
-    else if (w <= 8) k_fwd_soa_diag_body<T, NR, 8>(sn, list, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
-    else k_fwd_soa_diag_body<T, NR, 16>(sn, list, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    const SnDesc d = sn[list[blockIdx.x]];
+    fwd_soa_diag<T, NR>(d, int(blockIdx.y), Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
 }
 
 // Forward, rows below the diagonal blocks: one wave per (row block of
@@ -1261,14 +1264,9 @@ __global__ __launch_bounds__(64) void k_fwd_soa_diag(
 // columns in chunks of 16 (ascending j), stored in FV as the update vector.
 template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_fwd_soa_rows_body(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
-    const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
-    const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
+    const SnDesc &d, int rb, int bg, const T *__restrict__ Ls, int64_t Lsize,
     T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     int r0) {
-    const SnDesc d = sn[it_s[blockIdx.x]];
-    const int rb = it_r0[blockIdx.x];
-    const int bg = blockIdx.y;
     const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int re = min(c, rb + kSoaRows);
@@ -1319,18 +1317,23 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
 }
 
 template <typename T, int NR>
+__device__ __forceinline__ void fwd_soa_rows(const SnDesc &d, int rb, int bg, const T *__restrict__ Ls,
+                                             int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV,
+                                             int64_t n, int64_t fvsize, int nrhs, int r0) {
+    if (d.w <= 4) k_fwd_soa_rows_body<T, NR, 4>(d, rb, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else if (d.w <= 8) k_fwd_soa_rows_body<T, NR, 8>(d, rb, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    else k_fwd_soa_rows_body<T, NR, 16>(d, rb, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+}
+
+template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_fwd_soa_rows(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ gptr,
     const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
     T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
     int r0) {
-    // column-chunk width by the supernode's width (uniform per wave), so
-    // narrow supernodes issue no masked loads for absent columns
-    const int w = sn[it_s[blockIdx.x]].w;
-    if (w <= 4) k_fwd_soa_rows_body<T, NR, 4>(sn, it_s, it_r0, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
-    else if (w <= 8) k_fwd_soa_rows_body<T, NR, 8>(sn, it_s, it_r0, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
-    else k_fwd_soa_rows_body<T, NR, 16>(sn, it_s, it_r0, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    const SnDesc d = sn[it_s[blockIdx.x]];
+    fwd_soa_rows<T, NR>(d, it_r0[blockIdx.x], int(blockIdx.y), Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
 }
 
 // Backward, rows below the diagonal blocks: one wave per (row block,
@@ -1339,13 +1342,9 @@ __global__ __launch_bounds__(64) void k_fwd_soa_rows(
 // part + (block index) w + j.
 template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_bwd_soa_rows_body(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
-    const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
+    const SnDesc &d, int rb, int bg, const int32_t *__restrict__ rows,
     const T *__restrict__ Ls, int64_t Lsize, const T *__restrict__ Ys,
     T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
-    const SnDesc d = sn[it_s[blockIdx.x]];
-    const int rb = it_r0[blockIdx.x];
-    const int bg = blockIdx.y;
     const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int re = min(c, rb + kSoaRows);
@@ -1395,17 +1394,24 @@ __device__ __forceinline__ void k_bwd_soa_rows_body(
 }
 
 template <typename T, int NR>
+__device__ __forceinline__ void bwd_soa_rows(const SnDesc &d, int rb, int bg,
+                                             const int32_t *__restrict__ rows,
+                                             const T *__restrict__ Ls, int64_t Lsize,
+                                             const T *__restrict__ Ys, T *__restrict__ PS,
+                                             int64_t psize, int64_t n, int nrhs, int r0) {
+    if (d.w <= 4) k_bwd_soa_rows_body<T, NR, 4>(d, rb, bg, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else if (d.w <= 8) k_bwd_soa_rows_body<T, NR, 8>(d, rb, bg, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else k_bwd_soa_rows_body<T, NR, 16>(d, rb, bg, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+}
+
+template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_bwd_soa_rows(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ it_s,
     const int32_t *__restrict__ it_r0, const int32_t *__restrict__ rows,
     const T *__restrict__ Ls, int64_t Lsize, const T *__restrict__ Ys,
     T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
-    // column-chunk width by the supernode's width (uniform per wave), so
-    // narrow supernodes issue no masked loads for absent columns
-    const int w = sn[it_s[blockIdx.x]].w;
-    if (w <= 4) k_bwd_soa_rows_body<T, NR, 4>(sn, it_s, it_r0, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
-    else if (w <= 8) k_bwd_soa_rows_body<T, NR, 8>(sn, it_s, it_r0, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
-    else k_bwd_soa_rows_body<T, NR, 16>(sn, it_s, it_r0, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    const SnDesc d = sn[it_s[blockIdx.x]];
+    bwd_soa_rows<T, NR>(d, it_r0[blockIdx.x], int(blockIdx.y), rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
 }
 
 // Backward, diagonal blocks: one wave per (supernode, group).  Column
@@ -1416,11 +1422,8 @@ __global__ __launch_bounds__(64) void k_bwd_soa_rows(
 // sequence of operations as in the row-major kernels.
 template <typename T, int NR, int JW>
 __device__ __forceinline__ void k_bwd_soa_diag_body(
-    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
-    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
+    const SnDesc &d, int bg, const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
     const T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
-    const SnDesc d = sn[list[blockIdx.x]];
-    const int bg = blockIdx.y;
     const unsigned lane = threadIdx.x;
     const int c = d.c, w = d.w;
     const int nblk = (c - w + kSoaRows - 1) / kSoaRows;
@@ -1492,16 +1495,107 @@ __device__ __forceinline__ void k_bwd_soa_diag_body(
 }
 
 template <typename T, int NR>
+__device__ __forceinline__ void bwd_soa_diag(const SnDesc &d, int bg, const T *__restrict__ Ls,
+                                             int64_t Lsize, T *__restrict__ Ys,
+                                             const T *__restrict__ PS, int64_t psize, int64_t n,
+                                             int nrhs, int r0) {
+    if (d.w <= 4) k_bwd_soa_diag_body<T, NR, 4>(d, bg, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else if (d.w <= 8) k_bwd_soa_diag_body<T, NR, 8>(d, bg, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    else k_bwd_soa_diag_body<T, NR, 16>(d, bg, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+}
+
+template <typename T, int NR>
 __global__ __launch_bounds__(64) void k_bwd_soa_diag(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys,
     const T *__restrict__ PS, int64_t psize, int64_t n, int nrhs, int r0) {
-    // column-chunk width by the supernode's width (uniform per wave), so
-    // narrow supernodes issue no masked loads for absent columns
-    const int w = sn[list[blockIdx.x]].w;
-    if (w <= 4) k_bwd_soa_diag_body<T, NR, 4>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
-    else if (w <= 8) k_bwd_soa_diag_body<T, NR, 8>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
-    else k_bwd_soa_diag_body<T, NR, 16>(sn, list, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    const SnDesc d = sn[list[blockIdx.x]];
+    bwd_soa_diag<T, NR>(d, int(blockIdx.y), Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+}
+
+// Bottom subtrees in one launch (batch-interleaved layout).  The lowest
+// levels of the tree hold many small supernodes; solving them level by
+// level costs three launches per level and passes every update vector
+// through memory between launches.  Here one wave per (subtree, group of 64
+// matrices) walks a whole subtree: forward in postorder (children first),
+// backward in reverse postorder.  Each supernode goes through the same
+// three steps as in the level kernels (gather of its front vector, the
+// diagonal block, the rows below; backward: the row blocks' partial sums,
+// then the diagonal block), by the same code in the same order, so the bits
+// are those of the level-by-level solve.  A lane only ever reads entries of
+// its own matrix that it wrote earlier in the same wave or that earlier
+// launches wrote, so the wave needs no synchronization.
+
+// Front vector of supernode d (forward): row i = y_{first + i} (i < w) plus
+// the children's update entries of that row (gather map), as k_gather; eight
+// rows at a time.
+template <typename T, int NR>
+__device__ __forceinline__ void fwd_soa_gather(const SnDesc &d, int bg,
+                                               const int32_t *__restrict__ gptr,
+                                               const int32_t *__restrict__ gidx,
+                                               const T *__restrict__ Ys, T *__restrict__ FV,
+                                               int64_t n, int64_t fvsize, int nrhs, int r0) {
+    const unsigned lane = threadIdx.x & 63;
+    const Soa<const T> yb{Ys + (int64_t(bg) * n * nrhs + r0) * 64, lane};
+    const Soa<T> fb{FV + (int64_t(bg) * fvsize * nrhs + r0) * 64, lane};
+    constexpr int GR = 8;
+    for (int i0 = 0; i0 < d.c; i0 += GR) {
+        T a[GR][NR];
+#pragma unroll
+        for (int u = 0; u < GR; u++) {
+            const int i = i0 + u;
+            const bool own = i < d.w;
+#pragma unroll
+            for (int r = 0; r < NR; r++) a[u][r] = yb.ldz(int64_t(d.first + i) * nrhs + r, own);
+        }
+#pragma unroll
+        for (int u = 0; u < GR; u++) {
+            const int i = i0 + u;
+            if (i >= d.c) break;
+            const int64_t q = d.rowptr + i;
+            const int g0 = gptr[q], g1 = gptr[q + 1];
+            for (int g = g0; g < g1; g++) {
+                const int64_t src = gidx[g];
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[u][r] += fb[src * nrhs + r];
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) fb[q * nrhs + r] = a[u][r];
+        }
+    }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_fwd_soa_subtree(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ sub_ptr,
+    const int32_t *__restrict__ sub_sn, const int32_t *__restrict__ gptr,
+    const int32_t *__restrict__ gidx, const T *__restrict__ Ls, int64_t Lsize,
+    T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs, int r0) {
+    const int bg = blockIdx.y;
+    const int e0 = sub_ptr[blockIdx.x], e1 = sub_ptr[blockIdx.x + 1];
+    for (int e = e0; e < e1; e++) {
+        const SnDesc d = sn[sub_sn[e]];
+        fwd_soa_gather<T, NR>(d, bg, gptr, gidx, Ys, FV, n, fvsize, nrhs, r0);
+        fwd_soa_diag<T, NR>(d, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+        for (int rb = d.w; rb < d.c; rb += kSoaRows)
+            fwd_soa_rows<T, NR>(d, rb, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+    }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_bwd_soa_subtree(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ sub_ptr,
+    const int32_t *__restrict__ sub_sn, const int32_t *__restrict__ rows,
+    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ PS,
+    int64_t psize, int64_t n, int nrhs, int r0) {
+    const int bg = blockIdx.y;
+    const int e0 = sub_ptr[blockIdx.x], e1 = sub_ptr[blockIdx.x + 1];
+    for (int e = e1 - 1; e >= e0; e--) {
+        const SnDesc d = sn[sub_sn[e]];
+        for (int rb = d.w; rb < d.c; rb += kSoaRows)
+            bwd_soa_rows<T, NR>(d, rb, bg, rows, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+        bwd_soa_diag<T, NR>(d, bg, Ls, Lsize, Ys, PS, psize, n, nrhs, r0);
+    }
 }
 
 // Solve workspaces hold vectors in the factor's precision (allocated as
@@ -1849,7 +1943,45 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     // top levels with few supernodes: one lane per row (segment kernels)
     const int32_t segmax = P->opt.soa_seg_max == 0 ? kSoaSegMax : P->opt.soa_seg_max;
     auto by_rows = [&](const SLaunch &l) { return segmax > 0 && int64_t(l.nall) * G <= segmax; };
+    // bottom levels as whole subtrees: up to the highest level K such that
+    // every level up to K runs the interleaved level kernels and the
+    // subtrees closed at K still give enough (subtree, group) waves
+    const int32_t fmin = P->opt.soa_subtree_min == 0 ? kSoaSubtreeMin : P->opt.soa_subtree_min;
+    int32_t K = -1;
+    if (fmin > 0)
+        for (int32_t k = 0; k < int32_t(D->fz_roots.size()); k++) {
+            const SLaunch &l = D->ssched[k];
+            if (by_rows(l) || l.npan > 0 || int64_t(D->fz_roots[k]) * G < fmin) break;
+            K = k;
+        }
+    // algorithmic work of the fused launches (the levels they cover)
+    double ff = 0.0, fw = 0.0, fv = 0.0, fi = 0.0, fx = 0.0;
+    for (int32_t k = 0; k <= K; k++) {
+        const SLaunch &l = D->ssched[k];
+        ff += l.f_diag + l.f_rows;
+        fw += l.w_diag + l.w_rows;
+        fv += l.vw_diag + l.vw_rows + l.vw_gather;
+        fi += l.ib_diag + l.ib_rows + l.ib_gather;
+        fx += l.lx_diag + l.lx_rows;
+    }
+    if (K >= 0) {
+        prof.begin(KK_Fwd, ff * nr * nb, (fw * sz + (fv * sz + fi) * nr) * nb, st, fx * sz * nb);
+        for (int r0 = 0; r0 < nrhs; r0 += 4) {
+            const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_SUBF(NRV)                                                                         \
+    hipLaunchKernelGGL((k_fwd_soa_subtree<T, NRV>), dim3(unsigned(D->fz_roots[K]), G), dim3(64), \
+                       0, st, D->sn, D->fz_ptr[K], D->fz_sn[K], D->gptr, D->gidx, Ls, P->Lsize,  \
+                       as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs, r0)
+            if (nrr == 1) SPCHOL_SUBF(1);
+            else if (nrr == 2) SPCHOL_SUBF(2);
+            else if (nrr == 3) SPCHOL_SUBF(3);
+            else SPCHOL_SUBF(4);
+#undef SPCHOL_SUBF
+        }
+        prof.end(st);
+    }
     for (const SLaunch &l : D->ssched) {
+        if (l.level <= K) continue;  // in the subtrees above
         launch_gather<T, true>(l, P, N, nrhs, nullptr, st);
         if (by_rows(l)) {
             classes_forward<T, true>(l, P, N, nrhs, nullptr, st);
@@ -1892,6 +2024,25 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     }
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
+        if (l.level <= K) {  // the subtrees, once, after the levels above them
+            if (l.level == K) {
+                prof.begin(KK_Bwd, ff * nr * nb, (fw * sz + (fv * sz + fi) * nr) * nb, st, fx * sz * nb);
+                for (int r0 = 0; r0 < nrhs; r0 += 4) {
+                    const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_SUBB(NRV)                                                                         \
+    hipLaunchKernelGGL((k_bwd_soa_subtree<T, NRV>), dim3(unsigned(D->fz_roots[K]), G), dim3(64), \
+                       0, st, D->sn, D->fz_ptr[K], D->fz_sn[K], D->rows, Ls, P->Lsize,           \
+                       as<T>(N->wsc->y), as<T>(N->wsc->ps), P->soa_psize, P->n, nrhs, r0)
+                    if (nrr == 1) SPCHOL_SUBB(1);
+                    else if (nrr == 2) SPCHOL_SUBB(2);
+                    else if (nrr == 3) SPCHOL_SUBB(3);
+                    else SPCHOL_SUBB(4);
+#undef SPCHOL_SUBB
+                }
+                prof.end(st);
+            }
+            continue;
+        }
         if (l.npan > 0) {
             if (sn_fits<T>(l, N, nrhs)) sn_backward<T, true>(l, P, N, nrhs, nullptr, st);
             else panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
@@ -2075,6 +2226,55 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
         }
         D->ssched.push_back(s);
     }
+}
+
+// Subtree lists of the fused bottom-level solve, for every level K up to
+// which no level has panel-solved supernodes (host work once per plan, then
+// uploaded).
+hipError_t spchol_build_subtrees(const sc_plan *P, DevPlan *D) {
+    int32_t kmax = -1;
+    for (const SLaunch &l : D->ssched) {
+        if (l.npan > 0) break;
+        kmax = l.level;
+    }
+    D->fz_ptr.assign(size_t(kmax + 1), nullptr);
+    D->fz_sn.assign(size_t(kmax + 1), nullptr);
+    D->fz_roots.assign(size_t(kmax + 1), 0);
+    std::vector<int32_t> ptr, order;
+    for (int32_t K = 0; K <= kmax; K++) {
+        ptr.assign(1, 0);
+        order.clear();
+        for (int32_t s = 0; s < P->ns; s++) {
+            const SnDesc &d = P->sn[s];
+            if (d.level > K || (d.parent >= 0 && P->sn[d.parent].level <= K)) continue;
+            // postorder of the subtree of s: children (in list order) first
+            std::vector<std::pair<int32_t, int32_t>> st{{s, P->sn[s].chbeg}};
+            while (!st.empty()) {
+                auto &top = st.back();
+                const SnDesc &t = P->sn[top.first];
+                if (top.second < t.chend) {
+                    const int32_t ch = P->chlist[top.second++];
+                    st.push_back({ch, P->sn[ch].chbeg});
+                } else {
+                    order.push_back(top.first);
+                    st.pop_back();
+                }
+            }
+            ptr.push_back(int32_t(order.size()));
+        }
+        D->fz_roots[K] = int32_t(ptr.size() - 1);
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&D->fz_ptr[K]), ptr.size() * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(&D->fz_sn[K]),
+                          std::max<size_t>(order.size(), 1) * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(D->fz_ptr[K], ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !order.empty())
+            e = hipMemcpy(D->fz_sn[K], order.data(), order.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T, int NR>

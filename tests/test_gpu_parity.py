@@ -350,6 +350,28 @@ def test_interleaved_layout_bitwise_equal_rowmajor(name, make, dtype, seg_max):
                 assert oracle.within_conditioning(err, 1e-10, kap)
 
 
+@pytest.mark.parametrize("sub_min", [1, 24, 400], ids=["all-levels", "some-levels", "few-levels"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,make", [
+    ("grid3d_20x18x16_nd", lambda: W.small_grid((20, 18, 16), "nd", batch=70, nrhs=3, seed=53)),
+    ("trimesh_48", lambda: W.trimesh_workload(48, batch=40, nrhs=2, seed=54)),
+    ("random_180_dense", lambda: W.random_spd(180, 0.4, seed=55, batch=33, nrhs=5)),
+], ids=["grid3d", "trimesh", "dense"])
+def test_interleaved_subtrees_bitwise_equal_rowmajor(name, make, dtype, sub_min):
+    """The lowest levels of the interleaved solve run as whole subtrees, one
+    wave per (subtree, group of matrices), up to the highest level with at
+    least `sub_min` such waves.  Every supernode goes through the same
+    operations in the same order as in the level kernels, so the solutions
+    are bit-identical to the row-major layout's for every cut."""
+    w = make()
+    log("case %s batch=%d nrhs=%d %s subtree_min=%d" % (name, w.batch, w.nrhs, dtype, sub_min))
+    x_sub = _solve_with(w, dtype, soa_min_batch=32, soa_subtree_min=sub_min)
+    x_lvl = _solve_with(w, dtype, soa_min_batch=32, soa_subtree_min=-1)
+    x_row = _solve_with(w, dtype, soa_min_batch=-1)
+    assert np.array_equal(x_lvl, x_row)
+    assert np.array_equal(x_sub, x_row)
+
+
 def test_interleaved_copy_refreshed_after_refactor():
     """The interleaved copy of L is rebuilt after every factorization: value
     set A, then B, on one numeric object gives B's fresh solution."""
