@@ -303,9 +303,9 @@ MFMA_FAMILIES = {"syrk_mfma", "trsm"}
 # sources that define each kernel family (HBM counters taken on other
 # versions of them are stale)
 FAMILY_SOURCES = {
-    "factor": ("factor.hip", "device.hpp", "plan.hpp"),
-    "solve": ("solve.hip", "device.hpp", "plan.hpp"),
-    "refine": ("refine.hip", "device.hpp", "plan.hpp"),
+    "factor": ("factor.hip",),
+    "solve": ("solve.hip",),
+    "refine": ("refine.hip",),
 }
 FACTOR_FAMILIES = {"front_small", "assemble", "potrf", "trsm", "syrk_mfma"}
 REFINE_FAMILIES = {"spmv_residual", "refine_vector"}
