@@ -87,7 +87,7 @@ typedef struct {
                              levels are solved as whole subtrees, one wave
                              per (subtree, group of 64 matrices), up to the
                              highest level that still has at least this
-                             many such waves; 0 = library default (4096),
+                             many such waves; 0 = library default (2048),
                              a negative value never (level by level)     */
     int32_t ordering;      /* elimination order: SC_ORDER_NATURAL, or
                              SC_ORDER_GIVEN (default: the caller's perm,

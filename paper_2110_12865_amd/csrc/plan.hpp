@@ -83,7 +83,7 @@ constexpr int kSoaRows = 16;
 constexpr int kSoaChunk = 128;
 constexpr int kSoaMinBatch = 64;  // default of sc_options::soa_min_batch: whole lane groups
 constexpr int kSoaSegMax = 96;    // default of sc_options::soa_seg_max
-constexpr int kSoaSubtreeMin = 4096;  // default of sc_options::soa_subtree_min
+constexpr int kSoaSubtreeMin = 2048;  // default of sc_options::soa_subtree_min
 
 constexpr int kSellRows = 64;  // rows per slice of the sliced row structure of A
 

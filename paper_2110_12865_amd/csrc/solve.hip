@@ -1521,14 +1521,70 @@ __global__ __launch_bounds__(64) void k_bwd_soa_diag(
 // backward in reverse postorder.  Each supernode goes through the same
 // three steps as in the level kernels (gather of its front vector, the
 // diagonal block, the rows below; backward: the row blocks' partial sums,
-// then the diagonal block), by the same code in the same order, so the bits
-// are those of the level-by-level solve.  A lane only ever reads entries of
+// then the diagonal block) with the same arithmetic in the same order, so
+// the bits are those of the level-by-level solve; forward, a supernode of
+// width <= 16 takes the three steps in one pass (fwd_soa_fused_body).  A lane only ever reads entries of
 // its own matrix that it wrote earlier in the same wave or that earlier
 // launches wrote, so the wave needs no synchronization.
 
-// Front vector of supernode d (forward): row i = y_{first + i} (i < w) plus
-// the children's update entries of that row (gather map), as k_gather; eight
-// rows at a time.
+// Gathered front-vector rows i0 .. i0 + GR - 1 of supernode d: y_{first + i}
+// for i < w (0 below), plus the children's update entries of the row in map
+// order; rows at or past `lim` give 0 and load nothing.  The chunk's gather
+// indices come in with one vector load (lane l holds entry g0 + l) and are
+// broadcast from there, so the first GK entries of every row are loaded
+// before any is added; later entries of a row, if any, follow one by one.
+template <typename T, int NR, int GR, int GK>
+__device__ __forceinline__ void soa_gather_chunk(const SnDesc &d, int i0, int lim,
+                                                 const int32_t *__restrict__ gptr,
+                                                 const int32_t *__restrict__ gidx,
+                                                 const Soa<const T> &yg, const Soa<T> &fg,
+                                                 int nrhs, T (&a)[GR][NR]) {
+    const int64_t q0 = d.rowptr + i0;
+    const int nr = min(GR, lim - i0);
+    int gb[GR + 1];
+#pragma unroll
+    for (int u = 0; u <= GR; u++) gb[u] = gptr[q0 + min(u, nr)];
+    const int gcnt = gb[GR] - gb[0];
+    const int gl = fg.lane < unsigned(gcnt) ? gidx[gb[0] + int(fg.lane)] : 0;
+#pragma unroll
+    for (int u = 0; u < GR; u++) {
+        const int i = i0 + u;
+        const bool own = i < d.w && u < nr;
+#pragma unroll
+        for (int r = 0; r < NR; r++) a[u][r] = yg.ldz(int64_t(d.first + i) * nrhs + r, own);
+    }
+    T t[GR][GK][NR];
+#pragma unroll
+    for (int u = 0; u < GR; u++)
+#pragma unroll
+        for (int k = 0; k < GK; k++) {
+            const int g = gb[u] + k;
+            const bool ok = g < gb[u + 1] && g - gb[0] < 64;
+            const int64_t src = __builtin_amdgcn_readlane(gl, ok ? g - gb[0] : 0);
+#pragma unroll
+            for (int r = 0; r < NR; r++) t[u][k][r] = fg.ldc(src * nrhs + r, ok);
+        }
+#pragma unroll
+    for (int u = 0; u < GR; u++) {
+        if (u >= nr) break;
+        int g = gb[u];
+#pragma unroll
+        for (int k = 0; k < GK; k++) {
+            if (g < gb[u + 1] && g - gb[0] < 64) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[u][r] += t[u][k][r];
+                g++;
+            }
+        }
+        for (; g < gb[u + 1]; g++) {
+            const int64_t src = gidx[g];
+#pragma unroll
+            for (int r = 0; r < NR; r++) a[u][r] += fg[src * nrhs + r];
+        }
+    }
+}
+
+// Front vector of supernode d (forward) into FV, as k_gather.
 template <typename T, int NR>
 __device__ __forceinline__ void fwd_soa_gather(const SnDesc &d, int bg,
                                                const int32_t *__restrict__ gptr,
@@ -1536,32 +1592,94 @@ __device__ __forceinline__ void fwd_soa_gather(const SnDesc &d, int bg,
                                                const T *__restrict__ Ys, T *__restrict__ FV,
                                                int64_t n, int64_t fvsize, int nrhs, int r0) {
     const unsigned lane = threadIdx.x & 63;
-    const Soa<const T> yb{Ys + (int64_t(bg) * n * nrhs + r0) * 64, lane};
-    const Soa<T> fb{FV + (int64_t(bg) * fvsize * nrhs + r0) * 64, lane};
-    constexpr int GR = 8;
+    const Soa<const T> yg{Ys + (int64_t(bg) * n * nrhs + r0) * 64, lane};
+    const Soa<T> fg{FV + (int64_t(bg) * fvsize * nrhs + r0) * 64, lane};
+    constexpr int GR = 8, GK = sizeof(T) == 4 ? 4 : 2;
     for (int i0 = 0; i0 < d.c; i0 += GR) {
         T a[GR][NR];
+        soa_gather_chunk<T, NR, GR, GK>(d, i0, d.c, gptr, gidx, yg, fg, nrhs, a);
 #pragma unroll
-        for (int u = 0; u < GR; u++) {
-            const int i = i0 + u;
-            const bool own = i < d.w;
+        for (int u = 0; u < GR; u++)
+            if (i0 + u < d.c)
 #pragma unroll
-            for (int r = 0; r < NR; r++) a[u][r] = yb.ldz(int64_t(d.first + i) * nrhs + r, own);
+                for (int r = 0; r < NR; r++) fg[(d.rowptr + i0 + u) * nrhs + r] = a[u][r];
+    }
+}
+
+// Gather, diagonal block and rows below of one supernode with w <= JW (one
+// column chunk), in one pass: the diagonal block's front rows stay in
+// registers and the update rows are gathered, reduced and stored once.  The
+// arithmetic is that of fwd_soa_gather + fwd_soa_diag + fwd_soa_rows with
+// the same JW, operation for operation, so the bits are the same.
+template <typename T, int NR, int JW>
+__device__ __forceinline__ void fwd_soa_fused_body(
+    const SnDesc &d, int bg, const int32_t *__restrict__ gptr, const int32_t *__restrict__ gidx,
+    const T *__restrict__ Ls, int64_t Lsize, T *__restrict__ Ys, T *__restrict__ FV, int64_t n,
+    int64_t fvsize, int nrhs, int r0) {
+    const unsigned lane = threadIdx.x & 63;
+    const int c = d.c, w = d.w;
+    // four update rows per step and two child entries per row in flight:
+    // larger steps take more registers than three waves per SIMD allow
+    constexpr int GK = 2, GR = 4;
+    constexpr int TR = JW < GR ? JW : GR;  // diagonal-block rows per gather chunk
+    const Soa<const T> yg{Ys + (int64_t(bg) * n * nrhs + r0) * 64, lane};
+    const Soa<T> fg{FV + (int64_t(bg) * fvsize * nrhs + r0) * 64, lane};
+    const SoaBlk<T> Lb(Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane);
+    const SoaBlk<T> yb(Ys + ((int64_t(bg) * n + d.first) * nrhs + r0) * 64, lane);
+    T v[JW][NR];
+#pragma unroll
+    for (int k = 0; k < JW / TR; k++) {
+        T a[TR][NR];
+        if (k * TR < w) {
+            soa_gather_chunk<T, NR, TR, GK>(d, k * TR, w, gptr, gidx, yg, fg, nrhs, a);
+        } else {
+#pragma unroll
+            for (int u = 0; u < TR; u++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[u][r] = T(0);
         }
 #pragma unroll
-        for (int u = 0; u < GR; u++) {
-            const int i = i0 + u;
-            if (i >= d.c) break;
-            const int64_t q = d.rowptr + i;
-            const int g0 = gptr[q], g1 = gptr[q + 1];
-            for (int g = g0; g < g1; g++) {
-                const int64_t src = gidx[g];
+        for (int u = 0; u < TR; u++)
 #pragma unroll
-                for (int r = 0; r < NR; r++) a[u][r] += fb[src * nrhs + r];
-            }
+            for (int r = 0; r < NR; r++) v[k * TR + u][r] = a[u][r];
+    }
 #pragma unroll
-            for (int r = 0; r < NR; r++) fb[q * nrhs + r] = a[u][r];
+    for (int jj = 0; jj < JW; jj++) {
+        const bool ok = jj < w;
+        T lrow[JW];
+#pragma unroll
+        for (int kk = 0; kk <= jj; kk++) lrow[kk] = Lb.ldz(int64_t(kk) * c + jj, ok);
+#pragma unroll
+        for (int kk = 0; kk < jj; kk++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) v[jj][r] -= T(lrow[kk]) * v[kk][r];
+        const T rinv = ok ? T(1) / T(lrow[jj]) : T(0);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            v[jj][r] *= rinv;
+            if (ok) yb.st(int64_t(jj) * nrhs + r, v[jj][r]);
         }
+    }
+    for (int i0 = w; i0 < c; i0 += GR) {
+        T a[GR][NR];
+        soa_gather_chunk<T, NR, GR, GK>(d, i0, c, gptr, gidx, yg, fg, nrhs, a);
+        T l[GR][JW];
+#pragma unroll
+        for (int u = 0; u < GR; u++)
+#pragma unroll
+            for (int jj = 0; jj < JW; jj++)
+                l[u][jj] = Lb.ldc(int64_t(jj) * c + i0 + u, i0 + u < c && jj < w);
+#pragma unroll
+        for (int u = 0; u < GR; u++)
+#pragma unroll
+            for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[u][r] -= T(l[u][jj]) * v[jj][r];
+#pragma unroll
+        for (int u = 0; u < GR; u++)
+            if (i0 + u < c)
+#pragma unroll
+                for (int r = 0; r < NR; r++) fg[(d.rowptr + i0 + u) * nrhs + r] = a[u][r];
     }
 }
 
@@ -1575,10 +1693,18 @@ __global__ __launch_bounds__(64) void k_fwd_soa_subtree(
     const int e0 = sub_ptr[blockIdx.x], e1 = sub_ptr[blockIdx.x + 1];
     for (int e = e0; e < e1; e++) {
         const SnDesc d = sn[sub_sn[e]];
-        fwd_soa_gather<T, NR>(d, bg, gptr, gidx, Ys, FV, n, fvsize, nrhs, r0);
-        fwd_soa_diag<T, NR>(d, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
-        for (int rb = d.w; rb < d.c; rb += kSoaRows)
-            fwd_soa_rows<T, NR>(d, rb, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+        if (d.w <= 4) {
+            fwd_soa_fused_body<T, NR, 4>(d, bg, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+        } else if (d.w <= 8) {
+            fwd_soa_fused_body<T, NR, 8>(d, bg, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+        } else if (d.w <= 16) {
+            fwd_soa_fused_body<T, NR, 16>(d, bg, gptr, gidx, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+        } else {
+            fwd_soa_gather<T, NR>(d, bg, gptr, gidx, Ys, FV, n, fvsize, nrhs, r0);
+            fwd_soa_diag<T, NR>(d, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+            for (int rb = d.w; rb < d.c; rb += kSoaRows)
+                fwd_soa_rows<T, NR>(d, rb, bg, Ls, Lsize, Ys, FV, n, fvsize, nrhs, r0);
+        }
     }
 }
 
