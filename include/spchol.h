@@ -96,6 +96,17 @@ typedef struct {
                              graph: separators from breadth-first level
                              structures rooted at pseudo-peripheral
                              vertices; perm must be NULL)                  */
+    int32_t panel_inverse; /* batched solves (at least 16 matrices) of the
+                             levels whose supernodes are solved by 64-column
+                             panels, all at most 1024 columns wide: each
+                             factorization also forms X = L11^{-1} of those
+                             supernodes' diagonal blocks, and the solves
+                             multiply by X (many workgroups per supernode)
+                             instead of substituting panel after panel; the
+                             results agree to rounding, not bit for bit.
+                             0 = library default (on for SC_F32 factors, off
+                             for SC_F64), 1 = on for both, a negative value
+                             never                                          */
 } sc_options;
 
 /* Values of sc_options.ordering. */

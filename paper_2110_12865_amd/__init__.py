@@ -60,7 +60,7 @@ class Options(ctypes.Structure):
                 ("relax_zeros", ctypes.c_double), ("small_front", ctypes.c_int32),
                 ("soa_min_batch", ctypes.c_int32), ("soa_seg_max", ctypes.c_int32),
                 ("soa_subtree_min", ctypes.c_int32),
-                ("ordering", ctypes.c_int32)]
+                ("ordering", ctypes.c_int32), ("panel_inverse", ctypes.c_int32)]
 
 
 class TuneEntry(ctypes.Structure):

@@ -551,6 +551,34 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             }
             P->slv_pan_ptr[l + 1] = int32_t(P->slv_pan.size());
         }
+        // whole-block inverses of the diagonal blocks, for the levels whose
+        // panel-solved supernodes are all narrow enough
+        P->xoff.assign(ns, -1);
+        P->slv_pan_x.assign(nlev, 0);
+        P->xg_ptr.assign(nlev + 1, 0);
+        for (int32_t l = 0; l < nlev; l++) {
+            const int32_t e0 = P->slv_pan_ptr[l], e1 = P->slv_pan_ptr[l + 1];
+            if (opt.panel_inverse >= 0 && e0 < e1 && P->slv_pan_maxw[l] <= kXMaxW) {
+                P->slv_pan_x[l] = 1;
+                for (int32_t e = e0; e < e1; e++) {
+                    const int32_t s = P->slv_pan[e];
+                    const SnDesc &d = P->sn[s];
+                    const int64_t w = d.w;
+                    P->xoff[s] = P->xsize;
+                    P->xsize += w * w;
+                    P->x_list.push_back(s);
+                    P->x_nbmax = std::max<int32_t>(P->x_nbmax, int32_t((w + kSolvePanel - 1) / kSolvePanel));
+                    for (int32_t i = 0; i < d.c; i++) {
+                        P->xg_q.push_back(int32_t(d.rowptr + i));
+                        P->xg_y.push_back(i < d.w ? d.first + i : -1);
+                    }
+                }
+            }
+            P->xg_ptr[l + 1] = int32_t(P->xg_q.size());
+        }
+        // widest first: the longest chains of the inversion start first
+        std::stable_sort(P->x_list.begin(), P->x_list.end(),
+                         [&](int32_t a, int32_t b) { return P->sn[a].w > P->sn[b].w; });
         // panel-solved supernodes whose diagonal blocks the tiled factor
         // does not invert (small fronts): inverted after the factorization
         for (int32_t s : P->slv_pan)

@@ -55,7 +55,7 @@ void free_devplan(DevPlan *D) {
                     D->asm_col, D->csr_ptr, D->sell_ptr, D->sell_col, D->sell_vidx,
                     D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr,
                     D->gidx, D->dinv_list, D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
-                    D->val_row, D->val_col};
+                    D->val_row, D->val_col, D->xoff, D->x_list, D->xg_q, D->xg_y};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int32_t *p : D->fz_ptr)
@@ -99,6 +99,10 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->slv_small, P->slv_small);
     if (e == hipSuccess) e = upload(&D->slv_pan, P->slv_pan);
     if (e == hipSuccess) e = upload(&D->dinv_list, P->dinv_list);
+    if (e == hipSuccess) e = upload(&D->xoff, P->xoff);
+    if (e == hipSuccess) e = upload(&D->x_list, P->x_list);
+    if (e == hipSuccess) e = upload(&D->xg_q, P->xg_q);
+    if (e == hipSuccess) e = upload(&D->xg_y, P->xg_y);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
     if (e == hipSuccess) e = upload(&D->sell_ptr, P->sell_ptr);
     if (e == hipSuccess) e = upload(&D->sell_col, P->sell_col);
@@ -266,6 +270,7 @@ sc_status sc_options_default(sc_options *opt) {
     opt->soa_seg_max = kSoaSegMax;
     opt->soa_subtree_min = kSoaSubtreeMin;
     opt->ordering = SC_ORDER_GIVEN;
+    opt->panel_inverse = 0;
     return SC_OK;
 }
 
@@ -453,6 +458,9 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
                       std::max<size_t>(size_t(batch) * P->dinv_size * sizeof(double), 8));
     if (e == hipSuccess && N->soa)
         e = hipMalloc(&N->Ls, std::max<size_t>(size_t((batch + 63) / 64) * 64 * P->Lsize * sz, 8));
+    const bool xinv = P->xsize > 0 && batch >= kXMinBatch &&
+                      (P->opt.panel_inverse > 0 || (P->opt.panel_inverse == 0 && dtype == SC_F32));
+    if (e == hipSuccess && xinv) e = hipMalloc(&N->xinv, size_t(batch) * P->xsize * sz);
     if (e == hipSuccess) e = hipMemset(N->info, 0, sizeof(int32_t) * ninfo);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&N->ev_fork, hipEventDisableTiming);
@@ -471,7 +479,7 @@ void sc_numeric_destroy(sc_numeric_t *N) {
     if (N->L) (void)hipFree(N->L);
     if (N->U) (void)hipFree(N->U);
     if (N->info) (void)hipFree(N->info);
-    void *ws[] = {N->pinv, N->dinv, N->Ls};
+    void *ws[] = {N->pinv, N->dinv, N->Ls, N->xinv};
     for (void *q : ws)
         if (q) (void)hipFree(q);
     free_solve_ws(N->ws);

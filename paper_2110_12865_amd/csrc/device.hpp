@@ -74,6 +74,11 @@ struct SLaunch {  // one level of a triangular solve
     double lx_diag = 0.0, lx_rows = 0.0;  // exact entries of L in those parts
     int32_t pan0 = 0, npan = 0;      // supernodes solved by panels
     int32_t maxc_pan = 0;
+    int32_t maxw_pan = 0;
+    bool xpan = false;  // the panel-solved supernodes have whole-block inverses
+    double x_words = 0.0, x_lx = 0.0;  // X and L21 scalars read per sweep; exact L entries
+    int32_t xg0 = 0, nxg = 0;          // their front rows in xg_q / xg_y
+    double vw_xg = 0.0, ib_xg = 0.0;
     double vw_pan = 0.0, ib_pan = 0.0;
     std::vector<SPanel> panels;
 };
@@ -96,6 +101,10 @@ struct DevPlan {
     int32_t *slv_small = nullptr;     // solve schedule lists
     int32_t *slv_pan = nullptr;
     int32_t *dinv_list = nullptr;     // panel-solved small fronts
+    int64_t *xoff = nullptr;          // whole-block inverses: offset per supernode
+    int32_t *x_list = nullptr;        // supernodes that have one
+    int32_t *xg_q = nullptr;          // their front rows (forward gather)
+    int32_t *xg_y = nullptr;
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int64_t *sell_ptr = nullptr;      // the same rows sliced by kSellRows
     int32_t *sell_col = nullptr;
@@ -205,6 +214,9 @@ struct sc_numeric {
     int32_t *info = nullptr; // batch
     void *pinv = nullptr;    // batch * max_lvl_big * 64 * 64: panel inverses (factor)
     double *dinv = nullptr;  // batch * dinv_size: inverted diagonal blocks
+    // batch * xsize scalars: whole-block inverses of the diagonal blocks of
+    // the plan's X supernodes (null: the solves substitute panel by panel)
+    void *xinv = nullptr;
     // solve workspaces owned by the numeric object (allocated on first use,
     // grown for more right-hand sides), and the set the solve kernels use:
     // `wsc` points at `ws` except inside sc_solve_noalloc, which points it at

@@ -572,6 +572,147 @@ __device__ inline void tile_pos(int a, int q, int r, int &j, int &i) {
     i = (wv >> 1) * 32 + 16 * q + (lane & 15);
 }
 
+// Whole-block inverse X = L11^{-1} of the diagonal block of a panel-solved
+// supernode, by 64-column block columns J (one workgroup of 256 threads per
+// (J, supernode, matrix)): X_JJ = D_J, the inverted diagonal block the
+// factor already holds, and below it, for I = J + 1, J + 2, ...,
+//   X_IJ = -D_I (sum_{K=J}^{I-1} L_IK X_KJ),
+// the standard block recurrence of the inverse of a lower-triangular matrix
+// (from L X = I, block row I).  The 64 x 64 products run on the matrix cores
+// with the K sum in ascending order; the next pair of operand tiles is in
+// flight while the current one is multiplied.  The grid runs matrices
+// fastest and the supernodes widest first, so the longest chains (block
+// column 0 of the widest blocks) start first.  X is stored column-major
+// with leading dimension w (entry (i, j) at j w + i); blocks above the
+// diagonal blocks are never written nor read.
+constexpr int kXPitch = kTile + 1;  // LDS pitch of the [t][i] operand written across lanes
+template <typename T>
+__device__ inline void xtile_mma(const T *sA, const T *sB, typename Mma<T>::acc_t (&acc)[2][2]) {
+    // C[j][i] += sum_t sA[t * 64 + j] sB[t * kXPitch + i], the wave's 32 x 32 quadrant
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int jw = (wv & 1) * 32, iw = (wv >> 1) * 32;
+    const int lk = lane >> 4, lm = lane & 15;
+#pragma unroll 4
+    for (int kk = 0; kk < kTile; kk += 4) {
+        const T *rA = sA + (kk + lk) * kTile;
+        const T *rB = sB + (kk + lk) * kXPitch;
+        T av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++) av[a] = rA[jw + 16 * a + lm];
+#pragma unroll
+        for (int q = 0; q < 2; q++) bv[q] = rB[iw + 16 * q + lm];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int q = 0; q < 2; q++) acc[a][q] = Mma<T>::mma(av[a], bv[q], acc[a][q]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trtri(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int64_t *__restrict__ xoff, const T *__restrict__ L, int64_t Lsize,
+    const T *__restrict__ Dinv, int64_t dsize, T *__restrict__ X, int64_t xsize) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sA = reinterpret_cast<T *>(smem_raw);  // [t][j]: L_IK[j][t], then D_I[j][t]
+    T *sB = sA + kTile * kTile;               // [t][i] (pitch kXPitch): X_KJ[t][i], then T[t][i]
+    const int b = blockIdx.x;
+    const int J = blockIdx.y;
+    const int s = list[blockIdx.z];
+    const SnDesc d = sn[s];
+    const int w = d.w, c = d.c;
+    const int nb = (w + kTile - 1) / kTile;
+    if (J >= nb) return;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    const T *Db = Dinv + int64_t(b) * dsize + d.dinv;
+    T *Xb = X + int64_t(b) * xsize + xoff[s];
+    const int tid = threadIdx.x, li = tid & 63, lt = tid >> 6;
+    const int cJ = kTile * J, kbJ = min(kTile, w - cJ);
+    // X_JJ = D_J (column-major, zero-padded past kbJ)
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const int col = lt + 4 * q;
+        if (col < kbJ && li < kbJ)
+            Xb[int64_t(cJ + col) * w + cJ + li] = Db[int64_t(J) * kTile * kTile + col * kTile + li];
+    }
+    // below J every block column is whole: only block I may be partial
+    T ra[16], rb[16];
+    // operands of step (I, K): K < I gives L_IK and X_KJ, K == I gives D_I
+    auto load = [&](int I, int K) {
+        const int cI = kTile * I, kbI = min(kTile, w - cI);
+        if (K < I) {
+            const int cK = kTile * K;
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int t = lt + 4 * q;  // ra: L_IK[li][t]; rb: X_KJ[li][t] (t = column)
+                ra[q] = li < kbI ? Lb[int64_t(cK + t) * c + cI + li] : T(0);
+                rb[q] = Xb[int64_t(cJ + t) * w + cK + li];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int t = lt + 4 * q;  // D_I[li][t], zero-padded
+                ra[q] = Db[int64_t(I) * kTile * kTile + t * kTile + li];
+            }
+        }
+    };
+    if (J + 1 < nb) load(J + 1, J);
+    for (int I = J + 1; I < nb; I++) {
+        const int cI = kTile * I, kbI = min(kTile, w - cI);
+        typename Mma<T>::acc_t acc[2][2];
+        acc_zero<T>(acc);
+        for (int K = J; K < I; K++) {
+            __syncthreads();  // the previous products have read sA and sB
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int t = lt + 4 * q;
+                sA[t * kTile + li] = ra[q];
+                sB[li * kXPitch + t] = rb[q];
+            }
+            __syncthreads();
+            load(I, K + 1);  // the next pair (or D_I), in flight during the products
+            xtile_mma(sA, sB, acc);
+        }
+        __syncthreads();  // the last products have read sA and sB
+        // sB <- T (rows t of T are the K index of the next product), sA <- D_I
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    int j, i;
+                    tile_pos<T>(a, q, r, j, i);
+                    sB[j * kXPitch + i] = acc[a][q][r];
+                }
+#pragma unroll
+        for (int q = 0; q < 16; q++) sA[(lt + 4 * q) * kTile + li] = ra[q];
+        __syncthreads();
+        if (I + 1 < nb) load(I + 1, J);
+        typename Mma<T>::acc_t acc2[2][2];
+        acc_zero<T>(acc2);
+        xtile_mma(sA, sB, acc2);
+        __syncthreads();  // sA is read; it now stages X_IJ for a coalesced store
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    int j, i;
+                    tile_pos<T>(a, q, r, j, i);
+                    sA[i * kTile + j] = -acc2[a][q][r];
+                }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int col = lt + 4 * q;
+            if (li < kbI) Xb[int64_t(cJ + col) * w + cI + li] = sA[col * kTile + li];
+        }
+    }
+}
+
 // Fronts of 64 < c <= kFrontWgMaxC rows, one workgroup of 256 threads per
 // (front, matrix).  The front's lower triangle is packed in LDS (column t
 // from t c - t (t - 1) / 2, rows t .. c - 1): A's entries are placed and the
@@ -935,6 +1076,8 @@ void set_lds_limits(int big) {
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_potrf<T>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trtri<T>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
 // Flops of the partial factorization of the first w columns of a c-row
@@ -1181,7 +1324,17 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return spchol_dinv_run(P, N, st);  // inverted diagonal blocks for the solves
+    e = spchol_dinv_run(P, N, st);  // inverted diagonal blocks for the solves
+    if (e != hipSuccess || !N->xinv || P->x_list.empty()) return e;
+    // whole-block inverses from them
+    prof.begin(KK_Dinv, 0.0, 0.0, st);
+    hipLaunchKernelGGL(k_trtri<T>,
+                       dim3(unsigned(N->batch), unsigned(P->x_nbmax), unsigned(P->x_list.size())),
+                       dim3(256), size_t(kTile * kTile + kTile * kXPitch) * sizeof(T), st, D->sn,
+                       D->x_list, D->xoff, L, P->Lsize, reinterpret_cast<const T *>(N->dinv),
+                       P->dinv_size, static_cast<T *>(N->xinv), P->xsize);
+    prof.end(st);
+    return hipGetLastError();
 }
 
 }  // namespace

@@ -87,6 +87,13 @@ constexpr int kSoaSubtreeMin = 2048;  // default of sc_options::soa_subtree_min
 
 constexpr int kSellRows = 64;  // rows per slice of the sliced row structure of A
 
+// Whole-block inverses X = L11^{-1} of the diagonal blocks of panel-solved
+// supernodes (sc_options::panel_inverse): levels whose panel-solved
+// supernodes are all at most kXMaxW columns wide, for numeric objects of at
+// least kXMinBatch matrices (the batched solves that use them).
+constexpr int kXMaxW = 1024;
+constexpr int kXMinBatch = 16;
+
 // Fronts of 64 < c rows factored by one workgroup keep their packed lower
 // triangle and the 64-row tiles of L21 ([k][64], k padded to 4) in LDS;
 // scalars needed for a front of c rows and width w.  A front goes there only
@@ -194,6 +201,18 @@ struct sc_plan {
     // writes the others as it factors each block)
     std::vector<int32_t> dinv_list;
     int64_t part_size = 0;   // partial sums per right-hand side
+    // whole-block inverses: per supernode the offset of its w x w
+    // column-major X (-1: none), scalars per matrix, the supernodes that have
+    // one
+    // (x_list widest first), and per level whether its panel-solved
+    // supernodes use them, with their front rows for the forward gather
+    // (as grow_*: position rowptr_s + i, right-hand-side row or -1)
+    std::vector<int64_t> xoff;
+    int64_t xsize = 0;
+    std::vector<int32_t> x_list;
+    std::vector<uint8_t> slv_pan_x;
+    std::vector<int32_t> xg_ptr, xg_q, xg_y;
+    int32_t x_nbmax = 0;  // most 64-column blocks of one X
     int32_t npan = 0;        // supernodes solved by panels
     std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts
     int32_t max_lvl_big = 0;              // most large fronts in one level

@@ -1056,6 +1056,236 @@ __global__ __launch_bounds__(kSnThreads) void k_bwd_sn(
 }
 
 // ---------------------------------------------------------------------------
+// Panel-solved supernodes with whole-block inverses X = L11^{-1} of their
+// diagonal blocks (formed after the factorization; column-major, leading
+// dimension w, zero above the diagonal inside the diagonal 64 x 64 blocks,
+// blocks above those never read).  Forward, after the gather of the front
+// vector v = (v1, v2): y = X v1, then u = v2 - L21 y; backward: rhs = y -
+// L21^T x2, then x1 = X^T rhs.  Each is a dense product over the whole
+// block, split over 64-row (or 64-column) blocks so that a supernode takes
+// many workgroups instead of one chain of 64-column panels.
+
+constexpr int kXChunk = 512;  // vector rows staged in LDS at a time (backward)
+
+// Column sums of the wave's 16 columns j0 .. j0 + 15 (those below jn) of a
+// column-major block M (leading dimension ld) over rows [i0, i1), times the
+// vector rows staged in vs (row i at vs[i - i0]): acc[k][r] += sum_i
+// M[(j0 + k) ld + i] vs[i - i0][r].  Lanes take the rows 64 at a time, so
+// every load of M is 64 consecutive entries of one column.
+template <typename T, int NR>
+__device__ __forceinline__ void wave_colsums(const T *__restrict__ M, int64_t ld, int i0, int i1,
+                                             int j0, int jn, const T (*vs)[NR],
+                                             T (&acc)[16][NR]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll 2
+    for (int ib = i0; ib < i1; ib += 64) {
+        const int i = ib + lane;
+        const bool ok = i < i1;
+        T v[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) v[r] = ok ? vs[i - i0][r] : T(0);
+        T m[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) m[k] = ldz(M, int64_t(j0 + k) * ld + i, ok && j0 + k < jn);
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[k][r] += m[k] * v[r];
+    }
+}
+
+// The lanes' column sums meet in a fixed butterfly; lane k (k < 16) returns
+// column k's sums (lane 0's rounding), the others garbage.
+template <typename T, int NR>
+__device__ __forceinline__ void wave_colsums_finish(T (&acc)[16][NR], T (&out)[NR]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            T a = acc[k][r];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+            a = seg_bcast<64>(a, 0);
+            if (lane == k) out[r] = a;
+        }
+}
+
+// Forward, y = X v1: workgroup (row block R, supernode, matrix); lane = row
+// 64 R + lane, the four waves take every fourth column j < 64 (R + 1)
+// (X_RJ, J <= R) and their partial sums are added in wave order.
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(256) void k_fx_y(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
+    const int64_t *__restrict__ xoff, const T *__restrict__ X, int64_t xsize,
+    T *__restrict__ Ys, const T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    const int32_t *__restrict__ active) {
+    __shared__ T vs[kXMaxW][NR];
+    __shared__ T red[3][64][NR];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const int s = list[blockIdx.y];
+    const SnDesc d = sn[s];
+    const int w = d.w, i0 = 64 * int(blockIdx.x);
+    if (i0 >= w) return;
+    const int jend = min(w, i0 + 64);
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    for (int j = tid; j < jend; j += 256)
+#pragma unroll
+        for (int r = 0; r < NR; r++) vs[j][r] = FV[vix<SOA>(b, d.rowptr + j, r0 + r, fvsize, nrhs)];
+    __syncthreads();
+    const int i = i0 + lane;
+    const bool ok = i < w;
+    const T *Xb = X + int64_t(b) * xsize + xoff[s];
+    T acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[r] = T(0);
+#pragma unroll 8
+    for (int j = wv; j < jend; j += 4) {
+        const T x = ldz(Xb, int64_t(j) * w + i, ok);
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] += x * vs[j][r];
+    }
+    if (wv > 0)
+#pragma unroll
+        for (int r = 0; r < NR; r++) red[wv - 1][lane][r] = acc[r];
+    __syncthreads();
+    if (wv == 0 && ok)
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            Ys[vix<SOA>(b, d.first + i, r0 + r, n, nrhs)] =
+                ((acc[r] + red[0][lane][r]) + red[1][lane][r]) + red[2][lane][r];
+}
+
+// Forward, u = v2 - L21 y into the front vector's rows >= w: workgroup (256
+// rows below the diagonal block, supernode, matrix), lane = row, every
+// column j < w in ascending order.
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(256) void k_fx_u(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
+    const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Ys, T *__restrict__ FV,
+    int64_t n, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
+    __shared__ T ys[kXMaxW][NR];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[list[blockIdx.y]];
+    const int w = d.w, c = d.c, i0 = w + 256 * int(blockIdx.x);
+    if (i0 >= c) return;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < w; j += 256)
+#pragma unroll
+        for (int r = 0; r < NR; r++) ys[j][r] = Ys[vix<SOA>(b, d.first + j, r0 + r, n, nrhs)];
+    __syncthreads();
+    const int i = i0 + tid;
+    if (i >= c) return;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    T acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[r] = T(0);
+#pragma unroll 8
+    for (int j = 0; j < w; j++) {
+        const T l = Lb[int64_t(j) * c + i];
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] += l * ys[j][r];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        const int64_t q = vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs);
+        FV[q] = FV[q] - acc[r];
+    }
+}
+
+// Backward, rhs = y - L21^T x2 into the front vector's rows < w: workgroup
+// (column block C, supernode, matrix), wave wv takes columns 64 C + 16 wv
+// .. + 15; x2 (read through the supernode's row list) is staged in LDS
+// kXChunk rows at a time.
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(256) void k_bx_t(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
+    const int32_t *__restrict__ rows, const T *__restrict__ L, int64_t Lsize,
+    const T *__restrict__ Ys, T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    const int32_t *__restrict__ active) {
+    __shared__ T xs[kXChunk][NR];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const SnDesc d = sn[list[blockIdx.y]];
+    const int w = d.w, c = d.c;
+    if (64 * int(blockIdx.x) >= w) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int j0 = 64 * int(blockIdx.x) + 16 * (tid >> 6);
+    const int32_t *R = rows + d.rowptr;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    T acc[16][NR];
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[k][r] = T(0);
+    for (int cb = w; cb < c; cb += kXChunk) {
+        const int ce = min(c, cb + kXChunk);
+        __syncthreads();  // the previous chunk is read
+        for (int i = cb + tid; i < ce; i += 256) {
+            const int ri = R[i];
+#pragma unroll
+            for (int r = 0; r < NR; r++) xs[i - cb][r] = Ys[vix<SOA>(b, ri, r0 + r, n, nrhs)];
+        }
+        __syncthreads();
+        if (j0 < w) wave_colsums<T, NR>(Lb, c, cb, ce, j0, w, xs, acc);
+    }
+    T t[NR];
+    wave_colsums_finish<T, NR>(acc, t);
+    const int j = j0 + lane;
+    if (lane < 16 && j < w)
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const T y = Ys[vix<SOA>(b, d.first + j, r0 + r, n, nrhs)];
+            FV[vix<SOA>(b, d.rowptr + j, r0 + r, fvsize, nrhs)] = y - t[r];
+        }
+}
+
+// Backward, x1 = X^T rhs: workgroup (column block C, supernode, matrix),
+// columns split as in k_bx_t, rows i >= 64 C (X_IC, I >= C) with rhs staged
+// in LDS.
+template <typename T, int NR, bool SOA>
+__global__ __launch_bounds__(256) void k_bx_x(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
+    const int64_t *__restrict__ xoff, const T *__restrict__ X, int64_t xsize,
+    T *__restrict__ Ys, const T *__restrict__ FV, int64_t n, int64_t fvsize, int nrhs,
+    const int32_t *__restrict__ active) {
+    __shared__ T rs[kXChunk][NR];
+    const int b = blockIdx.z;
+    if (active && !active[b]) return;
+    const int s = list[blockIdx.y];
+    const SnDesc d = sn[s];
+    const int w = d.w;
+    const int c0 = 64 * int(blockIdx.x);
+    if (c0 >= w) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int j0 = c0 + 16 * (tid >> 6);
+    const T *Xb = X + int64_t(b) * xsize + xoff[s];
+    T acc[16][NR];
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[k][r] = T(0);
+    for (int cb = c0; cb < w; cb += kXChunk) {
+        const int ce = min(w, cb + kXChunk);
+        __syncthreads();
+        for (int i = cb + tid; i < ce; i += 256)
+#pragma unroll
+            for (int r = 0; r < NR; r++)
+                rs[i - cb][r] = FV[vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs)];
+        __syncthreads();
+        if (j0 < w) wave_colsums<T, NR>(Xb, w, cb, ce, j0, w, rs, acc);
+    }
+    T x[NR];
+    wave_colsums_finish<T, NR>(acc, x);
+    const int j = j0 + lane;
+    if (lane < 16 && j < w)
+#pragma unroll
+        for (int r = 0; r < NR; r++) Ys[vix<SOA>(b, d.first + j, r0 + r, n, nrhs)] = x[r];
+}
+
+// ---------------------------------------------------------------------------
 // Batch-interleaved solves.  A group of 64 matrices shares one wave, lane =
 // matrix: every lane runs the same sequential substitution on its own
 // values, so every load of L or of a vector is 64 consecutive words and no
@@ -1744,25 +1974,23 @@ hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Gather of the front vectors of one level (rows of the supernodes not
-// solved by panels), every right-hand side.
 template <typename T, bool SOA>
-void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
-                   const int32_t *active, hipStream_t st) {
-    if (l.ngrow == 0) return;
+void launch_gather_rows(const int32_t *gq, const int32_t *gy, int32_t nrow, double vw, double ib,
+                        const sc_plan *P, sc_numeric *N, int nrhs, const int32_t *active,
+                        hipStream_t st) {
+    if (nrow == 0) return;
     const DevPlan *D = P->dev;
     const int B = N->batch;
     const int64_t fvsize = int64_t(P->rows.size());
-    N->prof.begin(KK_Gather, 0.0,
-                  (l.vw_gather * double(sizeof(T)) + l.ib_gather) * double(nrhs) * double(B), st);
-    const dim3 g = SOA ? dim3(unsigned((l.ngrow + 3) / 4), unsigned((B + 63) / 64))
-                       : dim3(unsigned((int64_t(l.ngrow) * B + 255) / 256));
+    N->prof.begin(KK_Gather, 0.0, (vw * double(sizeof(T)) + ib) * double(nrhs) * double(B), st);
+    const dim3 g = SOA ? dim3(unsigned((nrow + 3) / 4), unsigned((B + 63) / 64))
+                       : dim3(unsigned((int64_t(nrow) * B + 255) / 256));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
         const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_GATHER(NRV)                                                                     \
-    hipLaunchKernelGGL((k_gather<T, SOA, NRV>), g, dim3(256), 0, st, D->grow_q + l.grow0,          \
-                       D->grow_y + l.grow0, l.ngrow, D->gptr, D->gidx, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n,  \
-                       fvsize, nrhs, r0, B, active)
+    hipLaunchKernelGGL((k_gather<T, SOA, NRV>), g, dim3(256), 0, st, gq, gy, nrow, D->gptr,       \
+                       D->gidx, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs, r0, B,  \
+                       active)
         if (nrr == 1) SPCHOL_GATHER(1);
         else if (nrr == 2) SPCHOL_GATHER(2);
         else if (nrr == 3) SPCHOL_GATHER(3);
@@ -1770,6 +1998,16 @@ void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 #undef SPCHOL_GATHER
     }
     N->prof.end(st);
+}
+
+// Gather of the front vectors of one level (rows of the supernodes not
+// solved by panels), every right-hand side.
+template <typename T, bool SOA>
+void launch_gather(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                   const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    launch_gather_rows<T, SOA>(D->grow_q + l.grow0, D->grow_y + l.grow0, l.ngrow, l.vw_gather,
+                               l.ib_gather, P, N, nrhs, active, st);
 }
 
 // One launch of the segment kernels for row class k.
@@ -2040,6 +2278,76 @@ void sn_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     N->prof.end(st);
 }
 
+// Panel-solved supernodes of a level with whole-block inverses (the level's
+// supernodes are all at most kXMaxW wide and the numeric object holds X).
+template <typename T, bool SOA>
+void x_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+               const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const T *X = static_cast<const T *>(N->xinv);
+    const int B = N->batch;
+    const int64_t fvsize = int64_t(P->rows.size());
+    Profiler &prof = N->prof;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    launch_gather_rows<T, SOA>(D->xg_q + l.xg0, D->xg_y + l.xg0, l.nxg, l.vw_xg, l.ib_xg, P, N,
+                               nrhs, active, st);
+    prof.begin(KK_FwdPanel, 2.0 * l.x_words * nr * nb, l.x_words * sz * nb, st, l.x_lx * sz * nb);
+    const dim3 gy(unsigned((l.maxw_pan + 63) / 64), unsigned(l.npan), unsigned(B));
+    const dim3 gu(unsigned((l.maxc_pan + 255) / 256), unsigned(l.npan), unsigned(B));
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_FX(NRV)                                                                          \
+    do {                                                                                        \
+        hipLaunchKernelGGL((k_fx_y<T, NRV, SOA>), gy, dim3(256), 0, st, D->sn,                   \
+                           D->slv_pan + l.pan0, r0, D->xoff, X, P->xsize, as<T>(N->wsc->y),      \
+                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
+        hipLaunchKernelGGL((k_fx_u<T, NRV, SOA>), gu, dim3(256), 0, st, D->sn,                   \
+                           D->slv_pan + l.pan0, r0, L, P->Lsize, as<T>(N->wsc->y),               \
+                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
+    } while (0)
+        if (nrr == 1) SPCHOL_FX(1);
+        else if (nrr == 2) SPCHOL_FX(2);
+        else if (nrr == 3) SPCHOL_FX(3);
+        else SPCHOL_FX(4);
+#undef SPCHOL_FX
+    }
+    prof.end(st);
+}
+
+template <typename T, bool SOA>
+void x_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const T *L = static_cast<const T *>(N->L);
+    const T *X = static_cast<const T *>(N->xinv);
+    const int B = N->batch;
+    const int64_t fvsize = int64_t(P->rows.size());
+    Profiler &prof = N->prof;
+    const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
+    prof.begin(KK_BwdPanel, 2.0 * l.x_words * nr * nb,
+               (l.x_words * sz + l.vw_pan * sz * nr) * nb, st, l.x_lx * sz * nb);
+    const dim3 g(unsigned((l.maxw_pan + 63) / 64), unsigned(l.npan), unsigned(B));
+    for (int r0 = 0; r0 < nrhs; r0 += 4) {
+        const int nrr = std::min(4, nrhs - r0);
+#define SPCHOL_BX(NRV)                                                                          \
+    do {                                                                                        \
+        hipLaunchKernelGGL((k_bx_t<T, NRV, SOA>), g, dim3(256), 0, st, D->sn,                    \
+                           D->slv_pan + l.pan0, r0, D->rows, L, P->Lsize, as<T>(N->wsc->y),      \
+                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
+        hipLaunchKernelGGL((k_bx_x<T, NRV, SOA>), g, dim3(256), 0, st, D->sn,                    \
+                           D->slv_pan + l.pan0, r0, D->xoff, X, P->xsize, as<T>(N->wsc->y),      \
+                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
+    } while (0)
+        if (nrr == 1) SPCHOL_BX(1);
+        else if (nrr == 2) SPCHOL_BX(2);
+        else if (nrr == 3) SPCHOL_BX(3);
+        else SPCHOL_BX(4);
+#undef SPCHOL_BX
+    }
+    prof.end(st);
+}
+
 // Batch-interleaved solve (groups of 64 matrices, lane = matrix).
 template <typename T>
 hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double *b,
@@ -2144,7 +2452,8 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             prof.end(st);
         }
         if (l.npan > 0) {
-            if (sn_fits<T>(l, N, nrhs)) sn_forward<T, true>(l, P, N, nrhs, nullptr, st);
+            if (N->xinv && l.xpan) x_forward<T, true>(l, P, N, nrhs, nullptr, st);
+            else if (sn_fits<T>(l, N, nrhs)) sn_forward<T, true>(l, P, N, nrhs, nullptr, st);
             else panels_forward<T, true>(l, P, N, nrhs, nullptr, st);
         }
     }
@@ -2170,7 +2479,8 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             continue;
         }
         if (l.npan > 0) {
-            if (sn_fits<T>(l, N, nrhs)) sn_backward<T, true>(l, P, N, nrhs, nullptr, st);
+            if (N->xinv && l.xpan) x_backward<T, true>(l, P, N, nrhs, nullptr, st);
+            else if (sn_fits<T>(l, N, nrhs)) sn_backward<T, true>(l, P, N, nrhs, nullptr, st);
             else panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
         }
         if (by_rows(l)) {
@@ -2234,7 +2544,8 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
         launch_gather<T, false>(l, P, N, nrhs, active, st);
         classes_forward<T, false>(l, P, N, nrhs, active, st);
         if (l.npan > 0) {
-            if (sn_fits<T>(l, N, nrhs)) sn_forward<T, false>(l, P, N, nrhs, active, st);
+            if (N->xinv && l.xpan) x_forward<T, false>(l, P, N, nrhs, active, st);
+            else if (sn_fits<T>(l, N, nrhs)) sn_forward<T, false>(l, P, N, nrhs, active, st);
             else panels_forward<T, false>(l, P, N, nrhs, active, st);
         }
     }
@@ -2242,7 +2553,8 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
         if (l.npan > 0) {
-            if (sn_fits<T>(l, N, nrhs)) sn_backward<T, false>(l, P, N, nrhs, active, st);
+            if (N->xinv && l.xpan) x_backward<T, false>(l, P, N, nrhs, active, st);
+            else if (sn_fits<T>(l, N, nrhs)) sn_backward<T, false>(l, P, N, nrhs, active, st);
             else panels_backward<T, false>(l, P, N, nrhs, active, st);
         }
         classes_backward<T, false>(l, P, N, nrhs, active, st);
@@ -2325,10 +2637,21 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
         s.pan0 = P->slv_pan_ptr[l];
         s.npan = P->slv_pan_ptr[l + 1] - s.pan0;
         s.maxc_pan = P->slv_pan_maxc[l];
+        s.maxw_pan = P->slv_pan_maxw[l];
+        s.xpan = P->slv_pan_x[l] != 0;
+        s.xg0 = P->xg_ptr[l];
+        s.nxg = P->xg_ptr[l + 1] - s.xg0;
+        for (int32_t q = s.xg0; q < s.xg0 + s.nxg; q++) {
+            const int32_t row = P->xg_q[q];
+            s.vw_xg += 1.0 + (P->xg_y[q] >= 0 ? 1.0 : 0.0) + double(P->gptr[row + 1] - P->gptr[row]);
+            s.ib_xg += 12.0 + 4.0 * double(P->gptr[row + 1] - P->gptr[row]);
+        }
         for (int32_t e = s.pan0; e < s.pan0 + s.npan; e++) {
             const SnDesc &d = P->sn[P->slv_pan[e]];
             s.vw_pan += 2.0 * d.c;
             s.ib_pan += 4.0 * d.c;
+            s.x_words += double(d.w) * (d.w + 1) / 2 + double(d.c - d.w) * d.w;
+            s.x_lx += l_exact(d, 0, d.w);
         }
         const int np = (P->slv_pan_maxw[l] + kP - 1) / kP;
         for (int q = 0; q < np; q++) {

@@ -398,7 +398,8 @@ def test_panel_workgroup_path_bitwise_equal(dtype, soa):
     with one workgroup per (supernode, matrix); smaller batches use one
     launch per panel over many workgroups.  Both perform the same operations
     in the same order, so matrices 0..14 of a 16-matrix batch solve to the
-    same bits as the same 15 matrices alone."""
+    same bits as the same 15 matrices alone (whole-block inverses off: they
+    apply to batches of 16 or more only)."""
     import dataclasses
     import paper_2110_12865_amd as S
     w16 = W.small_grid((24, 22, 20), "nd", batch=16, nrhs=5, seed=53)
@@ -411,8 +412,8 @@ def test_panel_workgroup_path_bitwise_equal(dtype, soa):
     log("case grid 24x22x20 %s soa=%d: %d panel supernodes (max w %d, max c %d)"
         % (dtype, soa, npan, wd.max(), c.max()))
     assert npan > 0
-    x16 = _solve_with(w16, dtype, soa_min_batch=soa)
-    x15 = _solve_with(w15, dtype, soa_min_batch=soa)
+    x16 = _solve_with(w16, dtype, soa_min_batch=soa, panel_inverse=-1)
+    x15 = _solve_with(w15, dtype, soa_min_batch=soa, panel_inverse=-1)
     assert np.array_equal(x16[:15], x15)
     if dtype == "f64":
         sym = oracle.symbolic(p.n, p.colptr, p.rowind, w16.perm)
@@ -420,6 +421,51 @@ def test_panel_workgroup_path_bitwise_equal(dtype, soa):
         xo = oracle.solve(sym, Lx, w16.b[15])
         for r in range(w16.nrhs):
             assert oracle.forward_error(x16[15, r], xo[r]) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,make", [
+    ("grid3d_24x22x20_nd", lambda: W.small_grid((24, 22, 20), "nd", batch=16, nrhs=5, seed=56)),
+    ("trimesh_128", lambda: W.trimesh_workload(128, batch=20, nrhs=3, seed=57)),
+], ids=["grid3d", "trimesh"])
+def test_panel_inverse_solve(name, make, dtype):
+    """Batches of 16 or more may solve the panel-solved supernodes with the
+    whole-block inverse X = L11^{-1} of each diagonal block (formed after the
+    factorization): y = X v1, u = v2 - L21 y forward, x1 = X^T (y - L21^T x2)
+    backward.  The result agrees with panel-by-panel substitution to the
+    precision of the factor (not bit for bit), the FP64 result matches the
+    oracle, and the interleaved and row-major layouts give the same bits."""
+    import paper_2110_12865_amd as S
+    w = make()
+    p = w.pattern
+    plan = S.analyze(p.colptr, p.rowind, w.perm)
+    first, parent, level, rowptr, rows = plan.export_supernodes()
+    wd, c = np.diff(first), np.diff(rowptr)
+    pan = (wd > 64) | (c > 512)
+    log("case %s %s batch=%d: %d panel supernodes (max w %d)" % (name, dtype, w.batch,
+        int(pan.sum()), int(wd[pan].max()) if pan.any() else 0))
+    assert pan.any() and wd[pan].max() <= 1024
+    x_sub = _solve_with(w, dtype, soa_min_batch=-1, panel_inverse=-1)
+    x_inv = _solve_with(w, dtype, soa_min_batch=-1, panel_inverse=1)
+    x_soa = _solve_with(w, dtype, soa_min_batch=16, panel_inverse=1)
+    assert np.array_equal(x_soa, x_inv)
+    assert not np.array_equal(x_inv, x_sub)  # the inverse path was taken
+    sym = oracle.symbolic(p.n, p.colptr, p.rowind, w.perm)
+    for s in (0, w.batch - 1):
+        Lx, info = oracle.factor(p.n, p.colptr, p.rowind, w.values[s], sym)
+        xo = oracle.solve(sym, Lx, w.b[s])
+        kap = oracle.kappa1_estimate(p.n, p.colptr, p.rowind, w.values[s], sym, Lx)
+        for r in range(w.nrhs):
+            e_inv = oracle.forward_error(x_inv[s, r], xo[r])
+            e_sub = oracle.forward_error(x_sub[s, r], xo[r])
+            log("  set %d rhs %d: x err %.2e (substitution %.2e, kappa_1 ~ %.2e)"
+                % (s, r, e_inv, e_sub, kap))
+            if dtype == "f64":
+                assert oracle.within_conditioning(e_inv, 1e-10, kap)
+            else:
+                # FP32 factor and solve: both paths within the FP32 bound
+                assert e_inv <= max(1e-4, 10.0 * kap * 2.0 ** -24)
+                assert e_inv <= 10.0 * max(e_sub, 1e-6)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
