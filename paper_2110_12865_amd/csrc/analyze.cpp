@@ -576,6 +576,20 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             }
             P->xg_ptr[l + 1] = int32_t(P->xg_q.size());
         }
+        P->slv_small_x.assign(nlev, 0);
+        for (int32_t l = 0; l < nlev && opt.panel_inverse >= 0; l++) {
+            const int32_t e0 = P->slv_cls_ptr[size_t(l) * kSolveClasses];
+            const int32_t e1 = P->slv_cls_ptr[size_t(l + 1) * kSolveClasses];
+            if (e0 == e1 || e1 - e0 > kXSmallMax) continue;
+            P->slv_small_x[l] = 1;
+            for (int32_t e = e0; e < e1; e++) {
+                const int32_t s = P->slv_small[e];
+                const int64_t w = P->sn[s].w;
+                P->xoff[s] = P->xsize;
+                P->xsize += w * w;
+                P->xs_list.push_back(s);
+            }
+        }
         // widest first: the longest chains of the inversion start first
         std::stable_sort(P->x_list.begin(), P->x_list.end(),
                          [&](int32_t a, int32_t b) { return P->sn[a].w > P->sn[b].w; });

@@ -55,7 +55,8 @@ void free_devplan(DevPlan *D) {
                     D->asm_col, D->csr_ptr, D->sell_ptr, D->sell_col, D->sell_vidx,
                     D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr,
                     D->gidx, D->dinv_list, D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
-                    D->val_row, D->val_col, D->xoff, D->x_list, D->xg_q, D->xg_y};
+                    D->val_row, D->val_col, D->xoff, D->x_list, D->xg_q, D->xg_y,
+                    D->xs_list};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int32_t *p : D->fz_ptr)
@@ -103,6 +104,7 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->x_list, P->x_list);
     if (e == hipSuccess) e = upload(&D->xg_q, P->xg_q);
     if (e == hipSuccess) e = upload(&D->xg_y, P->xg_y);
+    if (e == hipSuccess) e = upload(&D->xs_list, P->xs_list);
     if (e == hipSuccess) e = upload(&D->csr_ptr, P->csr_ptr);
     if (e == hipSuccess) e = upload(&D->sell_ptr, P->sell_ptr);
     if (e == hipSuccess) e = upload(&D->sell_col, P->sell_col);

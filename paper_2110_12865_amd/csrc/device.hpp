@@ -79,6 +79,10 @@ struct SLaunch {  // one level of a triangular solve
     double x_words = 0.0, x_lx = 0.0;  // X and L21 scalars read per sweep; exact L entries
     int32_t xg0 = 0, nxg = 0;          // their front rows in xg_q / xg_y
     double vw_xg = 0.0, ib_xg = 0.0;
+    // the supernodes outside the panel kernels have whole-block inverses
+    bool xsmall = false;
+    int32_t maxw_small = 0, maxc_small = 0;
+    double xs_words = 0.0, xs_lx = 0.0;
     double vw_pan = 0.0, ib_pan = 0.0;
     std::vector<SPanel> panels;
 };
@@ -105,6 +109,7 @@ struct DevPlan {
     int32_t *x_list = nullptr;        // supernodes that have one
     int32_t *xg_q = nullptr;          // their front rows (forward gather)
     int32_t *xg_y = nullptr;
+    int32_t *xs_list = nullptr;       // small supernodes with whole-block inverses
     int64_t *csr_ptr = nullptr;       // A (both triangles) by rows, for A x
     int64_t *sell_ptr = nullptr;      // the same rows sliced by kSellRows
     int32_t *sell_col = nullptr;

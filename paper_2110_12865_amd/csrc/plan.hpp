@@ -91,8 +91,12 @@ constexpr int kSellRows = 64;  // rows per slice of the sliced row structure of 
 // supernodes (sc_options::panel_inverse): levels whose panel-solved
 // supernodes are all at most kXMaxW columns wide, for numeric objects of at
 // least kXMinBatch matrices (the batched solves that use them).
+// Levels with at most kXSmallMax supernodes outside the panel kernels (the
+// top levels, where one wave per supernode and matrix leaves the chip idle)
+// get whole-block inverses of those supernodes' diagonal blocks as well.
 constexpr int kXMaxW = 1024;
 constexpr int kXMinBatch = 16;
+constexpr int kXSmallMax = 96;
 
 // Fronts of 64 < c rows factored by one workgroup keep their packed lower
 // triangle and the 64-row tiles of L21 ([k][64], k padded to 4) in LDS;
@@ -212,6 +216,10 @@ struct sc_plan {
     std::vector<int32_t> x_list;
     std::vector<uint8_t> slv_pan_x;
     std::vector<int32_t> xg_ptr, xg_q, xg_y;
+    // the other supernodes (at most 64 wide) of the levels with at most
+    // kXSmallMax of them: their inverses, and per level whether it has them
+    std::vector<int32_t> xs_list;
+    std::vector<uint8_t> slv_small_x;
     int32_t x_nbmax = 0;  // most 64-column blocks of one X
     int32_t npan = 0;        // supernodes solved by panels
     std::vector<int64_t> lvl_bigcols;     // sum of c over big fronts

@@ -136,6 +136,43 @@ __global__ __launch_bounds__(64) void k_dinv(
     for (int col = 0; col < kP; col++) D[col * kP + lane] = T(Lp[col * (kP + 1) + lane]);
 }
 
+// Whole-block inverse X = L11^{-1} of a supernode at most 64 wide (one wave
+// per (matrix, supernode)): the same substitution as k_dinv, in FP64 with
+// one lane per column of X, stored column-major with leading dimension w.
+template <typename T>
+__global__ __launch_bounds__(64) void k_xsmall(
+    const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
+    const int64_t *__restrict__ xoff, const T *__restrict__ L, int64_t Lsize,
+    T *__restrict__ X, int64_t xsize) {
+    __shared__ double Lp[kP * (kP + 1)];  // [i][t] row-major
+    const int b = blockIdx.x;
+    const int s = list[blockIdx.y];
+    const SnDesc d = sn[s];
+    const int w = d.w, c = d.c;
+    const T *Lb = L + int64_t(b) * Lsize + d.loff;
+    const int lane = threadIdx.x;
+#pragma unroll 8
+    for (int t = 0; t < kP; t++)
+        Lp[lane * (kP + 1) + t] =
+            (lane < w && t < w) ? double(Lb[int64_t(t) * c + lane]) : (lane == t ? 1.0 : 0.0);
+    __syncthreads();
+    double x[kP];
+#pragma unroll
+    for (int i = 0; i < kP; i++) {
+        double sum = lane == i ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < i; t++) sum -= Lp[i * (kP + 1) + t] * x[t];
+        x[i] = sum / Lp[i * (kP + 1) + i];
+    }
+    __syncthreads();  // every read of Lp above precedes the transpose below
+#pragma unroll
+    for (int i = 0; i < kP; i++) Lp[lane * (kP + 1) + i] = x[i];  // Lp[col][i] = X[i][col]
+    __syncthreads();
+    T *Xb = X + int64_t(b) * xsize + xoff[s];
+    if (lane < w)
+        for (int col = 0; col < w; col++) Xb[int64_t(col) * w + lane] = T(Lp[col * (kP + 1) + lane]);
+}
+
 // Position of entry (matrix b, row, right-hand side r) in a solve vector
 // set with `rows` rows per matrix.  Row-major per matrix (rows, then
 // right-hand sides) or, batch-interleaved, groups of 64 matrices with the
@@ -1961,9 +1998,16 @@ T *as(double *p) { return reinterpret_cast<T *>(p); }
 
 template <typename T>
 hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
-    if (P->dinv_list.empty()) return hipSuccess;
     DevPlan *D = P->dev;
     const T *L = static_cast<const T *>(N->L);
+    if (N->xinv && !P->xs_list.empty()) {
+        N->prof.begin(KK_Dinv, 0.0, 0.0, st);
+        hipLaunchKernelGGL(k_xsmall<T>, dim3(unsigned(N->batch), unsigned(P->xs_list.size())),
+                           dim3(64), 0, st, D->sn, D->xs_list, D->xoff, L, P->Lsize,
+                           static_cast<T *>(N->xinv), P->xsize);
+        N->prof.end(st);
+    }
+    if (P->dinv_list.empty()) return hipGetLastError();
     const int64_t maxp = (P->max_width + kP - 1) / kP;
     N->prof.begin(KK_Dinv, 0.0, 0.0, st);
     hipLaunchKernelGGL(k_dinv<T>,
@@ -2278,10 +2322,25 @@ void sn_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     N->prof.end(st);
 }
 
-// Panel-solved supernodes of a level with whole-block inverses (the level's
-// supernodes are all at most kXMaxW wide and the numeric object holds X).
+// Supernodes of a level with whole-block inverses: the panel-solved ones
+// (all at most kXMaxW wide) or the others of a level with few of them; the
+// front vectors are gathered beforehand.  `list` holds cnt supernodes at
+// most maxw wide with at most maxc rows; xw and lx are the scalars of X and
+// L21 read per sweep and the exact entries of L (per matrix).
+struct XSet {
+    const int32_t *list;
+    int32_t cnt, maxw, maxc;
+    double xw, lx;
+};
+inline XSet xset_panels(const SLaunch &l, const DevPlan *D) {
+    return XSet{D->slv_pan + l.pan0, l.npan, l.maxw_pan, l.maxc_pan, l.x_words, l.x_lx};
+}
+inline XSet xset_small(const SLaunch &l, const DevPlan *D) {
+    return XSet{D->slv_small + l.all0, l.nall, l.maxw_small, l.maxc_small, l.xs_words, l.xs_lx};
+}
+
 template <typename T, bool SOA>
-void x_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+void x_forward(const XSet &xs, const sc_plan *P, sc_numeric *N, int nrhs,
                const int32_t *active, hipStream_t st) {
     const DevPlan *D = P->dev;
     const T *L = static_cast<const T *>(N->L);
@@ -2290,21 +2349,19 @@ void x_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const int64_t fvsize = int64_t(P->rows.size());
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
-    launch_gather_rows<T, SOA>(D->xg_q + l.xg0, D->xg_y + l.xg0, l.nxg, l.vw_xg, l.ib_xg, P, N,
-                               nrhs, active, st);
-    prof.begin(KK_FwdPanel, 2.0 * l.x_words * nr * nb, l.x_words * sz * nb, st, l.x_lx * sz * nb);
-    const dim3 gy(unsigned((l.maxw_pan + 63) / 64), unsigned(l.npan), unsigned(B));
-    const dim3 gu(unsigned((l.maxc_pan + 255) / 256), unsigned(l.npan), unsigned(B));
+    prof.begin(KK_FwdPanel, 2.0 * xs.xw * nr * nb, xs.xw * sz * nb, st, xs.lx * sz * nb);
+    const dim3 gy(unsigned((xs.maxw + 63) / 64), unsigned(xs.cnt), unsigned(B));
+    const dim3 gu(unsigned((xs.maxc + 255) / 256), unsigned(xs.cnt), unsigned(B));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
         const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_FX(NRV)                                                                          \
     do {                                                                                        \
-        hipLaunchKernelGGL((k_fx_y<T, NRV, SOA>), gy, dim3(256), 0, st, D->sn,                   \
-                           D->slv_pan + l.pan0, r0, D->xoff, X, P->xsize, as<T>(N->wsc->y),      \
-                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
-        hipLaunchKernelGGL((k_fx_u<T, NRV, SOA>), gu, dim3(256), 0, st, D->sn,                   \
-                           D->slv_pan + l.pan0, r0, L, P->Lsize, as<T>(N->wsc->y),               \
-                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
+        hipLaunchKernelGGL((k_fx_y<T, NRV, SOA>), gy, dim3(256), 0, st, D->sn, xs.list, r0,      \
+                           D->xoff, X, P->xsize, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n,      \
+                           fvsize, nrhs, active);                                               \
+        hipLaunchKernelGGL((k_fx_u<T, NRV, SOA>), gu, dim3(256), 0, st, D->sn, xs.list, r0, L,   \
+                           P->Lsize, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n, fvsize, nrhs,    \
+                           active);                                                             \
     } while (0)
         if (nrr == 1) SPCHOL_FX(1);
         else if (nrr == 2) SPCHOL_FX(2);
@@ -2316,7 +2373,7 @@ void x_forward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 }
 
 template <typename T, bool SOA>
-void x_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+void x_backward(const XSet &xs, const sc_plan *P, sc_numeric *N, int nrhs,
                 const int32_t *active, hipStream_t st) {
     const DevPlan *D = P->dev;
     const T *L = static_cast<const T *>(N->L);
@@ -2325,19 +2382,18 @@ void x_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
     const int64_t fvsize = int64_t(P->rows.size());
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
-    prof.begin(KK_BwdPanel, 2.0 * l.x_words * nr * nb,
-               (l.x_words * sz + l.vw_pan * sz * nr) * nb, st, l.x_lx * sz * nb);
-    const dim3 g(unsigned((l.maxw_pan + 63) / 64), unsigned(l.npan), unsigned(B));
+    prof.begin(KK_BwdPanel, 2.0 * xs.xw * nr * nb, xs.xw * sz * nb, st, xs.lx * sz * nb);
+    const dim3 g(unsigned((xs.maxw + 63) / 64), unsigned(xs.cnt), unsigned(B));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
         const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_BX(NRV)                                                                          \
     do {                                                                                        \
-        hipLaunchKernelGGL((k_bx_t<T, NRV, SOA>), g, dim3(256), 0, st, D->sn,                    \
-                           D->slv_pan + l.pan0, r0, D->rows, L, P->Lsize, as<T>(N->wsc->y),      \
-                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
-        hipLaunchKernelGGL((k_bx_x<T, NRV, SOA>), g, dim3(256), 0, st, D->sn,                    \
-                           D->slv_pan + l.pan0, r0, D->xoff, X, P->xsize, as<T>(N->wsc->y),      \
-                           as<T>(N->wsc->u), P->n, fvsize, nrhs, active);                       \
+        hipLaunchKernelGGL((k_bx_t<T, NRV, SOA>), g, dim3(256), 0, st, D->sn, xs.list, r0,       \
+                           D->rows, L, P->Lsize, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n,      \
+                           fvsize, nrhs, active);                                               \
+        hipLaunchKernelGGL((k_bx_x<T, NRV, SOA>), g, dim3(256), 0, st, D->sn, xs.list, r0,       \
+                           D->xoff, X, P->xsize, as<T>(N->wsc->y), as<T>(N->wsc->u), P->n,      \
+                           fvsize, nrhs, active);                                               \
     } while (0)
         if (nrr == 1) SPCHOL_BX(1);
         else if (nrr == 2) SPCHOL_BX(2);
@@ -2346,6 +2402,17 @@ void x_backward(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
 #undef SPCHOL_BX
     }
     prof.end(st);
+}
+
+// Panel-solved supernodes of a level with whole-block inverses: the gather
+// of their front vectors, then the products.
+template <typename T, bool SOA>
+void x_forward_panels(const SLaunch &l, const sc_plan *P, sc_numeric *N, int nrhs,
+                      const int32_t *active, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    launch_gather_rows<T, SOA>(D->xg_q + l.xg0, D->xg_y + l.xg0, l.nxg, l.vw_xg, l.ib_xg, P, N,
+                               nrhs, active, st);
+    x_forward<T, SOA>(xset_panels(l, D), P, N, nrhs, active, st);
 }
 
 // Batch-interleaved solve (groups of 64 matrices, lane = matrix).
@@ -2385,7 +2452,9 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     if (fmin > 0)
         for (int32_t k = 0; k < int32_t(D->fz_roots.size()); k++) {
             const SLaunch &l = D->ssched[k];
-            if (by_rows(l) || l.npan > 0 || int64_t(D->fz_roots[k]) * G < fmin) break;
+            if (by_rows(l) || l.npan > 0 || (N->xinv && l.xsmall) ||
+                int64_t(D->fz_roots[k]) * G < fmin)
+                break;
             K = k;
         }
     // algorithmic work of the fused launches (the levels they cover)
@@ -2417,7 +2486,10 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     for (const SLaunch &l : D->ssched) {
         if (l.level <= K) continue;  // in the subtrees above
         launch_gather<T, true>(l, P, N, nrhs, nullptr, st);
-        if (by_rows(l)) {
+        const bool xsm = N->xinv && l.xsmall;
+        if (xsm) {
+            x_forward<T, true>(xset_small(l, D), P, N, nrhs, nullptr, st);
+        } else if (by_rows(l)) {
             classes_forward<T, true>(l, P, N, nrhs, nullptr, st);
         } else if (l.nall > 0) {
             prof.begin(KK_Fwd, l.f_diag * nr * nb, (l.w_diag * sz + (l.vw_diag * sz + l.ib_diag) * nr) * nb, st, l.lx_diag * sz * nb);
@@ -2435,7 +2507,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             }
             prof.end(st);
         }
-        if (l.nit > 0 && !by_rows(l)) {
+        if (l.nit > 0 && !by_rows(l) && !xsm) {
             prof.begin(KK_FwdRows, l.f_rows * nr * nb, (l.w_rows * sz + (l.vw_rows * sz + l.ib_rows) * nr) * nb, st, l.lx_rows * sz * nb);
             for (int r0 = 0; r0 < nrhs; r0 += 4) {
                 const int nrr = std::min(4, nrhs - r0);
@@ -2452,7 +2524,7 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             prof.end(st);
         }
         if (l.npan > 0) {
-            if (N->xinv && l.xpan) x_forward<T, true>(l, P, N, nrhs, nullptr, st);
+            if (N->xinv && l.xpan) x_forward_panels<T, true>(l, P, N, nrhs, nullptr, st);
             else if (sn_fits<T>(l, N, nrhs)) sn_forward<T, true>(l, P, N, nrhs, nullptr, st);
             else panels_forward<T, true>(l, P, N, nrhs, nullptr, st);
         }
@@ -2479,9 +2551,13 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
             continue;
         }
         if (l.npan > 0) {
-            if (N->xinv && l.xpan) x_backward<T, true>(l, P, N, nrhs, nullptr, st);
+            if (N->xinv && l.xpan) x_backward<T, true>(xset_panels(l, D), P, N, nrhs, nullptr, st);
             else if (sn_fits<T>(l, N, nrhs)) sn_backward<T, true>(l, P, N, nrhs, nullptr, st);
             else panels_backward<T, true>(l, P, N, nrhs, nullptr, st);
+        }
+        if (N->xinv && l.xsmall) {
+            x_backward<T, true>(xset_small(l, D), P, N, nrhs, nullptr, st);
+            continue;
         }
         if (by_rows(l)) {
             classes_backward<T, true>(l, P, N, nrhs, nullptr, st);
@@ -2542,9 +2618,10 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
     // forward: levels ascending
     for (const SLaunch &l : D->ssched) {
         launch_gather<T, false>(l, P, N, nrhs, active, st);
-        classes_forward<T, false>(l, P, N, nrhs, active, st);
+        if (N->xinv && l.xsmall) x_forward<T, false>(xset_small(l, D), P, N, nrhs, active, st);
+        else classes_forward<T, false>(l, P, N, nrhs, active, st);
         if (l.npan > 0) {
-            if (N->xinv && l.xpan) x_forward<T, false>(l, P, N, nrhs, active, st);
+            if (N->xinv && l.xpan) x_forward_panels<T, false>(l, P, N, nrhs, active, st);
             else if (sn_fits<T>(l, N, nrhs)) sn_forward<T, false>(l, P, N, nrhs, active, st);
             else panels_forward<T, false>(l, P, N, nrhs, active, st);
         }
@@ -2553,11 +2630,12 @@ hipError_t solve_impl(const sc_plan *P, sc_numeric *N, const double *bin, double
     for (auto it = D->ssched.rbegin(); it != D->ssched.rend(); ++it) {
         const SLaunch &l = *it;
         if (l.npan > 0) {
-            if (N->xinv && l.xpan) x_backward<T, false>(l, P, N, nrhs, active, st);
+            if (N->xinv && l.xpan) x_backward<T, false>(xset_panels(l, D), P, N, nrhs, active, st);
             else if (sn_fits<T>(l, N, nrhs)) sn_backward<T, false>(l, P, N, nrhs, active, st);
             else panels_backward<T, false>(l, P, N, nrhs, active, st);
         }
-        classes_backward<T, false>(l, P, N, nrhs, active, st);
+        if (N->xinv && l.xsmall) x_backward<T, false>(xset_small(l, D), P, N, nrhs, active, st);
+        else classes_backward<T, false>(l, P, N, nrhs, active, st);
     }
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
     hipLaunchKernelGGL(k_perm_out<T>, pgrid, dim3(256), 0, st, D->pinv, as<T>(N->wsc->y), b, ldb, P->n, nrhs,
@@ -2639,6 +2717,14 @@ void spchol_build_solve_schedule(const sc_plan *P, DevPlan *D) {
         s.maxc_pan = P->slv_pan_maxc[l];
         s.maxw_pan = P->slv_pan_maxw[l];
         s.xpan = P->slv_pan_x[l] != 0;
+        s.xsmall = P->slv_small_x[l] != 0;
+        for (int32_t e = s.all0; s.xsmall && e < s.all0 + s.nall; e++) {
+            const SnDesc &d = P->sn[P->slv_small[e]];
+            s.maxw_small = std::max(s.maxw_small, d.w);
+            s.maxc_small = std::max(s.maxc_small, d.c);
+            s.xs_words += double(d.w) * (d.w + 1) / 2 + double(d.c - d.w) * d.w;
+            s.xs_lx += l_exact(d, 0, d.w);
+        }
         s.xg0 = P->xg_ptr[l];
         s.nxg = P->xg_ptr[l + 1] - s.xg0;
         for (int32_t q = s.xg0; q < s.xg0 + s.nxg; q++) {
