@@ -113,10 +113,16 @@ __global__ __launch_bounds__(64) void k_dinv(
     const int c = d.c;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
     const int lane = threadIdx.x;
-#pragma unroll 8
+    // every load in flight at once: unconditional, at a clamped address
+    T lv[kP];
+#pragma unroll
+    for (int t = 0; t < kP; t++) {
+        const bool ok = lane < kb && t < kb;
+        lv[t] = Lb[ok ? int64_t(c0 + t) * c + c0 + lane : 0];
+    }
+#pragma unroll
     for (int t = 0; t < kP; t++)
-        Lp[lane * (kP + 1) + t] =
-            (lane < kb && t < kb) ? double(Lb[int64_t(c0 + t) * c + c0 + lane]) : (lane == t ? 1.0 : 0.0);
+        Lp[lane * (kP + 1) + t] = (lane < kb && t < kb) ? double(lv[t]) : (lane == t ? 1.0 : 0.0);
     __syncthreads();
     double x[kP];
 #pragma unroll
@@ -137,40 +143,54 @@ __global__ __launch_bounds__(64) void k_dinv(
 }
 
 // Whole-block inverse X = L11^{-1} of a supernode at most 64 wide (one wave
-// per (matrix, supernode)): the same substitution as k_dinv, in FP64 with
-// one lane per column of X, stored column-major with leading dimension w.
+// per (matrix, supernode)), in the factor's precision with one lane per
+// column of X (LDS and registers then allow nine waves per CU in FP32):
+// column by column, x_i = b_i / L_ii and then b_t -= L_ti x_i for every
+// later row t (independent updates, no serial sum chain); the reciprocals
+// of the diagonal come first, one per lane.  Stored column-major with
+// leading dimension w.
 template <typename T>
 __global__ __launch_bounds__(64) void k_xsmall(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list,
     const int64_t *__restrict__ xoff, const T *__restrict__ L, int64_t Lsize,
     T *__restrict__ X, int64_t xsize) {
-    __shared__ double Lp[kP * (kP + 1)];  // [i][t] row-major
+    __shared__ T Lc[kP * (kP + 1)];  // [t][i] = L[i][t]: column t of L11 at Lc + t (kP + 1)
+    __shared__ T rv[kP];
     const int b = blockIdx.x;
     const int s = list[blockIdx.y];
     const SnDesc d = sn[s];
     const int w = d.w, c = d.c;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
     const int lane = threadIdx.x;
-#pragma unroll 8
+    // every load in flight at once: unconditional, at a clamped address
+    T lv[kP];
+#pragma unroll
+    for (int t = 0; t < kP; t++) {
+        const bool ok = lane < w && t < w;
+        lv[t] = Lb[ok ? int64_t(t) * c + lane : 0];
+    }
+#pragma unroll
     for (int t = 0; t < kP; t++)
-        Lp[lane * (kP + 1) + t] =
-            (lane < w && t < w) ? double(Lb[int64_t(t) * c + lane]) : (lane == t ? 1.0 : 0.0);
+        Lc[t * (kP + 1) + lane] = (lane < w && t < w) ? lv[t] : (lane == t ? T(1) : T(0));
     __syncthreads();
-    double x[kP];
+    rv[lane] = T(1) / Lc[lane * (kP + 1) + lane];
+    __syncthreads();
+    T x[kP];  // column `lane` of X; starts as column `lane` of the identity
+#pragma unroll
+    for (int i = 0; i < kP; i++) x[i] = lane == i ? T(1) : T(0);
 #pragma unroll
     for (int i = 0; i < kP; i++) {
-        double sum = lane == i ? 1.0 : 0.0;
+        x[i] *= rv[i];
 #pragma unroll
-        for (int t = 0; t < i; t++) sum -= Lp[i * (kP + 1) + t] * x[t];
-        x[i] = sum / Lp[i * (kP + 1) + i];
+        for (int t = i + 1; t < kP; t++) x[t] -= Lc[i * (kP + 1) + t] * x[i];
     }
-    __syncthreads();  // every read of Lp above precedes the transpose below
+    __syncthreads();  // every read of Lc above precedes the transpose below
 #pragma unroll
-    for (int i = 0; i < kP; i++) Lp[lane * (kP + 1) + i] = x[i];  // Lp[col][i] = X[i][col]
+    for (int i = 0; i < kP; i++) Lc[lane * (kP + 1) + i] = x[i];  // Lc[col][i] = X[i][col]
     __syncthreads();
     T *Xb = X + int64_t(b) * xsize + xoff[s];
     if (lane < w)
-        for (int col = 0; col < w; col++) Xb[int64_t(col) * w + lane] = T(Lp[col * (kP + 1) + lane]);
+        for (int col = 0; col < w; col++) Xb[int64_t(col) * w + lane] = Lc[col * (kP + 1) + lane];
 }
 
 // Position of entry (matrix b, row, right-hand side r) in a solve vector
