@@ -25,15 +25,32 @@ namespace {
 // The values of A in the order of its sliced row structure (both
 // triangles), one copy per matrix: vc[b * nsell + e] = values[b][vidx[e]]
 // (0 for padding).  Made once per refinement call so that every later
-// product reads A contiguously.
+// product reads A contiguously.  A thread takes entry e of kGatherMats
+// consecutive matrices, so the shared index is read once for all of them.
+constexpr int kGatherMats = 8;
 __global__ __launch_bounds__(256) void k_gather_rows(
     const int64_t *__restrict__ vidx, const double *__restrict__ vals, int64_t ldv,
-    int64_t nsell, double *__restrict__ vc) {
-    const int b = blockIdx.y;
+    int64_t nsell, int batch, double *__restrict__ vc) {
+    const int b0 = blockIdx.y * kGatherMats;
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= nsell) return;
     const int64_t v = vidx[e];
-    vc[int64_t(b) * nsell + e] = v >= 0 ? vals[int64_t(b) * ldv + v] : 0.0;
+    const int nb = min(kGatherMats, batch - b0);
+    double a[kGatherMats];
+#pragma unroll
+    for (int k = 0; k < kGatherMats; k++)
+        a[k] = (v >= 0 && k < nb) ? vals[int64_t(b0 + k) * ldv + (v >= 0 ? v : 0)] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kGatherMats; k++)
+        if (k < nb) vc[int64_t(b0 + k) * nsell + e] = a[k];
+}
+
+// Sum of v over the 64 lanes of a wave, by a fixed butterfly; lane 0's
+// result is the one used (other lanes may round differently).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 // Y = B - A X (mode 1) or Y = A X (mode 0) for every right-hand side of the
@@ -42,19 +59,26 @@ __global__ __launch_bounds__(256) void k_gather_rows(
 // one contiguous load of values and of column indices), all NR right-hand
 // sides of the matrix at once so every value of A is read once per matrix.
 // Workgroups of consecutive matrices cover the same rows, so the shared row
-// structure is reused from cache.
+// structure is reused from cache.  With psum (mode 1, plans of one block),
+// also the workgroup's partial sums of Y.Y, B.B and X.X per right-hand side:
+// psum[((matrix * nrhs + r) * nrb + block of rows) * 3 + {0, 1, 2}], lanes
+// in a fixed butterfly, waves in order.
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply(
     const int64_t *__restrict__ ptr, const int64_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const double *__restrict__ vc, int64_t nsell,
     const double *__restrict__ B, const double *__restrict__ X, double *__restrict__ Y,
-    int64_t ldb, int64_t n, int nrhs, int r0, int mode, const int32_t *__restrict__ active) {
+    int64_t ldb, int64_t n, int nrhs, int r0, int mode, const int32_t *__restrict__ active,
+    double *__restrict__ psum, int nrb) {
+    __shared__ double red[4][NR][3];
     const int b = blockIdx.x;
     if (active && !active[b]) return;
     const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t e0 = sptr[i / kSellRows] + i % kSellRows;
-    const int len = int(ptr[i + 1] - ptr[i]);
+    const bool in = i < n;
+    if (!in && !psum) return;
+    const int64_t ic = in ? i : n - 1;  // rows past n compute row n - 1 and add nothing
+    const int64_t e0 = sptr[ic / kSellRows] + ic % kSellRows;
+    const int len = int(ptr[ic + 1] - ptr[ic]);
     const double *v = vc + int64_t(b) * nsell + e0;
     const int32_t *cl = col + e0;
     const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
@@ -67,17 +91,32 @@ __global__ __launch_bounds__(256) void k_apply(
 #pragma unroll
         for (int r = 0; r < NR; r++) t[r] += a * X[base + r * ldb + j];
     }
+    double y[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++)
-        Y[base + r * ldb + i] = mode ? B[base + r * ldb + i] - t[r] : t[r];
-}
-
-// Sum of v over the 64 lanes of a wave, by a fixed butterfly; lane 0's
-// result is the one used (other lanes may round differently).
-__device__ inline double wave_sum(double v) {
+    for (int r = 0; r < NR; r++) {
+        y[r] = mode ? B[base + r * ldb + ic] - t[r] : t[r];
+        if (in) Y[base + r * ldb + i] = y[r];
+    }
+    if (!psum) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int r = 0; r < NR; r++) {
+        const double bb = B[base + r * ldb + ic], xx = X[base + r * ldb + ic];
+        const double s0 = wave_sum(in ? y[r] * y[r] : 0.0);
+        const double s1 = wave_sum(in ? bb * bb : 0.0);
+        const double s2 = wave_sum(in ? xx * xx : 0.0);
+        if (lane == 0) {
+            red[wv][r][0] = s0;
+            red[wv][r][1] = s1;
+            red[wv][r][2] = s2;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 * NR) {
+        const int r = threadIdx.x / 3, q = threadIdx.x % 3;
+        psum[((int64_t(b) * nrhs + r0 + r) * nrb + blockIdx.y) * 3 + q] =
+            ((red[0][r][q] + red[1][r][q]) + red[2][r][q]) + red[3][r][q];
+    }
 }
 
 // Y1 = B - A X1 and Y2 = A X2 in one pass over A (each sum in the order
@@ -436,7 +475,7 @@ double vec_bytes(const sc_plan *P, double nsys, int nvec) {
 // active matrices, up to four right-hand sides per pass.
 void apply_A(const sc_plan *P, const double *vc, const double *B,
              const double *X, double *Y, int64_t ldb, int batch, int nrhs, int mode,
-             const int32_t *active, hipStream_t st) {
+             const int32_t *active, hipStream_t st, double *psum = nullptr) {
     const DevPlan *D = P->dev;
     const int64_t nsell = P->sell_ptr.back();
     const dim3 grid(unsigned(batch), unsigned((P->n + 255) / 256));
@@ -444,7 +483,8 @@ void apply_A(const sc_plan *P, const double *vc, const double *B,
         const int nr = std::min(4, nrhs - r0);
 #define SPCHOL_APPLY(NR)                                                                   \
     hipLaunchKernelGGL(k_apply<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->sell_ptr,        \
-                       D->sell_col, vc, nsell, B, X, Y, ldb, P->n, nrhs, r0, mode, active)
+                       D->sell_col, vc, nsell, B, X, Y, ldb, P->n, nrhs, r0, mode, active,   \
+                       psum, int(grid.y))
         if (nr == 1) SPCHOL_APPLY(1);
         else if (nr == 2) SPCHOL_APPLY(2);
         else if (nr == 3) SPCHOL_APPLY(3);
@@ -496,23 +536,32 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
     e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr, b);
     if (e != hipSuccess) return e;
     const int64_t nsell = P->sell_ptr.back();
-    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nsell + 255) / 256), unsigned(batch)),
-                       dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, W.vc);
+    hipLaunchKernelGGL(k_gather_rows,
+                       dim3(unsigned((nsell + 255) / 256), unsigned((batch + kGatherMats - 1) / kGatherMats)),
+                       dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, batch, W.vc);
     hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
                        D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
                        W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
+    // plans of one block: the norms of the test come from the residual's own
+    // pass (partial sums per 256-row block)
+    const int nrb = int((n + 255) / 256);
+    const bool fuse = nblk == 1;
     for (int it = 0;; it++) {
         prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
-        apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st);
+        apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st, fuse ? W.part2 : nullptr);
         prof.end(st);
-        prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
-        hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x, it == 0 ? 3 : 4,
-                           ldb, D->blk_col0, nblk, nrhs, W.active, W.conv, W.part);
-        prof.end(st);
-        hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part, kRB, nseg, nrhs, nblk, W.anorm,
-                           tol, it, W.active, W.conv, W.stat);
+        if (!fuse) {
+            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
+            hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x,
+                               it == 0 ? 3 : 4, ldb, D->blk_col0, nblk, nrhs, W.active, W.conv,
+                               W.part);
+            prof.end(st);
+        }
+        hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, fuse ? W.part2 : W.part,
+                           fuse ? nrb : kRB, nseg, nrhs, nblk, W.anorm, tol, it, W.active, W.conv,
+                           W.stat);
         hipLaunchKernelGGL(k_active, dim3(1), dim3(256), 0, st, W.conv, batch, per, W.active,
                            W.count);
         if (sync) {
@@ -564,8 +613,9 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     e = spchol_solve_run(P, N, x, nrhs, ldb, st, nullptr, b);  // x0 = M^{-1} b
     if (e != hipSuccess) return e;
     const int64_t nsell = P->sell_ptr.back();
-    hipLaunchKernelGGL(k_gather_rows, dim3(unsigned((nsell + 255) / 256), unsigned(batch)),
-                       dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, W.vc);
+    hipLaunchKernelGGL(k_gather_rows,
+                       dim3(unsigned((nsell + 255) / 256), unsigned((batch + kGatherMats - 1) / kGatherMats)),
+                       dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, batch, W.vc);
     hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
                        D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
     hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
@@ -584,10 +634,14 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                      fuse ? W.part2 : nullptr, st);
         } else {
             prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
-            apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st);
+            apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st,
+                    nblk == 1 ? W.part2 : nullptr);
         }
         prof.end(st);
-        if (fuse) {
+        if (!pnext && nblk == 1) {  // the test's norms came with the residual
+            hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part2, nrb, nseg, nrhs, nblk,
+                               W.anorm, tol, it, W.active, W.conv, W.stat);
+        } else if (fuse) {
             hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part2, nrb, nseg, nrhs, nblk,
                                W.anorm, tol, it, W.active, W.conv, W.stat);
             hipLaunchKernelGGL(k_sums_final, rgrid, dim3(256), 0, st, W.part2, nrb, 1, nseg, per,
