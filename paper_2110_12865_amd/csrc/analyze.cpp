@@ -602,7 +602,7 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
         P->grow_ptr.assign(nlev + 1, 0);
         P->soa_psize = 0;
         {
-            std::vector<std::pair<int64_t, int64_t>> iv;
+            std::vector<std::pair<int64_t, int64_t>> iv, ivx;
             for (int32_t l = 0; l < nlev; l++) {
                 for (int32_t e = P->slv_cls_ptr[size_t(l) * kSolveClasses];
                      e < P->slv_cls_ptr[size_t(l + 1) * kSolveClasses]; e++) {
@@ -615,6 +615,7 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                         P->soa_psize += d.w;
                     }
                     iv.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
+                    if (!P->slv_small_x[l]) ivx.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
                 }
                 P->soa_it_ptr[l + 1] = int32_t(P->soa_it_s.size());
                 for (int32_t e = P->slv_cls_ptr[size_t(l) * kSolveClasses];
@@ -627,13 +628,20 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                 }
                 P->grow_ptr[l + 1] = int32_t(P->grow_q.size());
             }
-            std::sort(iv.begin(), iv.end());
-            int64_t covered = 0;  // every scalar below this is already covered
-            for (const auto &q : iv) {
-                int64_t k = std::max(q.first, covered);
-                for (; k < q.second; k += kSoaChunk) P->soa_chunks.push_back(k);
-                covered = std::max(covered, k);
-            }
+            // the copy skips the supernodes of levels solved with whole-block
+            // inverses when the numeric object has them (soa_chunks_x)
+            auto chunks = [](std::vector<std::pair<int64_t, int64_t>> &v,
+                             std::vector<int64_t> &out) {
+                std::sort(v.begin(), v.end());
+                int64_t covered = 0;  // every scalar below this is already covered
+                for (const auto &q : v) {
+                    int64_t k = std::max(q.first, covered);
+                    for (; k < q.second; k += kSoaChunk) out.push_back(k);
+                    covered = std::max(covered, k);
+                }
+            };
+            chunks(iv, P->soa_chunks);
+            chunks(ivx, P->soa_chunks_x);
         }
         // forward-solve gather map (children in chlist order)
         P->gptr.assign(P->rows.size() + 1, 0);

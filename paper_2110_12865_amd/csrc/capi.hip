@@ -56,7 +56,7 @@ void free_devplan(DevPlan *D) {
                     D->slv_small, D->slv_pan, D->asm_pc, D->colblk, D->blk_col0, D->gptr,
                     D->gidx, D->dinv_list, D->soa_it_s, D->soa_it_r0, D->soa_chunks, D->grow_q, D->grow_y,
                     D->val_row, D->val_col, D->xoff, D->x_list, D->xg_q, D->xg_y,
-                    D->xs_list};
+                    D->xs_list, D->soa_chunks_x};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int32_t *p : D->fz_ptr)
@@ -115,6 +115,7 @@ sc_status ensure_device(const sc_plan *P) {
     if (e == hipSuccess) e = upload(&D->soa_it_s, P->soa_it_s);
     if (e == hipSuccess) e = upload(&D->soa_it_r0, P->soa_it_r0);
     if (e == hipSuccess) e = upload(&D->soa_chunks, P->soa_chunks);
+    if (e == hipSuccess) e = upload(&D->soa_chunks_x, P->soa_chunks_x);
     if (e == hipSuccess) e = upload(&D->grow_q, P->grow_q);
     if (e == hipSuccess) e = upload(&D->grow_y, P->grow_y);
     if (e == hipSuccess) e = upload(&D->val_row, P->val_row);

@@ -117,6 +117,7 @@ struct DevPlan {
     int32_t *soa_it_s = nullptr;      // batch-interleaved solve items
     int32_t *soa_it_r0 = nullptr;
     int64_t *soa_chunks = nullptr;    // chunk starts of the interleaved L copy
+    int64_t *soa_chunks_x = nullptr;  // the same without the levels with inverses
     int32_t *grow_q = nullptr;        // forward gather rows
     int32_t *grow_y = nullptr;
     int32_t *val_row = nullptr;       // (row, column) of every stored entry

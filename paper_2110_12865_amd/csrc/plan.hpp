@@ -198,7 +198,7 @@ struct sc_plan {
     // below the diagonal block); level l owns [grow_ptr[l], grow_ptr[l+1])
     std::vector<int32_t> grow_ptr, grow_q, grow_y;
     int64_t soa_psize = 0;
-    std::vector<int64_t> soa_chunks;
+    std::vector<int64_t> soa_chunks, soa_chunks_x;
     int64_t dinv_size = 0;   // scalars of inverted diagonal blocks
     // panel-solved supernodes factored as small fronts (their inverted
     // diagonal blocks are formed after the factorization; the tiled factor

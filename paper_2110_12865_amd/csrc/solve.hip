@@ -2447,11 +2447,13 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
     if (!N->ls_ok) {
-        const size_t nch = P->soa_chunks.size();
+        // the levels solved with whole-block inverses read L, not the copy
+        const size_t nch = (N->xinv ? P->soa_chunks_x : P->soa_chunks).size();
         prof.begin(KK_ToSoa, 0.0, 2.0 * sz * nb * double(nch) * kSoaChunk, st);
         if (nch > 0)
             hipLaunchKernelGGL(k_to_soa<T>, dim3(unsigned(nch), G), dim3(256), 0, st,
-                               static_cast<const T *>(N->L), P->Lsize, D->soa_chunks, B,
+                               static_cast<const T *>(N->L), P->Lsize,
+                               N->xinv ? D->soa_chunks_x : D->soa_chunks, B,
                                static_cast<T *>(N->Ls));
         prof.end(st);
         N->ls_ok = true;
