@@ -1564,6 +1564,46 @@ __device__ __forceinline__ void k_fwd_soa_rows_body(
     const Soa<const T> Lb{Ls + (int64_t(bg) * Lsize + d.loff) * 64, lane};
     const Soa<const T> yb{Ys + ((int64_t(bg) * n + d.first) * nrhs + r0) * 64, lane};
     const Soa<T> fb{FV + ((int64_t(bg) * fvsize + d.rowptr) * nrhs + r0) * 64, lane};
+    if (w > JW) {
+        // several column chunks: each row group stays in registers across
+        // the chunks (the same operations in the same order per row as the
+        // chunk-outer loop below, without storing and reloading the front
+        // vector between chunks); y's chunk is reloaded per row group
+        for (int i0 = rb; i0 < re; i0 += RU) {
+            T a[RU][NR];
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) a[u][r] = fb.ldc(int64_t(i0 + u) * nrhs + r, i0 + u < re);
+            for (int j0 = 0; j0 < w; j0 += JW) {
+                const int jn = min(JW, w - j0);
+                T y[JW][NR];
+                T l[RU][JW];
+#pragma unroll
+                for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+                    for (int r = 0; r < NR; r++)
+                        y[jj][r] = yb.ldz(int64_t(j0 + jj) * nrhs + r, jj < jn);
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+#pragma unroll
+                    for (int jj = 0; jj < JW; jj++)
+                        l[u][jj] = Lb.ldc(int64_t(j0 + jj) * c + i0 + u, i0 + u < re && jj < jn);
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+#pragma unroll
+                    for (int jj = 0; jj < JW; jj++)
+#pragma unroll
+                        for (int r = 0; r < NR; r++) a[u][r] -= T(l[u][jj]) * y[jj][r];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+                if (i0 + u < re)
+#pragma unroll
+                    for (int r = 0; r < NR; r++) fb[int64_t(i0 + u) * nrhs + r] = a[u][r];
+        }
+        return;
+    }
     for (int j0 = 0; j0 < w; j0 += JW) {
         const int jn = min(JW, w - j0);
         T y[JW][NR];
