@@ -615,7 +615,11 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
                         P->soa_psize += d.w;
                     }
                     iv.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
-                    if (!P->slv_small_x[l]) ivx.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
+                    P->soa_copy_lev = l;
+                    if (!P->slv_small_x[l]) {
+                        ivx.emplace_back(d.loff, d.loff + int64_t(d.c) * d.w);
+                        P->soa_copy_lev_x = l;
+                    }
                 }
                 P->soa_it_ptr[l + 1] = int32_t(P->soa_it_s.size());
                 for (int32_t e = P->slv_cls_ptr[size_t(l) * kSolveClasses];

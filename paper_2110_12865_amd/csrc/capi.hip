@@ -468,6 +468,9 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&N->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&N->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&N->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess && N->soa) e = hipStreamCreateWithFlags(&N->side2, hipStreamNonBlocking);
+    if (e == hipSuccess && N->soa) e = hipEventCreateWithFlags(&N->ev_fork2, hipEventDisableTiming);
+    if (e == hipSuccess && N->soa) e = hipEventCreateWithFlags(&N->ev_join2, hipEventDisableTiming);
     if (e != hipSuccess) {
         sc_numeric_destroy(N);
         return map_err(e);
@@ -479,6 +482,7 @@ sc_status sc_numeric_create(const sc_plan_t *P, int32_t batch, sc_dtype dtype,
 void sc_numeric_destroy(sc_numeric_t *N) {
     if (!N) return;
     if (N->side) (void)hipStreamDestroy(N->side);  // waits for its work
+    if (N->side2) (void)hipStreamDestroy(N->side2);
     if (N->L) (void)hipFree(N->L);
     if (N->U) (void)hipFree(N->U);
     if (N->info) (void)hipFree(N->info);
@@ -489,6 +493,8 @@ void sc_numeric_destroy(sc_numeric_t *N) {
     free_refine_ws(N->rws);
     if (N->ev_fork) (void)hipEventDestroy(N->ev_fork);
     if (N->ev_join) (void)hipEventDestroy(N->ev_join);
+    if (N->ev_fork2) (void)hipEventDestroy(N->ev_fork2);
+    if (N->ev_join2) (void)hipEventDestroy(N->ev_join2);
     delete N;
 }
 

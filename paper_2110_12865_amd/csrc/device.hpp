@@ -244,6 +244,11 @@ struct sc_numeric {
     // large fronts) and the events that order it against the caller's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // third stream: the interleaved copy of L, beside the factorization of
+    // the levels above the copied supernodes (forked and joined inside the
+    // factorization)
+    hipStream_t side2 = nullptr;
+    hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;
 };
 
 // Launchers (factor.hip / solve.hip).  Return hipSuccess or the first error.
@@ -257,6 +262,8 @@ hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b,
                             int32_t nrhs, int64_t ldb, hipStream_t st,
                             const int32_t *active, const double *bin = nullptr);
 hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
+// The interleaved copy of L (batch-interleaved numeric objects), on stream st.
+hipError_t spchol_to_soa_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,
                              int64_t ldv, const double *b, double *x, int32_t nrhs,
                              int64_t ldb, double tol, int32_t maxit, int32_t method,

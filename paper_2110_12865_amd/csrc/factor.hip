@@ -1248,7 +1248,24 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         if (size_t(f.lds) * sizeof(T) > size_t(g_max_lds)) return hipErrorInvalidValue;
     Profiler &prof = N->prof;
     const double wsz = double(sizeof(T));
+    // batch-interleaved objects: the copy of L to the interleaved layout runs
+    // on a third stream as soon as the levels it covers are factored, beside
+    // the levels above (it is joined before the factorization returns)
+    const int32_t copy_lev = N->soa ? (N->xinv ? P->soa_copy_lev_x : P->soa_copy_lev) : -1;
+    bool copy_forked = false;
+    auto fork_copy = [&]() -> hipError_t {
+        copy_forked = true;
+        hipError_t e = hipEventRecord(N->ev_fork2, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(N->side2, N->ev_fork2, 0);
+        if (e == hipSuccess) e = spchol_to_soa_run(P, N, N->side2);
+        if (e == hipSuccess) e = hipEventRecord(N->ev_join2, N->side2);
+        return e;
+    };
     for (const FLaunch &f : D->fsched) {
+        if (copy_lev >= 0 && !copy_forked && f.level > copy_lev) {
+            const hipError_t e = fork_copy();
+            if (e != hipSuccess) return e;
+        }
         if (f.kind == FLaunch::Fork || f.kind == FLaunch::Join) {
             const bool fork = f.kind == FLaunch::Fork;
             hipError_t e = hipEventRecord(fork ? N->ev_fork : N->ev_join, fork ? st : N->side);
@@ -1324,17 +1341,21 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = spchol_dinv_run(P, N, st);  // inverted diagonal blocks for the solves
-    if (e != hipSuccess || !N->xinv || P->x_list.empty()) return e;
-    // whole-block inverses from them
-    prof.begin(KK_Dinv, 0.0, 0.0, st);
+    if (copy_lev >= 0 && !copy_forked) e = fork_copy();
+    if (e == hipSuccess) e = spchol_dinv_run(P, N, st);  // inverted diagonal blocks for the solves
+    if (e == hipSuccess && N->xinv && !P->x_list.empty()) {
+        // whole-block inverses from them
+        prof.begin(KK_Dinv, 0.0, 0.0, st);
     hipLaunchKernelGGL(k_trtri<T>,
                        dim3(unsigned(N->batch), unsigned(P->x_nbmax), unsigned(P->x_list.size())),
                        dim3(256), size_t(kTile * kTile + kTile * kXPitch) * sizeof(T), st, D->sn,
                        D->x_list, D->xoff, L, P->Lsize, reinterpret_cast<const T *>(N->dinv),
                        P->dinv_size, static_cast<T *>(N->xinv), P->xsize);
-    prof.end(st);
-    return hipGetLastError();
+        prof.end(st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && copy_forked) e = hipStreamWaitEvent(st, N->ev_join2, 0);
+    return e;
 }
 
 }  // namespace

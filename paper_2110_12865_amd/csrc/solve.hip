@@ -2486,17 +2486,9 @@ hipError_t solve_soa(const sc_plan *P, sc_numeric *N, const double *bin, double 
     const T *Ls = static_cast<const T *>(N->Ls);
     Profiler &prof = N->prof;
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
-    if (!N->ls_ok) {
-        // the levels solved with whole-block inverses read L, not the copy
-        const size_t nch = (N->xinv ? P->soa_chunks_x : P->soa_chunks).size();
-        prof.begin(KK_ToSoa, 0.0, 2.0 * sz * nb * double(nch) * kSoaChunk, st);
-        if (nch > 0)
-            hipLaunchKernelGGL(k_to_soa<T>, dim3(unsigned(nch), G), dim3(256), 0, st,
-                               static_cast<const T *>(N->L), P->Lsize,
-                               N->xinv ? D->soa_chunks_x : D->soa_chunks, B,
-                               static_cast<T *>(N->Ls));
-        prof.end(st);
-        N->ls_ok = true;
+    if (!N->ls_ok) {  // normally made during the factorization
+        const hipError_t e = spchol_to_soa_run(P, N, st);
+        if (e != hipSuccess) return e;
     }
     const dim3 pgrid(unsigned((P->n + 63) / 64), G);
     prof.begin(KK_Perm, 0.0, nb * nr * (8.0 + sz) * double(P->n) + 4.0 * double(P->n), st);
@@ -2898,6 +2890,28 @@ hipError_t spchol_solve_init() {
     sn_lds_limits<float, 4>();
     (void)hipGetLastError();  // an attribute the runtime refuses keeps the default
     return hipSuccess;
+}
+
+template <typename T>
+hipError_t to_soa_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const int B = N->batch;
+    const unsigned G = unsigned((B + 63) / 64);
+    // the levels solved with whole-block inverses read L, not the copy
+    const size_t nch = (N->xinv ? P->soa_chunks_x : P->soa_chunks).size();
+    N->prof.begin(KK_ToSoa, 0.0, 2.0 * double(sizeof(T)) * double(B) * double(nch) * kSoaChunk, st);
+    if (nch > 0)
+        hipLaunchKernelGGL(k_to_soa<T>, dim3(unsigned(nch), G), dim3(256), 0, st,
+                           static_cast<const T *>(N->L), P->Lsize,
+                           N->xinv ? D->soa_chunks_x : D->soa_chunks, B, static_cast<T *>(N->Ls));
+    N->prof.end(st);
+    N->ls_ok = true;
+    return hipGetLastError();
+}
+
+hipError_t spchol_to_soa_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
+    if (N->dtype == SC_F64) return to_soa_impl<double>(P, N, st);
+    return to_soa_impl<float>(P, N, st);
 }
 
 hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
