@@ -1113,10 +1113,12 @@ __global__ __launch_bounds__(kSnThreads) void k_bwd_sn(
 }
 
 // ---------------------------------------------------------------------------
-// Panel-solved supernodes with whole-block inverses X = L11^{-1} of their
-// diagonal blocks (formed after the factorization; column-major, leading
-// dimension w, zero above the diagonal inside the diagonal 64 x 64 blocks,
-// blocks above those never read).  Forward, after the gather of the front
+// Supernodes with whole-block inverses X = L11^{-1} of their diagonal
+// blocks (the panel-solved ones of levels whose panel supernodes are all at
+// most kXMaxW wide, and the others of levels with at most kXSmallMax of
+// them; formed after the factorization; column-major, leading dimension w,
+// zero above the diagonal inside the diagonal 64 x 64 blocks, blocks above
+// those never read).  Forward, after the gather of the front
 // vector v = (v1, v2): y = X v1, then u = v2 - L21 y; backward: rhs = y -
 // L21^T x2, then x1 = X^T rhs.  Each is a dense product over the whole
 // block, split over 64-row (or 64-column) blocks so that a supernode takes
