@@ -216,7 +216,12 @@ void sc_plan_destroy(sc_plan_t *plan);
  * and a private non-blocking stream with two events on the current device
  * (the factorization runs part of the trailing updates of large fronts
  * there, ordered against the caller's stream by those events; a call
- * still returns with all its work ordered on the caller's stream).
+ * still returns with all its work ordered on the caller's stream).  Objects
+ * that solve in the batch-interleaved layout (batch >= soa_min_batch) get a
+ * second such stream with two events: the factorization copies L to that
+ * layout there, beside its top levels, and joins it before returning.
+ * Batches of at least 16 with whole-block inverses (sc_options.panel_inverse)
+ * also hold those inverses (w^2 scalars per inverted supernode and matrix).
  * Uploads the plan to the current device if not done yet.
  * Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
  */
