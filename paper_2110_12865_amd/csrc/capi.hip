@@ -225,7 +225,8 @@ sc_status ensure_refine_ws(sc_numeric *N, int32_t nrhs, int64_t ldb) {
         e = hipMalloc(reinterpret_cast<void **>(&W.part), 32 * 3 * sizeof(double) * nseg);
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.part2),
-                      3 * sizeof(double) * size_t(nsys) * size_t((N->plan->n + 255) / 256));
+                      sizeof(double) * size_t(3 * nsys + N->batch) *
+                          size_t((N->plan->n + 255) / 256));
     if (e == hipSuccess)
         e = hipMalloc(reinterpret_cast<void **>(&W.anorm),
                       sizeof(double) * N->batch * N->plan->nblk);

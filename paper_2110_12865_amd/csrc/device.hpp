@@ -191,7 +191,9 @@ struct RefineWs {
     // per system (matrix, right-hand side, block): nseg = nsys * nblk
     double *sc = nullptr;       // scalars, 4 * nseg
     double *part = nullptr;     // reduction partials, nseg * 32 * 3
-    double *part2 = nullptr;    // partials of the fused residual product, nsys * ceil(n/256) * 3
+    // partials of the fused residual product, nsys * ceil(n/256) * 3, then
+    // the row-sum maxima of |A| per (matrix, 256-row block), batch * ceil(n/256)
+    double *part2 = nullptr;
     double *anorm = nullptr;    // batch * nblk
     double *vc = nullptr;       // values of A in row order, batch * nnz(both triangles)
     double *stat = nullptr;     // nseg * 6

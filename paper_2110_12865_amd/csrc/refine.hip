@@ -53,70 +53,145 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// The entries of one 64-row slice of the sliced row structure, read by the
+// wave that owns the slice (lane = row): the slice's padded length (uniform
+// over the wave) and the wave's base entry.  Waves past the last slice get
+// length 0.
+struct SliceRef {
+    int64_t e0;  // entry of lane 0 in row position 0
+    int len;     // padded entries per row
+};
+__device__ inline SliceRef slice_of(const int64_t *__restrict__ sptr, int64_t i, int64_t n) {
+    const int64_t s = __builtin_amdgcn_readfirstlane(int(i / kSellRows));
+    const int64_t nsl = (n + kSellRows - 1) / kSellRows;
+    SliceRef r;
+    r.e0 = s < nsl ? sptr[s] : 0;
+    r.len = s < nsl ? int((sptr[s + 1] - r.e0) / kSellRows) : 0;
+    return r;
+}
+
+// t[r] += sum_k a_k X[base + r ldb + j_k] over the entries of row i in
+// order (k < len), each chunk of U entries loaded (values, columns, then the
+// U * NR entries of X) before its sums; positions past the row's length but
+// inside the slice are padding (column 0, value 0) and are loaded but not
+// added.
+template <int NR, int U>
+__device__ inline void row_dot(const SliceRef &sl, int len, const double *__restrict__ v,
+                               const int32_t *__restrict__ cl, const double *__restrict__ X,
+                               int64_t base, int64_t ldb, double *t, double &asum) {
+    for (int k0 = 0; k0 < sl.len; k0 += U) {
+        double a[U], x[U][NR];
+        int32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t k = min(k0 + u, sl.len - 1);
+            a[u] = v[k * kSellRows];
+            j[u] = cl[k * kSellRows];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) x[u][r] = X[base + r * ldb + j[u]];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (k0 + u < len) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) t[r] += a[u] * x[u][r];
+                asum += fabs(a[u]);
+            }
+    }
+}
+
+// Maximum of v over the 64 lanes of a wave (any order gives the same value).
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 // Y = B - A X (mode 1) or Y = A X (mode 0) for every right-hand side of the
 // matrices with active[matrix] != 0: one lane per row of A, entries in row
 // order from the sliced layout (entry k of the 64 rows of a wave's slice is
 // one contiguous load of values and of column indices), all NR right-hand
 // sides of the matrix at once so every value of A is read once per matrix.
 // Workgroups of consecutive matrices cover the same rows, so the shared row
-// structure is reused from cache.  With psum (mode 1, plans of one block),
-// also the workgroup's partial sums of Y.Y, B.B and X.X per right-hand side:
+// structure is reused from cache.  With psum (plans of one block), also the
+// workgroup's partial sums per right-hand side, in mode 1 of Y.Y, B.B and
+// X.X, in mode 0 of X.Y and B.X (B is then read for these sums only):
 // psum[((matrix * nrhs + r) * nrb + block of rows) * 3 + {0, 1, 2}], lanes
-// in a fixed butterfly, waves in order.
+// in a fixed butterfly, waves in order.  With amax (right-hand sides from
+// r0 = 0), the workgroup's largest row sum of |A|: amax[matrix * nrb + block
+// of rows], each row summed in entry order.
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply(
     const int64_t *__restrict__ ptr, const int64_t *__restrict__ sptr,
     const int32_t *__restrict__ col, const double *__restrict__ vc, int64_t nsell,
     const double *__restrict__ B, const double *__restrict__ X, double *__restrict__ Y,
     int64_t ldb, int64_t n, int nrhs, int r0, int mode, const int32_t *__restrict__ active,
-    double *__restrict__ psum, int nrb) {
+    double *__restrict__ psum, int nrb, double *__restrict__ amax) {
     __shared__ double red[4][NR][3];
+    __shared__ double redm[4];
     const int b = blockIdx.x;
     if (active && !active[b]) return;
     const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
     const bool in = i < n;
-    if (!in && !psum) return;
+    if (!in && !psum && !amax) return;
     const int64_t ic = in ? i : n - 1;  // rows past n compute row n - 1 and add nothing
-    const int64_t e0 = sptr[ic / kSellRows] + ic % kSellRows;
-    const int len = int(ptr[ic + 1] - ptr[ic]);
-    const double *v = vc + int64_t(b) * nsell + e0;
-    const int32_t *cl = col + e0;
+    const SliceRef sl = slice_of(sptr, i, n);
+    const int len = in ? int(ptr[i + 1] - ptr[i]) : 0;
+    const int64_t e0 = sl.e0 + i % kSellRows;
     const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
     double t[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) t[r] = 0.0;
-    for (int k = 0; k < len; k++) {
-        const double a = v[int64_t(k) * kSellRows];
-        const int64_t j = cl[int64_t(k) * kSellRows];
-#pragma unroll
-        for (int r = 0; r < NR; r++) t[r] += a * X[base + r * ldb + j];
-    }
+    double asum = 0.0;
+    row_dot<NR, 8>(sl, len, vc + int64_t(b) * nsell + e0, col + e0, X, base, ldb, t, asum);
     double y[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         y[r] = mode ? B[base + r * ldb + ic] - t[r] : t[r];
         if (in) Y[base + r * ldb + i] = y[r];
     }
-    if (!psum) return;
+    if (!psum && !amax) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (amax) {
+        const double m = wave_max(asum);  // rows past n have asum = 0
+        if (lane == 0) redm[wv] = m;
+    }
+    if (psum) {
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const double bb = B[base + r * ldb + ic], xx = X[base + r * ldb + ic];
-        const double s0 = wave_sum(in ? y[r] * y[r] : 0.0);
-        const double s1 = wave_sum(in ? bb * bb : 0.0);
-        const double s2 = wave_sum(in ? xx * xx : 0.0);
-        if (lane == 0) {
-            red[wv][r][0] = s0;
-            red[wv][r][1] = s1;
-            red[wv][r][2] = s2;
+        for (int r = 0; r < NR; r++) {
+            const double bb = B[base + r * ldb + ic], xx = X[base + r * ldb + ic];
+            const double s0 = wave_sum(in ? (mode ? y[r] * y[r] : xx * y[r]) : 0.0);
+            const double s1 = wave_sum(in ? (mode ? bb * bb : bb * xx) : 0.0);
+            const double s2 = wave_sum(in && mode ? xx * xx : 0.0);
+            if (lane == 0) {
+                red[wv][r][0] = s0;
+                red[wv][r][1] = s1;
+                red[wv][r][2] = s2;
+            }
         }
     }
     __syncthreads();
-    if (threadIdx.x < 3 * NR) {
+    if (psum && threadIdx.x < 3 * NR) {
         const int r = threadIdx.x / 3, q = threadIdx.x % 3;
         psum[((int64_t(b) * nrhs + r0 + r) * nrb + blockIdx.y) * 3 + q] =
             ((red[0][r][q] + red[1][r][q]) + red[2][r][q]) + red[3][r][q];
     }
+    if (amax && threadIdx.x == 0)
+        amax[int64_t(b) * nrb + blockIdx.y] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+}
+
+// anorm[matrix] = the largest of the nrb row-block maxima of k_apply (one
+// wave per matrix; the maximum does not depend on the order).
+__global__ __launch_bounds__(256) void k_anorm_blocks(const double *__restrict__ amax, int nrb,
+                                                      int batch, double *__restrict__ anorm) {
+    const int b = blockIdx.x * 4 + int(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= batch) return;
+    double m = 0.0;
+    for (int q = lane; q < nrb; q += 64) m = fmax(m, amax[int64_t(b) * nrb + q]);
+    m = wave_max(m);
+    if (lane == 0) anorm[b] = m;
 }
 
 // Y1 = B - A X1 and Y2 = A X2 in one pass over A (each sum in the order
@@ -137,21 +212,40 @@ __global__ __launch_bounds__(256) void k_apply2(
     const int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x;
     const bool in = i < n;
     const int64_t ic = in ? i : n - 1;  // rows past n compute row n - 1 and add nothing
-    const int64_t e0 = sptr[ic / kSellRows] + ic % kSellRows;
-    const int len = int(ptr[ic + 1] - ptr[ic]);
-    const double *v = vc + int64_t(b) * nsell + e0;
-    const int32_t *cl = col + e0;
+    const SliceRef sl = slice_of(sptr, i, n);
+    const int len = in ? int(ptr[i + 1] - ptr[i]) : 0;
+    const int64_t e0 = sl.e0 + i % kSellRows;
     const int64_t base = (int64_t(b) * nrhs + r0) * ldb;
     double t1[NR], t2[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) t1[r] = t2[r] = 0.0;
-    for (int k = 0; k < len; k++) {
-        const double a = v[int64_t(k) * kSellRows];
-        const int64_t j = cl[int64_t(k) * kSellRows];
+    {
+        const double *v = vc + int64_t(b) * nsell + e0;
+        const int32_t *cl = col + e0;
+        for (int k0 = 0; k0 < sl.len; k0 += 4) {
+            double a[4], x1[4][NR], x2[4][NR];
+            int32_t j[4];
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            t1[r] += a * X1[base + r * ldb + j];
-            t2[r] += a * X2[base + r * ldb + j];
+            for (int u = 0; u < 4; u++) {
+                const int64_t k = min(k0 + u, sl.len - 1);
+                a[u] = v[k * kSellRows];
+                j[u] = cl[k * kSellRows];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    x1[u][r] = X1[base + r * ldb + j[u]];
+                    x2[u][r] = X2[base + r * ldb + j[u]];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (k0 + u < len)
+#pragma unroll
+                    for (int r = 0; r < NR; r++) {
+                        t1[r] += a[u] * x1[u][r];
+                        t2[r] += a[u] * x2[u][r];
+                    }
         }
     }
     double y1[NR];
@@ -390,15 +484,33 @@ __global__ void k_active(const int32_t *__restrict__ conv, int batch, int per_ma
     if (threadIdx.x == 0) count[0] = cnt;
 }
 
+// The vector kernels below take kVecPer elements per thread (strided by
+// the workgroup size, so every load is coalesced), with their loads issued
+// before the per-system scalars are tested: a workgroup covers
+// 256 * kVecPer consecutive elements of one system vector.
+constexpr int kVecPer = 4;
+constexpr int kVecSpan = 256 * kVecPer;
+
 // x += d on the systems that have not passed
-__global__ void k_axpy(double *__restrict__ X, const double *__restrict__ D, int64_t ldb,
-                       int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
-                       const int32_t *__restrict__ active, const int32_t *__restrict__ conv) {
+__global__ __launch_bounds__(256) void k_axpy(
+    double *__restrict__ X, const double *__restrict__ D, int64_t ldb, int64_t n, int nrhs,
+    int nblk, const int32_t *__restrict__ colblk, const int32_t *__restrict__ active,
+    const int32_t *__restrict__ conv) {
     const int br = blockIdx.y;
     if (!active[br / nrhs]) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n || conv[seg_of(br, nblk, colblk, i)]) return;
-    X[int64_t(br) * ldb + i] += D[int64_t(br) * ldb + i];
+    const int64_t i0 = int64_t(blockIdx.x) * kVecSpan + threadIdx.x, o0 = int64_t(br) * ldb;
+    double x[kVecPer], d[kVecPer];
+#pragma unroll
+    for (int q = 0; q < kVecPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        x[q] = i < n ? X[o0 + i] : 0.0;
+        d[q] = i < n ? D[o0 + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kVecPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        if (i < n && !conv[seg_of(br, nblk, colblk, i)]) X[o0 + i] = x[q] + d[q];
+    }
 }
 
 __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
@@ -406,52 +518,68 @@ __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_copy_sys(const double *__restrict__ X, double *__restrict__ Y, int64_t ldb,
-                           int64_t n, int nrhs, const int32_t *__restrict__ active) {
-    const int br = blockIdx.y;
-    if (active && !active[br / nrhs]) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) Y[int64_t(br) * ldb + i] = X[int64_t(br) * ldb + i];
-}
-
 // CG step on systems that have not passed: alpha = rz / pq,
 // x += alpha p, r -= alpha q (a system with pq <= 0 is left unchanged)
-__global__ void k_cg_xr(double *__restrict__ X, double *__restrict__ R,
-                        const double *__restrict__ Pv, const double *__restrict__ Q, int64_t ldb,
-                        int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
-                        const int32_t *__restrict__ active, const int32_t *__restrict__ conv,
-                        const double *__restrict__ rz, const double *__restrict__ pq) {
+__global__ __launch_bounds__(256) void k_cg_xr(
+    double *__restrict__ X, double *__restrict__ R, const double *__restrict__ Pv,
+    const double *__restrict__ Q, int64_t ldb, int64_t n, int nrhs, int nblk,
+    const int32_t *__restrict__ colblk, const int32_t *__restrict__ active,
+    const int32_t *__restrict__ conv, const double *__restrict__ rz,
+    const double *__restrict__ pq) {
     const int br = blockIdx.y;
     if (!active[br / nrhs]) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int sg = seg_of(br, nblk, colblk, i);
-    if (conv[sg]) return;
-    const double den = pq[sg];
-    if (!(den > 0.0)) return;
-    const double alpha = rz[sg] / den;
-    const int64_t o = int64_t(br) * ldb + i;
-    X[o] += alpha * Pv[o];
-    R[o] -= alpha * Q[o];
+    const int64_t i0 = int64_t(blockIdx.x) * kVecSpan + threadIdx.x, o0 = int64_t(br) * ldb;
+    double x[kVecPer], r[kVecPer], p[kVecPer], q4[kVecPer];
+#pragma unroll
+    for (int q = 0; q < kVecPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        const bool on = i < n;
+        x[q] = on ? X[o0 + i] : 0.0;
+        r[q] = on ? R[o0 + i] : 0.0;
+        p[q] = on ? Pv[o0 + i] : 0.0;
+        q4[q] = on ? Q[o0 + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kVecPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        if (i >= n) continue;
+        const int sg = seg_of(br, nblk, colblk, i);
+        const double den = pq[sg];
+        if (conv[sg] || !(den > 0.0)) continue;
+        const double alpha = rz[sg] / den;
+        X[o0 + i] = x[q] + alpha * p[q];
+        R[o0 + i] = r[q] - alpha * q4[q];
+    }
 }
 
 // p = z + beta p with beta = z_new.(r_new - r_old) / (z_old.r_old), the form
 // that tolerates a preconditioner applied in lower precision (Golub and Ye,
 // inexact preconditioned CG).  With r_new - r_old = -alpha q and alpha =
 // z_old.r_old / p.q this is beta = -z_new.q / p.q.
-__global__ void k_cg_p(double *__restrict__ Pv, const double *__restrict__ Z, int64_t ldb,
-                       int64_t n, int nrhs, int nblk, const int32_t *__restrict__ colblk,
-                       const int32_t *__restrict__ active, const int32_t *__restrict__ conv,
-                       const double *__restrict__ zq, const double *__restrict__ pq) {
+__global__ __launch_bounds__(256) void k_cg_p(
+    double *__restrict__ Pv, const double *__restrict__ Z, int64_t ldb, int64_t n, int nrhs,
+    int nblk, const int32_t *__restrict__ colblk, const int32_t *__restrict__ active,
+    const int32_t *__restrict__ conv, const double *__restrict__ zq,
+    const double *__restrict__ pq) {
     const int br = blockIdx.y;
     if (!active[br / nrhs]) return;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int sg = seg_of(br, nblk, colblk, i);
-    if (conv[sg]) return;
-    const double beta = pq[sg] > 0.0 ? -zq[sg] / pq[sg] : 0.0;
-    const int64_t o = int64_t(br) * ldb + i;
-    Pv[o] = Z[o] + beta * Pv[o];
+    const int64_t i0 = int64_t(blockIdx.x) * kVecSpan + threadIdx.x, o0 = int64_t(br) * ldb;
+    double p[kVecPer], z[kVecPer];
+#pragma unroll
+    for (int q = 0; q < kVecPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        p[q] = i < n ? Pv[o0 + i] : 0.0;
+        z[q] = i < n ? Z[o0 + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kVecPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        if (i >= n) continue;
+        const int sg = seg_of(br, nblk, colblk, i);
+        if (conv[sg]) continue;
+        const double beta = pq[sg] > 0.0 ? -zq[sg] / pq[sg] : 0.0;
+        Pv[o0 + i] = z[q] + beta * p[q];
+    }
 }
 
 }  // namespace
@@ -472,10 +600,12 @@ double vec_bytes(const sc_plan *P, double nsys, int nvec) {
 }
 
 // Y = B - A X (mode 1) or A X (mode 0) for all right-hand sides of the
-// active matrices, up to four right-hand sides per pass.
+// active matrices, up to four right-hand sides per pass; psum and amax as
+// in k_apply.
 void apply_A(const sc_plan *P, const double *vc, const double *B,
              const double *X, double *Y, int64_t ldb, int batch, int nrhs, int mode,
-             const int32_t *active, hipStream_t st, double *psum = nullptr) {
+             const int32_t *active, hipStream_t st, double *psum = nullptr,
+             double *amax = nullptr) {
     const DevPlan *D = P->dev;
     const int64_t nsell = P->sell_ptr.back();
     const dim3 grid(unsigned(batch), unsigned((P->n + 255) / 256));
@@ -484,7 +614,7 @@ void apply_A(const sc_plan *P, const double *vc, const double *B,
 #define SPCHOL_APPLY(NR)                                                                   \
     hipLaunchKernelGGL(k_apply<NR>, grid, dim3(256), 0, st, D->csr_ptr, D->sell_ptr,        \
                        D->sell_col, vc, nsell, B, X, Y, ldb, P->n, nrhs, r0, mode, active,   \
-                       psum, int(grid.y))
+                       psum, int(grid.y), r0 == 0 ? amax : nullptr)
         if (nr == 1) SPCHOL_APPLY(1);
         else if (nr == 2) SPCHOL_APPLY(2);
         else if (nr == 3) SPCHOL_APPLY(3);
@@ -514,6 +644,17 @@ void apply_A2(const sc_plan *P, const double *vc, const double *B, const double 
     }
 }
 
+// ||A_k||_inf of every (matrix, block) of a group plan into W.anorm, from
+// the values in row order (W.vc)
+void anorm_blocks(const sc_plan *P, RefineWs &W, int batch, int64_t nsell, hipStream_t st) {
+    const DevPlan *D = P->dev;
+    const int nblk = P->nblk;
+    hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
+                       D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
+    hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
+                       W.part, batch * nblk, W.anorm);
+}
+
 hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
                             int64_t ldv, const double *b, double *x, int32_t nrhs,
                             int64_t ldb, double tol, int32_t maxit, double *stat_host,
@@ -525,7 +666,7 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
     const int nsys = batch * nrhs, nseg = nsys * nblk, per = nrhs * nblk;
     const int64_t n = P->n;
     const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
-    const dim3 vgrid(unsigned((n + 255) / 256), unsigned(nsys));
+    const dim3 vgrid(unsigned((n + kVecSpan - 1) / kVecSpan), unsigned(nsys));
     const dim3 sgrid(unsigned((nseg + 255) / 256));
     const dim3 rgrid(unsigned((nseg + 3) / 4));  // one wave per system
     hipError_t e;
@@ -539,19 +680,21 @@ hipError_t refine_classical(const sc_plan *P, sc_numeric *N, const double *vals,
     hipLaunchKernelGGL(k_gather_rows,
                        dim3(unsigned((nsell + 255) / 256), unsigned((batch + kGatherMats - 1) / kGatherMats)),
                        dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, batch, W.vc);
-    hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
-                       D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
-    hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
-                       W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     // plans of one block: the norms of the test come from the residual's own
-    // pass (partial sums per 256-row block)
+    // pass (partial sums per 256-row block), ||A||_inf from the first one
     const int nrb = int((n + 255) / 256);
     const bool fuse = nblk == 1;
+    double *amax = W.part2 + size_t(3) * nsys * nrb;
+    if (!fuse) anorm_blocks(P, W, batch, nsell, st);
     for (int it = 0;; it++) {
         prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
-        apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st, fuse ? W.part2 : nullptr);
+        apply_A(P, W.vc, b, x, W.r, ldb, batch, nrhs, 1, W.active, st, fuse ? W.part2 : nullptr,
+                fuse && it == 0 ? amax : nullptr);
         prof.end(st);
+        if (fuse && it == 0)
+            hipLaunchKernelGGL(k_anorm_blocks, dim3((batch + 3) / 4), dim3(256), 0, st, amax, nrb,
+                               batch, W.anorm);
         if (!fuse) {
             prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, it == 0 ? 3 : 2), st);
             hipLaunchKernelGGL(k_sums, dim3(kRB, nseg), dim3(256), 0, st, W.r, b, x,
@@ -600,7 +743,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     const int nsys = batch * nrhs, nseg = nsys * nblk, per = nrhs * nblk;
     const int64_t n = P->n;
     const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
-    const dim3 vgrid(unsigned((n + 255) / 256), unsigned(nsys));
+    const dim3 vgrid(unsigned((n + kVecSpan - 1) / kVecSpan), unsigned(nsys));
     const dim3 sgrid(unsigned((nseg + 255) / 256));
     const dim3 rgrid(unsigned((nseg + 3) / 4));  // one wave per system
     const size_t vsz = size_t(nsys) * ldb;
@@ -616,15 +759,14 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     hipLaunchKernelGGL(k_gather_rows,
                        dim3(unsigned((nsell + 255) / 256), unsigned((batch + kGatherMats - 1) / kGatherMats)),
                        dim3(256), 0, st, D->sell_vidx, vals, ldv, nsell, batch, W.vc);
-    hipLaunchKernelGGL(k_anorm_part, dim3(32, batch * nblk), dim3(256), 0, st, D->csr_ptr,
-                       D->sell_ptr, W.vc, nsell, D->blk_col0, nblk, W.part);
-    hipLaunchKernelGGL(k_anorm_final, dim3((batch * nblk + 255) / 256), dim3(256), 0, st,
-                       W.part, batch * nblk, W.anorm);
     int32_t nact = batch;
     // true residual b - A x into res, stop test; with pnext, q = A pnext in
     // the same pass over A, and for a plan of one block the norms of the test
-    // and p.q of the next step from that pass too (pq_ready)
+    // and p.q of the next step from that pass too (pq_ready); ||A||_inf from
+    // the first residual's pass (plans of one block)
     const int nrb = int((n + 255) / 256);
+    double *amax = W.part2 + size_t(3) * nsys * nrb;
+    if (nblk > 1) anorm_blocks(P, W, batch, nsell, st);
     bool pq_ready = false;
     auto check = [&](int it, double *res, const double *pnext) -> hipError_t {
         const bool fuse = pnext && nblk == 1 && it > 0;
@@ -635,9 +777,12 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         } else {
             prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
             apply_A(P, W.vc, b, x, res, ldb, batch, nrhs, 1, W.active, st,
-                    nblk == 1 ? W.part2 : nullptr);
+                    nblk == 1 ? W.part2 : nullptr, nblk == 1 && it == 0 ? amax : nullptr);
         }
         prof.end(st);
+        if (nblk == 1 && it == 0)
+            hipLaunchKernelGGL(k_anorm_blocks, dim3((batch + 3) / 4), dim3(256), 0, st, amax, nrb,
+                               batch, W.anorm);
         if (!pnext && nblk == 1) {  // the test's norms came with the residual
             hipLaunchKernelGGL(k_check, rgrid, dim3(256), 0, st, W.part2, nrb, nseg, nrhs, nblk,
                                W.anorm, tol, it, W.active, W.conv, W.stat);
@@ -688,11 +833,21 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     if (nact > 0 && maxit > 0) {
         e = spchol_solve_run(P, N, pv, nrhs, ldb, st, W.active, r);  // p_1 = z_0 = M^{-1} r_0
         if (e != hipSuccess) return e;
-        dots(r, pv, rz0);
         double *rz = rz0, *rzn = rz1;
-        prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st, 12.0 * double(P->nnzA) * nact);
-        apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);  // q_1 = A p_1
-        prof.end(st);
+        if (nblk == 1) {
+            // q_1 = A p_1 with r_0.p_1 and p_1.q_1 from the same pass
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
+            apply_A(P, W.vc, r, pv, q, ldb, batch, nrhs, 0, W.active, st, W.part2);
+            prof.end(st);
+            hipLaunchKernelGGL(k_sums_final, rgrid, dim3(256), 0, st, W.part2, nrb, 0, nseg, per,
+                               W.active, pq, rz0);
+            pq_ready = true;
+        } else {
+            dots(r, pv, rz0);
+            prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st, 12.0 * double(P->nnzA) * nact);
+            apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);  // q_1 = A p_1
+            prof.end(st);
+        }
         for (int it = 1; it <= maxit; it++) {
             if (!pq_ready) dots(pv, q, pq);
             pq_ready = false;
