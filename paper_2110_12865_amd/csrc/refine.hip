@@ -484,10 +484,10 @@ __global__ void k_active(const int32_t *__restrict__ conv, int batch, int per_ma
     if (threadIdx.x == 0) count[0] = cnt;
 }
 
-// The vector kernels below take kVecPer elements per thread (strided by
-// the workgroup size, so every load is coalesced), with their loads issued
-// before the per-system scalars are tested: a workgroup covers
-// 256 * kVecPer consecutive elements of one system vector.
+// The vector kernels below take several elements per thread (kVecPer, or
+// PER; strided by the workgroup size, so every load is coalesced), with
+// their loads issued before the per-system scalars are tested: a workgroup
+// covers 256 * kVecPer consecutive elements of one system vector.
 constexpr int kVecPer = 4;
 constexpr int kVecSpan = 256 * kVecPer;
 
@@ -519,7 +519,10 @@ __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
 }
 
 // CG step on systems that have not passed: alpha = rz / pq,
-// x += alpha p, r -= alpha q (a system with pq <= 0 is left unchanged)
+// x += alpha p, r -= alpha q (a system with pq <= 0 is left unchanged);
+// PER elements per thread (four vectors in flight at PER = 1 already keep
+// this kernel at the bandwidth of the others)
+template <int PER>
 __global__ __launch_bounds__(256) void k_cg_xr(
     double *__restrict__ X, double *__restrict__ R, const double *__restrict__ Pv,
     const double *__restrict__ Q, int64_t ldb, int64_t n, int nrhs, int nblk,
@@ -528,10 +531,10 @@ __global__ __launch_bounds__(256) void k_cg_xr(
     const double *__restrict__ pq) {
     const int br = blockIdx.y;
     if (!active[br / nrhs]) return;
-    const int64_t i0 = int64_t(blockIdx.x) * kVecSpan + threadIdx.x, o0 = int64_t(br) * ldb;
-    double x[kVecPer], r[kVecPer], p[kVecPer], q4[kVecPer];
+    const int64_t i0 = int64_t(blockIdx.x) * (256 * PER) + threadIdx.x, o0 = int64_t(br) * ldb;
+    double x[PER], r[PER], p[PER], q4[PER];
 #pragma unroll
-    for (int q = 0; q < kVecPer; q++) {
+    for (int q = 0; q < PER; q++) {
         const int64_t i = i0 + 256 * q;
         const bool on = i < n;
         x[q] = on ? X[o0 + i] : 0.0;
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(256) void k_cg_xr(
         q4[q] = on ? Q[o0 + i] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < kVecPer; q++) {
+    for (int q = 0; q < PER; q++) {
         const int64_t i = i0 + 256 * q;
         if (i >= n) continue;
         const int sg = seg_of(br, nblk, colblk, i);
@@ -744,6 +747,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
     const int64_t n = P->n;
     const int32_t *colblk = nblk > 1 ? D->colblk : nullptr;
     const dim3 vgrid(unsigned((n + kVecSpan - 1) / kVecSpan), unsigned(nsys));
+    const dim3 xgrid(unsigned((n + 255) / 256), unsigned(nsys));
     const dim3 sgrid(unsigned((nseg + 255) / 256));
     const dim3 rgrid(unsigned((nseg + 3) / 4));  // one wave per system
     const size_t vsz = size_t(nsys) * ldb;
@@ -852,7 +856,7 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
             if (!pq_ready) dots(pv, q, pq);
             pq_ready = false;
             prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 6), st);
-            hipLaunchKernelGGL(k_cg_xr, vgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
+            hipLaunchKernelGGL(k_cg_xr<1>, xgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
                                nblk, colblk, W.active, W.conv, rz, pq);
             prof.end(st);
             if (it == maxit) {
