@@ -519,9 +519,10 @@ __global__ void k_set_i32(int32_t *p, int n, int32_t v) {
 }
 
 // CG step on systems that have not passed: alpha = rz / pq,
-// x += alpha p, r -= alpha q (a system with pq <= 0 is left unchanged);
-// PER elements per thread (four vectors in flight at PER = 1 already keep
-// this kernel at the bandwidth of the others)
+// x += alpha p, r -= alpha q (a system with pq <= 0 is left unchanged; x
+// only when R is null: the last step of a fixed budget, whose recursive
+// residual nobody reads); PER elements per thread (four vectors in flight
+// at PER = 1 already keep this kernel at the bandwidth of the others)
 template <int PER>
 __global__ __launch_bounds__(256) void k_cg_xr(
     double *__restrict__ X, double *__restrict__ R, const double *__restrict__ Pv,
@@ -538,9 +539,9 @@ __global__ __launch_bounds__(256) void k_cg_xr(
         const int64_t i = i0 + 256 * q;
         const bool on = i < n;
         x[q] = on ? X[o0 + i] : 0.0;
-        r[q] = on ? R[o0 + i] : 0.0;
         p[q] = on ? Pv[o0 + i] : 0.0;
-        q4[q] = on ? Q[o0 + i] : 0.0;
+        r[q] = on && R ? R[o0 + i] : 0.0;
+        q4[q] = on && R ? Q[o0 + i] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < PER; q++) {
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(256) void k_cg_xr(
         if (conv[sg] || !(den > 0.0)) continue;
         const double alpha = rz[sg] / den;
         X[o0 + i] = x[q] + alpha * p[q];
-        R[o0 + i] = r[q] - alpha * q4[q];
+        if (R) R[o0 + i] = r[q] - alpha * q4[q];
     }
 }
 
@@ -855,9 +856,12 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
         for (int it = 1; it <= maxit; it++) {
             if (!pq_ready) dots(pv, q, pq);
             pq_ready = false;
-            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, 6), st);
-            hipLaunchKernelGGL(k_cg_xr<1>, xgrid, dim3(256), 0, st, x, r, pv, q, ldb, n, nrhs,
-                               nblk, colblk, W.active, W.conv, rz, pq);
+            // at the last step of the budget only x changes (the test below
+            // forms the true residual)
+            const bool last = it == maxit;
+            prof.begin(KK_Vec, 0.0, vec_bytes(P, nact * nrhs, last ? 3 : 6), st);
+            hipLaunchKernelGGL(k_cg_xr<1>, xgrid, dim3(256), 0, st, x, last ? nullptr : r, pv, q,
+                               ldb, n, nrhs, nblk, colblk, W.active, W.conv, rz, pq);
             prof.end(st);
             if (it == maxit) {
                 e = check(it, rt, nullptr);
