@@ -868,9 +868,19 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                 if (e != hipSuccess) return e;
                 break;
             }
-            // the next direction comes before this step's test, so that the
-            // test's product and q = A p share one pass over A (a system that
-            // passes the test is frozen from here on; its new p is unused)
+            // Without host synchronization (a fixed budget, as in a captured
+            // graph) the next direction comes before this step's test, so that
+            // the test's product and q = A p share one pass over A (a system
+            // that passes the test is frozen from here on; its new p is
+            // unused).  With it, the test comes first and a step that ends
+            // the refinement costs no further solve; q = A p then takes a pass
+            // of its own.  Both orders give the same bits: every sum is formed
+            // by the same products in the same order.
+            if (sync) {
+                e = check(it, rt, nullptr);
+                if (e != hipSuccess) return e;
+                if (nact == 0) break;
+            }
             e = spchol_solve_run(P, N, z, nrhs, ldb, st, W.active, r);
             if (e != hipSuccess) return e;
             dots2(r, z, q, rzn, zq);
@@ -879,9 +889,22 @@ hipError_t refine_pcg(const sc_plan *P, sc_numeric *N, const double *vals, int64
                                colblk, W.active, W.conv, zq, pq);
             prof.end(st);
             std::swap(rz, rzn);
-            e = check(it, rt, pv);
-            if (e != hipSuccess) return e;
-            if (nact == 0) break;
+            if (!sync) {
+                e = check(it, rt, pv);
+                if (e != hipSuccess) return e;
+            } else if (nblk == 1) {
+                // q = A p with p.q from the same pass (component 0)
+                prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 3), st, 12.0 * double(P->nnzA) * nact);
+                apply_A(P, W.vc, r, pv, q, ldb, batch, nrhs, 0, W.active, st, W.part2);
+                prof.end(st);
+                hipLaunchKernelGGL(k_sums_final, rgrid, dim3(256), 0, st, W.part2, nrb, 0, nseg,
+                                   per, W.active, pq, nullptr);
+                pq_ready = true;
+            } else {
+                prof.begin(KK_Spmv, 0.0, spmv_bytes(P, nact, nrhs, 2), st, 12.0 * double(P->nnzA) * nact);
+                apply_A(P, W.vc, nullptr, pv, q, ldb, batch, nrhs, 0, W.active, st);
+                prof.end(st);
+            }
         }
     }
     if (!sync) return hipGetLastError();

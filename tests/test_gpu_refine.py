@@ -89,6 +89,43 @@ def test_refine_ill_conditioned_mesh_reaches_floor(method):
     assert np.all(relres_g <= np.maximum(10 * relres_o, 1e-10))
 
 
+@pytest.mark.parametrize("method", ["classical", "pcg"])
+def test_refine_six_rhs_floor_clause_against_host_norm(method):
+    """Six right-hand sides (two passes of the residual product, 4 + 2) on
+    the ill-conditioned 64^2 mesh: every system stops; a system stopped by
+    the floor clause satisfies ||r||_2 <= 2 u ||A||_inf ||x||_2 with its own
+    recorded norms and ||A||_inf computed on the host (the device takes
+    ||A||_inf from the first residual pass); a system stopped by the first
+    clause has relres <= tol; each refined x is as good as the direct FP64
+    solve."""
+    import paper_2110_12865_amd as S
+    w = W.trimesh_workload(64, 2, 6, seed=69)
+    tol = 1e-10
+    rc, stats, x = _refine(w, "f32", tol=tol, maxit=20, method=method)
+    assert rc == S.SC_OK
+    p = w.pattern
+    u = np.finfo(np.float64).eps / 2
+    nfloor = 0
+    for s in range(w.batch):
+        anorm = oracle.norm_inf_sym(p.n, p.colptr, p.rowind, w.values[s])
+        sym, Lx, _, xo = oracle_run(w, s)
+        relres_o, _ = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[s], xo, w.b[s])
+        relres_g, _ = oracle.residual_measures(p.n, p.colptr, p.rowind, w.values[s], x[s], w.b[s])
+        for r in range(w.nrhs):
+            st = stats[s * w.nrhs + r]
+            log("%s set %d rhs %d: iters %d clause %d relres %.2e rnorm %.3e xnorm %.3e ||A|| %.6e"
+                % (method, s, r, st["iters"], st["clause"], st["relres"], st["rnorm"],
+                   st["xnorm"], anorm))
+            assert st["clause"] in (1, 2)
+            if st["clause"] == 1:
+                assert st["relres"] <= tol
+            else:
+                nfloor += 1
+                assert st["rnorm"] <= 2 * u * anorm * st["xnorm"] * (1 + 1e-12)
+            assert relres_g[r] <= max(10 * relres_o[r], tol)
+    log("%s: %d of %d systems stopped on the floor clause" % (method, nfloor, len(stats)))
+
+
 def test_refine_batch_matches_single_bitwise():
     w = W.small_grid((10, 10, 10), "nd", seed=64, batch=3, nrhs=1)
     rc, stats, xb = _refine(w, "f32")
