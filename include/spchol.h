@@ -315,8 +315,10 @@ enum { SC_REFINE_CLASSICAL = 0, SC_REFINE_PCG = 1 };
  *     than maxit corrections were applied: r = b - A x, x += solve(r).
  *   SC_REFINE_PCG: conjugate gradients on A preconditioned by the factor,
  *     at most maxit steps; the stop rule is tested on the true residual
- *     b - A x after each step.  Converges when the factor's precision is
- *     too low for classical refinement (kappa(A) u_factor > 1).
+ *     b - A x after each step, before the next direction is formed, so
+ *     the step that meets the rule costs no further solve.  Converges when
+ *     the factor's precision is too low for classical refinement
+ *     (kappa(A) u_factor > 1).
  * Stop rule per system (matrix b, right-hand side r, block k; norms over
  * the block's rows, ||A||_inf of the block):
  * ||r||_2 <= tol ||b||_2, or ||r||_2 <= 2 u ||A||_inf ||x||_2 (the residual
