@@ -1216,41 +1216,57 @@ __global__ __launch_bounds__(256) void k_fx_y(
                 ((acc[r] + red[0][lane][r]) + red[1][lane][r]) + red[2][lane][r];
 }
 
-// Forward, u = v2 - L21 y into the front vector's rows >= w: workgroup (256
-// rows below the diagonal block, supernode, matrix), lane = row, every
-// column j < w in ascending order.
+// Forward, u = v2 - L21 y into the front vector's rows >= w: workgroup
+// (256 kFxRows rows below the diagonal block, supernode, matrix), thread t
+// takes rows t + 256 q (q < kFxRows; the rows' loads of one column in flight
+// together), every column j < w in ascending order.
+constexpr int kFxRows = 4;  // rows per thread of k_fx_u
 template <typename T, int NR, bool SOA>
 __global__ __launch_bounds__(256) void k_fx_u(
     const SnDesc *__restrict__ sn, const int32_t *__restrict__ list, int r0,
     const T *__restrict__ L, int64_t Lsize, const T *__restrict__ Ys, T *__restrict__ FV,
     int64_t n, int64_t fvsize, int nrhs, const int32_t *__restrict__ active) {
+    constexpr int RPT = kFxRows;
     __shared__ T ys[kXMaxW][NR];
     const int b = blockIdx.z;
     if (active && !active[b]) return;
     const SnDesc d = sn[list[blockIdx.y]];
-    const int w = d.w, c = d.c, i0 = w + 256 * int(blockIdx.x);
+    const int w = d.w, c = d.c, i0 = w + 256 * RPT * int(blockIdx.x);
     if (i0 >= c) return;
     const int tid = threadIdx.x;
     for (int j = tid; j < w; j += 256)
 #pragma unroll
         for (int r = 0; r < NR; r++) ys[j][r] = Ys[vix<SOA>(b, d.first + j, r0 + r, n, nrhs)];
     __syncthreads();
-    const int i = i0 + tid;
-    if (i >= c) return;
+    if (i0 + tid >= c) return;
     const T *Lb = L + int64_t(b) * Lsize + d.loff;
-    T acc[NR];
+    int ic[RPT];
 #pragma unroll
-    for (int r = 0; r < NR; r++) acc[r] = T(0);
+    for (int q = 0; q < RPT; q++) ic[q] = min(i0 + tid + 256 * q, c - 1);
+    T acc[RPT][NR];
+#pragma unroll
+    for (int q = 0; q < RPT; q++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[q][r] = T(0);
 #pragma unroll 8
     for (int j = 0; j < w; j++) {
-        const T l = Lb[int64_t(j) * c + i];
+        T l[RPT];
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += l * ys[j][r];
+        for (int q = 0; q < RPT; q++) l[q] = Lb[int64_t(j) * c + ic[q]];
+#pragma unroll
+        for (int q = 0; q < RPT; q++)
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[q][r] += l[q] * ys[j][r];
     }
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const int64_t q = vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs);
-        FV[q] = FV[q] - acc[r];
+    for (int q = 0; q < RPT; q++) {
+        const int i = i0 + tid + 256 * q;
+        if (i < c)
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const int64_t o = vix<SOA>(b, d.rowptr + i, r0 + r, fvsize, nrhs);
+                FV[o] = FV[o] - acc[q][r];
+            }
     }
 }
 
@@ -2413,7 +2429,7 @@ void x_forward(const XSet &xs, const sc_plan *P, sc_numeric *N, int nrhs,
     const double sz = double(sizeof(T)), nr = double(nrhs), nb = double(B);
     prof.begin(KK_FwdPanel, 2.0 * xs.xw * nr * nb, xs.xw * sz * nb, st, xs.lx * sz * nb);
     const dim3 gy(unsigned((xs.maxw + 63) / 64), unsigned(xs.cnt), unsigned(B));
-    const dim3 gu(unsigned((xs.maxc + 255) / 256), unsigned(xs.cnt), unsigned(B));
+    const dim3 gu(unsigned((xs.maxc + 256 * kFxRows - 1) / (256 * kFxRows)), unsigned(xs.cnt), unsigned(B));
     for (int r0 = 0; r0 < nrhs; r0 += 4) {
         const int nrr = std::min(4, nrhs - r0);
 #define SPCHOL_FX(NRV)                                                                          \
