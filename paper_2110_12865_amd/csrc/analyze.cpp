@@ -582,6 +582,7 @@ sc_status spchol_build_plan(int64_t n, const int64_t *colptr,
             const int32_t e1 = P->slv_cls_ptr[size_t(l + 1) * kSolveClasses];
             if (e0 == e1 || e1 - e0 > kXSmallMax) continue;
             P->slv_small_x[l] = 1;
+            P->xs_lev = l;
             for (int32_t e = e0; e < e1; e++) {
                 const int32_t s = P->slv_small[e];
                 const int64_t w = P->sn[s].w;

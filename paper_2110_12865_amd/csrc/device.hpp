@@ -263,7 +263,9 @@ hipError_t spchol_factor_run(const sc_plan *P, sc_numeric *N,
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b,
                             int32_t nrhs, int64_t ldb, hipStream_t st,
                             const int32_t *active, const double *bin = nullptr);
-hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
+// parts: 1 = whole-block inverses of the small levels (xs_list), 2 = the
+// inverted diagonal blocks of dinv_list, 3 = both
+hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st, int parts = 3);
 // The interleaved copy of L (batch-interleaved numeric objects), on stream st.
 hipError_t spchol_to_soa_run(const sc_plan *P, sc_numeric *N, hipStream_t st);
 hipError_t spchol_refine_run(const sc_plan *P, sc_numeric *N, const double *vals,

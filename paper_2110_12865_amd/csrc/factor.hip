@@ -1261,9 +1261,26 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         if (e == hipSuccess) e = hipEventRecord(N->ev_join2, N->side2);
         return e;
     };
+    // the whole-block inverses of the small levels follow on the third
+    // stream as soon as those levels are factored (after the copy when that
+    // was forked first), beside the levels above
+    const bool xs_side = N->side2 && N->xinv && !P->xs_list.empty() && P->xs_lev >= 0;
+    bool xs_forked = false;
+    auto fork_xs = [&]() -> hipError_t {
+        xs_forked = true;
+        hipError_t e = hipEventRecord(N->ev_fork2, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(N->side2, N->ev_fork2, 0);
+        if (e == hipSuccess) e = spchol_dinv_run(P, N, N->side2, 1);
+        if (e == hipSuccess) e = hipEventRecord(N->ev_join2, N->side2);
+        return e;
+    };
     for (const FLaunch &f : D->fsched) {
         if (copy_lev >= 0 && !copy_forked && f.level > copy_lev) {
             const hipError_t e = fork_copy();
+            if (e != hipSuccess) return e;
+        }
+        if (xs_side && !xs_forked && f.level > P->xs_lev) {
+            const hipError_t e = fork_xs();
             if (e != hipSuccess) return e;
         }
         if (f.kind == FLaunch::Fork || f.kind == FLaunch::Join) {
@@ -1342,7 +1359,10 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (copy_lev >= 0 && !copy_forked) e = fork_copy();
-    if (e == hipSuccess) e = spchol_dinv_run(P, N, st);  // inverted diagonal blocks for the solves
+    if (e == hipSuccess && xs_side && !xs_forked) e = fork_xs();
+    // inverted diagonal blocks for the solves (and the small levels' whole-
+    // block inverses when they did not go to the third stream)
+    if (e == hipSuccess) e = spchol_dinv_run(P, N, st, xs_forked ? 2 : 3);
     if (e == hipSuccess && N->xinv && !P->x_list.empty()) {
         // whole-block inverses from them
         prof.begin(KK_Dinv, 0.0, 0.0, st);
@@ -1354,7 +1374,7 @@ hipError_t factor_impl(const sc_plan *P, sc_numeric *N, const double *vals,
         prof.end(st);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && copy_forked) e = hipStreamWaitEvent(st, N->ev_join2, 0);
+    if (e == hipSuccess && (copy_forked || xs_forked)) e = hipStreamWaitEvent(st, N->ev_join2, 0);
     return e;
 }
 

@@ -200,6 +200,7 @@ struct sc_plan {
     int64_t soa_psize = 0;
     std::vector<int64_t> soa_chunks, soa_chunks_x;
     int32_t soa_copy_lev = -1, soa_copy_lev_x = -1;  // highest level each copy covers
+    int32_t xs_lev = -1;  // highest level of the supernodes in xs_list
     int64_t dinv_size = 0;   // scalars of inverted diagonal blocks
     // panel-solved supernodes factored as small fronts (their inverted
     // diagonal blocks are formed after the factorization; the tiled factor

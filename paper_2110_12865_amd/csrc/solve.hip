@@ -2075,17 +2075,17 @@ template <typename T>
 T *as(double *p) { return reinterpret_cast<T *>(p); }
 
 template <typename T>
-hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st) {
+hipError_t dinv_impl(const sc_plan *P, sc_numeric *N, hipStream_t st, int parts) {
     DevPlan *D = P->dev;
     const T *L = static_cast<const T *>(N->L);
-    if (N->xinv && !P->xs_list.empty()) {
+    if ((parts & 1) && N->xinv && !P->xs_list.empty()) {
         N->prof.begin(KK_Dinv, 0.0, 0.0, st);
         hipLaunchKernelGGL(k_xsmall<T>, dim3(unsigned(N->batch), unsigned(P->xs_list.size())),
                            dim3(64), 0, st, D->sn, D->xs_list, D->xoff, L, P->Lsize,
                            static_cast<T *>(N->xinv), P->xsize);
         N->prof.end(st);
     }
-    if (P->dinv_list.empty()) return hipGetLastError();
+    if (!(parts & 2) || P->dinv_list.empty()) return hipGetLastError();
     const int64_t maxp = (P->max_width + kP - 1) / kP;
     N->prof.begin(KK_Dinv, 0.0, 0.0, st);
     hipLaunchKernelGGL(k_dinv<T>,
@@ -2932,9 +2932,9 @@ hipError_t spchol_to_soa_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
     return to_soa_impl<float>(P, N, st);
 }
 
-hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st) {
-    if (N->dtype == SC_F64) return dinv_impl<double>(P, N, st);
-    return dinv_impl<float>(P, N, st);
+hipError_t spchol_dinv_run(const sc_plan *P, sc_numeric *N, hipStream_t st, int parts) {
+    if (N->dtype == SC_F64) return dinv_impl<double>(P, N, st, parts);
+    return dinv_impl<float>(P, N, st, parts);
 }
 
 hipError_t spchol_solve_run(const sc_plan *P, sc_numeric *N, double *b, int32_t nrhs,
